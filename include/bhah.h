@@ -1,0 +1,225 @@
+/*
+ * bhah.h -- C ABI of the MI355X-native BSSN evolution core.
+ *
+ * What the library computes (paper: "superB/NRPy: Scalable, Task-Based
+ * Numerical Relativity for 3G Gravitational Wave Science", arXiv:2505.00097):
+ *   - the right-hand sides of the covariant BSSN system with 1+log slicing and
+ *     the Gamma-driver shift (Sec. 2.1, Eqs. 7-15, Ricci tensor Eq. 12), for
+ *     the 24 rescaled evolved variables (Sec. 2.2) on cell-centred curvilinear
+ *     grids (Sec. 3, first paragraphs; sinh radial map Eq. 22);
+ *   - classical RK4 time stepping (Sec. 4.2.1, footnote on the integrator);
+ *   - the ghost-zone fill: outer-boundary ghosts first, then inner-boundary
+ *     (parity) ghosts, after every Runge-Kutta substage (Sec. 3, ghost-point
+ *     classes and the ordered list of boundary steps);
+ *   - Brill-Lindquist puncture initial data and the Hamiltonian constraint
+ *     (Eq. 16) as a diagnostic.
+ *
+ * Conventions shared by every entry point
+ *   Return codes : BHAH_OK (0) or a negative BHAH_E* code. A message for the
+ *                  last failure on the calling thread is in bhah_last_error().
+ *                  No C++ exception crosses this boundary and nothing aborts.
+ *   Precision    : IEEE FP64 everywhere.
+ *   State layout : y[g][i2][i1][i0], i0 fastest, gridfunction-major, with
+ *                  n_total[d] = N[d] + 2*nghosts points per direction and no
+ *                  padding: element (g,i0,i1,i2) is at
+ *                  ((g*n_total[2] + i2)*n_total[1] + i1)*n_total[0] + i0.
+ *                  The 24 gridfunctions are ordered as in enum bhah_gf.
+ *   Pointers     : pointers named y, rhs, aux, H, workspace are DEVICE
+ *                  pointers owned by the caller, 8-byte aligned, on the device
+ *                  that was current when the grid was created. Pointers named
+ *                  host_* or taken as parameters structs are host pointers.
+ *   Streams      : `stream` is a hipStream_t passed as void*; NULL means the
+ *                  null stream. Every call that takes a stream only enqueues
+ *                  work and returns; results are ready when the stream is.
+ *   Memory       : calls that take a stream allocate no device memory. All
+ *                  temporaries live in the caller's `workspace`.
+ */
+#ifndef BHAH_H
+#define BHAH_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+enum {
+  BHAH_OK = 0,
+  BHAH_EINVAL = -1,  /* bad argument: NULL pointer, unsupported parameter,
+                        grid too small, odd N_phi where a pi shift is needed */
+  BHAH_EDEVICE = -2, /* a HIP runtime call failed (text in bhah_last_error) */
+  BHAH_ENOMEM = -3   /* a host or device allocation inside a *_create failed */
+};
+
+/* ---- coordinate systems (Sec. 3 first paragraph; Eq. 22) ---------------- *
+ * Logical coordinates xx^i are uniform and cell-centred (Sec. 3): point j of
+ * direction i sits at xx^i_min + (j - nghosts + 1/2) * dxx^i with
+ * dxx^i = (xx^i_max - xx^i_min) / N[i].
+ *   BHAH_SINH_SPHERICAL  : xx0 in [0,1] -> r = ampl[0] sinh(xx0/w0)/sinh(1/w0),
+ *                          xx1 = theta in [0,pi], xx2 = phi in [-pi,pi].
+ *   BHAH_SINH_CYLINDRICAL: xx0 in [0,1] -> rho = ampl[0] sinh(xx0/w0)/sinh(1/w0),
+ *                          xx1 = phi in [-pi,pi],
+ *                          xx2 in [-1,1] -> z = ampl[2] sinh(xx2/w2)/sinh(1/w2).
+ *   BHAH_SPHERICAL       : xx0 in [0,1] -> r = ampl[0] * xx0 (uniform radius,
+ *                          the grid of the paper's single-node benchmark),
+ *                          xx1 = theta, xx2 = phi.
+ * Scale factors S_(i) = sqrt(gammahat_ii) (Sec. 2.2) are taken with their
+ * analytic sign: (r', r, r sin(theta)) and (rho', rho, z').                  */
+enum { BHAH_SINH_SPHERICAL = 0, BHAH_SINH_CYLINDRICAL = 1, BHAH_SPHERICAL = 2 };
+
+/* ---- outer boundary condition (Sec. 3, outer boundary points) ---------- *
+ * BHAH_BC_EXTRAP: quadratic extrapolation along the face normal,
+ * f(g) = 3 f(g-1) - 3 f(g-2) + f(g-3), applied ghost layer by ghost layer in
+ * the order x0 faces, x1 faces, x2 faces, each face range growing by the
+ * layers already filled.                                                     */
+enum { BHAH_BC_EXTRAP = 0 };
+
+/* ---- the 24 evolved rescaled gridfunctions (Sec. 2.1 last gauge paragraph;
+ * rescaling Sec. 2.2): h_ij = eps_ij/(S_i S_j), a_ij = Abar_ij/(S_i S_j),
+ * lambda^i = S_i Lambdabar^i, vet^i = S_i beta^i, bet^i = S_i B^i,
+ * cf = W = exp(-2 phi), trK = K, alpha = lapse.                              */
+enum bhah_gf {
+  BHAH_ADD00 = 0, BHAH_ADD01, BHAH_ADD02, BHAH_ADD11, BHAH_ADD12, BHAH_ADD22,
+  BHAH_ALPHA, BHAH_BETU0, BHAH_BETU1, BHAH_BETU2, BHAH_CF,
+  BHAH_HDD00, BHAH_HDD01, BHAH_HDD02, BHAH_HDD11, BHAH_HDD12, BHAH_HDD22,
+  BHAH_LAMBDAU0, BHAH_LAMBDAU1, BHAH_LAMBDAU2, BHAH_TRK,
+  BHAH_VETU0, BHAH_VETU1, BHAH_VETU2,
+  BHAH_NUM_GFS /* = 24 */
+};
+
+/* Number of gridfunctions in the `aux` array of bhah_bssn_rhs. */
+#define BHAH_NUM_AUX_GFS 6
+
+typedef struct bhah_grid bhah_grid;   /* opaque, immutable after create */
+typedef struct bhah_batch bhah_batch; /* opaque ensemble of grids        */
+
+/* Grid parameters. nghosts must be 3 (4th-order FD with upwinded advection
+ * needs N_FD/2 + 1 ghost layers, Sec. 3 and Sec. 4.2.1). ampl[]/sinhw[]
+ * entries for directions without a map are ignored. cfl scales the time step
+ * (Sec. 4.1 uses 0.5). bc_kind must be BHAH_BC_EXTRAP.                       */
+typedef struct {
+  int coord;
+  int N[3];
+  int nghosts;
+  double ampl[3];
+  double sinhw[3];
+  double cfl;
+  int bc_kind;
+} bhah_grid_params;
+
+/* Gauge parameters: eta is the Gamma-driver damping of Eq. 15 (Sec. 4.1 uses
+ * 2.0). shift_variant must be 0: dB^i/dt uses the full dLambdabar^i/dt of
+ * Eq. 11 including its advection term.                                       */
+typedef struct {
+  double eta;
+  int shift_variant;
+} bhah_gauge_params;
+
+typedef struct {
+  int n_total[3];              /* N[d] + 2*nghosts                           */
+  long long n_points;          /* n_total[0]*n_total[1]*n_total[2]          */
+  long long n_interior;        /* N[0]*N[1]*N[2]                            */
+  long long state_doubles;     /* 24 * n_points: size of one state array    */
+  long long aux_doubles;       /* BHAH_NUM_AUX_GFS * n_points               */
+  long long workspace_doubles; /* size of the rk4_step workspace            */
+  long long n_pure_outer;      /* ghost points filled by extrapolation      */
+  long long n_inner;           /* ghost points filled by a parity copy      */
+  double dxx[3];
+  double xxmin[3];
+  double dt;                   /* cfl * min over interior of min_i S_i dxx^i */
+} bhah_grid_info;
+
+/* Create a grid: validates the parameters, builds the 1-D reference-metric
+ * tables and the boundary maps on the host and copies them to the current
+ * device. Host-synchronous. Returns BHAH_EINVAL for coord/nghosts/bc_kind out
+ * of range, any N[d] < nghosts, or an odd N_phi (the inner maps shift phi by
+ * pi); BHAH_ENOMEM / BHAH_EDEVICE on allocation failure. *out is set only on
+ * success. (Sec. 3: grid and ghost points; Sec. 2.2: rescaling.)            */
+int bhah_grid_create(const bhah_grid_params* params, bhah_grid** out);
+
+/* Free the grid and its device tables. NULL is accepted. The caller must
+ * make sure no enqueued work still uses the grid.                           */
+void bhah_grid_destroy(bhah_grid* g);
+
+/* Sizes, spacing and the CFL time step of a grid (host, synchronous).       */
+int bhah_grid_get_info(const bhah_grid* g, bhah_grid_info* info);
+
+/* Copy the boundary maps to host arrays (host, synchronous). Each pointer may
+ * be NULL to skip it; non-NULL arrays must hold n_points ints.
+ *   host_kind[p]   : 0 interior, 1 pure outer (filled by extrapolation),
+ *                    2 inner (filled by a parity copy)
+ *   host_src[p]    : flat index of the source point of an inner ghost,
+ *                    p itself for the other kinds
+ *   host_parity[p] : bit d set means the rescaled basis vector e~_(d) flips
+ *                    sign between source and destination (p_d = -1); 0 for
+ *                    non-inner points.
+ * (Sec. 3: inner boundary points copy mapped values with tensor parity.)    */
+int bhah_grid_get_bc_maps(const bhah_grid* g, int* host_kind, int* host_src,
+                          int* host_parity);
+
+/* Brill-Lindquist puncture data: psi = 1 + sum_n m_n / (2 |x - x_n|),
+ * W = psi^-2, alpha = psi^-2 (lapse_kind 0) or 1 (lapse_kind 1), all other
+ * variables zero; interior points are set, then bhah_apply_bcs fills the
+ * ghosts. host_masses[n_punct] and host_pos[3*n_punct] (Cartesian x,y,z) are
+ * host arrays read before the call returns. n_punct may be 0 (flat space).  */
+int bhah_set_initial_data_brill_lindquist(const bhah_grid* g, int n_punct,
+                                          const double* host_masses,
+                                          const double* host_pos,
+                                          int lapse_kind, double* y,
+                                          void* stream);
+
+/* Ghost-zone fill in place (Sec. 3, boundary steps 1 and 2): every pure-outer
+ * ghost by quadratic extrapolation in shell order, then every inner ghost as
+ * y_g[dst] = s_g * y_g[src] with s_g = product of p_d over the gridfunction's
+ * tensor indices. Interior points are not modified.                          */
+int bhah_apply_bcs(const bhah_grid* g, double* y, void* stream);
+
+/* BSSN + gauge right-hand sides (Eqs. 7-15 with Eq. 12) of the rescaled
+ * variables at every interior point. y must have valid ghosts. rhs has the
+ * state layout; only its interior points are written. aux may be NULL; if
+ * given it receives BHAH_NUM_AUX_GFS gridfunctions (state layout, interior
+ * points) holding the rescaled conformal Ricci tensor Rbar_ij/(S_i S_j) in
+ * the order 00,01,02,11,12,22. All 4th-order finite differences, advection
+ * terms beta^k d_k upwinded (Sec. 3 second paragraph).                     */
+int bhah_bssn_rhs(const bhah_grid* g, const bhah_gauge_params* gp,
+                  const double* y, double* rhs, double* aux, void* stream);
+
+/* One classical RK4 step of size dt, in place on y (interior updated, ghosts
+ * refilled by bhah_apply_bcs after every stage and after the final combine,
+ * Sec. 3 boundary order; RK4 per Sec. 4.2.1). workspace must hold
+ * info.workspace_doubles doubles and must not alias y.                       */
+int bhah_rk4_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt,
+                  double* y, double* workspace, void* stream);
+
+/* Hamiltonian constraint H of Eq. 16 at every interior point (centred
+ * 4th-order differences), written into H (one gridfunction, state point
+ * layout, interior points only). y must have valid ghosts.                  */
+int bhah_hamiltonian_constraint(const bhah_grid* g, const double* y, double* H,
+                                void* stream);
+
+/* ---- ensembles: many independent grids advanced together ---------------- *
+ * A batch advances n grids that share gauge parameters with the same per-point
+ * arithmetic as bhah_rk4_step, launching each kernel once for all jobs.
+ * The per-job states and workspaces are device pointers set per step, so jobs
+ * can be swapped in and out between steps. tune_cache_path may be NULL; if it
+ * names a file, tile choices are read from / written to it.                 */
+int bhah_batch_create(const bhah_grid* const* grids, int n,
+                      const bhah_gauge_params* gp, const char* tune_cache_path,
+                      bhah_batch** out);
+
+/* Advance the jobs with host_active[j] != 0 by nsteps RK4 steps each, job j
+ * at its own step host_dt[j], on y[j] (state) with workspace ws[j]. y and ws
+ * are host arrays of n device pointers. The result for every job equals what
+ * bhah_rk4_step gives for that job alone.                                   */
+int bhah_batch_step(bhah_batch* b, double* const* y, double* const* ws,
+                    const double* host_dt, const unsigned char* host_active,
+                    int nsteps, void* stream);
+
+void bhah_batch_destroy(bhah_batch* b);
+
+/* Message describing the last failed call on this thread ("" if none).      */
+const char* bhah_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BHAH_H */

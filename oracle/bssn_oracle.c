@@ -1,0 +1,1113 @@
+/*
+ * bssn_oracle.c -- TEST INFRASTRUCTURE: the plain CPU oracle.
+ *
+ * A deliberately direct FP64 evaluation of the discretised BSSN evolution of
+ * arXiv:2505.00097. Every quantity is built with full 3x3(x3x3) index loops in
+ * the order and notation of the paper's equations, with no blocking, fusion
+ * or symmetry tricks, so that each step can be compared with the paper by
+ * eye. It is used only by tests/, the smoke check and the CPU baseline of the
+ * benchmark, to check the HIP library; it shares no source with that library.
+ *
+ * Discretisation (the plain definition the GPU path must reproduce):
+ *   - cell-centred logical grid, N_G ghost layers (Sec. 3);
+ *   - every partial derivative of an evolved rescaled variable is a 4th-order
+ *     finite difference: centred 5-point stencils, their tensor product for
+ *     mixed derivatives, and for the advection terms beta^k d_k the 5-point
+ *     stencil shifted one point upwind (Sec. 3, second paragraph);
+ *   - every reference-metric quantity (S_i, its derivatives, Gammahat and its
+ *     derivatives) is evaluated analytically (Sec. 2.2, Eq. 22);
+ *   - RHS = Eqs. 7-15 with Eq. 12 (Sec. 2.1), unrescaled/rescaled per Sec. 2.2;
+ *   - boundary fill after every RK substage: outer extrapolation, then inner
+ *     parity copies (Sec. 3, ordered boundary steps);
+ *   - classical RK4 (Sec. 4.2.1 footnote).
+ * Readings where the paper is silent or garbled are marked "Reading:".
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared.
+ */
+#include "bssn_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define NGF ORACLE_NGF
+
+/* gridfunction order (alphabetical names of the rescaled variables) */
+enum {
+  ADD00, ADD01, ADD02, ADD11, ADD12, ADD22, ALPHA, BETU0, BETU1, BETU2, CF,
+  HDD00, HDD01, HDD02, HDD11, HDD12, HDD22, LAMU0, LAMU1, LAMU2, TRK,
+  VETU0, VETU1, VETU2
+};
+
+/* position of the symmetric pair (i,j) in the 00,01,02,11,12,22 order */
+static const int SYM[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+
+/* tensor type of each gridfunction: 0 scalar, 1 vector (index in vidx),
+ * 2 symmetric rank-2 (indices in tidx) */
+static const int GF_TYPE[NGF] = {2, 2, 2, 2, 2, 2, 0, 1, 1, 1, 0,
+                                 2, 2, 2, 2, 2, 2, 1, 1, 1, 0, 1, 1, 1};
+static const int GF_I[NGF] = {0, 0, 0, 1, 1, 2, 0, 0, 1, 2, 0,
+                              0, 0, 0, 1, 1, 2, 0, 1, 2, 0, 0, 1, 2};
+static const int GF_J[NGF] = {0, 1, 2, 1, 2, 2, 0, 0, 0, 0, 0,
+                              0, 1, 2, 1, 2, 2, 0, 0, 0, 0, 0, 0, 0};
+
+/* ------------------------------------------------------------------------ */
+/* Grid (Sec. 3, first paragraph): logical domain [xxmin, xxmax], N cells,
+ * cell-centred points xxmin + (j - ng + 1/2) dxx.                           */
+typedef struct {
+  oracle_params p;
+  int n[3];
+  long long np;     /* points incl. ghosts */
+  long long st[3];  /* flat-index strides */
+  double xxmin[3], xxmax[3], dxx[3];
+} Grid;
+
+int oracle_check(const oracle_params* p) {
+  if (!p) return -1;
+  if (p->coord < 0 || p->coord > 2) return -1;
+  if (p->ng < 3) return -1;
+  /* the periodic phi direction may have fewer cells than ghost layers (its
+   * ghosts wrap around as often as needed); the others need N >= ng */
+  const int dphi = p->coord == 1 ? 1 : 2;
+  for (int d = 0; d < 3; d++)
+    if (d != dphi && p->N[d] < p->ng) return -1;
+  if (p->N[dphi] < 2) return -1;
+  if (p->coord == 1) {
+    if (p->N[1] % 2) return -1;
+    if (!(p->ampl[0] > 0) || !(p->ampl[2] > 0) || !(p->sinhw[0] > 0) || !(p->sinhw[2] > 0))
+      return -1;
+  } else {
+    if (p->N[2] % 2) return -1;
+    if (!(p->ampl[0] > 0)) return -1;
+    if (p->coord == 0 && !(p->sinhw[0] > 0)) return -1;
+  }
+  return 0;
+}
+
+static int grid_setup(const oracle_params* p, Grid* G) {
+  if (oracle_check(p)) return -1;
+  G->p = *p;
+  const double PI = M_PI;
+  if (p->coord == 1) { /* SinhCylindrical: (xx0, phi, xx2) */
+    G->xxmin[0] = 0.0; G->xxmax[0] = 1.0;
+    G->xxmin[1] = -PI; G->xxmax[1] = PI;
+    G->xxmin[2] = -1.0; G->xxmax[2] = 1.0;
+  } else { /* (Sinh)Spherical: (xx0, theta, phi) */
+    G->xxmin[0] = 0.0; G->xxmax[0] = 1.0;
+    G->xxmin[1] = 0.0; G->xxmax[1] = PI;
+    G->xxmin[2] = -PI; G->xxmax[2] = PI;
+  }
+  for (int d = 0; d < 3; d++) {
+    G->n[d] = p->N[d] + 2 * p->ng;
+    G->dxx[d] = (G->xxmax[d] - G->xxmin[d]) / (double)p->N[d];
+  }
+  G->st[0] = 1;
+  G->st[1] = G->n[0];
+  G->st[2] = (long long)G->n[0] * G->n[1];
+  G->np = G->st[2] * G->n[2];
+  return 0;
+}
+
+static double xx_of(const Grid* G, int d, int j) {
+  return G->xxmin[d] + ((double)(j - G->p.ng) + 0.5) * G->dxx[d];
+}
+
+double oracle_xx(const oracle_params* p, int d, int j) {
+  Grid G;
+  if (grid_setup(p, &G)) return NAN;
+  return xx_of(&G, d, j);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Radial map of Eq. 22: x' = A sinh(x/w)/sinh(1/w), with its first three
+ * derivatives; the uniform map x' = A x for plain Spherical.               */
+static void radial_map(int linear, double A, double w, double x, double out[4]) {
+  if (linear) {
+    out[0] = A * x; out[1] = A; out[2] = 0.0; out[3] = 0.0;
+    return;
+  }
+  const double s = sinh(1.0 / w);
+  out[0] = A * sinh(x / w) / s;
+  out[1] = A * cosh(x / w) / (w * s);
+  out[2] = A * sinh(x / w) / (w * w * s);
+  out[3] = A * cosh(x / w) / (w * w * w * s);
+}
+
+/* inverse of radial_map's value */
+static double radial_map_inv(int linear, double A, double w, double r) {
+  if (linear) return r / A;
+  return w * asinh(r * sinh(1.0 / w) / A);
+}
+
+/* Scale factors S_(i) = sqrt(gammahat_ii) of the flat reference metric in the
+ * logical coordinates (Sec. 2.2), with analytic sign, and their first and
+ * second logical derivatives: dS[i][k] = d_k S_i, ddS[i][k][l] = d_k d_l S_i.
+ *   (Sinh)Spherical: gammahat = diag(r'^2, r^2, r^2 sin^2 theta)
+ *   SinhCylindrical: gammahat = diag(rho'^2, rho^2, z'^2)                  */
+static void scale_factors(const Grid* G, const double xx[3], double S[3], double dS[3][3],
+                          double ddS[3][3][3]) {
+  memset(dS, 0, 9 * sizeof(double));
+  memset(ddS, 0, 27 * sizeof(double));
+  const oracle_params* p = &G->p;
+  if (p->coord == 1) {
+    double R[4], Z[4];
+    radial_map(0, p->ampl[0], p->sinhw[0], xx[0], R);
+    radial_map(0, p->ampl[2], p->sinhw[2], xx[2], Z);
+    S[0] = R[1]; S[1] = R[0]; S[2] = Z[1];
+    dS[0][0] = R[2]; dS[1][0] = R[1]; dS[2][2] = Z[2];
+    ddS[0][0][0] = R[3]; ddS[1][0][0] = R[2]; ddS[2][2][2] = Z[3];
+  } else {
+    double R[4];
+    radial_map(p->coord == 2, p->ampl[0], p->sinhw[0], xx[0], R);
+    const double st = sin(xx[1]), ct = cos(xx[1]);
+    S[0] = R[1]; S[1] = R[0]; S[2] = R[0] * st;
+    dS[0][0] = R[2];
+    dS[1][0] = R[1];
+    dS[2][0] = R[1] * st; dS[2][1] = R[0] * ct;
+    ddS[0][0][0] = R[3];
+    ddS[1][0][0] = R[2];
+    ddS[2][0][0] = R[2] * st;
+    ddS[2][0][1] = ddS[2][1][0] = R[1] * ct;
+    ddS[2][1][1] = -R[0] * st;
+  }
+}
+
+void oracle_scalefactors(const oracle_params* p, const double xx[3], double S[3], double dS[9],
+                         double ddS[27]) {
+  Grid G;
+  if (grid_setup(p, &G)) return;
+  double a[3][3], b[3][3][3];
+  scale_factors(&G, xx, S, a, b);
+  memcpy(dS, a, sizeof a);
+  memcpy(ddS, b, sizeof b);
+}
+
+/* Cartesian position (Eqs. 18-20 for the spherical family; x = rho cos phi,
+ * y = rho sin phi, z for the cylindrical one).                              */
+static void xx_to_cart(const Grid* G, const double xx[3], double x[3]) {
+  const oracle_params* p = &G->p;
+  double R[4];
+  if (p->coord == 1) {
+    double Z[4];
+    radial_map(0, p->ampl[0], p->sinhw[0], xx[0], R);
+    radial_map(0, p->ampl[2], p->sinhw[2], xx[2], Z);
+    x[0] = R[0] * cos(xx[1]);
+    x[1] = R[0] * sin(xx[1]);
+    x[2] = Z[0];
+  } else {
+    radial_map(p->coord == 2, p->ampl[0], p->sinhw[0], xx[0], R);
+    x[0] = R[0] * sin(xx[1]) * cos(xx[2]);
+    x[1] = R[0] * sin(xx[1]) * sin(xx[2]);
+    x[2] = R[0] * cos(xx[1]);
+  }
+}
+
+void oracle_xx_to_cart(const oracle_params* p, const double xx[3], double x[3]) {
+  Grid G;
+  if (grid_setup(p, &G)) return;
+  xx_to_cart(&G, xx, x);
+}
+
+/* Rescaled basis e~_(i) = e^_(i) / S_(i) with e^_(i) = d x / d xx^i (Sec. 2.2),
+ * e[i][a] = Cartesian component a of e~_(i).                                */
+static void rescaled_basis(const Grid* G, const double xx[3], double e[3][3]) {
+  const oracle_params* p = &G->p;
+  double S[3], dS[3][3], ddS[3][3][3];
+  scale_factors(G, xx, S, dS, ddS);
+  double J[3][3]; /* J[i][a] = d x^a / d xx^i */
+  double R[4];
+  if (p->coord == 1) {
+    double Z[4];
+    radial_map(0, p->ampl[0], p->sinhw[0], xx[0], R);
+    radial_map(0, p->ampl[2], p->sinhw[2], xx[2], Z);
+    const double cp = cos(xx[1]), sp = sin(xx[1]);
+    J[0][0] = R[1] * cp;  J[0][1] = R[1] * sp; J[0][2] = 0.0;
+    J[1][0] = -R[0] * sp; J[1][1] = R[0] * cp; J[1][2] = 0.0;
+    J[2][0] = 0.0;        J[2][1] = 0.0;       J[2][2] = Z[1];
+  } else {
+    radial_map(p->coord == 2, p->ampl[0], p->sinhw[0], xx[0], R);
+    const double st = sin(xx[1]), ct = cos(xx[1]), sp = sin(xx[2]), cp = cos(xx[2]);
+    J[0][0] = R[1] * st * cp; J[0][1] = R[1] * st * sp; J[0][2] = R[1] * ct;
+    J[1][0] = R[0] * ct * cp; J[1][1] = R[0] * ct * sp; J[1][2] = -R[0] * st;
+    J[2][0] = -R[0] * st * sp; J[2][1] = R[0] * st * cp; J[2][2] = 0.0;
+  }
+  for (int i = 0; i < 3; i++)
+    for (int a = 0; a < 3; a++) e[i][a] = J[i][a] / S[i];
+}
+
+void oracle_rescaled_basis(const oracle_params* p, const double xx[3], double ebasis[9]) {
+  Grid G;
+  if (grid_setup(p, &G)) return;
+  double e[3][3];
+  rescaled_basis(&G, xx, e);
+  memcpy(ebasis, e, sizeof e);
+}
+
+/* ------------------------------------------------------------------------ */
+/* CFL time step. Reading: dt = CFL * min over interior points and directions
+ * of S_i dxx^i (the proper grid spacing); with CFL = 0.5 (Sec. 4.1) this
+ * reproduces the 8428 iterations quoted for 7.5 M in Sec. 4.2.1.            */
+double oracle_dt(const oracle_params* p) {
+  Grid G;
+  if (grid_setup(p, &G)) return NAN;
+  double dsmin = INFINITY;
+  for (int i2 = p->ng; i2 < p->ng + p->N[2]; i2++)
+    for (int i1 = p->ng; i1 < p->ng + p->N[1]; i1++)
+      for (int i0 = p->ng; i0 < p->ng + p->N[0]; i0++) {
+        double xx[3] = {xx_of(&G, 0, i0), xx_of(&G, 1, i1), xx_of(&G, 2, i2)};
+        double S[3], dS[3][3], ddS[3][3][3];
+        scale_factors(&G, xx, S, dS, ddS);
+        for (int d = 0; d < 3; d++) {
+          double ds = fabs(S[d]) * G.dxx[d];
+          if (ds < dsmin) dsmin = ds;
+        }
+      }
+  return p->cfl * dsmin;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Boundary maps (Sec. 3, Fig. 1): a ghost point is mapped to Cartesian
+ * coordinates and back to the canonical coordinate range; the nearest cell
+ * is its source. If that is the point itself it is an outer-boundary point,
+ * otherwise an inner-boundary point whose value is copied from the source
+ * with the parity of the rescaled basis vectors, e~(dst).e~(src) = +-1.     */
+static long long flat(const Grid* G, int i0, int i1, int i2) {
+  return (long long)i0 + G->st[1] * i1 + G->st[2] * i2;
+}
+
+static int is_interior(const Grid* G, int i0, int i1, int i2) {
+  const int ng = G->p.ng;
+  return i0 >= ng && i0 < ng + G->p.N[0] && i1 >= ng && i1 < ng + G->p.N[1] && i2 >= ng &&
+         i2 < ng + G->p.N[2];
+}
+
+static int nearest_cell(const Grid* G, int d, double xx) {
+  return (int)floor((xx - G->xxmin[d]) / G->dxx[d] + (double)G->p.ng);
+}
+
+static int wrap_periodic(const Grid* G, int d, int j) {
+  const int ng = G->p.ng, N = G->p.N[d];
+  int m = (j - ng) % N;
+  if (m < 0) m += N;
+  return ng + m;
+}
+
+/* Cartesian -> canonical logical coordinates -> nearest cell indices. */
+static void cart_to_cell(const Grid* G, const double x[3], int c[3]) {
+  const oracle_params* p = &G->p;
+  if (p->coord == 1) {
+    const double rho = sqrt(x[0] * x[0] + x[1] * x[1]);
+    const double phi = atan2(x[1], x[0]);
+    c[0] = nearest_cell(G, 0, radial_map_inv(0, p->ampl[0], p->sinhw[0], rho));
+    c[1] = wrap_periodic(G, 1, nearest_cell(G, 1, phi));
+    c[2] = nearest_cell(G, 2, radial_map_inv(0, p->ampl[2], p->sinhw[2], x[2]));
+  } else {
+    const double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    const double th = acos(x[2] / r);
+    const double phi = atan2(x[1], x[0]);
+    c[0] = nearest_cell(G, 0, radial_map_inv(p->coord == 2, p->ampl[0], p->sinhw[0], r));
+    c[1] = nearest_cell(G, 1, th);
+    c[2] = wrap_periodic(G, 2, nearest_cell(G, 2, phi));
+  }
+}
+
+static int build_maps(const Grid* G, int* kind, int* src, int* parity) {
+  int bad = 0;
+  for (int i2 = 0; i2 < G->n[2]; i2++)
+    for (int i1 = 0; i1 < G->n[1]; i1++)
+      for (int i0 = 0; i0 < G->n[0]; i0++) {
+        const long long q = flat(G, i0, i1, i2);
+        src[q] = (int)q;
+        parity[q] = 0;
+        if (is_interior(G, i0, i1, i2)) { kind[q] = 0; continue; }
+        double xx[3] = {xx_of(G, 0, i0), xx_of(G, 1, i1), xx_of(G, 2, i2)};
+        double x[3];
+        xx_to_cart(G, xx, x);
+        int c[3];
+        cart_to_cell(G, x, c);
+        if (c[0] == i0 && c[1] == i1 && c[2] == i2) { kind[q] = 1; continue; }
+        kind[q] = 2;
+        if (c[0] < 0 || c[0] >= G->n[0] || c[1] < 0 || c[1] >= G->n[1] || c[2] < 0 ||
+            c[2] >= G->n[2]) { bad = 1; kind[q] = -1; continue; }
+        src[q] = (int)flat(G, c[0], c[1], c[2]);
+        double xs[3] = {xx_of(G, 0, c[0]), xx_of(G, 1, c[1]), xx_of(G, 2, c[2])};
+        double ed[3][3], es[3][3];
+        rescaled_basis(G, xx, ed);
+        rescaled_basis(G, xs, es);
+        for (int d = 0; d < 3; d++) {
+          const double dot = ed[d][0] * es[d][0] + ed[d][1] * es[d][1] + ed[d][2] * es[d][2];
+          if (fabs(fabs(dot) - 1.0) > 1e-10) bad = 1;
+          if (dot < 0) parity[q] |= 1 << d;
+        }
+      }
+  /* every source must be an interior or an outer-boundary point */
+  for (long long q = 0; q < G->np; q++)
+    if (kind[q] == 2) {
+      const int k = kind[src[q]];
+      if (k != 0 && k != 1) bad = 1;
+    }
+  return bad ? -1 : 0;
+}
+
+int oracle_bc_maps(const oracle_params* p, int* kind, int* src, int* parity) {
+  Grid G;
+  if (grid_setup(p, &G)) return -1;
+  return build_maps(&G, kind, src, parity);
+}
+
+/* sign picked up by gridfunction g under the per-direction parities */
+static double gf_sign(int g, int parity) {
+  double s = 1.0;
+  if (GF_TYPE[g] >= 1 && (parity >> GF_I[g] & 1)) s = -s;
+  if (GF_TYPE[g] == 2 && (parity >> GF_J[g] & 1)) s = -s;
+  return s;
+}
+
+/* Ghost fill (Sec. 3, ordered boundary steps 1 and 2).
+ * Step 1, outer boundary. Reading: quadratic extrapolation along the inward
+ * face normal, f(g) = 3 f(g-1) - 3 f(g-2) + f(g-3), done layer by layer; in
+ * each layer the x0 faces, then the x1 faces, then the x2 faces, each face's
+ * transverse range widened by the faces already done. Only outer-boundary
+ * points (those the round trip maps to themselves) are written.
+ * Step 2, inner boundary: copy from the mapped source with parity signs.   */
+static void apply_bcs_with_maps(const Grid* G, const int* kind, const int* src,
+                                const int* parity, double* y) {
+  const int ng = G->p.ng;
+  int lo[3], hi[3]; /* current face ranges, [lo, hi) */
+  for (int d = 0; d < 3; d++) { lo[d] = ng; hi[d] = ng + G->p.N[d]; }
+  for (int layer = 0; layer < ng; layer++) {
+    for (int d = 0; d < 3; d++) {
+      for (int side = 0; side < 2; side++) {
+        const int face = side == 0 ? lo[d] - 1 : hi[d];
+        const int inward = side == 0 ? +1 : -1;
+        int a0 = lo[0], b0 = hi[0], a1 = lo[1], b1 = hi[1], a2 = lo[2], b2 = hi[2];
+        if (d == 0) { a0 = face; b0 = face + 1; }
+        if (d == 1) { a1 = face; b1 = face + 1; }
+        if (d == 2) { a2 = face; b2 = face + 1; }
+        const long long step = inward * G->st[d];
+        for (int i2 = a2; i2 < b2; i2++)
+          for (int i1 = a1; i1 < b1; i1++)
+            for (int i0 = a0; i0 < b0; i0++) {
+              const long long q = flat(G, i0, i1, i2);
+              if (kind[q] != 1) continue;
+              for (int g = 0; g < NGF; g++) {
+                double* f = y + g * G->np + q;
+                f[0] = 3.0 * f[step] - 3.0 * f[2 * step] + f[3 * step];
+              }
+            }
+      }
+      lo[d]--;
+      hi[d]++;
+    }
+  }
+  for (long long q = 0; q < G->np; q++)
+    if (kind[q] == 2)
+      for (int g = 0; g < NGF; g++)
+        y[g * G->np + q] = gf_sign(g, parity[q]) * y[g * G->np + src[q]];
+}
+
+int oracle_apply_bcs(const oracle_params* p, double* y) {
+  Grid G;
+  if (grid_setup(p, &G)) return -1;
+  int* kind = (int*)malloc(sizeof(int) * G.np);
+  int* src = (int*)malloc(sizeof(int) * G.np);
+  int* par = (int*)malloc(sizeof(int) * G.np);
+  int rc = build_maps(&G, kind, src, par);
+  if (rc == 0) apply_bcs_with_maps(&G, kind, src, par, y);
+  free(kind); free(src); free(par);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Brill-Lindquist punctures: conformally flat, time symmetric (K_ij = 0),
+ * psi = 1 + sum m_n / (2 |x - x_n|), gamma_ij = psi^4 delta_ij, so
+ * W = psi^-2, eps = Abar = K = Lambdabar = 0; precollapsed lapse psi^-2
+ * (or 1), zero shift and B. Interior points, then the ghost fill.           */
+int oracle_id_brill_lindquist(const oracle_params* p, int np, const double* m,
+                              const double* pos, int lapse_kind, double* y) {
+  Grid G;
+  if (grid_setup(p, &G)) return -1;
+  memset(y, 0, sizeof(double) * NGF * G.np);
+  for (int i2 = p->ng; i2 < p->ng + p->N[2]; i2++)
+    for (int i1 = p->ng; i1 < p->ng + p->N[1]; i1++)
+      for (int i0 = p->ng; i0 < p->ng + p->N[0]; i0++) {
+        double xx[3] = {xx_of(&G, 0, i0), xx_of(&G, 1, i1), xx_of(&G, 2, i2)};
+        double x[3];
+        xx_to_cart(&G, xx, x);
+        double psi = 1.0;
+        for (int n = 0; n < np; n++) {
+          const double dx = x[0] - pos[3 * n], dy = x[1] - pos[3 * n + 1],
+                       dz = x[2] - pos[3 * n + 2];
+          psi += m[n] / (2.0 * sqrt(dx * dx + dy * dy + dz * dz));
+        }
+        const long long q = flat(&G, i0, i1, i2);
+        y[CF * G.np + q] = 1.0 / (psi * psi);
+        y[ALPHA * G.np + q] = lapse_kind == 0 ? 1.0 / (psi * psi) : 1.0;
+      }
+  return oracle_apply_bcs(p, y);
+}
+
+/* ------------------------------------------------------------------------ */
+/* 4th-order finite differences along a direction with stride s and spacing h
+ * (f points at the centre). Centred: 5 points; upwinded: shifted one point
+ * toward +s (U+) or -s (U-), 5 points. Weights:
+ *   D f  = [8 (f1 - f-1) - (f2 - f-2)] / 12h
+ *   D2 f = [-f-2 + 16 f-1 - 30 f0 + 16 f1 - f2] / 12h^2
+ *   U+ f = [-3 f-1 - 10 f0 + 18 f1 - 6 f2 + f3] / 12h
+ *   U- f = [3 f1 + 10 f0 - 18 f-1 + 6 f-2 - f-3] / 12h
+ * Reading: each sum is grouped into differences so that a constant field has
+ * exactly zero derivatives (the discrete operator is the same).             */
+static double fd_d1(const double* f, long long s, double h) {
+  return (8.0 * (f[s] - f[-s]) - (f[2 * s] - f[-2 * s])) / (12.0 * h);
+}
+static double fd_d2(const double* f, long long s, double h) {
+  return (16.0 * (f[s] + f[-s]) - (f[2 * s] + f[-2 * s]) - 30.0 * f[0]) / (12.0 * h * h);
+}
+static double fd_d11(const double* f, long long sk, long long sl, double hk, double hl) {
+  return (8.0 * (fd_d1(f + sk, sl, hl) - fd_d1(f - sk, sl, hl)) -
+          (fd_d1(f + 2 * sk, sl, hl) - fd_d1(f - 2 * sk, sl, hl))) /
+         (12.0 * hk);
+}
+static double fd_up(const double* f, long long s, double h) {
+  return (3.0 * (f[s] - f[-s]) + 10.0 * (f[s] - f[0]) - 6.0 * (f[2 * s] - f[s]) + (f[3 * s] - f[s])) /
+         (12.0 * h);
+}
+static double fd_dn(const double* f, long long s, double h) {
+  return (3.0 * (f[s] - f[-s]) + 10.0 * (f[0] - f[-s]) - 6.0 * (f[-s] - f[-2 * s]) + (f[-s] - f[-3 * s])) /
+         (12.0 * h);
+}
+
+int oracle_fd_point(const oracle_params* p, const double* f, long long idx, double d1[3],
+                    double d2[9], double uplus[3], double uminus[3]) {
+  Grid G;
+  if (grid_setup(p, &G)) return -1;
+  const double* c = f + idx;
+  for (int k = 0; k < 3; k++) {
+    d1[k] = fd_d1(c, G.st[k], G.dxx[k]);
+    uplus[k] = fd_up(c, G.st[k], G.dxx[k]);
+    uminus[k] = fd_dn(c, G.st[k], G.dxx[k]);
+    for (int l = 0; l < 3; l++)
+      d2[3 * k + l] = k == l ? fd_d2(c, G.st[k], G.dxx[k])
+                             : fd_d11(c, G.st[k], G.st[l], G.dxx[k], G.dxx[l]);
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* general symmetric 3x3 inverse */
+static void inverse3(const double a[3][3], double inv[3][3]) {
+  const double det = a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) -
+                     a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
+                     a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
+  inv[0][0] = (a[1][1] * a[2][2] - a[1][2] * a[2][1]) / det;
+  inv[0][1] = (a[0][2] * a[2][1] - a[0][1] * a[2][2]) / det;
+  inv[0][2] = (a[0][1] * a[1][2] - a[0][2] * a[1][1]) / det;
+  inv[1][0] = (a[1][2] * a[2][0] - a[1][0] * a[2][2]) / det;
+  inv[1][1] = (a[0][0] * a[2][2] - a[0][2] * a[2][0]) / det;
+  inv[1][2] = (a[0][2] * a[1][0] - a[0][0] * a[1][2]) / det;
+  inv[2][0] = (a[1][0] * a[2][1] - a[1][1] * a[2][0]) / det;
+  inv[2][1] = (a[0][1] * a[2][0] - a[0][0] * a[2][1]) / det;
+  inv[2][2] = (a[0][0] * a[1][1] - a[0][1] * a[1][0]) / det;
+}
+
+/* Everything the RHS, the Ricci tensor and the constraints need at a point. */
+typedef struct {
+  double rhs[NGF];
+  double ricci_resc[6];
+  double H, M_resc[3], C_resc[3];
+} PointOut;
+
+static void bssn_point(const Grid* G, double eta, const double* y, int i0, int i1, int i2,
+                       PointOut* out) {
+  const long long q = flat(G, i0, i1, i2);
+  const long long np = G->np;
+  const double xx[3] = {xx_of(G, 0, i0), xx_of(G, 1, i1), xx_of(G, 2, i2)};
+
+  /* ---- 1. finite differences of the rescaled evolved variables --------- */
+  double v[NGF], d1[NGF][3], d2[NGF][3][3], up[NGF][3];
+  for (int g = 0; g < NGF; g++) {
+    const double* f = y + g * np + q;
+    v[g] = f[0];
+    for (int k = 0; k < 3; k++) d1[g][k] = fd_d1(f, G->st[k], G->dxx[k]);
+    for (int k = 0; k < 3; k++)
+      for (int l = k; l < 3; l++) {
+        d2[g][k][l] = k == l ? fd_d2(f, G->st[k], G->dxx[k])
+                             : fd_d11(f, G->st[k], G->st[l], G->dxx[k], G->dxx[l]);
+        d2[g][l][k] = d2[g][k][l];
+      }
+  }
+  /* Reading: the upwind side is chosen by the sign of the shift component
+   * (vet^k > 0: stencil shifted toward +k, else toward -k).                 */
+  for (int g = 0; g < NGF; g++) {
+    const double* f = y + g * np + q;
+    for (int k = 0; k < 3; k++)
+      up[g][k] = v[VETU0 + k] > 0.0 ? fd_up(f, G->st[k], G->dxx[k]) : fd_dn(f, G->st[k], G->dxx[k]);
+  }
+
+  /* ---- 2. reference metric (analytic): gammahat_ij = S_i^2 delta_ij ---- */
+  double S[3], dS[3][3], ddS[3][3][3];
+  scale_factors(G, xx, S, dS, ddS);
+  double gh[3][3] = {{0}}, dgh[3][3][3] = {{{0}}}, ddgh[3][3][3][3] = {{{{0}}}};
+  for (int i = 0; i < 3; i++) {
+    gh[i][i] = S[i] * S[i];
+    for (int k = 0; k < 3; k++) {
+      dgh[i][i][k] = 2.0 * S[i] * dS[i][k];
+      for (int l = 0; l < 3; l++)
+        ddgh[i][i][k][l] = 2.0 * (dS[i][l] * dS[i][k] + S[i] * ddS[i][k][l]);
+    }
+  }
+  double ghUU[3][3];
+  inverse3(gh, ghUU);
+  /* Christoffel symbols of gammahat and their derivatives:
+   * Gh[i][j][k] = Gammahat^i_jk, dGh[i][j][k][l] = d_l Gammahat^i_jk       */
+  double Gh[3][3][3], dGh[3][3][3][3];
+  double dghUU[3][3][3]; /* d_l gammahat^ij */
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++)
+      for (int l = 0; l < 3; l++) {
+        double s = 0.0;
+        for (int a = 0; a < 3; a++)
+          for (int b = 0; b < 3; b++) s -= ghUU[i][a] * dgh[a][b][l] * ghUU[b][j];
+        dghUU[i][j][l] = s;
+      }
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++)
+      for (int k = 0; k < 3; k++) {
+        double s = 0.0;
+        for (int m = 0; m < 3; m++)
+          s += 0.5 * ghUU[i][m] * (dgh[m][k][j] + dgh[m][j][k] - dgh[j][k][m]);
+        Gh[i][j][k] = s;
+        for (int l = 0; l < 3; l++) {
+          double t = 0.0;
+          for (int m = 0; m < 3; m++)
+            t += 0.5 * dghUU[i][m][l] * (dgh[m][k][j] + dgh[m][j][k] - dgh[j][k][m]) +
+                 0.5 * ghUU[i][m] * (ddgh[m][k][j][l] + ddgh[m][j][k][l] - ddgh[j][k][m][l]);
+          dGh[i][j][k][l] = t;
+        }
+      }
+
+  /* ---- 3. unrescale (Sec. 2.2): eps_ij = h_ij S_i S_j, Abar likewise,
+   *      Lambdabar^i = lambda^i / S_i, beta^i = vet^i / S_i, B^i = bet^i / S_i,
+   *      derivatives by the product rule with analytic derivatives of S.   */
+  double ReDD[3][3], dReDD[3][3][3], ddReDD[3][3][3][3];
+  double ReU[3], dReU[3][3], ddReU[3][3][3];
+  for (int i = 0; i < 3; i++) {
+    ReU[i] = 1.0 / S[i];
+    for (int k = 0; k < 3; k++) {
+      dReU[i][k] = -dS[i][k] / (S[i] * S[i]);
+      for (int l = 0; l < 3; l++)
+        ddReU[i][k][l] = -ddS[i][k][l] / (S[i] * S[i]) +
+                         2.0 * dS[i][k] * dS[i][l] / (S[i] * S[i] * S[i]);
+    }
+    for (int j = 0; j < 3; j++) {
+      ReDD[i][j] = S[i] * S[j];
+      for (int k = 0; k < 3; k++) {
+        dReDD[i][j][k] = dS[i][k] * S[j] + S[i] * dS[j][k];
+        for (int l = 0; l < 3; l++)
+          ddReDD[i][j][k][l] = ddS[i][k][l] * S[j] + dS[i][k] * dS[j][l] +
+                               dS[i][l] * dS[j][k] + S[i] * ddS[j][k][l];
+      }
+    }
+  }
+  double eps[3][3], deps[3][3][3], ddeps[3][3][3][3], deps_up[3][3][3];
+  double Abar[3][3], dAbar[3][3][3], dAbar_up[3][3][3];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      const int gh_ = HDD00 + SYM[i][j], ga = ADD00 + SYM[i][j];
+      eps[i][j] = v[gh_] * ReDD[i][j];
+      Abar[i][j] = v[ga] * ReDD[i][j];
+      for (int k = 0; k < 3; k++) {
+        deps[i][j][k] = d1[gh_][k] * ReDD[i][j] + v[gh_] * dReDD[i][j][k];
+        deps_up[i][j][k] = up[gh_][k] * ReDD[i][j] + v[gh_] * dReDD[i][j][k];
+        dAbar[i][j][k] = d1[ga][k] * ReDD[i][j] + v[ga] * dReDD[i][j][k];
+        dAbar_up[i][j][k] = up[ga][k] * ReDD[i][j] + v[ga] * dReDD[i][j][k];
+        for (int l = 0; l < 3; l++)
+          ddeps[i][j][k][l] = d2[gh_][k][l] * ReDD[i][j] + d1[gh_][k] * dReDD[i][j][l] +
+                              d1[gh_][l] * dReDD[i][j][k] + v[gh_] * ddReDD[i][j][k][l];
+      }
+    }
+  double Lam[3], dLam[3][3], dLam_up[3][3];
+  double beta[3], dbeta[3][3], ddbeta[3][3][3], dbeta_up[3][3];
+  double B[3], dB_up[3][3];
+  for (int i = 0; i < 3; i++) {
+    const int gl = LAMU0 + i, gv = VETU0 + i, gb = BETU0 + i;
+    Lam[i] = v[gl] * ReU[i];
+    beta[i] = v[gv] * ReU[i];
+    B[i] = v[gb] * ReU[i];
+    for (int k = 0; k < 3; k++) {
+      dLam[i][k] = d1[gl][k] * ReU[i] + v[gl] * dReU[i][k];
+      dLam_up[i][k] = up[gl][k] * ReU[i] + v[gl] * dReU[i][k];
+      dbeta[i][k] = d1[gv][k] * ReU[i] + v[gv] * dReU[i][k];
+      dbeta_up[i][k] = up[gv][k] * ReU[i] + v[gv] * dReU[i][k];
+      dB_up[i][k] = up[gb][k] * ReU[i] + v[gb] * dReU[i][k];
+      for (int l = 0; l < 3; l++)
+        ddbeta[i][k][l] = d2[gv][k][l] * ReU[i] + d1[gv][k] * dReU[i][l] +
+                          d1[gv][l] * dReU[i][k] + v[gv] * ddReU[i][k][l];
+    }
+  }
+  const double W = v[CF], K = v[TRK], alpha = v[ALPHA];
+  double dW[3], ddW[3][3], dW_up[3], dK[3], dK_up[3], dalpha[3], ddalpha[3][3], dalpha_up[3];
+  for (int k = 0; k < 3; k++) {
+    dW[k] = d1[CF][k]; dW_up[k] = up[CF][k];
+    dK[k] = d1[TRK][k]; dK_up[k] = up[TRK][k];
+    dalpha[k] = d1[ALPHA][k]; dalpha_up[k] = up[ALPHA][k];
+    for (int l = 0; l < 3; l++) { ddW[k][l] = d2[CF][k][l]; ddalpha[k][l] = d2[ALPHA][k][l]; }
+  }
+
+  /* ---- 4. conformal metric, Eq. 3: gammabar_ij = gammahat_ij + eps_ij --- */
+  double gb[3][3], gbUU[3][3], dgb[3][3][3], ddgb[3][3][3][3];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      gb[i][j] = gh[i][j] + eps[i][j];
+      for (int k = 0; k < 3; k++) {
+        dgb[i][j][k] = dgh[i][j][k] + deps[i][j][k];
+        for (int l = 0; l < 3; l++) ddgb[i][j][k][l] = ddgh[i][j][k][l] + ddeps[i][j][k][l];
+      }
+    }
+  inverse3(gb, gbUU);
+
+  /* ---- 5. connection difference, Eqs. 4-5. Eq. 4 is evaluated in the
+   * equivalent reference-covariant form
+   *   Delta^k_ij = 1/2 gammabar^kl (Dhat_i eps_lj + Dhat_j eps_il - Dhat_l eps_ij),
+   * Dhat_k eps_ij = d_k eps_ij - Gammahat^m_ki eps_mj - Gammahat^m_kj eps_im
+   * (Dhat gammahat = 0), which vanishes exactly when eps does.             */
+  double Dhat_eps[3][3][3]; /* [i][j][k] = Dhat_k eps_ij */
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++)
+      for (int k = 0; k < 3; k++) {
+        double s = deps[i][j][k];
+        for (int m = 0; m < 3; m++) s -= Gh[m][k][i] * eps[m][j] + Gh[m][k][j] * eps[i][m];
+        Dhat_eps[i][j][k] = s;
+      }
+  double DeltaUDD[3][3][3], DeltaU[3], DeltaDDD[3][3][3], Gb[3][3][3];
+  for (int k = 0; k < 3; k++)
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) {
+        double s = 0.0;
+        for (int l = 0; l < 3; l++)
+          s += 0.5 * gbUU[k][l] * (Dhat_eps[l][j][i] + Dhat_eps[i][l][j] - Dhat_eps[i][j][l]);
+        DeltaUDD[k][i][j] = s;
+        Gb[k][i][j] = Gh[k][i][j] + s; /* Gammabar = Gammahat + Delta (Eq. 4) */
+      }
+  for (int k = 0; k < 3; k++) {
+    double s = 0.0;
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) s += gbUU[i][j] * DeltaUDD[k][i][j];
+    DeltaU[k] = s; /* Eq. 5 */
+  }
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++)
+      for (int k = 0; k < 3; k++) {
+        double s = 0.0;
+        for (int l = 0; l < 3; l++) s += gb[i][l] * DeltaUDD[l][j][k];
+        DeltaDDD[i][j][k] = s; /* Delta_ijk = gammabar_il Delta^l_jk */
+      }
+
+  /* ---- 6. conformal Ricci tensor, Eq. 12 ------------------------------- */
+  /* d_k (Dhat_l eps_ij) and Dhat_k Dhat_l eps_ij (= Dhat_k Dhat_l gammabar_ij) */
+  double DDeps[3][3][3][3]; /* [i][j][l][k] = Dhat_k Dhat_l eps_ij */
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++)
+      for (int l = 0; l < 3; l++)
+        for (int k = 0; k < 3; k++) {
+          double dD = ddeps[i][j][l][k];
+          for (int m = 0; m < 3; m++)
+            dD -= dGh[m][l][i][k] * eps[m][j] + Gh[m][l][i] * deps[m][j][k] +
+                  dGh[m][l][j][k] * eps[i][m] + Gh[m][l][j] * deps[i][m][k];
+          double s = dD;
+          for (int m = 0; m < 3; m++)
+            s -= Gh[m][k][l] * Dhat_eps[i][j][m] + Gh[m][k][i] * Dhat_eps[m][j][l] +
+                 Gh[m][k][j] * Dhat_eps[i][m][l];
+          DDeps[i][j][l][k] = s;
+        }
+  double DhatLam[3][3]; /* [k][j] = Dhat_j Lambdabar^k */
+  for (int k = 0; k < 3; k++)
+    for (int j = 0; j < 3; j++) {
+      double s = dLam[k][j];
+      for (int m = 0; m < 3; m++) s += Gh[k][j][m] * Lam[m];
+      DhatLam[k][j] = s;
+    }
+  double R[3][3];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      double s = 0.0;
+      for (int k = 0; k < 3; k++)
+        for (int l = 0; l < 3; l++) s += -0.5 * gbUU[k][l] * DDeps[i][j][l][k];
+      for (int k = 0; k < 3; k++)
+        s += 0.5 * (gb[k][i] * DhatLam[k][j] + gb[k][j] * DhatLam[k][i]);
+      for (int k = 0; k < 3; k++) s += 0.5 * DeltaU[k] * (DeltaDDD[i][j][k] + DeltaDDD[j][i][k]);
+      for (int k = 0; k < 3; k++)
+        for (int l = 0; l < 3; l++)
+          for (int m = 0; m < 3; m++)
+            s += gbUU[k][l] * (DeltaUDD[m][k][i] * DeltaDDD[j][m][l] +
+                               DeltaUDD[m][k][j] * DeltaDDD[i][m][l] +
+                               DeltaUDD[m][i][k] * DeltaDDD[m][j][l]);
+      R[i][j] = s;
+    }
+
+  /* ---- 7. conformal factor: W = exp(-2 phi) (Sec. 2.1 after Eq. 2) ----- */
+  double phi_d[3], phi_dd[3][3];
+  for (int i = 0; i < 3; i++) phi_d[i] = -dW[i] / (2.0 * W);
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) phi_dd[i][j] = -ddW[i][j] / (2.0 * W) + dW[i] * dW[j] / (2.0 * W * W);
+  const double em4phi = W * W; /* exp(-4 phi) */
+
+  /* ---- 8. covariant derivatives and contractions ----------------------- */
+  double DbDb_alpha[3][3], DbDb_phi[3][3];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      double a = ddalpha[i][j], b = phi_dd[i][j];
+      for (int k = 0; k < 3; k++) { a -= Gb[k][i][j] * dalpha[k]; b -= Gb[k][i][j] * phi_d[k]; }
+      DbDb_alpha[i][j] = a;
+      DbDb_phi[i][j] = b;
+    }
+  double Dbar_beta = 0.0; /* Dbar_k beta^k = d_k beta^k + Gammabar^k_km beta^m */
+  for (int k = 0; k < 3; k++) {
+    Dbar_beta += dbeta[k][k];
+    for (int m = 0; m < 3; m++) Dbar_beta += Gb[k][k][m] * beta[m];
+  }
+  double Dhat_betaU[3][3]; /* [i][j] = Dhat_j beta^i */
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      double s = dbeta[i][j];
+      for (int m = 0; m < 3; m++) s += Gh[i][j][m] * beta[m];
+      Dhat_betaU[i][j] = s;
+    }
+  double Dhat_betaD[3][3]; /* [i][j] = Dhat_i beta_j, beta_j = gammahat_jm beta^m */
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      double s = 0.0;
+      for (int m = 0; m < 3; m++) s += gh[j][m] * Dhat_betaU[m][i];
+      Dhat_betaD[i][j] = s;
+    }
+  double AbarUD[3][3], AbarUU[3][3];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      double s = 0.0;
+      for (int k = 0; k < 3; k++) s += gbUU[i][k] * Abar[k][j];
+      AbarUD[i][j] = s;
+    }
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      double s = 0.0;
+      for (int k = 0; k < 3; k++)
+        for (int l = 0; l < 3; l++) s += gbUU[i][k] * gbUU[j][l] * Abar[k][l];
+      AbarUU[i][j] = s;
+    }
+  double trAbar = 0.0, AbarAbar = 0.0;
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      trAbar += gbUU[i][j] * Abar[i][j];
+      AbarAbar += Abar[i][j] * AbarUU[i][j];
+    }
+
+  /* ---- 9. Eq. 7: d_perp eps_ij; d_t = d_perp + Lie_beta ----------------
+   * Reading: beta_j in Eq. 7 is lowered with gammahat, so that
+   * 2 Dhat_(i beta_j) = Lie_beta gammahat_ij.                              */
+  double rhs_eps[3][3];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      const double dperp = 2.0 / 3.0 * gb[i][j] * (alpha * trAbar - Dbar_beta) +
+                           Dhat_betaD[i][j] + Dhat_betaD[j][i] - 2.0 * alpha * Abar[i][j];
+      double lie = 0.0;
+      for (int k = 0; k < 3; k++)
+        lie += beta[k] * deps_up[i][j][k] + eps[k][j] * dbeta[k][i] + eps[i][k] * dbeta[k][j];
+      rhs_eps[i][j] = dperp + lie;
+    }
+
+  /* ---- 10. Eq. 8: d_perp Abar_ij --------------------------------------- */
+  double X[3][3];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++)
+      X[i][j] = -2.0 * alpha * DbDb_phi[i][j] + 4.0 * alpha * phi_d[i] * phi_d[j] +
+                2.0 * (dalpha[i] * phi_d[j] + dalpha[j] * phi_d[i]) - DbDb_alpha[i][j] +
+                alpha * R[i][j];
+  double trX = 0.0;
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) trX += gbUU[i][j] * X[i][j];
+  double rhs_Abar[3][3];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      const double XTF = X[i][j] - 1.0 / 3.0 * gb[i][j] * trX;
+      double AA = 0.0;
+      for (int k = 0; k < 3; k++) AA += Abar[i][k] * AbarUD[k][j];
+      const double dperp = -2.0 / 3.0 * Abar[i][j] * Dbar_beta - 2.0 * alpha * AA +
+                           alpha * Abar[i][j] * K + em4phi * XTF;
+      double lie = 0.0;
+      for (int k = 0; k < 3; k++)
+        lie += beta[k] * dAbar_up[i][j][k] + Abar[k][j] * dbeta[k][i] + Abar[i][k] * dbeta[k][j];
+      rhs_Abar[i][j] = dperp + lie;
+    }
+
+  /* ---- 11. Eq. 9: d_perp W;  Eq. 10: d_perp K ------------------------- */
+  double advW = 0.0, advK = 0.0, advAlpha = 0.0;
+  for (int k = 0; k < 3; k++) {
+    advW += beta[k] * dW_up[k];
+    advK += beta[k] * dK_up[k];
+    advAlpha += beta[k] * dalpha_up[k];
+  }
+  const double rhs_W = -1.0 / 3.0 * W * (Dbar_beta - alpha * K) + advW;
+  double lap_alpha = 0.0, dalpha_dphi = 0.0;
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      lap_alpha += gbUU[i][j] * DbDb_alpha[i][j];
+      dalpha_dphi += gbUU[i][j] * dalpha[i] * phi_d[j];
+    }
+  const double rhs_K = 1.0 / 3.0 * alpha * K * K + alpha * AbarAbar -
+                       em4phi * (lap_alpha + 2.0 * dalpha_dphi) + advK;
+
+  /* ---- 12. Eq. 11: d_perp Lambdabar^i ---------------------------------
+   * Reading: the printed equation lacks lapse factors; the terms are
+   * -2 Abar^ij (d_j alpha - 6 alpha d_j phi) + 2 alpha Abar^jk Delta^i_jk,
+   * the form that follows from adding alpha times the momentum constraint
+   * (Eq. 17) and the only one under which the constraints are preserved.   */
+  double DhatDhat_beta[3][3][3]; /* [i][k][j] = Dhat_j Dhat_k beta^i */
+  for (int i = 0; i < 3; i++)
+    for (int k = 0; k < 3; k++)
+      for (int j = 0; j < 3; j++) {
+        double s = ddbeta[i][k][j]; /* d_j (Dhat_k beta^i) */
+        for (int m = 0; m < 3; m++) s += dGh[i][k][m][j] * beta[m] + Gh[i][k][m] * dbeta[m][j];
+        for (int m = 0; m < 3; m++)
+          s += Gh[i][j][m] * Dhat_betaU[m][k] - Gh[m][j][k] * Dhat_betaU[i][m];
+        DhatDhat_beta[i][k][j] = s;
+      }
+  /* d_k Gammabar^j_jm = 1/2 d_k (gammabar^jl d_m gammabar_jl)             */
+  double dGbc[3][3]; /* [m][k] */
+  for (int m = 0; m < 3; m++)
+    for (int k = 0; k < 3; k++) {
+      double s = 0.0;
+      for (int j = 0; j < 3; j++)
+        for (int l = 0; l < 3; l++) {
+          double dUU = 0.0; /* d_k gammabar^jl */
+          for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) dUU -= gbUU[j][a] * gbUU[l][b] * dgb[a][b][k];
+          s += 0.5 * (dUU * dgb[j][l][m] + gbUU[j][l] * ddgb[j][l][k][m]);
+        }
+      dGbc[m][k] = s;
+    }
+  double Gbc[3]; /* Gammabar^j_jm */
+  for (int m = 0; m < 3; m++) {
+    Gbc[m] = 0.0;
+    for (int j = 0; j < 3; j++) Gbc[m] += Gb[j][j][m];
+  }
+  double dDbar_beta[3]; /* d_k (Dbar_j beta^j) */
+  for (int k = 0; k < 3; k++) {
+    double s = 0.0;
+    for (int j = 0; j < 3; j++) s += ddbeta[j][j][k];
+    for (int m = 0; m < 3; m++) s += dGbc[m][k] * beta[m] + Gbc[m] * dbeta[m][k];
+    dDbar_beta[k] = s;
+  }
+  double rhs_Lam[3];
+  for (int i = 0; i < 3; i++) {
+    double t2 = 0.0, t4 = 0.0, t5 = 0.0, t6 = 0.0, t7 = 0.0;
+    for (int j = 0; j < 3; j++)
+      for (int k = 0; k < 3; k++) t2 += gbUU[j][k] * DhatDhat_beta[i][k][j];
+    const double t3 = 2.0 / 3.0 * DeltaU[i] * Dbar_beta;
+    for (int k = 0; k < 3; k++) t4 += gbUU[i][k] * dDbar_beta[k];
+    t4 *= 1.0 / 3.0;
+    for (int j = 0; j < 3; j++) t5 += -2.0 * AbarUU[i][j] * (dalpha[j] - 6.0 * alpha * phi_d[j]);
+    for (int j = 0; j < 3; j++)
+      for (int k = 0; k < 3; k++) t6 += 2.0 * alpha * AbarUU[j][k] * DeltaUDD[i][j][k];
+    for (int j = 0; j < 3; j++) t7 += -4.0 / 3.0 * alpha * gbUU[i][j] * dK[j];
+    double lie = 0.0; /* Lie_beta Lambdabar^i = beta^k d_k Lambdabar^i - Lambdabar^k d_k beta^i */
+    for (int k = 0; k < 3; k++) lie += beta[k] * dLam_up[i][k] - Lam[k] * dbeta[i][k];
+    rhs_Lam[i] = t2 + t3 + t4 + t5 + t6 + t7 + lie;
+  }
+
+  /* ---- 13. gauge, Eqs. 13-15. Reading: d_t Lambdabar^i in Eq. 15 is the
+   * full right-hand side of Lambdabar^i just computed.                     */
+  const double rhs_alpha = -2.0 * alpha * K + advAlpha;
+  double rhs_beta[3], rhs_B[3];
+  for (int i = 0; i < 3; i++) {
+    double ab = 0.0, aB = 0.0;
+    for (int j = 0; j < 3; j++) { ab += beta[j] * dbeta_up[i][j]; aB += beta[j] * dB_up[i][j]; }
+    rhs_beta[i] = B[i] + ab;
+    rhs_B[i] = 0.75 * rhs_Lam[i] - eta * B[i] + aB;
+  }
+
+  /* ---- 14. rescale the right-hand sides (Sec. 2.2) -------------------- */
+  for (int i = 0; i < 3; i++)
+    for (int j = i; j < 3; j++) {
+      out->rhs[HDD00 + SYM[i][j]] = rhs_eps[i][j] / ReDD[i][j];
+      out->rhs[ADD00 + SYM[i][j]] = rhs_Abar[i][j] / ReDD[i][j];
+      out->ricci_resc[SYM[i][j]] = R[i][j] / ReDD[i][j];
+    }
+  for (int i = 0; i < 3; i++) {
+    out->rhs[LAMU0 + i] = rhs_Lam[i] / ReU[i];
+    out->rhs[VETU0 + i] = rhs_beta[i] / ReU[i];
+    out->rhs[BETU0 + i] = rhs_B[i] / ReU[i];
+  }
+  out->rhs[CF] = rhs_W;
+  out->rhs[TRK] = rhs_K;
+  out->rhs[ALPHA] = rhs_alpha;
+
+  /* ---- 15. constraints: Eq. 16 (H), Eq. 17 (M^i), C^i ------------------ */
+  double Rtr = 0.0, dphi2 = 0.0, lap_phi = 0.0;
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      Rtr += gbUU[i][j] * R[i][j];
+      dphi2 += gbUU[i][j] * phi_d[i] * phi_d[j];
+      lap_phi += gbUU[i][j] * DbDb_phi[i][j];
+    }
+  out->H = 2.0 / 3.0 * K * K - AbarAbar + em4phi * (Rtr - 8.0 * dphi2 - 8.0 * lap_phi);
+
+  double dgbUU[3][3][3]; /* d_k gammabar^ij */
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++)
+      for (int k = 0; k < 3; k++) {
+        double s = 0.0;
+        for (int a = 0; a < 3; a++)
+          for (int b = 0; b < 3; b++) s -= gbUU[i][a] * dgb[a][b][k] * gbUU[b][j];
+        dgbUU[i][j][k] = s;
+      }
+  double dAbarUU[3][3][3]; /* d_k Abar^ij */
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++)
+      for (int k = 0; k < 3; k++) {
+        double s = 0.0;
+        for (int a = 0; a < 3; a++)
+          for (int b = 0; b < 3; b++)
+            s += dgbUU[i][a][k] * gbUU[j][b] * Abar[a][b] + gbUU[i][a] * dgbUU[j][b][k] * Abar[a][b] +
+                 gbUU[i][a] * gbUU[j][b] * dAbar[a][b][k];
+        dAbarUU[i][j][k] = s;
+      }
+  for (int i = 0; i < 3; i++) {
+    double div = 0.0; /* Dhat_j Abar^ij */
+    for (int j = 0; j < 3; j++) {
+      div += dAbarUU[i][j][j];
+      for (int m = 0; m < 3; m++) div += Gh[i][j][m] * AbarUU[m][j] + Gh[j][j][m] * AbarUU[i][m];
+    }
+    double sym = 0.0; /* 2 Abar^k(i Delta^j)_jk */
+    for (int j = 0; j < 3; j++)
+      for (int k = 0; k < 3; k++)
+        sym += AbarUU[k][i] * DeltaUDD[j][j][k] + AbarUU[k][j] * DeltaUDD[i][j][k];
+    double t6 = 0.0, tK = 0.0;
+    for (int j = 0; j < 3; j++) {
+      t6 += 6.0 * AbarUU[i][j] * phi_d[j];
+      tK += -2.0 / 3.0 * gbUU[i][j] * dK[j];
+    }
+    out->M_resc[i] = em4phi * (div + sym + t6 + tK) * S[i];
+    out->C_resc[i] = (Lam[i] - DeltaU[i]) * S[i];
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+static void interior_index(const Grid* G, long long t, int* i0, int* i1, int* i2) {
+  const int ng = G->p.ng;
+  const long long N0 = G->p.N[0], N1 = G->p.N[1];
+  *i0 = ng + (int)(t % N0);
+  *i1 = ng + (int)((t / N0) % N1);
+  *i2 = ng + (int)(t / (N0 * N1));
+}
+
+int oracle_rhs(const oracle_params* p, double eta, const double* y, double* rhs) {
+  Grid G;
+  if (grid_setup(p, &G)) return -1;
+  const long long nint = (long long)p->N[0] * p->N[1] * p->N[2];
+#pragma omp parallel for schedule(static)
+  for (long long t = 0; t < nint; t++) {
+    int i0, i1, i2;
+    interior_index(&G, t, &i0, &i1, &i2);
+    PointOut o;
+    bssn_point(&G, eta, y, i0, i1, i2, &o);
+    const long long q = flat(&G, i0, i1, i2);
+    for (int g = 0; g < NGF; g++) rhs[g * G.np + q] = o.rhs[g];
+  }
+  return 0;
+}
+
+int oracle_rhs_points(const oracle_params* p, double eta, const double* y, int npts,
+                      const long long* idx, double* out, double* ricci) {
+  Grid G;
+  if (grid_setup(p, &G)) return -1;
+  for (int t = 0; t < npts; t++) {
+    const long long q = idx[t];
+    const int i0 = (int)(q % G.n[0]), i1 = (int)((q / G.n[0]) % G.n[1]),
+              i2 = (int)(q / ((long long)G.n[0] * G.n[1]));
+    if (!is_interior(&G, i0, i1, i2)) return -1;
+  }
+#pragma omp parallel for schedule(static)
+  for (int t = 0; t < npts; t++) {
+    const long long q = idx[t];
+    const int i0 = (int)(q % G.n[0]), i1 = (int)((q / G.n[0]) % G.n[1]),
+              i2 = (int)(q / ((long long)G.n[0] * G.n[1]));
+    PointOut o;
+    bssn_point(&G, eta, y, i0, i1, i2, &o);
+    for (int g = 0; g < NGF; g++) out[(long long)NGF * t + g] = o.rhs[g];
+    if (ricci)
+      for (int c = 0; c < 6; c++) ricci[6LL * t + c] = o.ricci_resc[c];
+  }
+  return 0;
+}
+
+int oracle_constraints(const oracle_params* p, const double* y, double* H, double* M, double* C) {
+  Grid G;
+  if (grid_setup(p, &G)) return -1;
+  const long long nint = (long long)p->N[0] * p->N[1] * p->N[2];
+#pragma omp parallel for schedule(static)
+  for (long long t = 0; t < nint; t++) {
+    int i0, i1, i2;
+    interior_index(&G, t, &i0, &i1, &i2);
+    PointOut o;
+    bssn_point(&G, 0.0, y, i0, i1, i2, &o);
+    const long long q = flat(&G, i0, i1, i2);
+    if (H) H[q] = o.H;
+    for (int i = 0; i < 3; i++) {
+      if (M) M[i * G.np + q] = o.M_resc[i];
+      if (C) C[i * G.np + q] = o.C_resc[i];
+    }
+  }
+  return 0;
+}
+
+/* Classical RK4 (Sec. 4.2.1 footnote) with the ghost fill after each stage
+ * and after the final combination (Sec. 3, boundary steps per substage):
+ *   k1 = f(y_n), y1 = y_n + dt/2 k1; k2 = f(y1), y2 = y_n + dt/2 k2;
+ *   k3 = f(y2), y3 = y_n + dt k3;    k4 = f(y3);
+ *   y_n+1 = y_n + dt/6 (k1 + 2 k2 + 2 k3 + k4). Interior points only.      */
+int oracle_rk4_step(const oracle_params* p, double eta, double dt, double* y) {
+  Grid G;
+  if (grid_setup(p, &G)) return -1;
+  const long long n = NGF * G.np;
+  double* k[4];
+  for (int s = 0; s < 4; s++) k[s] = (double*)calloc((size_t)n, sizeof(double));
+  double* ys = (double*)malloc(sizeof(double) * n);
+  int* kind = (int*)malloc(sizeof(int) * G.np);
+  int* src = (int*)malloc(sizeof(int) * G.np);
+  int* par = (int*)malloc(sizeof(int) * G.np);
+  int rc = build_maps(&G, kind, src, par);
+  if (rc == 0) {
+    const double c[3] = {0.5, 0.5, 1.0};
+    memcpy(ys, y, sizeof(double) * n);
+    for (int s = 0; s < 4; s++) {
+      oracle_rhs(p, eta, ys, k[s]);
+      if (s == 3) break;
+      for (long long t = 0; t < G.np; t++)
+        if (kind[t] == 0)
+          for (int g = 0; g < NGF; g++)
+            ys[g * G.np + t] = y[g * G.np + t] + c[s] * dt * k[s][g * G.np + t];
+      apply_bcs_with_maps(&G, kind, src, par, ys);
+    }
+    for (long long t = 0; t < G.np; t++)
+      if (kind[t] == 0)
+        for (int g = 0; g < NGF; g++) {
+          const long long e = g * G.np + t;
+          y[e] = y[e] + dt / 6.0 * (k[0][e] + 2.0 * k[1][e] + 2.0 * k[2][e] + k[3][e]);
+        }
+    apply_bcs_with_maps(&G, kind, src, par, y);
+  }
+  for (int s = 0; s < 4; s++) free(k[s]);
+  free(ys); free(kind); free(src); free(par);
+  return rc;
+}
+
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

@@ -1,0 +1,354 @@
+"""Pins of the oracle's right-hand sides (Sec. 2.1 Eqs. 7-16, rescaling of
+Sec. 2.2) against facts the paper and the mathematics fix.
+
+Convergence checks evaluate analytic data at every point (ghosts included),
+so they test the discrete operator alone; errors are taken at coarse points
+that are also fine points after 3x refinement of a cell-centred grid, where
+4th-order finite differences give an error ratio near 3^4 = 81 (2nd order
+would give 9; a wrong or missing term gives about 1).
+"""
+import numpy as np
+import pytest
+
+import analytic as an
+from oracle import oracle as orc
+
+RATIO_MIN = 30.0
+KS_RATIO_MIN = 20.0  # strong-field case, not fully asymptotic at these sizes
+
+
+def _refine(Nc, r=3):
+    return tuple(n * r if n > 2 else n for n in Nc)
+
+
+def _common_index(Nc, fine):
+    c, f = an.common_points(Nc, ratio=tuple(3 if n > 2 else 1 for n in Nc))
+    return np.ix_(*(f if fine else c)[::-1])
+
+
+# ---------------------------------------------------------------- flat space
+@pytest.mark.parametrize("coord,N", [(an.SINH_SPHERICAL, (8, 6, 4)), (an.SINH_CYLINDRICAL, (8, 4, 10)),
+                                     (an.SPHERICAL, (6, 6, 6)), (an.SINH_SPHERICAL, (32, 16, 2))])
+def test_flat_space_rhs_and_constraints_exactly_zero(coord, N):
+    g = orc.Grid(coord, N, ampl=(10.0,) * 3)
+    y = g.brill_lindquist([], np.zeros((0, 3)), lapse_kind=1)
+    rhs = g.rhs(y, eta=2.0)
+    H, M, C = g.constraints(y)
+    I = g.interior()
+    assert np.all(rhs[(slice(None),) + I] == 0.0)
+    assert np.all(H[I] == 0.0) and np.all(M[(slice(None),) + I] == 0.0) and np.all(C[(slice(None),) + I] == 0.0)
+
+
+def test_initial_data_matches_definition():
+    coord, N, ampl, w = an.SINH_SPHERICAL, (12, 8, 6), (4.0,) * 3, (0.3,) * 3
+    g = orc.Grid(coord, N, ampl=ampl, sinhw=w)
+    m, pos = [0.6, 0.4], [(0.7, 0.0, 0.0), (-0.7, 0.0, 0.0)]
+    y = g.brill_lindquist(m, pos)
+    ex = an.bl_state(coord, N, ampl, w, m, pos)
+    I = (slice(None),) + g.interior()
+    assert np.allclose(y[I], ex[I], rtol=1e-14, atol=0)
+
+
+# ------------------------------------------------- Brill-Lindquist closed form
+BL_CASES = [
+    # 3D: one puncture off the axis (SinhSpherical)
+    (an.SINH_SPHERICAL, (12, 8, 8), (4.0,) * 3, (0.3,) * 3, [1.0], [(0.3, 0.2, 0.4)]),
+    # head-on pair on the z axis (SinhCylindrical)
+    (an.SINH_CYLINDRICAL, (12, 2, 24), (4.0,) * 3, (0.3,) * 3, [0.5, 0.5], [(0, 0, 0.5), (0, 0, -0.5)]),
+]
+
+
+def _away(x, pos, rp, rmax):
+    ok = np.sqrt(np.sum(x * x, -1)) < rmax
+    for c in pos:
+        ok &= np.sqrt(np.sum((x - np.asarray(c)) ** 2, -1)) > rp
+    return ok
+
+
+@pytest.mark.parametrize("coord,Nc,ampl,w,m,pos", BL_CASES)
+def test_bl_rhs_converges_to_closed_form(coord, Nc, ampl, w, m, pos):
+    """d_t K = -2 psi^-8 |grad psi|^2, d_t a_ij = -8 psi^-8 (psi_i psi_j -
+    delta_ij |grad psi|^2/3) in the rescaled frame, every other RHS exactly 0
+    (conformally flat, time-symmetric data with alpha = psi^-2, beta = 0)."""
+    errs = []
+    for fine in (False, True):
+        N = _refine(Nc) if fine else Nc
+        g = orc.Grid(coord, N, ampl=ampl, sinhw=w)
+        y = an.bl_state(coord, N, ampl, w, m, pos)
+        rhs = g.rhs(y, eta=2.0)
+        ex = an.bl_rhs_closed_form(coord, N, ampl, w, m, pos)
+        I = g.interior()
+        for gi, name in enumerate(an.GF_NAMES):
+            if name != "trK" and not name.startswith("aDD"):
+                assert np.all(rhs[gi][I] == 0.0), name
+        _, x, _ = an.mesh(coord, N, ampl, w)
+        idx = _common_index(Nc, fine)
+        sel = _away(x[idx], pos, 0.6, 0.75 * ampl[0])
+        errs.append({n: np.max(np.abs(rhs[an.GF[n]][idx] - ex[an.GF[n]][idx])[sel])
+                     for n in ("trK", "aDD00", "aDD11", "aDD22", "aDD02")})
+        scale = {n: np.max(np.abs(ex[an.GF[n]][idx])[sel]) for n in errs[-1]}
+    for n in errs[0]:
+        assert errs[1][n] < 1e-2 * scale[n]
+        assert errs[0][n] / errs[1][n] > RATIO_MIN, (n, errs[0][n], errs[1][n])
+
+
+@pytest.mark.parametrize("coord,Nc,ampl,w,m,pos", BL_CASES)
+def test_bl_hamiltonian_constraint_converges_to_zero(coord, Nc, ampl, w, m, pos):
+    """H = 0 for BL data since psi is harmonic away from the punctures (Eq. 16
+    reduces to -8 psi^-5 lap psi); also M^i = C^i = 0."""
+    errs = []
+    for fine in (False, True):
+        N = _refine(Nc) if fine else Nc
+        g = orc.Grid(coord, N, ampl=ampl, sinhw=w)
+        y = an.bl_state(coord, N, ampl, w, m, pos)
+        H, M, C = g.constraints(y)
+        assert np.all(M[(slice(None),) + g.interior()] == 0.0)
+        assert np.all(C[(slice(None),) + g.interior()] == 0.0)
+        _, x, _ = an.mesh(coord, N, ampl, w)
+        idx = _common_index(Nc, fine)
+        sel = _away(x[idx], pos, 0.6, 0.75 * ampl[0])
+        errs.append(np.max(np.abs(H[idx])[sel]))
+    assert errs[0] / errs[1] > RATIO_MIN, errs
+
+
+# ----------------------------------------------- Ricci tensor of a curved metric
+def _ricci_case(coord, N, ampl, w, amp=0.15, sigma=0.8, c=(0.35, -0.2, 0.3)):
+    rng = np.random.default_rng(19)
+    M = rng.uniform(-1, 1, (3, 3))
+    M = M + M.T
+    _, x, E = an.mesh(coord, N, ampl, w)
+    gmet, dg, ddg = an.gaussian_metric(x, amp, M, c, sigma)
+    _, Lam, R = an.christoffel_and_ricci(gmet, dg, ddg)
+    y = np.zeros((an.NGF,) + x.shape[:-1])
+    y[an.GF["cf"]] = 1.0
+    y[an.GF["alpha"]] = 1.0
+    hf = an.to_frame_sym(E, gmet - np.eye(3))
+    lf = an.to_frame_vec(E, Lam)
+    Rf = an.to_frame_sym(E, R)
+    for k, (i, j) in enumerate(an.SYM):
+        y[an.GF["hDD00"] + k] = hf[..., i, j]
+    for i in range(3):
+        y[an.GF["lambdaU0"] + i] = lf[..., i]
+    return y, Rf
+
+
+@pytest.mark.parametrize("coord,Nc,ampl,w", [(an.SINH_SPHERICAL, (12, 8, 8), (2.0,) * 3, (0.4,) * 3),
+                                             (an.SINH_CYLINDRICAL, (10, 8, 12), (2.0,) * 3, (0.4,) * 3)])
+def test_ricci_converges_to_textbook_ricci(coord, Nc, ampl, w):
+    """Eq. 12 with Lambdabar^i = Delta^i equals the Ricci tensor of gammabar
+    computed from its Christoffel symbols, R_bd = d_a G^a_bd - d_d G^a_ba +
+    G^a_ae G^e_bd - G^a_de G^e_ba (here in Cartesian coordinates)."""
+    errs, errs_away = [], []
+    for fine in (False, True):
+        N = _refine(Nc) if fine else Nc
+        g = orc.Grid(coord, N, ampl=ampl, sinhw=w)
+        y, Rf = _ricci_case(coord, N, ampl, w)
+        idx = _common_index(Nc, fine)
+        flat = np.array([g.flat(i0, i1, i2) for i2 in idx[0].ravel() for i1 in idx[1].ravel()
+                         for i0 in idx[2].ravel()])
+        _, ric = g.rhs_points(y, flat, want_ricci=True)
+        ex = np.stack([Rf[idx][..., i, j].ravel() for (i, j) in an.SYM], -1)
+        err = np.abs(ric - ex)
+        errs.append(np.max(err, axis=0))
+        # away from the coordinate singularities, where the 1/(r sin(theta))^2
+        # factors of the curvilinear operators do not amplify the FD error
+        _, x, _ = an.mesh(coord, N, ampl, w)
+        xs = x[idx].reshape(-1, 3)
+        away = np.sqrt(xs[:, 0] ** 2 + xs[:, 1] ** 2) > 0.4
+        errs_away.append(np.max(err[away], axis=0))
+        scale = np.max(np.abs(ex))
+    # 4th-order convergence at every common point, the axis included
+    assert np.all(errs[0] / errs[1] > RATIO_MIN), (errs[0], errs[1])
+    assert np.all(errs_away[1] < 2e-2 * scale), (errs_away[1], scale)
+    assert np.all(errs_away[0] / errs_away[1] > RATIO_MIN), (errs_away[0], errs_away[1])
+
+
+# ------------------------------------------------------------ pure gauge shift
+def _gauge_case(coord, N, ampl, w):
+    (X0, X1, X2), x, E = an.mesh(coord, N, ampl, w)
+    V = (0.3, -0.2, 0.25)
+    L = ((0.2, -0.1, 0.3), (0.15, 0.1, -0.2), (-0.3, 0.25, 0.05))
+    xi, dxi, ddxi = an.gauge_field(x, 0.5, (0.2, -0.3, 0.25), 0.9, V, L)
+    y = np.zeros((an.NGF,) + x.shape[:-1])
+    y[an.GF["cf"]] = 1.0
+    y[an.GF["alpha"]] = 1.0
+    vf = an.to_frame_vec(E, xi)
+    for i in range(3):
+        y[an.GF["vetU0"] + i] = vf[..., i]
+    # closed forms (flat, W = alpha = 1, K = Abar = Lambdabar = B = 0)
+    div = np.einsum("...aa->...", dxi)
+    sym = dxi + np.swapaxes(dxi, -1, -2) - (2.0 / 3.0) * div[..., None, None] * np.eye(3)
+    lap = np.einsum("...abb->...a", ddxi)
+    graddiv = np.einsum("...bba->...a", ddxi)
+    lam_rhs = an.to_frame_vec(E, lap + graddiv / 3.0)
+    adv = np.einsum("...b,...ab->...a", xi, dxi)  # (xi . grad) xi, a tensor
+    S, Gam = an.diag_christoffel(coord, X0, X1, X2, ampl, w)
+    beta = vf / S                                   # coordinate components
+    # d_t beta^i = beta^j d_j beta^i = beta^j Dhat_j beta^i - Gammahat^i_jk beta^j beta^k
+    vet_rhs = an.to_frame_vec(E, adv) - S * np.einsum("...ijk,...j,...k->...i", Gam, beta, beta)
+    ex = np.zeros_like(y)
+    hf = an.to_frame_sym(E, sym)
+    for k, (i, j) in enumerate(an.SYM):
+        ex[an.GF["hDD00"] + k] = hf[..., i, j]
+    for i in range(3):
+        ex[an.GF["lambdaU0"] + i] = lam_rhs[..., i]
+        ex[an.GF["betU0"] + i] = 0.75 * lam_rhs[..., i]
+        ex[an.GF["vetU0"] + i] = vet_rhs[..., i]
+    ex[an.GF["cf"]] = -div / 3.0
+    return y, ex
+
+
+@pytest.mark.parametrize("coord,Nc,ampl,w", [(an.SINH_SPHERICAL, (12, 8, 8), (2.0,) * 3, (0.4,) * 3),
+                                             (an.SINH_CYLINDRICAL, (10, 8, 12), (2.0,) * 3, (0.4,) * 3)])
+def test_pure_gauge_shift_converges_to_closed_form(coord, Nc, ampl, w):
+    """Flat data with a shift beta = xi: d_t gammabar = Lie_xi delta - 2/3 delta
+    div xi, d_t Lambdabar = lap xi + grad div xi / 3, d_t W = -div xi / 3,
+    d_t B = 3/4 d_t Lambdabar, d_t beta^i = beta^j d_j beta^i (coordinate
+    components), d_t of alpha, K, Abar zero."""
+    errs, errs_away = [], []
+    for fine in (False, True):
+        N = _refine(Nc) if fine else Nc
+        g = orc.Grid(coord, N, ampl=ampl, sinhw=w)
+        y, ex = _gauge_case(coord, N, ampl, w)
+        rhs = g.rhs(y, eta=2.0)
+        I = g.interior()
+        for name in ("alpha", "trK", "aDD00", "aDD01", "aDD02", "aDD11", "aDD12", "aDD22"):
+            assert np.all(rhs[an.GF[name]][I] == 0.0), name
+        idx = _common_index(Nc, fine)
+        _, x, _ = an.mesh(coord, N, ampl, w)
+        away = np.sqrt(x[idx][..., 0] ** 2 + x[idx][..., 1] ** 2) > 0.4
+        errs.append(np.array([np.max(np.abs(rhs[gi][idx] - ex[gi][idx])) for gi in range(an.NGF)]))
+        errs_away.append(np.array([np.max(np.abs(rhs[gi][idx] - ex[gi][idx])[away]) for gi in range(an.NGF)]))
+        scale = np.array([np.max(np.abs(ex[gi][idx])) for gi in range(an.NGF)])
+    checked = [n for n in an.GF_NAMES if n.startswith(("hDD", "lambdaU", "betU", "vetU")) or n == "cf"]
+    for n in checked:
+        gi = an.GF[n]
+        assert errs[0][gi] / errs[1][gi] > RATIO_MIN, (n, errs[0][gi], errs[1][gi])
+        assert errs_away[0][gi] / errs_away[1][gi] > RATIO_MIN, (n, errs_away[0][gi], errs_away[1][gi])
+        assert errs_away[1][gi] < 2e-2 * max(scale[gi], 1e-3), n
+
+
+# ---------------------------------------------------------------- RK4 order
+def test_rk4_is_fourth_order_on_uniform_data():
+    """Spatially uniform data reduce the system to the ODEs K' = alpha K^2/3,
+    alpha' = -2 alpha K, W' = alpha K W / 3 (Eqs. 9, 10, 13); RK4's global error
+    falls by 2^4 when dt halves."""
+    from scipy.integrate import solve_ivp
+    K0, T = 0.6, 0.8
+
+    def f(t, u):
+        K, a, W = u
+        return [a * K * K / 3.0, -2.0 * a * K, a * K * W / 3.0]
+    ref = solve_ivp(f, (0, T), [K0, 1.0, 1.0], method="DOP853", rtol=2.5e-14, atol=1e-15).y[:, -1]
+    g = orc.Grid(an.SINH_SPHERICAL, (6, 4, 2), ampl=(2.0,) * 3)
+    errs = []
+    for nsteps in (4, 8, 16):
+        y = g.state()
+        y[an.GF["cf"]] = 1.0
+        y[an.GF["alpha"]] = 1.0
+        y[an.GF["trK"]] = K0
+        for _ in range(nsteps):
+            g.rk4_step(y, T / nsteps, eta=2.0)
+        # stays uniform: ghosts and interior identical
+        assert np.all(y[an.GF["trK"]] == y[an.GF["trK"]].flat[0])
+        u = [y[an.GF[n]].flat[0] for n in ("trK", "alpha", "cf")]
+        errs.append(np.max(np.abs(np.array(u) - ref)))
+    assert 13.0 < errs[0] / errs[1] < 19.0, errs
+    assert 13.0 < errs[1] / errs[2] < 19.0, errs
+
+
+# ------------------------------------- stationary strong field: Kerr-Schild
+def _kerr_schild_case(coord, N, ampl, w, M=1.0, c=(0.2, -0.1, 2.0)):
+    (X0, X1, X2), x, E = an.mesh(coord, N, ampl, w)
+    ks = an.kerr_schild(x, M, c)
+    gam, dgam, gi = ks["gam"], ks["dgam"], ks["gi"]
+    W = np.linalg.det(gam) ** (-1.0 / 6.0)
+    dW = -W[..., None] / 6.0 * np.einsum("...ij,...ijk->...k", gi, dgam)
+    gb = W[..., None, None] ** 2 * gam
+    dgb = (2.0 * W[..., None, None, None] * np.einsum("...ij,...k->...ijk", gam, dW)
+           + W[..., None, None, None] ** 2 * dgam)
+    gbi = np.linalg.inv(gb)
+    Gl = 0.5 * (np.einsum("...dcb->...dbc", dgb) + dgb - np.einsum("...bcd->...dbc", dgb))
+    Lam = np.einsum("...bc,...ad,...dbc->...a", gbi, gbi, Gl)
+    K = np.einsum("...ij,...ij->...", gi, ks["K"])
+    Abar = W[..., None, None] ** 2 * (ks["K"] - gam * K[..., None, None] / 3.0)
+    y = np.zeros((an.NGF,) + x.shape[:-1])
+    hf = an.to_frame_sym(E, gb - np.eye(3))
+    af = an.to_frame_sym(E, Abar)
+    for k, (i, j) in enumerate(an.SYM):
+        y[an.GF["hDD00"] + k] = hf[..., i, j]
+        y[an.GF["aDD00"] + k] = af[..., i, j]
+    lf = an.to_frame_vec(E, Lam)
+    vf = an.to_frame_vec(E, ks["beta"])
+    for i in range(3):
+        y[an.GF["lambdaU0"] + i] = lf[..., i]
+        y[an.GF["vetU0"] + i] = vf[..., i]
+    y[an.GF["cf"]] = W
+    y[an.GF["trK"]] = K
+    y[an.GF["alpha"]] = ks["alpha"]
+    # continuum right-hand sides: the spacetime is stationary in these
+    # coordinates for its own lapse and shift, so every BSSN variable has
+    # d_t = 0; the gauge equations give d_t alpha = -2 alpha K + beta.grad alpha,
+    # d_t beta^i = beta^j d_j beta^i (B = 0), d_t B = 3/4 d_t Lambdabar = 0.
+    ex = np.zeros_like(y)
+    ex[an.GF["alpha"]] = -2.0 * ks["alpha"] * K + np.einsum("...j,...j->...", ks["beta"], ks["dalpha"])
+    adv = np.einsum("...j,...ij->...i", ks["beta"], ks["dbeta"])
+    S, Gh = an.diag_christoffel(coord, X0, X1, X2, ampl, w)
+    bc = vf / S
+    vr = an.to_frame_vec(E, adv) - S * np.einsum("...ijk,...j,...k->...i", Gh, bc, bc)
+    for i in range(3):
+        ex[an.GF["vetU0"] + i] = vr[..., i]
+    return y, ex
+
+
+@pytest.mark.parametrize("coord,Nc,ampl,w", [(an.SINH_SPHERICAL, (12, 8, 8), (1.0,) * 3, (0.6,) * 3),
+                                             (an.SINH_CYLINDRICAL, (10, 8, 12), (1.0,) * 3, (0.6,) * 3)])
+def test_kerr_schild_is_stationary(coord, Nc, ampl, w):
+    """Schwarzschild in Kerr-Schild coordinates (hole centred off the grid, so
+    the data are smooth and strong: W down to ~0.7, K_ij, Abar_ij, eps_ij,
+    beta all O(1)) is time independent under its own lapse and shift. All of
+    Eqs. 7-12 are active, including the terms quadratic in Abar, Delta and
+    eps; their sum must converge to zero at 4th order."""
+    errs, errs_away = [], []
+    for fine in (False, True):
+        N = _refine(Nc) if fine else Nc
+        g = orc.Grid(coord, N, ampl=ampl, sinhw=w)
+        y, ex = _kerr_schild_case(coord, N, ampl, w)
+        rhs = g.rhs(y, eta=2.0)
+        idx = _common_index(Nc, fine)
+        _, x, _ = an.mesh(coord, N, ampl, w)
+        away = np.sqrt(x[idx][..., 0] ** 2 + x[idx][..., 1] ** 2) > 0.2 * ampl[0]
+        errs.append(np.array([np.max(np.abs(rhs[gi][idx] - ex[gi][idx])) for gi in range(an.NGF)]))
+        errs_away.append(np.array([np.max(np.abs(rhs[gi][idx] - ex[gi][idx])[away]) for gi in range(an.NGF)]))
+        mags = np.array([np.max(np.abs(y[gi][idx])) for gi in range(an.NGF)])
+    for n in ("aDD00", "aDD12", "hDD00", "hDD12", "trK", "cf", "lambdaU0", "vetU2"):
+        assert mags[an.GF[n]] > 0.05, n
+    for gi, n in enumerate(an.GF_NAMES):
+        assert errs[0][gi] / errs[1][gi] > KS_RATIO_MIN, (n, errs[0][gi], errs[1][gi])
+        assert errs_away[0][gi] / errs_away[1][gi] > KS_RATIO_MIN, (n, errs_away[0][gi], errs_away[1][gi])
+        assert errs_away[1][gi] < 5e-2, (n, errs_away[1][gi])
+
+
+@pytest.mark.parametrize("coord,N", [(an.SINH_SPHERICAL, (8, 6, 4)), (an.SINH_CYLINDRICAL, (8, 4, 10))])
+def test_gamma_driver_damps_B_on_flat_space(coord, N):
+    """Flat space with beta = 0 and a constant Cartesian B: Eq. 14 gives
+    d_t beta = B and Eq. 15 reduces to d_t B = -eta B (eta damps B); every other
+    right-hand side vanishes."""
+    ampl, w, eta = (3.0,) * 3, (0.3,) * 3, 1.7
+    g = orc.Grid(coord, N, ampl=ampl, sinhw=w)
+    _, x, E = an.mesh(coord, N, ampl, w)
+    y = np.zeros((an.NGF,) + x.shape[:-1])
+    y[an.GF["cf"]] = 1.0
+    y[an.GF["alpha"]] = 1.0
+    bf = an.to_frame_vec(E, np.array([0.3, -0.7, 0.45]))
+    for i in range(3):
+        y[an.GF["betU0"] + i] = bf[..., i]
+    rhs = g.rhs(y, eta=eta)
+    I = g.interior()
+    for gi, n in enumerate(an.GF_NAMES):
+        if n.startswith("betU"):
+            assert np.allclose(rhs[gi][I], -eta * y[gi][I], rtol=1e-14, atol=1e-15)
+        elif n.startswith("vetU"):
+            assert np.allclose(rhs[gi][I], y[an.GF["betU0"] + int(n[-1])][I], rtol=1e-14, atol=1e-15)
+        else:
+            assert np.all(rhs[gi][I] == 0.0), n
