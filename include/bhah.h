@@ -86,8 +86,10 @@ enum bhah_gf {
   BHAH_NUM_GFS /* = 24 */
 };
 
-/* Number of gridfunctions in the `aux` array of bhah_bssn_rhs. */
-#define BHAH_NUM_AUX_GFS 6
+/* Number of gridfunctions in the `aux` array of bhah_bssn_rhs: the rescaled
+ * conformal Ricci tensor Rbar_ij/(S_i S_j) (00,01,02,11,12,22), then
+ * Q_k = (d_k Gammabar^j_jm) beta^m (k = 0,1,2).                              */
+#define BHAH_NUM_AUX_GFS 9
 
 typedef struct bhah_grid bhah_grid;   /* opaque, immutable after create */
 typedef struct bhah_batch bhah_batch; /* opaque ensemble of grids        */
@@ -175,11 +177,12 @@ int bhah_apply_bcs(const bhah_grid* g, double* y, void* stream);
 
 /* BSSN + gauge right-hand sides (Eqs. 7-15 with Eq. 12) of the rescaled
  * variables at every interior point. y must have valid ghosts. rhs has the
- * state layout; only its interior points are written. aux may be NULL; if
- * given it receives BHAH_NUM_AUX_GFS gridfunctions (state layout, interior
- * points) holding the rescaled conformal Ricci tensor Rbar_ij/(S_i S_j) in
- * the order 00,01,02,11,12,22. All 4th-order finite differences, advection
- * terms beta^k d_k upwinded (Sec. 3 second paragraph).                     */
+ * state layout; only its interior points are written. aux receives
+ * BHAH_NUM_AUX_GFS gridfunctions (state layout, interior points) computed on
+ * the way; it may be NULL, in which case a buffer owned by the grid is used
+ * (then calls on the same grid must not overlap in time). All 4th-order
+ * finite differences, advection terms beta^k d_k upwinded (Sec. 3 second
+ * paragraph).                                                               */
 int bhah_bssn_rhs(const bhah_grid* g, const bhah_gauge_params* gp,
                   const double* y, double* rhs, double* aux, void* stream);
 

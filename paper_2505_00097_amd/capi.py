@@ -1,0 +1,231 @@
+"""Thin ctypes binding of libbhah.so (include/bhah.h).
+
+Argument marshalling only: torch tensors supply device memory and streams;
+every step of the evolution runs in the library's HIP kernels. The library
+must have been built (paper_2505_00097_amd/build.py); there is no fallback.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libbhah.so")
+
+NUM_GFS = 24
+NUM_AUX_GFS = 9
+SINH_SPHERICAL, SINH_CYLINDRICAL, SPHERICAL = 0, 1, 2
+OK, EINVAL, EDEVICE, ENOMEM = 0, -1, -2, -3
+GF_NAMES = ["aDD00", "aDD01", "aDD02", "aDD11", "aDD12", "aDD22", "alpha",
+            "betU0", "betU1", "betU2", "cf", "hDD00", "hDD01", "hDD02", "hDD11",
+            "hDD12", "hDD22", "lambdaU0", "lambdaU1", "lambdaU2", "trK",
+            "vetU0", "vetU1", "vetU2"]
+
+
+class GridParams(ctypes.Structure):
+    _fields_ = [("coord", ctypes.c_int), ("N", ctypes.c_int * 3), ("nghosts", ctypes.c_int),
+                ("ampl", ctypes.c_double * 3), ("sinhw", ctypes.c_double * 3),
+                ("cfl", ctypes.c_double), ("bc_kind", ctypes.c_int)]
+
+
+class GaugeParams(ctypes.Structure):
+    _fields_ = [("eta", ctypes.c_double), ("shift_variant", ctypes.c_int)]
+
+
+class GridInfo(ctypes.Structure):
+    _fields_ = [("n_total", ctypes.c_int * 3), ("n_points", ctypes.c_longlong),
+                ("n_interior", ctypes.c_longlong), ("state_doubles", ctypes.c_longlong),
+                ("aux_doubles", ctypes.c_longlong), ("workspace_doubles", ctypes.c_longlong),
+                ("n_pure_outer", ctypes.c_longlong), ("n_inner", ctypes.c_longlong),
+                ("dxx", ctypes.c_double * 3), ("xxmin", ctypes.c_double * 3), ("dt", ctypes.c_double)]
+
+
+class BhahError(RuntimeError):
+    pass
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_SIGS = {
+    "bhah_last_error": (ctypes.c_char_p, []),
+    "bhah_grid_create": (ctypes.c_int, [ctypes.POINTER(GridParams), ctypes.POINTER(_vp)]),
+    "bhah_grid_destroy": (None, [_vp]),
+    "bhah_grid_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(GridInfo)]),
+    "bhah_grid_get_bc_maps": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "bhah_set_initial_data_brill_lindquist": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp, _vp]),
+    "bhah_apply_bcs": (ctypes.c_int, [_vp, _vp, _vp]),
+    "bhah_bssn_rhs": (ctypes.c_int, [_vp, ctypes.POINTER(GaugeParams), _vp, _vp, _vp, _vp]),
+    "bhah_rk4_step": (ctypes.c_int, [_vp, ctypes.POINTER(GaugeParams), ctypes.c_double, _vp, _vp, _vp]),
+    "bhah_hamiltonian_constraint": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "bhah_batch_create": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(GaugeParams), ctypes.c_char_p,
+                                         ctypes.POINTER(_vp)]),
+    "bhah_batch_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp]),
+    "bhah_batch_destroy": (None, [_vp]),
+}
+
+
+def lib():
+    """Load libbhah.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise ImportError(f"{LIBPATH} is missing: build it with paper_2505_00097_amd/build.py")
+        L = ctypes.CDLL(LIBPATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != OK:
+        msg = lib().bhah_last_error().decode(errors="replace")
+        raise BhahError(f"{what} failed ({rc}): {msg}")
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    import torch
+    assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+    return _vp(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return _vp(s.cuda_stream)
+
+
+def last_error():
+    return lib().bhah_last_error().decode(errors="replace")
+
+
+def gauge(eta=2.0):
+    return GaugeParams(float(eta), 0)
+
+
+# ---- the C ABI, one Python function per entry point ----------------------
+def grid_create(coord, N, ampl=(10.0, 10.0, 10.0), sinhw=(0.2, 0.2, 0.2), cfl=0.5):
+    p = GridParams()
+    p.coord = int(coord)
+    for d in range(3):
+        p.N[d] = int(N[d])
+        p.ampl[d] = float(ampl[d])
+        p.sinhw[d] = float(sinhw[d])
+    p.nghosts = 3
+    p.cfl = float(cfl)
+    p.bc_kind = 0
+    h = _vp()
+    _check(lib().bhah_grid_create(ctypes.byref(p), ctypes.byref(h)), "bhah_grid_create")
+    return h
+
+
+def grid_destroy(h):
+    lib().bhah_grid_destroy(h)
+
+
+def grid_get_info(h):
+    info = GridInfo()
+    _check(lib().bhah_grid_get_info(h, ctypes.byref(info)), "bhah_grid_get_info")
+    return info
+
+
+def grid_get_bc_maps(h, n_points):
+    import numpy as np
+    kind = np.zeros(n_points, dtype=np.int32)
+    src = np.zeros(n_points, dtype=np.int32)
+    par = np.zeros(n_points, dtype=np.int32)
+    _check(lib().bhah_grid_get_bc_maps(h, kind.ctypes.data, src.ctypes.data, par.ctypes.data),
+           "bhah_grid_get_bc_maps")
+    return kind, src, par
+
+
+def set_initial_data_brill_lindquist(h, masses, positions, y, lapse_kind=0, stream=None):
+    n = len(masses)
+    m = (ctypes.c_double * max(n, 1))(*[float(v) for v in masses])
+    flat = [float(c) for p in positions for c in p]
+    pos = (ctypes.c_double * max(3 * n, 1))(*flat)
+    _check(lib().bhah_set_initial_data_brill_lindquist(h, n, m, pos, int(lapse_kind), _ptr(y), _stream(stream)),
+           "bhah_set_initial_data_brill_lindquist")
+
+
+def apply_bcs(h, y, stream=None):
+    _check(lib().bhah_apply_bcs(h, _ptr(y), _stream(stream)), "bhah_apply_bcs")
+
+
+def bssn_rhs(h, y, rhs, aux=None, eta=2.0, stream=None):
+    gp = gauge(eta)
+    _check(lib().bhah_bssn_rhs(h, ctypes.byref(gp), _ptr(y), _ptr(rhs), _ptr(aux), _stream(stream)),
+           "bhah_bssn_rhs")
+
+
+def rk4_step(h, y, workspace, dt, eta=2.0, stream=None):
+    gp = gauge(eta)
+    _check(lib().bhah_rk4_step(h, ctypes.byref(gp), float(dt), _ptr(y), _ptr(workspace), _stream(stream)),
+           "bhah_rk4_step")
+
+
+def hamiltonian_constraint(h, y, H, stream=None):
+    _check(lib().bhah_hamiltonian_constraint(h, _ptr(y), _ptr(H), _stream(stream)),
+           "bhah_hamiltonian_constraint")
+
+
+def batch_create(grid_handles, eta=2.0, tune_cache_path=None):
+    n = len(grid_handles)
+    arr = (_vp * n)(*[g.value for g in grid_handles])
+    gp = gauge(eta)
+    b = _vp()
+    path = tune_cache_path.encode() if tune_cache_path else None
+    _check(lib().bhah_batch_create(arr, n, ctypes.byref(gp), path, ctypes.byref(b)), "bhah_batch_create")
+    return b
+
+
+def batch_step(b, ys, wss, dts, active=None, nsteps=1, stream=None):
+    n = len(ys)
+    yp = (_vp * n)(*[t.data_ptr() for t in ys])
+    wp = (_vp * n)(*[t.data_ptr() for t in wss])
+    dp = (ctypes.c_double * n)(*[float(d) for d in dts])
+    ap = None if active is None else (ctypes.c_ubyte * n)(*[1 if a else 0 for a in active])
+    _check(lib().bhah_batch_step(b, yp, wp, dp, ap, int(nsteps), _stream(stream)), "bhah_batch_step")
+
+
+def batch_destroy(b):
+    lib().bhah_batch_destroy(b)
+
+
+# ---- convenience wrapper ------------------------------------------------
+class Grid:
+    """A grid on the current device plus helpers to allocate its arrays."""
+
+    def __init__(self, coord, N, ampl=(10.0, 10.0, 10.0), sinhw=(0.2, 0.2, 0.2), cfl=0.5):
+        self.h = grid_create(coord, N, ampl, sinhw, cfl)
+        self.info = grid_get_info(self.h)
+        self.coord = int(coord)
+        self.N = tuple(int(n) for n in N)
+        self.n = tuple(self.info.n_total[d] for d in range(3))
+        self.dt = self.info.dt
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and _lib is not None:
+            grid_destroy(h)
+            self.h = None
+
+    def _empty(self, count):
+        import torch
+        return torch.empty((count, self.n[2], self.n[1], self.n[0]), dtype=torch.float64, device="cuda")
+
+    def state(self):
+        return self._empty(NUM_GFS)
+
+    def aux(self):
+        return self._empty(NUM_AUX_GFS)
+
+    def workspace(self):
+        import torch
+        return torch.empty(self.info.workspace_doubles, dtype=torch.float64, device="cuda")
+
+    def bc_maps(self):
+        return grid_get_bc_maps(self.h, self.info.n_points)

@@ -1,0 +1,89 @@
+// bhah_internal.h -- internal types of the HIP library (host + device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/bhah.h"
+
+namespace bhah {
+
+constexpr int NG = 3;     // ghost layers
+constexpr int NGF = 24;   // evolved gridfunctions
+constexpr int NAUX = 9;   // rescaled Ricci (6) + contracted d Gammabar term (3)
+
+// Per-direction 1-D tables, one row per grid index (ghosts included), TAB_W
+// doubles per row. Mapped directions (r or rho, and z): [map, d map, d2 map,
+// d3 map, 1/map, 1/d map] (derivatives with respect to the logical
+// coordinate). Angles (theta, phi): [sin, cos, 1/sin].
+constexpr int TAB_W = 8;
+
+// Everything a kernel needs to address one grid. Passed by value.
+struct GridDev {
+  int coord;
+  int N0, N1, N2;      // interior points
+  int n0, n1, n2;      // incl. ghosts
+  int s1, s2;          // flat strides of i1, i2 (s0 = 1)
+  long long sgf;       // gridfunction stride = n0*n1*n2
+  double inv_dx[3];    // 1/dxx
+  const double* tab0;  // [n0][TAB_W]
+  const double* tab1;  // [n1][TAB_W]
+  const double* tab2;  // [n2][TAB_W]
+};
+
+// Ghost fill list: every ghost point p receives
+//   y_g[p] = sign_g(parity_p) * sum_t w_t * y_g[src_t]
+// over interior sources only (outer extrapolation composed in exact integer
+// arithmetic on the host; inner copies carry their source's combination).
+struct GhostDev {
+  int n_ghost;
+  const int* dst;       // [n_ghost]
+  const int* start;     // [n_ghost + 1] offsets into src/w
+  const int* parity;    // [n_ghost] bit d: e~_(d) flips
+  const int* src;       // [n_terms]
+  const double* w;      // [n_terms]
+};
+
+// RK stage epilogue of the right-hand-side kernel: with rhs != nullptr the
+// right-hand side k is stored; otherwise out1 = base1 + c1 k and, if out2 is
+// set, out2 = base2 + c2 k, gridfunction by gridfunction.
+struct StageArgs {
+  double* rhs;
+  const double* base1;
+  double* out1;
+  double c1;
+  const double* base2;
+  double* out2;
+  double c2;
+};
+
+}  // namespace bhah
+
+struct bhah_grid {
+  bhah_grid_params params;
+  bhah_grid_info info;
+  int device;
+  bhah::GridDev dev;       // device pointers inside
+  bhah::GhostDev ghost;    // device pointers inside
+  // host copies
+  std::vector<double> tab[3];
+  std::vector<int> kind, src_map, parity_map;  // per point (exported maps)
+  std::vector<int> g_dst, g_start, g_par, g_src;
+  std::vector<double> g_w;
+  int max_terms;
+  // device allocations
+  double* d_tab[3];
+  int* d_ints;      // dst | start | parity | src packed
+  double* d_w;
+  double* d_aux;    // scratch used when the caller passes aux == NULL
+  long long n_int_block;
+};
+
+namespace bhah {
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+int check_hip(hipError_t e, const char* what);
+}  // namespace bhah

@@ -1,0 +1,199 @@
+// capi.cpp -- the extern "C" entry points declared in include/bhah.h.
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "bhah_internal.h"
+
+namespace bhah {
+
+int build_grid_host(const bhah_grid_params* p, bhah_grid* g);
+void launch_ghosts(const GhostDev& gh, double* y, long long sgf, hipStream_t s);
+int launch_brill_lindquist(const GridDev& G, int n, const double* m, const double* pos, int lapse_kind,
+                           double* y, hipStream_t s);
+void launch_rhs(const GridDev& G, double eta, const double* y, double* aux, const StageArgs& st,
+                hipStream_t s);
+void launch_hamiltonian(const GridDev& G, const double* y, double* H, hipStream_t s);
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int check_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return BHAH_OK;
+  return fail(BHAH_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static int check_launch(const char* what) { return check_hip(hipGetLastError(), what); }
+
+static void free_device(bhah_grid* g) {
+  for (int d = 0; d < 3; d++)
+    if (g->d_tab[d]) (void)hipFree(g->d_tab[d]);
+  if (g->d_ints) (void)hipFree(g->d_ints);
+  if (g->d_w) (void)hipFree(g->d_w);
+  if (g->d_aux) (void)hipFree(g->d_aux);
+}
+
+}  // namespace bhah
+
+using namespace bhah;
+
+extern "C" {
+
+const char* bhah_last_error(void) { return bhah::g_last_error.c_str(); }
+
+int bhah_grid_create(const bhah_grid_params* params, bhah_grid** out) {
+  if (!params || !out) return fail(BHAH_EINVAL, "bhah_grid_create: NULL argument");
+  bhah_grid* g = new (std::nothrow) bhah_grid();
+  if (!g) return fail(BHAH_ENOMEM, "bhah_grid_create: host allocation failed");
+  for (int d = 0; d < 3; d++) g->d_tab[d] = nullptr;
+  g->d_ints = nullptr;
+  g->d_w = nullptr;
+  g->d_aux = nullptr;
+  int rc = build_grid_host(params, g);
+  if (rc) { delete g; return rc; }
+  if ((rc = check_hip(hipGetDevice(&g->device), "hipGetDevice"))) { delete g; return rc; }
+
+  const bhah_grid_info& I = g->info;
+  const size_t nghost = g->g_dst.size();
+  const size_t nterm = g->g_src.size();
+  const size_t nints = nghost + (nghost + 1) + nghost + nterm;
+  hipError_t e = hipSuccess;
+  for (int d = 0; d < 3 && e == hipSuccess; d++) {
+    e = hipMalloc((void**)&g->d_tab[d], g->tab[d].size() * sizeof(double));
+    if (e == hipSuccess)
+      e = hipMemcpy(g->d_tab[d], g->tab[d].data(), g->tab[d].size() * sizeof(double), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = hipMalloc((void**)&g->d_ints, nints * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void**)&g->d_w, (nterm ? nterm : 1) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&g->d_aux, I.aux_doubles * sizeof(double));
+  if (e == hipSuccess) {
+    std::vector<int> packed;
+    packed.reserve(nints);
+    packed.insert(packed.end(), g->g_dst.begin(), g->g_dst.end());
+    packed.insert(packed.end(), g->g_start.begin(), g->g_start.end());
+    packed.insert(packed.end(), g->g_par.begin(), g->g_par.end());
+    packed.insert(packed.end(), g->g_src.begin(), g->g_src.end());
+    e = hipMemcpy(g->d_ints, packed.data(), nints * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess && nterm)
+      e = hipMemcpy(g->d_w, g->g_w.data(), nterm * sizeof(double), hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    const int code = e == hipErrorOutOfMemory ? BHAH_ENOMEM : BHAH_EDEVICE;
+    fail(code, std::string("bhah_grid_create: ") + hipGetErrorString(e));
+    free_device(g);
+    delete g;
+    return code;
+  }
+  GridDev& D = g->dev;
+  D.coord = params->coord;
+  D.N0 = params->N[0]; D.N1 = params->N[1]; D.N2 = params->N[2];
+  D.n0 = I.n_total[0]; D.n1 = I.n_total[1]; D.n2 = I.n_total[2];
+  D.s1 = D.n0;
+  D.s2 = D.n0 * D.n1;
+  D.sgf = I.n_points;
+  for (int d = 0; d < 3; d++) D.inv_dx[d] = 1.0 / I.dxx[d];
+  D.tab0 = g->d_tab[0]; D.tab1 = g->d_tab[1]; D.tab2 = g->d_tab[2];
+  GhostDev& Gh = g->ghost;
+  Gh.n_ghost = (int)nghost;
+  Gh.dst = g->d_ints;
+  Gh.start = g->d_ints + nghost;
+  Gh.parity = g->d_ints + 2 * nghost + 1;
+  Gh.src = g->d_ints + 3 * nghost + 1;
+  Gh.w = g->d_w;
+  *out = g;
+  return BHAH_OK;
+}
+
+void bhah_grid_destroy(bhah_grid* g) {
+  if (!g) return;
+  free_device(g);
+  delete g;
+}
+
+int bhah_grid_get_info(const bhah_grid* g, bhah_grid_info* info) {
+  if (!g || !info) return fail(BHAH_EINVAL, "bhah_grid_get_info: NULL argument");
+  *info = g->info;
+  return BHAH_OK;
+}
+
+int bhah_grid_get_bc_maps(const bhah_grid* g, int* host_kind, int* host_src, int* host_parity) {
+  if (!g) return fail(BHAH_EINVAL, "bhah_grid_get_bc_maps: NULL grid");
+  const size_t n = g->kind.size();
+  if (host_kind) std::memcpy(host_kind, g->kind.data(), n * sizeof(int));
+  if (host_src) std::memcpy(host_src, g->src_map.data(), n * sizeof(int));
+  if (host_parity) std::memcpy(host_parity, g->parity_map.data(), n * sizeof(int));
+  return BHAH_OK;
+}
+
+int bhah_apply_bcs(const bhah_grid* g, double* y, void* stream) {
+  if (!g || !y) return fail(BHAH_EINVAL, "bhah_apply_bcs: NULL argument");
+  launch_ghosts(g->ghost, y, g->dev.sgf, (hipStream_t)stream);
+  return check_launch("bhah_apply_bcs");
+}
+
+int bhah_set_initial_data_brill_lindquist(const bhah_grid* g, int n_punct, const double* host_masses,
+                                          const double* host_pos, int lapse_kind, double* y,
+                                          void* stream) {
+  if (!g || !y) return fail(BHAH_EINVAL, "bhah_set_initial_data_brill_lindquist: NULL argument");
+  if (n_punct > 0 && (!host_masses || !host_pos))
+    return fail(BHAH_EINVAL, "bhah_set_initial_data_brill_lindquist: NULL puncture arrays");
+  if (lapse_kind != 0 && lapse_kind != 1)
+    return fail(BHAH_EINVAL, "bhah_set_initial_data_brill_lindquist: lapse_kind must be 0 or 1");
+  if (launch_brill_lindquist(g->dev, n_punct, host_masses, host_pos, lapse_kind, y, (hipStream_t)stream))
+    return fail(BHAH_EINVAL, "bhah_set_initial_data_brill_lindquist: 0 <= n_punct <= 16 required");
+  int rc = check_launch("bhah_set_initial_data_brill_lindquist");
+  if (rc) return rc;
+  return bhah_apply_bcs(g, y, stream);
+}
+
+int bhah_bssn_rhs(const bhah_grid* g, const bhah_gauge_params* gp, const double* y, double* rhs,
+                  double* aux, void* stream) {
+  if (!g || !gp || !y || !rhs) return fail(BHAH_EINVAL, "bhah_bssn_rhs: NULL argument");
+  if (gp->shift_variant != 0) return fail(BHAH_EINVAL, "bhah_bssn_rhs: shift_variant must be 0");
+  StageArgs st{rhs, nullptr, nullptr, 0.0, nullptr, nullptr, 0.0};
+  launch_rhs(g->dev, gp->eta, y, aux ? aux : g->d_aux, st, (hipStream_t)stream);
+  return check_launch("bhah_bssn_rhs");
+}
+
+int bhah_rk4_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt, double* y, double* workspace,
+                  void* stream) {
+  if (!g || !gp || !y || !workspace) return fail(BHAH_EINVAL, "bhah_rk4_step: NULL argument");
+  if (gp->shift_variant != 0) return fail(BHAH_EINVAL, "bhah_rk4_step: shift_variant must be 0");
+  hipStream_t s = (hipStream_t)stream;
+  const long long n = g->info.state_doubles;
+  double* A = workspace;
+  double* B = workspace + n;
+  double* Cacc = workspace + 2 * n;
+  double* aux = workspace + 3 * n;
+  // classical RK4 (Sec. 4.2.1 footnote); boundary fill after each stage
+  // update and after the final combination (Sec. 3). Cacc accumulates
+  // y_n + dt/6 (k1 + 2 k2 + 2 k3).
+  const StageArgs s1{nullptr, y, A, 0.5 * dt, y, Cacc, dt / 6.0};
+  const StageArgs s2{nullptr, y, B, 0.5 * dt, Cacc, Cacc, dt / 3.0};
+  const StageArgs s3{nullptr, y, A, dt, Cacc, Cacc, dt / 3.0};
+  const StageArgs s4{nullptr, Cacc, y, dt / 6.0, nullptr, nullptr, 0.0};
+  launch_rhs(g->dev, gp->eta, y, aux, s1, s);
+  launch_ghosts(g->ghost, A, g->dev.sgf, s);
+  launch_rhs(g->dev, gp->eta, A, aux, s2, s);
+  launch_ghosts(g->ghost, B, g->dev.sgf, s);
+  launch_rhs(g->dev, gp->eta, B, aux, s3, s);
+  launch_ghosts(g->ghost, A, g->dev.sgf, s);
+  launch_rhs(g->dev, gp->eta, A, aux, s4, s);
+  launch_ghosts(g->ghost, y, g->dev.sgf, s);
+  return check_launch("bhah_rk4_step");
+}
+
+int bhah_hamiltonian_constraint(const bhah_grid* g, const double* y, double* H, void* stream) {
+  if (!g || !y || !H) return fail(BHAH_EINVAL, "bhah_hamiltonian_constraint: NULL argument");
+  launch_hamiltonian(g->dev, y, H, (hipStream_t)stream);
+  return check_launch("bhah_hamiltonian_constraint");
+}
+
+}  // extern "C"

@@ -1,0 +1,249 @@
+// grid.cpp -- host-side grid construction: 1-D reference-metric tables, the
+// CFL time step, and the ghost-fill lists.
+//
+// Ghost classes (Sec. 3 of arXiv:2505.00097, Fig. 1): outer-boundary points
+// lie beyond the outer edge of a non-periodic logical direction and are
+// filled by quadratic extrapolation; inner-boundary points come from the
+// coordinate singularities (r < 0, theta outside [0,pi], rho < 0) and from
+// phi periodicity, and copy the value of the point they coincide with, with
+// the sign flips of the rescaled basis vectors (Sec. 2.2). Here the inner maps
+// are the closed-form index reflections of the coordinates:
+//   spherical family  r -> -r      : (i0,i1,i2) -> (2NG-1-i0, N1+2NG-1-i1, i2+N2/2), flips e~0, e~2
+//                     theta < 0    : i1 -> 2NG-1-i1, i2 -> i2+N2/2,                 flips e~1, e~2
+//                     theta > pi   : i1 -> 2(N1+NG)-1-i1, i2 -> i2+N2/2,            flips e~1, e~2
+//   cylindrical       rho -> -rho  : (i0,i1) -> (2NG-1-i0, i1+N1/2),                flips e~0, e~1
+//   phi (either)      periodic wrap into the interior range.
+// Classes compose (indices applied in turn, flips multiplied).
+//
+// The outer extrapolation is applied, in exact arithmetic, layer by layer in
+// the order x0 faces, x1 faces, x2 faces with face ranges growing as layers
+// are filled. Because it is linear, every outer ghost is an integer-weighted
+// combination of interior values; the host composes these weights exactly and
+// the device evaluates each ghost in one pass with no ordering between
+// ghosts. Inner ghosts whose source is an outer ghost take that combination.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "bhah_internal.h"
+
+namespace bhah {
+
+namespace {
+
+struct Dom {
+  double lo[3], hi[3];
+};
+
+Dom domain_of(int coord) {
+  Dom d;
+  if (coord == BHAH_SINH_CYLINDRICAL) {
+    d.lo[0] = 0; d.hi[0] = 1;
+    d.lo[1] = -M_PI; d.hi[1] = M_PI;
+    d.lo[2] = -1; d.hi[2] = 1;
+  } else {
+    d.lo[0] = 0; d.hi[0] = 1;
+    d.lo[1] = 0; d.hi[1] = M_PI;
+    d.lo[2] = -M_PI; d.hi[2] = M_PI;
+  }
+  return d;
+}
+
+// sinh map of Eq. 22 (uniform for plain spherical): value and derivatives
+void map_row(bool linear, double A, double w, double x, double* out) {
+  if (linear) {
+    out[0] = A * x; out[1] = A; out[2] = 0.0; out[3] = 0.0;
+    return;
+  }
+  const double s = std::sinh(1.0 / w);
+  const double sh = std::sinh(x / w), ch = std::cosh(x / w);
+  out[0] = A * sh / s;
+  out[1] = A * ch / (w * s);
+  out[2] = A * sh / (w * w * s);
+  out[3] = A * ch / (w * w * w * s);
+}
+
+using Comb = std::map<int, long long>;  // interior flat index -> integer weight
+
+}  // namespace
+
+int build_grid_host(const bhah_grid_params* p, bhah_grid* g) {
+  const int coord = p->coord;
+  if (coord < 0 || coord > 2) return fail(BHAH_EINVAL, "coord must be 0, 1 or 2");
+  if (p->nghosts != NG) return fail(BHAH_EINVAL, "nghosts must be 3");
+  if (p->bc_kind != BHAH_BC_EXTRAP) return fail(BHAH_EINVAL, "bc_kind must be BHAH_BC_EXTRAP");
+  const int dphi = coord == BHAH_SINH_CYLINDRICAL ? 1 : 2;
+  for (int d = 0; d < 3; d++) {
+    if (d != dphi && p->N[d] < NG) return fail(BHAH_EINVAL, "N[d] < nghosts in a non-periodic direction");
+  }
+  if (p->N[dphi] < 2 || p->N[dphi] % 2) return fail(BHAH_EINVAL, "N_phi must be even and >= 2");
+  if (!(p->ampl[0] > 0)) return fail(BHAH_EINVAL, "ampl[0] must be > 0");
+  if (coord != BHAH_SPHERICAL && !(p->sinhw[0] > 0)) return fail(BHAH_EINVAL, "sinhw[0] must be > 0");
+  if (coord == BHAH_SINH_CYLINDRICAL && (!(p->ampl[2] > 0) || !(p->sinhw[2] > 0)))
+    return fail(BHAH_EINVAL, "ampl[2] and sinhw[2] must be > 0");
+  if (!(p->cfl > 0)) return fail(BHAH_EINVAL, "cfl must be > 0");
+  const long long n0 = p->N[0] + 2 * NG, n1 = p->N[1] + 2 * NG, n2 = p->N[2] + 2 * NG;
+  if (n0 * n1 * n2 >= (1LL << 31) / 2) return fail(BHAH_EINVAL, "grid too large for 32-bit point indices");
+
+  g->params = *p;
+  bhah_grid_info& I = g->info;
+  const Dom dom = domain_of(coord);
+  int n[3] = {(int)n0, (int)n1, (int)n2};
+  for (int d = 0; d < 3; d++) {
+    I.n_total[d] = n[d];
+    I.xxmin[d] = dom.lo[d];
+    I.dxx[d] = (dom.hi[d] - dom.lo[d]) / p->N[d];
+  }
+  I.n_points = n0 * n1 * n2;
+  I.n_interior = (long long)p->N[0] * p->N[1] * p->N[2];
+  I.state_doubles = NGF * I.n_points;
+  I.aux_doubles = NAUX * I.n_points;
+  I.workspace_doubles = 3 * I.state_doubles + I.aux_doubles;
+
+  // ---- 1-D tables --------------------------------------------------------
+  auto xx = [&](int d, int j) { return dom.lo[d] + ((double)(j - NG) + 0.5) * I.dxx[d]; };
+  for (int d = 0; d < 3; d++) g->tab[d].assign((size_t)n[d] * TAB_W, 0.0);
+  auto map_full = [&](bool linear, double A, double w, double x, double* row) {
+    map_row(linear, A, w, x, row);
+    row[4] = 1.0 / row[0];
+    row[5] = 1.0 / row[1];
+  };
+  auto angle = [&](double a, double* row) {
+    row[0] = std::sin(a);
+    row[1] = std::cos(a);
+    row[2] = 1.0 / row[0];
+  };
+  for (int j = 0; j < n[0]; j++)
+    map_full(coord == BHAH_SPHERICAL, p->ampl[0], p->sinhw[0], xx(0, j), &g->tab[0][(size_t)j * TAB_W]);
+  for (int j = 0; j < n[1]; j++) angle(xx(1, j), &g->tab[1][(size_t)j * TAB_W]);
+  for (int j = 0; j < n[2]; j++) {
+    if (coord == BHAH_SINH_CYLINDRICAL)
+      map_full(false, p->ampl[2], p->sinhw[2], xx(2, j), &g->tab[2][(size_t)j * TAB_W]);
+    else
+      angle(xx(2, j), &g->tab[2][(size_t)j * TAB_W]);
+  }
+
+  // ---- CFL time step: cfl * min over interior points of min_i S_i dxx^i ----
+  double dsmin = INFINITY;
+  for (int i2 = NG; i2 < NG + p->N[2]; i2++)
+    for (int i1 = NG; i1 < NG + p->N[1]; i1++)
+      for (int i0 = NG; i0 < NG + p->N[0]; i0++) {
+        const double* t0 = &g->tab[0][(size_t)i0 * TAB_W];
+        double S[3];
+        if (coord == BHAH_SINH_CYLINDRICAL) {
+          S[0] = t0[1]; S[1] = t0[0]; S[2] = g->tab[2][(size_t)i2 * TAB_W + 1];
+        } else {
+          S[0] = t0[1]; S[1] = t0[0]; S[2] = t0[0] * g->tab[1][(size_t)i1 * TAB_W + 0];
+        }
+        for (int d = 0; d < 3; d++) dsmin = std::min(dsmin, std::fabs(S[d]) * I.dxx[d]);
+      }
+  I.dt = p->cfl * dsmin;
+
+  // ---- ghost classification by index reflection -------------------------
+  const long long np = I.n_points;
+  g->kind.assign(np, 0);
+  g->src_map.resize(np);
+  g->parity_map.assign(np, 0);
+  auto flat = [&](int a, int b, int c) { return (int)(a + n0 * (b + n1 * (long long)c)); };
+  auto interior = [&](int a, int b, int c) {
+    return a >= NG && a < NG + p->N[0] && b >= NG && b < NG + p->N[1] && c >= NG && c < NG + p->N[2];
+  };
+  auto wrap = [&](int j, int N) { int m = (j - NG) % N; if (m < 0) m += N; return NG + m; };
+  for (int i2 = 0; i2 < n[2]; i2++)
+    for (int i1 = 0; i1 < n[1]; i1++)
+      for (int i0 = 0; i0 < n[0]; i0++) {
+        const int q = flat(i0, i1, i2);
+        g->src_map[q] = q;
+        if (interior(i0, i1, i2)) { g->kind[q] = 0; continue; }
+        int j0 = i0, j1 = i1, j2 = i2, par = 0;
+        if (coord == BHAH_SINH_CYLINDRICAL) {
+          if (j0 < NG) { j0 = 2 * NG - 1 - j0; j1 += p->N[1] / 2; par ^= 0b011; }
+          j1 = wrap(j1, p->N[1]);
+        } else {
+          if (j0 < NG) {
+            j0 = 2 * NG - 1 - j0; j1 = p->N[1] + 2 * NG - 1 - j1; j2 += p->N[2] / 2; par ^= 0b101;
+          }
+          if (j1 < NG) { j1 = 2 * NG - 1 - j1; j2 += p->N[2] / 2; par ^= 0b110; }
+          else if (j1 >= p->N[1] + NG) { j1 = 2 * (p->N[1] + NG) - 1 - j1; j2 += p->N[2] / 2; par ^= 0b110; }
+          j2 = wrap(j2, p->N[2]);
+        }
+        if (j0 == i0 && j1 == i1 && j2 == i2) { g->kind[q] = 1; continue; }
+        g->kind[q] = 2;
+        g->src_map[q] = flat(j0, j1, j2);
+        g->parity_map[q] = par;
+      }
+  // inner ghosts must map to interior or outer points (one hop)
+  for (long long q = 0; q < np; q++)
+    if (g->kind[q] == 2 && g->kind[g->src_map[q]] == 2)
+      return fail(BHAH_EINVAL, "inner ghost maps to another inner ghost");
+
+  // ---- outer extrapolation composed into interior weights ---------------
+  std::vector<Comb> comb(np);
+  int lo[3] = {NG, NG, NG}, hi[3] = {NG + p->N[0], NG + p->N[1], NG + p->N[2]};
+  const long long st[3] = {1, n0, n0 * n1};
+  for (int layer = 0; layer < NG; layer++) {
+    for (int d = 0; d < 3; d++) {
+      for (int side = 0; side < 2; side++) {
+        const int face = side == 0 ? lo[d] - 1 : hi[d];
+        const long long step = (side == 0 ? 1 : -1) * st[d];
+        int a[3] = {lo[0], lo[1], lo[2]}, b[3] = {hi[0], hi[1], hi[2]};
+        a[d] = face; b[d] = face + 1;
+        for (int i2 = a[2]; i2 < b[2]; i2++)
+          for (int i1 = a[1]; i1 < b[1]; i1++)
+            for (int i0 = a[0]; i0 < b[0]; i0++) {
+              const int q = flat(i0, i1, i2);
+              if (g->kind[q] != 1) continue;
+              Comb c;
+              const long long w3[3] = {3, -3, 1};
+              for (int t = 1; t <= 3; t++) {
+                const int s = (int)(q + t * step);
+                if (g->kind[s] == 0) {
+                  c[s] += w3[t - 1];
+                } else if (g->kind[s] == 1 && !comb[s].empty()) {
+                  for (auto& kv : comb[s]) c[kv.first] += w3[t - 1] * kv.second;
+                } else {
+                  return fail(BHAH_EINVAL, "extrapolation reads a point not yet filled");
+                }
+              }
+              for (auto it = c.begin(); it != c.end();) it = it->second == 0 ? c.erase(it) : std::next(it);
+              comb[q] = c;
+            }
+      }
+      lo[d]--;
+      hi[d]++;
+    }
+  }
+  // every outer point must have been reached
+  for (long long q = 0; q < np; q++)
+    if (g->kind[q] == 1 && comb[q].empty()) return fail(BHAH_EINVAL, "outer ghost not reached by the shell order");
+
+  // ---- ghost list --------------------------------------------------------
+  g->g_dst.clear(); g->g_start.clear(); g->g_par.clear(); g->g_src.clear(); g->g_w.clear();
+  g->max_terms = 0;
+  long long n_outer = 0, n_inner = 0;
+  for (long long q = 0; q < np; q++) {
+    if (g->kind[q] == 0) continue;
+    const Comb* c;
+    Comb single;
+    if (g->kind[q] == 1) { c = &comb[q]; n_outer++; }
+    else {
+      n_inner++;
+      const int s = g->src_map[q];
+      if (g->kind[s] == 0) { single[s] = 1; c = &single; }
+      else c = &comb[s];
+    }
+    g->g_dst.push_back((int)q);
+    g->g_start.push_back((int)g->g_src.size());
+    g->g_par.push_back(g->parity_map[q]);
+    for (auto& kv : *c) { g->g_src.push_back(kv.first); g->g_w.push_back((double)kv.second); }
+    g->max_terms = std::max(g->max_terms, (int)c->size());
+  }
+  g->g_start.push_back((int)g->g_src.size());
+  I.n_pure_outer = n_outer;
+  I.n_inner = n_inner;
+  return BHAH_OK;
+}
+
+}  // namespace bhah

@@ -1,0 +1,96 @@
+// misc.hip -- ghost fill and Brill-Lindquist initial data.
+#include "bhah_internal.h"
+
+namespace bhah {
+
+// tensor type of each gridfunction: scalar (-1,-1), vector (i,-1), rank 2 (i,j)
+__device__ __forceinline__ int gf_flip(int g, int par) {
+  constexpr int I[NGF] = {0, 0, 0, 1, 1, 2, -1, 0, 1, 2, -1, 0, 0, 0, 1, 1, 2, 0, 1, 2, -1, 0, 1, 2};
+  constexpr int J[NGF] = {0, 1, 2, 1, 2, 2, -1, -1, -1, -1, -1, 0, 1, 2, 1, 2, 2, -1, -1, -1, -1, -1, -1, -1};
+  int f = 0;
+  if (I[g] >= 0) f ^= (par >> I[g]) & 1;
+  if (J[g] >= 0) f ^= (par >> J[g]) & 1;
+  return f;
+}
+
+// Every ghost point takes sign * sum_t w_t y[src_t]; all sources are interior
+// points, so ghosts can be filled in any order and in parallel (Sec. 3
+// outer-then-inner boundary order is folded into the weights on the host).
+__global__ void __launch_bounds__(256) k_ghosts(GhostDev gh, double* __restrict__ y, long long sgf) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= gh.n_ghost) return;
+  const int dst = gh.dst[t], s0 = gh.start[t], s1 = gh.start[t + 1], par = gh.parity[t];
+  if (s1 - s0 == 1) {
+    const int src = gh.src[s0];
+#pragma unroll
+    for (int g = 0; g < NGF; g++) {
+      const double v = y[g * sgf + src];
+      y[g * sgf + dst] = gf_flip(g, par) ? -v : v;
+    }
+    return;
+  }
+#pragma unroll
+  for (int g = 0; g < NGF; g++) {
+    double v = 0.0;
+    for (int k = s0; k < s1; k++) v += gh.w[k] * y[g * sgf + gh.src[k]];
+    y[g * sgf + dst] = gf_flip(g, par) ? -v : v;
+  }
+}
+
+void launch_ghosts(const GhostDev& gh, double* y, long long sgf, hipStream_t s) {
+  if (gh.n_ghost == 0) return;
+  hipLaunchKernelGGL(k_ghosts, dim3((gh.n_ghost + 255) / 256), dim3(256), 0, s, gh, y, sgf);
+}
+
+constexpr int MAX_PUNCT = 16;
+struct Punctures {
+  int n;
+  int lapse_kind;
+  double m[MAX_PUNCT];
+  double x[MAX_PUNCT][3];
+};
+
+// Brill-Lindquist: psi = 1 + sum m_n / (2 |x - x_n|); W = psi^-2; alpha =
+// psi^-2 (precollapsed) or 1; all other variables zero. Interior points.
+__global__ void __launch_bounds__(64) k_brill_lindquist(GridDev G, Punctures P, double* __restrict__ y) {
+  const int i0 = NG + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  const int i1 = NG + (int)blockIdx.y, i2 = NG + (int)blockIdx.z;
+  if (i0 >= NG + G.N0) return;
+  const double r = G.tab0[i0 * TAB_W];
+  double x[3];
+  if (G.coord == BHAH_SINH_CYLINDRICAL) {
+    const double sp = G.tab1[i1 * TAB_W], cp = G.tab1[i1 * TAB_W + 1];
+    x[0] = r * cp; x[1] = r * sp; x[2] = G.tab2[i2 * TAB_W];
+  } else {
+    const double st = G.tab1[i1 * TAB_W], ct = G.tab1[i1 * TAB_W + 1];
+    const double sp = G.tab2[i2 * TAB_W], cp = G.tab2[i2 * TAB_W + 1];
+    x[0] = r * st * cp; x[1] = r * st * sp; x[2] = r * ct;
+  }
+  double psi = 1.0;
+  for (int n = 0; n < P.n; n++) {
+    const double dx = x[0] - P.x[n][0], dy = x[1] - P.x[n][1], dz = x[2] - P.x[n][2];
+    psi += P.m[n] / (2.0 * sqrt(dx * dx + dy * dy + dz * dz));
+  }
+  const double ip2 = 1.0 / (psi * psi);
+  const long long q = i0 + (long long)G.s1 * i1 + (long long)G.s2 * i2;
+#pragma unroll
+  for (int g = 0; g < NGF; g++) y[g * G.sgf + q] = 0.0;
+  y[10 * G.sgf + q] = ip2;                              // cf
+  y[6 * G.sgf + q] = P.lapse_kind == 0 ? ip2 : 1.0;     // alpha
+}
+
+int launch_brill_lindquist(const GridDev& G, int n, const double* m, const double* pos, int lapse_kind,
+                           double* y, hipStream_t s) {
+  if (n < 0 || n > MAX_PUNCT) return -1;
+  Punctures P{};
+  P.n = n;
+  P.lapse_kind = lapse_kind;
+  for (int i = 0; i < n; i++) {
+    P.m[i] = m[i];
+    for (int d = 0; d < 3; d++) P.x[i][d] = pos[3 * i + d];
+  }
+  hipLaunchKernelGGL(k_brill_lindquist, dim3((G.N0 + 63) / 64, G.N1, G.N2), dim3(64), 0, s, G, P, y);
+  return 0;
+}
+
+}  // namespace bhah
