@@ -122,7 +122,7 @@ typedef struct {
   long long n_interior;        /* N[0]*N[1]*N[2]                            */
   long long state_doubles;     /* 24 * n_points: size of one state array    */
   long long aux_doubles;       /* BHAH_NUM_AUX_GFS * n_points               */
-  long long workspace_doubles; /* size of the rk4_step workspace            */
+  long long workspace_doubles; /* size of the rk4_step workspace (3 states)  */
   long long n_pure_outer;      /* ghost points filled by extrapolation      */
   long long n_inner;           /* ghost points filled by a parity copy      */
   double dxx[3];
@@ -179,10 +179,8 @@ int bhah_apply_bcs(const bhah_grid* g, double* y, void* stream);
  * variables at every interior point. y must have valid ghosts. rhs has the
  * state layout; only its interior points are written. aux receives
  * BHAH_NUM_AUX_GFS gridfunctions (state layout, interior points) computed on
- * the way; it may be NULL, in which case a buffer owned by the grid is used
- * (then calls on the same grid must not overlap in time). All 4th-order
- * finite differences, advection terms beta^k d_k upwinded (Sec. 3 second
- * paragraph).                                                               */
+ * the way, or may be NULL to skip them. All 4th-order finite differences,
+ * advection terms beta^k d_k upwinded (Sec. 3 second paragraph).            */
 int bhah_bssn_rhs(const bhah_grid* g, const bhah_gauge_params* gp,
                   const double* y, double* rhs, double* aux, void* stream);
 

@@ -18,7 +18,8 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function"]
 DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-ffp-contract=fast"]
 SOURCES = {
-    "rhs.hip": DEVICE + ["-fno-signed-zeros", "-ffinite-math-only"],
+    "rhs_fused.hip": DEVICE + ["-fno-signed-zeros", "-ffinite-math-only"],
+    "hamiltonian.hip": DEVICE + ["-fno-signed-zeros", "-ffinite-math-only"],
     "misc.hip": DEVICE,
     "grid.cpp": [],
     "capi.cpp": [],

@@ -78,7 +78,6 @@ struct bhah_grid {
   double* d_tab[3];
   int* d_ints;      // dst | start | parity | src packed
   double* d_w;
-  double* d_aux;    // scratch used when the caller passes aux == NULL
   long long n_int_block;
 };
 

@@ -12,8 +12,8 @@ int build_grid_host(const bhah_grid_params* p, bhah_grid* g);
 void launch_ghosts(const GhostDev& gh, double* y, long long sgf, hipStream_t s);
 int launch_brill_lindquist(const GridDev& G, int n, const double* m, const double* pos, int lapse_kind,
                            double* y, hipStream_t s);
-void launch_rhs(const GridDev& G, double eta, const double* y, double* aux, const StageArgs& st,
-                hipStream_t s);
+void launch_rhs_fused(const GridDev& G, double eta, const double* y, double* aux, const StageArgs& st,
+                      hipStream_t s);
 void launch_hamiltonian(const GridDev& G, const double* y, double* H, hipStream_t s);
 
 static thread_local std::string g_last_error;
@@ -37,7 +37,6 @@ static void free_device(bhah_grid* g) {
     if (g->d_tab[d]) (void)hipFree(g->d_tab[d]);
   if (g->d_ints) (void)hipFree(g->d_ints);
   if (g->d_w) (void)hipFree(g->d_w);
-  if (g->d_aux) (void)hipFree(g->d_aux);
 }
 
 }  // namespace bhah
@@ -55,7 +54,6 @@ int bhah_grid_create(const bhah_grid_params* params, bhah_grid** out) {
   for (int d = 0; d < 3; d++) g->d_tab[d] = nullptr;
   g->d_ints = nullptr;
   g->d_w = nullptr;
-  g->d_aux = nullptr;
   int rc = build_grid_host(params, g);
   if (rc) { delete g; return rc; }
   if ((rc = check_hip(hipGetDevice(&g->device), "hipGetDevice"))) { delete g; return rc; }
@@ -72,7 +70,6 @@ int bhah_grid_create(const bhah_grid_params* params, bhah_grid** out) {
   }
   if (e == hipSuccess) e = hipMalloc((void**)&g->d_ints, nints * sizeof(int));
   if (e == hipSuccess) e = hipMalloc((void**)&g->d_w, (nterm ? nterm : 1) * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc((void**)&g->d_aux, I.aux_doubles * sizeof(double));
   if (e == hipSuccess) {
     std::vector<int> packed;
     packed.reserve(nints);
@@ -158,7 +155,7 @@ int bhah_bssn_rhs(const bhah_grid* g, const bhah_gauge_params* gp, const double*
   if (!g || !gp || !y || !rhs) return fail(BHAH_EINVAL, "bhah_bssn_rhs: NULL argument");
   if (gp->shift_variant != 0) return fail(BHAH_EINVAL, "bhah_bssn_rhs: shift_variant must be 0");
   StageArgs st{rhs, nullptr, nullptr, 0.0, nullptr, nullptr, 0.0};
-  launch_rhs(g->dev, gp->eta, y, aux ? aux : g->d_aux, st, (hipStream_t)stream);
+  launch_rhs_fused(g->dev, gp->eta, y, aux, st, (hipStream_t)stream);
   return check_launch("bhah_bssn_rhs");
 }
 
@@ -171,7 +168,6 @@ int bhah_rk4_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt, do
   double* A = workspace;
   double* B = workspace + n;
   double* Cacc = workspace + 2 * n;
-  double* aux = workspace + 3 * n;
   // classical RK4 (Sec. 4.2.1 footnote); boundary fill after each stage
   // update and after the final combination (Sec. 3). Cacc accumulates
   // y_n + dt/6 (k1 + 2 k2 + 2 k3).
@@ -179,13 +175,13 @@ int bhah_rk4_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt, do
   const StageArgs s2{nullptr, y, B, 0.5 * dt, Cacc, Cacc, dt / 3.0};
   const StageArgs s3{nullptr, y, A, dt, Cacc, Cacc, dt / 3.0};
   const StageArgs s4{nullptr, Cacc, y, dt / 6.0, nullptr, nullptr, 0.0};
-  launch_rhs(g->dev, gp->eta, y, aux, s1, s);
+  launch_rhs_fused(g->dev, gp->eta, y, nullptr, s1, s);
   launch_ghosts(g->ghost, A, g->dev.sgf, s);
-  launch_rhs(g->dev, gp->eta, A, aux, s2, s);
+  launch_rhs_fused(g->dev, gp->eta, A, nullptr, s2, s);
   launch_ghosts(g->ghost, B, g->dev.sgf, s);
-  launch_rhs(g->dev, gp->eta, B, aux, s3, s);
+  launch_rhs_fused(g->dev, gp->eta, B, nullptr, s3, s);
   launch_ghosts(g->ghost, A, g->dev.sgf, s);
-  launch_rhs(g->dev, gp->eta, A, aux, s4, s);
+  launch_rhs_fused(g->dev, gp->eta, A, nullptr, s4, s);
   launch_ghosts(g->ghost, y, g->dev.sgf, s);
   return check_launch("bhah_rk4_step");
 }

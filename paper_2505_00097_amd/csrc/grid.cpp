@@ -100,7 +100,7 @@ int build_grid_host(const bhah_grid_params* p, bhah_grid* g) {
   I.n_interior = (long long)p->N[0] * p->N[1] * p->N[2];
   I.state_doubles = NGF * I.n_points;
   I.aux_doubles = NAUX * I.n_points;
-  I.workspace_doubles = 3 * I.state_doubles + I.aux_doubles;
+  I.workspace_doubles = 3 * I.state_doubles;
 
   // ---- 1-D tables --------------------------------------------------------
   auto xx = [&](int d, int j) { return dom.lo[d] + ((double)(j - NG) + 0.5) * I.dxx[d]; };

@@ -20,21 +20,26 @@ __global__ void __launch_bounds__(256) k_ghosts(GhostDev gh, double* __restrict_
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= gh.n_ghost) return;
   const int dst = gh.dst[t], s0 = gh.start[t], s1 = gh.start[t + 1], par = gh.parity[t];
+  // all loads before any store: sources are interior points, never ghosts,
+  // but the compiler cannot know that and would otherwise keep each load
+  // behind the previous store
+  double v[NGF];
   if (s1 - s0 == 1) {
     const int src = gh.src[s0];
 #pragma unroll
-    for (int g = 0; g < NGF; g++) {
-      const double v = y[g * sgf + src];
-      y[g * sgf + dst] = gf_flip(g, par) ? -v : v;
+    for (int g = 0; g < NGF; g++) v[g] = y[g * sgf + src];
+  } else {
+#pragma unroll
+    for (int g = 0; g < NGF; g++) v[g] = 0.0;
+    for (int k = s0; k < s1; k++) {
+      const double w = gh.w[k];
+      const int src = gh.src[k];
+#pragma unroll
+      for (int g = 0; g < NGF; g++) v[g] += w * y[g * sgf + src];
     }
-    return;
   }
 #pragma unroll
-  for (int g = 0; g < NGF; g++) {
-    double v = 0.0;
-    for (int k = s0; k < s1; k++) v += gh.w[k] * y[g * sgf + gh.src[k]];
-    y[g * sgf + dst] = gf_flip(g, par) ? -v : v;
-  }
+  for (int g = 0; g < NGF; g++) y[g * sgf + dst] = gf_flip(g, par) ? -v[g] : v[g];
 }
 
 void launch_ghosts(const GhostDev& gh, double* y, long long sgf, hipStream_t s) {

@@ -21,20 +21,39 @@ enum {
 
 // symmetric pair (i,j) -> 0..5 in the order 00,01,02,11,12,22
 __host__ __device__ constexpr int sy(int i, int j) {
-  return i > j ? sy(j, i) : (i == 0 ? j : (i == 1 ? 2 + j : 5));
+  return i <= j ? (i * (5 - i)) / 2 + j : (j * (5 - j)) / 2 + i;
 }
 
-// Address of gridfunction g at the point q shifted by (a,b,c).
+// Stencil loads through buffer descriptors: one descriptor per gridfunction
+// (base = that gridfunction's first element, range = its size in bytes), a
+// per-lane byte offset `vc` of the stencil's low corner (q - 3 - 3 s1 - 3 s2),
+// and the stencil offset -- uniform across the wave -- as scalar offset plus
+// immediate. No per-load vector address arithmetic; an access outside the
+// gridfunction returns 0 instead of faulting.
+typedef unsigned int bhah_u2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t gf_rsrc(const double* y, long long sgf, int g) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)(y + g * sgf), (short)0, (int)(sgf * 8), 0x00020000);
+}
+
+__device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff) {
+  const bhah_u2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+  return __builtin_bit_cast(double, v);
+}
+
 struct Pt {
   const double* __restrict__ y;
   long long sgf;
   int s1, s2;
-  unsigned q;
-  // uniform base pointer + 32-bit per-lane index: the offset part stays in
-  // scalar registers and each load needs no vector address arithmetic
+  unsigned q;   // flat index of the point
+  unsigned vc;  // byte offset of the point's stencil corner, (q - 3 - 3 s1 - 3 s2) * 8
+
+  __device__ __forceinline__ Pt(const double* y_, long long sgf_, int s1_, int s2_, unsigned q_)
+      : y(y_), sgf(sgf_), s1(s1_), s2(s2_), q(q_), vc((q_ - 3u - 3u * (unsigned)s1_ - 3u * (unsigned)s2_) * 8u) {}
+
   __device__ __forceinline__ double at(int g, int a, int b, int c) const {
-    const double* base = y + (g * sgf + (long long)(a + b * s1 + c * s2));
-    return base[q];
+    const int soff = ((b + 3) * s1 + (c + 3) * s2) * 8;
+    return buf_ld(gf_rsrc(y, sgf, g), vc + (unsigned)((a + 3) * 8), soff);
   }
   template <int K>
   __device__ __forceinline__ double ax(int g, int m) const {

@@ -1,0 +1,600 @@
+// rhs_fused.hip -- the full BSSN + gauge right-hand side (Eqs. 7-15 with the
+// conformal Ricci tensor of Eq. 12, arXiv:2505.00097) in one kernel, one
+// thread per interior point, with the RK4 stage combination as epilogue.
+//
+// The per-point work is ordered to keep few values live at a time:
+//   phase 1  stencil loop over the six index pairs (k,l): every second
+//            derivative is consumed at once into the contractions the
+//            equations need (22 accumulators):
+//              P_ij  = sum_kl gammabar^kl d_k d_l h_ij            (Ricci)
+//              Qs_k  = sum_m beta^m gammabar^ab S_a S_b d_k d_m h_ab
+//              Y_kl  = (alpha/W) d_k d_l W - d_k d_l alpha         (Abar eq.)
+//              Za    = gammabar^kl d_k d_l alpha                   (K eq.)
+//              Bv^i  = gammabar^kl d_k d_l vet^i, Bd_k = sum_j d_k d_j vet^j / S_j
+//   phase 2  first derivatives, the metric pieces (Eqs. 3-5), the remaining
+//            lower-order Ricci terms, then Eqs. 7-15 and the rescaling.
+// Reference-metric structural zeros fold away per coordinate family.
+#include "rhs_common.h"
+
+namespace bhah {
+
+// Upwinded advection beta^k d_k f of a rescaled gridfunction (Sec. 3: shift
+// advection terms use the stencil shifted one point upwind). With
+// sigma = sign(vet^k) and f(m) = f at offset m*sigma along k:
+//   beta^k U_k f = |beta^k|/(12 dxx^k) [3 (f(1) - f(-1)) + 10 (f(1) - f(0))
+//                                       - 6 (f(2) - f(1)) + (f(3) - f(1))].
+struct Upwind2 {
+  unsigned vp[3], vm[3], v2[3], v3[3];  // per-lane byte offsets of q+s, q-s, q+2s, q+3s
+  unsigned v0;
+  double w[3];                          // |beta^k| / (12 dxx^k)
+};
+
+__device__ __forceinline__ double advect2(const Pt& P, int g, const Upwind2& U) {
+  const __amdgpu_buffer_rsrc_t r = gf_rsrc(P.y, P.sgf, g);
+  const double f0 = buf_ld(r, U.v0, 0);
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    const double fp = buf_ld(r, U.vp[k], 0), fm = buf_ld(r, U.vm[k], 0);
+    const double f2 = buf_ld(r, U.v2[k], 0), f3 = buf_ld(r, U.v3[k], 0);
+    s += U.w[k] * (3.0 * (fp - fm) + 10.0 * (fp - f0) - 6.0 * (f2 - fp) + (f3 - fp));
+  }
+  return s;
+}
+
+#define BHAH_PHASE_BARRIER() __builtin_amdgcn_sched_barrier(0)
+
+// LDS slots per thread for values carried from one phase to a later one, and
+// for the 24 results: they are written to global memory only at the end, so
+// no global store sits between two stencil loads (the compiler would have to
+// keep such loads and stores in order, exposing memory latency each time).
+constexpr int PARK = 55;
+enum { PK_PC = 0, PK_QS = 6, PK_Y = 9, PK_ZA = 15, PK_BV = 16, PK_BD = 19, PK_RT = 22, PK_Q = 28, PK_OUT = 31 };
+
+template <int C>
+__device__ __forceinline__ void fused_point(const GridDev& G, double eta, const double* __restrict__ y,
+                                            const StageArgs& st, int i0, int i1, int i2, unsigned q,
+                                            double* __restrict__ aux, double* __restrict__ park) {
+  // park[v * 64] is this thread's slot v (lane-consecutive, bank-conflict free)
+  auto put = [&](int v, double x) { park[v * 64] = x; };
+  auto get = [&](int v) { return park[v * 64]; };
+  Pt P{y, G.sgf, G.s1, G.s2, q};
+  const Spacing sp = make_spacing(G);
+  Ref R;
+  load_ref<C>(G, i0, i1, i2, R);
+
+  // ---- phase 0: point values and the conformal metric (Eq. 3) -----------
+  double h[6], SS[6], gb[6], gbU[6];
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = i; j < 3; j++) {
+      const int a = sy(i, j);
+      SS[a] = R.S[i] * R.S[j];
+      h[a] = P.at(G_HDD00 + a, 0, 0, 0);
+      gb[a] = (i == j ? R.S[i] * R.S[i] : 0.0) + h[a] * SS[a];
+    }
+  sym_inverse(gb, gbU);
+  const double W = P.at(G_CF, 0, 0, 0), alpha = P.at(G_ALPHA, 0, 0, 0);
+  const double iW = 1.0 / W;
+  double vet[3], beta[3];
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    vet[i] = P.at(G_VETU0 + i, 0, 0, 0);
+    beta[i] = vet[i] * R.iS[i];
+  }
+
+  // ---- phase 1: second-derivative contractions ---------------------------
+  double Pc[6], Qs[3], Y[6], Za = 0.0, Bv[3], Bd[3];
+#pragma unroll
+  for (int a = 0; a < 6; a++) Pc[a] = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; i++) { Qs[i] = 0.0; Bv[i] = 0.0; Bd[i] = 0.0; }
+  {
+    double G2[6];  // gammabar^ab S_a S_b, doubled off the diagonal
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+      for (int b = a; b < 3; b++) G2[sy(a, b)] = (a == b ? 1.0 : 2.0) * gbU[sy(a, b)] * SS[sy(a, b)];
+    const double aW = alpha * iW;
+#pragma unroll
+    for (int k = 0; k < 3; k++)
+#pragma unroll
+      for (int l = k; l < 3; l++) {
+        const int kl = sy(k, l);
+        const double wg = (k == l ? 1.0 : 2.0) * gbU[kl];
+        double c = 0.0;
+#pragma unroll
+        for (int a = 0; a < 6; a++) {
+          const double dd = fd2kl(P, G_HDD00 + a, k, l, sp);
+          Pc[a] += wg * dd;
+          c += G2[a] * dd;
+        }
+        Qs[k] += beta[l] * c;
+        if (k != l) Qs[l] += beta[k] * c;
+        const double dda = fd2kl(P, G_ALPHA, k, l, sp);
+        Y[kl] = aW * fd2kl(P, G_CF, k, l, sp) - dda;
+        Za += wg * dda;
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+          const double ddv = fd2kl(P, G_VETU0 + i, k, l, sp);
+          Bv[i] += wg * ddv;
+          if (i == l) Bd[k] += ddv * R.iS[l];
+          if (k != l && i == k) Bd[l] += ddv * R.iS[k];
+        }
+      }
+  }
+#pragma unroll
+  for (int a = 0; a < 6; a++) { put(PK_PC + a, Pc[a]); put(PK_Y + a, Y[a]); }
+#pragma unroll
+  for (int i = 0; i < 3; i++) { put(PK_QS + i, Qs[i]); put(PK_BV + i, Bv[i]); put(PK_BD + i, Bd[i]); }
+  put(PK_ZA, Za);
+  BHAH_PHASE_BARRIER();
+
+  // ---- phase 2a: first derivatives of h, eps, Dhat eps -------------------
+  double Gh[3][3][3];
+  ref_christoffel(R, Gh);
+  double dh[6][3], eps[6], Dh_eps[6][3];
+#pragma unroll
+  for (int a = 0; a < 6; a++) {
+    eps[a] = h[a] * SS[a];
+#pragma unroll
+    for (int k = 0; k < 3; k++) dh[a][k] = fd1k(P, G_HDD00 + a, k, sp);
+  }
+  // d_k eps_ij = S_i S_j d_k h_ij + h_ij d_k (S_i S_j)
+  auto deps = [&](int i, int j, int k) {
+    const int a = sy(i, j);
+    return dh[a][k] * SS[a] + h[a] * (R.dS[i][k] * R.S[j] + R.S[i] * R.dS[j][k]);
+  };
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = i; j < 3; j++)
+#pragma unroll
+      for (int k = 0; k < 3; k++) {
+        double s = deps(i, j, k);
+#pragma unroll
+        for (int m = 0; m < 3; m++) s -= Gh[m][k][i] * eps[sy(m, j)] + Gh[m][k][j] * eps[sy(i, m)];
+        Dh_eps[sy(i, j)][k] = s;
+      }
+  BHAH_PHASE_BARRIER();
+
+  // ---- phase 2b: Ricci (Eq. 12) terms from Dhat Dhat eps below second
+  // order, and the pieces of Q_k -----------------------------------------
+  double Rl[6], Q[3];
+#pragma unroll
+  for (int a = 0; a < 6; a++) Rl[a] = 0.0;
+  {
+    double dGh[3][3][3][3];
+    ref_christoffel_deriv(R, dGh);
+    double cq[6];  // gammabar^ab (d_k d_m gammahat_ab + lower-order part of d_k d_m eps_ab)
+#pragma unroll
+    for (int k = 0; k < 3; k++)
+#pragma unroll
+      for (int l = k; l < 3; l++) {
+        const double wkl = (k == l ? -0.5 : -1.0) * gbU[sy(k, l)];
+        double cqa = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+          for (int j = i; j < 3; j++) {
+            const int a = sy(i, j);
+            const double ddSS = R.ddS[i][k][l] * R.S[j] + R.dS[i][k] * R.dS[j][l] +
+                                R.dS[i][l] * R.dS[j][k] + R.S[i] * R.ddS[j][k][l];
+            const double dSSk = R.dS[i][k] * R.S[j] + R.S[i] * R.dS[j][k];
+            const double dSSl = R.dS[i][l] * R.S[j] + R.S[i] * R.dS[j][l];
+            const double low = dh[a][k] * dSSl + dh[a][l] * dSSk + h[a] * ddSS;
+            double s = low;
+#pragma unroll
+            for (int m = 0; m < 3; m++)
+              s -= dGh[m][l][i][k] * eps[sy(m, j)] + Gh[m][l][i] * deps(m, j, k) +
+                   dGh[m][l][j][k] * eps[sy(i, m)] + Gh[m][l][j] * deps(i, m, k);
+#pragma unroll
+            for (int m = 0; m < 3; m++)
+              s -= Gh[m][k][l] * Dh_eps[a][m] + Gh[m][k][i] * Dh_eps[sy(m, j)][l] +
+                   Gh[m][k][j] * Dh_eps[sy(i, m)][l];
+            Rl[a] += wkl * s;
+            const double ddgh = i == j ? 2.0 * (R.dS[i][k] * R.dS[i][l] + R.S[i] * R.ddS[i][k][l]) : 0.0;
+            cqa += (i == j ? 1.0 : 2.0) * gbU[a] * (ddgh + low);
+          }
+        cq[sy(k, l)] = cqa;
+      }
+    // A_k = gammabar^-1 d_k gammabar; Q_k = 1/2 beta^m (Qs + cq - tr(A_k A_m))
+    double A[3][3][3];
+#pragma unroll
+    for (int k = 0; k < 3; k++)
+#pragma unroll
+      for (int a = 0; a < 3; a++)
+#pragma unroll
+        for (int b = 0; b < 3; b++) {
+          double s = 0.0;
+#pragma unroll
+          for (int c = 0; c < 3; c++)
+            s += gbU[sy(a, c)] * ((c == b ? 2.0 * R.S[c] * R.dS[c][k] : 0.0) + deps(c, b, k));
+          A[k][a][b] = s;
+        }
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+      double s = get(PK_QS + k);
+#pragma unroll
+      for (int m = 0; m < 3; m++) {
+        double tr = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+          for (int b = 0; b < 3; b++) tr += A[k][a][b] * A[m][b][a];
+        s += beta[m] * (cq[sy(k, m)] - tr);
+      }
+      Q[k] = 0.5 * s;
+    }
+  }
+  BHAH_PHASE_BARRIER();
+
+  // ---- phase 2c: Delta^k_ij (Eq. 4, as 1/2 gammabar^kl (Dhat_i eps_lj +
+  // Dhat_j eps_il - Dhat_l eps_ij)), Delta^k (Eq. 5), remaining Ricci terms --
+  double DUDD[3][6], DU[3];
+#pragma unroll
+  for (int k = 0; k < 3; k++)
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+      for (int j = i; j < 3; j++) {
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l < 3; l++)
+          s += gbU[sy(k, l)] * (Dh_eps[sy(l, j)][i] + Dh_eps[sy(i, l)][j] - Dh_eps[sy(i, j)][l]);
+        DUDD[k][sy(i, j)] = 0.5 * s;
+      }
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+      for (int j = 0; j < 3; j++) s += gbU[sy(i, j)] * DUDD[k][sy(i, j)];
+    DU[k] = s;
+  }
+  {
+    // Delta terms, Delta_abc = gammabar_al Delta^l_bc formed on the fly
+    auto Dl = [&](int a, int b, int c) {
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l < 3; l++) s += gb[sy(a, l)] * DUDD[l][sy(b, c)];
+      return s;
+    };
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+      for (int j = i; j < 3; j++) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; k++) s += 0.5 * DU[k] * (Dl(i, j, k) + Dl(j, i, k));
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+#pragma unroll
+          for (int l = 0; l < 3; l++) {
+            double t = 0.0;
+#pragma unroll
+            for (int m = 0; m < 3; m++)
+              t += DUDD[m][sy(k, i)] * Dl(j, m, l) + DUDD[m][sy(k, j)] * Dl(i, m, l) +
+                   DUDD[m][sy(i, k)] * Dl(m, j, l);
+            s += gbU[sy(k, l)] * t;
+          }
+        Rl[sy(i, j)] += s;
+      }
+    // Lambdabar terms: gammabar_k(i Dhat_j) Lambdabar^k
+    double Lam[3], DLam[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) Lam[k] = P.at(G_LAMU0 + k, 0, 0, 0) * R.iS[k];
+#pragma unroll
+    for (int k = 0; k < 3; k++)
+#pragma unroll
+      for (int j = 0; j < 3; j++) {
+        double d = fd1k(P, G_LAMU0 + k, j, sp) * R.iS[k] - Lam[k] * R.dS[k][j] * R.iS[k];
+#pragma unroll
+        for (int m = 0; m < 3; m++) d += Gh[k][j][m] * Lam[m];
+        DLam[k][j] = d;
+      }
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+      for (int j = i; j < 3; j++) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; k++) s += gb[sy(k, i)] * DLam[k][j] + gb[sy(k, j)] * DLam[k][i];
+        Rl[sy(i, j)] += 0.5 * s;
+      }
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+      for (int j = i; j < 3; j++) {
+        const int a = sy(i, j);
+        put(PK_RT + a, -0.5 * get(PK_PC + a) + Rl[a] * (R.iS[i] * R.iS[j]));
+      }
+#pragma unroll
+    for (int k = 0; k < 3; k++) put(PK_Q + k, Q[k]);
+  }
+  BHAH_PHASE_BARRIER();
+
+  // ---- phase 3: the evolution equations ----------------------------------
+  auto emit = [&](int g, double v) { put(PK_OUT + g, v); };
+  double diS[3][3];  // d_k (1/S_i)
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int k = 0; k < 3; k++) diS[i][k] = -R.dS[i][k] * (R.iS[i] * R.iS[i]);
+  double dvet[3][3], dbeta[3][3];  // d_j vet^i, d_j beta^i
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+      dvet[i][j] = fd1k(P, G_VETU0 + i, j, sp);
+      dbeta[i][j] = dvet[i][j] * R.iS[i] + vet[i] * diS[i][j];
+    }
+  Upwind2 U;
+  U.v0 = q * 8u;
+  {
+    const int str[3] = {1, G.s1, G.s2};
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+      const int o = vet[k] > 0.0 ? str[k] : -str[k];
+      U.vp[k] = (q + o) * 8u; U.vm[k] = (q - o) * 8u; U.v2[k] = (q + 2 * o) * 8u; U.v3[k] = (q + 3 * o) * 8u;
+      U.w[k] = fabs(beta[k]) * sp.i12h[k];
+    }
+  }
+  double bS[3];  // beta^k d_k S_i / S_i
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; k++) s += beta[k] * R.dS[i][k];
+    bS[i] = s * R.iS[i];
+  }
+  const double K = P.at(G_TRK, 0, 0, 0);
+  double dW[3], dalpha[3], phi_d[3];
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    dW[k] = fd1k(P, G_CF, k, sp);
+    dalpha[k] = fd1k(P, G_ALPHA, k, sp);
+    phi_d[k] = -0.5 * dW[k] * iW;
+  }
+  double Gbc[3];  // Gammabar^k_km
+#pragma unroll
+  for (int m = 0; m < 3; m++) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; k++) s += Gh[k][k][m] + DUDD[k][sy(k, m)];
+    Gbc[m] = s;
+  }
+  double Dbeta = 0.0;  // Dbar_k beta^k
+#pragma unroll
+  for (int k = 0; k < 3; k++) Dbeta += dbeta[k][k] + Gbc[k] * beta[k];
+
+  double a6[6], Abar[6], AUD[3][3], AUU[6];
+#pragma unroll
+  for (int c = 0; c < 6; c++) { a6[c] = P.at(G_ADD00 + c, 0, 0, 0); Abar[c] = a6[c] * SS[c]; }
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; k++) s += gbU[sy(i, k)] * Abar[sy(k, j)];
+      AUD[i][j] = s;
+    }
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = i; j < 3; j++) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; k++) s += AUD[i][k] * gbU[sy(k, j)];
+      AUU[sy(i, j)] = s;
+    }
+  double trA = 0.0, AA = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    trA += AUD[i][i];
+#pragma unroll
+    for (int j = 0; j < 3; j++) AA += Abar[sy(i, j)] * AUU[sy(i, j)];
+  }
+  const double W2 = W * W;
+
+  // Eq. 9 (W), Eq. 13 (alpha), Eq. 10 (K)
+  emit(G_CF, -(1.0 / 3.0) * W * (Dbeta - alpha * K) + advect2(P, G_CF, U));
+  emit(G_ALPHA, -2.0 * alpha * K + advect2(P, G_ALPHA, U));
+  {
+    double lap = get(PK_ZA), da_dphi = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+      for (int j = 0; j < 3; j++) {
+        double Ga = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; k++) Ga += (Gh[k][i][j] + DUDD[k][sy(i, j)]) * dalpha[k];
+        lap -= gbU[sy(i, j)] * Ga;
+        da_dphi += gbU[sy(i, j)] * dalpha[i] * phi_d[j];
+      }
+    emit(G_TRK, (1.0 / 3.0) * alpha * K * K + alpha * AA - W2 * (lap + 2.0 * da_dphi) + advect2(P, G_TRK, U));
+  }
+  BHAH_PHASE_BARRIER();
+
+  // Eq. 7 (eps)
+  double Dbh[3][3];  // Dhat_j beta^i
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+      double s = dbeta[i][j];
+#pragma unroll
+      for (int m = 0; m < 3; m++) s += Gh[i][j][m] * beta[m];
+      Dbh[i][j] = s;
+    }
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = i; j < 3; j++) {
+      const int c = sy(i, j);
+      double r = (2.0 / 3.0) * gb[c] * (alpha * trA - Dbeta) + R.S[j] * R.S[j] * Dbh[j][i] +
+                 R.S[i] * R.S[i] * Dbh[i][j] - 2.0 * alpha * Abar[c];
+#pragma unroll
+      for (int k = 0; k < 3; k++) r += eps[sy(k, j)] * dbeta[k][i] + eps[sy(i, k)] * dbeta[k][j];
+      emit(G_HDD00 + c, r * (R.iS[i] * R.iS[j]) + advect2(P, G_HDD00 + c, U) + h[c] * (bS[i] + bS[j]));
+    }
+  BHAH_PHASE_BARRIER();
+
+  // Eq. 8 (Abar)
+  {
+    double X[6], trX = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+      for (int j = i; j < 3; j++) {
+        const int c = sy(i, j);
+        double Gphi = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+          Gphi += (Gh[k][i][j] + DUDD[k][c]) * (2.0 * alpha * phi_d[k] + dalpha[k]);
+        X[c] = get(PK_Y + c) - alpha * dW[i] * dW[j] * (iW * iW) + Gphi + 4.0 * alpha * phi_d[i] * phi_d[j] +
+               2.0 * (dalpha[i] * phi_d[j] + dalpha[j] * phi_d[i]) + alpha * get(PK_RT + c) * SS[c];
+      }
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+      for (int j = 0; j < 3; j++) trX += gbU[sy(i, j)] * X[sy(i, j)];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+      for (int j = i; j < 3; j++) {
+        const int c = sy(i, j);
+        double AikAkj = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; k++) AikAkj += Abar[sy(i, k)] * AUD[k][j];
+        double r = -(2.0 / 3.0) * Abar[c] * Dbeta - 2.0 * alpha * AikAkj + alpha * Abar[c] * K +
+                   W2 * (X[c] - (1.0 / 3.0) * gb[c] * trX);
+#pragma unroll
+        for (int k = 0; k < 3; k++) r += Abar[sy(k, j)] * dbeta[k][i] + Abar[sy(i, k)] * dbeta[k][j];
+        emit(G_ADD00 + c, r * (R.iS[i] * R.iS[j]) + advect2(P, G_ADD00 + c, U) + a6[c] * (bS[i] + bS[j]));
+      }
+  }
+  BHAH_PHASE_BARRIER();
+
+  // Eq. 11 (Lambdabar, lapse factors restored), Eqs. 14-15 (shift, B)
+  {
+    double dGh[3][3][3][3];
+    ref_christoffel_deriv(R, dGh);
+    double dK[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) dK[k] = fd1k(P, G_TRK, k, sp);
+    double ddiS[3][6];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+      for (int j = 0; j < 3; j++)
+#pragma unroll
+        for (int k = j; k < 3; k++)
+          ddiS[i][sy(j, k)] = -R.ddS[i][j][k] * (R.iS[i] * R.iS[i]) +
+                              2.0 * R.dS[i][j] * R.dS[i][k] * (R.iS[i] * R.iS[i] * R.iS[i]);
+    double dDbeta[3];  // d_k (Dbar_j beta^j)
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+      double s = get(PK_BD + k) + get(PK_Q + k);
+#pragma unroll
+      for (int j = 0; j < 3; j++) s += dvet[j][k] * diS[j][j] + dvet[j][j] * diS[j][k] + vet[j] * ddiS[j][sy(j, k)];
+#pragma unroll
+      for (int m = 0; m < 3; m++) s += Gbc[m] * dbeta[m][k];
+      dDbeta[k] = s;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+      double t2 = get(PK_BV + i) * R.iS[i];  // gammabar^jk Dhat_j Dhat_k beta^i
+#pragma unroll
+      for (int j = 0; j < 3; j++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+          double s = dvet[i][j] * diS[i][k] + dvet[i][k] * diS[i][j] + vet[i] * ddiS[i][sy(j, k)];
+#pragma unroll
+          for (int m = 0; m < 3; m++)
+            s += dGh[i][k][m][j] * beta[m] + Gh[i][k][m] * dbeta[m][j] + Gh[i][j][m] * Dbh[m][k] -
+                 Gh[m][j][k] * Dbh[i][m];
+          t2 += gbU[sy(j, k)] * s;
+        }
+      double t4 = 0.0, t5 = 0.0, t6 = 0.0, t7 = 0.0, lie = 0.0;
+#pragma unroll
+      for (int j = 0; j < 3; j++) {
+        const double Lamj = P.at(G_LAMU0 + j, 0, 0, 0) * R.iS[j];
+        t4 += gbU[sy(i, j)] * dDbeta[j];
+        t5 += AUU[sy(i, j)] * (dalpha[j] - 6.0 * alpha * phi_d[j]);
+        t7 += gbU[sy(i, j)] * dK[j];
+        lie -= Lamj * dbeta[i][j];
+#pragma unroll
+        for (int k = 0; k < 3; k++) t6 += AUU[sy(j, k)] * DUDD[i][sy(j, k)];
+      }
+      const double r = t2 + (2.0 / 3.0) * DU[i] * Dbeta + (1.0 / 3.0) * t4 - 2.0 * t5 + 2.0 * alpha * t6 -
+                       (4.0 / 3.0) * alpha * t7 + lie;
+      const double lam = P.at(G_LAMU0 + i, 0, 0, 0);
+      const double rl = r * R.S[i] + advect2(P, G_LAMU0 + i, U) - lam * bS[i];
+      emit(G_LAMU0 + i, rl);
+      const double bet = P.at(G_BETU0 + i, 0, 0, 0);
+      emit(G_VETU0 + i, bet + advect2(P, G_VETU0 + i, U) - vet[i] * bS[i]);
+      emit(G_BETU0 + i, 0.75 * rl - eta * bet + advect2(P, G_BETU0 + i, U) - bet * bS[i]);
+    }
+  }
+  BHAH_PHASE_BARRIER();
+
+  // ---- results: right-hand side or RK stage combination ------------------
+  if (st.rhs) {
+#pragma unroll
+    for (int g = 0; g < NGF; g++) st.rhs[g * G.sgf + q] = get(PK_OUT + g);
+  } else {
+#pragma unroll
+    for (int g = 0; g < NGF; g++) {
+      const long long e = g * G.sgf + q;
+      const double k = get(PK_OUT + g);
+      st.out1[e] = st.base1[e] + st.c1 * k;
+      if (st.out2) st.out2[e] = st.base2[e] + st.c2 * k;
+    }
+  }
+  if (aux) {
+#pragma unroll
+    for (int a = 0; a < 6; a++) aux[a * G.sgf + q] = get(PK_RT + a);
+#pragma unroll
+    for (int k = 0; k < 3; k++) aux[(6 + k) * G.sgf + q] = get(PK_Q + k);
+  }
+}
+
+// Occupancy target of the fused kernel: 1 keeps every value in registers
+// (vector + accumulation registers), 2 trades some scratch for latency hiding.
+#ifndef BHAH_RHS_WAVES
+#define BHAH_RHS_WAVES 1
+#endif
+
+template <int C>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BHAH_RHS_WAVES, BHAH_RHS_WAVES)))
+k_rhs_fused(GridDev G, double eta, const double* __restrict__ y,
+                                                  StageArgs st, double* __restrict__ aux) {
+  const int i0 = NG + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  const int i1 = NG + (int)blockIdx.y, i2 = NG + (int)blockIdx.z;
+  if (i0 >= NG + G.N0) return;
+  const unsigned q = (unsigned)(i0 + G.s1 * i1 + G.s2 * i2);
+  __shared__ double park[PARK * 64];
+  fused_point<C>(G, eta, y, st, i0, i1, i2, q, aux, park + threadIdx.x);
+}
+
+void launch_rhs_fused(const GridDev& G, double eta, const double* y, double* aux, const StageArgs& st,
+                      hipStream_t s) {
+  const dim3 g((G.N0 + 63) / 64, G.N1, G.N2);
+  switch (G.coord) {
+    case BHAH_SINH_SPHERICAL:
+      hipLaunchKernelGGL(k_rhs_fused<BHAH_SINH_SPHERICAL>, g, dim3(64), 0, s, G, eta, y, st, aux);
+      break;
+    case BHAH_SINH_CYLINDRICAL:
+      hipLaunchKernelGGL(k_rhs_fused<BHAH_SINH_CYLINDRICAL>, g, dim3(64), 0, s, G, eta, y, st, aux);
+      break;
+    default:
+      hipLaunchKernelGGL(k_rhs_fused<BHAH_SPHERICAL>, g, dim3(64), 0, s, G, eta, y, st, aux);
+      break;
+  }
+}
+
+}  // namespace bhah
