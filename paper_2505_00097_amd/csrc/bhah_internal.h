@@ -21,6 +21,13 @@ constexpr int NAUX = 9;   // rescaled Ricci (6) + contracted d Gammabar term (3)
 // coordinate). Angles (theta, phi): [sin, cos, 1/sin].
 constexpr int TAB_W = 8;
 
+#ifndef BHAH_DEFAULT_BAND
+#define BHAH_DEFAULT_BAND 4
+#endif
+#ifndef BHAH_NXCD
+#define BHAH_NXCD 8
+#endif
+
 // Everything a kernel needs to address one grid. Passed by value.
 struct GridDev {
   int coord;
@@ -74,6 +81,7 @@ struct bhah_grid {
   std::vector<int> g_dst, g_start, g_par, g_src;
   std::vector<double> g_w;
   int max_terms;
+  int band;         // i1 rows per band in the RHS tile order (tunable)
   // device allocations
   double* d_tab[3];
   int* d_ints;      // dst | start | parity | src packed

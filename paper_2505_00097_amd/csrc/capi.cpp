@@ -13,7 +13,7 @@ void launch_ghosts(const GhostDev& gh, double* y, long long sgf, hipStream_t s);
 int launch_brill_lindquist(const GridDev& G, int n, const double* m, const double* pos, int lapse_kind,
                            double* y, hipStream_t s);
 void launch_rhs_fused(const GridDev& G, double eta, const double* y, double* aux, const StageArgs& st,
-                      hipStream_t s);
+                      hipStream_t s, int band);
 void launch_hamiltonian(const GridDev& G, const double* y, double* H, hipStream_t s);
 
 static thread_local std::string g_last_error;
@@ -88,6 +88,7 @@ int bhah_grid_create(const bhah_grid_params* params, bhah_grid** out) {
     delete g;
     return code;
   }
+  g->band = BHAH_DEFAULT_BAND;
   GridDev& D = g->dev;
   D.coord = params->coord;
   D.N0 = params->N[0]; D.N1 = params->N[1]; D.N2 = params->N[2];
@@ -155,7 +156,7 @@ int bhah_bssn_rhs(const bhah_grid* g, const bhah_gauge_params* gp, const double*
   if (!g || !gp || !y || !rhs) return fail(BHAH_EINVAL, "bhah_bssn_rhs: NULL argument");
   if (gp->shift_variant != 0) return fail(BHAH_EINVAL, "bhah_bssn_rhs: shift_variant must be 0");
   StageArgs st{rhs, nullptr, nullptr, 0.0, nullptr, nullptr, 0.0};
-  launch_rhs_fused(g->dev, gp->eta, y, aux, st, (hipStream_t)stream);
+  launch_rhs_fused(g->dev, gp->eta, y, aux, st, (hipStream_t)stream, g->band);
   return check_launch("bhah_bssn_rhs");
 }
 
@@ -175,13 +176,13 @@ int bhah_rk4_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt, do
   const StageArgs s2{nullptr, y, B, 0.5 * dt, Cacc, Cacc, dt / 3.0};
   const StageArgs s3{nullptr, y, A, dt, Cacc, Cacc, dt / 3.0};
   const StageArgs s4{nullptr, Cacc, y, dt / 6.0, nullptr, nullptr, 0.0};
-  launch_rhs_fused(g->dev, gp->eta, y, nullptr, s1, s);
+  launch_rhs_fused(g->dev, gp->eta, y, nullptr, s1, s, g->band);
   launch_ghosts(g->ghost, A, g->dev.sgf, s);
-  launch_rhs_fused(g->dev, gp->eta, A, nullptr, s2, s);
+  launch_rhs_fused(g->dev, gp->eta, A, nullptr, s2, s, g->band);
   launch_ghosts(g->ghost, B, g->dev.sgf, s);
-  launch_rhs_fused(g->dev, gp->eta, B, nullptr, s3, s);
+  launch_rhs_fused(g->dev, gp->eta, B, nullptr, s3, s, g->band);
   launch_ghosts(g->ghost, A, g->dev.sgf, s);
-  launch_rhs_fused(g->dev, gp->eta, A, nullptr, s4, s);
+  launch_rhs_fused(g->dev, gp->eta, A, nullptr, s4, s, g->band);
   launch_ghosts(g->ghost, y, g->dev.sgf, s);
   return check_launch("bhah_rk4_step");
 }

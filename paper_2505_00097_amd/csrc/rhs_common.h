@@ -111,6 +111,34 @@ __device__ __forceinline__ double fdm(const Pt& P, int g, const Spacing& s) {
   };
   return (8.0 * (e(1) - e(-1)) - (e(2) - e(-2))) * s.i144[K][L];
 }
+// Batched stencil gathers: values land in a local array first so that a
+// whole batch of loads is in flight before any is consumed.
+//   axis : f(-2), f(-1), f(0), f(1), f(2) along K
+//   cross: f(m, n) along (K, L) for m, n in {-2, -1, 1, 2}, m-major
+template <int K>
+__device__ __forceinline__ void gather_axis(const Pt& P, int g, double v[5]) {
+#pragma unroll
+  for (int t = 0; t < 5; t++) v[t] = P.ax<K>(g, t - 2);
+}
+template <int K, int L>
+__device__ __forceinline__ void gather_cross(const Pt& P, int g, double v[16]) {
+  constexpr int off[4] = {-2, -1, 1, 2};
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++) v[4 * a + b] = P.pl<K, L>(g, off[a], off[b]);
+}
+__device__ __forceinline__ double d1_axis(const double v[5], double s) {
+  return (8.0 * (v[3] - v[1]) - (v[4] - v[0])) * s;
+}
+__device__ __forceinline__ double d2_axis(const double v[5], double s) {
+  return (16.0 * (v[3] + v[1]) - (v[4] + v[0]) - 30.0 * v[2]) * s;
+}
+__device__ __forceinline__ double d2_cross(const double v[16], double s) {
+  auto e = [&](int a) { return 8.0 * (v[4 * a + 2] - v[4 * a + 1]) - (v[4 * a + 3] - v[4 * a + 0]); };
+  return (8.0 * (e(2) - e(1)) - (e(3) - e(0))) * s;
+}
+
 __device__ __forceinline__ double fd1k(const Pt& P, int g, int k, const Spacing& s) {
   return k == 0 ? fd1<0>(P, g, s) : (k == 1 ? fd1<1>(P, g, s) : fd1<2>(P, g, s));
 }

@@ -44,6 +44,62 @@ __device__ __forceinline__ double advect2(const Pt& P, int g, const Upwind2& U) 
 
 #define BHAH_PHASE_BARRIER() __builtin_amdgcn_sched_barrier(0)
 
+// compile-time dispatch of the gathers on a (compile-time after unrolling)
+// direction index
+__device__ __forceinline__ void gather_axis_k(const Pt& P, int g, int k, double v[5]) {
+  if (k == 0) gather_axis<0>(P, g, v);
+  else if (k == 1) gather_axis<1>(P, g, v);
+  else gather_axis<2>(P, g, v);
+}
+__device__ __forceinline__ void gather_cross_kl(const Pt& P, int g, int k, int l, double v[16]) {
+  if (k == 0 && l == 1) gather_cross<0, 1>(P, g, v);
+  else if (k == 0) gather_cross<0, 2>(P, g, v);
+  else gather_cross<1, 2>(P, g, v);
+}
+
+// first derivatives of N gridfunctions in one batch of loads
+template <int N>
+__device__ __forceinline__ void grad_batch(const Pt& P, const int (&gf)[N], const Spacing& sp, double (&d)[N][3]) {
+  double v[N][3][5];
+#pragma unroll
+  for (int t = 0; t < N; t++)
+#pragma unroll
+    for (int k = 0; k < 3; k++) gather_axis_k(P, gf[t], k, v[t][k]);
+  BHAH_PHASE_BARRIER();
+#pragma unroll
+  for (int t = 0; t < N; t++)
+#pragma unroll
+    for (int k = 0; k < 3; k++) d[t][k] = d1_axis(v[t][k], sp.i12h[k]);
+}
+
+// upwinded advection of N gridfunctions in one batch of loads
+template <int N>
+__device__ __forceinline__ void advect_batch(const Pt& P, int g0, const Upwind2& U, double (&out)[N]) {
+  double f0[N], fp[N][3], fm[N][3], f2[N][3], f3[N][3];
+#pragma unroll
+  for (int t = 0; t < N; t++) {
+    const __amdgpu_buffer_rsrc_t r = gf_rsrc(P.y, P.sgf, g0 + t);
+    f0[t] = buf_ld(r, U.v0, 0);
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+      fp[t][k] = buf_ld(r, U.vp[k], 0);
+      fm[t][k] = buf_ld(r, U.vm[k], 0);
+      f2[t][k] = buf_ld(r, U.v2[k], 0);
+      f3[t][k] = buf_ld(r, U.v3[k], 0);
+    }
+  }
+  BHAH_PHASE_BARRIER();
+#pragma unroll
+  for (int t = 0; t < N; t++) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; k++)
+      s += U.w[k] * (3.0 * (fp[t][k] - fm[t][k]) + 10.0 * (fp[t][k] - f0[t]) - 6.0 * (f2[t][k] - fp[t][k]) +
+                     (f3[t][k] - fp[t][k]));
+    out[t] = s;
+  }
+}
+
 // LDS slots per thread for values carried from one phase to a later one, and
 // for the 24 results: they are written to global memory only at the end, so
 // no global store sits between two stencil loads (the compiler would have to
@@ -97,30 +153,51 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
 #pragma unroll
       for (int b = a; b < 3; b++) G2[sy(a, b)] = (a == b ? 1.0 : 2.0) * gbU[sy(a, b)] * SS[sy(a, b)];
     const double aW = alpha * iW;
+    // the 11 gridfunctions whose second derivatives enter: h_ij, W, alpha, vet^i
+    constexpr int G11[11] = {G_HDD00, G_HDD00 + 1, G_HDD00 + 2, G_HDD00 + 3, G_HDD00 + 4, G_HDD00 + 5,
+                             G_CF, G_ALPHA, G_VETU0, G_VETU0 + 1, G_VETU0 + 2};
 #pragma unroll
     for (int k = 0; k < 3; k++)
 #pragma unroll
       for (int l = k; l < 3; l++) {
+        double dd[11];
+        if (k == l) {
+          double v[11][5];
+#pragma unroll
+          for (int t = 0; t < 11; t++) gather_axis_k(P, G11[t], k, v[t]);
+          BHAH_PHASE_BARRIER();
+#pragma unroll
+          for (int t = 0; t < 11; t++) dd[t] = d2_axis(v[t], sp.i12hh[k]);
+        } else {
+#pragma unroll
+          for (int t0 = 0; t0 < 11; t0 += 4) {
+            double v[4][16];
+#pragma unroll
+            for (int t = 0; t < 4; t++)
+              if (t0 + t < 11) gather_cross_kl(P, G11[t0 + t], k, l, v[t]);
+            BHAH_PHASE_BARRIER();
+#pragma unroll
+            for (int t = 0; t < 4; t++)
+              if (t0 + t < 11) dd[t0 + t] = d2_cross(v[t], sp.i144[k][l]);
+          }
+        }
         const int kl = sy(k, l);
         const double wg = (k == l ? 1.0 : 2.0) * gbU[kl];
         double c = 0.0;
 #pragma unroll
         for (int a = 0; a < 6; a++) {
-          const double dd = fd2kl(P, G_HDD00 + a, k, l, sp);
-          Pc[a] += wg * dd;
-          c += G2[a] * dd;
+          Pc[a] += wg * dd[a];
+          c += G2[a] * dd[a];
         }
         Qs[k] += beta[l] * c;
         if (k != l) Qs[l] += beta[k] * c;
-        const double dda = fd2kl(P, G_ALPHA, k, l, sp);
-        Y[kl] = aW * fd2kl(P, G_CF, k, l, sp) - dda;
-        Za += wg * dda;
+        Y[kl] = aW * dd[6] - dd[7];
+        Za += wg * dd[7];
 #pragma unroll
         for (int i = 0; i < 3; i++) {
-          const double ddv = fd2kl(P, G_VETU0 + i, k, l, sp);
-          Bv[i] += wg * ddv;
-          if (i == l) Bd[k] += ddv * R.iS[l];
-          if (k != l && i == k) Bd[l] += ddv * R.iS[k];
+          Bv[i] += wg * dd[8 + i];
+          if (i == l) Bd[k] += dd[8 + i] * R.iS[l];
+          if (k != l && i == k) Bd[l] += dd[8 + i] * R.iS[k];
         }
       }
   }
@@ -135,12 +212,12 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
   double Gh[3][3][3];
   ref_christoffel(R, Gh);
   double dh[6][3], eps[6], Dh_eps[6][3];
-#pragma unroll
-  for (int a = 0; a < 6; a++) {
-    eps[a] = h[a] * SS[a];
-#pragma unroll
-    for (int k = 0; k < 3; k++) dh[a][k] = fd1k(P, G_HDD00 + a, k, sp);
+  {
+    constexpr int GH[6] = {G_HDD00, G_HDD00 + 1, G_HDD00 + 2, G_HDD00 + 3, G_HDD00 + 4, G_HDD00 + 5};
+    grad_batch<6>(P, GH, sp, dh);
   }
+#pragma unroll
+  for (int a = 0; a < 6; a++) eps[a] = h[a] * SS[a];
   // d_k eps_ij = S_i S_j d_k h_ij + h_ij d_k (S_i S_j)
   auto deps = [&](int i, int j, int k) {
     const int a = sy(i, j);
@@ -283,14 +360,18 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
         Rl[sy(i, j)] += s;
       }
     // Lambdabar terms: gammabar_k(i Dhat_j) Lambdabar^k
-    double Lam[3], DLam[3][3];
+    double Lam[3], DLam[3][3], dlam[3][3];
+    {
+      constexpr int GL[3] = {G_LAMU0, G_LAMU0 + 1, G_LAMU0 + 2};
+      grad_batch<3>(P, GL, sp, dlam);
+    }
 #pragma unroll
     for (int k = 0; k < 3; k++) Lam[k] = P.at(G_LAMU0 + k, 0, 0, 0) * R.iS[k];
 #pragma unroll
     for (int k = 0; k < 3; k++)
 #pragma unroll
       for (int j = 0; j < 3; j++) {
-        double d = fd1k(P, G_LAMU0 + k, j, sp) * R.iS[k] - Lam[k] * R.dS[k][j] * R.iS[k];
+        double d = dlam[k][j] * R.iS[k] - Lam[k] * R.dS[k][j] * R.iS[k];
 #pragma unroll
         for (int m = 0; m < 3; m++) d += Gh[k][j][m] * Lam[m];
         DLam[k][j] = d;
@@ -317,20 +398,31 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
   BHAH_PHASE_BARRIER();
 
   // ---- phase 3: the evolution equations ----------------------------------
-  auto emit = [&](int g, double v) { put(PK_OUT + g, v); };
+  // the result slots start out holding the upwinded advection terms; each
+  // equation then adds the rest of its right-hand side
+  auto emit = [&](int g, double v) { put(PK_OUT + g, get(PK_OUT + g) + v); };
   double diS[3][3];  // d_k (1/S_i)
 #pragma unroll
   for (int i = 0; i < 3; i++)
 #pragma unroll
     for (int k = 0; k < 3; k++) diS[i][k] = -R.dS[i][k] * (R.iS[i] * R.iS[i]);
   double dvet[3][3], dbeta[3][3];  // d_j vet^i, d_j beta^i
+  double dW[3], dalpha[3], dK[3], phi_d[3];
+  {
+    constexpr int GV[6] = {G_VETU0, G_VETU0 + 1, G_VETU0 + 2, G_CF, G_ALPHA, G_TRK};
+    double d6[6][3];
+    grad_batch<6>(P, GV, sp, d6);
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+      dvet[0][k] = d6[0][k]; dvet[1][k] = d6[1][k]; dvet[2][k] = d6[2][k];
+      dW[k] = d6[3][k]; dalpha[k] = d6[4][k]; dK[k] = d6[5][k];
+      phi_d[k] = -0.5 * dW[k] * iW;
+    }
+  }
 #pragma unroll
   for (int i = 0; i < 3; i++)
 #pragma unroll
-    for (int j = 0; j < 3; j++) {
-      dvet[i][j] = fd1k(P, G_VETU0 + i, j, sp);
-      dbeta[i][j] = dvet[i][j] * R.iS[i] + vet[i] * diS[i][j];
-    }
+    for (int j = 0; j < 3; j++) dbeta[i][j] = dvet[i][j] * R.iS[i] + vet[i] * diS[i][j];
   Upwind2 U;
   U.v0 = q * 8u;
   {
@@ -351,13 +443,15 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
     bS[i] = s * R.iS[i];
   }
   const double K = P.at(G_TRK, 0, 0, 0);
-  double dW[3], dalpha[3], phi_d[3];
+  // upwinded advection of all 24 rescaled variables, 4 per batch of loads
 #pragma unroll
-  for (int k = 0; k < 3; k++) {
-    dW[k] = fd1k(P, G_CF, k, sp);
-    dalpha[k] = fd1k(P, G_ALPHA, k, sp);
-    phi_d[k] = -0.5 * dW[k] * iW;
+  for (int g0 = 0; g0 < NGF; g0 += 4) {
+    double a4[4];
+    advect_batch<4>(P, g0, U, a4);
+#pragma unroll
+    for (int t = 0; t < 4; t++) put(PK_OUT + g0 + t, a4[t]);
   }
+  BHAH_PHASE_BARRIER();
   double Gbc[3];  // Gammabar^k_km
 #pragma unroll
   for (int m = 0; m < 3; m++) {
@@ -401,8 +495,8 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
   const double W2 = W * W;
 
   // Eq. 9 (W), Eq. 13 (alpha), Eq. 10 (K)
-  emit(G_CF, -(1.0 / 3.0) * W * (Dbeta - alpha * K) + advect2(P, G_CF, U));
-  emit(G_ALPHA, -2.0 * alpha * K + advect2(P, G_ALPHA, U));
+  emit(G_CF, -(1.0 / 3.0) * W * (Dbeta - alpha * K));
+  emit(G_ALPHA, -2.0 * alpha * K);
   {
     double lap = get(PK_ZA), da_dphi = 0.0;
 #pragma unroll
@@ -415,7 +509,7 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
         lap -= gbU[sy(i, j)] * Ga;
         da_dphi += gbU[sy(i, j)] * dalpha[i] * phi_d[j];
       }
-    emit(G_TRK, (1.0 / 3.0) * alpha * K * K + alpha * AA - W2 * (lap + 2.0 * da_dphi) + advect2(P, G_TRK, U));
+    emit(G_TRK, (1.0 / 3.0) * alpha * K * K + alpha * AA - W2 * (lap + 2.0 * da_dphi));
   }
   BHAH_PHASE_BARRIER();
 
@@ -439,7 +533,7 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
                  R.S[i] * R.S[i] * Dbh[i][j] - 2.0 * alpha * Abar[c];
 #pragma unroll
       for (int k = 0; k < 3; k++) r += eps[sy(k, j)] * dbeta[k][i] + eps[sy(i, k)] * dbeta[k][j];
-      emit(G_HDD00 + c, r * (R.iS[i] * R.iS[j]) + advect2(P, G_HDD00 + c, U) + h[c] * (bS[i] + bS[j]));
+      emit(G_HDD00 + c, r * (R.iS[i] * R.iS[j]) + h[c] * (bS[i] + bS[j]));
     }
   BHAH_PHASE_BARRIER();
 
@@ -474,7 +568,7 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
                    W2 * (X[c] - (1.0 / 3.0) * gb[c] * trX);
 #pragma unroll
         for (int k = 0; k < 3; k++) r += Abar[sy(k, j)] * dbeta[k][i] + Abar[sy(i, k)] * dbeta[k][j];
-        emit(G_ADD00 + c, r * (R.iS[i] * R.iS[j]) + advect2(P, G_ADD00 + c, U) + a6[c] * (bS[i] + bS[j]));
+        emit(G_ADD00 + c, r * (R.iS[i] * R.iS[j]) + a6[c] * (bS[i] + bS[j]));
       }
   }
   BHAH_PHASE_BARRIER();
@@ -483,9 +577,6 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
   {
     double dGh[3][3][3][3];
     ref_christoffel_deriv(R, dGh);
-    double dK[3];
-#pragma unroll
-    for (int k = 0; k < 3; k++) dK[k] = fd1k(P, G_TRK, k, sp);
     double ddiS[3][6];
 #pragma unroll
     for (int i = 0; i < 3; i++)
@@ -533,11 +624,11 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
       const double r = t2 + (2.0 / 3.0) * DU[i] * Dbeta + (1.0 / 3.0) * t4 - 2.0 * t5 + 2.0 * alpha * t6 -
                        (4.0 / 3.0) * alpha * t7 + lie;
       const double lam = P.at(G_LAMU0 + i, 0, 0, 0);
-      const double rl = r * R.S[i] + advect2(P, G_LAMU0 + i, U) - lam * bS[i];
-      emit(G_LAMU0 + i, rl);
+      emit(G_LAMU0 + i, r * R.S[i] - lam * bS[i]);
+      const double rl = get(PK_OUT + G_LAMU0 + i);  // full d_t lambda^i, advection included
       const double bet = P.at(G_BETU0 + i, 0, 0, 0);
-      emit(G_VETU0 + i, bet + advect2(P, G_VETU0 + i, U) - vet[i] * bS[i]);
-      emit(G_BETU0 + i, 0.75 * rl - eta * bet + advect2(P, G_BETU0 + i, U) - bet * bS[i]);
+      emit(G_VETU0 + i, bet - vet[i] * bS[i]);
+      emit(G_BETU0 + i, 0.75 * rl - eta * bet - bet * bS[i]);
     }
   }
   BHAH_PHASE_BARRIER();
@@ -569,30 +660,74 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
 #define BHAH_RHS_WAVES 1
 #endif
 
+// Block -> tile mapping. Tiles are 64 consecutive i0 points of one (i1, i2)
+// row. The hardware hands consecutive block ids to the XCDs in turn, so the
+// block id is first remapped so that every XCD works through one contiguous
+// range of tiles (its own L2 then sees a compact part of the grid); tiles are
+// ordered in bands of `band` rows of i1, then i2, then i1 within the band,
+// then i0, so the stencils of concurrently running tiles overlap.
+struct TileMap {
+  int nx;      // tiles per row, ceil(N0 / 64)
+  int ntiles;  // nx * N1 * N2
+  int per;     // tiles per XCD, ceil(ntiles / nxcd)
+  int nxcd;
+  int band;    // rows of i1 per band
+};
+
+__device__ __forceinline__ bool tile_of(const GridDev& G, const TileMap& T, int b, int& i0, int& i1, int& i2) {
+  const int w = (b % T.nxcd) * T.per + b / T.nxcd;
+  if (w >= T.ntiles) return false;
+  const int full = T.band * G.N2 * T.nx;  // tiles in one full band
+  const int nb = (G.N1 + T.band - 1) / T.band;
+  int bi = w / full;
+  if (bi > nb - 1) bi = nb - 1;
+  const int start = bi * T.band;
+  const int hgt = min(T.band, G.N1 - start);
+  const int idx = w - start * G.N2 * T.nx;
+  const int j2 = idx / (hgt * T.nx);
+  const int r = idx - j2 * hgt * T.nx;
+  const int j1 = start + r / T.nx;
+  const int xt = r - (r / T.nx) * T.nx;
+  i0 = NG + xt * 64 + (int)threadIdx.x;
+  i1 = NG + j1;
+  i2 = NG + j2;
+  return i0 < NG + G.N0;
+}
+
 template <int C>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BHAH_RHS_WAVES, BHAH_RHS_WAVES)))
-k_rhs_fused(GridDev G, double eta, const double* __restrict__ y,
-                                                  StageArgs st, double* __restrict__ aux) {
-  const int i0 = NG + (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  const int i1 = NG + (int)blockIdx.y, i2 = NG + (int)blockIdx.z;
-  if (i0 >= NG + G.N0) return;
+k_rhs_fused(GridDev G, TileMap T, double eta, const double* __restrict__ y, StageArgs st,
+            double* __restrict__ aux) {
+  int i0, i1, i2;
+  if (!tile_of(G, T, (int)blockIdx.x, i0, i1, i2)) return;
   const unsigned q = (unsigned)(i0 + G.s1 * i1 + G.s2 * i2);
   __shared__ double park[PARK * 64];
   fused_point<C>(G, eta, y, st, i0, i1, i2, q, aux, park + threadIdx.x);
 }
 
+TileMap make_tilemap(const GridDev& G, int band) {
+  TileMap T;
+  T.nx = (G.N0 + 63) / 64;
+  T.ntiles = T.nx * G.N1 * G.N2;
+  T.nxcd = BHAH_NXCD;
+  T.per = (T.ntiles + T.nxcd - 1) / T.nxcd;
+  T.band = band < 1 ? 1 : (band > G.N1 ? G.N1 : band);
+  return T;
+}
+
 void launch_rhs_fused(const GridDev& G, double eta, const double* y, double* aux, const StageArgs& st,
-                      hipStream_t s) {
-  const dim3 g((G.N0 + 63) / 64, G.N1, G.N2);
+                      hipStream_t s, int band) {
+  const TileMap T = make_tilemap(G, band);
+  const dim3 g(T.per * T.nxcd);
   switch (G.coord) {
     case BHAH_SINH_SPHERICAL:
-      hipLaunchKernelGGL(k_rhs_fused<BHAH_SINH_SPHERICAL>, g, dim3(64), 0, s, G, eta, y, st, aux);
+      hipLaunchKernelGGL(k_rhs_fused<BHAH_SINH_SPHERICAL>, g, dim3(64), 0, s, G, T, eta, y, st, aux);
       break;
     case BHAH_SINH_CYLINDRICAL:
-      hipLaunchKernelGGL(k_rhs_fused<BHAH_SINH_CYLINDRICAL>, g, dim3(64), 0, s, G, eta, y, st, aux);
+      hipLaunchKernelGGL(k_rhs_fused<BHAH_SINH_CYLINDRICAL>, g, dim3(64), 0, s, G, T, eta, y, st, aux);
       break;
     default:
-      hipLaunchKernelGGL(k_rhs_fused<BHAH_SPHERICAL>, g, dim3(64), 0, s, G, eta, y, st, aux);
+      hipLaunchKernelGGL(k_rhs_fused<BHAH_SPHERICAL>, g, dim3(64), 0, s, G, T, eta, y, st, aux);
       break;
   }
 }

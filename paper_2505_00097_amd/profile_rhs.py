@@ -1,0 +1,45 @@
+"""Profiling driver: right-hand-side launches on one workload grid.
+
+Runs `--reps` launches of the fused right-hand-side kernel on the workload's
+Brill-Lindquist state (after a few RK4 steps so every field is nonzero), then
+one plain device-to-device copy of exactly `--copy-mib` MiB, whose counters
+calibrate the HBM traffic counters (FETCH_SIZE / WRITE_SIZE) of a profile.
+Meant to run under rocprofv3.
+"""
+import argparse
+import os
+import sys
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--workload", default="vacuum3d_sinhspherical_256x128x64")
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--copy-mib", type=int, default=256)
+    args = ap.parse_args()
+    import torch
+    from paper_2505_00097_amd import capi
+    from paper_2505_00097_amd import workloads as wl
+    w = wl.WORKLOADS[args.workload]
+    g = capi.Grid(w["coord"], w["N"], w["ampl"], w["sinhw"], w["cfl"])
+    y = g.state()
+    capi.set_initial_data_brill_lindquist(g.h, w["masses"], w["positions"], y)
+    ws = g.workspace()
+    for _ in range(2):
+        capi.rk4_step(g.h, y, ws, g.dt, eta=w["eta"])
+    rhs = g.state()
+    for _ in range(args.reps):
+        capi.bssn_rhs(g.h, y, rhs, None, eta=w["eta"])
+    n = args.copy_mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"profile_rhs: {args.reps} launches on {args.workload} "
+          f"({g.info.n_interior} interior points); copied {args.copy_mib} MiB", flush=True)
+
+
+if __name__ == "__main__":
+    main()
