@@ -198,24 +198,126 @@ int bhah_hamiltonian_constraint(const bhah_grid* g, const double* y, double* H,
                                 void* stream);
 
 /* ---- ensembles: many independent grids advanced together ---------------- *
- * A batch advances n grids that share gauge parameters with the same per-point
- * arithmetic as bhah_rk4_step, launching each kernel once for all jobs.
- * The per-job states and workspaces are device pointers set per step, so jobs
- * can be swapped in and out between steps. tune_cache_path may be NULL; if it
- * names a file, tile choices are read from / written to it.                 */
+ * A batch advances n independent grids (jobs) that share gauge parameters.
+ * It is the ensemble form of bhah_rk4_step: per stage, one persistent
+ * right-hand-side kernel per coordinate family strides over a (job, tile)
+ * work list covering every active job, and one ghost-fill kernel over a
+ * (job, ghost chunk) list; a step count's worth of stages is captured once
+ * in a hipGraph and replayed. The per-point arithmetic is the same device
+ * code as bhah_rk4_step, so each job's result equals its solo evolution
+ * bit for bit. Tile shapes are chosen per size class (coordinate family and
+ * interior extents) by timing the candidates on the jobs' own data the first
+ * time the class is seen (right-hand side written into workspace, which
+ * every step overwrites anyway). tune_cache_path may be NULL; if it names a
+ * file, choices are read from it and written back (JSON, one entry per
+ * line). The same grid may appear several times (jobs of one resolution).
+ * Device memory held by the batch: a work description of roughly
+ * 600 B per job + 8 B per tile + 8 B per 256 ghost points.
+ * Errors: BHAH_EINVAL for NULL or inconsistent arguments, BHAH_EDEVICE /
+ * BHAH_ENOMEM from the runtime. Calls on one batch must not overlap and must
+ * be ordered on one stream (or the caller orders them).                      */
 int bhah_batch_create(const bhah_grid* const* grids, int n,
                       const bhah_gauge_params* gp, const char* tune_cache_path,
                       bhah_batch** out);
 
-/* Advance the jobs with host_active[j] != 0 by nsteps RK4 steps each, job j
- * at its own step host_dt[j], on y[j] (state) with workspace ws[j]. y and ws
- * are host arrays of n device pointers. The result for every job equals what
- * bhah_rk4_step gives for that job alone.                                   */
+/* Advance the jobs with host_active[j] != 0 (host_active may be NULL: all)
+ * by nsteps RK4 steps each, job j at its own step host_dt[j], on y[j]
+ * (state, valid ghosts) with workspace ws[j] (info.workspace_doubles).
+ * y, ws and host_dt are host arrays of n entries (device pointers in y, ws).
+ * Asynchronous on stream; the first call for a new size class also times
+ * tile candidates (synchronising the stream).                               */
 int bhah_batch_step(bhah_batch* b, double* const* y, double* const* ws,
                     const double* host_dt, const unsigned char* host_active,
                     int nsteps, void* stream);
 
+/* RK4 steps captured per graph (default 10; larger step counts replay it). */
+int bhah_batch_set_graph_steps(bhah_batch* b, int steps);
+
+typedef struct {
+  int n_active;          /* jobs in the current work lists                   */
+  int n_tiles;           /* (job, tile) entries, 64 points each              */
+  int n_chunks;          /* (job, 256 ghost points) entries                  */
+  int graph_steps;       /* RK4 steps per captured graph                     */
+  int rhs_blocks;        /* persistent blocks of the right-hand-side kernel  */
+  int n_classes_tuned;   /* size classes with a tile choice                  */
+  double tune_seconds;   /* wall time spent timing tile candidates           */
+} bhah_batch_info;
+
+int bhah_batch_get_info(const bhah_batch* b, bhah_batch_info* info);
+
+/* Tile choice for job j's size class: log2 extents along i0 and i1 (the
+ * extent along i2 is 64 >> (lx + ly)) and band (tile rows of i1 walked
+ * together). Defaults (6, 0, 4) before the class is tuned.                  */
+int bhah_batch_get_tile(const bhah_batch* b, int j, int* lx, int* ly, int* band);
+
 void bhah_batch_destroy(bhah_batch* b);
+
+/* ---- serving: continuous batching of evolution jobs ---------------------- *
+ * A server accepts head-on (or any Brill-Lindquist) evolution jobs as they
+ * arrive, admits them while a job slot is free and the device memory it
+ * holds for job states stays within budget_bytes, keeps every admitted
+ * job's state (state + RK4 workspace, 4 x info.state_doubles doubles) in
+ * device memory, and on each tick advances all running jobs together
+ * through one ensemble engine (bhah_batch's kernels and graphs). Jobs of one
+ * grid shape share one bhah_grid; freed state slots are reused by later jobs
+ * of the same shape. Times are seconds since bhah_server_create on the host
+ * steady clock.                                                            */
+typedef struct bhah_server bhah_server;
+
+typedef struct {
+  double budget_bytes;      /* device memory for job states                   */
+  int max_jobs;             /* running jobs at most                           */
+  int steps_per_tick;       /* RK4 steps per tick at most                     */
+  int keep_results;         /* 1: a finished job's state stays until fetched  */
+  bhah_gauge_params gauge;
+  const char* tune_cache_path; /* may be NULL                                 */
+} bhah_server_params;
+
+typedef struct {
+  bhah_grid_params grid;
+  int n_punct;              /* <= 16                                          */
+  double masses[16];
+  double pos[16][3];        /* Cartesian positions                            */
+  int lapse_kind;           /* as bhah_set_initial_data_brill_lindquist       */
+  long long nsteps;         /* RK4 steps at the grid's CFL dt (info.dt)       */
+} bhah_job_desc;
+
+enum { BHAH_JOB_QUEUED = 0, BHAH_JOB_RUNNING = 1, BHAH_JOB_DONE = 2, BHAH_JOB_RELEASED = 3 };
+
+typedef struct {
+  int state;                /* BHAH_JOB_*                                      */
+  long long steps_done;
+  long long interior_points;
+  double t_submit, t_admit, t_done;   /* -1 while not reached               */
+} bhah_job_status;
+
+typedef struct {
+  long long submitted, done, running, queued;
+  long long point_steps;    /* interior point RK4 updates done                */
+  double busy_seconds;      /* summed wall time of ticks that ran work        */
+  double elapsed_seconds;   /* since create                                   */
+  double step_ms_p50, step_ms_p99;  /* per job-step latency over all steps    */
+  double job_s_p50, job_s_p99;      /* submit -> done of finished jobs        */
+  double held_bytes, peak_held_bytes;
+  int peak_running;
+} bhah_server_stats;
+
+/* stream: the stream every device operation of the server runs on.          */
+int bhah_server_create(const bhah_server_params* p, void* stream, bhah_server** out);
+/* Queue a job (arrival time = now); *id receives its handle.                */
+int bhah_server_submit(bhah_server* s, const bhah_job_desc* job, long long* id);
+/* Admit queued jobs that fit, advance the running ones by
+ * min(steps_per_tick, fewest steps left) steps, retire finished ones.
+ * Blocks until the tick's device work is done. *running / *queued (may be
+ * NULL) receive the counts after the tick.                                  */
+int bhah_server_tick(bhah_server* s, int* running, int* queued);
+int bhah_server_job_status(const bhah_server* s, long long id, bhah_job_status* st);
+/* Copy a finished job's state (info.state_doubles doubles, device pointer
+ * dst, ordered on the server's stream and completed on return) and release
+ * its memory. BHAH_EINVAL if the job is unknown, not done or released.      */
+int bhah_server_fetch(bhah_server* s, long long id, double* dst);
+int bhah_server_get_stats(const bhah_server* s, bhah_server_stats* st);
+void bhah_server_destroy(bhah_server* s);
 
 /* Message describing the last failed call on this thread ("" if none).      */
 const char* bhah_last_error(void);

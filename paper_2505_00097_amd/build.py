@@ -23,7 +23,9 @@ SOURCES = {
     "misc.hip": DEVICE,
     "grid.cpp": [],
     "capi.cpp": [],
+    "engine.cpp": [],
     "batch.cpp": [],
+    "server.cpp": [],
 }
 
 

@@ -38,6 +38,43 @@ class GridInfo(ctypes.Structure):
                 ("dxx", ctypes.c_double * 3), ("xxmin", ctypes.c_double * 3), ("dt", ctypes.c_double)]
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("n_active", ctypes.c_int), ("n_tiles", ctypes.c_int), ("n_chunks", ctypes.c_int),
+                ("graph_steps", ctypes.c_int), ("rhs_blocks", ctypes.c_int),
+                ("n_classes_tuned", ctypes.c_int), ("tune_seconds", ctypes.c_double)]
+
+
+class ServerParams(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_double), ("max_jobs", ctypes.c_int),
+                ("steps_per_tick", ctypes.c_int), ("keep_results", ctypes.c_int),
+                ("gauge", GaugeParams), ("tune_cache_path", ctypes.c_char_p)]
+
+
+class JobDesc(ctypes.Structure):
+    _fields_ = [("grid", GridParams), ("n_punct", ctypes.c_int), ("masses", ctypes.c_double * 16),
+                ("pos", (ctypes.c_double * 3) * 16), ("lapse_kind", ctypes.c_int),
+                ("nsteps", ctypes.c_longlong)]
+
+
+class JobStatus(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int), ("steps_done", ctypes.c_longlong),
+                ("interior_points", ctypes.c_longlong), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_longlong), ("done", ctypes.c_longlong),
+                ("running", ctypes.c_longlong), ("queued", ctypes.c_longlong),
+                ("point_steps", ctypes.c_longlong), ("busy_seconds", ctypes.c_double),
+                ("elapsed_seconds", ctypes.c_double), ("step_ms_p50", ctypes.c_double),
+                ("step_ms_p99", ctypes.c_double), ("job_s_p50", ctypes.c_double),
+                ("job_s_p99", ctypes.c_double), ("held_bytes", ctypes.c_double),
+                ("peak_held_bytes", ctypes.c_double), ("peak_running", ctypes.c_int)]
+
+
+JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_RELEASED = 0, 1, 2, 3
+
+
 class BhahError(RuntimeError):
     pass
 
@@ -58,7 +95,17 @@ _SIGS = {
     "bhah_batch_create": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(GaugeParams), ctypes.c_char_p,
                                          ctypes.POINTER(_vp)]),
     "bhah_batch_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp]),
+    "bhah_batch_set_graph_steps": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "bhah_batch_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(BatchInfo)]),
+    "bhah_batch_get_tile": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp]),
     "bhah_batch_destroy": (None, [_vp]),
+    "bhah_server_create": (ctypes.c_int, [ctypes.POINTER(ServerParams), _vp, ctypes.POINTER(_vp)]),
+    "bhah_server_submit": (ctypes.c_int, [_vp, ctypes.POINTER(JobDesc), ctypes.POINTER(ctypes.c_longlong)]),
+    "bhah_server_tick": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "bhah_server_job_status": (ctypes.c_int, [_vp, ctypes.c_longlong, ctypes.POINTER(JobStatus)]),
+    "bhah_server_fetch": (ctypes.c_int, [_vp, ctypes.c_longlong, _vp]),
+    "bhah_server_get_stats": (ctypes.c_int, [_vp, ctypes.POINTER(ServerStats)]),
+    "bhah_server_destroy": (None, [_vp]),
 }
 
 
@@ -191,8 +238,80 @@ def batch_step(b, ys, wss, dts, active=None, nsteps=1, stream=None):
     _check(lib().bhah_batch_step(b, yp, wp, dp, ap, int(nsteps), _stream(stream)), "bhah_batch_step")
 
 
+def batch_set_graph_steps(b, steps):
+    _check(lib().bhah_batch_set_graph_steps(b, int(steps)), "bhah_batch_set_graph_steps")
+
+
+def batch_get_info(b):
+    info = BatchInfo()
+    _check(lib().bhah_batch_get_info(b, ctypes.byref(info)), "bhah_batch_get_info")
+    return info
+
+
+def batch_get_tile(b, j):
+    lx, ly, band = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib().bhah_batch_get_tile(b, int(j), ctypes.byref(lx), ctypes.byref(ly), ctypes.byref(band)),
+           "bhah_batch_get_tile")
+    return lx.value, ly.value, band.value
+
+
 def batch_destroy(b):
     lib().bhah_batch_destroy(b)
+
+
+def server_create(budget_bytes, max_jobs, steps_per_tick=10, keep_results=False, eta=2.0,
+                  tune_cache_path=None, stream=None):
+    p = ServerParams(float(budget_bytes), int(max_jobs), int(steps_per_tick), 1 if keep_results else 0,
+                     gauge(eta), tune_cache_path.encode() if tune_cache_path else None)
+    s = _vp()
+    _check(lib().bhah_server_create(ctypes.byref(p), _stream(stream), ctypes.byref(s)), "bhah_server_create")
+    return s
+
+
+def job_desc(coord, N, ampl, sinhw, cfl, masses, positions, nsteps, lapse_kind=0):
+    d = JobDesc()
+    d.grid = GridParams(int(coord), (ctypes.c_int * 3)(*N), 3, (ctypes.c_double * 3)(*ampl),
+                        (ctypes.c_double * 3)(*sinhw), float(cfl), 0)
+    d.n_punct = len(masses)
+    for i, (m, x) in enumerate(zip(masses, positions)):
+        d.masses[i] = float(m)
+        for k in range(3):
+            d.pos[i][k] = float(x[k])
+    d.lapse_kind = int(lapse_kind)
+    d.nsteps = int(nsteps)
+    return d
+
+
+def server_submit(s, desc):
+    i = ctypes.c_longlong()
+    _check(lib().bhah_server_submit(s, ctypes.byref(desc), ctypes.byref(i)), "bhah_server_submit")
+    return i.value
+
+
+def server_tick(s):
+    r, q = ctypes.c_int(), ctypes.c_int()
+    _check(lib().bhah_server_tick(s, ctypes.byref(r), ctypes.byref(q)), "bhah_server_tick")
+    return r.value, q.value
+
+
+def server_job_status(s, job_id):
+    st = JobStatus()
+    _check(lib().bhah_server_job_status(s, int(job_id), ctypes.byref(st)), "bhah_server_job_status")
+    return st
+
+
+def server_fetch(s, job_id, dst):
+    _check(lib().bhah_server_fetch(s, int(job_id), _ptr(dst)), "bhah_server_fetch")
+
+
+def server_get_stats(s):
+    st = ServerStats()
+    _check(lib().bhah_server_get_stats(s, ctypes.byref(st)), "bhah_server_get_stats")
+    return st
+
+
+def server_destroy(s):
+    lib().bhah_server_destroy(s)
 
 
 # ---- convenience wrapper ------------------------------------------------

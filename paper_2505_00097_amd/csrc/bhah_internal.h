@@ -67,6 +67,43 @@ struct StageArgs {
   double c2;
 };
 
+// Tile shape and walk of the right-hand-side kernel over one grid: tiles of
+// 64 points, 2^lx along i0, 2^ly along i1 and 64 >> (lx + ly) along i2,
+// walked in bands of `band` tile rows of i1.
+struct TileCfg {
+  int lx, ly, band;
+};
+
+struct TileMap {
+  int lx, ly;
+  int tx, ty, tz;  // tiles along i0, i1, i2
+  int band;        // tile rows of i1 per band
+  int ntiles;      // tx * ty * tz
+};
+
+// One job of an ensemble as the batched kernels see it. Stage s in 0..3 is
+// RK4 stage s + 1 (the right-hand side of in[s] combined as in st[s], then
+// the ghost fill of gdst[s]); stage 4 stores the right-hand side of in[4] in
+// st[4].rhs and fills nothing (used to time tile shapes).
+struct BatchJob {
+  GridDev G;
+  GhostDev gh;
+  TileMap T;
+  StageArgs st[5];
+  const double* in[5];
+  double* gdst[5];
+};
+
+// Work list header: the (job, tile) list of coordinate family c starts at
+// tile_off[c] and holds n_tiles[c] entries; the (job, chunk of 256 ghost
+// points) list holds n_chunks entries.
+struct BatchHdr {
+  int n_tiles[3];
+  int tile_off[3];
+  int n_chunks;
+  int pad;
+};
+
 }  // namespace bhah
 
 struct bhah_grid {
@@ -81,7 +118,7 @@ struct bhah_grid {
   std::vector<int> g_dst, g_start, g_par, g_src;
   std::vector<double> g_w;
   int max_terms;
-  int band;         // i1 rows per band in the RHS tile order (tunable)
+  bhah::TileCfg tile;  // tile shape and walk of the RHS kernel
   // device allocations
   double* d_tab[3];
   int* d_ints;      // dst | start | parity | src packed
@@ -90,6 +127,25 @@ struct bhah_grid {
 };
 
 namespace bhah {
+// kernel launchers (device code in the .hip sources)
+void launch_ghosts(const GhostDev& gh, double* y, long long sgf, hipStream_t s);
+int launch_brill_lindquist(const GridDev& G, int n, const double* m, const double* pos, int lapse_kind,
+                           double* y, hipStream_t s);
+void launch_rhs_fused(const GridDev& G, double eta, const double* y, double* aux, const StageArgs& st,
+                      hipStream_t s, const TileCfg& cfg);
+TileMap make_tilemap(const GridDev& G, int lx, int ly, int band);
+void launch_rhs_batch(int coord, const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage,
+                      double eta, int blocks, hipStream_t s);
+void launch_ghosts_batch(const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage, int blocks,
+                         hipStream_t s);
+void launch_hamiltonian(const GridDev& G, const double* y, double* H, hipStream_t s);
+
+// The four stages of one classical RK4 step on state y with workspace ws
+// (three state-sized arrays A, B, Cacc): inputs, stage combinations and the
+// array whose ghosts are filled after each stage.
+void rk4_stages(double dt, double* y, double* ws, long long n, StageArgs st[4], const double* in[4],
+                double* gdst[4]);
+
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);
 int check_hip(hipError_t e, const char* what);

@@ -9,12 +9,6 @@
 namespace bhah {
 
 int build_grid_host(const bhah_grid_params* p, bhah_grid* g);
-void launch_ghosts(const GhostDev& gh, double* y, long long sgf, hipStream_t s);
-int launch_brill_lindquist(const GridDev& G, int n, const double* m, const double* pos, int lapse_kind,
-                           double* y, hipStream_t s);
-void launch_rhs_fused(const GridDev& G, double eta, const double* y, double* aux, const StageArgs& st,
-                      hipStream_t s, int band);
-void launch_hamiltonian(const GridDev& G, const double* y, double* H, hipStream_t s);
 
 static thread_local std::string g_last_error;
 
@@ -31,6 +25,22 @@ int check_hip(hipError_t e, const char* what) {
 }
 
 static int check_launch(const char* what) { return check_hip(hipGetLastError(), what); }
+
+void rk4_stages(double dt, double* y, double* ws, long long n, StageArgs st[4], const double* in[4],
+                double* gdst[4]) {
+  double* A = ws;
+  double* B = ws + n;
+  double* Cacc = ws + 2 * n;
+  // classical RK4 (Sec. 4.2.1 footnote); boundary fill after each stage
+  // update and after the final combination (Sec. 3). Cacc accumulates
+  // y_n + dt/6 (k1 + 2 k2 + 2 k3).
+  st[0] = StageArgs{nullptr, y, A, 0.5 * dt, y, Cacc, dt / 6.0};
+  st[1] = StageArgs{nullptr, y, B, 0.5 * dt, Cacc, Cacc, dt / 3.0};
+  st[2] = StageArgs{nullptr, y, A, dt, Cacc, Cacc, dt / 3.0};
+  st[3] = StageArgs{nullptr, Cacc, y, dt / 6.0, nullptr, nullptr, 0.0};
+  in[0] = y; in[1] = A; in[2] = B; in[3] = A;
+  gdst[0] = A; gdst[1] = B; gdst[2] = A; gdst[3] = y;
+}
 
 static void free_device(bhah_grid* g) {
   for (int d = 0; d < 3; d++)
@@ -88,7 +98,7 @@ int bhah_grid_create(const bhah_grid_params* params, bhah_grid** out) {
     delete g;
     return code;
   }
-  g->band = BHAH_DEFAULT_BAND;
+  g->tile = TileCfg{6, 0, BHAH_DEFAULT_BAND};
   GridDev& D = g->dev;
   D.coord = params->coord;
   D.N0 = params->N[0]; D.N1 = params->N[1]; D.N2 = params->N[2];
@@ -156,7 +166,7 @@ int bhah_bssn_rhs(const bhah_grid* g, const bhah_gauge_params* gp, const double*
   if (!g || !gp || !y || !rhs) return fail(BHAH_EINVAL, "bhah_bssn_rhs: NULL argument");
   if (gp->shift_variant != 0) return fail(BHAH_EINVAL, "bhah_bssn_rhs: shift_variant must be 0");
   StageArgs st{rhs, nullptr, nullptr, 0.0, nullptr, nullptr, 0.0};
-  launch_rhs_fused(g->dev, gp->eta, y, aux, st, (hipStream_t)stream, g->band);
+  launch_rhs_fused(g->dev, gp->eta, y, aux, st, (hipStream_t)stream, g->tile);
   return check_launch("bhah_bssn_rhs");
 }
 
@@ -165,25 +175,14 @@ int bhah_rk4_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt, do
   if (!g || !gp || !y || !workspace) return fail(BHAH_EINVAL, "bhah_rk4_step: NULL argument");
   if (gp->shift_variant != 0) return fail(BHAH_EINVAL, "bhah_rk4_step: shift_variant must be 0");
   hipStream_t s = (hipStream_t)stream;
-  const long long n = g->info.state_doubles;
-  double* A = workspace;
-  double* B = workspace + n;
-  double* Cacc = workspace + 2 * n;
-  // classical RK4 (Sec. 4.2.1 footnote); boundary fill after each stage
-  // update and after the final combination (Sec. 3). Cacc accumulates
-  // y_n + dt/6 (k1 + 2 k2 + 2 k3).
-  const StageArgs s1{nullptr, y, A, 0.5 * dt, y, Cacc, dt / 6.0};
-  const StageArgs s2{nullptr, y, B, 0.5 * dt, Cacc, Cacc, dt / 3.0};
-  const StageArgs s3{nullptr, y, A, dt, Cacc, Cacc, dt / 3.0};
-  const StageArgs s4{nullptr, Cacc, y, dt / 6.0, nullptr, nullptr, 0.0};
-  launch_rhs_fused(g->dev, gp->eta, y, nullptr, s1, s, g->band);
-  launch_ghosts(g->ghost, A, g->dev.sgf, s);
-  launch_rhs_fused(g->dev, gp->eta, A, nullptr, s2, s, g->band);
-  launch_ghosts(g->ghost, B, g->dev.sgf, s);
-  launch_rhs_fused(g->dev, gp->eta, B, nullptr, s3, s, g->band);
-  launch_ghosts(g->ghost, A, g->dev.sgf, s);
-  launch_rhs_fused(g->dev, gp->eta, A, nullptr, s4, s, g->band);
-  launch_ghosts(g->ghost, y, g->dev.sgf, s);
+  StageArgs st[4];
+  const double* in[4];
+  double* gdst[4];
+  rk4_stages(dt, y, workspace, g->info.state_doubles, st, in, gdst);
+  for (int k = 0; k < 4; k++) {
+    launch_rhs_fused(g->dev, gp->eta, in[k], nullptr, st[k], s, g->tile);
+    launch_ghosts(g->ghost, gdst[k], g->dev.sgf, s);
+  }
   return check_launch("bhah_rk4_step");
 }
 

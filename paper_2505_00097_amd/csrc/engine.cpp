@@ -1,0 +1,388 @@
+// engine.cpp -- ensemble engine: work lists, graph cache and tile autotuner.
+#include "engine.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <set>
+
+namespace bhah {
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+SizeClass class_of(const bhah_grid* g) {
+  return SizeClass{g->params.coord, g->params.N[0], g->params.N[1], g->params.N[2]};
+}
+
+struct Layout {
+  size_t jobs, tiles, chunks, total;
+};
+
+Layout layout(int cap_jobs, int cap_tiles, int cap_chunks) {
+  Layout L;
+  L.jobs = align_up(sizeof(BatchHdr));
+  L.tiles = L.jobs + align_up(sizeof(BatchJob) * (size_t)cap_jobs);
+  L.chunks = L.tiles + align_up(sizeof(int2) * (size_t)cap_tiles);
+  L.total = L.chunks + align_up(sizeof(int2) * (size_t)cap_chunks);
+  return L;
+}
+
+// candidate tile configurations for one size class
+std::vector<TileCfg> candidates(const SizeClass& c) {
+  const int N0 = std::get<1>(c), N1 = std::get<2>(c), N2 = std::get<3>(c);
+  std::vector<TileCfg> out;
+  for (int lx = 6; lx >= 3; lx--)
+    for (int ly = 0; ly <= 3 && lx + ly <= 6; ly++) {
+      if (ly > 0 && (1 << ly) > N1) continue;
+      const int ez = 64 >> (lx + ly);
+      if (ez > 1 && ez > N2) continue;
+      if (lx < 6 && (1 << lx) > 2 * N0) continue;
+      const int ty = (N1 + (1 << ly) - 1) >> ly;
+      out.push_back(TileCfg{lx, ly, 1});
+      if (ty > 1) out.push_back(TileCfg{lx, ly, 4});
+    }
+  return out;
+}
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+Engine::Engine(const bhah_gauge_params& gp, const char* cache_path) : gp_(gp) {
+  if (cache_path) cache_path_ = cache_path;
+}
+
+Engine::~Engine() {
+  drop_graphs();
+  if (cap_stream_) (void)hipStreamDestroy(cap_stream_);
+  if (upload_done_) (void)hipEventDestroy(upload_done_);
+  if (d_blob_) (void)hipFree(d_blob_);
+  if (h_blob_) (void)hipHostFree(h_blob_);
+}
+
+TileCfg Engine::tile_of_class(const SizeClass& c) const {
+  auto it = tuned_.find(c);
+  return it == tuned_.end() ? TileCfg{6, 0, BHAH_DEFAULT_BAND} : it->second;
+}
+
+int Engine::set_jobs(const std::vector<EngineJob>& jobs) {
+  for (const EngineJob& j : jobs) {
+    if (!j.g || !j.y || !j.ws) return fail(BHAH_EINVAL, "batch: NULL grid, state or workspace");
+    if (j.g->params.coord < 0 || j.g->params.coord > 2) return fail(BHAH_EINVAL, "batch: bad coordinate family");
+  }
+  if (jobs != jobs_) {
+    jobs_ = jobs;
+    dirty_ = true;
+  }
+  return BHAH_OK;
+}
+
+int Engine::ensure_device(hipStream_t s) {
+  (void)s;
+  if (upload_done_) return BHAH_OK;
+  int dev = 0, cus = 0;
+  int rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (rc) return rc;
+  if ((rc = check_hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count")))
+    return rc;
+  hipDeviceProp_t prop;
+  if ((rc = check_hip(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties"))) return rc;
+  arch_ = prop.gcnArchName;
+  const size_t colon = arch_.find(':');
+  if (colon != std::string::npos) arch_ = arch_.substr(0, colon);
+  // one 64-lane block per SIMD (the RHS kernel runs at one wave per SIMD),
+  // rounded to a multiple of the XCD count
+  rhs_blocks_ = std::max(BHAH_NXCD, (4 * cus + BHAH_NXCD - 1) / BHAH_NXCD * BHAH_NXCD);
+  ghost_blocks_ = 8 * std::max(cus, 1);
+  if ((rc = check_hip(hipEventCreateWithFlags(&upload_done_, hipEventDisableTiming), "hipEventCreate"))) return rc;
+  if ((rc = check_hip(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking), "hipStreamCreate"))) return rc;
+  load_cache();
+  return BHAH_OK;
+}
+
+void Engine::drop_graphs() {
+  for (auto& kv : graphs_) (void)hipGraphExecDestroy(kv.second);
+  graphs_.clear();
+  for (int f = 0; f < 3; f++) fam_in_graphs_[f] = false;
+}
+
+// Fill the host blob: header, job table (all jobs) and work lists of the
+// jobs listed in `only` (all jobs if empty), with tile configuration cfg[j].
+// Grows the buffers if needed (dropping graphs, whose arguments point into
+// the old device buffer).
+void Engine::build_blob(const std::vector<TileCfg>& cfg, const std::vector<int>& only) {
+  std::vector<int> sel = only;
+  if (sel.empty())
+    for (int j = 0; j < (int)jobs_.size(); j++) sel.push_back(j);
+  std::vector<TileMap> maps(jobs_.size());
+  int nt = 0, nc = 0;
+  for (int j = 0; j < (int)jobs_.size(); j++)
+    maps[j] = make_tilemap(jobs_[j].g->dev, cfg[j].lx, cfg[j].ly, cfg[j].band);
+  for (int j : sel) {
+    nt += maps[j].ntiles;
+    nc += (jobs_[j].g->ghost.n_ghost + 255) / 256;
+  }
+  // the previous upload must have left the pinned buffer before it is reused
+  if (upload_done_) (void)hipEventSynchronize(upload_done_);
+  if ((int)jobs_.size() > cap_jobs_ || nt > cap_tiles_ || nc > cap_chunks_) {
+    (void)hipDeviceSynchronize();
+    drop_graphs();
+    if (d_blob_) (void)hipFree(d_blob_);
+    if (h_blob_) (void)hipHostFree(h_blob_);
+    d_blob_ = h_blob_ = nullptr;
+    cap_jobs_ = std::max<int>(cap_jobs_, (int)jobs_.size() * 3 / 2 + 1);
+    cap_tiles_ = std::max(cap_tiles_, nt * 3 / 2 + 64);
+    cap_chunks_ = std::max(cap_chunks_, nc * 3 / 2 + 64);
+    const Layout L = layout(cap_jobs_, cap_tiles_, cap_chunks_);
+    cap_bytes_ = L.total;
+    if (hipMalloc((void**)&d_blob_, cap_bytes_) != hipSuccess ||
+        hipHostMalloc((void**)&h_blob_, cap_bytes_, hipHostMallocDefault) != hipSuccess) {
+      set_error("batch: cannot allocate the work description");
+      cap_bytes_ = 0;
+      cap_jobs_ = cap_tiles_ = cap_chunks_ = 0;
+      return;
+    }
+  }
+  const Layout L = layout(cap_jobs_, cap_tiles_, cap_chunks_);
+  BatchHdr* hdr = (BatchHdr*)h_blob_;
+  BatchJob* J = (BatchJob*)(h_blob_ + L.jobs);
+  int2* tiles = (int2*)(h_blob_ + L.tiles);
+  int2* chunks = (int2*)(h_blob_ + L.chunks);
+  std::memset(hdr, 0, sizeof(BatchHdr));
+  for (int j = 0; j < (int)jobs_.size(); j++) {
+    const EngineJob& e = jobs_[j];
+    BatchJob& b = J[j];
+    b.G = e.g->dev;
+    b.gh = e.g->ghost;
+    b.T = maps[j];
+    const double* in[4];
+    double* gd[4];
+    rk4_stages(e.dt, e.y, e.ws, e.g->info.state_doubles, b.st, in, gd);
+    for (int k = 0; k < 4; k++) {
+      b.in[k] = in[k];
+      b.gdst[k] = gd[k];
+    }
+    b.st[4] = StageArgs{e.ws, nullptr, nullptr, 0.0, nullptr, nullptr, 0.0};
+    b.in[4] = e.y;
+    b.gdst[4] = nullptr;
+  }
+  int pos = 0;
+  for (int f = 0; f < 3; f++) {
+    hdr->tile_off[f] = pos;
+    for (int j : sel) {
+      if (jobs_[j].g->params.coord != f) continue;
+      for (int t = 0; t < maps[j].ntiles; t++) tiles[pos++] = int2{j, t};
+    }
+    hdr->n_tiles[f] = pos - hdr->tile_off[f];
+    fam_present_[f] = hdr->n_tiles[f] > 0 || fam_present_[f];
+  }
+  int cpos = 0;
+  for (int j : sel) {
+    const int n = (jobs_[j].g->ghost.n_ghost + 255) / 256;
+    for (int c = 0; c < n; c++) chunks[cpos++] = int2{j, c};
+  }
+  hdr->n_chunks = cpos;
+  n_tiles_ = pos;
+  n_chunks_ = cpos;
+  blob_bytes_ = (size_t)(L.chunks + sizeof(int2) * (size_t)cpos);
+}
+
+int Engine::upload(hipStream_t s) {
+  if (!d_blob_) return fail(BHAH_ENOMEM, "batch: no work description buffer");
+  int rc = check_hip(hipMemcpyAsync(d_blob_, h_blob_, blob_bytes_, hipMemcpyHostToDevice, s), "batch upload");
+  if (rc) return rc;
+  return check_hip(hipEventRecord(upload_done_, s), "hipEventRecord");
+}
+
+int Engine::time_class(const SizeClass& c, const TileCfg& cfg, hipStream_t s, double* us) {
+  std::vector<int> only;
+  std::vector<TileCfg> cfgs(jobs_.size(), TileCfg{6, 0, 1});
+  for (int j = 0; j < (int)jobs_.size(); j++)
+    if (class_of(jobs_[j].g) == c) {
+      only.push_back(j);
+      cfgs[j] = cfg;
+    }
+  build_blob(cfgs, only);
+  int rc = upload(s);
+  if (rc) return rc;
+  const Layout L = layout(cap_jobs_, cap_tiles_, cap_chunks_);
+  const BatchJob* dj = (const BatchJob*)(d_blob_ + L.jobs);
+  const BatchHdr* dh = (const BatchHdr*)d_blob_;
+  const int2* dt = (const int2*)(d_blob_ + L.tiles);
+  const int coord = std::get<0>(c);
+  hipEvent_t e0, e1;
+  if ((rc = check_hip(hipEventCreate(&e0), "hipEventCreate"))) return rc;
+  if ((rc = check_hip(hipEventCreate(&e1), "hipEventCreate"))) { (void)hipEventDestroy(e0); return rc; }
+  const int reps = 3;
+  launch_rhs_batch(coord, dj, dh, dt, 4, gp_.eta, rhs_blocks_, s);
+  (void)hipEventRecord(e0, s);
+  for (int r = 0; r < reps; r++) launch_rhs_batch(coord, dj, dh, dt, 4, gp_.eta, rhs_blocks_, s);
+  (void)hipEventRecord(e1, s);
+  rc = check_hip(hipEventSynchronize(e1), "tile timing");
+  float ms = 0.f;
+  if (!rc) rc = check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *us = 1e3 * ms / reps;
+  return rc;
+}
+
+int Engine::tune_missing(hipStream_t s) {
+  std::set<SizeClass> todo;
+  for (const EngineJob& j : jobs_)
+    if (!tuned_.count(class_of(j.g))) todo.insert(class_of(j.g));
+  if (todo.empty()) return BHAH_OK;
+  const double t0 = now_s();
+  for (const SizeClass& c : todo) {
+    double best = 1e300;
+    TileCfg bc{6, 0, 1};
+    for (const TileCfg& cfg : candidates(c)) {
+      double us = 0.0;
+      const int rc = time_class(c, cfg, s, &us);
+      if (rc) return rc;
+      if (us < best) {
+        best = us;
+        bc = cfg;
+      }
+    }
+    tuned_[c] = bc;
+    tuned_us_[c] = best;
+  }
+  tune_seconds_ += now_s() - t0;
+  dirty_ = true;
+  save_cache();
+  return BHAH_OK;
+}
+
+int Engine::capture(int nsteps, hipStream_t s, hipGraphExec_t* out) {
+  (void)s;
+  const Layout L = layout(cap_jobs_, cap_tiles_, cap_chunks_);
+  const BatchJob* dj = (const BatchJob*)(d_blob_ + L.jobs);
+  const BatchHdr* dh = (const BatchHdr*)d_blob_;
+  const int2* dt = (const int2*)(d_blob_ + L.tiles);
+  const int2* dc = (const int2*)(d_blob_ + L.chunks);
+  int rc = check_hip(hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal), "graph capture");
+  if (rc) return rc;
+  for (int k = 0; k < nsteps; k++)
+    for (int stage = 0; stage < 4; stage++) {
+      for (int f = 0; f < 3; f++)
+        if (fam_present_[f]) launch_rhs_batch(f, dj, dh, dt, stage, gp_.eta, rhs_blocks_, cap_stream_);
+      launch_ghosts_batch(dj, dh, dc, stage, ghost_blocks_, cap_stream_);
+    }
+  hipGraph_t graph = nullptr;
+  const hipError_t le = hipGetLastError();
+  rc = check_hip(hipStreamEndCapture(cap_stream_, &graph), "graph capture end");
+  if (!rc && le != hipSuccess) rc = check_hip(le, "graph capture launch");
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  rc = check_hip(hipGraphInstantiate(out, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+  (void)hipGraphDestroy(graph);
+  for (int f = 0; f < 3; f++) fam_in_graphs_[f] = fam_present_[f];
+  return rc;
+}
+
+int Engine::step(int nsteps, hipStream_t s) {
+  if (nsteps < 0) return fail(BHAH_EINVAL, "batch: nsteps < 0");
+  if (jobs_.empty() || nsteps == 0) return BHAH_OK;
+  int rc = ensure_device(s);
+  if (rc) return rc;
+  if ((rc = tune_missing(s))) return rc;
+  if (dirty_) {
+    std::vector<TileCfg> cfg;
+    for (const EngineJob& j : jobs_) cfg.push_back(tile_of_class(class_of(j.g)));
+    build_blob(cfg, {});
+    if ((rc = upload(s))) return rc;
+    dirty_ = false;
+  }
+  for (int f = 0; f < 3; f++)
+    if (fam_present_[f] && !fam_in_graphs_[f]) drop_graphs();
+  while (nsteps > 0) {
+    const int k = std::min(nsteps, graph_steps_);
+    auto it = graphs_.find(k);
+    if (it == graphs_.end()) {
+      hipGraphExec_t ex = nullptr;
+      if ((rc = capture(k, s, &ex))) return rc;
+      it = graphs_.emplace(k, ex).first;
+    }
+    if ((rc = check_hip(hipGraphLaunch(it->second, s), "hipGraphLaunch"))) return rc;
+    nsteps -= k;
+  }
+  return BHAH_OK;
+}
+
+// ---- tile cache: one JSON object per line inside an "entries" array -----
+void Engine::load_cache() {
+  if (cache_path_.empty()) return;
+  FILE* f = std::fopen(cache_path_.c_str(), "r");
+  if (!f) return;
+  char line[512];
+  while (std::fgets(line, sizeof line, f)) {
+    char arch[64];
+    int coord, n0, n1, n2, lx, ly, band;
+    double us;
+    const char* p = std::strchr(line, '{');
+    if (!p) continue;
+    if (std::sscanf(p, "{\"arch\": \"%63[^\"]\", \"coord\": %d, \"N\": [%d, %d, %d], \"lx\": %d, \"ly\": %d, "
+                       "\"band\": %d, \"us\": %lf}",
+                    arch, &coord, &n0, &n1, &n2, &lx, &ly, &band, &us) != 9)
+      continue;
+    if (arch_ != arch) continue;
+    if (lx < 0 || ly < 0 || lx + ly > 6 || band < 1) continue;
+    tuned_[SizeClass{coord, n0, n1, n2}] = TileCfg{lx, ly, band};
+    tuned_us_[SizeClass{coord, n0, n1, n2}] = us;
+  }
+  std::fclose(f);
+}
+
+void Engine::save_cache() {
+  if (cache_path_.empty()) return;
+  // keep entries of other architectures that are in the file
+  std::vector<std::string> keep;
+  if (FILE* f = std::fopen(cache_path_.c_str(), "r")) {
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+      const char* p = std::strstr(line, "{\"arch\": \"");
+      if (!p) continue;
+      const std::string a = std::string("{\"arch\": \"") + arch_ + "\"";
+      if (std::strncmp(p, a.c_str(), a.size()) == 0) continue;
+      std::string l(p);
+      while (!l.empty() && (l.back() == '\n' || l.back() == ',' || l.back() == ' ')) l.pop_back();
+      keep.push_back(l);
+    }
+    std::fclose(f);
+  }
+  const std::string tmp = cache_path_ + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;
+  std::fprintf(f, "{\"bhah_tile_cache\": 1, \"entries\": [\n");
+  bool first = true;
+  for (const std::string& l : keep) {
+    std::fprintf(f, "%s%s", first ? "" : ",\n", l.c_str());
+    first = false;
+  }
+  for (const auto& kv : tuned_) {
+    const SizeClass& c = kv.first;
+    const auto u = tuned_us_.find(c);
+    std::fprintf(f,
+                 "%s{\"arch\": \"%s\", \"coord\": %d, \"N\": [%d, %d, %d], \"lx\": %d, \"ly\": %d, \"band\": %d, "
+                 "\"us\": %.3f}",
+                 first ? "" : ",\n", arch_.c_str(), std::get<0>(c), std::get<1>(c), std::get<2>(c),
+                 std::get<3>(c), kv.second.lx, kv.second.ly, kv.second.band,
+                 u == tuned_us_.end() ? 0.0 : u->second);
+    first = false;
+  }
+  std::fprintf(f, "\n]}\n");
+  std::fclose(f);
+  std::rename(tmp.c_str(), cache_path_.c_str());
+}
+
+}  // namespace bhah

@@ -1,0 +1,91 @@
+// engine.h -- advancing an ensemble of independent grids together.
+//
+// The engine owns a device work description (job table + per-family (job,
+// tile) lists + (job, ghost chunk) list, uploaded as one blob) and a cache of
+// instantiated hipGraphs, one per step count, each replaying
+// steps x 4 stages x [batched RHS kernel per coordinate family, batched ghost
+// kernel]. The graphs read the blob at run time, so a changed job set only
+// needs a new upload, not a new graph. Tile shapes are chosen per size class
+// (coordinate family + interior extents) by timing candidates on the jobs
+// themselves; choices persist in a small JSON cache file.
+#pragma once
+
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "bhah_internal.h"
+
+namespace bhah {
+
+struct EngineJob {
+  const bhah_grid* g;
+  double* y;
+  double* ws;
+  double dt;
+  bool operator==(const EngineJob& o) const { return g == o.g && y == o.y && ws == o.ws && dt == o.dt; }
+};
+
+using SizeClass = std::tuple<int, int, int, int>;  // coord, N0, N1, N2
+
+class Engine {
+ public:
+  Engine(const bhah_gauge_params& gp, const char* cache_path);
+  ~Engine();
+  Engine(const Engine&) = delete;
+  Engine& operator=(const Engine&) = delete;
+
+  // Replace the job set (takes effect at the next step). Returns a status.
+  int set_jobs(const std::vector<EngineJob>& jobs);
+  // Advance every job by nsteps RK4 steps on stream s (asynchronous).
+  int step(int nsteps, hipStream_t s);
+  void set_graph_steps(int S) { graph_steps_ = S < 1 ? 1 : S; }
+
+  int n_jobs() const { return (int)jobs_.size(); }
+  int n_tiles() const { return n_tiles_; }
+  int n_chunks() const { return n_chunks_; }
+  int graph_steps() const { return graph_steps_; }
+  int rhs_blocks() const { return rhs_blocks_; }
+  int n_classes_tuned() const { return (int)tuned_.size(); }
+  double tune_seconds() const { return tune_seconds_; }
+  TileCfg tile_of_class(const SizeClass& c) const;
+
+ private:
+  int ensure_device(hipStream_t s);
+  int tune_missing(hipStream_t s);
+  int time_class(const SizeClass& c, const TileCfg& cfg, hipStream_t s, double* us);
+  void build_blob(const std::vector<TileCfg>& cfg, const std::vector<int>& only);
+  int upload(hipStream_t s);
+  int capture(int nsteps, hipStream_t s, hipGraphExec_t* out);
+  void drop_graphs();
+  void load_cache();
+  void save_cache();
+
+  bhah_gauge_params gp_;
+  std::string cache_path_;
+  std::string arch_;
+  std::vector<EngineJob> jobs_;
+  bool dirty_ = true;
+  std::map<SizeClass, TileCfg> tuned_;
+  std::map<SizeClass, double> tuned_us_;
+  double tune_seconds_ = 0.0;
+
+  // host blob (pinned) and its device copy
+  char* h_blob_ = nullptr;
+  char* d_blob_ = nullptr;
+  size_t cap_bytes_ = 0;
+  size_t blob_bytes_ = 0;
+  int cap_jobs_ = 0, cap_tiles_ = 0, cap_chunks_ = 0;
+  hipEvent_t upload_done_ = nullptr;
+  int n_tiles_ = 0, n_chunks_ = 0;
+  bool fam_present_[3] = {false, false, false};
+  bool fam_in_graphs_[3] = {false, false, false};
+
+  int rhs_blocks_ = 0, ghost_blocks_ = 0;
+  int graph_steps_ = 10;
+  std::map<int, hipGraphExec_t> graphs_;
+  hipStream_t cap_stream_ = nullptr;
+};
+
+}  // namespace bhah

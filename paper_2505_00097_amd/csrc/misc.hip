@@ -16,9 +16,7 @@ __device__ __forceinline__ int gf_flip(int g, int par) {
 // Every ghost point takes sign * sum_t w_t y[src_t]; all sources are interior
 // points, so ghosts can be filled in any order and in parallel (Sec. 3
 // outer-then-inner boundary order is folded into the weights on the host).
-__global__ void __launch_bounds__(256) k_ghosts(GhostDev gh, double* __restrict__ y, long long sgf) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= gh.n_ghost) return;
+__device__ __forceinline__ void ghost_point(const GhostDev& gh, double* __restrict__ y, long long sgf, int t) {
   const int dst = gh.dst[t], s0 = gh.start[t], s1 = gh.start[t + 1], par = gh.parity[t];
   // all loads before any store: sources are interior points, never ghosts,
   // but the compiler cannot know that and would otherwise keep each load
@@ -42,9 +40,33 @@ __global__ void __launch_bounds__(256) k_ghosts(GhostDev gh, double* __restrict_
   for (int g = 0; g < NGF; g++) y[g * sgf + dst] = gf_flip(g, par) ? -v[g] : v[g];
 }
 
+__global__ void __launch_bounds__(256) k_ghosts(GhostDev gh, double* __restrict__ y, long long sgf) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < gh.n_ghost) ghost_point(gh, y, sgf, t);
+}
+
 void launch_ghosts(const GhostDev& gh, double* y, long long sgf, hipStream_t s) {
   if (gh.n_ghost == 0) return;
   hipLaunchKernelGGL(k_ghosts, dim3((gh.n_ghost + 255) / 256), dim3(256), 0, s, gh, y, sgf);
+}
+
+// Ensemble form: a fixed grid of blocks strides over the (job, chunk of 256
+// ghost points) work list and fills the ghosts of the stage's target array.
+__global__ void __launch_bounds__(256) k_ghosts_batch(const BatchJob* __restrict__ jobs,
+                                                      const BatchHdr* __restrict__ hdr,
+                                                      const int2* __restrict__ work, int stage) {
+  const int n = hdr->n_chunks;
+  for (int c = (int)blockIdx.x; c < n; c += (int)gridDim.x) {
+    const int2 wk = work[c];
+    const BatchJob* J = jobs + wk.x;
+    const int t = wk.y * 256 + (int)threadIdx.x;
+    if (t < J->gh.n_ghost) ghost_point(J->gh, J->gdst[stage], J->G.sgf, t);
+  }
+}
+
+void launch_ghosts_batch(const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage, int blocks,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_ghosts_batch, dim3(blocks), dim3(256), 0, s, jobs, hdr, work, stage);
 }
 
 constexpr int MAX_PUNCT = 16;

@@ -660,65 +660,93 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
 #define BHAH_RHS_WAVES 1
 #endif
 
-// Block -> tile mapping. Tiles are 64 consecutive i0 points of one (i1, i2)
-// row. The hardware hands consecutive block ids to the XCDs in turn, so the
-// block id is first remapped so that every XCD works through one contiguous
-// range of tiles (its own L2 then sees a compact part of the grid); tiles are
-// ordered in bands of `band` rows of i1, then i2, then i1 within the band,
-// then i0, so the stencils of concurrently running tiles overlap.
-struct TileMap {
-  int nx;      // tiles per row, ceil(N0 / 64)
-  int ntiles;  // nx * N1 * N2
-  int per;     // tiles per XCD, ceil(ntiles / nxcd)
-  int nxcd;
-  int band;    // rows of i1 per band
-};
-
-__device__ __forceinline__ bool tile_of(const GridDev& G, const TileMap& T, int b, int& i0, int& i1, int& i2) {
-  const int w = (b % T.nxcd) * T.per + b / T.nxcd;
-  if (w >= T.ntiles) return false;
-  const int full = T.band * G.N2 * T.nx;  // tiles in one full band
-  const int nb = (G.N1 + T.band - 1) / T.band;
+// Tiles: 64 points, 2^lx along i0 times 2^ly along i1 times 64 >> (lx + ly)
+// along i2; the tile grid is walked in bands of `band` tile rows of i1, then
+// i2, then i1 within the band, then i0, so the stencils of tiles that run at
+// the same time overlap. The hardware hands consecutive workgroup ids to the
+// XCDs in turn; block ids are remapped so that every XCD works through one
+// contiguous range of the walk (its L2 then holds a compact part of the grid).
+__device__ __forceinline__ bool tile_point(const GridDev& G, const TileMap& T, int w, int lane, int& i0,
+                                           int& i1, int& i2) {
+  const int full = T.band * T.tz * T.tx;  // tiles in one full band
+  const int nb = (T.ty + T.band - 1) / T.band;
   int bi = w / full;
   if (bi > nb - 1) bi = nb - 1;
   const int start = bi * T.band;
-  const int hgt = min(T.band, G.N1 - start);
-  const int idx = w - start * G.N2 * T.nx;
-  const int j2 = idx / (hgt * T.nx);
-  const int r = idx - j2 * hgt * T.nx;
-  const int j1 = start + r / T.nx;
-  const int xt = r - (r / T.nx) * T.nx;
-  i0 = NG + xt * 64 + (int)threadIdx.x;
-  i1 = NG + j1;
-  i2 = NG + j2;
-  return i0 < NG + G.N0;
+  const int hgt = min(T.band, T.ty - start);
+  const int idx = w - start * T.tz * T.tx;
+  const int j2 = idx / (hgt * T.tx);
+  const int r = idx - j2 * hgt * T.tx;
+  const int j1 = start + r / T.tx;
+  const int xt = r - (r / T.tx) * T.tx;
+  const int ex = 1 << T.lx, ey = 1 << T.ly;
+  i0 = NG + xt * ex + (lane & (ex - 1));
+  i1 = NG + j1 * ey + ((lane >> T.lx) & (ey - 1));
+  i2 = NG + (j2 << (6 - T.lx - T.ly)) + (lane >> (T.lx + T.ly));
+  return i0 < NG + G.N0 && i1 < NG + G.N1 && i2 < NG + G.N2;
 }
+
+// logical position in the walk of the tile a block works on; with G_blocks a
+// multiple of the XCD count, block b runs on XCD b % nxcd
+__device__ __forceinline__ int xcd_remap(int b, int per) { return (b % BHAH_NXCD) * per + b / BHAH_NXCD; }
 
 template <int C>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BHAH_RHS_WAVES, BHAH_RHS_WAVES)))
 k_rhs_fused(GridDev G, TileMap T, double eta, const double* __restrict__ y, StageArgs st,
             double* __restrict__ aux) {
+  const int per = (T.ntiles + BHAH_NXCD - 1) / BHAH_NXCD;
+  const int w = xcd_remap((int)blockIdx.x, per);
+  if (w >= T.ntiles) return;
   int i0, i1, i2;
-  if (!tile_of(G, T, (int)blockIdx.x, i0, i1, i2)) return;
+  if (!tile_point(G, T, w, (int)threadIdx.x, i0, i1, i2)) return;
   const unsigned q = (unsigned)(i0 + G.s1 * i1 + G.s2 * i2);
   __shared__ double park[PARK * 64];
   fused_point<C>(G, eta, y, st, i0, i1, i2, q, aux, park + threadIdx.x);
 }
 
-TileMap make_tilemap(const GridDev& G, int band) {
+// Persistent form for ensembles: a fixed grid of blocks (a multiple of the XCD
+// count) strides over one coordinate family's (job, tile) work list; every
+// point runs the same fused_point as above.
+template <int C>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BHAH_RHS_WAVES, BHAH_RHS_WAVES)))
+k_rhs_batch(const BatchJob* __restrict__ jobs, const BatchHdr* __restrict__ hdr, const int2* __restrict__ work,
+            int stage, double eta) {
+  const int n = hdr->n_tiles[C];
+  const int2* wl = work + hdr->tile_off[C];
+  const int per = (n + BHAH_NXCD - 1) / BHAH_NXCD;
+  __shared__ double park[PARK * 64];
+  for (int t = (int)blockIdx.x; t < per * BHAH_NXCD; t += (int)gridDim.x) {
+    const int w = xcd_remap(t, per);
+    if (w >= n) continue;
+    const int2 wk = wl[w];
+    const BatchJob* J = jobs + wk.x;
+    const GridDev G = J->G;
+    int i0, i1, i2;
+    if (!tile_point(G, J->T, wk.y, (int)threadIdx.x, i0, i1, i2)) continue;
+    const unsigned q = (unsigned)(i0 + G.s1 * i1 + G.s2 * i2);
+    const StageArgs st = J->st[stage];
+    fused_point<C>(G, eta, J->in[stage], st, i0, i1, i2, q, nullptr, park + threadIdx.x);
+  }
+}
+
+TileMap make_tilemap(const GridDev& G, int lx, int ly, int band) {
   TileMap T;
-  T.nx = (G.N0 + 63) / 64;
-  T.ntiles = T.nx * G.N1 * G.N2;
-  T.nxcd = BHAH_NXCD;
-  T.per = (T.ntiles + T.nxcd - 1) / T.nxcd;
-  T.band = band < 1 ? 1 : (band > G.N1 ? G.N1 : band);
+  T.lx = lx;
+  T.ly = ly;
+  const int ex = 1 << lx, ey = 1 << ly, ez = 64 >> (lx + ly);
+  T.tx = (G.N0 + ex - 1) / ex;
+  T.ty = (G.N1 + ey - 1) / ey;
+  T.tz = (G.N2 + ez - 1) / ez;
+  T.ntiles = T.tx * T.ty * T.tz;
+  T.band = band < 1 ? 1 : (band > T.ty ? T.ty : band);
   return T;
 }
 
 void launch_rhs_fused(const GridDev& G, double eta, const double* y, double* aux, const StageArgs& st,
-                      hipStream_t s, int band) {
-  const TileMap T = make_tilemap(G, band);
-  const dim3 g(T.per * T.nxcd);
+                      hipStream_t s, const TileCfg& cfg) {
+  const TileMap T = make_tilemap(G, cfg.lx, cfg.ly, cfg.band);
+  const int per = (T.ntiles + BHAH_NXCD - 1) / BHAH_NXCD;
+  const dim3 g(per * BHAH_NXCD);
   switch (G.coord) {
     case BHAH_SINH_SPHERICAL:
       hipLaunchKernelGGL(k_rhs_fused<BHAH_SINH_SPHERICAL>, g, dim3(64), 0, s, G, T, eta, y, st, aux);
@@ -728,6 +756,22 @@ void launch_rhs_fused(const GridDev& G, double eta, const double* y, double* aux
       break;
     default:
       hipLaunchKernelGGL(k_rhs_fused<BHAH_SPHERICAL>, g, dim3(64), 0, s, G, T, eta, y, st, aux);
+      break;
+  }
+}
+
+void launch_rhs_batch(int coord, const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage,
+                      double eta, int blocks, hipStream_t s) {
+  const dim3 g(blocks), b(64);
+  switch (coord) {
+    case BHAH_SINH_SPHERICAL:
+      hipLaunchKernelGGL(k_rhs_batch<BHAH_SINH_SPHERICAL>, g, b, 0, s, jobs, hdr, work, stage, eta);
+      break;
+    case BHAH_SINH_CYLINDRICAL:
+      hipLaunchKernelGGL(k_rhs_batch<BHAH_SINH_CYLINDRICAL>, g, b, 0, s, jobs, hdr, work, stage, eta);
+      break;
+    default:
+      hipLaunchKernelGGL(k_rhs_batch<BHAH_SPHERICAL>, g, b, 0, s, jobs, hdr, work, stage, eta);
       break;
   }
 }

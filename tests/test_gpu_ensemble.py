@@ -1,0 +1,250 @@
+"""Ensembles and serving through the C ABI.
+
+The batched kernels run the same per-point device code as bhah_rk4_step, so
+every job of a batch, and every job run by the server, must equal its solo
+evolution bit for bit, whatever the tile shape, the job mix, the order of
+admission or the number of steps per captured graph. The solo path itself is
+checked against the oracle elsewhere; one batch job is also checked against
+the oracle directly here.
+"""
+import json
+
+import numpy as np
+import pytest
+
+from gpu_helpers import gf_errors, to_cpu
+from oracle import oracle as orc
+from paper_2505_00097_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(*a):
+    print("CASE", *a, flush=True)
+
+
+def _small_jobs():
+    """Mixed families, ragged sizes, one grid used by two jobs."""
+    jobs = wl.batched_jobs(n=3, seed=7)
+    for j in jobs:
+        j["N"] = (j["N"][0] // 4, 2, j["N"][2] // 4)
+    jobs.append(dict(jobs[0], masses=[0.3, 0.2], positions=[(0.0, 0.0, 0.4), (0.0, 0.0, -0.6)]))
+    jobs.append(dict(coord=wl.SINH_SPHERICAL, N=(20, 10, 6), ampl=(10.0,) * 3, sinhw=(0.2,) * 3, cfl=0.5,
+                     masses=[0.6, 0.4], positions=[(0.7, 0.0, 0.1), (-0.7, 0.0, -0.1)], eta=2.0))
+    jobs.append(dict(coord=wl.SPHERICAL, N=(18, 6, 12), ampl=(7.5,) * 3, sinhw=(0.2,) * 3, cfl=0.5,
+                     masses=[1.0], positions=[(0.0, 0.0, 0.0)], eta=2.0))
+    return jobs
+
+
+def _setup(jobs):
+    from paper_2505_00097_amd import capi
+    grids, ys, wss = [], [], []
+    cache = {}
+    for j in jobs:
+        key = (j["coord"], tuple(j["N"]), tuple(j["ampl"]), tuple(j["sinhw"]))
+        if key not in cache:
+            cache[key] = capi.Grid(j["coord"], j["N"], j["ampl"], j["sinhw"], j["cfl"])
+        g = cache[key]
+        y = g.state()
+        capi.set_initial_data_brill_lindquist(g.h, j["masses"], j["positions"], y)
+        grids.append(g)
+        ys.append(y)
+        wss.append(g.workspace())
+    return grids, ys, wss
+
+
+def _solo(grids, ys0, nsteps):
+    import torch
+    from paper_2505_00097_amd import capi
+    out = []
+    for g, y0, n in zip(grids, ys0, nsteps):
+        y = y0.clone()
+        ws = g.workspace()
+        for _ in range(n):
+            capi.rk4_step(g.h, y, ws, g.dt)
+        out.append(y)
+    torch.cuda.synchronize()
+    return out
+
+
+def test_batch_matches_solo_bitwise(tmp_path):
+    _case("batch mixed families")
+    import torch
+    from paper_2505_00097_amd import capi
+    jobs = _small_jobs()
+    grids, ys, wss = _setup(jobs)
+    ys0 = [y.clone() for y in ys]
+    cache = str(tmp_path / "tiles.json")
+    b = capi.batch_create([g.h for g in grids], eta=2.0, tune_cache_path=cache)
+    capi.batch_set_graph_steps(b, 5)
+    capi.batch_step(b, ys, wss, [g.dt for g in grids], nsteps=12)
+    torch.cuda.synchronize()
+    info = capi.batch_get_info(b)
+    assert info.n_active == len(jobs) and info.graph_steps == 5
+    assert info.n_classes_tuned == len({(j["coord"], tuple(j["N"])) for j in jobs})
+    solo = _solo(grids, ys0, [12] * len(jobs))
+    for k, (y, s) in enumerate(zip(ys, solo)):
+        assert torch.equal(y, s), k
+    entries = json.load(open(cache))["entries"]
+    assert len(entries) == info.n_classes_tuned
+    for j in range(len(jobs)):
+        lx, ly, band = capi.batch_get_tile(b, j)
+        assert 3 <= lx <= 6 and 0 <= ly and lx + ly <= 6 and band >= 1
+    capi.batch_destroy(b)
+
+
+def test_batch_active_mask_and_swaps():
+    _case("batch active mask")
+    import torch
+    from paper_2505_00097_amd import capi
+    jobs = _small_jobs()[:4]
+    grids, ys, wss = _setup(jobs)
+    ys0 = [y.clone() for y in ys]
+    b = capi.batch_create([g.h for g in grids], eta=2.0)
+    dts = [g.dt for g in grids]
+    capi.batch_step(b, ys, wss, dts, active=[1, 0, 1, 0], nsteps=3)
+    capi.batch_step(b, ys, wss, dts, active=[1, 1, 0, 1], nsteps=4)
+    # swap job 2's state for a fresh copy: new pointers, same grid
+    y2 = ys0[2].clone()
+    ys[2] = y2
+    capi.batch_step(b, ys, wss, dts, nsteps=2)
+    torch.cuda.synchronize()
+    solo = _solo(grids, ys0, [9, 6, 2, 6])
+    for k, (y, s) in enumerate(zip(ys, solo)):
+        assert torch.equal(y, s), k
+    capi.batch_destroy(b)
+
+
+@pytest.mark.parametrize("shape", [(6, 0, 4), (5, 1, 1), (4, 0, 1), (4, 1, 4), (3, 0, 4), (3, 3, 1), (4, 2, 4)])
+def test_every_tile_shape_covers_each_point_once(tmp_path, shape):
+    """Force a tile shape through the cache file; ragged extents in all three
+    directions must give the solo result exactly."""
+    _case("tile shape", shape)
+    import torch
+    from paper_2505_00097_amd import capi
+    jobs = [dict(coord=wl.SINH_SPHERICAL, N=(37, 11, 6), ampl=(10.0,) * 3, sinhw=(0.2,) * 3, cfl=0.5,
+                 masses=[0.6, 0.4], positions=[(0.7, 0.1, 0.0), (-0.7, 0.0, 0.2)], eta=2.0),
+            dict(wl.headon_job(2.0, 1.0, 29), N=(29, 2, 45))]
+    grids, ys, wss = _setup(jobs)
+    ys0 = [y.clone() for y in ys]
+    lx, ly, band = shape
+    path = tmp_path / "tiles.json"
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    lines = [json.dumps({"arch": arch, "coord": j["coord"], "N": list(j["N"]), "lx": lx, "ly": ly,
+                         "band": band, "us": 1.0}) for j in jobs]
+    path.write_text('{"bhah_tile_cache": 1, "entries": [\n' + ",\n".join(lines) + "\n]}\n")
+    b = capi.batch_create([g.h for g in grids], eta=2.0, tune_cache_path=str(path))
+    capi.batch_step(b, ys, wss, [g.dt for g in grids], nsteps=2)
+    torch.cuda.synchronize()
+    assert capi.batch_get_info(b).tune_seconds == 0.0
+    for j in range(len(jobs)):
+        assert capi.batch_get_tile(b, j) == shape
+    solo = _solo(grids, ys0, [2, 2])
+    for k, (y, s) in enumerate(zip(ys, solo)):
+        assert torch.equal(y, s), (k, shape)
+    capi.batch_destroy(b)
+
+
+def test_batch_job_against_oracle():
+    _case("batch vs oracle")
+    import torch
+    from paper_2505_00097_amd import capi
+    jobs = _small_jobs()
+    grids, ys, wss = _setup(jobs)
+    b = capi.batch_create([g.h for g in grids], eta=2.0)
+    n = 10
+    capi.batch_step(b, ys, wss, [g.dt for g in grids], nsteps=n)
+    torch.cuda.synchronize()
+    for k in (0, 4):
+        j = jobs[k]
+        og = orc.Grid(j["coord"], j["N"], ampl=j["ampl"], sinhw=j["sinhw"], cfl=j["cfl"])
+        yo = og.brill_lindquist(j["masses"], j["positions"])
+        for _ in range(n):
+            og.rk4_step(yo, og.dt(), eta=2.0)
+        err = gf_errors(to_cpu(ys[k]), yo, og.interior())
+        assert np.all(err <= 1e-9), err
+    capi.batch_destroy(b)
+
+
+def test_batch_ensemble_workload_sample():
+    """The first 16 jobs of the 64-job ensemble at full size, 2 steps."""
+    _case("batch ensemble sample")
+    import torch
+    from paper_2505_00097_amd import capi
+    jobs = wl.batched_jobs()[:16]
+    grids, ys, wss = _setup(jobs)
+    ys0 = [y.clone() for y in ys]
+    b = capi.batch_create([g.h for g in grids], eta=2.0)
+    capi.batch_step(b, ys, wss, [g.dt for g in grids], nsteps=2)
+    torch.cuda.synchronize()
+    solo = _solo(grids, ys0, [2] * len(jobs))
+    for k, (y, s) in enumerate(zip(ys, solo)):
+        assert torch.equal(y, s), k
+    capi.batch_destroy(b)
+
+
+def _server_jobs():
+    base = [wl.headon_job(1.5, 1.0, 24), wl.headon_job(3.0, 1.6, 40), wl.headon_job(2.0, 0.9, 24),
+            wl.headon_job(6.0, 2.5, 40), wl.headon_job(1.0, 1.2, 24)]
+    steps = [7, 12, 3, 20, 0]
+    for j, s in zip(base, steps):
+        j["steps"] = s
+    return base
+
+
+def test_server_results_same_alone_and_in_mix():
+    """Continuous batching: a budget of two state slots of the larger grid
+    forces queueing and slot reuse; each fetched result equals the job run
+    alone."""
+    _case("server mix")
+    import torch
+    from paper_2505_00097_amd import capi
+    jobs = _server_jobs()
+    gbig = capi.Grid(jobs[1]["coord"], jobs[1]["N"], jobs[1]["ampl"], jobs[1]["sinhw"], jobs[1]["cfl"])
+    slab = 4 * 8 * gbig.info.state_doubles
+    budget = 2 * slab
+    srv = capi.server_create(budget, max_jobs=3, steps_per_tick=4, keep_results=True)
+    ids = []
+    for j in jobs:
+        d = capi.job_desc(j["coord"], j["N"], j["ampl"], j["sinhw"], j["cfl"], j["masses"], j["positions"],
+                          j["steps"])
+        ids.append(capi.server_submit(srv, d))
+    results = {}
+    ticks = 0
+    while len(results) < len(jobs):
+        running, queued = capi.server_tick(srv)
+        ticks += 1
+        assert ticks < 1000
+        for k, i in enumerate(ids):
+            st = capi.server_job_status(srv, i)
+            if st.state == capi.JOB_DONE and k not in results:
+                g = capi.Grid(jobs[k]["coord"], jobs[k]["N"], jobs[k]["ampl"], jobs[k]["sinhw"], jobs[k]["cfl"])
+                out = g.state()
+                capi.server_fetch(srv, i, out)
+                assert capi.server_job_status(srv, i).state == capi.JOB_RELEASED
+                assert st.steps_done == jobs[k]["steps"]
+                results[k] = (g, out)
+    stats = capi.server_get_stats(srv)
+    assert stats.done == len(jobs) and stats.running == 0 and stats.queued == 0
+    assert stats.peak_held_bytes <= budget and stats.peak_running <= 3
+    assert stats.point_steps == sum(j["steps"] * j["N"][0] * j["N"][1] * j["N"][2] for j in jobs)
+    for k, j in enumerate(jobs):
+        g, out = results[k]
+        y = g.state()
+        capi.set_initial_data_brill_lindquist(g.h, j["masses"], j["positions"], y)
+        (s,) = _solo([g], [y], [j["steps"]])
+        assert torch.equal(out, s), k
+    with pytest.raises(capi.BhahError):
+        capi.server_fetch(srv, ids[0], results[0][1])
+    capi.server_destroy(srv)
+
+
+def test_server_rejects_job_larger_than_budget():
+    _case("server budget")
+    from paper_2505_00097_amd import capi
+    j = wl.headon_job(1.0, 1.0, 32)
+    srv = capi.server_create(1e6, max_jobs=2)
+    d = capi.job_desc(j["coord"], j["N"], j["ampl"], j["sinhw"], j["cfl"], j["masses"], j["positions"], 5)
+    with pytest.raises(capi.BhahError, match="budget"):
+        capi.server_submit(srv, d)
+    capi.server_destroy(srv)
