@@ -6,11 +6,14 @@ One step = one classical RK4 step of the whole hot path on the workload grid:
 with the fused stage update, and the ghost fill after every stage. The
 head-on workload also evaluates the Hamiltonian constraint every 50 steps.
 Prints one JSON line: whole-run throughput in interior grid-point RK4
-updates per second, the roofline of the right-hand-side evaluation (timed
-with HIP events on the stream it runs on), and the CPU oracle's rate on a
-bounded sample of the same workload.
+updates per second, the roofline of the right-hand-side kernel (timed with
+HIP events on the stream it runs on), the CPU oracle's rate on a bounded
+sample of the same workload, and, beside them, the ensemble forms:
+64 uneven head-on jobs advanced together against the same jobs one at a
+time, and Poisson-arriving jobs served with continuous batching.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,14 +27,46 @@ UNIT = "grid-point updates/s"
 PEAK_FP64_VECTOR = 78.6e12  # MI355X FP64 vector FLOP/s (no MFMA: stencil code)
 PEAK_HBM = 8.0e12           # bytes/s
 
-# FP64 operations per interior point for one right-hand-side evaluation: the
-# fadd/fsub/fmul/fdiv count of the optimised, fully unrolled fused kernel
-# (contracted to FMAs only later, so an FMA counts 2); per
-# coordinate family.
-F_ALG = {0: 5892, 1: 5414, 2: 5697}
+# FP64 operations per interior point for one right-hand-side evaluation, per
+# coordinate family: the fadd/fsub/fmul/fdiv count (an FMA counts 2) of the
+# optimised per-point code, as paper_2505_00097_amd/count_flops.py prints it
+# (a CPU test keeps the two in step).
+F_ALG = {0: 5792, 1: 5314, 2: 5597}
 # algorithmic HBM bytes per interior point per right-hand-side evaluation:
 # read 24 state gridfunctions, write 24 results (FP64)
 BYTES_ALG = 24 * 8 * 2
+# measured HBM traffic of the right-hand-side kernel (rocprofv3 counters,
+# calibrated by a copy of known size); valid only for the kernel source it
+# was taken from
+COUNTERS = os.path.join(ROOT, "profiles", "k_rhs_fused_headon_counters.txt")
+KERNEL_SOURCES = ["paper_2505_00097_amd/csrc/rhs_fused.hip", "paper_2505_00097_amd/csrc/rhs_common.h",
+                  "paper_2505_00097_amd/csrc/bhah_internal.h"]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch from the committed counter summary, or None if it
+    is absent, for another workload, or older than the kernel source."""
+    if not os.path.exists(COUNTERS):
+        return None
+    vals = {}
+    for line in open(COUNTERS):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha256") != kernel_source_hash() or vals.get("workload") != workload:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def percentile(v, p):
@@ -65,6 +100,188 @@ def cpu_baseline(w, budget_s):
                       f"{el:.1f} s"}
 
 
+def events(n):
+    import torch
+    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
+def time_rhs(capi, g, y, eta, reps, stream):
+    """Average duration of one right-hand-side launch (HIP events on the
+    launch stream)."""
+    import torch
+    rhs = g.state()
+    for _ in range(5):
+        capi.bssn_rhs(g.h, y, rhs, None, eta=eta, stream=stream)
+    e0, e1 = events(2)
+    e0.record(stream)
+    for _ in range(reps):
+        capi.bssn_rhs(g.h, y, rhs, None, eta=eta, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    del rhs
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def make_grids(capi, jobs):
+    cache, grids = {}, []
+    for j in jobs:
+        key = (j["coord"], tuple(j["N"]), tuple(j["ampl"]), tuple(j["sinhw"]), j["cfl"])
+        if key not in cache:
+            cache[key] = capi.Grid(j["coord"], j["N"], j["ampl"], j["sinhw"], j["cfl"])
+        grids.append(cache[key])
+    return grids
+
+
+def run_batched(capi, wl, stream, steps, seq_steps, graph_steps):
+    """64 uneven head-on jobs: one batch advancing all of them `steps` RK4
+    steps, against the same jobs advanced one at a time."""
+    import torch
+    jobs = wl.batched_jobs()
+    grids = make_grids(capi, jobs)
+    ys, wss = [], []
+    for j, g in zip(jobs, grids):
+        y = g.state()
+        capi.set_initial_data_brill_lindquist(g.h, j["masses"], j["positions"], y, stream=stream)
+        ys.append(y)
+        wss.append(g.workspace())
+    dts = [g.dt for g in grids]
+    pts = sum(g.info.n_interior for g in grids)
+    b = capi.batch_create([g.h for g in grids], eta=2.0)
+    capi.batch_set_graph_steps(b, graph_steps)
+    capi.batch_step(b, ys, wss, dts, nsteps=graph_steps, stream=stream)  # tunes tiles, captures graph
+    torch.cuda.synchronize()
+    info = capi.batch_get_info(b)
+    n_launch = (steps + graph_steps - 1) // graph_steps
+    ev = events(n_launch + 1)
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    done = 0
+    for k in range(n_launch):
+        n = min(graph_steps, steps - done)
+        capi.batch_step(b, ys, wss, dts, nsteps=n, stream=stream)
+        done += n
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    per_step = [ev[k].elapsed_time(ev[k + 1]) / min(graph_steps, steps - k * graph_steps)
+                for k in range(n_launch)]
+    finite = all(bool(torch.isfinite(y).all().item()) for y in ys)
+    capi.batch_destroy(b)
+    # the same jobs one after another, plain bhah_rk4_step
+    e0, e1 = events(2)
+    t1 = time.perf_counter()
+    e0.record(stream)
+    for g, y, ws in zip(grids, ys, wss):
+        for _ in range(seq_steps):
+            capi.rk4_step(g.h, y, ws, g.dt, eta=2.0, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    el_seq = time.perf_counter() - t1
+    batched = pts * steps / el
+    seq = pts * seq_steps / el_seq
+    return {"workload": "64 head-on BL jobs, SinhCylindrical N_rho~U{48..192} x 2 x 2N_rho, seed 250500097",
+            "interior_points": pts, "steps": steps, "value": batched, "unit": UNIT,
+            "ms_per_step_all_jobs": el * 1e3 / steps,
+            "p50_step_ms": percentile(per_step, 50), "p99_step_ms": percentile(per_step, 99),
+            "sequential_value": seq, "sequential_sample": f"each job {seq_steps} steps alone, {el_seq:.2f} s",
+            "speedup_vs_sequential": batched / seq, "graph_steps": graph_steps,
+            "tile_classes_tuned": info.n_classes_tuned, "tune_seconds": info.tune_seconds,
+            "tiles": info.n_tiles, "rhs_blocks": info.rhs_blocks, "finite": finite}
+
+
+def run_served(capi, wl, stream, n_jobs, steps_per_tick, seq_probe_steps):
+    """Poisson-arriving head-on jobs through the continuous-batching server,
+    and a first-come-first-served one-job-at-a-time schedule of the same
+    arrivals priced with measured solo step times."""
+    import torch
+    jobs = wl.served_jobs(n=n_jobs)
+    srv = capi.server_create(200e9, max_jobs=256, steps_per_tick=steps_per_tick, keep_results=False,
+                             eta=2.0, stream=stream)
+    descs = [capi.job_desc(j["coord"], j["N"], j["ampl"], j["sinhw"], j["cfl"], j["masses"], j["positions"],
+                           j["steps"]) for j in jobs]
+    t0 = time.perf_counter()
+    i = 0
+    last_print = t0
+    while True:
+        now = time.perf_counter() - t0
+        while i < len(jobs) and jobs[i]["arrival"] <= now:
+            capi.server_submit(srv, descs[i])
+            i += 1
+        running, queued = capi.server_tick(srv)
+        if running == 0 and queued == 0:
+            if i >= len(jobs):
+                break
+            time.sleep(max(0.0, jobs[i]["arrival"] - (time.perf_counter() - t0)))
+        if time.perf_counter() - last_print > 20.0:
+            last_print = time.perf_counter()
+            print(f"# served: {i}/{len(jobs)} arrived, {running} running, {queued} queued", file=sys.stderr,
+                  flush=True)
+    wall = time.perf_counter() - t0 - jobs[0]["arrival"]
+    st = capi.server_get_stats(srv)
+    capi.server_destroy(srv)
+    # measured solo step time per resolution
+    t_step = {}
+    for nr in sorted({j["N"][0] for j in jobs}):
+        j = wl.headon_job(2.0, 1.0, nr)
+        g = capi.Grid(j["coord"], j["N"], j["ampl"], j["sinhw"], j["cfl"])
+        y, ws = g.state(), g.workspace()
+        capi.set_initial_data_brill_lindquist(g.h, j["masses"], j["positions"], y, stream=stream)
+        for _ in range(3):
+            capi.rk4_step(g.h, y, ws, g.dt, stream=stream)
+        e0, e1 = events(2)
+        e0.record(stream)
+        for _ in range(seq_probe_steps):
+            capi.rk4_step(g.h, y, ws, g.dt, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_step[nr] = e0.elapsed_time(e1) / 1e3 / seq_probe_steps
+    free, lat, work = 0.0, [], 0.0
+    for j in jobs:
+        start = max(j["arrival"], free)
+        free = start + j["steps"] * t_step[j["N"][0]]
+        lat.append(free - j["arrival"])
+        work += j["steps"] * j["N"][0] * j["N"][1] * j["N"][2]
+    seq_wall = free - jobs[0]["arrival"]
+    return {"workload": f"{n_jobs} Poisson-arriving head-on jobs (4/s), N_rho in {{64,96,128,192}}, "
+                        "steps U{200..2000}, seed 250500098, 200 GB budget",
+            "value": st.point_steps / wall, "unit": UNIT, "wall_seconds": wall,
+            "busy_value": st.point_steps / st.busy_seconds if st.busy_seconds > 0 else None,
+            "busy_seconds": st.busy_seconds, "point_steps": st.point_steps, "jobs_done": st.done,
+            "p50_step_ms": st.step_ms_p50, "p99_step_ms": st.step_ms_p99,
+            "p50_job_s": st.job_s_p50, "p99_job_s": st.job_s_p99,
+            "peak_running": st.peak_running, "peak_held_GB": st.peak_held_bytes / 1e9,
+            "sequential_fcfs": {"value": work / seq_wall, "wall_seconds": seq_wall,
+                                "p50_job_s": percentile(lat, 50), "p99_job_s": percentile(lat, 99),
+                                "solo_step_ms": {str(k): v * 1e3 for k, v in t_step.items()},
+                                "how": "same arrivals, one job at a time in arrival order, priced with "
+                                       "measured solo RK4 step times"}}
+
+
+def run_rhs_study(capi, wl, stream, reps, steps):
+    """Right-hand-side kernel and RK4 step on the 3-D vacuum grid."""
+    import torch
+    w = wl.WORKLOADS["vacuum3d_sinhspherical_256x128x64"]
+    g = capi.Grid(w["coord"], w["N"], w["ampl"], w["sinhw"], w["cfl"])
+    y, ws = g.state(), g.workspace()
+    capi.set_initial_data_brill_lindquist(g.h, w["masses"], w["positions"], y, stream=stream)
+    for _ in range(2):
+        capi.rk4_step(g.h, y, ws, g.dt, eta=w["eta"], stream=stream)
+    e0, e1 = events(2)
+    e0.record(stream)
+    for _ in range(steps):
+        capi.rk4_step(g.h, y, ws, g.dt, eta=w["eta"], stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    step_s = e0.elapsed_time(e1) / 1e3 / steps
+    rhs_s = time_rhs(capi, g, y, w["eta"], reps, stream)
+    n = g.info.n_interior
+    return {"workload": "vacuum3d_sinhspherical_256x128x64", "interior_points": n,
+            "rhs_launch_s": rhs_s, "rhs_TFLOPs": F_ALG[w["coord"]] * n / rhs_s / 1e12,
+            "rhs_frac_fp64_peak": F_ALG[w["coord"]] * n / rhs_s / PEAK_FP64_VECTOR,
+            "rhs_alg_GBps": BYTES_ALG * n / rhs_s / 1e9,
+            "rk4_step_ms": step_s * 1e3, "value": n / step_s, "unit": UNIT}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +291,11 @@ def main():
     ap.add_argument("--rhs-reps", type=int, default=100)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=500)
+    ap.add_argument("--batched-seq-steps", type=int, default=50)
+    ap.add_argument("--graph-steps", type=int, default=10)
+    ap.add_argument("--served-jobs", type=int, default=256)
+    ap.add_argument("--study-steps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (no multi-GPU path); run with --gpus 1",
@@ -102,7 +324,7 @@ def main():
         torch.cuda.synchronize()
 
         # ---- timed region: exactly `steps` RK4 steps ----------------------
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        ev = events(args.steps + 1)
         t0 = time.perf_counter()
         ev[0].record(stream)
         for s in range(args.steps):
@@ -115,22 +337,29 @@ def main():
         step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)]
         elapsed = t1 - t0
         finite = bool(torch.isfinite(y).all().item())
+        print(f"# plain: {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
 
         # ---- the dominant kernel: one right-hand-side evaluation ----------
-        rhs = g.state()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        for _ in range(5):
-            capi.bssn_rhs(g.h, y, rhs, None, eta=w["eta"], stream=stream)
-        e0.record(stream)
-        for _ in range(args.rhs_reps):
-            capi.bssn_rhs(g.h, y, rhs, None, eta=w["eta"], stream=stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        rhs_s = e0.elapsed_time(e1) / 1e3 / args.rhs_reps
+        rhs_s = time_rhs(capi, g, y, w["eta"], args.rhs_reps, stream)
+        del y, ws, H
+
+        extras = {}
+        if args.batched_steps > 0:
+            extras["batched"] = run_batched(capi, wl, stream, args.batched_steps, args.batched_seq_steps,
+                                            args.graph_steps)
+            torch.cuda.empty_cache()
+            print(f"# batched: {extras['batched']['value']:.3e} pt-steps/s", file=sys.stderr, flush=True)
+        if args.study_steps > 0:
+            extras["rhs_study_3d"] = run_rhs_study(capi, wl, stream, args.rhs_reps // 5 + 1, args.study_steps)
+            torch.cuda.empty_cache()
+            print("# 3-D study done", file=sys.stderr, flush=True)
+        if args.served_jobs > 0:
+            extras["served"] = run_served(capi, wl, stream, args.served_jobs, args.graph_steps, 30)
+            print(f"# served: {extras['served']['value']:.3e} pt-steps/s", file=sys.stderr, flush=True)
 
     flops = F_ALG[w["coord"]] * n_int
     achieved = flops / rhs_s
+    traffic = measured_traffic(args.workload)
     out = {
         "metric": METRIC,
         "value": n_int * args.steps / elapsed,
@@ -152,9 +381,11 @@ def main():
         "finite": finite,
         "roofline": {"kernel": "k_rhs_fused", "bound": "alu",
                      "achieved": achieved / 1e12, "peak": PEAK_FP64_VECTOR / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_VECTOR, "traffic": None,
+                     "frac": achieved / PEAK_FP64_VECTOR, "traffic": traffic,
                      "flops_per_point": F_ALG[w["coord"]], "points": n_int, "launch_s": rhs_s,
-                     "hbm_alg_GBps": BYTES_ALG * n_int / rhs_s / 1e9},
+                     "hbm_alg_GBps": BYTES_ALG * n_int / rhs_s / 1e9,
+                     "hbm_measured_GBps": traffic / rhs_s / 1e9 if traffic else None},
+        "extras": extras,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)

@@ -233,6 +233,11 @@ int bhah_batch_step(bhah_batch* b, double* const* y, double* const* ws,
 /* RK4 steps captured per graph (default 10; larger step counts replay it). */
 int bhah_batch_set_graph_steps(bhah_batch* b, int steps);
 
+/* Launch shape of the right-hand-side kernel: blocks_per_cu > 0 runs that
+ * many persistent 64-lane blocks per compute unit striding over the work
+ * list (default 4: one wave per SIMD); 0 launches one block per tile.       */
+int bhah_batch_set_blocks_per_cu(bhah_batch* b, int blocks_per_cu);
+
 typedef struct {
   int n_active;          /* jobs in the current work lists                   */
   int n_tiles;           /* (job, tile) entries, 64 points each              */

@@ -96,6 +96,7 @@ _SIGS = {
                                          ctypes.POINTER(_vp)]),
     "bhah_batch_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp]),
     "bhah_batch_set_graph_steps": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "bhah_batch_set_blocks_per_cu": (ctypes.c_int, [_vp, ctypes.c_int]),
     "bhah_batch_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(BatchInfo)]),
     "bhah_batch_get_tile": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp]),
     "bhah_batch_destroy": (None, [_vp]),
@@ -240,6 +241,10 @@ def batch_step(b, ys, wss, dts, active=None, nsteps=1, stream=None):
 
 def batch_set_graph_steps(b, steps):
     _check(lib().bhah_batch_set_graph_steps(b, int(steps)), "bhah_batch_set_graph_steps")
+
+
+def batch_set_blocks_per_cu(b, blocks_per_cu):
+    _check(lib().bhah_batch_set_blocks_per_cu(b, int(blocks_per_cu)), "bhah_batch_set_blocks_per_cu")
 
 
 def batch_get_info(b):

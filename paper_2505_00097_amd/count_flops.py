@@ -1,0 +1,57 @@
+"""FP64 operations per interior point of one right-hand-side evaluation.
+
+Compiles the right-hand-side kernel source to optimised device LLVM IR with
+the library's own flags and counts, in each k_rhs_fused<C> kernel, the double
+precision fadd / fsub / fmul / fdiv instructions (an fma or fmuladd call
+counts 2) of the basic blocks that store nothing to global memory: that is
+the per-point arithmetic of Eqs. 7-15 after common-subexpression elimination,
+without the RK stage combination that follows it. The result is the FLOP
+figure the benchmark divides by the measured launch time.
+
+    python paper_2505_00097_amd/count_flops.py
+"""
+import os
+import re
+import subprocess
+import sys
+import tempfile
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+COORD_NAMES = {0: "SinhSpherical", 1: "SinhCylindrical", 2: "Spherical"}
+
+
+def device_ir(src):
+    import build
+    flags = [f for f in build.SOURCES[os.path.basename(src)]]
+    out = os.path.join(tempfile.mkdtemp(prefix="bhah_ir_"), "k.ll")
+    cmd = [build.HIPCC, "--offload-arch=gfx950", "--cuda-device-only", "-S", "-emit-llvm"] + flags + [src, "-o", out]
+    subprocess.run(cmd, check=True, stderr=subprocess.DEVNULL)
+    with open(out) as f:
+        return f.read()
+
+
+def count(ir, kernel_prefix="_ZN4bhah11k_rhs_fusedILi"):
+    res = {}
+    for m in re.finditer(r"define [^@]*@(" + re.escape(kernel_prefix) + r"(\d)E\S*)\(", ir):
+        name, c = m.group(1), int(m.group(2))
+        body = ir[m.start():ir.index("\n}\n", m.start())]
+        total = 0
+        for blk in re.split(r"\n(?=[\w.]+:)", body):
+            if re.search(r"store double [^,]+, ptr addrspace\(1\)", blk):
+                continue
+            total += len(re.findall(r"= (?:fadd|fsub|fmul|fdiv)(?: [a-z ]+)? double", blk))
+            total += 2 * len(re.findall(r"call [a-z ]*double @llvm\.(?:fma|fmuladd)\.f64", blk))
+        res[c] = total
+    return res
+
+
+def main():
+    ir = device_ir(os.path.join(HERE, "csrc", "rhs_fused.hip"))
+    for c, n in sorted(count(ir).items()):
+        print(f"{COORD_NAMES[c]}: {n} FP64 operations per point")
+
+
+if __name__ == "__main__":
+    main()

@@ -50,6 +50,12 @@ int bhah_batch_set_graph_steps(bhah_batch* b, int steps) {
   return BHAH_OK;
 }
 
+int bhah_batch_set_blocks_per_cu(bhah_batch* b, int blocks_per_cu) {
+  if (!b || blocks_per_cu < 0) return bhah::fail(BHAH_EINVAL, "bhah_batch_set_blocks_per_cu: bad argument");
+  b->engine.set_blocks_per_cu(blocks_per_cu);
+  return BHAH_OK;
+}
+
 int bhah_batch_get_info(const bhah_batch* b, bhah_batch_info* info) {
   if (!b || !info) return bhah::fail(BHAH_EINVAL, "bhah_batch_get_info: NULL argument");
   info->n_active = b->engine.n_jobs();

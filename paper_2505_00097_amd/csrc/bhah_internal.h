@@ -41,6 +41,18 @@ struct GridDev {
   const double* tab2;  // [n2][TAB_W]
 };
 
+// sign flip of gridfunction g under the parity bits par (bit d: the
+// direction-d basis vector reverses); tensor type per gridfunction: scalar,
+// vector (index i) or rank 2 (indices i, j)
+__host__ __device__ __forceinline__ int gf_flip(int g, int par) {
+  constexpr int I[NGF] = {0, 0, 0, 1, 1, 2, -1, 0, 1, 2, -1, 0, 0, 0, 1, 1, 2, 0, 1, 2, -1, 0, 1, 2};
+  constexpr int J[NGF] = {0, 1, 2, 1, 2, 2, -1, -1, -1, -1, -1, 0, 1, 2, 1, 2, 2, -1, -1, -1, -1, -1, -1, -1};
+  int f = 0;
+  if (I[g] >= 0) f ^= (par >> I[g]) & 1;
+  if (J[g] >= 0) f ^= (par >> J[g]) & 1;
+  return f;
+}
+
 // Ghost fill list: every ghost point p receives
 //   y_g[p] = sign_g(parity_p) * sum_t w_t * y_g[src_t]
 // over interior sources only (outer extrapolation composed in exact integer
@@ -74,6 +86,13 @@ struct TileCfg {
   int lx, ly, band;
 };
 
+// The stencil code reads the periodic direction (phi: i1 on SinhCylindrical
+// grids, i2 otherwise) with a wave-uniform wrapped index, so a tile must
+// have extent 1 along it.
+inline bool tile_fits_periodic(int coord, const TileCfg& c) {
+  return coord == BHAH_SINH_CYLINDRICAL ? c.ly == 0 : c.lx + c.ly == 6;
+}
+
 struct TileMap {
   int lx, ly;
   int tx, ty, tz;  // tiles along i0, i1, i2
@@ -83,11 +102,12 @@ struct TileMap {
 
 // One job of an ensemble as the batched kernels see it. Stage s in 0..3 is
 // RK4 stage s + 1 (the right-hand side of in[s] combined as in st[s], then
-// the ghost fill of gdst[s]); stage 4 stores the right-hand side of in[4] in
-// st[4].rhs and fills nothing (used to time tile shapes).
+// the ghost fill of gdst[s]: list gh[0] after stages 0-2, gh[1] after stage
+// 3); stage 4 stores the right-hand side of in[4] in st[4].rhs and fills
+// nothing (used to time tile shapes).
 struct BatchJob {
   GridDev G;
-  GhostDev gh;
+  GhostDev gh[2];  // ghosts filled after stages 0-2 (non-phi ghosts), after stage 3 (all)
   TileMap T;
   StageArgs st[5];
   const double* in[5];
@@ -96,12 +116,13 @@ struct BatchJob {
 
 // Work list header: the (job, tile) list of coordinate family c starts at
 // tile_off[c] and holds n_tiles[c] entries; the (job, chunk of 256 ghost
-// points) list holds n_chunks entries.
+// points) list of ghost list w (0: after stages 0-2, 1: after stage 3)
+// starts at chunk_off[w] and holds n_chunks[w] entries.
 struct BatchHdr {
   int n_tiles[3];
   int tile_off[3];
-  int n_chunks;
-  int pad;
+  int n_chunks[2];
+  int chunk_off[2];
 };
 
 }  // namespace bhah
@@ -117,12 +138,20 @@ struct bhah_grid {
   std::vector<int> kind, src_map, parity_map;  // per point (exported maps)
   std::vector<int> g_dst, g_start, g_par, g_src;
   std::vector<double> g_w;
+  // ghosts filled after the first three RK stages: those whose phi index is
+  // an interior one (phi ghost planes are never read by the stencils, which
+  // wrap phi onto the interior; they are filled after the last stage)
+  std::vector<int> r_dst, r_start, r_par, r_src;
+  std::vector<double> r_w;
+  bhah::GhostDev ghost_stage;  // device view of the r_* list
   int max_terms;
   bhah::TileCfg tile;  // tile shape and walk of the RHS kernel
   // device allocations
   double* d_tab[3];
   int* d_ints;      // dst | start | parity | src packed
   double* d_w;
+  int* d_rints;     // the same for the stage ghost list
+  double* d_rw;
   long long n_int_block;
 };
 

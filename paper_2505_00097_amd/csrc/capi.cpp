@@ -45,8 +45,33 @@ void rk4_stages(double dt, double* y, double* ws, long long n, StageArgs st[4], 
 static void free_device(bhah_grid* g) {
   for (int d = 0; d < 3; d++)
     if (g->d_tab[d]) (void)hipFree(g->d_tab[d]);
-  if (g->d_ints) (void)hipFree(g->d_ints);
-  if (g->d_w) (void)hipFree(g->d_w);
+  for (void* p : {(void*)g->d_ints, (void*)g->d_w, (void*)g->d_rints, (void*)g->d_rw})
+    if (p) (void)hipFree(p);
+}
+
+// Upload one ghost list (dst | start | parity | src packed as ints, weights
+// separately) and return its device view.
+static hipError_t upload_ghosts(const std::vector<int>& dst, const std::vector<int>& start,
+                                const std::vector<int>& par, const std::vector<int>& src,
+                                const std::vector<double>& w, int** d_ints, double** d_w, GhostDev* out) {
+  const size_t ng = dst.size(), nt = src.size();
+  std::vector<int> packed;
+  packed.reserve(3 * ng + 1 + nt);
+  packed.insert(packed.end(), dst.begin(), dst.end());
+  packed.insert(packed.end(), start.begin(), start.end());
+  packed.insert(packed.end(), par.begin(), par.end());
+  packed.insert(packed.end(), src.begin(), src.end());
+  hipError_t e = hipMalloc((void**)d_ints, packed.size() * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void**)d_w, (nt ? nt : 1) * sizeof(double));
+  if (e == hipSuccess) e = hipMemcpy(*d_ints, packed.data(), packed.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess && nt) e = hipMemcpy(*d_w, w.data(), nt * sizeof(double), hipMemcpyHostToDevice);
+  out->n_ghost = (int)ng;
+  out->dst = *d_ints;
+  out->start = *d_ints + ng;
+  out->parity = *d_ints + 2 * ng + 1;
+  out->src = *d_ints + 3 * ng + 1;
+  out->w = *d_w;
+  return e;
 }
 
 }  // namespace bhah
@@ -62,35 +87,23 @@ int bhah_grid_create(const bhah_grid_params* params, bhah_grid** out) {
   bhah_grid* g = new (std::nothrow) bhah_grid();
   if (!g) return fail(BHAH_ENOMEM, "bhah_grid_create: host allocation failed");
   for (int d = 0; d < 3; d++) g->d_tab[d] = nullptr;
-  g->d_ints = nullptr;
-  g->d_w = nullptr;
+  g->d_ints = g->d_rints = nullptr;
+  g->d_w = g->d_rw = nullptr;
   int rc = build_grid_host(params, g);
   if (rc) { delete g; return rc; }
   if ((rc = check_hip(hipGetDevice(&g->device), "hipGetDevice"))) { delete g; return rc; }
 
   const bhah_grid_info& I = g->info;
-  const size_t nghost = g->g_dst.size();
-  const size_t nterm = g->g_src.size();
-  const size_t nints = nghost + (nghost + 1) + nghost + nterm;
   hipError_t e = hipSuccess;
   for (int d = 0; d < 3 && e == hipSuccess; d++) {
     e = hipMalloc((void**)&g->d_tab[d], g->tab[d].size() * sizeof(double));
     if (e == hipSuccess)
       e = hipMemcpy(g->d_tab[d], g->tab[d].data(), g->tab[d].size() * sizeof(double), hipMemcpyHostToDevice);
   }
-  if (e == hipSuccess) e = hipMalloc((void**)&g->d_ints, nints * sizeof(int));
-  if (e == hipSuccess) e = hipMalloc((void**)&g->d_w, (nterm ? nterm : 1) * sizeof(double));
-  if (e == hipSuccess) {
-    std::vector<int> packed;
-    packed.reserve(nints);
-    packed.insert(packed.end(), g->g_dst.begin(), g->g_dst.end());
-    packed.insert(packed.end(), g->g_start.begin(), g->g_start.end());
-    packed.insert(packed.end(), g->g_par.begin(), g->g_par.end());
-    packed.insert(packed.end(), g->g_src.begin(), g->g_src.end());
-    e = hipMemcpy(g->d_ints, packed.data(), nints * sizeof(int), hipMemcpyHostToDevice);
-    if (e == hipSuccess && nterm)
-      e = hipMemcpy(g->d_w, g->g_w.data(), nterm * sizeof(double), hipMemcpyHostToDevice);
-  }
+  if (e == hipSuccess)
+    e = upload_ghosts(g->g_dst, g->g_start, g->g_par, g->g_src, g->g_w, &g->d_ints, &g->d_w, &g->ghost);
+  if (e == hipSuccess)
+    e = upload_ghosts(g->r_dst, g->r_start, g->r_par, g->r_src, g->r_w, &g->d_rints, &g->d_rw, &g->ghost_stage);
   if (e != hipSuccess) {
     const int code = e == hipErrorOutOfMemory ? BHAH_ENOMEM : BHAH_EDEVICE;
     fail(code, std::string("bhah_grid_create: ") + hipGetErrorString(e));
@@ -108,13 +121,6 @@ int bhah_grid_create(const bhah_grid_params* params, bhah_grid** out) {
   D.sgf = I.n_points;
   for (int d = 0; d < 3; d++) D.inv_dx[d] = 1.0 / I.dxx[d];
   D.tab0 = g->d_tab[0]; D.tab1 = g->d_tab[1]; D.tab2 = g->d_tab[2];
-  GhostDev& Gh = g->ghost;
-  Gh.n_ghost = (int)nghost;
-  Gh.dst = g->d_ints;
-  Gh.start = g->d_ints + nghost;
-  Gh.parity = g->d_ints + 2 * nghost + 1;
-  Gh.src = g->d_ints + 3 * nghost + 1;
-  Gh.w = g->d_w;
   *out = g;
   return BHAH_OK;
 }
@@ -181,7 +187,7 @@ int bhah_rk4_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt, do
   rk4_stages(dt, y, workspace, g->info.state_doubles, st, in, gdst);
   for (int k = 0; k < 4; k++) {
     launch_rhs_fused(g->dev, gp->eta, in[k], nullptr, st[k], s, g->tile);
-    launch_ghosts(g->ghost, gdst[k], g->dev.sgf, s);
+    launch_ghosts(k < 3 ? g->ghost_stage : g->ghost, gdst[k], g->dev.sgf, s);
   }
   return check_launch("bhah_rk4_step");
 }

@@ -37,6 +37,7 @@ std::vector<TileCfg> candidates(const SizeClass& c) {
   std::vector<TileCfg> out;
   for (int lx = 6; lx >= 3; lx--)
     for (int ly = 0; ly <= 3 && lx + ly <= 6; ly++) {
+      if (!tile_fits_periodic(std::get<0>(c), TileCfg{lx, ly, 1})) continue;
       if (ly > 0 && (1 << ly) > N1) continue;
       const int ez = 64 >> (lx + ly);
       if (ez > 1 && ez > N2) continue;
@@ -84,6 +85,15 @@ int Engine::set_jobs(const std::vector<EngineJob>& jobs) {
   return BHAH_OK;
 }
 
+// Blocks of the right-hand-side kernel: blocks_per_cu_ per compute unit
+// (the kernel runs one wave per SIMD, so 4 fill a CU) striding over the work
+// list, or with blocks_per_cu_ == 0 one block per tile of the current
+// capacity; always a multiple of the XCD count.
+int Engine::rhs_grid() const {
+  const long long want = blocks_per_cu_ > 0 ? (long long)blocks_per_cu_ * n_cus_ : (long long)cap_tiles_;
+  return (int)std::max<long long>(BHAH_NXCD, (want + BHAH_NXCD - 1) / BHAH_NXCD * BHAH_NXCD);
+}
+
 int Engine::ensure_device(hipStream_t s) {
   (void)s;
   if (upload_done_) return BHAH_OK;
@@ -97,10 +107,8 @@ int Engine::ensure_device(hipStream_t s) {
   arch_ = prop.gcnArchName;
   const size_t colon = arch_.find(':');
   if (colon != std::string::npos) arch_ = arch_.substr(0, colon);
-  // one 64-lane block per SIMD (the RHS kernel runs at one wave per SIMD),
-  // rounded to a multiple of the XCD count
-  rhs_blocks_ = std::max(BHAH_NXCD, (4 * cus + BHAH_NXCD - 1) / BHAH_NXCD * BHAH_NXCD);
-  ghost_blocks_ = 8 * std::max(cus, 1);
+  n_cus_ = std::max(cus, 1);
+  ghost_blocks_ = 8 * n_cus_;
   if ((rc = check_hip(hipEventCreateWithFlags(&upload_done_, hipEventDisableTiming), "hipEventCreate"))) return rc;
   if ((rc = check_hip(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking), "hipStreamCreate"))) return rc;
   load_cache();
@@ -114,10 +122,11 @@ void Engine::drop_graphs() {
 }
 
 // Fill the host blob: header, job table (all jobs) and work lists of the
-// jobs listed in `only` (all jobs if empty), with tile configuration cfg[j].
-// Grows the buffers if needed (dropping graphs, whose arguments point into
-// the old device buffer).
-void Engine::build_blob(const std::vector<TileCfg>& cfg, const std::vector<int>& only) {
+// jobs listed in `only` (all jobs if empty), with tile configuration cfg[j],
+// the tile list repeated `repeat` times (timing only: repeated tiles store
+// identical values). Grows the buffers if needed (dropping graphs, whose
+// arguments point into the old device buffer).
+void Engine::build_blob(const std::vector<TileCfg>& cfg, const std::vector<int>& only, int repeat) {
   std::vector<int> sel = only;
   if (sel.empty())
     for (int j = 0; j < (int)jobs_.size(); j++) sel.push_back(j);
@@ -126,8 +135,8 @@ void Engine::build_blob(const std::vector<TileCfg>& cfg, const std::vector<int>&
   for (int j = 0; j < (int)jobs_.size(); j++)
     maps[j] = make_tilemap(jobs_[j].g->dev, cfg[j].lx, cfg[j].ly, cfg[j].band);
   for (int j : sel) {
-    nt += maps[j].ntiles;
-    nc += (jobs_[j].g->ghost.n_ghost + 255) / 256;
+    nt += maps[j].ntiles * repeat;
+    nc += (jobs_[j].g->ghost_stage.n_ghost + 255) / 256 + (jobs_[j].g->ghost.n_ghost + 255) / 256;
   }
   // the previous upload must have left the pinned buffer before it is reused
   if (upload_done_) (void)hipEventSynchronize(upload_done_);
@@ -160,7 +169,8 @@ void Engine::build_blob(const std::vector<TileCfg>& cfg, const std::vector<int>&
     const EngineJob& e = jobs_[j];
     BatchJob& b = J[j];
     b.G = e.g->dev;
-    b.gh = e.g->ghost;
+    b.gh[0] = e.g->ghost_stage;
+    b.gh[1] = e.g->ghost;
     b.T = maps[j];
     const double* in[4];
     double* gd[4];
@@ -176,19 +186,24 @@ void Engine::build_blob(const std::vector<TileCfg>& cfg, const std::vector<int>&
   int pos = 0;
   for (int f = 0; f < 3; f++) {
     hdr->tile_off[f] = pos;
-    for (int j : sel) {
-      if (jobs_[j].g->params.coord != f) continue;
-      for (int t = 0; t < maps[j].ntiles; t++) tiles[pos++] = int2{j, t};
-    }
+    for (int r = 0; r < repeat; r++)
+      for (int j : sel) {
+        if (jobs_[j].g->params.coord != f) continue;
+        for (int t = 0; t < maps[j].ntiles; t++) tiles[pos++] = int2{j, t};
+      }
     hdr->n_tiles[f] = pos - hdr->tile_off[f];
     fam_present_[f] = hdr->n_tiles[f] > 0 || fam_present_[f];
   }
   int cpos = 0;
-  for (int j : sel) {
-    const int n = (jobs_[j].g->ghost.n_ghost + 255) / 256;
-    for (int c = 0; c < n; c++) chunks[cpos++] = int2{j, c};
+  for (int w = 0; w < 2; w++) {
+    hdr->chunk_off[w] = cpos;
+    for (int j : sel) {
+      const GhostDev& gh = w == 0 ? jobs_[j].g->ghost_stage : jobs_[j].g->ghost;
+      const int n = (gh.n_ghost + 255) / 256;
+      for (int c = 0; c < n; c++) chunks[cpos++] = int2{j, c};
+    }
+    hdr->n_chunks[w] = cpos - hdr->chunk_off[w];
   }
-  hdr->n_chunks = cpos;
   n_tiles_ = pos;
   n_chunks_ = cpos;
   blob_bytes_ = (size_t)(L.chunks + sizeof(int2) * (size_t)cpos);
@@ -204,12 +219,18 @@ int Engine::upload(hipStream_t s) {
 int Engine::time_class(const SizeClass& c, const TileCfg& cfg, hipStream_t s, double* us) {
   std::vector<int> only;
   std::vector<TileCfg> cfgs(jobs_.size(), TileCfg{6, 0, 1});
+  long long tiles = 0;
   for (int j = 0; j < (int)jobs_.size(); j++)
     if (class_of(jobs_[j].g) == c) {
       only.push_back(j);
       cfgs[j] = cfg;
+      tiles += make_tilemap(jobs_[j].g->dev, cfg.lx, cfg.ly, cfg.band).ntiles;
     }
-  build_blob(cfgs, only);
+  // time the class at full occupancy: repeat its tiles until every
+  // persistent block slot sees several
+  const long long target = 16LL * n_cus_;
+  const int repeat = (int)std::max<long long>(1, (target + tiles - 1) / std::max<long long>(tiles, 1));
+  build_blob(cfgs, only, repeat);
   int rc = upload(s);
   if (rc) return rc;
   const Layout L = layout(cap_jobs_, cap_tiles_, cap_chunks_);
@@ -221,16 +242,17 @@ int Engine::time_class(const SizeClass& c, const TileCfg& cfg, hipStream_t s, do
   if ((rc = check_hip(hipEventCreate(&e0), "hipEventCreate"))) return rc;
   if ((rc = check_hip(hipEventCreate(&e1), "hipEventCreate"))) { (void)hipEventDestroy(e0); return rc; }
   const int reps = 3;
-  launch_rhs_batch(coord, dj, dh, dt, 4, gp_.eta, rhs_blocks_, s);
+  const int blocks = rhs_grid();
+  launch_rhs_batch(coord, dj, dh, dt, 4, gp_.eta, blocks, s);
   (void)hipEventRecord(e0, s);
-  for (int r = 0; r < reps; r++) launch_rhs_batch(coord, dj, dh, dt, 4, gp_.eta, rhs_blocks_, s);
+  for (int r = 0; r < reps; r++) launch_rhs_batch(coord, dj, dh, dt, 4, gp_.eta, blocks, s);
   (void)hipEventRecord(e1, s);
   rc = check_hip(hipEventSynchronize(e1), "tile timing");
   float ms = 0.f;
   if (!rc) rc = check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  *us = 1e3 * ms / reps;
+  *us = 1e3 * ms / reps / repeat;
   return rc;
 }
 
@@ -268,6 +290,7 @@ int Engine::capture(int nsteps, hipStream_t s, hipGraphExec_t* out) {
   const BatchHdr* dh = (const BatchHdr*)d_blob_;
   const int2* dt = (const int2*)(d_blob_ + L.tiles);
   const int2* dc = (const int2*)(d_blob_ + L.chunks);
+  rhs_blocks_ = rhs_grid();
   int rc = check_hip(hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal), "graph capture");
   if (rc) return rc;
   for (int k = 0; k < nsteps; k++)
@@ -337,6 +360,7 @@ void Engine::load_cache() {
       continue;
     if (arch_ != arch) continue;
     if (lx < 0 || ly < 0 || lx + ly > 6 || band < 1) continue;
+    if (coord < 0 || coord > 2 || !tile_fits_periodic(coord, TileCfg{lx, ly, band})) continue;
     tuned_[SizeClass{coord, n0, n1, n2}] = TileCfg{lx, ly, band};
     tuned_us_[SizeClass{coord, n0, n1, n2}] = us;
   }

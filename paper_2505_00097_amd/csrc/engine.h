@@ -41,11 +41,19 @@ class Engine {
   // Advance every job by nsteps RK4 steps on stream s (asynchronous).
   int step(int nsteps, hipStream_t s);
   void set_graph_steps(int S) { graph_steps_ = S < 1 ? 1 : S; }
+  // persistent blocks of the right-hand-side kernel per compute unit;
+  // 0 launches one block per tile instead
+  void set_blocks_per_cu(int n) {
+    if (n != blocks_per_cu_) drop_graphs();
+    blocks_per_cu_ = n < 0 ? 0 : n;
+    rhs_blocks_ = 0;
+  }
 
   int n_jobs() const { return (int)jobs_.size(); }
   int n_tiles() const { return n_tiles_; }
   int n_chunks() const { return n_chunks_; }
   int graph_steps() const { return graph_steps_; }
+  int blocks_per_cu() const { return blocks_per_cu_; }
   int rhs_blocks() const { return rhs_blocks_; }
   int n_classes_tuned() const { return (int)tuned_.size(); }
   double tune_seconds() const { return tune_seconds_; }
@@ -55,7 +63,7 @@ class Engine {
   int ensure_device(hipStream_t s);
   int tune_missing(hipStream_t s);
   int time_class(const SizeClass& c, const TileCfg& cfg, hipStream_t s, double* us);
-  void build_blob(const std::vector<TileCfg>& cfg, const std::vector<int>& only);
+  void build_blob(const std::vector<TileCfg>& cfg, const std::vector<int>& only, int repeat = 1);
   int upload(hipStream_t s);
   int capture(int nsteps, hipStream_t s, hipGraphExec_t* out);
   void drop_graphs();
@@ -83,6 +91,9 @@ class Engine {
   bool fam_in_graphs_[3] = {false, false, false};
 
   int rhs_blocks_ = 0, ghost_blocks_ = 0;
+  int blocks_per_cu_ = 4;
+  int n_cus_ = 0;
+  int rhs_grid() const;
   int graph_steps_ = 10;
   std::map<int, hipGraphExec_t> graphs_;
   hipStream_t cap_stream_ = nullptr;

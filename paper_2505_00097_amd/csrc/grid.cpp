@@ -85,7 +85,8 @@ int build_grid_host(const bhah_grid_params* p, bhah_grid* g) {
     return fail(BHAH_EINVAL, "ampl[2] and sinhw[2] must be > 0");
   if (!(p->cfl > 0)) return fail(BHAH_EINVAL, "cfl must be > 0");
   const long long n0 = p->N[0] + 2 * NG, n1 = p->N[1] + 2 * NG, n2 = p->N[2] + 2 * NG;
-  if (n0 * n1 * n2 >= (1LL << 31) / 2) return fail(BHAH_EINVAL, "grid too large for 32-bit point indices");
+  if (n0 * n1 * n2 >= (1LL << 26))
+    return fail(BHAH_EINVAL, "grid too large: at most 2^26 points including ghosts (31-bit stencil offsets)");
 
   g->params = *p;
   bhah_grid_info& I = g->info;
@@ -241,6 +242,24 @@ int build_grid_host(const bhah_grid_params* p, bhah_grid* g) {
     g->max_terms = std::max(g->max_terms, (int)c->size());
   }
   g->g_start.push_back((int)g->g_src.size());
+
+  // ---- ghosts needed by the stencils during the RK stages ---------------
+  // (phi ghost planes are skipped: reads wrap phi onto the interior)
+  const int pd = coord == BHAH_SINH_CYLINDRICAL ? 1 : 2;
+  g->r_dst.clear(); g->r_start.clear(); g->r_par.clear(); g->r_src.clear(); g->r_w.clear();
+  for (size_t t = 0; t < g->g_dst.size(); t++) {
+    const int q = g->g_dst[t];
+    const int idx = pd == 1 ? (q / n[0]) % n[1] : q / (n[0] * n[1]);
+    if (idx < NG || idx >= NG + p->N[pd]) continue;
+    g->r_dst.push_back(q);
+    g->r_start.push_back((int)g->r_src.size());
+    g->r_par.push_back(g->g_par[t]);
+    for (int k = g->g_start[t]; k < g->g_start[t + 1]; k++) {
+      g->r_src.push_back(g->g_src[k]);
+      g->r_w.push_back(g->g_w[k]);
+    }
+  }
+  g->r_start.push_back((int)g->r_src.size());
   I.n_pure_outer = n_outer;
   I.n_inner = n_inner;
   return BHAH_OK;

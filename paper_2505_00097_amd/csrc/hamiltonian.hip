@@ -29,7 +29,7 @@ __global__ void __launch_bounds__(64) k_hamiltonian(GridDev G, const double* __r
                                                    double* __restrict__ H) {
   const PointIdx p = point_of(G);
   if (!p.valid) return;
-  Pt P{y, G.sgf, G.s1, G.s2, p.q};
+  const Pt P(y, G, C, p.i0, p.i1, p.i2);
   const Spacing sp = make_spacing(G);
   Ref R;
   load_ref<C>(G, p.i0, p.i1, p.i2, R);

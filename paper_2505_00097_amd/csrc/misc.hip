@@ -3,16 +3,6 @@
 
 namespace bhah {
 
-// tensor type of each gridfunction: scalar (-1,-1), vector (i,-1), rank 2 (i,j)
-__device__ __forceinline__ int gf_flip(int g, int par) {
-  constexpr int I[NGF] = {0, 0, 0, 1, 1, 2, -1, 0, 1, 2, -1, 0, 0, 0, 1, 1, 2, 0, 1, 2, -1, 0, 1, 2};
-  constexpr int J[NGF] = {0, 1, 2, 1, 2, 2, -1, -1, -1, -1, -1, 0, 1, 2, 1, 2, 2, -1, -1, -1, -1, -1, -1, -1};
-  int f = 0;
-  if (I[g] >= 0) f ^= (par >> I[g]) & 1;
-  if (J[g] >= 0) f ^= (par >> J[g]) & 1;
-  return f;
-}
-
 // Every ghost point takes sign * sum_t w_t y[src_t]; all sources are interior
 // points, so ghosts can be filled in any order and in parallel (Sec. 3
 // outer-then-inner boundary order is folded into the weights on the host).
@@ -55,12 +45,14 @@ void launch_ghosts(const GhostDev& gh, double* y, long long sgf, hipStream_t s) 
 __global__ void __launch_bounds__(256) k_ghosts_batch(const BatchJob* __restrict__ jobs,
                                                       const BatchHdr* __restrict__ hdr,
                                                       const int2* __restrict__ work, int stage) {
-  const int n = hdr->n_chunks;
+  const int which = stage == 3 ? 1 : 0;
+  const int n = hdr->n_chunks[which];
+  const int2* wl = work + hdr->chunk_off[which];
   for (int c = (int)blockIdx.x; c < n; c += (int)gridDim.x) {
-    const int2 wk = work[c];
+    const int2 wk = wl[c];
     const BatchJob* J = jobs + wk.x;
     const int t = wk.y * 256 + (int)threadIdx.x;
-    if (t < J->gh.n_ghost) ghost_point(J->gh, J->gdst[stage], J->G.sgf, t);
+    if (t < J->gh[which].n_ghost) ghost_point(J->gh[which], J->gdst[stage], J->G.sgf, t);
   }
 }
 

@@ -24,37 +24,65 @@ __host__ __device__ constexpr int sy(int i, int j) {
   return i <= j ? (i * (5 - i)) / 2 + j : (j * (5 - j)) / 2 + i;
 }
 
-// Stencil loads through buffer descriptors: one descriptor per gridfunction
-// (base = that gridfunction's first element, range = its size in bytes), a
-// per-lane byte offset `vc` of the stencil's low corner (q - 3 - 3 s1 - 3 s2),
-// and the stencil offset -- uniform across the wave -- as scalar offset plus
-// immediate. No per-load vector address arithmetic; an access outside the
-// gridfunction returns 0 instead of faulting.
+// Stencil loads through buffer descriptors: one descriptor per group of four
+// gridfunctions (base = the group's first element, range = its size in
+// bytes), the gridfunction's place in its group and the wave-uniform part of
+// the stencil offset as scalar offset, the per-lane part as vector offset.
+// Few descriptors stay live (scalar registers are scarce in the stencil
+// kernels); an access outside the group returns 0 instead of faulting.
+// Grids are limited to 2^26 points so every offset fits 31 bits.
 typedef unsigned int bhah_u2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t gf_rsrc(const double* y, long long sgf, int g) {
-  return __builtin_amdgcn_make_buffer_rsrc((void*)(y + g * sgf), (short)0, (int)(sgf * 8), 0x00020000);
-}
-
-__device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff) {
-  const bhah_u2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+__device__ __forceinline__ double gf_ld(const double* y, long long sgf, int g, unsigned voff, int soff) {
+  const __amdgpu_buffer_rsrc_t r =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(y + (g >> 2) * 4 * sgf), (short)0, (int)(4 * sgf * 8), 0x00020000);
+  const bhah_u2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff + (g & 3) * (int)(sgf * 8), 0);
   return __builtin_bit_cast(double, v);
 }
 
+// Stencil access around one point. Stencil values are read with raw buffer
+// loads: the per-lane part of the byte offset goes in the vector offset, the
+// part shared by the wave in the scalar offset. The periodic direction phi
+// (i1 on SinhCylindrical grids, i2 on spherical ones) is read with the index
+// wrapped onto the interior planes, so phi ghost points are never read: they
+// are exact copies of those planes (periodicity, no parity change), and the
+// values read are identical. The phi index must be the same for every lane of
+// the wave (tile extent 1 along phi).
 struct Pt {
   const double* __restrict__ y;
   long long sgf;
-  int s1, s2;
-  unsigned q;   // flat index of the point
-  unsigned vc;  // byte offset of the point's stencil corner, (q - 3 - 3 s1 - 3 s2) * 8
+  int pd;       // periodic direction (1 or 2)
+  int se;       // stride of the other transverse direction
+  unsigned vb;  // per-lane byte offset of (i0 - 3, i_e - 3) with the phi index removed
+  int sw[7];    // byte offsets of the wrapped phi planes at offsets -3..3 (wave-uniform)
 
-  __device__ __forceinline__ Pt(const double* y_, long long sgf_, int s1_, int s2_, unsigned q_)
-      : y(y_), sgf(sgf_), s1(s1_), s2(s2_), q(q_), vc((q_ - 3u - 3u * (unsigned)s1_ - 3u * (unsigned)s2_) * 8u) {}
-
-  __device__ __forceinline__ double at(int g, int a, int b, int c) const {
-    const int soff = ((b + 3) * s1 + (c + 3) * s2) * 8;
-    return buf_ld(gf_rsrc(y, sgf, g), vc + (unsigned)((a + 3) * 8), soff);
+  __device__ __forceinline__ Pt(const double* y_, const GridDev& G, int C, int i0, int i1, int i2)
+      : y(y_), sgf(G.sgf) {
+    pd = C == BHAH_SINH_CYLINDRICAL ? 1 : 2;
+    const int sd = pd == 1 ? G.s1 : G.s2;
+    const int nd = pd == 1 ? G.N1 : G.N2;
+    se = pd == 1 ? G.s2 : G.s1;
+    const int ie = pd == 1 ? i2 : i1;
+    const int id = __builtin_amdgcn_readfirstlane((pd == 1 ? i1 : i2) - NG);
+    vb = (unsigned)(i0 - 3 + se * (ie - 3)) * 8u;
+#pragma unroll
+    for (int o = -3; o <= 3; o++) {
+      int x = id + o;
+      x += x < 0 ? nd : 0;
+      x += x < 0 ? nd : 0;
+      x -= x >= nd ? nd : 0;
+      x -= x >= nd ? nd : 0;
+      sw[o + 3] = (NG + x) * sd * 8;
+    }
   }
+
+  // value at offsets (a, b, c) along (i0, i1, i2)
+  __device__ __forceinline__ double at(int g, int a, int b, int c) const {
+    const int od = pd == 1 ? b : c, oe = pd == 1 ? c : b;
+    return gf_ld(y, sgf, g, vb + (unsigned)((a + 3) * 8), sw[od + 3] + (oe + 3) * se * 8);
+  }
+  // byte offset of the point shifted by m along the periodic direction
+  __device__ __forceinline__ unsigned vper(int m) const { return vb + 24u + (unsigned)(3 * se * 8 + sw[m + 3]); }
   template <int K>
   __device__ __forceinline__ double ax(int g, int m) const {
     return K == 0 ? at(g, m, 0, 0) : (K == 1 ? at(g, 0, m, 0) : at(g, 0, 0, m));

@@ -30,13 +30,12 @@ struct Upwind2 {
 };
 
 __device__ __forceinline__ double advect2(const Pt& P, int g, const Upwind2& U) {
-  const __amdgpu_buffer_rsrc_t r = gf_rsrc(P.y, P.sgf, g);
-  const double f0 = buf_ld(r, U.v0, 0);
+  const double f0 = gf_ld(P.y, P.sgf, g, U.v0, 0);
   double s = 0.0;
 #pragma unroll
   for (int k = 0; k < 3; k++) {
-    const double fp = buf_ld(r, U.vp[k], 0), fm = buf_ld(r, U.vm[k], 0);
-    const double f2 = buf_ld(r, U.v2[k], 0), f3 = buf_ld(r, U.v3[k], 0);
+    const double fp = gf_ld(P.y, P.sgf, g, U.vp[k], 0), fm = gf_ld(P.y, P.sgf, g, U.vm[k], 0);
+    const double f2 = gf_ld(P.y, P.sgf, g, U.v2[k], 0), f3 = gf_ld(P.y, P.sgf, g, U.v3[k], 0);
     s += U.w[k] * (3.0 * (fp - fm) + 10.0 * (fp - f0) - 6.0 * (f2 - fp) + (f3 - fp));
   }
   return s;
@@ -78,14 +77,14 @@ __device__ __forceinline__ void advect_batch(const Pt& P, int g0, const Upwind2&
   double f0[N], fp[N][3], fm[N][3], f2[N][3], f3[N][3];
 #pragma unroll
   for (int t = 0; t < N; t++) {
-    const __amdgpu_buffer_rsrc_t r = gf_rsrc(P.y, P.sgf, g0 + t);
-    f0[t] = buf_ld(r, U.v0, 0);
+    const int g = g0 + t;
+    f0[t] = gf_ld(P.y, P.sgf, g, U.v0, 0);
 #pragma unroll
     for (int k = 0; k < 3; k++) {
-      fp[t][k] = buf_ld(r, U.vp[k], 0);
-      fm[t][k] = buf_ld(r, U.vm[k], 0);
-      f2[t][k] = buf_ld(r, U.v2[k], 0);
-      f3[t][k] = buf_ld(r, U.v3[k], 0);
+      fp[t][k] = gf_ld(P.y, P.sgf, g, U.vp[k], 0);
+      fm[t][k] = gf_ld(P.y, P.sgf, g, U.vm[k], 0);
+      f2[t][k] = gf_ld(P.y, P.sgf, g, U.v2[k], 0);
+      f3[t][k] = gf_ld(P.y, P.sgf, g, U.v3[k], 0);
     }
   }
   BHAH_PHASE_BARRIER();
@@ -114,7 +113,7 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
   // park[v * 64] is this thread's slot v (lane-consecutive, bank-conflict free)
   auto put = [&](int v, double x) { park[v * 64] = x; };
   auto get = [&](int v) { return park[v * 64]; };
-  Pt P{y, G.sgf, G.s1, G.s2, q};
+  const Pt P(y, G, C, i0, i1, i2);
   const Spacing sp = make_spacing(G);
   Ref R;
   load_ref<C>(G, i0, i1, i2, R);
@@ -429,8 +428,17 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
     const int str[3] = {1, G.s1, G.s2};
 #pragma unroll
     for (int k = 0; k < 3; k++) {
-      const int o = vet[k] > 0.0 ? str[k] : -str[k];
-      U.vp[k] = (q + o) * 8u; U.vm[k] = (q - o) * 8u; U.v2[k] = (q + 2 * o) * 8u; U.v3[k] = (q + 3 * o) * 8u;
+      const int s = vet[k] > 0.0 ? 1 : -1;
+      if (k == P.pd) {
+        const bool up = s > 0;
+        U.vp[k] = up ? P.vper(1) : P.vper(-1);
+        U.vm[k] = up ? P.vper(-1) : P.vper(1);
+        U.v2[k] = up ? P.vper(2) : P.vper(-2);
+        U.v3[k] = up ? P.vper(3) : P.vper(-3);
+      } else {
+        const int o = s * str[k];
+        U.vp[k] = (q + o) * 8u; U.vm[k] = (q - o) * 8u; U.v2[k] = (q + 2 * o) * 8u; U.v3[k] = (q + 3 * o) * 8u;
+      }
       U.w[k] = fabs(beta[k]) * sp.i12h[k];
     }
   }
@@ -743,7 +751,8 @@ TileMap make_tilemap(const GridDev& G, int lx, int ly, int band) {
 }
 
 void launch_rhs_fused(const GridDev& G, double eta, const double* y, double* aux, const StageArgs& st,
-                      hipStream_t s, const TileCfg& cfg) {
+                      hipStream_t s, const TileCfg& cfg_in) {
+  const TileCfg cfg = tile_fits_periodic(G.coord, cfg_in) ? cfg_in : TileCfg{6, 0, cfg_in.band};
   const TileMap T = make_tilemap(G, cfg.lx, cfg.ly, cfg.band);
   const int per = (T.ntiles + BHAH_NXCD - 1) / BHAH_NXCD;
   const dim3 g(per * BHAH_NXCD);

@@ -115,33 +115,68 @@ def test_batch_active_mask_and_swaps():
     capi.batch_destroy(b)
 
 
-@pytest.mark.parametrize("shape", [(6, 0, 4), (5, 1, 1), (4, 0, 1), (4, 1, 4), (3, 0, 4), (3, 3, 1), (4, 2, 4)])
-def test_every_tile_shape_covers_each_point_once(tmp_path, shape):
-    """Force a tile shape through the cache file; ragged extents in all three
-    directions must give the solo result exactly."""
-    _case("tile shape", shape)
-    import torch
-    from paper_2505_00097_amd import capi
-    jobs = [dict(coord=wl.SINH_SPHERICAL, N=(37, 11, 6), ampl=(10.0,) * 3, sinhw=(0.2,) * 3, cfl=0.5,
+# tile shapes (lx, ly, band) with extent 1 along phi (i2 on SinhSpherical,
+# i1 on SinhCylindrical grids), as the stencil reads require
+SPH_SHAPES = [(6, 0, 4), (5, 1, 1), (4, 2, 4), (3, 3, 1)]
+CYL_SHAPES = [(6, 0, 4), (5, 0, 1), (4, 0, 1), (3, 0, 4)]
+
+
+def _tile_jobs():
+    return [dict(coord=wl.SINH_SPHERICAL, N=(37, 11, 6), ampl=(10.0,) * 3, sinhw=(0.2,) * 3, cfl=0.5,
                  masses=[0.6, 0.4], positions=[(0.7, 0.1, 0.0), (-0.7, 0.0, 0.2)], eta=2.0),
             dict(wl.headon_job(2.0, 1.0, 29), N=(29, 2, 45))]
+
+
+def _write_cache(path, jobs, shapes):
+    import torch
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    lines = [json.dumps({"arch": arch, "coord": j["coord"], "N": list(j["N"]), "lx": s[0], "ly": s[1],
+                         "band": s[2], "us": 1.0}) for j, s in zip(jobs, shapes)]
+    path.write_text('{"bhah_tile_cache": 1, "entries": [\n' + ",\n".join(lines) + "\n]}\n")
+
+
+@pytest.mark.parametrize("k", range(4))
+def test_every_tile_shape_covers_each_point_once(tmp_path, k):
+    """Force tile shapes through the cache file; ragged extents in all three
+    directions must give the solo result exactly."""
+    shapes = (SPH_SHAPES[k], CYL_SHAPES[k])
+    _case("tile shapes", shapes)
+    import torch
+    from paper_2505_00097_amd import capi
+    jobs = _tile_jobs()
     grids, ys, wss = _setup(jobs)
     ys0 = [y.clone() for y in ys]
-    lx, ly, band = shape
     path = tmp_path / "tiles.json"
-    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
-    lines = [json.dumps({"arch": arch, "coord": j["coord"], "N": list(j["N"]), "lx": lx, "ly": ly,
-                         "band": band, "us": 1.0}) for j in jobs]
-    path.write_text('{"bhah_tile_cache": 1, "entries": [\n' + ",\n".join(lines) + "\n]}\n")
+    _write_cache(path, jobs, shapes)
     b = capi.batch_create([g.h for g in grids], eta=2.0, tune_cache_path=str(path))
     capi.batch_step(b, ys, wss, [g.dt for g in grids], nsteps=2)
     torch.cuda.synchronize()
     assert capi.batch_get_info(b).tune_seconds == 0.0
     for j in range(len(jobs)):
-        assert capi.batch_get_tile(b, j) == shape
+        assert capi.batch_get_tile(b, j) == shapes[j]
     solo = _solo(grids, ys0, [2, 2])
-    for k, (y, s) in enumerate(zip(ys, solo)):
-        assert torch.equal(y, s), (k, shape)
+    for j, (y, s) in enumerate(zip(ys, solo)):
+        assert torch.equal(y, s), (j, shapes)
+    capi.batch_destroy(b)
+
+
+def test_cached_shape_crossing_phi_is_ignored(tmp_path):
+    """A cached tile with extent > 1 along phi is rejected and the class is
+    tuned instead."""
+    _case("tile shape rejected")
+    import torch
+    from paper_2505_00097_amd import capi
+    jobs = _tile_jobs()
+    grids, ys, wss = _setup(jobs)
+    path = tmp_path / "tiles.json"
+    _write_cache(path, jobs, [(4, 0, 4), (5, 1, 1)])
+    b = capi.batch_create([g.h for g in grids], eta=2.0, tune_cache_path=str(path))
+    capi.batch_step(b, ys, wss, [g.dt for g in grids], nsteps=1)
+    torch.cuda.synchronize()
+    assert capi.batch_get_info(b).tune_seconds > 0.0
+    lx, ly, _ = capi.batch_get_tile(b, 0)
+    assert lx + ly == 6
+    assert capi.batch_get_tile(b, 1)[1] == 0
     capi.batch_destroy(b)
 
 
