@@ -103,8 +103,13 @@ __device__ __forceinline__ void advect_batch(const Pt& P, int g0, const Upwind2&
 // for the 24 results: they are written to global memory only at the end, so
 // no global store sits between two stencil loads (the compiler would have to
 // keep such loads and stores in order, exposing memory latency each time).
-constexpr int PARK = 55;
-enum { PK_PC = 0, PK_QS = 6, PK_Y = 9, PK_ZA = 15, PK_BV = 16, PK_BD = 19, PK_RT = 22, PK_Q = 28, PK_OUT = 31 };
+constexpr int PARK = 70;
+// PK_DH (first derivatives of h_ij, 18 slots) shares the result slots: it
+// is written in phase 1 and read in phase 2, before phase 3 writes results.
+// PK_D1 holds d_k vet^i (9), d_k W (3) and d_k alpha (3) from phase 1 to 3.
+enum { PK_PC = 0, PK_QS = 6, PK_Y = 9, PK_ZA = 15, PK_BV = 16, PK_BD = 19, PK_RT = 22, PK_Q = 28, PK_OUT = 31,
+       PK_DH = PK_OUT, PK_D1 = 55 };
+static_assert(PK_D1 + 15 == PARK, "park layout");
 
 template <int C>
 __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const double* __restrict__ y,
@@ -167,6 +172,13 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
           BHAH_PHASE_BARRIER();
 #pragma unroll
           for (int t = 0; t < 11; t++) dd[t] = d2_axis(v[t], sp.i12hh[k]);
+          // the same stencil values give the first derivatives along k
+#pragma unroll
+          for (int t = 0; t < 11; t++) {
+            const double d1 = d1_axis(v[t], sp.i12h[k]);
+            const int slot = t < 6 ? PK_DH + 3 * t : (t == 6 ? PK_D1 + 9 : (t == 7 ? PK_D1 + 12 : PK_D1 + 3 * (t - 8)));
+            put(slot + k, d1);
+          }
         } else {
 #pragma unroll
           for (int t0 = 0; t0 < 11; t0 += 4) {
@@ -211,10 +223,10 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
   double Gh[3][3][3];
   ref_christoffel(R, Gh);
   double dh[6][3], eps[6], Dh_eps[6][3];
-  {
-    constexpr int GH[6] = {G_HDD00, G_HDD00 + 1, G_HDD00 + 2, G_HDD00 + 3, G_HDD00 + 4, G_HDD00 + 5};
-    grad_batch<6>(P, GH, sp, dh);
-  }
+#pragma unroll
+  for (int a = 0; a < 6; a++)
+#pragma unroll
+    for (int k = 0; k < 3; k++) dh[a][k] = get(PK_DH + 3 * a + k);
 #pragma unroll
   for (int a = 0; a < 6; a++) eps[a] = h[a] * SS[a];
   // d_k eps_ij = S_i S_j d_k h_ij + h_ij d_k (S_i S_j)
@@ -408,13 +420,16 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
   double dvet[3][3], dbeta[3][3];  // d_j vet^i, d_j beta^i
   double dW[3], dalpha[3], dK[3], phi_d[3];
   {
-    constexpr int GV[6] = {G_VETU0, G_VETU0 + 1, G_VETU0 + 2, G_CF, G_ALPHA, G_TRK};
-    double d6[6][3];
-    grad_batch<6>(P, GV, sp, d6);
+    constexpr int GK[1] = {G_TRK};
+    double d1[1][3];
+    grad_batch<1>(P, GK, sp, d1);
 #pragma unroll
     for (int k = 0; k < 3; k++) {
-      dvet[0][k] = d6[0][k]; dvet[1][k] = d6[1][k]; dvet[2][k] = d6[2][k];
-      dW[k] = d6[3][k]; dalpha[k] = d6[4][k]; dK[k] = d6[5][k];
+#pragma unroll
+      for (int i = 0; i < 3; i++) dvet[i][k] = get(PK_D1 + 3 * i + k);
+      dW[k] = get(PK_D1 + 9 + k);
+      dalpha[k] = get(PK_D1 + 12 + k);
+      dK[k] = d1[0][k];
       phi_d[k] = -0.5 * dW[k] * iW;
     }
   }
