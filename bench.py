@@ -31,7 +31,7 @@ PEAK_HBM = 8.0e12           # bytes/s
 # coordinate family: the fadd/fsub/fmul/fdiv count (an FMA counts 2) of the
 # optimised per-point code, as paper_2505_00097_amd/count_flops.py prints it
 # (a CPU test keeps the two in step).
-F_ALG = {0: 5786, 1: 5308, 2: 5591}
+F_ALG = {0: 5792, 1: 5314, 2: 5597}
 # algorithmic HBM bytes per interior point per right-hand-side evaluation:
 # read 24 state gridfunctions, write 24 results (FP64)
 BYTES_ALG = 24 * 8 * 2

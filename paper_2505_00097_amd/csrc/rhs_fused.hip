@@ -29,18 +29,6 @@ struct Upwind2 {
   double w[3];                          // |beta^k| / (12 dxx^k)
 };
 
-__device__ __forceinline__ double advect2(const Pt& P, int g, const Upwind2& U) {
-  const double f0 = gf_ld(P.y, P.sgf, g, U.v0, 0);
-  double s = 0.0;
-#pragma unroll
-  for (int k = 0; k < 3; k++) {
-    const double fp = gf_ld(P.y, P.sgf, g, U.vp[k], 0), fm = gf_ld(P.y, P.sgf, g, U.vm[k], 0);
-    const double f2 = gf_ld(P.y, P.sgf, g, U.v2[k], 0), f3 = gf_ld(P.y, P.sgf, g, U.v3[k], 0);
-    s += U.w[k] * (3.0 * (fp - fm) + 10.0 * (fp - f0) - 6.0 * (f2 - fp) + (f3 - fp));
-  }
-  return s;
-}
-
 #define BHAH_PHASE_BARRIER() __builtin_amdgcn_sched_barrier(0)
 
 // compile-time dispatch of the gathers on a (compile-time after unrolling)
@@ -73,11 +61,11 @@ __device__ __forceinline__ void grad_batch(const Pt& P, const int (&gf)[N], cons
 
 // upwinded advection of N gridfunctions in one batch of loads
 template <int N>
-__device__ __forceinline__ void advect_batch(const Pt& P, int g0, const Upwind2& U, double (&out)[N]) {
+__device__ __forceinline__ void advect_batch(const Pt& P, const int (&gl)[N], const Upwind2& U, double (&out)[N]) {
   double f0[N], fp[N][3], fm[N][3], f2[N][3], f3[N][3];
 #pragma unroll
   for (int t = 0; t < N; t++) {
-    const int g = g0 + t;
+    const int g = gl[t];
     f0[t] = gf_ld(P.y, P.sgf, g, U.v0, 0);
 #pragma unroll
     for (int k = 0; k < 3; k++) {
@@ -103,13 +91,17 @@ __device__ __forceinline__ void advect_batch(const Pt& P, int g0, const Upwind2&
 // for the 24 results: they are written to global memory only at the end, so
 // no global store sits between two stencil loads (the compiler would have to
 // keep such loads and stores in order, exposing memory latency each time).
-constexpr int PARK = 70;
-// PK_DH (first derivatives of h_ij, 18 slots) shares the result slots: it
-// is written in phase 1 and read in phase 2, before phase 3 writes results.
-// PK_D1 holds d_k vet^i (9), d_k W (3) and d_k alpha (3) from phase 1 to 3.
+constexpr int PARK = 78;
+// PK_DH (first derivatives of h_ij, 18 slots) shares the result slots of
+// gridfunctions 0-17: it is written in phase 1 and read in phase 2, before
+// phase 3 writes results. PK_D1 holds d_k vet^i (9), d_k W (3) and d_k alpha
+// (3) from phase 1 to 3; PK_ADV the advection terms of h_ij (6), W and alpha
+// formed in phase 1 (those of vet^i go straight to their result slots,
+// which PK_DH does not cover). 78 slots x 64 lanes x 8 B = 39 KB per wave:
+// four waves still fit one CU's 160 KB.
 enum { PK_PC = 0, PK_QS = 6, PK_Y = 9, PK_ZA = 15, PK_BV = 16, PK_BD = 19, PK_RT = 22, PK_Q = 28, PK_OUT = 31,
-       PK_DH = PK_OUT, PK_D1 = 55 };
-static_assert(PK_D1 + 15 == PARK, "park layout");
+       PK_DH = PK_OUT, PK_D1 = 55, PK_ADV = 70 };
+static_assert(PK_ADV + 8 == PARK && PK_DH + 18 <= PK_OUT + G_VETU0, "park layout");
 
 template <int C>
 __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const double* __restrict__ y,
@@ -144,8 +136,32 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
     beta[i] = vet[i] * R.iS[i];
   }
 
+  // upwind stencil offsets (shift one point towards the side vet^k points to)
+  Upwind2 U;
+  U.v0 = q * 8u;
+  {
+    const int str[3] = {1, G.s1, G.s2};
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+      const int s = vet[k] > 0.0 ? 1 : -1;
+      if (k == P.pd) {
+        const bool up = s > 0;
+        U.vp[k] = up ? P.vper(1) : P.vper(-1);
+        U.vm[k] = up ? P.vper(-1) : P.vper(1);
+        U.v2[k] = up ? P.vper(2) : P.vper(-2);
+        U.v3[k] = up ? P.vper(3) : P.vper(-3);
+      } else {
+        const int o = s * str[k];
+        U.vp[k] = (q + o) * 8u; U.vm[k] = (q - o) * 8u; U.v2[k] = (q + 2 * o) * 8u; U.v3[k] = (q + 3 * o) * 8u;
+      }
+      U.w[k] = fabs(beta[k]) * sp.i12h[k];
+    }
+  }
+
   // ---- phase 1: second-derivative contractions ---------------------------
-  double Pc[6], Qs[3], Y[6], Za = 0.0, Bv[3], Bd[3];
+  double Pc[6], Qs[3], Y[6], Za = 0.0, Bv[3], Bd[3], adv[11];
+#pragma unroll
+  for (int t = 0; t < 11; t++) adv[t] = 0.0;
 #pragma unroll
   for (int a = 0; a < 6; a++) Pc[a] = 0.0;
 #pragma unroll
@@ -166,10 +182,21 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
       for (int l = k; l < 3; l++) {
         double dd[11];
         if (k == l) {
-          double v[11][5];
+          // f(-2..2) along k, and f(3 s) on the upwind side for the advection
+          double v[11][5], f3[11];
 #pragma unroll
-          for (int t = 0; t < 11; t++) gather_axis_k(P, G11[t], k, v[t]);
+          for (int t = 0; t < 11; t++) {
+            gather_axis_k(P, G11[t], k, v[t]);
+            f3[t] = gf_ld(P.y, P.sgf, G11[t], U.v3[k], 0);
+          }
           BHAH_PHASE_BARRIER();
+          const bool up = vet[k] > 0.0;
+#pragma unroll
+          for (int t = 0; t < 11; t++) {
+            const double fp = up ? v[t][3] : v[t][1], fm = up ? v[t][1] : v[t][3];
+            const double f2 = up ? v[t][4] : v[t][0], f0 = v[t][2];
+            adv[t] += U.w[k] * (3.0 * (fp - fm) + 10.0 * (fp - f0) - 6.0 * (f2 - fp) + (f3[t] - fp));
+          }
 #pragma unroll
           for (int t = 0; t < 11; t++) dd[t] = d2_axis(v[t], sp.i12hh[k]);
           // the same stencil values give the first derivatives along k
@@ -217,6 +244,10 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
 #pragma unroll
   for (int i = 0; i < 3; i++) { put(PK_QS + i, Qs[i]); put(PK_BV + i, Bv[i]); put(PK_BD + i, Bd[i]); }
   put(PK_ZA, Za);
+#pragma unroll
+  for (int t = 0; t < 8; t++) put(PK_ADV + t, adv[t]);
+#pragma unroll
+  for (int i = 0; i < 3; i++) put(PK_OUT + G_VETU0 + i, adv[8 + i]);
   BHAH_PHASE_BARRIER();
 
   // ---- phase 2a: first derivatives of h, eps, Dhat eps -------------------
@@ -420,43 +451,34 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
   double dvet[3][3], dbeta[3][3];  // d_j vet^i, d_j beta^i
   double dW[3], dalpha[3], dK[3], phi_d[3];
   {
-    constexpr int GK[1] = {G_TRK};
-    double d1[1][3];
-    grad_batch<1>(P, GK, sp, d1);
+    // K: first derivatives and advection from one gather
+    double v[3][5], f3[3];
 #pragma unroll
     for (int k = 0; k < 3; k++) {
+      gather_axis_k(P, G_TRK, k, v[k]);
+      f3[k] = gf_ld(P.y, P.sgf, G_TRK, U.v3[k], 0);
+    }
+    BHAH_PHASE_BARRIER();
+    double advK = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+      const bool up = vet[k] > 0.0;
+      const double fp = up ? v[k][3] : v[k][1], fm = up ? v[k][1] : v[k][3];
+      const double f2 = up ? v[k][4] : v[k][0], f0 = v[k][2];
+      advK += U.w[k] * (3.0 * (fp - fm) + 10.0 * (fp - f0) - 6.0 * (f2 - fp) + (f3[k] - fp));
+      dK[k] = d1_axis(v[k], sp.i12h[k]);
 #pragma unroll
       for (int i = 0; i < 3; i++) dvet[i][k] = get(PK_D1 + 3 * i + k);
       dW[k] = get(PK_D1 + 9 + k);
       dalpha[k] = get(PK_D1 + 12 + k);
-      dK[k] = d1[0][k];
       phi_d[k] = -0.5 * dW[k] * iW;
     }
+    put(PK_OUT + G_TRK, advK);
   }
 #pragma unroll
   for (int i = 0; i < 3; i++)
 #pragma unroll
     for (int j = 0; j < 3; j++) dbeta[i][j] = dvet[i][j] * R.iS[i] + vet[i] * diS[i][j];
-  Upwind2 U;
-  U.v0 = q * 8u;
-  {
-    const int str[3] = {1, G.s1, G.s2};
-#pragma unroll
-    for (int k = 0; k < 3; k++) {
-      const int s = vet[k] > 0.0 ? 1 : -1;
-      if (k == P.pd) {
-        const bool up = s > 0;
-        U.vp[k] = up ? P.vper(1) : P.vper(-1);
-        U.vm[k] = up ? P.vper(-1) : P.vper(1);
-        U.v2[k] = up ? P.vper(2) : P.vper(-2);
-        U.v3[k] = up ? P.vper(3) : P.vper(-3);
-      } else {
-        const int o = s * str[k];
-        U.vp[k] = (q + o) * 8u; U.vm[k] = (q - o) * 8u; U.v2[k] = (q + 2 * o) * 8u; U.v3[k] = (q + 3 * o) * 8u;
-      }
-      U.w[k] = fabs(beta[k]) * sp.i12h[k];
-    }
-  }
   double bS[3];  // beta^k d_k S_i / S_i
 #pragma unroll
   for (int i = 0; i < 3; i++) {
@@ -466,13 +488,23 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
     bS[i] = s * R.iS[i];
   }
   const double K = P.at(G_TRK, 0, 0, 0);
-  // upwinded advection of all 24 rescaled variables, 4 per batch of loads
+  // upwinded advection of the other rescaled variables, 4 per batch of
+  // loads; the terms formed in phase 1 move to their result slots
+  {
+    constexpr int GA[12] = {G_ADD00, G_ADD00 + 1, G_ADD00 + 2, G_ADD00 + 3, G_ADD00 + 4, G_ADD00 + 5,
+                            G_BETU0, G_BETU0 + 1, G_BETU0 + 2, G_LAMU0, G_LAMU0 + 1, G_LAMU0 + 2};
 #pragma unroll
-  for (int g0 = 0; g0 < NGF; g0 += 4) {
-    double a4[4];
-    advect_batch<4>(P, g0, U, a4);
+    for (int b = 0; b < 12; b += 4) {
+      const int gl[4] = {GA[b], GA[b + 1], GA[b + 2], GA[b + 3]};
+      double a4[4];
+      advect_batch<4>(P, gl, U, a4);
 #pragma unroll
-    for (int t = 0; t < 4; t++) put(PK_OUT + g0 + t, a4[t]);
+      for (int t = 0; t < 4; t++) put(PK_OUT + gl[t], a4[t]);
+    }
+#pragma unroll
+    for (int a = 0; a < 6; a++) put(PK_OUT + G_HDD00 + a, get(PK_ADV + a));
+    put(PK_OUT + G_CF, get(PK_ADV + 6));
+    put(PK_OUT + G_ALPHA, get(PK_ADV + 7));
   }
   BHAH_PHASE_BARRIER();
   double Gbc[3];  // Gammabar^k_km
