@@ -402,10 +402,32 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
         Rl[sy(i, j)] += s;
       }
     // Lambdabar terms: gammabar_k(i Dhat_j) Lambdabar^k
+    // lambda^i: first derivatives and advection from one gather (the
+    // result slots of lambda are free: phase 2 no longer reads PK_DH)
     double Lam[3], DLam[3][3], dlam[3][3];
     {
-      constexpr int GL[3] = {G_LAMU0, G_LAMU0 + 1, G_LAMU0 + 2};
-      grad_batch<3>(P, GL, sp, dlam);
+      double v[3][3][5], f3[3][3];
+#pragma unroll
+      for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+          gather_axis_k(P, G_LAMU0 + i, k, v[i][k]);
+          f3[i][k] = gf_ld(P.y, P.sgf, G_LAMU0 + i, U.v3[k], 0);
+        }
+      BHAH_PHASE_BARRIER();
+#pragma unroll
+      for (int i = 0; i < 3; i++) {
+        double a = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+          const bool up = vet[k] > 0.0;
+          const double fp = up ? v[i][k][3] : v[i][k][1], fm = up ? v[i][k][1] : v[i][k][3];
+          const double f2 = up ? v[i][k][4] : v[i][k][0], f0 = v[i][k][2];
+          a += U.w[k] * (3.0 * (fp - fm) + 10.0 * (fp - f0) - 6.0 * (f2 - fp) + (f3[i][k] - fp));
+          dlam[i][k] = d1_axis(v[i][k], sp.i12h[k]);
+        }
+        put(PK_OUT + G_LAMU0 + i, a);
+      }
     }
 #pragma unroll
     for (int k = 0; k < 3; k++) Lam[k] = P.at(G_LAMU0 + k, 0, 0, 0) * R.iS[k];
@@ -450,15 +472,40 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
     for (int k = 0; k < 3; k++) diS[i][k] = -R.dS[i][k] * (R.iS[i] * R.iS[i]);
   double dvet[3][3], dbeta[3][3];  // d_j vet^i, d_j beta^i
   double dW[3], dalpha[3], dK[3], phi_d[3];
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+#pragma unroll
+    for (int i = 0; i < 3; i++) dvet[i][k] = get(PK_D1 + 3 * i + k);
+    dW[k] = get(PK_D1 + 9 + k);
+    dalpha[k] = get(PK_D1 + 12 + k);
+    phi_d[k] = -0.5 * dW[k] * iW;
+  }
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = 0; j < 3; j++) dbeta[i][j] = dvet[i][j] * R.iS[i] + vet[i] * diS[i][j];
+  // upwinded advection of Abar_ij and B^i (five and four gridfunctions per
+  // batch of loads), K's first derivatives and advection from one gather in
+  // the second batch; the terms formed earlier move to their result slots
   {
-    // K: first derivatives and advection from one gather
+    constexpr int GA[5] = {G_ADD00, G_ADD00 + 1, G_ADD00 + 2, G_ADD00 + 3, G_ADD00 + 4};
+    double a5[5];
+    advect_batch<5>(P, GA, U, a5);
+#pragma unroll
+    for (int t = 0; t < 5; t++) put(PK_OUT + GA[t], a5[t]);
+  }
+  {
+    constexpr int GB[4] = {G_ADD00 + 5, G_BETU0, G_BETU0 + 1, G_BETU0 + 2};
+    double a4[4];
     double v[3][5], f3[3];
 #pragma unroll
     for (int k = 0; k < 3; k++) {
       gather_axis_k(P, G_TRK, k, v[k]);
       f3[k] = gf_ld(P.y, P.sgf, G_TRK, U.v3[k], 0);
     }
-    BHAH_PHASE_BARRIER();
+    advect_batch<4>(P, GB, U, a4);
+#pragma unroll
+    for (int t = 0; t < 4; t++) put(PK_OUT + GB[t], a4[t]);
     double advK = 0.0;
 #pragma unroll
     for (int k = 0; k < 3; k++) {
@@ -467,18 +514,14 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
       const double f2 = up ? v[k][4] : v[k][0], f0 = v[k][2];
       advK += U.w[k] * (3.0 * (fp - fm) + 10.0 * (fp - f0) - 6.0 * (f2 - fp) + (f3[k] - fp));
       dK[k] = d1_axis(v[k], sp.i12h[k]);
-#pragma unroll
-      for (int i = 0; i < 3; i++) dvet[i][k] = get(PK_D1 + 3 * i + k);
-      dW[k] = get(PK_D1 + 9 + k);
-      dalpha[k] = get(PK_D1 + 12 + k);
-      phi_d[k] = -0.5 * dW[k] * iW;
     }
     put(PK_OUT + G_TRK, advK);
   }
 #pragma unroll
-  for (int i = 0; i < 3; i++)
-#pragma unroll
-    for (int j = 0; j < 3; j++) dbeta[i][j] = dvet[i][j] * R.iS[i] + vet[i] * diS[i][j];
+  for (int a = 0; a < 6; a++) put(PK_OUT + G_HDD00 + a, get(PK_ADV + a));
+  put(PK_OUT + G_CF, get(PK_ADV + 6));
+  put(PK_OUT + G_ALPHA, get(PK_ADV + 7));
+  BHAH_PHASE_BARRIER();
   double bS[3];  // beta^k d_k S_i / S_i
 #pragma unroll
   for (int i = 0; i < 3; i++) {
@@ -488,25 +531,6 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
     bS[i] = s * R.iS[i];
   }
   const double K = P.at(G_TRK, 0, 0, 0);
-  // upwinded advection of the other rescaled variables, 4 per batch of
-  // loads; the terms formed in phase 1 move to their result slots
-  {
-    constexpr int GA[12] = {G_ADD00, G_ADD00 + 1, G_ADD00 + 2, G_ADD00 + 3, G_ADD00 + 4, G_ADD00 + 5,
-                            G_BETU0, G_BETU0 + 1, G_BETU0 + 2, G_LAMU0, G_LAMU0 + 1, G_LAMU0 + 2};
-#pragma unroll
-    for (int b = 0; b < 12; b += 4) {
-      const int gl[4] = {GA[b], GA[b + 1], GA[b + 2], GA[b + 3]};
-      double a4[4];
-      advect_batch<4>(P, gl, U, a4);
-#pragma unroll
-      for (int t = 0; t < 4; t++) put(PK_OUT + gl[t], a4[t]);
-    }
-#pragma unroll
-    for (int a = 0; a < 6; a++) put(PK_OUT + G_HDD00 + a, get(PK_ADV + a));
-    put(PK_OUT + G_CF, get(PK_ADV + 6));
-    put(PK_OUT + G_ALPHA, get(PK_ADV + 7));
-  }
-  BHAH_PHASE_BARRIER();
   double Gbc[3];  // Gammabar^k_km
 #pragma unroll
   for (int m = 0; m < 3; m++) {
