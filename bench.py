@@ -266,6 +266,7 @@ def run_rhs_study(capi, wl, stream, reps, steps):
     capi.set_initial_data_brill_lindquist(g.h, w["masses"], w["positions"], y, stream=stream)
     for _ in range(2):
         capi.rk4_step(g.h, y, ws, g.dt, eta=w["eta"], stream=stream)
+    capi.grid_tune(g.h, y, g.state(), eta=w["eta"], stream=stream)
     e0, e1 = events(2)
     e0.record(stream)
     for _ in range(steps):
@@ -279,7 +280,8 @@ def run_rhs_study(capi, wl, stream, reps, steps):
             "rhs_launch_s": rhs_s, "rhs_TFLOPs": F_ALG[w["coord"]] * n / rhs_s / 1e12,
             "rhs_frac_fp64_peak": F_ALG[w["coord"]] * n / rhs_s / PEAK_FP64_VECTOR,
             "rhs_alg_GBps": BYTES_ALG * n / rhs_s / 1e9,
-            "rk4_step_ms": step_s * 1e3, "value": n / step_s, "unit": UNIT}
+            "rk4_step_ms": step_s * 1e3, "value": n / step_s, "unit": UNIT,
+            "tile": list(capi.grid_get_tile(g.h))}
 
 
 def main():
@@ -317,6 +319,7 @@ def main():
         ws = g.workspace()
         H = g._empty(1)
         capi.set_initial_data_brill_lindquist(g.h, w["masses"], w["positions"], y, stream=stream)
+        capi.grid_tune(g.h, y, g.state(), eta=w["eta"], stream=stream)  # tile shape for this grid
         dt = g.dt
         h_every = w.get("h_every", 0)
         for _ in range(args.warmup):
@@ -376,7 +379,8 @@ def main():
         "config": {"workload": args.workload, "grid": {0: "SinhSpherical", 1: "SinhCylindrical",
                                                        2: "Spherical"}[w["coord"]] +
                    " {}x{}x{}".format(*w["N"]), "interior_points": n_int,
-                   "hamiltonian_every": h_every, "dt": dt, "parallelism": "single GPU"},
+                   "hamiltonian_every": h_every, "dt": dt, "parallelism": "single GPU",
+                   "tile": list(capi.grid_get_tile(g.h))},
         "latency": {"p50_step_ms": percentile(step_ms, 50), "p99_step_ms": percentile(step_ms, 99)},
         "finite": finite,
         "roofline": {"kernel": "k_rhs_fused", "bound": "alu",

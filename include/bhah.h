@@ -191,6 +191,20 @@ int bhah_bssn_rhs(const bhah_grid* g, const bhah_gauge_params* gp,
 int bhah_rk4_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt,
                   double* y, double* workspace, void* stream);
 
+/* Tile shape of this grid's right-hand-side kernel (bhah_bssn_rhs and
+ * bhah_rk4_step): 64 points, 2^lx along i0, 2^ly along i1, 64 >> (lx + ly)
+ * along i2, walked in bands of `band` tile rows of i1. The extent along phi
+ * (i1 on SinhCylindrical grids, i2 otherwise) must be 1. Default (6, 0, 4).
+ * The shape changes speed only: every point's arithmetic is the same.       */
+int bhah_grid_set_tile(bhah_grid* g, int lx, int ly, int band);
+int bhah_grid_get_tile(const bhah_grid* g, int* lx, int* ly, int* band);
+
+/* Time every allowed tile shape for this grid on state y (valid ghosts),
+ * writing right-hand sides into rhs (state layout, caller-owned scratch),
+ * and keep the fastest. Synchronises stream.                                */
+int bhah_grid_tune(bhah_grid* g, const bhah_gauge_params* gp, const double* y,
+                   double* rhs, void* stream);
+
 /* Hamiltonian constraint H of Eq. 16 at every interior point (centred
  * 4th-order differences), written into H (one gridfunction, state point
  * layout, interior points only). y must have valid ghosts.                  */

@@ -92,6 +92,9 @@ _SIGS = {
     "bhah_bssn_rhs": (ctypes.c_int, [_vp, ctypes.POINTER(GaugeParams), _vp, _vp, _vp, _vp]),
     "bhah_rk4_step": (ctypes.c_int, [_vp, ctypes.POINTER(GaugeParams), ctypes.c_double, _vp, _vp, _vp]),
     "bhah_hamiltonian_constraint": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "bhah_grid_set_tile": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "bhah_grid_get_tile": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "bhah_grid_tune": (ctypes.c_int, [_vp, ctypes.POINTER(GaugeParams), _vp, _vp, _vp]),
     "bhah_batch_create": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(GaugeParams), ctypes.c_char_p,
                                          ctypes.POINTER(_vp)]),
     "bhah_batch_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp]),
@@ -218,6 +221,22 @@ def rk4_step(h, y, workspace, dt, eta=2.0, stream=None):
 def hamiltonian_constraint(h, y, H, stream=None):
     _check(lib().bhah_hamiltonian_constraint(h, _ptr(y), _ptr(H), _stream(stream)),
            "bhah_hamiltonian_constraint")
+
+
+def grid_set_tile(h, lx, ly, band):
+    _check(lib().bhah_grid_set_tile(h, int(lx), int(ly), int(band)), "bhah_grid_set_tile")
+
+
+def grid_get_tile(h):
+    lx, ly, band = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib().bhah_grid_get_tile(h, ctypes.byref(lx), ctypes.byref(ly), ctypes.byref(band)),
+           "bhah_grid_get_tile")
+    return lx.value, ly.value, band.value
+
+
+def grid_tune(h, y, rhs, eta=2.0, stream=None):
+    gp = gauge(eta)
+    _check(lib().bhah_grid_tune(h, ctypes.byref(gp), _ptr(y), _ptr(rhs), _stream(stream)), "bhah_grid_tune")
 
 
 def batch_create(grid_handles, eta=2.0, tune_cache_path=None):

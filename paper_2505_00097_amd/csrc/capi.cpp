@@ -4,7 +4,7 @@
 #include <string>
 #include <vector>
 
-#include "bhah_internal.h"
+#include "engine.h"
 
 namespace bhah {
 
@@ -190,6 +190,57 @@ int bhah_rk4_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt, do
     launch_ghosts(k < 3 ? g->ghost_stage : g->ghost, gdst[k], g->dev.sgf, s);
   }
   return check_launch("bhah_rk4_step");
+}
+
+int bhah_grid_set_tile(bhah_grid* g, int lx, int ly, int band) {
+  if (!g) return fail(BHAH_EINVAL, "bhah_grid_set_tile: NULL grid");
+  const TileCfg c{lx, ly, band};
+  if (lx < 0 || ly < 0 || lx + ly > 6 || band < 1 || !tile_fits_periodic(g->params.coord, c))
+    return fail(BHAH_EINVAL, "bhah_grid_set_tile: need 0 <= lx, ly, lx + ly <= 6, band >= 1 and extent 1 along phi");
+  g->tile = c;
+  return BHAH_OK;
+}
+
+int bhah_grid_get_tile(const bhah_grid* g, int* lx, int* ly, int* band) {
+  if (!g) return fail(BHAH_EINVAL, "bhah_grid_get_tile: NULL grid");
+  if (lx) *lx = g->tile.lx;
+  if (ly) *ly = g->tile.ly;
+  if (band) *band = g->tile.band;
+  return BHAH_OK;
+}
+
+int bhah_grid_tune(bhah_grid* g, const bhah_gauge_params* gp, const double* y, double* rhs, void* stream) {
+  if (!g || !gp || !y || !rhs) return fail(BHAH_EINVAL, "bhah_grid_tune: NULL argument");
+  if (gp->shift_variant != 0) return fail(BHAH_EINVAL, "bhah_grid_tune: shift_variant must be 0");
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  int rc = check_hip(hipEventCreate(&e0), "hipEventCreate");
+  if (rc) return rc;
+  if ((rc = check_hip(hipEventCreate(&e1), "hipEventCreate"))) {
+    (void)hipEventDestroy(e0);
+    return rc;
+  }
+  const StageArgs st{rhs, nullptr, nullptr, 0.0, nullptr, nullptr, 0.0};
+  const SizeClass cls{g->params.coord, g->params.N[0], g->params.N[1], g->params.N[2]};
+  float best = 1e30f;
+  TileCfg bc = g->tile;
+  for (const TileCfg& c : tile_candidates(cls)) {
+    launch_rhs_fused(g->dev, gp->eta, y, nullptr, st, s, c);
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < 3; r++) launch_rhs_fused(g->dev, gp->eta, y, nullptr, st, s, c);
+    (void)hipEventRecord(e1, s);
+    if ((rc = check_hip(hipEventSynchronize(e1), "bhah_grid_tune"))) break;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best) {
+      best = ms;
+      bc = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (!rc) g->tile = bc;
+  return rc ? rc : check_launch("bhah_grid_tune");
 }
 
 int bhah_hamiltonian_constraint(const bhah_grid* g, const double* y, double* H, void* stream) {

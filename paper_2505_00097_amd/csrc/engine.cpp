@@ -31,8 +31,15 @@ Layout layout(int cap_jobs, int cap_tiles, int cap_chunks) {
   return L;
 }
 
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
 // candidate tile configurations for one size class
-std::vector<TileCfg> candidates(const SizeClass& c) {
+std::vector<TileCfg> tile_candidates(const SizeClass& c) {
   const int N0 = std::get<1>(c), N1 = std::get<2>(c), N2 = std::get<3>(c);
   std::vector<TileCfg> out;
   for (int lx = 6; lx >= 3; lx--)
@@ -48,13 +55,6 @@ std::vector<TileCfg> candidates(const SizeClass& c) {
     }
   return out;
 }
-
-double now_s() {
-  using namespace std::chrono;
-  return duration<double>(steady_clock::now().time_since_epoch()).count();
-}
-
-}  // namespace
 
 Engine::Engine(const bhah_gauge_params& gp, const char* cache_path) : gp_(gp) {
   if (cache_path) cache_path_ = cache_path;
@@ -265,7 +265,7 @@ int Engine::tune_missing(hipStream_t s) {
   for (const SizeClass& c : todo) {
     double best = 1e300;
     TileCfg bc{6, 0, 1};
-    for (const TileCfg& cfg : candidates(c)) {
+    for (const TileCfg& cfg : tile_candidates(c)) {
       double us = 0.0;
       const int rc = time_class(c, cfg, s, &us);
       if (rc) return rc;

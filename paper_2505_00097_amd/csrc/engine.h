@@ -29,6 +29,9 @@ struct EngineJob {
 
 using SizeClass = std::tuple<int, int, int, int>;  // coord, N0, N1, N2
 
+// tile shapes worth timing for a size class (extent 1 along phi)
+std::vector<TileCfg> tile_candidates(const SizeClass& c);
+
 class Engine {
  public:
   Engine(const bhah_gauge_params& gp, const char* cache_path);

@@ -333,3 +333,39 @@ def test_phi_ghost_planes_are_never_read(name):
     torch.cuda.synchronize()
     assert torch.equal(r1, r2)
     assert torch.equal(H1, H2)
+
+
+@pytest.mark.parametrize("name", ["sph_ragged", "cyl_ragged", "spherical"])
+def test_tile_shape_does_not_change_results(name):
+    """Every allowed tile shape of the solo kernel gives the same RK4 step,
+    bit for bit; bhah_grid_tune picks one of them; shapes that cross phi are
+    rejected."""
+    _print_case("solo tiles", name)
+    import torch
+    from paper_2505_00097_amd import capi
+    g, og = _pair(name)
+    y0 = to_gpu(og.apply_bcs(wl.smooth_random_state(og.n, seed=21)))
+    ws = g.workspace()
+    ref = None
+    shapes = [(6, 0, 4), (5, 0, 1), (4, 0, 4), (3, 0, 1)] if g.coord == wl.SINH_CYLINDRICAL else \
+        [(6, 0, 4), (5, 1, 1), (4, 2, 4), (3, 3, 1)]
+    for shp in shapes:
+        capi.grid_set_tile(g.h, *shp)
+        assert capi.grid_get_tile(g.h) == shp
+        y = y0.clone()
+        capi.rk4_step(g.h, y, ws, g.dt)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = y
+        else:
+            assert torch.equal(y, ref), shp
+    bad = (5, 1, 1) if g.coord == wl.SINH_CYLINDRICAL else (4, 0, 4)
+    with pytest.raises(capi.BhahError):
+        capi.grid_set_tile(g.h, *bad)
+    capi.grid_tune(g.h, y0, g.state())
+    lx, ly, band = capi.grid_get_tile(g.h)
+    assert 3 <= lx <= 6 and lx + ly <= 6 and band >= 1
+    y = y0.clone()
+    capi.rk4_step(g.h, y, ws, g.dt)
+    torch.cuda.synchronize()
+    assert torch.equal(y, ref)
