@@ -33,6 +33,19 @@ __host__ __device__ constexpr int sy(int i, int j) {
 // Grids are limited to 2^26 points so every offset fits 31 bits.
 typedef unsigned int bhah_u2 __attribute__((ext_vector_type(2)));
 
+typedef unsigned int bhah_u4 __attribute__((ext_vector_type(4)));
+
+// two consecutive doubles (along i0) in one 16-byte load: a wave's vector
+// memory pipeline moves twice the data per instruction
+__device__ __forceinline__ void gf_ld2(const double* y, long long sgf, int g, unsigned voff, int soff, double& lo,
+                                       double& hi) {
+  const __amdgpu_buffer_rsrc_t r =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(y + (g >> 2) * 4 * sgf), (short)0, (int)(4 * sgf * 8), 0x00020000);
+  const bhah_u4 v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff + (g & 3) * (int)(sgf * 8), 0);
+  lo = __builtin_bit_cast(double, (unsigned long long)v.x | ((unsigned long long)v.y << 32));
+  hi = __builtin_bit_cast(double, (unsigned long long)v.z | ((unsigned long long)v.w << 32));
+}
+
 __device__ __forceinline__ double gf_ld(const double* y, long long sgf, int g, unsigned voff, int soff) {
   const __amdgpu_buffer_rsrc_t r =
       __builtin_amdgcn_make_buffer_rsrc((void*)(y + (g >> 2) * 4 * sgf), (short)0, (int)(4 * sgf * 8), 0x00020000);
@@ -80,6 +93,11 @@ struct Pt {
   __device__ __forceinline__ double at(int g, int a, int b, int c) const {
     const int od = pd == 1 ? b : c, oe = pd == 1 ? c : b;
     return gf_ld(y, sgf, g, vb + (unsigned)((a + 3) * 8), sw[od + 3] + (oe + 3) * se * 8);
+  }
+  // values at offsets (a, b, c) and (a + 1, b, c)
+  __device__ __forceinline__ void at2(int g, int a, int b, int c, double& lo, double& hi) const {
+    const int od = pd == 1 ? b : c, oe = pd == 1 ? c : b;
+    gf_ld2(y, sgf, g, vb + (unsigned)((a + 3) * 8), sw[od + 3] + (oe + 3) * se * 8, lo, hi);
   }
   // byte offset of the point shifted by m along the periodic direction
   __device__ __forceinline__ unsigned vper(int m) const { return vb + 24u + (unsigned)(3 * se * 8 + sw[m + 3]); }
@@ -145,16 +163,31 @@ __device__ __forceinline__ double fdm(const Pt& P, int g, const Spacing& s) {
 //   cross: f(m, n) along (K, L) for m, n in {-2, -1, 1, 2}, m-major
 template <int K>
 __device__ __forceinline__ void gather_axis(const Pt& P, int g, double v[5]) {
+  if constexpr (K == 0) {  // i0 neighbours are adjacent in memory: pairs per load
+    P.at2(g, -2, 0, 0, v[0], v[1]);
+    v[2] = P.at(g, 0, 0, 0);
+    P.at2(g, 1, 0, 0, v[3], v[4]);
+  } else {
 #pragma unroll
-  for (int t = 0; t < 5; t++) v[t] = P.ax<K>(g, t - 2);
+    for (int t = 0; t < 5; t++) v[t] = P.ax<K>(g, t - 2);
+  }
 }
 template <int K, int L>
 __device__ __forceinline__ void gather_cross(const Pt& P, int g, double v[16]) {
   constexpr int off[4] = {-2, -1, 1, 2};
+  if constexpr (K == 0) {  // rows along i0 in pairs per load
 #pragma unroll
-  for (int a = 0; a < 4; a++)
+    for (int b = 0; b < 4; b++) {
+      const int o1 = L == 1 ? off[b] : 0, o2 = L == 2 ? off[b] : 0;
+      P.at2(g, -2, o1, o2, v[b], v[4 + b]);
+      P.at2(g, 1, o1, o2, v[8 + b], v[12 + b]);
+    }
+  } else {
 #pragma unroll
-    for (int b = 0; b < 4; b++) v[4 * a + b] = P.pl<K, L>(g, off[a], off[b]);
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int b = 0; b < 4; b++) v[4 * a + b] = P.pl<K, L>(g, off[a], off[b]);
+  }
 }
 __device__ __forceinline__ double d1_axis(const double v[5], double s) {
   return (8.0 * (v[3] - v[1]) - (v[4] - v[0])) * s;
