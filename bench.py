@@ -284,6 +284,33 @@ def run_rhs_study(capi, wl, stream, reps, steps):
             "tile": list(capi.grid_get_tile(g.h))}
 
 
+def run_paper_grid(capi, wl, stream, name, N, r_max, steps, graph_steps, paper):
+    """One of the paper's own benchmark grids (plain Spherical, two
+    punctures on z), advanced `steps` RK4 steps as a one-job batch (captured
+    graphs); the paper's wall time on its hardware is quoted beside it."""
+    import torch
+    g = capi.Grid(wl.SPHERICAL, N, (r_max,) * 3, (0.2,) * 3, 0.5)
+    y, ws = g.state(), g.workspace()
+    capi.set_initial_data_brill_lindquist(g.h, [0.5, 0.5], [(0.0, 0.0, 0.5), (0.0, 0.0, -0.5)], y, stream=stream)
+    b = capi.batch_create([g.h], eta=2.0)
+    capi.batch_set_graph_steps(b, graph_steps)
+    capi.batch_step(b, [y], [ws], [g.dt], nsteps=min(steps, graph_steps), stream=stream)  # tune + capture
+    torch.cuda.synchronize()
+    capi.set_initial_data_brill_lindquist(g.h, [0.5, 0.5], [(0.0, 0.0, 0.5), (0.0, 0.0, -0.5)], y, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    capi.batch_step(b, [y], [ws], [g.dt], nsteps=steps, stream=stream)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    finite = bool(torch.isfinite(y).all().item())
+    capi.batch_destroy(b)
+    n = g.info.n_interior
+    del y, ws
+    return {"workload": name, "grid": "Spherical {}x{}x{}, r_max {}".format(*N, r_max), "interior_points": n,
+            "steps": steps, "wall_seconds": el, "value": n * steps / el, "unit": UNIT, "finite": finite,
+            "paper": paper}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -298,6 +325,7 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=10)
     ap.add_argument("--served-jobs", type=int, default=256)
     ap.add_argument("--study-steps", type=int, default=20)
+    ap.add_argument("--no-paper-grids", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (no multi-GPU path); run with --gpus 1",
@@ -356,6 +384,16 @@ def main():
             extras["rhs_study_3d"] = run_rhs_study(capi, wl, stream, args.rhs_reps // 5 + 1, args.study_steps)
             torch.cuda.empty_cache()
             print("# 3-D study done", file=sys.stderr, flush=True)
+        if not args.no_paper_grids:
+            extras["paper_desktop_grid"] = run_paper_grid(
+                capi, wl, stream, "the paper's single-node benchmark grid", (72, 12, 24), 7.5, 8428, 50,
+                "37.2 s with NRPy/OpenMP on a 16-core Ryzen 9 3950X (62.0 s superB SMP)")
+            torch.cuda.empty_cache()
+            extras["paper_strong_scaling_grid"] = run_paper_grid(
+                capi, wl, stream, "the paper's strong-scaling grid", (1008, 168, 336), 7.5, 124, 4,
+                "about 33 s with superB on 64 nodes (7168 cores); about 1462 s with NRPy/OpenMP on one node")
+            torch.cuda.empty_cache()
+            print("# paper grids done", file=sys.stderr, flush=True)
         if args.served_jobs > 0:
             extras["served"] = run_served(capi, wl, stream, args.served_jobs, args.graph_steps, 30)
             print(f"# served: {extras['served']['value']:.3e} pt-steps/s", file=sys.stderr, flush=True)

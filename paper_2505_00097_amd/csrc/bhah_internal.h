@@ -125,6 +125,40 @@ struct BatchHdr {
   int chunk_off[2];
 };
 
+// Ghost classification of a point from the closed-form index reflections
+// that the Cartesian round trip reduces to (Sec. 3): 0 interior, 1 pure
+// outer (the round trip returns the point itself), 2 inner, with the source
+// point and parity bits (bit d: the direction-d basis vector reverses).
+struct Classifier {
+  int coord = 0;
+  int N[3] = {0, 0, 0};
+  int n[3] = {0, 0, 0};
+  int flat(int a, int b, int c) const { return (int)(a + n[0] * (b + n[1] * (long long)c)); }
+  static int wrap(int j, int N) {
+    int m = (j - NG) % N;
+    if (m < 0) m += N;
+    return NG + m;
+  }
+  int operator()(int i0, int i1, int i2, int& src, int& par) const {
+    src = flat(i0, i1, i2);
+    par = 0;
+    if (i0 >= NG && i0 < NG + N[0] && i1 >= NG && i1 < NG + N[1] && i2 >= NG && i2 < NG + N[2]) return 0;
+    int j0 = i0, j1 = i1, j2 = i2;
+    if (coord == BHAH_SINH_CYLINDRICAL) {
+      if (j0 < NG) { j0 = 2 * NG - 1 - j0; j1 += N[1] / 2; par ^= 0b011; }
+      j1 = wrap(j1, N[1]);
+    } else {
+      if (j0 < NG) { j0 = 2 * NG - 1 - j0; j1 = N[1] + 2 * NG - 1 - j1; j2 += N[2] / 2; par ^= 0b101; }
+      if (j1 < NG) { j1 = 2 * NG - 1 - j1; j2 += N[2] / 2; par ^= 0b110; }
+      else if (j1 >= N[1] + NG) { j1 = 2 * (N[1] + NG) - 1 - j1; j2 += N[2] / 2; par ^= 0b110; }
+      j2 = wrap(j2, N[2]);
+    }
+    if (j0 == i0 && j1 == i1 && j2 == i2) { par = 0; return 1; }
+    src = flat(j0, j1, j2);
+    return 2;
+  }
+};
+
 }  // namespace bhah
 
 struct bhah_grid {
@@ -135,7 +169,7 @@ struct bhah_grid {
   bhah::GhostDev ghost;    // device pointers inside
   // host copies
   std::vector<double> tab[3];
-  std::vector<int> kind, src_map, parity_map;  // per point (exported maps)
+  bhah::Classifier classify;  // ghost class of any point (closed form)
   std::vector<int> g_dst, g_start, g_par, g_src;
   std::vector<double> g_w;
   // ghosts filled after the first three RK stages: those whose phi index is

@@ -139,10 +139,17 @@ int bhah_grid_get_info(const bhah_grid* g, bhah_grid_info* info) {
 
 int bhah_grid_get_bc_maps(const bhah_grid* g, int* host_kind, int* host_src, int* host_parity) {
   if (!g) return fail(BHAH_EINVAL, "bhah_grid_get_bc_maps: NULL grid");
-  const size_t n = g->kind.size();
-  if (host_kind) std::memcpy(host_kind, g->kind.data(), n * sizeof(int));
-  if (host_src) std::memcpy(host_src, g->src_map.data(), n * sizeof(int));
-  if (host_parity) std::memcpy(host_parity, g->parity_map.data(), n * sizeof(int));
+  const int* n = g->info.n_total;
+  long long q = 0;
+  for (int i2 = 0; i2 < n[2]; i2++)
+    for (int i1 = 0; i1 < n[1]; i1++)
+      for (int i0 = 0; i0 < n[0]; i0++, q++) {
+        int src, par;
+        const int k = g->classify(i0, i1, i2, src, par);
+        if (host_kind) host_kind[q] = k;
+        if (host_src) host_src[q] = src;
+        if (host_parity) host_parity[q] = par;
+      }
   return BHAH_OK;
 }
 

@@ -25,6 +25,7 @@
 #include <cmath>
 #include <map>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "bhah_internal.h"
@@ -144,44 +145,32 @@ int build_grid_host(const bhah_grid_params* p, bhah_grid* g) {
 
   // ---- ghost classification by index reflection -------------------------
   const long long np = I.n_points;
-  g->kind.assign(np, 0);
-  g->src_map.resize(np);
-  g->parity_map.assign(np, 0);
   auto flat = [&](int a, int b, int c) { return (int)(a + n0 * (b + n1 * (long long)c)); };
-  auto interior = [&](int a, int b, int c) {
-    return a >= NG && a < NG + p->N[0] && b >= NG && b < NG + p->N[1] && c >= NG && c < NG + p->N[2];
+  auto coords = [&](int q, int& a, int& b, int& c) {
+    a = q % n[0];
+    b = (q / n[0]) % n[1];
+    c = q / (n[0] * n[1]);
   };
-  auto wrap = [&](int j, int N) { int m = (j - NG) % N; if (m < 0) m += N; return NG + m; };
-  for (int i2 = 0; i2 < n[2]; i2++)
-    for (int i1 = 0; i1 < n[1]; i1++)
-      for (int i0 = 0; i0 < n[0]; i0++) {
-        const int q = flat(i0, i1, i2);
-        g->src_map[q] = q;
-        if (interior(i0, i1, i2)) { g->kind[q] = 0; continue; }
-        int j0 = i0, j1 = i1, j2 = i2, par = 0;
-        if (coord == BHAH_SINH_CYLINDRICAL) {
-          if (j0 < NG) { j0 = 2 * NG - 1 - j0; j1 += p->N[1] / 2; par ^= 0b011; }
-          j1 = wrap(j1, p->N[1]);
-        } else {
-          if (j0 < NG) {
-            j0 = 2 * NG - 1 - j0; j1 = p->N[1] + 2 * NG - 1 - j1; j2 += p->N[2] / 2; par ^= 0b101;
-          }
-          if (j1 < NG) { j1 = 2 * NG - 1 - j1; j2 += p->N[2] / 2; par ^= 0b110; }
-          else if (j1 >= p->N[1] + NG) { j1 = 2 * (p->N[1] + NG) - 1 - j1; j2 += p->N[2] / 2; par ^= 0b110; }
-          j2 = wrap(j2, p->N[2]);
-        }
-        if (j0 == i0 && j1 == i1 && j2 == i2) { g->kind[q] = 1; continue; }
-        g->kind[q] = 2;
-        g->src_map[q] = flat(j0, j1, j2);
-        g->parity_map[q] = par;
-      }
-  // inner ghosts must map to interior or outer points (one hop)
-  for (long long q = 0; q < np; q++)
-    if (g->kind[q] == 2 && g->kind[g->src_map[q]] == 2)
-      return fail(BHAH_EINVAL, "inner ghost maps to another inner ghost");
+  Classifier& classify = g->classify;
+  classify.coord = coord;
+  for (int d = 0; d < 3; d++) {
+    classify.N[d] = p->N[d];
+    classify.n[d] = n[d];
+  }
+  auto kind_of = [&](int q) {
+    int a, b, c, s2, p2;
+    coords(q, a, b, c);
+    return classify(a, b, c, s2, p2);
+  };
 
   // ---- outer extrapolation composed into interior weights ---------------
-  std::vector<Comb> comb(np);
+  // combinations of the outer points only (a few layers of a large grid)
+  std::unordered_map<int, Comb> comb;
+  const Comb none;
+  auto comb_of = [&](int q) -> const Comb& {
+    const auto it = comb.find(q);
+    return it == comb.end() ? none : it->second;
+  };
   int lo[3] = {NG, NG, NG}, hi[3] = {NG + p->N[0], NG + p->N[1], NG + p->N[2]};
   const long long st[3] = {1, n0, n0 * n1};
   for (int layer = 0; layer < NG; layer++) {
@@ -194,59 +183,80 @@ int build_grid_host(const bhah_grid_params* p, bhah_grid* g) {
         for (int i2 = a[2]; i2 < b[2]; i2++)
           for (int i1 = a[1]; i1 < b[1]; i1++)
             for (int i0 = a[0]; i0 < b[0]; i0++) {
+              int src, par;
+              if (classify(i0, i1, i2, src, par) != 1) continue;
               const int q = flat(i0, i1, i2);
-              if (g->kind[q] != 1) continue;
               Comb c;
               const long long w3[3] = {3, -3, 1};
               for (int t = 1; t <= 3; t++) {
                 const int s = (int)(q + t * step);
-                if (g->kind[s] == 0) {
+                const int ks = kind_of(s);
+                if (ks == 0) {
                   c[s] += w3[t - 1];
-                } else if (g->kind[s] == 1 && !comb[s].empty()) {
-                  for (auto& kv : comb[s]) c[kv.first] += w3[t - 1] * kv.second;
+                } else if (ks == 1 && !comb_of(s).empty()) {
+                  for (auto& kv : comb_of(s)) c[kv.first] += w3[t - 1] * kv.second;
                 } else {
                   return fail(BHAH_EINVAL, "extrapolation reads a point not yet filled");
                 }
               }
               for (auto it = c.begin(); it != c.end();) it = it->second == 0 ? c.erase(it) : std::next(it);
-              comb[q] = c;
+              comb[q] = std::move(c);
             }
       }
       lo[d]--;
       hi[d]++;
     }
   }
-  // every outer point must have been reached
-  for (long long q = 0; q < np; q++)
-    if (g->kind[q] == 1 && comb[q].empty()) return fail(BHAH_EINVAL, "outer ghost not reached by the shell order");
 
   // ---- ghost list --------------------------------------------------------
+  const long long n_ghosts = np - I.n_interior;
   g->g_dst.clear(); g->g_start.clear(); g->g_par.clear(); g->g_src.clear(); g->g_w.clear();
+  g->g_dst.reserve(n_ghosts); g->g_start.reserve(n_ghosts + 1); g->g_par.reserve(n_ghosts);
+  g->g_src.reserve(n_ghosts); g->g_w.reserve(n_ghosts);
   g->max_terms = 0;
   long long n_outer = 0, n_inner = 0;
-  for (long long q = 0; q < np; q++) {
-    if (g->kind[q] == 0) continue;
-    const Comb* c;
-    Comb single;
-    if (g->kind[q] == 1) { c = &comb[q]; n_outer++; }
-    else {
-      n_inner++;
-      const int s = g->src_map[q];
-      if (g->kind[s] == 0) { single[s] = 1; c = &single; }
-      else c = &comb[s];
-    }
-    g->g_dst.push_back((int)q);
-    g->g_start.push_back((int)g->g_src.size());
-    g->g_par.push_back(g->parity_map[q]);
-    for (auto& kv : *c) { g->g_src.push_back(kv.first); g->g_w.push_back((double)kv.second); }
-    g->max_terms = std::max(g->max_terms, (int)c->size());
-  }
+  std::vector<std::pair<int, long long>> single(1);
+  for (int i2 = 0; i2 < n[2]; i2++)
+    for (int i1 = 0; i1 < n[1]; i1++)
+      for (int i0 = 0; i0 < n[0]; i0++) {
+        int src, par;
+        const int k = classify(i0, i1, i2, src, par);
+        if (k == 0) continue;
+        const int q = flat(i0, i1, i2);
+        const Comb* c = nullptr;
+        bool one = false;
+        if (k == 1) {
+          c = &comb_of(q);
+          n_outer++;
+          if (c->empty()) return fail(BHAH_EINVAL, "outer ghost not reached by the shell order");
+        } else {
+          n_inner++;
+          const int ks = kind_of(src);
+          // inner ghosts map to interior or outer points (one hop)
+          if (ks == 2) return fail(BHAH_EINVAL, "inner ghost maps to another inner ghost");
+          if (ks == 0) one = true;
+          else c = &comb_of(src);
+        }
+        g->g_dst.push_back(q);
+        g->g_start.push_back((int)g->g_src.size());
+        g->g_par.push_back(par);
+        if (one) {
+          g->g_src.push_back(src);
+          g->g_w.push_back(1.0);
+          g->max_terms = std::max(g->max_terms, 1);
+        } else {
+          for (auto& kv : *c) { g->g_src.push_back(kv.first); g->g_w.push_back((double)kv.second); }
+          g->max_terms = std::max(g->max_terms, (int)c->size());
+        }
+      }
   g->g_start.push_back((int)g->g_src.size());
 
   // ---- ghosts needed by the stencils during the RK stages ---------------
   // (phi ghost planes are skipped: reads wrap phi onto the interior)
   const int pd = coord == BHAH_SINH_CYLINDRICAL ? 1 : 2;
   g->r_dst.clear(); g->r_start.clear(); g->r_par.clear(); g->r_src.clear(); g->r_w.clear();
+  g->r_dst.reserve(g->g_dst.size()); g->r_start.reserve(g->g_dst.size() + 1); g->r_par.reserve(g->g_dst.size());
+  g->r_src.reserve(g->g_src.size()); g->r_w.reserve(g->g_src.size());
   for (size_t t = 0; t < g->g_dst.size(); t++) {
     const int q = g->g_dst[t];
     const int idx = pd == 1 ? (q / n[0]) % n[1] : q / (n[0] * n[1]);
