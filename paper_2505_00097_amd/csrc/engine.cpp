@@ -108,7 +108,7 @@ int Engine::ensure_device(hipStream_t s) {
   const size_t colon = arch_.find(':');
   if (colon != std::string::npos) arch_ = arch_.substr(0, colon);
   n_cus_ = std::max(cus, 1);
-  ghost_blocks_ = 8 * n_cus_;
+  ghost_blocks_ = 2 * n_cus_;  // times NGF / GF_PER gridfunction groups
   if ((rc = check_hip(hipEventCreateWithFlags(&upload_done_, hipEventDisableTiming), "hipEventCreate"))) return rc;
   if ((rc = check_hip(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking), "hipStreamCreate"))) return rc;
   load_cache();

@@ -6,59 +6,68 @@ namespace bhah {
 // Every ghost point takes sign * sum_t w_t y[src_t]; all sources are interior
 // points, so ghosts can be filled in any order and in parallel (Sec. 3
 // outer-then-inner boundary order is folded into the weights on the host).
-__device__ __forceinline__ void ghost_point(const GhostDev& gh, double* __restrict__ y, long long sgf, int t) {
+// A thread fills GF_PER gridfunctions of one ghost point; blockIdx.y picks the
+// group of gridfunctions, so a fill runs NGF / GF_PER times more threads than
+// ghost points and keeps more loads in flight.
+constexpr int GF_PER = 4;
+static_assert(NGF % GF_PER == 0, "gridfunction groups");
+
+__device__ __forceinline__ void ghost_point(const GhostDev& gh, double* __restrict__ y, long long sgf, int t,
+                                            int g0) {
   const int dst = gh.dst[t], s0 = gh.start[t], s1 = gh.start[t + 1], par = gh.parity[t];
   // all loads before any store: sources are interior points, never ghosts,
   // but the compiler cannot know that and would otherwise keep each load
   // behind the previous store
-  double v[NGF];
+  double v[GF_PER];
   if (s1 - s0 == 1) {
     const int src = gh.src[s0];
 #pragma unroll
-    for (int g = 0; g < NGF; g++) v[g] = y[g * sgf + src];
+    for (int j = 0; j < GF_PER; j++) v[j] = y[(g0 + j) * sgf + src];
   } else {
 #pragma unroll
-    for (int g = 0; g < NGF; g++) v[g] = 0.0;
+    for (int j = 0; j < GF_PER; j++) v[j] = 0.0;
     for (int k = s0; k < s1; k++) {
       const double w = gh.w[k];
       const int src = gh.src[k];
 #pragma unroll
-      for (int g = 0; g < NGF; g++) v[g] += w * y[g * sgf + src];
+      for (int j = 0; j < GF_PER; j++) v[j] += w * y[(g0 + j) * sgf + src];
     }
   }
 #pragma unroll
-  for (int g = 0; g < NGF; g++) y[g * sgf + dst] = gf_flip(g, par) ? -v[g] : v[g];
+  for (int j = 0; j < GF_PER; j++) y[(g0 + j) * sgf + dst] = gf_flip(g0 + j, par) ? -v[j] : v[j];
 }
 
 __global__ void __launch_bounds__(256) k_ghosts(GhostDev gh, double* __restrict__ y, long long sgf) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < gh.n_ghost) ghost_point(gh, y, sgf, t);
+  if (t < gh.n_ghost) ghost_point(gh, y, sgf, t, (int)blockIdx.y * GF_PER);
 }
 
 void launch_ghosts(const GhostDev& gh, double* y, long long sgf, hipStream_t s) {
   if (gh.n_ghost == 0) return;
-  hipLaunchKernelGGL(k_ghosts, dim3((gh.n_ghost + 255) / 256), dim3(256), 0, s, gh, y, sgf);
+  hipLaunchKernelGGL(k_ghosts, dim3((gh.n_ghost + 255) / 256, NGF / GF_PER), dim3(256), 0, s, gh, y, sgf);
 }
 
 // Ensemble form: a fixed grid of blocks strides over the (job, chunk of 256
-// ghost points) work list and fills the ghosts of the stage's target array.
+// ghost points) work list (x) for one group of gridfunctions (y) and fills
+// the ghosts of the stage's target array.
 __global__ void __launch_bounds__(256) k_ghosts_batch(const BatchJob* __restrict__ jobs,
                                                       const BatchHdr* __restrict__ hdr,
                                                       const int2* __restrict__ work, int stage) {
   const int which = stage == 3 ? 1 : 0;
   const int n = hdr->n_chunks[which];
   const int2* wl = work + hdr->chunk_off[which];
+  const int g0 = (int)blockIdx.y * GF_PER;
   for (int c = (int)blockIdx.x; c < n; c += (int)gridDim.x) {
     const int2 wk = wl[c];
     const BatchJob* J = jobs + wk.x;
     const int t = wk.y * 256 + (int)threadIdx.x;
-    if (t < J->gh[which].n_ghost) ghost_point(J->gh[which], J->gdst[stage], J->G.sgf, t);
+    if (t < J->gh[which].n_ghost) ghost_point(J->gh[which], J->gdst[stage], J->G.sgf, t, g0);
   }
 }
 
 void launch_ghosts_batch(const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage, int blocks,
                          hipStream_t s) {
-  hipLaunchKernelGGL(k_ghosts_batch, dim3(blocks), dim3(256), 0, s, jobs, hdr, work, stage);
+  hipLaunchKernelGGL(k_ghosts_batch, dim3(blocks, NGF / GF_PER), dim3(256), 0, s, jobs, hdr, work, stage);
 }
 
 constexpr int MAX_PUNCT = 16;
