@@ -242,6 +242,7 @@ def run_served(capi, wl, stream, n_jobs, steps_per_tick, seq_probe_steps):
         lat.append(free - j["arrival"])
         work += j["steps"] * j["N"][0] * j["N"][1] * j["N"][2]
     seq_wall = free - jobs[0]["arrival"]
+    seq_busy = sum(j["steps"] * t_step[j["N"][0]] for j in jobs)
     return {"workload": f"{n_jobs} Poisson-arriving head-on jobs (4/s), N_rho in {{64,96,128,192}}, "
                         "steps U{200..2000}, seed 250500098, 200 GB budget",
             "value": st.point_steps / wall, "unit": UNIT, "wall_seconds": wall,
@@ -251,6 +252,7 @@ def run_served(capi, wl, stream, n_jobs, steps_per_tick, seq_probe_steps):
             "p50_job_s": st.job_s_p50, "p99_job_s": st.job_s_p99,
             "peak_running": st.peak_running, "peak_held_GB": st.peak_held_bytes / 1e9,
             "sequential_fcfs": {"value": work / seq_wall, "wall_seconds": seq_wall,
+                                "busy_seconds": seq_busy, "busy_value": work / seq_busy,
                                 "p50_job_s": percentile(lat, 50), "p99_job_s": percentile(lat, 99),
                                 "solo_step_ms": {str(k): v * 1e3 for k, v in t_step.items()},
                                 "how": "same arrivals, one job at a time in arrival order, priced with "

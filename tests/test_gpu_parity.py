@@ -192,6 +192,8 @@ def test_rhs_full_size_sampled(wname):
     og = orc.Grid(w["coord"], w["N"], ampl=w["ampl"], sinhw=w["sinhw"], cfl=w["cfl"])
     y = og.brill_lindquist(w["masses"], w["positions"])
     y = og.apply_bcs(y + 0.05 * wl.smooth_random_state(og.n, seed=3))
+    # the launch configuration the benchmark times: the tuned tile shape
+    capi.grid_tune(g.h, to_gpu(y), g.state())
     out, _ = _rhs_gpu(g, y)
     rng = np.random.default_rng(1)
     N = og.N
@@ -233,6 +235,47 @@ def test_rk4_evolution_matches_oracle(name, m, pos, steps):
     assert np.all(err <= EVOL_TOL), fmt(orc.GF_NAMES, err)
     # ghosts too
     assert np.max(np.abs(out - yo)) <= EVOL_TOL * np.max(np.abs(yo))
+
+
+def test_headon_workload_100_steps_matches_oracle():
+    """The head-on workload at full size (SinhCylindrical 128x2x256, two
+    punctures), 100 RK4 steps with the tuned tile shape the benchmark uses
+    and H at the end, against the oracle."""
+    name = "headon_sinhcylindrical_128x2x256"
+    _print_case("evolve_full", name, 100)
+    from paper_2505_00097_amd import capi
+    w = wl.WORKLOADS[name]
+    g = capi.Grid(w["coord"], w["N"], w["ampl"], w["sinhw"], w["cfl"])
+    og = orc.Grid(w["coord"], w["N"], ampl=w["ampl"], sinhw=w["sinhw"], cfl=w["cfl"])
+    y = g.state()
+    capi.set_initial_data_brill_lindquist(g.h, w["masses"], w["positions"], y)
+    capi.grid_tune(g.h, y, g.state())
+    ws = g.workspace()
+    yo = og.brill_lindquist(w["masses"], w["positions"])
+    dt = og.dt()
+    assert g.dt == pytest.approx(dt, rel=1e-14)
+    for s in range(100):
+        capi.rk4_step(g.h, y, ws, dt, eta=w["eta"])
+        og.rk4_step(yo, dt, eta=w["eta"])
+        if s % 25 == 24:
+            print("  step", s + 1, flush=True)
+    out = to_cpu(y)
+    err = gf_errors(out, yo, og.interior())
+    print("  err", fmt(orc.GF_NAMES, err), flush=True)
+    assert np.all(err <= EVOL_TOL), fmt(orc.GF_NAMES, err)
+    # H on the evolved full-size state (same input on both sides)
+    Hg = g._empty(1)
+    capi.hamiltonian_constraint(g.h, y, Hg)
+    I = og.interior()
+
+    def ham(v):
+        return og.constraints(v)[0][None]
+
+    def rel(a, b):
+        return gf_errors(a, b, I, groups=[[0]])
+    herr = rel(to_cpu(Hg), ham(out))
+    floor = rounding_floor(ham, out, rel)
+    assert np.all(herr <= np.maximum(RHS_TOL, floor)), (herr, floor)
 
 
 @pytest.mark.parametrize("name", ["tiny", "cyl_3d", "sph_ragged"])
