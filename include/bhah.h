@@ -237,6 +237,10 @@ int bhah_batch_create(const bhah_grid* const* grids, int n,
 /* Advance the jobs with host_active[j] != 0 (host_active may be NULL: all)
  * by nsteps RK4 steps each, job j at its own step host_dt[j], on y[j]
  * (state, valid ghosts) with workspace ws[j] (info.workspace_doubles).
+ * On return every ghost of y[j] is valid again. Between the steps inside
+ * one captured graph only the ghosts the stencils read are refilled (phi
+ * ghost planes are exact periodic copies that the stencils never read);
+ * the results are the same as nsteps calls of bhah_rk4_step, bit for bit.
  * y, ws and host_dt are host arrays of n entries (device pointers in y, ws).
  * Asynchronous on stream; the first call for a new size class also times
  * tile candidates (synchronising the stream).                               */

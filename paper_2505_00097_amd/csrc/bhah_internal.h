@@ -102,12 +102,13 @@ struct TileMap {
 
 // One job of an ensemble as the batched kernels see it. Stage s in 0..3 is
 // RK4 stage s + 1 (the right-hand side of in[s] combined as in st[s], then
-// the ghost fill of gdst[s]: list gh[0] after stages 0-2, gh[1] after stage
-// 3); stage 4 stores the right-hand side of in[4] in st[4].rhs and fills
-// nothing (used to time tile shapes).
+// the ghost fill of gdst[s] from list gh[0] (ghosts with an interior phi
+// index, all the stencils read) or gh[1] (all ghosts, after the last stage
+// of a batch step)); stage 4 stores the right-hand side of in[4] in
+// st[4].rhs and fills nothing (used to time tile shapes).
 struct BatchJob {
   GridDev G;
-  GhostDev gh[2];  // ghosts filled after stages 0-2 (non-phi ghosts), after stage 3 (all)
+  GhostDev gh[2];  // ghosts with an interior phi index; all ghosts
   TileMap T;
   StageArgs st[5];
   const double* in[5];
@@ -116,8 +117,8 @@ struct BatchJob {
 
 // Work list header: the (job, tile) list of coordinate family c starts at
 // tile_off[c] and holds n_tiles[c] entries; the (job, chunk of 256 ghost
-// points) list of ghost list w (0: after stages 0-2, 1: after stage 3)
-// starts at chunk_off[w] and holds n_chunks[w] entries.
+// points) list of ghost list w (as BatchJob::gh) starts at chunk_off[w] and
+// holds n_chunks[w] entries.
 struct BatchHdr {
   int n_tiles[3];
   int tile_off[3];
@@ -199,8 +200,8 @@ void launch_rhs_fused(const GridDev& G, double eta, const double* y, double* aux
 TileMap make_tilemap(const GridDev& G, int lx, int ly, int band);
 void launch_rhs_batch(int coord, const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage,
                       double eta, int blocks, hipStream_t s);
-void launch_ghosts_batch(const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage, int blocks,
-                         hipStream_t s);
+void launch_ghosts_batch(const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage, int which,
+                         int blocks, hipStream_t s);
 void launch_hamiltonian(const GridDev& G, const double* y, double* H, hipStream_t s);
 
 // The four stages of one classical RK4 step on state y with workspace ws

@@ -293,11 +293,15 @@ int Engine::capture(int nsteps, hipStream_t s, hipGraphExec_t* out) {
   rhs_blocks_ = rhs_grid();
   int rc = check_hip(hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal), "graph capture");
   if (rc) return rc;
+  // The stencils never read phi ghost planes (they wrap phi onto the
+  // interior), so within the captured steps only the ghosts with an interior
+  // phi index are filled; the last stage of the last step fills all of them.
   for (int k = 0; k < nsteps; k++)
     for (int stage = 0; stage < 4; stage++) {
       for (int f = 0; f < 3; f++)
         if (fam_present_[f]) launch_rhs_batch(f, dj, dh, dt, stage, gp_.eta, rhs_blocks_, cap_stream_);
-      launch_ghosts_batch(dj, dh, dc, stage, ghost_blocks_, cap_stream_);
+      const int which = stage == 3 && k == nsteps - 1 ? 1 : 0;
+      launch_ghosts_batch(dj, dh, dc, stage, which, ghost_blocks_, cap_stream_);
     }
   hipGraph_t graph = nullptr;
   const hipError_t le = hipGetLastError();

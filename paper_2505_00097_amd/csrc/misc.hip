@@ -49,11 +49,11 @@ void launch_ghosts(const GhostDev& gh, double* y, long long sgf, hipStream_t s) 
 
 // Ensemble form: a fixed grid of blocks strides over the (job, chunk of 256
 // ghost points) work list (x) for one group of gridfunctions (y) and fills
-// the ghosts of the stage's target array.
+// the ghosts of the stage's target array: list `which` (0: ghosts with an
+// interior phi index, 1: all ghosts).
 __global__ void __launch_bounds__(256) k_ghosts_batch(const BatchJob* __restrict__ jobs,
                                                       const BatchHdr* __restrict__ hdr,
-                                                      const int2* __restrict__ work, int stage) {
-  const int which = stage == 3 ? 1 : 0;
+                                                      const int2* __restrict__ work, int stage, int which) {
   const int n = hdr->n_chunks[which];
   const int2* wl = work + hdr->chunk_off[which];
   const int g0 = (int)blockIdx.y * GF_PER;
@@ -65,9 +65,9 @@ __global__ void __launch_bounds__(256) k_ghosts_batch(const BatchJob* __restrict
   }
 }
 
-void launch_ghosts_batch(const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage, int blocks,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(k_ghosts_batch, dim3(blocks, NGF / GF_PER), dim3(256), 0, s, jobs, hdr, work, stage);
+void launch_ghosts_batch(const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage, int which,
+                         int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_ghosts_batch, dim3(blocks, NGF / GF_PER), dim3(256), 0, s, jobs, hdr, work, stage, which);
 }
 
 constexpr int MAX_PUNCT = 16;

@@ -44,21 +44,6 @@ __device__ __forceinline__ void gather_cross_kl(const Pt& P, int g, int k, int l
   else gather_cross<1, 2>(P, g, v);
 }
 
-// first derivatives of N gridfunctions in one batch of loads
-template <int N>
-__device__ __forceinline__ void grad_batch(const Pt& P, const int (&gf)[N], const Spacing& sp, double (&d)[N][3]) {
-  double v[N][3][5];
-#pragma unroll
-  for (int t = 0; t < N; t++)
-#pragma unroll
-    for (int k = 0; k < 3; k++) gather_axis_k(P, gf[t], k, v[t][k]);
-  BHAH_PHASE_BARRIER();
-#pragma unroll
-  for (int t = 0; t < N; t++)
-#pragma unroll
-    for (int k = 0; k < 3; k++) d[t][k] = d1_axis(v[t][k], sp.i12h[k]);
-}
-
 // upwinded advection of N gridfunctions in one batch of loads
 template <int N>
 __device__ __forceinline__ void advect_batch(const Pt& P, const int (&gl)[N], const Upwind2& U, double (&out)[N]) {
