@@ -53,3 +53,38 @@ def test_grid_create_reports_errors_without_gpu():
         p.nghosts = 3
         h = ctypes.c_void_p()
         capi._check(capi.lib().bhah_grid_create(ctypes.byref(p), ctypes.byref(h)), "bhah_grid_create")
+
+
+@pytest.mark.parametrize("coord,N,msg", [
+    (0, (2, 8, 2), "N\\[d\\] < nghosts"),          # radial direction narrower than the stencil
+    (0, (8, 2, 2), "N\\[d\\] < nghosts"),          # theta is not periodic
+    (0, (8, 8, 3), "N_phi must be even"),        # odd phi count: no phi + pi partner
+    (1, (8, 0, 8), "N_phi must be even"),
+    (2, (1024, 256, 512), "grid too large"),     # beyond 2^26 points with ghosts
+    (3, (8, 8, 8), "coord"),
+])
+def test_grid_create_rejects_bad_shapes_before_any_device_call(coord, N, msg):
+    from paper_2505_00097_amd import capi
+    with pytest.raises(capi.BhahError, match=msg):
+        capi.grid_create(coord, N)
+
+
+def test_grid_create_rejects_bad_map_parameters():
+    from paper_2505_00097_amd import capi
+    with pytest.raises(capi.BhahError, match="ampl"):
+        capi.grid_create(0, (8, 8, 2), ampl=(0.0, 1.0, 1.0))
+    with pytest.raises(capi.BhahError, match="sinhw"):
+        capi.grid_create(1, (8, 2, 8), sinhw=(0.2, 0.2, 0.0))
+    with pytest.raises(capi.BhahError, match="cfl"):
+        capi.grid_create(0, (8, 8, 2), cfl=0.0)
+
+
+def test_null_arguments_are_rejected():
+    from paper_2505_00097_amd import capi
+    L = capi.lib()
+    assert L.bhah_grid_create(None, None) == capi.EINVAL
+    assert L.bhah_apply_bcs(None, None, None) == capi.EINVAL
+    assert L.bhah_rk4_step(None, None, 0.0, None, None, None) == capi.EINVAL
+    assert L.bhah_batch_create(None, 0, None, None, None) == capi.EINVAL
+    assert L.bhah_server_create(None, None, None) == capi.EINVAL
+    assert "NULL" in capi.last_error() or "bad argument" in capi.last_error()

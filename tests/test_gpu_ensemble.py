@@ -283,3 +283,36 @@ def test_server_rejects_job_larger_than_budget():
     with pytest.raises(capi.BhahError, match="budget"):
         capi.server_submit(srv, d)
     capi.server_destroy(srv)
+
+
+def test_empty_and_zero_step_calls():
+    """No active job, zero steps, and a server tick with nothing submitted are
+    no-ops; a job asking for zero steps finishes at once with its initial
+    data."""
+    _case("empty calls")
+    import torch
+    from paper_2505_00097_amd import capi
+    jobs = _small_jobs()[:2]
+    grids, ys, wss = _setup(jobs)
+    ys0 = [y.clone() for y in ys]
+    b = capi.batch_create([g.h for g in grids], eta=2.0)
+    capi.batch_step(b, ys, wss, [g.dt for g in grids], active=[0, 0], nsteps=5)
+    capi.batch_step(b, ys, wss, [g.dt for g in grids], nsteps=0)
+    torch.cuda.synchronize()
+    for y, y0 in zip(ys, ys0):
+        assert torch.equal(y, y0)
+    with pytest.raises(capi.BhahError):
+        capi.batch_step(b, ys, wss, [g.dt for g in grids], nsteps=-1)
+    capi.batch_destroy(b)
+    srv = capi.server_create(1e9, max_jobs=2, keep_results=True)
+    assert capi.server_tick(srv) == (0, 0)
+    j = jobs[0]
+    i = capi.server_submit(srv, capi.job_desc(j["coord"], j["N"], j["ampl"], j["sinhw"], j["cfl"], j["masses"],
+                                              j["positions"], 0))
+    capi.server_tick(srv)
+    assert capi.server_job_status(srv, i).state == capi.JOB_DONE
+    out = grids[0].state()
+    capi.server_fetch(srv, i, out)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ys0[0])
+    capi.server_destroy(srv)

@@ -412,3 +412,46 @@ def test_tile_shape_does_not_change_results(name):
     capi.rk4_step(g.h, y, ws, g.dt)
     torch.cuda.synchronize()
     assert torch.equal(y, ref)
+
+
+@pytest.mark.parametrize("coord,N", [(wl.SINH_SPHERICAL, (3, 3, 2)), (wl.SINH_CYLINDRICAL, (3, 2, 3)),
+                                     (wl.SPHERICAL, (3, 3, 2))])
+def test_smallest_grids(coord, N):
+    """Grids one stencil radius wide: every interior point's stencils reach
+    the outermost ghost layers on both sides; RHS and 10 RK4 steps against
+    the oracle."""
+    _print_case("smallest", coord, N)
+    from paper_2505_00097_amd import capi
+    ampl = (2.0, 2.0, 3.0)
+    g = capi.Grid(coord, N, ampl, (0.3,) * 3)
+    og = orc.Grid(coord, N, ampl=ampl, sinhw=(0.3,) * 3)
+    y = og.apply_bcs(og.brill_lindquist([0.4], [(0.1, 0.0, 0.2)]) + 0.01 * wl.smooth_random_state(og.n, seed=2))
+    out, _ = _rhs_gpu(g, y)
+    ref = og.rhs(y, eta=2.0)
+    I = og.interior()
+    err = gf_errors(out, ref, I)
+    floor = rounding_floor(lambda v: og.rhs(v, eta=2.0), y, lambda a, b: gf_errors(a, b, I))
+    assert np.all(err <= np.maximum(RHS_TOL, floor)), fmt(orc.GF_NAMES, err)
+    yg = to_gpu(y)
+    ws = g.workspace()
+    dt = og.dt()
+    for _ in range(10):
+        capi.rk4_step(g.h, yg, ws, dt)
+        og.rk4_step(y, dt, eta=2.0)
+    err = gf_errors(to_cpu(yg), y, I)
+    assert np.all(err <= EVOL_TOL), fmt(orc.GF_NAMES, err)
+
+
+def test_invalid_calls_report_errors():
+    _print_case("errors")
+    from paper_2505_00097_amd import capi
+    g = capi.Grid(wl.SINH_SPHERICAL, (8, 8, 2))
+    y = g.state()
+    with pytest.raises(capi.BhahError, match="n_punct"):
+        capi.set_initial_data_brill_lindquist(g.h, [0.1] * 17, [(0.0, 0.0, 0.0)] * 17, y)
+    with pytest.raises(capi.BhahError, match="lapse_kind"):
+        capi.set_initial_data_brill_lindquist(g.h, [1.0], [(0.0, 0.0, 0.0)], y, lapse_kind=3)
+    with pytest.raises(capi.BhahError, match="shift_variant"):
+        gp = capi.GaugeParams(2.0, 1)
+        capi._check(capi.lib().bhah_bssn_rhs(g.h, capi.ctypes.byref(gp), capi._ptr(y), capi._ptr(g.state()),
+                                             None, capi._stream(None)), "bhah_bssn_rhs")
