@@ -189,14 +189,14 @@ def run_batched(capi, wl, stream, steps, seq_steps, graph_steps):
             "tiles": info.n_tiles, "rhs_blocks": info.rhs_blocks, "finite": finite}
 
 
-def run_served(capi, wl, stream, n_jobs, steps_per_tick, seq_probe_steps):
+def run_served(capi, wl, stream, n_jobs, steps_per_tick, seq_probe_steps, target_points):
     """Poisson-arriving head-on jobs through the continuous-batching server,
     and a first-come-first-served one-job-at-a-time schedule of the same
     arrivals priced with measured solo step times."""
     import torch
     jobs = wl.served_jobs(n=n_jobs)
     srv = capi.server_create(200e9, max_jobs=256, steps_per_tick=steps_per_tick, keep_results=False,
-                             eta=2.0, stream=stream)
+                             eta=2.0, stream=stream, target_points=target_points)
     descs = [capi.job_desc(j["coord"], j["N"], j["ampl"], j["sinhw"], j["cfl"], j["masses"], j["positions"],
                            j["steps"]) for j in jobs]
     t0 = time.perf_counter()
@@ -246,6 +246,7 @@ def run_served(capi, wl, stream, n_jobs, steps_per_tick, seq_probe_steps):
     return {"workload": f"{n_jobs} Poisson-arriving head-on jobs (4/s), N_rho in {{64,96,128,192}}, "
                         "steps U{200..2000}, seed 250500098, 200 GB budget",
             "value": st.point_steps / wall, "unit": UNIT, "wall_seconds": wall,
+            "target_points": target_points,
             "busy_value": st.point_steps / st.busy_seconds if st.busy_seconds > 0 else None,
             "busy_seconds": st.busy_seconds, "point_steps": st.point_steps, "jobs_done": st.done,
             "p50_step_ms": st.step_ms_p50, "p99_step_ms": st.step_ms_p99,
@@ -326,6 +327,8 @@ def main():
     ap.add_argument("--batched-seq-steps", type=int, default=50)
     ap.add_argument("--graph-steps", type=int, default=10)
     ap.add_argument("--served-jobs", type=int, default=256)
+    ap.add_argument("--served-target-points", type=int, default=262144,
+                    help="admit while running jobs hold fewer interior points (0: no limit)")
     ap.add_argument("--study-steps", type=int, default=20)
     ap.add_argument("--no-paper-grids", action="store_true")
     args = ap.parse_args()
@@ -397,7 +400,8 @@ def main():
             torch.cuda.empty_cache()
             print("# paper grids done", file=sys.stderr, flush=True)
         if args.served_jobs > 0:
-            extras["served"] = run_served(capi, wl, stream, args.served_jobs, args.graph_steps, 30)
+            extras["served"] = run_served(capi, wl, stream, args.served_jobs, args.graph_steps, 30,
+                                          args.served_target_points)
             print(f"# served: {extras['served']['value']:.3e} pt-steps/s", file=sys.stderr, flush=True)
 
     flops = F_ALG[w["coord"]] * n_int

@@ -292,6 +292,10 @@ typedef struct {
   int max_jobs;             /* running jobs at most                           */
   int steps_per_tick;       /* RK4 steps per tick at most                     */
   int keep_results;         /* 1: a finished job's state stays until fetched  */
+  long long target_points;  /* admit while running jobs hold fewer interior
+                               points than this (0: no limit); about four
+                               64-point tiles per SIMD fill the GPU, more only
+                               lengthens every running job's step           */
   bhah_gauge_params gauge;
   const char* tune_cache_path; /* may be NULL                                 */
 } bhah_server_params;

@@ -47,6 +47,7 @@ class BatchInfo(ctypes.Structure):
 class ServerParams(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_double), ("max_jobs", ctypes.c_int),
                 ("steps_per_tick", ctypes.c_int), ("keep_results", ctypes.c_int),
+                ("target_points", ctypes.c_longlong),
                 ("gauge", GaugeParams), ("tune_cache_path", ctypes.c_char_p)]
 
 
@@ -284,9 +285,9 @@ def batch_destroy(b):
 
 
 def server_create(budget_bytes, max_jobs, steps_per_tick=10, keep_results=False, eta=2.0,
-                  tune_cache_path=None, stream=None):
+                  tune_cache_path=None, stream=None, target_points=0):
     p = ServerParams(float(budget_bytes), int(max_jobs), int(steps_per_tick), 1 if keep_results else 0,
-                     gauge(eta), tune_cache_path.encode() if tune_cache_path else None)
+                     int(target_points), gauge(eta), tune_cache_path.encode() if tune_cache_path else None)
     s = _vp()
     _check(lib().bhah_server_create(ctypes.byref(p), _stream(stream), ctypes.byref(s)), "bhah_server_create")
     return s

@@ -110,10 +110,19 @@ struct bhah_server {
     j.mem = nullptr;
   }
 
-  // admit queued jobs in arrival order while a slot and memory are free
+  long long running_points() {
+    long long n = 0;
+    for (long long id : running) n += jobs[id].g->info.n_interior;
+    return n;
+  }
+
+  // admit queued jobs in arrival order while a slot and memory are free and
+  // the running set is below the target size
   int admit() {
+    long long pts = running_points();
     for (auto it = queue.begin(); it != queue.end();) {
       if ((int)running.size() >= p.max_jobs) break;
+      if (p.target_points > 0 && pts >= p.target_points) break;
       Job& j = jobs[*it];
       std::vector<double*>& fl = free_slabs[j.key];
       double* mem = nullptr;
@@ -141,6 +150,7 @@ struct bhah_server {
       if (rc) return rc;
       j.state = BHAH_JOB_RUNNING;
       j.t_admit = now();
+      pts += j.g->info.n_interior;
       running.push_back(*it);
       it = queue.erase(it);
     }
