@@ -316,3 +316,33 @@ def test_empty_and_zero_step_calls():
     torch.cuda.synchronize()
     assert torch.equal(out, ys0[0])
     capi.server_destroy(srv)
+
+
+def test_server_target_points_caps_the_running_set():
+    """With the running-point target at one job's size, jobs run one at a
+    time (continuous admission as each finishes); results still equal the
+    solo evolution."""
+    _case("server target")
+    import torch
+    from paper_2505_00097_amd import capi
+    jobs = _server_jobs()[:3]
+    n_pts = jobs[0]["N"][0] * jobs[0]["N"][1] * jobs[0]["N"][2]
+    srv = capi.server_create(1e10, max_jobs=8, steps_per_tick=3, keep_results=True, target_points=n_pts)
+    ids = [capi.server_submit(srv, capi.job_desc(j["coord"], j["N"], j["ampl"], j["sinhw"], j["cfl"], j["masses"],
+                                                 j["positions"], j["steps"])) for j in jobs]
+    for _ in range(200):
+        running, queued = capi.server_tick(srv)
+        assert running <= 1
+        if running == 0 and queued == 0:
+            break
+    st = capi.server_get_stats(srv)
+    assert st.done == 3 and st.peak_running == 1
+    for k, j in enumerate(jobs):
+        g = capi.Grid(j["coord"], j["N"], j["ampl"], j["sinhw"], j["cfl"])
+        out = g.state()
+        capi.server_fetch(srv, ids[k], out)
+        y = g.state()
+        capi.set_initial_data_brill_lindquist(g.h, j["masses"], j["positions"], y)
+        (s,) = _solo([g], [y], [j["steps"]])
+        assert torch.equal(out, s), k
+    capi.server_destroy(srv)
