@@ -191,6 +191,14 @@ int bhah_bssn_rhs(const bhah_grid* g, const bhah_gauge_params* gp,
 int bhah_rk4_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt,
                   double* y, double* workspace, void* stream);
 
+/* All three constraints at every interior point, centred 4th-order
+ * differences: H of Eq. 16 (one gridfunction), the momentum constraint M^i of
+ * Eq. 17 and C^i = Lambdabar^i - Delta^i (three gridfunctions each, rescaled
+ * like lambda^i: times S_i). Same layout as the state, interior points only;
+ * any of H, M, C may be NULL (skipped). y must have valid ghosts.           */
+int bhah_constraints(const bhah_grid* g, const double* y, double* H, double* M,
+                     double* C, void* stream);
+
 /* Tile shape of this grid's right-hand-side kernel (bhah_bssn_rhs and
  * bhah_rk4_step): 64 points, 2^lx along i0, 2^ly along i1, 64 >> (lx + ly)
  * along i2, walked in bands of `band` tile rows of i1. The extent along phi

@@ -93,6 +93,7 @@ _SIGS = {
     "bhah_bssn_rhs": (ctypes.c_int, [_vp, ctypes.POINTER(GaugeParams), _vp, _vp, _vp, _vp]),
     "bhah_rk4_step": (ctypes.c_int, [_vp, ctypes.POINTER(GaugeParams), ctypes.c_double, _vp, _vp, _vp]),
     "bhah_hamiltonian_constraint": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "bhah_constraints": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "bhah_grid_set_tile": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "bhah_grid_get_tile": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "bhah_grid_tune": (ctypes.c_int, [_vp, ctypes.POINTER(GaugeParams), _vp, _vp, _vp]),
@@ -222,6 +223,10 @@ def rk4_step(h, y, workspace, dt, eta=2.0, stream=None):
 def hamiltonian_constraint(h, y, H, stream=None):
     _check(lib().bhah_hamiltonian_constraint(h, _ptr(y), _ptr(H), _stream(stream)),
            "bhah_hamiltonian_constraint")
+
+
+def constraints(h, y, H=None, M=None, C=None, stream=None):
+    _check(lib().bhah_constraints(h, _ptr(y), _ptr(H), _ptr(M), _ptr(C), _stream(stream)), "bhah_constraints")
 
 
 def grid_set_tile(h, lx, ly, band):

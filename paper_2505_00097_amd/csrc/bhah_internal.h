@@ -203,6 +203,7 @@ void launch_rhs_batch(int coord, const BatchJob* jobs, const BatchHdr* hdr, cons
 void launch_ghosts_batch(const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage, int which,
                          int blocks, hipStream_t s);
 void launch_hamiltonian(const GridDev& G, const double* y, double* H, hipStream_t s);
+void launch_constraints(const GridDev& G, const double* y, double* H, double* Mo, double* Co, hipStream_t s);
 
 // The four stages of one classical RK4 step on state y with workspace ws
 // (three state-sized arrays A, B, Cacc): inputs, stage combinations and the

@@ -250,6 +250,13 @@ int bhah_grid_tune(bhah_grid* g, const bhah_gauge_params* gp, const double* y, d
   return rc ? rc : check_launch("bhah_grid_tune");
 }
 
+int bhah_constraints(const bhah_grid* g, const double* y, double* H, double* M, double* C, void* stream) {
+  if (!g || !y) return fail(BHAH_EINVAL, "bhah_constraints: NULL grid or state");
+  if (!H && !M && !C) return BHAH_OK;
+  launch_constraints(g->dev, y, H, M, C, (hipStream_t)stream);
+  return check_launch("bhah_constraints");
+}
+
 int bhah_hamiltonian_constraint(const bhah_grid* g, const double* y, double* H, void* stream) {
   if (!g || !y || !H) return fail(BHAH_EINVAL, "bhah_hamiltonian_constraint: NULL argument");
   launch_hamiltonian(g->dev, y, H, (hipStream_t)stream);

@@ -455,3 +455,52 @@ def test_invalid_calls_report_errors():
         gp = capi.GaugeParams(2.0, 1)
         capi._check(capi.lib().bhah_bssn_rhs(g.h, capi.ctypes.byref(gp), capi._ptr(y), capi._ptr(g.state()),
                                              None, capi._stream(None)), "bhah_bssn_rhs")
+
+
+@pytest.mark.parametrize("name", ["tiny", "cyl_3d", "sph_ragged", "spherical"])
+def test_constraints_match_oracle(name):
+    """H (Eq. 16), M^i (Eq. 17) and C^i from bhah_constraints against the
+    oracle: exactly zero momentum and C^i on Brill-Lindquist data, and within
+    max(1e-12, the oracle's rounding floor) on evolved and smooth random
+    states (each constraint measured against its own largest magnitude)."""
+    _print_case("constraints", name)
+    import torch
+    from paper_2505_00097_amd import capi
+    g, og = _pair(name)
+    I = og.interior()
+    bl = og.brill_lindquist([0.8], [(0.1, 0.0, 0.2)])
+    ev = bl.copy()
+    for _ in range(10):
+        og.rk4_step(ev, og.dt(), eta=2.0)
+    rnd = og.apply_bcs(wl.smooth_random_state(og.n, seed=8))
+
+    def cons(v):
+        H, M, C = og.constraints(v)
+        return np.concatenate([H[None], M, C])
+
+    groups = [[0], [1, 2, 3], [4, 5, 6]]
+    for label, y in (("bl", bl), ("evolved", ev), ("random", rnd)):
+        H, M, C = g._empty(1), g._empty(3), g._empty(3)
+        for t in (H, M, C):
+            t.zero_()
+        capi.constraints(g.h, to_gpu(y), H, M, C)
+        torch.cuda.synchronize()
+        got = np.concatenate([to_cpu(H), to_cpu(M), to_cpu(C)])
+        if label == "bl":
+            assert np.all(got[1:][(slice(None),) + I] == 0.0)
+        ref = cons(y)
+
+        def rel(a, b):
+            return gf_errors(a, b, I, groups=groups)
+        err = rel(got, ref)
+        tol = np.maximum(RHS_TOL, rounding_floor(cons, y, rel))
+        print("  ", label, err, flush=True)
+        assert np.all(err <= tol), (label, err, tol)
+    # bhah_hamiltonian_constraint gives the same H up to rounding (another
+    # kernel instance: the compiler may contract differently)
+    y = to_gpu(ev)
+    H1, H2 = g._empty(1), g._empty(1)
+    capi.hamiltonian_constraint(g.h, y, H1)
+    capi.constraints(g.h, y, H2, None, None)
+    a, b = to_cpu(H1)[0][I], to_cpu(H2)[0][I]
+    assert np.max(np.abs(a - b)) <= RHS_TOL * np.max(np.abs(a))
