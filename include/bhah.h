@@ -184,9 +184,13 @@ int bhah_apply_bcs(const bhah_grid* g, double* y, void* stream);
 int bhah_bssn_rhs(const bhah_grid* g, const bhah_gauge_params* gp,
                   const double* y, double* rhs, double* aux, void* stream);
 
-/* One classical RK4 step of size dt, in place on y (interior updated, ghosts
- * refilled by bhah_apply_bcs after every stage and after the final combine,
- * Sec. 3 boundary order; RK4 per Sec. 4.2.1). workspace must hold
+/* One classical RK4 step of size dt, in place on y (RK4 per Sec. 4.2.1; the
+ * boundary fill of Sec. 3 after every stage and after the final combine).
+ * On return every ghost of y is valid, exactly as bhah_apply_bcs leaves it.
+ * The intermediate stage arrays get only the ghosts the stencils read: phi
+ * ghost planes are exact periodic copies that the stencils never read (they
+ * wrap the phi index onto the interior), so they are filled once, after the
+ * final combine; the result is the same. workspace must hold
  * info.workspace_doubles doubles and must not alias y.                       */
 int bhah_rk4_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt,
                   double* y, double* workspace, void* stream);

@@ -2,18 +2,27 @@
 // conformal Ricci tensor of Eq. 12, arXiv:2505.00097) in one kernel, one
 // thread per interior point, with the RK4 stage combination as epilogue.
 //
-// The per-point work is ordered to keep few values live at a time:
-//   phase 1  stencil loop over the six index pairs (k,l): every second
-//            derivative is consumed at once into the contractions the
-//            equations need (22 accumulators):
+// The per-point work is ordered to keep few values live at a time; values
+// needed by a later phase wait in a per-lane LDS park.
+//   phase 0  point values, the conformal metric and its inverse, the upwind
+//            stencil offsets
+//   phase 1  stencil loop over the six index pairs (k,l) of h_ij, W, alpha
+//            and vet^i: every second derivative is consumed at once into the
+//            contractions the equations need (22 accumulators):
 //              P_ij  = sum_kl gammabar^kl d_k d_l h_ij            (Ricci)
 //              Qs_k  = sum_m beta^m gammabar^ab S_a S_b d_k d_m h_ab
 //              Y_kl  = (alpha/W) d_k d_l W - d_k d_l alpha         (Abar eq.)
 //              Za    = gammabar^kl d_k d_l alpha                   (K eq.)
 //              Bv^i  = gammabar^kl d_k d_l vet^i, Bd_k = sum_j d_k d_j vet^j / S_j
-//   phase 2  first derivatives, the metric pieces (Eqs. 3-5), the remaining
-//            lower-order Ricci terms, then Eqs. 7-15 and the rescaling.
-// Reference-metric structural zeros fold away per coordinate family.
+//            the diagonal gathers also give these gridfunctions' first
+//            derivatives and upwinded advection terms
+//   phase 2  the metric pieces (Eqs. 3-5), the Ricci tensor (Eq. 12), Delta
+//            terms; lambda^i's derivatives and advection
+//   phase 3  the remaining advection, then Eqs. 7-15 and the rescaling
+//   epilogue the right-hand side, or the RK stage combination
+// Stencil values are loaded in batches of up to about 64 ahead of the
+// arithmetic that uses them. Reference-metric structural zeros fold away per
+// coordinate family.
 #include "rhs_common.h"
 
 namespace bhah {
@@ -734,11 +743,10 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
   }
 }
 
-// Occupancy target of the fused kernel: 1 keeps every value in registers
-// (vector + accumulation registers), 2 trades some scratch for latency hiding.
-#ifndef BHAH_RHS_WAVES
-#define BHAH_RHS_WAVES 1
-#endif
+// The fused kernel runs one wave per SIMD: every value of a point fits the
+// wave's vector and accumulation registers plus its LDS park. At two waves
+// per SIMD the compiler spills 700-1000 bytes per lane and the kernel is
+// slower.
 
 // Tiles: 64 points, 2^lx along i0 times 2^ly along i1 times 64 >> (lx + ly)
 // along i2; the tile grid is walked in bands of `band` tile rows of i1, then
@@ -771,7 +779,7 @@ __device__ __forceinline__ bool tile_point(const GridDev& G, const TileMap& T, i
 __device__ __forceinline__ int xcd_remap(int b, int per) { return (b % BHAH_NXCD) * per + b / BHAH_NXCD; }
 
 template <int C>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BHAH_RHS_WAVES, BHAH_RHS_WAVES)))
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
 k_rhs_fused(GridDev G, TileMap T, double eta, const double* __restrict__ y, StageArgs st,
             double* __restrict__ aux) {
   const int per = (T.ntiles + BHAH_NXCD - 1) / BHAH_NXCD;
@@ -788,7 +796,7 @@ k_rhs_fused(GridDev G, TileMap T, double eta, const double* __restrict__ y, Stag
 // count) strides over one coordinate family's (job, tile) work list; every
 // point runs the same fused_point as above.
 template <int C>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BHAH_RHS_WAVES, BHAH_RHS_WAVES)))
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
 k_rhs_batch(const BatchJob* __restrict__ jobs, const BatchHdr* __restrict__ hdr, const int2* __restrict__ work,
             int stage, double eta) {
   const int n = hdr->n_tiles[C];
