@@ -331,6 +331,8 @@ def main():
                     help="admit while running jobs hold fewer interior points (0: no limit)")
     ap.add_argument("--study-steps", type=int, default=20)
     ap.add_argument("--no-paper-grids", action="store_true")
+    ap.add_argument("--no-probe-peaks", action="store_true",
+                    help="skip measuring the device's FP64 FMA and HBM triad ceilings")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (no multi-GPU path); run with --gpus 1",
@@ -378,6 +380,7 @@ def main():
         # ---- the dominant kernel: one right-hand-side evaluation ----------
         rhs_s = time_rhs(capi, g, y, w["eta"], args.rhs_reps, stream)
         del y, ws, H
+        probe = None if args.no_probe_peaks else capi.probe_peaks(stream)
 
         extras = {}
         if args.batched_steps > 0:
@@ -432,7 +435,11 @@ def main():
                      "frac": achieved / PEAK_FP64_VECTOR, "traffic": traffic,
                      "flops_per_point": F_ALG[w["coord"]], "points": n_int, "launch_s": rhs_s,
                      "hbm_alg_GBps": BYTES_ALG * n_int / rhs_s / 1e9,
-                     "hbm_measured_GBps": traffic / rhs_s / 1e9 if traffic else None},
+                     "hbm_measured_GBps": traffic / rhs_s / 1e9 if traffic else None,
+                     # ceilings measured on this device (FMA chains, streaming triad)
+                     "device_fp64_tflops": probe[0] if probe else None,
+                     "frac_of_device_fp64": achieved / 1e12 / probe[0] if probe else None,
+                     "device_triad_GBps": probe[1] if probe else None},
         "extras": extras,
     }
     if not args.no_cpu_baseline:

@@ -358,6 +358,17 @@ int bhah_server_fetch(bhah_server* s, long long id, double* dst);
 int bhah_server_get_stats(const bhah_server* s, bhah_server_stats* st);
 void bhah_server_destroy(bhah_server* s);
 
+/* ---- machine peaks --------------------------------------------------------
+ * Measured ceilings of the current device, for reading the kernels' roofline
+ * fractions against what the card sustains as well as against its published
+ * figures. *fp64_tflops: independent FP64 FMA chains (2 flops per FMA) at
+ * full occupancy. *hbm_gbps: a streaming triad a = b + s*c over three 2 GiB
+ * arrays, 48 bytes moved per pair of doubles. Outputs are host pointers.
+ * Allocates about 6 GiB of device memory for the duration of the call and
+ * frees it; returns after the stream has drained. BHAH_EINVAL on NULL
+ * outputs, BHAH_EDEVICE on a HIP failure.                                   */
+int bhah_probe_peaks(double* fp64_tflops, double* hbm_gbps, void* stream);
+
 /* Message describing the last failed call on this thread ("" if none).      */
 const char* bhah_last_error(void);
 

@@ -21,6 +21,7 @@ SOURCES = {
     "rhs_fused.hip": DEVICE + ["-fno-signed-zeros", "-ffinite-math-only"],
     "hamiltonian.hip": DEVICE + ["-fno-signed-zeros", "-ffinite-math-only"],
     "misc.hip": DEVICE,
+    "probe.hip": DEVICE,
     "grid.cpp": [],
     "capi.cpp": [],
     "engine.cpp": [],

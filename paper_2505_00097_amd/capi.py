@@ -112,6 +112,7 @@ _SIGS = {
     "bhah_server_fetch": (ctypes.c_int, [_vp, ctypes.c_longlong, _vp]),
     "bhah_server_get_stats": (ctypes.c_int, [_vp, ctypes.POINTER(ServerStats)]),
     "bhah_server_destroy": (None, [_vp]),
+    "bhah_probe_peaks": (ctypes.c_int, [_vp, _vp, _vp]),
 }
 
 
@@ -243,6 +244,13 @@ def grid_get_tile(h):
 def grid_tune(h, y, rhs, eta=2.0, stream=None):
     gp = gauge(eta)
     _check(lib().bhah_grid_tune(h, ctypes.byref(gp), _ptr(y), _ptr(rhs), _stream(stream)), "bhah_grid_tune")
+
+
+def probe_peaks(stream=None):
+    """Measured (FP64 TFLOP/s, HBM GB/s) of the current device."""
+    tf, gb = ctypes.c_double(), ctypes.c_double()
+    _check(lib().bhah_probe_peaks(ctypes.byref(tf), ctypes.byref(gb), _stream(stream)), "bhah_probe_peaks")
+    return tf.value, gb.value
 
 
 def batch_create(grid_handles, eta=2.0, tune_cache_path=None):

@@ -504,3 +504,13 @@ def test_constraints_match_oracle(name):
     capi.constraints(g.h, y, H2, None, None)
     a, b = to_cpu(H1)[0][I], to_cpu(H2)[0][I]
     assert np.max(np.abs(a - b)) <= RHS_TOL * np.max(np.abs(a))
+
+
+def test_probe_peaks_are_plausible():
+    """The measured ceilings fall between a sanity floor and the published
+    MI355X figures (FP64 vector 78.6 TFLOP/s, HBM 8 TB/s), within 5 %."""
+    from paper_2505_00097_amd import capi
+    tf, gbps = capi.probe_peaks()
+    print(f"probe: fp64 {tf:.1f} TFLOP/s, triad {gbps:.0f} GB/s")
+    assert 5.0 < tf < 78.6 * 1.05
+    assert 500.0 < gbps < 8000.0 * 1.05
