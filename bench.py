@@ -28,10 +28,24 @@ PEAK_FP64_VECTOR = 78.6e12  # MI355X FP64 vector FLOP/s (no MFMA: stencil code)
 PEAK_HBM = 8.0e12           # bytes/s
 
 # FP64 operations per interior point for one right-hand-side evaluation, per
-# coordinate family: the fadd/fsub/fmul/fdiv count (an FMA counts 2) of the
-# optimised per-point code, as paper_2505_00097_amd/count_flops.py prints it
-# (a CPU test keeps the two in step).
-F_ALG = {0: 5792, 1: 5314, 2: 5597}
+# (coordinate family, two phi planes): the fadd/fsub/fmul/fdiv count (an FMA
+# counts 2) of the optimised per-point code, as
+# paper_2505_00097_amd/count_flops.py prints it (a CPU test keeps the two in
+# step). On grids with two phi planes the kernel variant drops the phi
+# derivatives that vanish identically there, and its own count applies.
+F_ALG = {(0, False): 5792, (0, True): 5037, (1, False): 5314, (1, True): 4553, (2, False): 5597,
+         (2, True): 4842}
+
+
+def two_planes(coord, N):
+    """True where the grid has exactly two phi planes (phi = i1 on
+    SinhCylindrical grids, i2 otherwise)."""
+    return (N[1] if coord == 1 else N[2]) == 2
+
+
+def f_alg(coord, N):
+    """FP64 operations per point of the kernel variant that runs on this grid."""
+    return F_ALG[(coord, two_planes(coord, N))]
 # algorithmic HBM bytes per interior point per right-hand-side evaluation:
 # read 24 state gridfunctions, write 24 results (FP64)
 BYTES_ALG = 24 * 8 * 2
@@ -280,8 +294,8 @@ def run_rhs_study(capi, wl, stream, reps, steps):
     rhs_s = time_rhs(capi, g, y, w["eta"], reps, stream)
     n = g.info.n_interior
     return {"workload": "vacuum3d_sinhspherical_256x128x64", "interior_points": n,
-            "rhs_launch_s": rhs_s, "rhs_TFLOPs": F_ALG[w["coord"]] * n / rhs_s / 1e12,
-            "rhs_frac_fp64_peak": F_ALG[w["coord"]] * n / rhs_s / PEAK_FP64_VECTOR,
+            "rhs_launch_s": rhs_s, "rhs_TFLOPs": f_alg(w["coord"], w["N"]) * n / rhs_s / 1e12,
+            "rhs_frac_fp64_peak": f_alg(w["coord"], w["N"]) * n / rhs_s / PEAK_FP64_VECTOR,
             "rhs_alg_GBps": BYTES_ALG * n / rhs_s / 1e9,
             "rk4_step_ms": step_s * 1e3, "value": n / step_s, "unit": UNIT,
             "tile": list(capi.grid_get_tile(g.h))}
@@ -407,7 +421,7 @@ def main():
                                           args.served_target_points)
             print(f"# served: {extras['served']['value']:.3e} pt-steps/s", file=sys.stderr, flush=True)
 
-    flops = F_ALG[w["coord"]] * n_int
+    flops = f_alg(w["coord"], w["N"]) * n_int
     achieved = flops / rhs_s
     traffic = measured_traffic(args.workload)
     out = {
@@ -430,10 +444,11 @@ def main():
                    "tile": list(capi.grid_get_tile(g.h))},
         "latency": {"p50_step_ms": percentile(step_ms, 50), "p99_step_ms": percentile(step_ms, 99)},
         "finite": finite,
-        "roofline": {"kernel": "k_rhs_fused", "bound": "alu",
+        "roofline": {"kernel": "k_rhs_fused<%d,%s>" % (w["coord"], "true" if two_planes(w["coord"], w["N"])
+                                                         else "false"), "bound": "alu",
                      "achieved": achieved / 1e12, "peak": PEAK_FP64_VECTOR / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_VECTOR, "traffic": traffic,
-                     "flops_per_point": F_ALG[w["coord"]], "points": n_int, "launch_s": rhs_s,
+                     "flops_per_point": f_alg(w["coord"], w["N"]), "points": n_int, "launch_s": rhs_s,
                      "hbm_alg_GBps": BYTES_ALG * n_int / rhs_s / 1e9,
                      "hbm_measured_GBps": traffic / rhs_s / 1e9 if traffic else None,
                      # ceilings measured on this device (FMA chains, streaming triad)

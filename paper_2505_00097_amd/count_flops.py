@@ -1,7 +1,9 @@
 """FP64 operations per interior point of one right-hand-side evaluation.
 
 Compiles the right-hand-side kernel source to optimised device LLVM IR with
-the library's own flags and counts, in each k_rhs_fused<C> kernel, the double
+the library's own flags and counts, in each k_rhs_fused<C, AX> kernel (AX: the
+variant for grids with two phi planes, whose identically vanishing phi
+derivatives the compiler removes), the double
 precision fadd / fsub / fmul / fdiv instructions (an fma or fmuladd call
 counts 2) of the basic blocks that store nothing to global memory: that is
 the per-point arithmetic of Eqs. 7-15 after common-subexpression elimination,
@@ -33,9 +35,10 @@ def device_ir(src):
 
 
 def count(ir, kernel_prefix="_ZN4bhah11k_rhs_fusedILi"):
+    """{(coord, two_phi_planes): FP64 operations per point}"""
     res = {}
-    for m in re.finditer(r"define [^@]*@(" + re.escape(kernel_prefix) + r"(\d)E\S*)\(", ir):
-        name, c = m.group(1), int(m.group(2))
+    for m in re.finditer(r"define [^@]*@(" + re.escape(kernel_prefix) + r"(\d)ELb(\d)E\S*)\(", ir):
+        name, c = m.group(1), (int(m.group(2)), bool(int(m.group(3))))
         body = ir[m.start():ir.index("\n}\n", m.start())]
         total = 0
         for blk in re.split(r"\n(?=[\w.]+:)", body):
@@ -49,8 +52,8 @@ def count(ir, kernel_prefix="_ZN4bhah11k_rhs_fusedILi"):
 
 def main():
     ir = device_ir(os.path.join(HERE, "csrc", "rhs_fused.hip"))
-    for c, n in sorted(count(ir).items()):
-        print(f"{COORD_NAMES[c]}: {n} FP64 operations per point")
+    for (c, ax), n in sorted(count(ir).items()):
+        print(f"{COORD_NAMES[c]}{' (two phi planes)' if ax else ''}: {n} FP64 operations per point")
 
 
 if __name__ == "__main__":

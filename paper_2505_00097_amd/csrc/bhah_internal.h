@@ -93,6 +93,15 @@ inline bool tile_fits_periodic(int coord, const TileCfg& c) {
   return coord == BHAH_SINH_CYLINDRICAL ? c.ly == 0 : c.lx + c.ly == 6;
 }
 
+// The right-hand-side kernel is built per coordinate family and per phi
+// extent: a grid with exactly two interior phi planes (axisymmetric runs)
+// gets a variant that reads each phi stencil as its two planes and drops the
+// phi derivatives that vanish identically there. Variant = 2 coord + that.
+constexpr int NVAR = 6;
+__host__ __device__ inline int rhs_variant(int coord, int N1, int N2) {
+  return 2 * coord + ((coord == BHAH_SINH_CYLINDRICAL ? N1 : N2) == 2 ? 1 : 0);
+}
+
 struct TileMap {
   int lx, ly;
   int tx, ty, tz;  // tiles along i0, i1, i2
@@ -115,13 +124,13 @@ struct BatchJob {
   double* gdst[5];
 };
 
-// Work list header: the (job, tile) list of coordinate family c starts at
-// tile_off[c] and holds n_tiles[c] entries; the (job, chunk of 256 ghost
+// Work list header: the (job, tile) list of kernel variant v (rhs_variant)
+// starts at tile_off[v] and holds n_tiles[v] entries; the (job, chunk of 256 ghost
 // points) list of ghost list w (as BatchJob::gh) starts at chunk_off[w] and
 // holds n_chunks[w] entries.
 struct BatchHdr {
-  int n_tiles[3];
-  int tile_off[3];
+  int n_tiles[NVAR];
+  int tile_off[NVAR];
   int n_chunks[2];
   int chunk_off[2];
 };
@@ -198,7 +207,7 @@ int launch_brill_lindquist(const GridDev& G, int n, const double* m, const doubl
 void launch_rhs_fused(const GridDev& G, double eta, const double* y, double* aux, const StageArgs& st,
                       hipStream_t s, const TileCfg& cfg);
 TileMap make_tilemap(const GridDev& G, int lx, int ly, int band);
-void launch_rhs_batch(int coord, const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage,
+void launch_rhs_batch(int variant, const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage,
                       double eta, int blocks, hipStream_t s);
 void launch_ghosts_batch(const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage, int which,
                          int blocks, hipStream_t s);

@@ -118,7 +118,7 @@ int Engine::ensure_device(hipStream_t s) {
 void Engine::drop_graphs() {
   for (auto& kv : graphs_) (void)hipGraphExecDestroy(kv.second);
   graphs_.clear();
-  for (int f = 0; f < 3; f++) fam_in_graphs_[f] = false;
+  for (int f = 0; f < NVAR; f++) fam_in_graphs_[f] = false;
 }
 
 // Fill the host blob: header, job table (all jobs) and work lists of the
@@ -184,11 +184,12 @@ void Engine::build_blob(const std::vector<TileCfg>& cfg, const std::vector<int>&
     b.gdst[4] = nullptr;
   }
   int pos = 0;
-  for (int f = 0; f < 3; f++) {
+  for (int f = 0; f < NVAR; f++) {
     hdr->tile_off[f] = pos;
     for (int r = 0; r < repeat; r++)
       for (int j : sel) {
-        if (jobs_[j].g->params.coord != f) continue;
+        const GridDev& G = jobs_[j].g->dev;
+        if (rhs_variant(G.coord, G.N1, G.N2) != f) continue;
         for (int t = 0; t < maps[j].ntiles; t++) tiles[pos++] = int2{j, t};
       }
     hdr->n_tiles[f] = pos - hdr->tile_off[f];
@@ -237,15 +238,15 @@ int Engine::time_class(const SizeClass& c, const TileCfg& cfg, hipStream_t s, do
   const BatchJob* dj = (const BatchJob*)(d_blob_ + L.jobs);
   const BatchHdr* dh = (const BatchHdr*)d_blob_;
   const int2* dt = (const int2*)(d_blob_ + L.tiles);
-  const int coord = std::get<0>(c);
+  const int variant = rhs_variant(std::get<0>(c), std::get<2>(c), std::get<3>(c));
   hipEvent_t e0, e1;
   if ((rc = check_hip(hipEventCreate(&e0), "hipEventCreate"))) return rc;
   if ((rc = check_hip(hipEventCreate(&e1), "hipEventCreate"))) { (void)hipEventDestroy(e0); return rc; }
   const int reps = 3;
   const int blocks = rhs_grid();
-  launch_rhs_batch(coord, dj, dh, dt, 4, gp_.eta, blocks, s);
+  launch_rhs_batch(variant, dj, dh, dt, 4, gp_.eta, blocks, s);
   (void)hipEventRecord(e0, s);
-  for (int r = 0; r < reps; r++) launch_rhs_batch(coord, dj, dh, dt, 4, gp_.eta, blocks, s);
+  for (int r = 0; r < reps; r++) launch_rhs_batch(variant, dj, dh, dt, 4, gp_.eta, blocks, s);
   (void)hipEventRecord(e1, s);
   rc = check_hip(hipEventSynchronize(e1), "tile timing");
   float ms = 0.f;
@@ -298,7 +299,7 @@ int Engine::capture(int nsteps, hipStream_t s, hipGraphExec_t* out) {
   // phi index are filled; the last stage of the last step fills all of them.
   for (int k = 0; k < nsteps; k++)
     for (int stage = 0; stage < 4; stage++) {
-      for (int f = 0; f < 3; f++)
+      for (int f = 0; f < NVAR; f++)
         if (fam_present_[f]) launch_rhs_batch(f, dj, dh, dt, stage, gp_.eta, rhs_blocks_, cap_stream_);
       const int which = stage == 3 && k == nsteps - 1 ? 1 : 0;
       launch_ghosts_batch(dj, dh, dc, stage, which, ghost_blocks_, cap_stream_);
@@ -313,7 +314,7 @@ int Engine::capture(int nsteps, hipStream_t s, hipGraphExec_t* out) {
   }
   rc = check_hip(hipGraphInstantiate(out, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
   (void)hipGraphDestroy(graph);
-  for (int f = 0; f < 3; f++) fam_in_graphs_[f] = fam_present_[f];
+  for (int f = 0; f < NVAR; f++) fam_in_graphs_[f] = fam_present_[f];
   return rc;
 }
 
@@ -330,7 +331,7 @@ int Engine::step(int nsteps, hipStream_t s) {
     if ((rc = upload(s))) return rc;
     dirty_ = false;
   }
-  for (int f = 0; f < 3; f++)
+  for (int f = 0; f < NVAR; f++)
     if (fam_present_[f] && !fam_in_graphs_[f]) drop_graphs();
   while (nsteps > 0) {
     const int k = std::min(nsteps, graph_steps_);

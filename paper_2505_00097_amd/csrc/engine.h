@@ -1,9 +1,9 @@
 // engine.h -- advancing an ensemble of independent grids together.
 //
-// The engine owns a device work description (job table + per-family (job,
+// The engine owns a device work description (job table + per-variant (job,
 // tile) lists + (job, ghost chunk) list, uploaded as one blob) and a cache of
 // instantiated hipGraphs, one per step count, each replaying
-// steps x 4 stages x [batched RHS kernel per coordinate family, batched ghost
+// steps x 4 stages x [batched RHS kernel per kernel variant, batched ghost
 // kernel]. The graphs read the blob at run time, so a changed job set only
 // needs a new upload, not a new graph. Tile shapes are chosen per size class
 // (coordinate family + interior extents) by timing candidates on the jobs
@@ -90,8 +90,8 @@ class Engine {
   int cap_jobs_ = 0, cap_tiles_ = 0, cap_chunks_ = 0;
   hipEvent_t upload_done_ = nullptr;
   int n_tiles_ = 0, n_chunks_ = 0;
-  bool fam_present_[3] = {false, false, false};
-  bool fam_in_graphs_[3] = {false, false, false};
+  bool fam_present_[NVAR] = {};    // kernel variants with tiles in some blob
+  bool fam_in_graphs_[NVAR] = {};  // ... and in the captured graphs
 
   int rhs_blocks_ = 0, ghost_blocks_ = 0;
   int blocks_per_cu_ = 4;

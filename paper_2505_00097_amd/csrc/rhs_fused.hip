@@ -40,12 +40,38 @@ struct Upwind2 {
 
 #define BHAH_PHASE_BARRIER() __builtin_amdgcn_sched_barrier(0)
 
+// Two-plane phi (AX): with exactly two interior phi planes the wrapped
+// offsets +-1 and +-3 land on the other plane and +-2 on the point's own, so
+// a phi stencil reads two values, every centred phi first derivative and
+// every mixed derivative involving phi vanishes identically (the grouped
+// differences of equal values), and the upwinded phi stencil reduces to the
+// two planes. The arithmetic on the values read is unchanged.
+
+// axis gather along K; along phi on a two-plane grid only the two planes are
+// read
+template <int K, int PD, bool AX>
+__device__ __forceinline__ void gather_axis_ax(const Pt& P, int g, double v[5]) {
+  if constexpr (AX && K == PD) {
+    const double c = P.at(g, 0, 0, 0), o = P.ax<K>(g, 1);
+    v[0] = c; v[1] = o; v[2] = c; v[3] = o; v[4] = c;
+  } else {
+    gather_axis<K>(P, g, v);
+  }
+}
+
 // compile-time dispatch of the gathers on a (compile-time after unrolling)
 // direction index
+template <int PD, bool AX>
 __device__ __forceinline__ void gather_axis_k(const Pt& P, int g, int k, double v[5]) {
-  if (k == 0) gather_axis<0>(P, g, v);
-  else if (k == 1) gather_axis<1>(P, g, v);
-  else gather_axis<2>(P, g, v);
+  if (k == 0) gather_axis_ax<0, PD, AX>(P, g, v);
+  else if (k == 1) gather_axis_ax<1, PD, AX>(P, g, v);
+  else gather_axis_ax<2, PD, AX>(P, g, v);
+}
+// value three points upwind along k (the fourth point of the shifted stencil)
+template <int PD, bool AX>
+__device__ __forceinline__ double upwind3(const Pt& P, int g, int k, const unsigned (&v3)[3], const double v[5]) {
+  if (AX && k == PD) return v[1];
+  return gf_ld(P.y, P.sgf, g, v3[k], 0);
 }
 __device__ __forceinline__ void gather_cross_kl(const Pt& P, int g, int k, int l, double v[16]) {
   if (k == 0 && l == 1) gather_cross<0, 1>(P, g, v);
@@ -54,7 +80,7 @@ __device__ __forceinline__ void gather_cross_kl(const Pt& P, int g, int k, int l
 }
 
 // upwinded advection of N gridfunctions in one batch of loads
-template <int N>
+template <int N, int PD, bool AX>
 __device__ __forceinline__ void advect_batch(const Pt& P, const int (&gl)[N], const Upwind2& U, double (&out)[N]) {
   double f0[N], fp[N][3], fm[N][3], f2[N][3], f3[N][3];
 #pragma unroll
@@ -64,9 +90,15 @@ __device__ __forceinline__ void advect_batch(const Pt& P, const int (&gl)[N], co
 #pragma unroll
     for (int k = 0; k < 3; k++) {
       fp[t][k] = gf_ld(P.y, P.sgf, g, U.vp[k], 0);
-      fm[t][k] = gf_ld(P.y, P.sgf, g, U.vm[k], 0);
-      f2[t][k] = gf_ld(P.y, P.sgf, g, U.v2[k], 0);
-      f3[t][k] = gf_ld(P.y, P.sgf, g, U.v3[k], 0);
+      if (AX && k == PD) {  // two phi planes: +-1, +-3 are the other plane, +-2 this one
+        fm[t][k] = fp[t][k];
+        f2[t][k] = f0[t];
+        f3[t][k] = fp[t][k];
+      } else {
+        fm[t][k] = gf_ld(P.y, P.sgf, g, U.vm[k], 0);
+        f2[t][k] = gf_ld(P.y, P.sgf, g, U.v2[k], 0);
+        f3[t][k] = gf_ld(P.y, P.sgf, g, U.v3[k], 0);
+      }
     }
   }
   BHAH_PHASE_BARRIER();
@@ -97,10 +129,11 @@ enum { PK_PC = 0, PK_QS = 6, PK_Y = 9, PK_ZA = 15, PK_BV = 16, PK_BD = 19, PK_RT
        PK_DH = PK_OUT, PK_D1 = 55, PK_ADV = 70 };
 static_assert(PK_ADV + 8 == PARK && PK_DH + 18 <= PK_OUT + G_VETU0, "park layout");
 
-template <int C>
+template <int C, bool AX>
 __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const double* __restrict__ y,
                                             const StageArgs& st, int i0, int i1, int i2, unsigned q,
                                             double* __restrict__ aux, double* __restrict__ park) {
+  constexpr int PD = C == BHAH_SINH_CYLINDRICAL ? 1 : 2;  // the periodic (phi) direction
   // park[v * 64] is this thread's slot v (lane-consecutive, bank-conflict free)
   auto put = [&](int v, double x) { park[v * 64] = x; };
   auto get = [&](int v) { return park[v * 64]; };
@@ -180,8 +213,8 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
           double v[11][5], f3[11];
 #pragma unroll
           for (int t = 0; t < 11; t++) {
-            gather_axis_k(P, G11[t], k, v[t]);
-            f3[t] = gf_ld(P.y, P.sgf, G11[t], U.v3[k], 0);
+            gather_axis_k<PD, AX>(P, G11[t], k, v[t]);
+            f3[t] = upwind3<PD, AX>(P, G11[t], k, U.v3, v[t]);
           }
           BHAH_PHASE_BARRIER();
           const bool up = vet[k] > 0.0;
@@ -196,10 +229,13 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
           // the same stencil values give the first derivatives along k
 #pragma unroll
           for (int t = 0; t < 11; t++) {
-            const double d1 = d1_axis(v[t], sp.i12h[k]);
+            const double d1 = AX && k == PD ? 0.0 : d1_axis(v[t], sp.i12h[k]);
             const int slot = t < 6 ? PK_DH + 3 * t : (t == 6 ? PK_D1 + 9 : (t == 7 ? PK_D1 + 12 : PK_D1 + 3 * (t - 8)));
             put(slot + k, d1);
           }
+        } else if (AX && (k == PD || l == PD)) {
+#pragma unroll
+          for (int t = 0; t < 11; t++) dd[t] = 0.0;
         } else {
 #pragma unroll
           for (int t0 = 0; t0 < 11; t0 += 4) {
@@ -405,8 +441,8 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
       for (int i = 0; i < 3; i++)
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-          gather_axis_k(P, G_LAMU0 + i, k, v[i][k]);
-          f3[i][k] = gf_ld(P.y, P.sgf, G_LAMU0 + i, U.v3[k], 0);
+          gather_axis_k<PD, AX>(P, G_LAMU0 + i, k, v[i][k]);
+          f3[i][k] = upwind3<PD, AX>(P, G_LAMU0 + i, k, U.v3, v[i][k]);
         }
       BHAH_PHASE_BARRIER();
 #pragma unroll
@@ -418,7 +454,7 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
           const double fp = up ? v[i][k][3] : v[i][k][1], fm = up ? v[i][k][1] : v[i][k][3];
           const double f2 = up ? v[i][k][4] : v[i][k][0], f0 = v[i][k][2];
           a += U.w[k] * (3.0 * (fp - fm) + 10.0 * (fp - f0) - 6.0 * (f2 - fp) + (f3[i][k] - fp));
-          dlam[i][k] = d1_axis(v[i][k], sp.i12h[k]);
+          dlam[i][k] = AX && k == PD ? 0.0 : d1_axis(v[i][k], sp.i12h[k]);
         }
         put(PK_OUT + G_LAMU0 + i, a);
       }
@@ -484,7 +520,7 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
   {
     constexpr int GA[5] = {G_ADD00, G_ADD00 + 1, G_ADD00 + 2, G_ADD00 + 3, G_ADD00 + 4};
     double a5[5];
-    advect_batch<5>(P, GA, U, a5);
+    advect_batch<5, PD, AX>(P, GA, U, a5);
 #pragma unroll
     for (int t = 0; t < 5; t++) put(PK_OUT + GA[t], a5[t]);
   }
@@ -494,10 +530,10 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
     double v[3][5], f3[3];
 #pragma unroll
     for (int k = 0; k < 3; k++) {
-      gather_axis_k(P, G_TRK, k, v[k]);
-      f3[k] = gf_ld(P.y, P.sgf, G_TRK, U.v3[k], 0);
+      gather_axis_k<PD, AX>(P, G_TRK, k, v[k]);
+      f3[k] = upwind3<PD, AX>(P, G_TRK, k, U.v3, v[k]);
     }
-    advect_batch<4>(P, GB, U, a4);
+    advect_batch<4, PD, AX>(P, GB, U, a4);
 #pragma unroll
     for (int t = 0; t < 4; t++) put(PK_OUT + GB[t], a4[t]);
     double advK = 0.0;
@@ -507,7 +543,7 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
       const double fp = up ? v[k][3] : v[k][1], fm = up ? v[k][1] : v[k][3];
       const double f2 = up ? v[k][4] : v[k][0], f0 = v[k][2];
       advK += U.w[k] * (3.0 * (fp - fm) + 10.0 * (fp - f0) - 6.0 * (f2 - fp) + (f3[k] - fp));
-      dK[k] = d1_axis(v[k], sp.i12h[k]);
+      dK[k] = AX && k == PD ? 0.0 : d1_axis(v[k], sp.i12h[k]);
     }
     put(PK_OUT + G_TRK, advK);
   }
@@ -778,7 +814,7 @@ __device__ __forceinline__ bool tile_point(const GridDev& G, const TileMap& T, i
 // multiple of the XCD count, block b runs on XCD b % nxcd
 __device__ __forceinline__ int xcd_remap(int b, int per) { return (b % BHAH_NXCD) * per + b / BHAH_NXCD; }
 
-template <int C>
+template <int C, bool AX>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
 k_rhs_fused(GridDev G, TileMap T, double eta, const double* __restrict__ y, StageArgs st,
             double* __restrict__ aux) {
@@ -789,18 +825,18 @@ k_rhs_fused(GridDev G, TileMap T, double eta, const double* __restrict__ y, Stag
   if (!tile_point(G, T, w, (int)threadIdx.x, i0, i1, i2)) return;
   const unsigned q = (unsigned)(i0 + G.s1 * i1 + G.s2 * i2);
   __shared__ double park[PARK * 64];
-  fused_point<C>(G, eta, y, st, i0, i1, i2, q, aux, park + threadIdx.x);
+  fused_point<C, AX>(G, eta, y, st, i0, i1, i2, q, aux, park + threadIdx.x);
 }
 
 // Persistent form for ensembles: a fixed grid of blocks (a multiple of the XCD
-// count) strides over one coordinate family's (job, tile) work list; every
+// count) strides over one kernel variant's (job, tile) work list; every
 // point runs the same fused_point as above.
-template <int C>
+template <int C, bool AX>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
 k_rhs_batch(const BatchJob* __restrict__ jobs, const BatchHdr* __restrict__ hdr, const int2* __restrict__ work,
             int stage, double eta) {
-  const int n = hdr->n_tiles[C];
-  const int2* wl = work + hdr->tile_off[C];
+  const int n = hdr->n_tiles[2 * C + AX];
+  const int2* wl = work + hdr->tile_off[2 * C + AX];
   const int per = (n + BHAH_NXCD - 1) / BHAH_NXCD;
   __shared__ double park[PARK * 64];
   for (int t = (int)blockIdx.x; t < per * BHAH_NXCD; t += (int)gridDim.x) {
@@ -813,7 +849,7 @@ k_rhs_batch(const BatchJob* __restrict__ jobs, const BatchHdr* __restrict__ hdr,
     if (!tile_point(G, J->T, wk.y, (int)threadIdx.x, i0, i1, i2)) continue;
     const unsigned q = (unsigned)(i0 + G.s1 * i1 + G.s2 * i2);
     const StageArgs st = J->st[stage];
-    fused_point<C>(G, eta, J->in[stage], st, i0, i1, i2, q, nullptr, park + threadIdx.x);
+    fused_point<C, AX>(G, eta, J->in[stage], st, i0, i1, i2, q, nullptr, park + threadIdx.x);
   }
 }
 
@@ -835,33 +871,29 @@ void launch_rhs_fused(const GridDev& G, double eta, const double* y, double* aux
   const TileCfg cfg = tile_fits_periodic(G.coord, cfg_in) ? cfg_in : TileCfg{6, 0, cfg_in.band};
   const TileMap T = make_tilemap(G, cfg.lx, cfg.ly, cfg.band);
   const int per = (T.ntiles + BHAH_NXCD - 1) / BHAH_NXCD;
-  const dim3 g(per * BHAH_NXCD);
-  switch (G.coord) {
-    case BHAH_SINH_SPHERICAL:
-      hipLaunchKernelGGL(k_rhs_fused<BHAH_SINH_SPHERICAL>, g, dim3(64), 0, s, G, T, eta, y, st, aux);
-      break;
-    case BHAH_SINH_CYLINDRICAL:
-      hipLaunchKernelGGL(k_rhs_fused<BHAH_SINH_CYLINDRICAL>, g, dim3(64), 0, s, G, T, eta, y, st, aux);
-      break;
-    default:
-      hipLaunchKernelGGL(k_rhs_fused<BHAH_SPHERICAL>, g, dim3(64), 0, s, G, T, eta, y, st, aux);
-      break;
+  const dim3 g(per * BHAH_NXCD), b(64);
+  constexpr int SS = BHAH_SINH_SPHERICAL, SC = BHAH_SINH_CYLINDRICAL, SP = BHAH_SPHERICAL;
+  switch (rhs_variant(G.coord, G.N1, G.N2)) {
+    case 2 * SS: hipLaunchKernelGGL((k_rhs_fused<SS, false>), g, b, 0, s, G, T, eta, y, st, aux); break;
+    case 2 * SS + 1: hipLaunchKernelGGL((k_rhs_fused<SS, true>), g, b, 0, s, G, T, eta, y, st, aux); break;
+    case 2 * SC: hipLaunchKernelGGL((k_rhs_fused<SC, false>), g, b, 0, s, G, T, eta, y, st, aux); break;
+    case 2 * SC + 1: hipLaunchKernelGGL((k_rhs_fused<SC, true>), g, b, 0, s, G, T, eta, y, st, aux); break;
+    case 2 * SP: hipLaunchKernelGGL((k_rhs_fused<SP, false>), g, b, 0, s, G, T, eta, y, st, aux); break;
+    default: hipLaunchKernelGGL((k_rhs_fused<SP, true>), g, b, 0, s, G, T, eta, y, st, aux); break;
   }
 }
 
-void launch_rhs_batch(int coord, const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage,
+void launch_rhs_batch(int variant, const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage,
                       double eta, int blocks, hipStream_t s) {
   const dim3 g(blocks), b(64);
-  switch (coord) {
-    case BHAH_SINH_SPHERICAL:
-      hipLaunchKernelGGL(k_rhs_batch<BHAH_SINH_SPHERICAL>, g, b, 0, s, jobs, hdr, work, stage, eta);
-      break;
-    case BHAH_SINH_CYLINDRICAL:
-      hipLaunchKernelGGL(k_rhs_batch<BHAH_SINH_CYLINDRICAL>, g, b, 0, s, jobs, hdr, work, stage, eta);
-      break;
-    default:
-      hipLaunchKernelGGL(k_rhs_batch<BHAH_SPHERICAL>, g, b, 0, s, jobs, hdr, work, stage, eta);
-      break;
+  constexpr int SS = BHAH_SINH_SPHERICAL, SC = BHAH_SINH_CYLINDRICAL, SP = BHAH_SPHERICAL;
+  switch (variant) {
+    case 2 * SS: hipLaunchKernelGGL((k_rhs_batch<SS, false>), g, b, 0, s, jobs, hdr, work, stage, eta); break;
+    case 2 * SS + 1: hipLaunchKernelGGL((k_rhs_batch<SS, true>), g, b, 0, s, jobs, hdr, work, stage, eta); break;
+    case 2 * SC: hipLaunchKernelGGL((k_rhs_batch<SC, false>), g, b, 0, s, jobs, hdr, work, stage, eta); break;
+    case 2 * SC + 1: hipLaunchKernelGGL((k_rhs_batch<SC, true>), g, b, 0, s, jobs, hdr, work, stage, eta); break;
+    case 2 * SP: hipLaunchKernelGGL((k_rhs_batch<SP, false>), g, b, 0, s, jobs, hdr, work, stage, eta); break;
+    default: hipLaunchKernelGGL((k_rhs_batch<SP, true>), g, b, 0, s, jobs, hdr, work, stage, eta); break;
   }
 }
 
