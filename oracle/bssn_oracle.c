@@ -19,7 +19,9 @@
  *   - RHS = Eqs. 7-15 with Eq. 12 (Sec. 2.1), unrescaled/rescaled per Sec. 2.2;
  *   - boundary fill after every RK substage: outer extrapolation, then inner
  *     parity copies (Sec. 3, ordered boundary steps);
- *   - classical RK4 (Sec. 4.2.1 footnote).
+ *   - classical RK4 (Sec. 4.2.1 footnote), or the three-stage strong-
+ *     stability-preserving Runge-Kutta scheme the production head-on run of
+ *     Sec. 4.2 uses (SSPRK3 of Gottlieb, Shu and Tadmor, cited there).
  * Readings where the paper is silent or garbled are marked "Reading:".
  *
  * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared.
@@ -1101,6 +1103,58 @@ int oracle_rk4_step(const oracle_params* p, double eta, double dt, double* y) {
   }
   for (int s = 0; s < 4; s++) free(k[s]);
   free(ys); free(kind); free(src); free(par);
+  return rc;
+}
+
+/* SSPRK3 (Sec. 4.2, the scheme of the Gottlieb-Shu-Tadmor reference), in
+ * its convex-combination form of forward-Euler steps, with the ghost fill
+ * after each stage as for RK4:
+ *   y1 = y_n + dt f(y_n);
+ *   y2 = 3/4 y_n + 1/4 (y1 + dt f(y1));
+ *   y_n+1 = 1/3 y_n + 2/3 (y2 + dt f(y2)).  Interior points only.          */
+int oracle_ssprk3_step(const oracle_params* p, double eta, double dt, double* y) {
+  Grid G;
+  if (grid_setup(p, &G)) return -1;
+  const long long n = NGF * G.np;
+  double* k = (double*)calloc((size_t)n, sizeof(double));
+  double* y1 = (double*)malloc(sizeof(double) * n);
+  double* y2 = (double*)malloc(sizeof(double) * n);
+  int* kind = (int*)malloc(sizeof(int) * G.np);
+  int* src = (int*)malloc(sizeof(int) * G.np);
+  int* par = (int*)malloc(sizeof(int) * G.np);
+  int rc = build_maps(&G, kind, src, par);
+  if (rc == 0) {
+    /* stage 1: forward Euler from y_n */
+    memcpy(y1, y, sizeof(double) * n);
+    oracle_rhs(p, eta, y, k);
+    for (long long t = 0; t < G.np; t++)
+      if (kind[t] == 0)
+        for (int g = 0; g < NGF; g++) {
+          const long long e = g * G.np + t;
+          y1[e] = y[e] + dt * k[e];
+        }
+    apply_bcs_with_maps(&G, kind, src, par, y1);
+    /* stage 2: average of y_n and a forward-Euler step from y1 */
+    memcpy(y2, y1, sizeof(double) * n);
+    oracle_rhs(p, eta, y1, k);
+    for (long long t = 0; t < G.np; t++)
+      if (kind[t] == 0)
+        for (int g = 0; g < NGF; g++) {
+          const long long e = g * G.np + t;
+          y2[e] = 0.75 * y[e] + 0.25 * (y1[e] + dt * k[e]);
+        }
+    apply_bcs_with_maps(&G, kind, src, par, y2);
+    /* stage 3: average of y_n and a forward-Euler step from y2 */
+    oracle_rhs(p, eta, y2, k);
+    for (long long t = 0; t < G.np; t++)
+      if (kind[t] == 0)
+        for (int g = 0; g < NGF; g++) {
+          const long long e = g * G.np + t;
+          y[e] = (1.0 / 3.0) * y[e] + (2.0 / 3.0) * (y2[e] + dt * k[e]);
+        }
+    apply_bcs_with_maps(&G, kind, src, par, y);
+  }
+  free(k); free(y1); free(y2); free(kind); free(src); free(par);
   return rc;
 }
 

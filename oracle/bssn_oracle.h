@@ -86,6 +86,9 @@ int oracle_constraints(const oracle_params* p, const double* y, double* H, doubl
 /* One classical RK4 step in place (ghosts refilled after each stage). */
 int oracle_rk4_step(const oracle_params* p, double eta, double dt, double* y);
 
+/* One SSPRK3 step in place (ghosts refilled after each stage). */
+int oracle_ssprk3_step(const oracle_params* p, double eta, double dt, double* y);
+
 /* Finite-difference operators applied to a single gridfunction f (n_points
  * doubles) at flat index idx: d1[k], d2[3*k+l], upwinded U+[k], U-[k]. */
 int oracle_fd_point(const oracle_params* p, const double* f, long long idx, double d1[3],

@@ -54,6 +54,7 @@ def lib():
             "oracle_rhs_points": (ctypes.c_int, [P, ctypes.c_double, dp, ctypes.c_int, llp, dp, dp]),
             "oracle_constraints": (ctypes.c_int, [P, dp, dp, dp, dp]),
             "oracle_rk4_step": (ctypes.c_int, [P, ctypes.c_double, ctypes.c_double, dp]),
+            "oracle_ssprk3_step": (ctypes.c_int, [P, ctypes.c_double, ctypes.c_double, dp]),
             "oracle_fd_point": (ctypes.c_int, [P, dp, ctypes.c_longlong, dp, dp, dp, dp]),
             "oracle_num_threads": (ctypes.c_int, []),
         }
@@ -190,6 +191,12 @@ class Grid:
         rc = lib().oracle_rk4_step(ctypes.byref(self.p), float(eta), float(dt), _dp(y))
         if rc:
             raise RuntimeError("oracle_rk4_step failed")
+        return y
+
+    def ssprk3_step(self, y, dt, eta=2.0):
+        rc = lib().oracle_ssprk3_step(ctypes.byref(self.p), float(eta), float(dt), _dp(y))
+        if rc:
+            raise RuntimeError("oracle_ssprk3_step failed")
         return y
 
     def fd_point(self, f, idx):

@@ -257,6 +257,78 @@ def test_rk4_is_fourth_order_on_uniform_data():
     assert 13.0 < errs[1] / errs[2] < 19.0, errs
 
 
+# ------------------------------------------------------------- SSPRK3 order
+def _uniform_reference(K0, T):
+    from scipy.integrate import solve_ivp
+
+    def f(t, u):
+        K, a, W = u
+        return [a * K * K / 3.0, -2.0 * a * K, a * K * W / 3.0]
+    return solve_ivp(f, (0, T), [K0, 1.0, 1.0], method="DOP853", rtol=2.5e-14, atol=1e-15).y[:, -1]
+
+
+def _uniform_state(g, K0):
+    y = g.state()
+    y[an.GF["cf"]] = 1.0
+    y[an.GF["alpha"]] = 1.0
+    y[an.GF["trK"]] = K0
+    return y
+
+
+def test_ssprk3_is_third_order_on_uniform_data():
+    """The uniform-data ODEs of the RK4 pin above (Eqs. 9, 10, 13): the
+    SSPRK3 scheme's global error falls by 2^3 when dt halves."""
+    K0, T = 0.6, 0.8
+    ref = _uniform_reference(K0, T)
+    g = orc.Grid(an.SINH_SPHERICAL, (6, 4, 2), ampl=(2.0,) * 3)
+    errs = []
+    for nsteps in (8, 16, 32):
+        y = _uniform_state(g, K0)
+        for _ in range(nsteps):
+            g.ssprk3_step(y, T / nsteps, eta=2.0)
+        assert np.all(y[an.GF["trK"]] == y[an.GF["trK"]].flat[0])
+        u = [y[an.GF[n]].flat[0] for n in ("trK", "alpha", "cf")]
+        errs.append(np.max(np.abs(np.array(u) - ref)))
+    assert 6.5 < errs[0] / errs[1] < 9.5, errs
+    assert 6.5 < errs[1] / errs[2] < 9.5, errs
+
+
+def test_ssprk3_single_step_error_is_fourth_order():
+    """One step of a third-order scheme is exact to O(dt^3): its error falls
+    by 2^4 when dt halves. A stage weight off by anything (3/4, 1/4, 1/3,
+    2/3) breaks this."""
+    K0 = 0.9
+    g = orc.Grid(an.SINH_SPHERICAL, (6, 4, 2), ampl=(2.0,) * 3)
+    errs = []
+    for dt in (0.2, 0.1, 0.05):
+        ref = _uniform_reference(K0, dt)
+        y = _uniform_state(g, K0)
+        g.ssprk3_step(y, dt, eta=2.0)
+        u = [y[an.GF[n]].flat[0] for n in ("trK", "alpha", "cf")]
+        errs.append(np.max(np.abs(np.array(u) - ref)))
+    assert 13.0 < errs[0] / errs[1] < 19.0, errs
+    assert 13.0 < errs[1] / errs[2] < 19.0, errs
+
+
+def test_ssprk3_and_rk4_agree_to_the_time_error_on_punctures():
+    """On Brill-Lindquist data both integrators solve the same semi-discrete
+    system: after a few steps their difference is of the size of the
+    time-discretisation error and falls by at least 2^3 when dt halves."""
+    g = orc.Grid(an.SINH_CYLINDRICAL, (10, 2, 20), ampl=(4.0,) * 3, sinhw=(0.3,) * 3)
+    y0 = g.brill_lindquist([0.5, 0.5], [(0, 0, 0.6), (0, 0, -0.6)])
+    I = g.interior()
+    diffs = []
+    for n in (8, 16):
+        a, b = y0.copy(), y0.copy()
+        dt = 2 * g.dt() / n
+        for _ in range(n):
+            g.rk4_step(a, dt, eta=2.0)
+            g.ssprk3_step(b, dt, eta=2.0)
+        diffs.append(max(np.max(np.abs(a[k][I] - b[k][I])) / max(np.max(np.abs(a[k][I])), 1e-300)
+                         for k in range(an.NGF) if np.max(np.abs(a[k][I])) > 0))
+    assert diffs[0] < 1e-3 and diffs[0] / diffs[1] > 6.5, diffs
+
+
 # ------------------------------------- stationary strong field: Kerr-Schild
 def _kerr_schild_case(coord, N, ampl, w, M=1.0, c=(0.2, -0.1, 2.0)):
     (X0, X1, X2), x, E = an.mesh(coord, N, ampl, w)
