@@ -146,6 +146,32 @@ def make_grids(capi, jobs):
     return grids
 
 
+def run_ssprk3(capi, wl, stream, steps):
+    """The head-on workload advanced with SSPRK3, the integrator of the
+    paper's production head-on run (three right-hand sides per step)."""
+    import torch
+    w = wl.WORKLOADS["headon_sinhcylindrical_128x2x256"]
+    g = capi.Grid(w["coord"], w["N"], w["ampl"], w["sinhw"], w["cfl"])
+    y, ws = g.state(), g.workspace()
+    capi.set_initial_data_brill_lindquist(g.h, w["masses"], w["positions"], y, stream=stream)
+    capi.grid_tune(g.h, y, g.state(), eta=w["eta"], stream=stream)
+    for _ in range(10):
+        capi.ssprk3_step(g.h, y, ws, g.dt, eta=w["eta"], stream=stream)
+    ev = events(steps + 1)
+    ev[0].record(stream)
+    for s in range(steps):
+        capi.ssprk3_step(g.h, y, ws, g.dt, eta=w["eta"], stream=stream)
+        ev[s + 1].record(stream)
+    torch.cuda.synchronize()
+    step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    total_s = ev[0].elapsed_time(ev[-1]) / 1e3
+    n = g.info.n_interior
+    return {"workload": "headon_sinhcylindrical_128x2x256 with SSPRK3", "steps": steps,
+            "value": n * steps / total_s, "unit": UNIT, "ms_per_step": 1e3 * total_s / steps,
+            "p50_step_ms": percentile(step_ms, 50), "p99_step_ms": percentile(step_ms, 99),
+            "finite": bool(torch.isfinite(y).all().item())}
+
+
 def run_batched(capi, wl, stream, steps, seq_steps, graph_steps):
     """64 uneven head-on jobs: one batch advancing all of them `steps` RK4
     steps, against the same jobs advanced one at a time."""
@@ -345,6 +371,7 @@ def main():
                     help="admit while running jobs hold fewer interior points (0: no limit)")
     ap.add_argument("--study-steps", type=int, default=20)
     ap.add_argument("--no-paper-grids", action="store_true")
+    ap.add_argument("--ssprk3-steps", type=int, default=500)
     ap.add_argument("--no-probe-peaks", action="store_true",
                     help="skip measuring the device's FP64 FMA and HBM triad ceilings")
     args = ap.parse_args()
@@ -397,6 +424,10 @@ def main():
         probe = None if args.no_probe_peaks else capi.probe_peaks(stream)
 
         extras = {}
+        if args.ssprk3_steps > 0:
+            extras["ssprk3"] = run_ssprk3(capi, wl, stream, args.ssprk3_steps)
+            torch.cuda.empty_cache()
+            print(f"# ssprk3: {extras['ssprk3']['value']:.3e} pt-steps/s", file=sys.stderr, flush=True)
         if args.batched_steps > 0:
             extras["batched"] = run_batched(capi, wl, stream, args.batched_steps, args.batched_seq_steps,
                                             args.graph_steps)

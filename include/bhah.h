@@ -195,6 +195,17 @@ int bhah_bssn_rhs(const bhah_grid* g, const bhah_gauge_params* gp,
 int bhah_rk4_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt,
                   double* y, double* workspace, void* stream);
 
+/* One step of size dt of the three-stage strong-stability-preserving
+ * Runge-Kutta scheme that the production head-on run of Sec. 4.2 uses
+ * (Gottlieb, Shu and Tadmor), in place on y:
+ *   A = y + dt f(y); B = 3/4 y + 1/4 (A + dt f(A));
+ *   y <- 1/3 y + 2/3 (B + dt f(B)),
+ * with the boundary fill of Sec. 3 after every stage. Ghost handling,
+ * workspace (the first two thirds of info.workspace_doubles are used) and
+ * errors are as for bhah_rk4_step.                                          */
+int bhah_ssprk3_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt,
+                     double* y, double* workspace, void* stream);
+
 /* All three constraints at every interior point, centred 4th-order
  * differences: H of Eq. 16 (one gridfunction), the momentum constraint M^i of
  * Eq. 17 and C^i = Lambdabar^i - Delta^i (three gridfunctions each, rescaled

@@ -113,6 +113,7 @@ _SIGS = {
     "bhah_server_get_stats": (ctypes.c_int, [_vp, ctypes.POINTER(ServerStats)]),
     "bhah_server_destroy": (None, [_vp]),
     "bhah_probe_peaks": (ctypes.c_int, [_vp, _vp, _vp]),
+    "bhah_ssprk3_step": (ctypes.c_int, [_vp, ctypes.POINTER(GaugeParams), ctypes.c_double, _vp, _vp, _vp]),
 }
 
 
@@ -219,6 +220,12 @@ def rk4_step(h, y, workspace, dt, eta=2.0, stream=None):
     gp = gauge(eta)
     _check(lib().bhah_rk4_step(h, ctypes.byref(gp), float(dt), _ptr(y), _ptr(workspace), _stream(stream)),
            "bhah_rk4_step")
+
+
+def ssprk3_step(h, y, workspace, dt, eta=2.0, stream=None):
+    gp = gauge(eta)
+    _check(lib().bhah_ssprk3_step(h, ctypes.byref(gp), float(dt), _ptr(y), _ptr(workspace), _stream(stream)),
+           "bhah_ssprk3_step")
 
 
 def hamiltonian_constraint(h, y, H, stream=None):

@@ -68,7 +68,8 @@ struct GhostDev {
 
 // RK stage epilogue of the right-hand-side kernel: with rhs != nullptr the
 // right-hand side k is stored; otherwise out1 = base1 + c1 k and, if out2 is
-// set, out2 = base2 + c2 k, gridfunction by gridfunction.
+// set, out2 = base2 + c2 k, gridfunction by gridfunction. With base2 set but
+// no out2 the stage mixes two states: out1 = m1 base1 + m2 base2 + c1 k.
 struct StageArgs {
   double* rhs;
   const double* base1;
@@ -77,6 +78,7 @@ struct StageArgs {
   const double* base2;
   double* out2;
   double c2;
+  double m1, m2;
 };
 
 // Tile shape and walk of the right-hand-side kernel over one grid: tiles of
@@ -219,6 +221,9 @@ void launch_constraints(const GridDev& G, const double* y, double* H, double* Mo
 // array whose ghosts are filled after each stage.
 void rk4_stages(double dt, double* y, double* ws, long long n, StageArgs st[4], const double* in[4],
                 double* gdst[4]);
+// The same for the three stages of one SSPRK3 step (arrays A, B of ws).
+void ssprk3_stages(double dt, double* y, double* ws, long long n, StageArgs st[3], const double* in[3],
+                   double* gdst[3]);
 
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);

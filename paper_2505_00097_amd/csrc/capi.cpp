@@ -42,6 +42,20 @@ void rk4_stages(double dt, double* y, double* ws, long long n, StageArgs st[4], 
   gdst[0] = A; gdst[1] = B; gdst[2] = A; gdst[3] = y;
 }
 
+void ssprk3_stages(double dt, double* y, double* ws, long long n, StageArgs st[3], const double* in[3],
+                   double* gdst[3]) {
+  double* A = ws;
+  double* B = ws + n;
+  // SSPRK3 (Sec. 4.2, Gottlieb-Shu-Tadmor), each stage a convex combination
+  // of y_n and a forward-Euler step: A = y + dt k1; B = 3/4 y + 1/4 A +
+  // dt/4 k2; y_n+1 = 1/3 y + 2/3 B + 2/3 dt k3, boundary fill after each.
+  st[0] = StageArgs{nullptr, y, A, dt, nullptr, nullptr, 0.0, 0.0, 0.0};
+  st[1] = StageArgs{nullptr, y, B, 0.25 * dt, A, nullptr, 0.0, 0.75, 0.25};
+  st[2] = StageArgs{nullptr, y, y, (2.0 / 3.0) * dt, B, nullptr, 0.0, 1.0 / 3.0, 2.0 / 3.0};
+  in[0] = y; in[1] = A; in[2] = B;
+  gdst[0] = A; gdst[1] = B; gdst[2] = y;
+}
+
 static void free_device(bhah_grid* g) {
   for (int d = 0; d < 3; d++)
     if (g->d_tab[d]) (void)hipFree(g->d_tab[d]);
@@ -197,6 +211,22 @@ int bhah_rk4_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt, do
     launch_ghosts(k < 3 ? g->ghost_stage : g->ghost, gdst[k], g->dev.sgf, s);
   }
   return check_launch("bhah_rk4_step");
+}
+
+int bhah_ssprk3_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt, double* y, double* workspace,
+                     void* stream) {
+  if (!g || !gp || !y || !workspace) return fail(BHAH_EINVAL, "bhah_ssprk3_step: NULL argument");
+  if (gp->shift_variant != 0) return fail(BHAH_EINVAL, "bhah_ssprk3_step: shift_variant must be 0");
+  hipStream_t s = (hipStream_t)stream;
+  StageArgs st[3];
+  const double* in[3];
+  double* gdst[3];
+  ssprk3_stages(dt, y, workspace, g->info.state_doubles, st, in, gdst);
+  for (int k = 0; k < 3; k++) {
+    launch_rhs_fused(g->dev, gp->eta, in[k], nullptr, st[k], s, g->tile);
+    launch_ghosts(k < 2 ? g->ghost_stage : g->ghost, gdst[k], g->dev.sgf, s);
+  }
+  return check_launch("bhah_ssprk3_step");
 }
 
 int bhah_grid_set_tile(bhah_grid* g, int lx, int ly, int band) {

@@ -748,14 +748,15 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
     for (int g = 0; g < NGF; g++) st.rhs[g * G.sgf + q] = get(PK_OUT + g);
   } else {
     // Every base value is read before any result is stored. Within a stage
-    // the arrays never overlap (base1 is y or Cacc, out1 is A, B or y; base2
-    // and out2 are Cacc at the same point), but the compiler cannot know it
-    // and would otherwise put each load behind the stores before it.
-    const bool two = st.out2 != nullptr, same = st.base2 == st.base1;
+    // the arrays never overlap (RK4: base1 is y or Cacc, out1 is A, B or y;
+    // base2 and out2 are Cacc at the same point; SSPRK3 mixes y with A or B
+    // into B or y), but the compiler cannot know it and would otherwise put
+    // each load behind the stores before it.
+    const bool two = st.out2 != nullptr, mix = !two && st.base2 != nullptr, same = st.base2 == st.base1;
     double b1[NGF], b2[NGF];
 #pragma unroll
     for (int g = 0; g < NGF; g++) b1[g] = gf_ld(st.base1, G.sgf, g, q * 8u, 0);
-    if (two && !same) {
+    if ((two || mix) && !same) {
 #pragma unroll
       for (int g = 0; g < NGF; g++) b2[g] = gf_ld(st.base2, G.sgf, g, q * 8u, 0);
     } else {
@@ -763,12 +764,20 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
       for (int g = 0; g < NGF; g++) b2[g] = b1[g];
     }
     BHAH_PHASE_BARRIER();
+    if (mix) {
 #pragma unroll
-    for (int g = 0; g < NGF; g++) {
-      const long long e = g * G.sgf + q;
-      const double k = get(PK_OUT + g);
-      st.out1[e] = b1[g] + st.c1 * k;
-      if (two) st.out2[e] = b2[g] + st.c2 * k;
+      for (int g = 0; g < NGF; g++) {
+        const long long e = g * G.sgf + q;
+        st.out1[e] = st.m1 * b1[g] + st.m2 * b2[g] + st.c1 * get(PK_OUT + g);
+      }
+    } else {
+#pragma unroll
+      for (int g = 0; g < NGF; g++) {
+        const long long e = g * G.sgf + q;
+        const double k = get(PK_OUT + g);
+        st.out1[e] = b1[g] + st.c1 * k;
+        if (two) st.out2[e] = b2[g] + st.c2 * k;
+      }
     }
   }
   if (aux) {

@@ -85,6 +85,8 @@ def test_null_arguments_are_rejected():
     assert L.bhah_grid_create(None, None) == capi.EINVAL
     assert L.bhah_apply_bcs(None, None, None) == capi.EINVAL
     assert L.bhah_rk4_step(None, None, 0.0, None, None, None) == capi.EINVAL
+    assert L.bhah_ssprk3_step(None, None, 0.0, None, None, None) == capi.EINVAL
+    assert L.bhah_probe_peaks(None, None, None) == capi.EINVAL
     assert L.bhah_batch_create(None, 0, None, None, None) == capi.EINVAL
     assert L.bhah_server_create(None, None, None) == capi.EINVAL
     assert "NULL" in capi.last_error() or "bad argument" in capi.last_error()

@@ -237,6 +237,32 @@ def test_rk4_evolution_matches_oracle(name, m, pos, steps):
     assert np.max(np.abs(out - yo)) <= EVOL_TOL * np.max(np.abs(yo))
 
 
+@pytest.mark.parametrize("name,m,pos,steps", [
+    ("tiny", [1.0], [(0, 0, 0)], 100),
+    ("cyl_ragged", [0.5, 0.5], [(0, 0, 0.5), (0, 0, -0.5)], 60),
+    ("cyl_3d", [0.7, 0.3], [(0.3, 0.1, 0.6), (-0.2, 0, -0.5)], 40),
+])
+def test_ssprk3_evolution_matches_oracle(name, m, pos, steps):
+    """The SSPRK3 integrator (three stages, two of them mixing y_n with a
+    stage state in the kernel epilogue) against the oracle's."""
+    _print_case("evolve_ssprk3", name, steps)
+    from paper_2505_00097_amd import capi
+    g, og = _pair(name)
+    y = g.state()
+    capi.set_initial_data_brill_lindquist(g.h, m, pos, y)
+    ws = g.workspace()
+    yo = og.brill_lindquist(m, np.array(pos).reshape(-1, 3))
+    dt = og.dt()
+    for _ in range(steps):
+        capi.ssprk3_step(g.h, y, ws, dt, eta=2.0)
+        og.ssprk3_step(yo, dt, eta=2.0)
+    out = to_cpu(y)
+    err = gf_errors(out, yo, og.interior())
+    print("  err", fmt(orc.GF_NAMES, err), flush=True)
+    assert np.all(err <= EVOL_TOL), fmt(orc.GF_NAMES, err)
+    assert np.max(np.abs(out - yo)) <= EVOL_TOL * np.max(np.abs(yo))
+
+
 def test_headon_workload_100_steps_matches_oracle():
     """The head-on workload at full size (SinhCylindrical 128x2x256, two
     punctures), 100 RK4 steps with the tuned tile shape the benchmark uses
