@@ -17,6 +17,8 @@
  *   - every reference-metric quantity (S_i, its derivatives, Gammahat and its
  *     derivatives) is evaluated analytically (Sec. 2.2, Eq. 22);
  *   - RHS = Eqs. 7-15 with Eq. 12 (Sec. 2.1), unrescaled/rescaled per Sec. 2.2;
+ *   - optional Kreiss-Oliger dissipation added to each rescaled right-hand
+ *     side (Sec. 4.2, strengths for gauge and metric variables);
  *   - boundary fill after every RK substage: outer extrapolation, then inner
  *     parity copies (Sec. 3, ordered boundary steps);
  *   - classical RK4 (Sec. 4.2.1 footnote), or the three-stage strong-
@@ -476,6 +478,15 @@ static double fd_d11(const double* f, long long sk, long long sl, double hk, dou
 static double fd_up(const double* f, long long s, double h) {
   return (3.0 * (f[s] - f[-s]) + 10.0 * (f[s] - f[0]) - 6.0 * (f[2 * s] - f[s]) + (f[3 * s] - f[s])) /
          (12.0 * h);
+}
+/* Kreiss-Oliger operator along one direction (Sec. 4.2 names the strengths
+ * and the order: one above the finite-difference order). Reading: with the
+ * 4th-order stencils and three ghost layers here it is the radius-3 sixth
+ * difference, (1/64) h^5 (d/dx)^6 f = delta^6 f / (64 h), whose Fourier
+ * symbol -sin^6(theta/2)/h damps the grid-scale modes.                      */
+static double fd_ko(const double* f, long long s, double h) {
+  return ((f[3 * s] + f[-3 * s]) - 6.0 * (f[2 * s] + f[-2 * s]) + 15.0 * (f[s] + f[-s]) - 20.0 * f[0]) /
+         (64.0 * h);
 }
 static double fd_dn(const double* f, long long s, double h) {
   return (3.0 * (f[s] - f[-s]) + 10.0 * (f[0] - f[-s]) - 6.0 * (f[-s] - f[-2 * s]) + (f[-s] - f[-3 * s])) /
@@ -945,6 +956,19 @@ static void bssn_point(const Grid* G, double eta, const double* y, int i0, int i
   out->rhs[CF] = rhs_W;
   out->rhs[TRK] = rhs_K;
   out->rhs[ALPHA] = rhs_alpha;
+
+  /* ---- 14b. Kreiss-Oliger dissipation (Sec. 4.2) ---------------------- */
+  /* Reading: the dissipation is added to each rescaled right-hand side after
+   * the equations, with the gauge strength for alpha, vet^i and bet^i and
+   * the metric strength for the rest; the 3/4 d_t lambda^i inside bet^i's
+   * right-hand side above is the undissipated one.                          */
+  if (G->p.diss_gauge != 0.0 || G->p.diss_metric != 0.0)
+    for (int g = 0; g < NGF; g++) {
+      const int gauge = g == ALPHA || (g >= BETU0 && g <= BETU2) || (g >= VETU0 && g <= VETU2);
+      const double eps = gauge ? G->p.diss_gauge : G->p.diss_metric;
+      const double* f = y + g * np + q;
+      for (int k = 0; k < 3; k++) out->rhs[g] += eps * fd_ko(f, G->st[k], G->dxx[k]);
+    }
 
   /* ---- 15. constraints: Eq. 16 (H), Eq. 17 (M^i), C^i ------------------ */
   double Rtr = 0.0, dphi2 = 0.0, lap_phi = 0.0;

@@ -31,6 +31,9 @@ typedef struct {
   double ampl[3];  /* outer extent of the sinh (or linear) maps */
   double sinhw[3]; /* sinh widths */
   double cfl;
+  /* Kreiss-Oliger dissipation strengths (Sec. 4.2), 0 = off: diss_gauge for
+   * alpha, vet^i, bet^i; diss_metric for every other gridfunction. */
+  double diss_gauge, diss_metric;
 } oracle_params;
 
 /* 0 if the parameters describe a grid the oracle supports, -1 otherwise. */

@@ -23,7 +23,8 @@ SINH_SPHERICAL, SINH_CYLINDRICAL, SPHERICAL = 0, 1, 2
 class OracleParams(ctypes.Structure):
     _fields_ = [("coord", ctypes.c_int), ("N", ctypes.c_int * 3), ("ng", ctypes.c_int),
                 ("ampl", ctypes.c_double * 3), ("sinhw", ctypes.c_double * 3),
-                ("cfl", ctypes.c_double)]
+                ("cfl", ctypes.c_double), ("diss_gauge", ctypes.c_double),
+                ("diss_metric", ctypes.c_double)]
 
 
 _lib = None
@@ -76,8 +77,12 @@ def _dp(a):
 class Grid:
     """A grid description for the oracle (host arrays only)."""
 
-    def __init__(self, coord, N, ampl=(10.0, 10.0, 10.0), sinhw=(0.2, 0.2, 0.2), cfl=0.5, ng=3):
+    def __init__(self, coord, N, ampl=(10.0, 10.0, 10.0), sinhw=(0.2, 0.2, 0.2), cfl=0.5, ng=3,
+                 diss=(0.0, 0.0)):
+        """diss: Kreiss-Oliger strengths (gauge, metric); (0, 0) is off."""
         self.p = OracleParams()
+        self.p.diss_gauge = float(diss[0])
+        self.p.diss_metric = float(diss[1])
         self.p.coord = int(coord)
         for d in range(3):
             self.p.N[d] = int(N[d])
