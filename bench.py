@@ -146,27 +146,29 @@ def make_grids(capi, jobs):
     return grids
 
 
-def run_ssprk3(capi, wl, stream, steps):
+def run_ssprk3(capi, wl, stream, steps, diss=(0.0, 0.0)):
     """The head-on workload advanced with SSPRK3, the integrator of the
-    paper's production head-on run (three right-hand sides per step)."""
+    paper's production head-on run (three right-hand sides per step), with
+    optional Kreiss-Oliger dissipation (the run's strengths: 0.99, 0.3)."""
     import torch
     w = wl.WORKLOADS["headon_sinhcylindrical_128x2x256"]
     g = capi.Grid(w["coord"], w["N"], w["ampl"], w["sinhw"], w["cfl"])
     y, ws = g.state(), g.workspace()
     capi.set_initial_data_brill_lindquist(g.h, w["masses"], w["positions"], y, stream=stream)
-    capi.grid_tune(g.h, y, g.state(), eta=w["eta"], stream=stream)
+    capi.grid_tune(g.h, y, g.state(), eta=w["eta"], diss=diss, stream=stream)
     for _ in range(10):
-        capi.ssprk3_step(g.h, y, ws, g.dt, eta=w["eta"], stream=stream)
+        capi.ssprk3_step(g.h, y, ws, g.dt, eta=w["eta"], diss=diss, stream=stream)
     ev = events(steps + 1)
     ev[0].record(stream)
     for s in range(steps):
-        capi.ssprk3_step(g.h, y, ws, g.dt, eta=w["eta"], stream=stream)
+        capi.ssprk3_step(g.h, y, ws, g.dt, eta=w["eta"], diss=diss, stream=stream)
         ev[s + 1].record(stream)
     torch.cuda.synchronize()
     step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
     total_s = ev[0].elapsed_time(ev[-1]) / 1e3
     n = g.info.n_interior
-    return {"workload": "headon_sinhcylindrical_128x2x256 with SSPRK3", "steps": steps,
+    return {"workload": "headon_sinhcylindrical_128x2x256 with SSPRK3"
+                        + (", Kreiss-Oliger %g/%g" % diss if diss[0] or diss[1] else ""), "steps": steps,
             "value": n * steps / total_s, "unit": UNIT, "ms_per_step": 1e3 * total_s / steps,
             "p50_step_ms": percentile(step_ms, 50), "p99_step_ms": percentile(step_ms, 99),
             "finite": bool(torch.isfinite(y).all().item())}
@@ -426,8 +428,10 @@ def main():
         extras = {}
         if args.ssprk3_steps > 0:
             extras["ssprk3"] = run_ssprk3(capi, wl, stream, args.ssprk3_steps)
+            extras["ssprk3_dissipation"] = run_ssprk3(capi, wl, stream, args.ssprk3_steps, diss=(0.99, 0.3))
             torch.cuda.empty_cache()
-            print(f"# ssprk3: {extras['ssprk3']['value']:.3e} pt-steps/s", file=sys.stderr, flush=True)
+            print(f"# ssprk3: {extras['ssprk3']['value']:.3e} pt-steps/s, with dissipation "
+                  f"{extras['ssprk3_dissipation']['value']:.3e}", file=sys.stderr, flush=True)
         if args.batched_steps > 0:
             extras["batched"] = run_batched(capi, wl, stream, args.batched_steps, args.batched_seq_steps,
                                             args.graph_steps)

@@ -110,10 +110,18 @@ typedef struct {
 
 /* Gauge parameters: eta is the Gamma-driver damping of Eq. 15 (Sec. 4.1 uses
  * 2.0). shift_variant must be 0: dB^i/dt uses the full dLambdabar^i/dt of
- * Eq. 11 including its advection term.                                       */
+ * Eq. 11 including its advection term.
+ * diss_gauge, diss_metric: Kreiss-Oliger dissipation strengths (Sec. 4.2
+ * uses 0.99 and 0.3), >= 0, 0 = off. The term eps/(64 dxx^k) sum_k
+ * delta_k^6 f (the radius-3 sixth difference along each logical direction)
+ * is added to each rescaled right-hand side after Eqs. 7-15: diss_gauge for
+ * alpha, vet^i, bet^i, diss_metric for the other gridfunctions; bet^i's
+ * 3/4 dlambda^i/dt is the undissipated one.                                 */
 typedef struct {
   double eta;
   int shift_variant;
+  double diss_gauge;
+  double diss_metric;
 } bhah_gauge_params;
 
 typedef struct {

@@ -27,7 +27,8 @@ class GridParams(ctypes.Structure):
 
 
 class GaugeParams(ctypes.Structure):
-    _fields_ = [("eta", ctypes.c_double), ("shift_variant", ctypes.c_int)]
+    _fields_ = [("eta", ctypes.c_double), ("shift_variant", ctypes.c_int), ("diss_gauge", ctypes.c_double),
+                ("diss_metric", ctypes.c_double)]
 
 
 class GridInfo(ctypes.Structure):
@@ -157,8 +158,9 @@ def last_error():
     return lib().bhah_last_error().decode(errors="replace")
 
 
-def gauge(eta=2.0):
-    return GaugeParams(float(eta), 0)
+def gauge(eta=2.0, diss=(0.0, 0.0)):
+    """diss: Kreiss-Oliger strengths (gauge, metric); (0, 0) is off."""
+    return GaugeParams(float(eta), 0, float(diss[0]), float(diss[1]))
 
 
 # ---- the C ABI, one Python function per entry point ----------------------
@@ -210,20 +212,20 @@ def apply_bcs(h, y, stream=None):
     _check(lib().bhah_apply_bcs(h, _ptr(y), _stream(stream)), "bhah_apply_bcs")
 
 
-def bssn_rhs(h, y, rhs, aux=None, eta=2.0, stream=None):
-    gp = gauge(eta)
+def bssn_rhs(h, y, rhs, aux=None, eta=2.0, diss=(0.0, 0.0), stream=None):
+    gp = gauge(eta, diss)
     _check(lib().bhah_bssn_rhs(h, ctypes.byref(gp), _ptr(y), _ptr(rhs), _ptr(aux), _stream(stream)),
            "bhah_bssn_rhs")
 
 
-def rk4_step(h, y, workspace, dt, eta=2.0, stream=None):
-    gp = gauge(eta)
+def rk4_step(h, y, workspace, dt, eta=2.0, diss=(0.0, 0.0), stream=None):
+    gp = gauge(eta, diss)
     _check(lib().bhah_rk4_step(h, ctypes.byref(gp), float(dt), _ptr(y), _ptr(workspace), _stream(stream)),
            "bhah_rk4_step")
 
 
-def ssprk3_step(h, y, workspace, dt, eta=2.0, stream=None):
-    gp = gauge(eta)
+def ssprk3_step(h, y, workspace, dt, eta=2.0, diss=(0.0, 0.0), stream=None):
+    gp = gauge(eta, diss)
     _check(lib().bhah_ssprk3_step(h, ctypes.byref(gp), float(dt), _ptr(y), _ptr(workspace), _stream(stream)),
            "bhah_ssprk3_step")
 
@@ -248,8 +250,8 @@ def grid_get_tile(h):
     return lx.value, ly.value, band.value
 
 
-def grid_tune(h, y, rhs, eta=2.0, stream=None):
-    gp = gauge(eta)
+def grid_tune(h, y, rhs, eta=2.0, diss=(0.0, 0.0), stream=None):
+    gp = gauge(eta, diss)
     _check(lib().bhah_grid_tune(h, ctypes.byref(gp), _ptr(y), _ptr(rhs), _stream(stream)), "bhah_grid_tune")
 
 
@@ -260,10 +262,10 @@ def probe_peaks(stream=None):
     return tf.value, gb.value
 
 
-def batch_create(grid_handles, eta=2.0, tune_cache_path=None):
+def batch_create(grid_handles, eta=2.0, tune_cache_path=None, diss=(0.0, 0.0)):
     n = len(grid_handles)
     arr = (_vp * n)(*[g.value for g in grid_handles])
-    gp = gauge(eta)
+    gp = gauge(eta, diss)
     b = _vp()
     path = tune_cache_path.encode() if tune_cache_path else None
     _check(lib().bhah_batch_create(arr, n, ctypes.byref(gp), path, ctypes.byref(b)), "bhah_batch_create")
@@ -305,9 +307,9 @@ def batch_destroy(b):
 
 
 def server_create(budget_bytes, max_jobs, steps_per_tick=10, keep_results=False, eta=2.0,
-                  tune_cache_path=None, stream=None, target_points=0):
+                  tune_cache_path=None, stream=None, target_points=0, diss=(0.0, 0.0)):
     p = ServerParams(float(budget_bytes), int(max_jobs), int(steps_per_tick), 1 if keep_results else 0,
-                     int(target_points), gauge(eta), tune_cache_path.encode() if tune_cache_path else None)
+                     int(target_points), gauge(eta, diss), tune_cache_path.encode() if tune_cache_path else None)
     s = _vp()
     _check(lib().bhah_server_create(ctypes.byref(p), _stream(stream), ctypes.byref(s)), "bhah_server_create")
     return s

@@ -16,7 +16,7 @@ extern "C" {
 int bhah_batch_create(const bhah_grid* const* grids, int n, const bhah_gauge_params* gp,
                       const char* tune_cache_path, bhah_batch** out) {
   if (!grids || n <= 0 || !gp || !out) return bhah::fail(BHAH_EINVAL, "bhah_batch_create: bad argument");
-  if (gp->shift_variant != 0) return bhah::fail(BHAH_EINVAL, "bhah_batch_create: shift_variant must be 0");
+  if (int rc = bhah::check_gauge(gp, "bhah_batch_create")) return rc;
   for (int j = 0; j < n; j++)
     if (!grids[j]) return bhah::fail(BHAH_EINVAL, "bhah_batch_create: NULL grid");
   bhah_batch* b = new (std::nothrow) bhah_batch(*gp, tune_cache_path);

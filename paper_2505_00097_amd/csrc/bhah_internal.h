@@ -81,6 +81,16 @@ struct StageArgs {
   double m1, m2;
 };
 
+// Gauge and dissipation parameters as the right-hand-side kernel takes them:
+// eta of Eq. 15, Kreiss-Oliger strengths for gauge and metric variables.
+struct Gauge {
+  double eta, dg, dm;
+  bool ko() const { return dg != 0.0 || dm != 0.0; }
+};
+inline Gauge gauge_of(const bhah_gauge_params& p) { return Gauge{p.eta, p.diss_gauge, p.diss_metric}; }
+// BHAH_OK, or BHAH_EINVAL with a message naming the caller
+int check_gauge(const bhah_gauge_params* gp, const char* who);
+
 // Tile shape and walk of the right-hand-side kernel over one grid: tiles of
 // 64 points, 2^lx along i0, 2^ly along i1 and 64 >> (lx + ly) along i2,
 // walked in bands of `band` tile rows of i1.
@@ -206,11 +216,11 @@ namespace bhah {
 void launch_ghosts(const GhostDev& gh, double* y, long long sgf, hipStream_t s);
 int launch_brill_lindquist(const GridDev& G, int n, const double* m, const double* pos, int lapse_kind,
                            double* y, hipStream_t s);
-void launch_rhs_fused(const GridDev& G, double eta, const double* y, double* aux, const StageArgs& st,
+void launch_rhs_fused(const GridDev& G, const Gauge& ga, const double* y, double* aux, const StageArgs& st,
                       hipStream_t s, const TileCfg& cfg);
 TileMap make_tilemap(const GridDev& G, int lx, int ly, int band);
 void launch_rhs_batch(int variant, const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage,
-                      double eta, int blocks, hipStream_t s);
+                      const Gauge& ga, int blocks, hipStream_t s);
 void launch_ghosts_batch(const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage, int which,
                          int blocks, hipStream_t s);
 void launch_hamiltonian(const GridDev& G, const double* y, double* H, hipStream_t s);

@@ -1,4 +1,5 @@
 // capi.cpp -- the extern "C" entry points declared in include/bhah.h.
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -25,6 +26,14 @@ int check_hip(hipError_t e, const char* what) {
 }
 
 static int check_launch(const char* what) { return check_hip(hipGetLastError(), what); }
+
+int check_gauge(const bhah_gauge_params* gp, const char* who) {
+  if (gp->shift_variant != 0) return fail(BHAH_EINVAL, std::string(who) + ": shift_variant must be 0");
+  if (!(gp->diss_gauge >= 0.0) || !(gp->diss_metric >= 0.0) || !std::isfinite(gp->diss_gauge) ||
+      !std::isfinite(gp->diss_metric))
+    return fail(BHAH_EINVAL, std::string(who) + ": dissipation strengths must be finite and >= 0");
+  return BHAH_OK;
+}
 
 void rk4_stages(double dt, double* y, double* ws, long long n, StageArgs st[4], const double* in[4],
                 double* gdst[4]) {
@@ -191,23 +200,23 @@ int bhah_set_initial_data_brill_lindquist(const bhah_grid* g, int n_punct, const
 int bhah_bssn_rhs(const bhah_grid* g, const bhah_gauge_params* gp, const double* y, double* rhs,
                   double* aux, void* stream) {
   if (!g || !gp || !y || !rhs) return fail(BHAH_EINVAL, "bhah_bssn_rhs: NULL argument");
-  if (gp->shift_variant != 0) return fail(BHAH_EINVAL, "bhah_bssn_rhs: shift_variant must be 0");
+  if (int rc = check_gauge(gp, "bhah_bssn_rhs")) return rc;
   StageArgs st{rhs, nullptr, nullptr, 0.0, nullptr, nullptr, 0.0};
-  launch_rhs_fused(g->dev, gp->eta, y, aux, st, (hipStream_t)stream, g->tile);
+  launch_rhs_fused(g->dev, gauge_of(*gp), y, aux, st, (hipStream_t)stream, g->tile);
   return check_launch("bhah_bssn_rhs");
 }
 
 int bhah_rk4_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt, double* y, double* workspace,
                   void* stream) {
   if (!g || !gp || !y || !workspace) return fail(BHAH_EINVAL, "bhah_rk4_step: NULL argument");
-  if (gp->shift_variant != 0) return fail(BHAH_EINVAL, "bhah_rk4_step: shift_variant must be 0");
+  if (int rc = check_gauge(gp, "bhah_rk4_step")) return rc;
   hipStream_t s = (hipStream_t)stream;
   StageArgs st[4];
   const double* in[4];
   double* gdst[4];
   rk4_stages(dt, y, workspace, g->info.state_doubles, st, in, gdst);
   for (int k = 0; k < 4; k++) {
-    launch_rhs_fused(g->dev, gp->eta, in[k], nullptr, st[k], s, g->tile);
+    launch_rhs_fused(g->dev, gauge_of(*gp), in[k], nullptr, st[k], s, g->tile);
     launch_ghosts(k < 3 ? g->ghost_stage : g->ghost, gdst[k], g->dev.sgf, s);
   }
   return check_launch("bhah_rk4_step");
@@ -216,14 +225,14 @@ int bhah_rk4_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt, do
 int bhah_ssprk3_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt, double* y, double* workspace,
                      void* stream) {
   if (!g || !gp || !y || !workspace) return fail(BHAH_EINVAL, "bhah_ssprk3_step: NULL argument");
-  if (gp->shift_variant != 0) return fail(BHAH_EINVAL, "bhah_ssprk3_step: shift_variant must be 0");
+  if (int rc = check_gauge(gp, "bhah_ssprk3_step")) return rc;
   hipStream_t s = (hipStream_t)stream;
   StageArgs st[3];
   const double* in[3];
   double* gdst[3];
   ssprk3_stages(dt, y, workspace, g->info.state_doubles, st, in, gdst);
   for (int k = 0; k < 3; k++) {
-    launch_rhs_fused(g->dev, gp->eta, in[k], nullptr, st[k], s, g->tile);
+    launch_rhs_fused(g->dev, gauge_of(*gp), in[k], nullptr, st[k], s, g->tile);
     launch_ghosts(k < 2 ? g->ghost_stage : g->ghost, gdst[k], g->dev.sgf, s);
   }
   return check_launch("bhah_ssprk3_step");
@@ -248,7 +257,7 @@ int bhah_grid_get_tile(const bhah_grid* g, int* lx, int* ly, int* band) {
 
 int bhah_grid_tune(bhah_grid* g, const bhah_gauge_params* gp, const double* y, double* rhs, void* stream) {
   if (!g || !gp || !y || !rhs) return fail(BHAH_EINVAL, "bhah_grid_tune: NULL argument");
-  if (gp->shift_variant != 0) return fail(BHAH_EINVAL, "bhah_grid_tune: shift_variant must be 0");
+  if (int rc = check_gauge(gp, "bhah_grid_tune")) return rc;
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0, e1;
   int rc = check_hip(hipEventCreate(&e0), "hipEventCreate");
@@ -262,9 +271,9 @@ int bhah_grid_tune(bhah_grid* g, const bhah_gauge_params* gp, const double* y, d
   float best = 1e30f;
   TileCfg bc = g->tile;
   for (const TileCfg& c : tile_candidates(cls)) {
-    launch_rhs_fused(g->dev, gp->eta, y, nullptr, st, s, c);
+    launch_rhs_fused(g->dev, gauge_of(*gp), y, nullptr, st, s, c);
     (void)hipEventRecord(e0, s);
-    for (int r = 0; r < 3; r++) launch_rhs_fused(g->dev, gp->eta, y, nullptr, st, s, c);
+    for (int r = 0; r < 3; r++) launch_rhs_fused(g->dev, gauge_of(*gp), y, nullptr, st, s, c);
     (void)hipEventRecord(e1, s);
     if ((rc = check_hip(hipEventSynchronize(e1), "bhah_grid_tune"))) break;
     float ms = 0.f;

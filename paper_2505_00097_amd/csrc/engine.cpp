@@ -244,9 +244,9 @@ int Engine::time_class(const SizeClass& c, const TileCfg& cfg, hipStream_t s, do
   if ((rc = check_hip(hipEventCreate(&e1), "hipEventCreate"))) { (void)hipEventDestroy(e0); return rc; }
   const int reps = 3;
   const int blocks = rhs_grid();
-  launch_rhs_batch(variant, dj, dh, dt, 4, gp_.eta, blocks, s);
+  launch_rhs_batch(variant, dj, dh, dt, 4, gauge_of(gp_), blocks, s);
   (void)hipEventRecord(e0, s);
-  for (int r = 0; r < reps; r++) launch_rhs_batch(variant, dj, dh, dt, 4, gp_.eta, blocks, s);
+  for (int r = 0; r < reps; r++) launch_rhs_batch(variant, dj, dh, dt, 4, gauge_of(gp_), blocks, s);
   (void)hipEventRecord(e1, s);
   rc = check_hip(hipEventSynchronize(e1), "tile timing");
   float ms = 0.f;
@@ -300,7 +300,7 @@ int Engine::capture(int nsteps, hipStream_t s, hipGraphExec_t* out) {
   for (int k = 0; k < nsteps; k++)
     for (int stage = 0; stage < 4; stage++) {
       for (int f = 0; f < NVAR; f++)
-        if (fam_present_[f]) launch_rhs_batch(f, dj, dh, dt, stage, gp_.eta, rhs_blocks_, cap_stream_);
+        if (fam_present_[f]) launch_rhs_batch(f, dj, dh, dt, stage, gauge_of(gp_), rhs_blocks_, cap_stream_);
       const int which = stage == 3 && k == nsteps - 1 ? 1 : 0;
       launch_ghosts_batch(dj, dh, dc, stage, which, ghost_blocks_, cap_stream_);
     }

@@ -34,9 +34,19 @@ namespace bhah {
 //                                       - 6 (f(2) - f(1)) + (f(3) - f(1))].
 struct Upwind2 {
   unsigned vp[3], vm[3], v2[3], v3[3];  // per-lane byte offsets of q+s, q-s, q+2s, q+3s
+  unsigned v2m[3], v3m[3];              // q-2s, q-3s (dissipation only)
   unsigned v0;
   double w[3];                          // |beta^k| / (12 dxx^k)
 };
+
+// Kreiss-Oliger dissipation (Sec. 4.2): the sixth difference
+// delta^6 f = f(3) + f(-3) - 6 (f(2) + f(-2)) + 15 (f(1) + f(-1)) - 20 f(0)
+// along each logical direction, weighted by eps/(64 dxx^k). Symmetric in the
+// two sides, so the upwind-ordered stencil values serve as they are.
+__device__ __forceinline__ double ko6(double f3, double fm3, double f2, double fm2, double f1, double fm1,
+                                      double f0) {
+  return (f3 + fm3) - 6.0 * (f2 + fm2) + 15.0 * (f1 + fm1) - 20.0 * f0;
+}
 
 #define BHAH_PHASE_BARRIER() __builtin_amdgcn_sched_barrier(0)
 
@@ -67,7 +77,8 @@ __device__ __forceinline__ void gather_axis_k(const Pt& P, int g, int k, double 
   else if (k == 1) gather_axis_ax<1, PD, AX>(P, g, v);
   else gather_axis_ax<2, PD, AX>(P, g, v);
 }
-// value three points upwind along k (the fourth point of the shifted stencil)
+// value three points upwind along k (the fourth point of the shifted stencil),
+// or, with the offsets of the other side, three points downwind
 template <int PD, bool AX>
 __device__ __forceinline__ double upwind3(const Pt& P, int g, int k, const unsigned (&v3)[3], const double v[5]) {
   if (AX && k == PD) return v[1];
@@ -79,10 +90,13 @@ __device__ __forceinline__ void gather_cross_kl(const Pt& P, int g, int k, int l
   else gather_cross<1, 2>(P, g, v);
 }
 
-// upwinded advection of N gridfunctions in one batch of loads
-template <int N, int PD, bool AX>
-__device__ __forceinline__ void advect_batch(const Pt& P, const int (&gl)[N], const Upwind2& U, double (&out)[N]) {
+// upwinded advection of N gridfunctions in one batch of loads; with KO also
+// their dissipation (strength eps[t], weights kw[k] = 1/(64 dxx^k))
+template <int N, int PD, bool AX, bool KO>
+__device__ __forceinline__ void advect_batch(const Pt& P, const int (&gl)[N], const Upwind2& U, double (&out)[N],
+                                             const double (&eps)[N], const double (&kw)[3]) {
   double f0[N], fp[N][3], fm[N][3], f2[N][3], f3[N][3];
+  double fm2[KO ? N : 1][3], fm3[KO ? N : 1][3];
 #pragma unroll
   for (int t = 0; t < N; t++) {
     const int g = gl[t];
@@ -94,10 +108,18 @@ __device__ __forceinline__ void advect_batch(const Pt& P, const int (&gl)[N], co
         fm[t][k] = fp[t][k];
         f2[t][k] = f0[t];
         f3[t][k] = fp[t][k];
+        if constexpr (KO) {
+          fm2[t][k] = f0[t];
+          fm3[t][k] = fp[t][k];
+        }
       } else {
         fm[t][k] = gf_ld(P.y, P.sgf, g, U.vm[k], 0);
         f2[t][k] = gf_ld(P.y, P.sgf, g, U.v2[k], 0);
         f3[t][k] = gf_ld(P.y, P.sgf, g, U.v3[k], 0);
+        if constexpr (KO) {
+          fm2[t][k] = gf_ld(P.y, P.sgf, g, U.v2m[k], 0);
+          fm3[t][k] = gf_ld(P.y, P.sgf, g, U.v3m[k], 0);
+        }
       }
     }
   }
@@ -109,6 +131,13 @@ __device__ __forceinline__ void advect_batch(const Pt& P, const int (&gl)[N], co
     for (int k = 0; k < 3; k++)
       s += U.w[k] * (3.0 * (fp[t][k] - fm[t][k]) + 10.0 * (fp[t][k] - f0[t]) - 6.0 * (f2[t][k] - fp[t][k]) +
                      (f3[t][k] - fp[t][k]));
+    if constexpr (KO) {
+      double d = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; k++)
+        d += kw[k] * ko6(f3[t][k], fm3[t][k], f2[t][k], fm2[t][k], fp[t][k], fm[t][k], f0[t]);
+      s += eps[t] * d;
+    }
     out[t] = s;
   }
 }
@@ -129,11 +158,15 @@ enum { PK_PC = 0, PK_QS = 6, PK_Y = 9, PK_ZA = 15, PK_BV = 16, PK_BD = 19, PK_RT
        PK_DH = PK_OUT, PK_D1 = 55, PK_ADV = 70 };
 static_assert(PK_ADV + 8 == PARK && PK_DH + 18 <= PK_OUT + G_VETU0, "park layout");
 
-template <int C, bool AX>
-__device__ __forceinline__ void fused_point(const GridDev& G, double eta, const double* __restrict__ y,
+template <int C, bool AX, bool KO>
+__device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, const double* __restrict__ y,
                                             const StageArgs& st, int i0, int i1, int i2, unsigned q,
                                             double* __restrict__ aux, double* __restrict__ park) {
   constexpr int PD = C == BHAH_SINH_CYLINDRICAL ? 1 : 2;  // the periodic (phi) direction
+  const double eta = ga.eta;
+  double kw[3];  // dissipation weights 1/(64 dxx^k)
+#pragma unroll
+  for (int k = 0; k < 3; k++) kw[k] = G.inv_dx[k] * (1.0 / 64.0);
   // park[v * 64] is this thread's slot v (lane-consecutive, bank-conflict free)
   auto put = [&](int v, double x) { park[v * 64] = x; };
   auto get = [&](int v) { return park[v * 64]; };
@@ -177,9 +210,17 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
         U.vm[k] = up ? P.vper(-1) : P.vper(1);
         U.v2[k] = up ? P.vper(2) : P.vper(-2);
         U.v3[k] = up ? P.vper(3) : P.vper(-3);
+        if constexpr (KO) {
+          U.v2m[k] = up ? P.vper(-2) : P.vper(2);
+          U.v3m[k] = up ? P.vper(-3) : P.vper(3);
+        }
       } else {
         const int o = s * str[k];
         U.vp[k] = (q + o) * 8u; U.vm[k] = (q - o) * 8u; U.v2[k] = (q + 2 * o) * 8u; U.v3[k] = (q + 3 * o) * 8u;
+        if constexpr (KO) {
+          U.v2m[k] = (q - 2 * o) * 8u;
+          U.v3m[k] = (q - 3 * o) * 8u;
+        }
       }
       U.w[k] = fabs(beta[k]) * sp.i12h[k];
     }
@@ -210,11 +251,12 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
         double dd[11];
         if (k == l) {
           // f(-2..2) along k, and f(3 s) on the upwind side for the advection
-          double v[11][5], f3[11];
+          double v[11][5], f3[11], fm3[KO ? 11 : 1];
 #pragma unroll
           for (int t = 0; t < 11; t++) {
             gather_axis_k<PD, AX>(P, G11[t], k, v[t]);
             f3[t] = upwind3<PD, AX>(P, G11[t], k, U.v3, v[t]);
+            if constexpr (KO) fm3[t] = upwind3<PD, AX>(P, G11[t], k, U.v3m, v[t]);
           }
           BHAH_PHASE_BARRIER();
           const bool up = vet[k] > 0.0;
@@ -223,6 +265,9 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
             const double fp = up ? v[t][3] : v[t][1], fm = up ? v[t][1] : v[t][3];
             const double f2 = up ? v[t][4] : v[t][0], f0 = v[t][2];
             adv[t] += U.w[k] * (3.0 * (fp - fm) + 10.0 * (fp - f0) - 6.0 * (f2 - fp) + (f3[t] - fp));
+            // h_ij and W take the metric strength, alpha and vet^i the gauge one
+            if constexpr (KO)
+              adv[t] += (t < 7 ? ga.dm : ga.dg) * kw[k] * ko6(f3[t], fm3[t], v[t][4], v[t][0], v[t][3], v[t][1], f0);
           }
 #pragma unroll
           for (int t = 0; t < 11; t++) dd[t] = d2_axis(v[t], sp.i12hh[k]);
@@ -436,27 +481,33 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
     // result slots of lambda are free: phase 2 no longer reads PK_DH)
     double Lam[3], DLam[3][3], dlam[3][3];
     {
-      double v[3][3][5], f3[3][3];
+      double v[3][3][5], f3[3][3], fm3[KO ? 3 : 1][3];
 #pragma unroll
       for (int i = 0; i < 3; i++)
 #pragma unroll
         for (int k = 0; k < 3; k++) {
           gather_axis_k<PD, AX>(P, G_LAMU0 + i, k, v[i][k]);
           f3[i][k] = upwind3<PD, AX>(P, G_LAMU0 + i, k, U.v3, v[i][k]);
+          if constexpr (KO) fm3[i][k] = upwind3<PD, AX>(P, G_LAMU0 + i, k, U.v3m, v[i][k]);
         }
       BHAH_PHASE_BARRIER();
 #pragma unroll
       for (int i = 0; i < 3; i++) {
-        double a = 0.0;
+        double a = 0.0, d = 0.0;
 #pragma unroll
         for (int k = 0; k < 3; k++) {
           const bool up = vet[k] > 0.0;
           const double fp = up ? v[i][k][3] : v[i][k][1], fm = up ? v[i][k][1] : v[i][k][3];
           const double f2 = up ? v[i][k][4] : v[i][k][0], f0 = v[i][k][2];
           a += U.w[k] * (3.0 * (fp - fm) + 10.0 * (fp - f0) - 6.0 * (f2 - fp) + (f3[i][k] - fp));
+          if constexpr (KO) d += kw[k] * ko6(f3[i][k], fm3[i][k], v[i][k][4], v[i][k][0], v[i][k][3], v[i][k][1], f0);
           dlam[i][k] = AX && k == PD ? 0.0 : d1_axis(v[i][k], sp.i12h[k]);
         }
-        put(PK_OUT + G_LAMU0 + i, a);
+        put(PK_OUT + G_LAMU0 + i, a + ga.dm * d);
+        // bet^i's right-hand side takes 3/4 of lambda^i's undissipated one:
+        // its result slot (free until phase 3) starts at -3/4 of lambda's
+        // dissipation, which the 3/4 of lambda's full slot then cancels
+        if constexpr (KO) put(PK_OUT + G_BETU0 + i, -0.75 * (ga.dm * d));
       }
     }
 #pragma unroll
@@ -520,22 +571,26 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
   {
     constexpr int GA[5] = {G_ADD00, G_ADD00 + 1, G_ADD00 + 2, G_ADD00 + 3, G_ADD00 + 4};
     double a5[5];
-    advect_batch<5, PD, AX>(P, GA, U, a5);
+    const double e5[5] = {ga.dm, ga.dm, ga.dm, ga.dm, ga.dm};
+    advect_batch<5, PD, AX, KO>(P, GA, U, a5, e5, kw);
 #pragma unroll
     for (int t = 0; t < 5; t++) put(PK_OUT + GA[t], a5[t]);
   }
   {
     constexpr int GB[4] = {G_ADD00 + 5, G_BETU0, G_BETU0 + 1, G_BETU0 + 2};
     double a4[4];
-    double v[3][5], f3[3];
+    double v[3][5], f3[3], fm3[3];
 #pragma unroll
     for (int k = 0; k < 3; k++) {
       gather_axis_k<PD, AX>(P, G_TRK, k, v[k]);
       f3[k] = upwind3<PD, AX>(P, G_TRK, k, U.v3, v[k]);
+      if constexpr (KO) fm3[k] = upwind3<PD, AX>(P, G_TRK, k, U.v3m, v[k]);
     }
-    advect_batch<4, PD, AX>(P, GB, U, a4);
+    const double e4[4] = {ga.dm, ga.dg, ga.dg, ga.dg};
+    advect_batch<4, PD, AX, KO>(P, GB, U, a4, e4, kw);
+    put(PK_OUT + GB[0], a4[0]);
 #pragma unroll
-    for (int t = 0; t < 4; t++) put(PK_OUT + GB[t], a4[t]);
+    for (int t = 1; t < 4; t++) put(PK_OUT + GB[t], KO ? get(PK_OUT + GB[t]) + a4[t] : a4[t]);
     double advK = 0.0;
 #pragma unroll
     for (int k = 0; k < 3; k++) {
@@ -543,6 +598,7 @@ __device__ __forceinline__ void fused_point(const GridDev& G, double eta, const 
       const double fp = up ? v[k][3] : v[k][1], fm = up ? v[k][1] : v[k][3];
       const double f2 = up ? v[k][4] : v[k][0], f0 = v[k][2];
       advK += U.w[k] * (3.0 * (fp - fm) + 10.0 * (fp - f0) - 6.0 * (f2 - fp) + (f3[k] - fp));
+      if constexpr (KO) advK += ga.dm * kw[k] * ko6(f3[k], fm3[k], v[k][4], v[k][0], v[k][3], v[k][1], f0);
       dK[k] = AX && k == PD ? 0.0 : d1_axis(v[k], sp.i12h[k]);
     }
     put(PK_OUT + G_TRK, advK);
@@ -823,9 +879,9 @@ __device__ __forceinline__ bool tile_point(const GridDev& G, const TileMap& T, i
 // multiple of the XCD count, block b runs on XCD b % nxcd
 __device__ __forceinline__ int xcd_remap(int b, int per) { return (b % BHAH_NXCD) * per + b / BHAH_NXCD; }
 
-template <int C, bool AX>
+template <int C, bool AX, bool KO>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
-k_rhs_fused(GridDev G, TileMap T, double eta, const double* __restrict__ y, StageArgs st,
+k_rhs_fused(GridDev G, TileMap T, Gauge ga, const double* __restrict__ y, StageArgs st,
             double* __restrict__ aux) {
   const int per = (T.ntiles + BHAH_NXCD - 1) / BHAH_NXCD;
   const int w = xcd_remap((int)blockIdx.x, per);
@@ -834,16 +890,16 @@ k_rhs_fused(GridDev G, TileMap T, double eta, const double* __restrict__ y, Stag
   if (!tile_point(G, T, w, (int)threadIdx.x, i0, i1, i2)) return;
   const unsigned q = (unsigned)(i0 + G.s1 * i1 + G.s2 * i2);
   __shared__ double park[PARK * 64];
-  fused_point<C, AX>(G, eta, y, st, i0, i1, i2, q, aux, park + threadIdx.x);
+  fused_point<C, AX, KO>(G, ga, y, st, i0, i1, i2, q, aux, park + threadIdx.x);
 }
 
 // Persistent form for ensembles: a fixed grid of blocks (a multiple of the XCD
 // count) strides over one kernel variant's (job, tile) work list; every
 // point runs the same fused_point as above.
-template <int C, bool AX>
+template <int C, bool AX, bool KO>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
 k_rhs_batch(const BatchJob* __restrict__ jobs, const BatchHdr* __restrict__ hdr, const int2* __restrict__ work,
-            int stage, double eta) {
+            int stage, Gauge ga) {
   const int n = hdr->n_tiles[2 * C + AX];
   const int2* wl = work + hdr->tile_off[2 * C + AX];
   const int per = (n + BHAH_NXCD - 1) / BHAH_NXCD;
@@ -858,7 +914,7 @@ k_rhs_batch(const BatchJob* __restrict__ jobs, const BatchHdr* __restrict__ hdr,
     if (!tile_point(G, J->T, wk.y, (int)threadIdx.x, i0, i1, i2)) continue;
     const unsigned q = (unsigned)(i0 + G.s1 * i1 + G.s2 * i2);
     const StageArgs st = J->st[stage];
-    fused_point<C, AX>(G, eta, J->in[stage], st, i0, i1, i2, q, nullptr, park + threadIdx.x);
+    fused_point<C, AX, KO>(G, ga, J->in[stage], st, i0, i1, i2, q, nullptr, park + threadIdx.x);
   }
 }
 
@@ -875,35 +931,47 @@ TileMap make_tilemap(const GridDev& G, int lx, int ly, int band) {
   return T;
 }
 
-void launch_rhs_fused(const GridDev& G, double eta, const double* y, double* aux, const StageArgs& st,
+// launch tables over (variant = 2 coord + two phi planes, dissipation on)
+template <int C, bool AX, bool KO>
+void launch_fused_t(dim3 g, hipStream_t s, const GridDev& G, const TileMap& T, const Gauge& ga, const double* y,
+                    const StageArgs& st, double* aux) {
+  hipLaunchKernelGGL((k_rhs_fused<C, AX, KO>), g, dim3(64), 0, s, G, T, ga, y, st, aux);
+}
+template <int C, bool AX, bool KO>
+void launch_batch_t(dim3 g, hipStream_t s, const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage,
+                    const Gauge& ga) {
+  hipLaunchKernelGGL((k_rhs_batch<C, AX, KO>), g, dim3(64), 0, s, jobs, hdr, work, stage, ga);
+}
+using FusedLaunch = void (*)(dim3, hipStream_t, const GridDev&, const TileMap&, const Gauge&, const double*,
+                             const StageArgs&, double*);
+using BatchLaunch = void (*)(dim3, hipStream_t, const BatchJob*, const BatchHdr*, const int2*, int, const Gauge&);
+constexpr int SS = BHAH_SINH_SPHERICAL, SC = BHAH_SINH_CYLINDRICAL, SP = BHAH_SPHERICAL;
+static const FusedLaunch kFused[NVAR][2] = {
+    {launch_fused_t<SS, false, false>, launch_fused_t<SS, false, true>},
+    {launch_fused_t<SS, true, false>, launch_fused_t<SS, true, true>},
+    {launch_fused_t<SC, false, false>, launch_fused_t<SC, false, true>},
+    {launch_fused_t<SC, true, false>, launch_fused_t<SC, true, true>},
+    {launch_fused_t<SP, false, false>, launch_fused_t<SP, false, true>},
+    {launch_fused_t<SP, true, false>, launch_fused_t<SP, true, true>}};
+static const BatchLaunch kBatch[NVAR][2] = {
+    {launch_batch_t<SS, false, false>, launch_batch_t<SS, false, true>},
+    {launch_batch_t<SS, true, false>, launch_batch_t<SS, true, true>},
+    {launch_batch_t<SC, false, false>, launch_batch_t<SC, false, true>},
+    {launch_batch_t<SC, true, false>, launch_batch_t<SC, true, true>},
+    {launch_batch_t<SP, false, false>, launch_batch_t<SP, false, true>},
+    {launch_batch_t<SP, true, false>, launch_batch_t<SP, true, true>}};
+
+void launch_rhs_fused(const GridDev& G, const Gauge& ga, const double* y, double* aux, const StageArgs& st,
                       hipStream_t s, const TileCfg& cfg_in) {
   const TileCfg cfg = tile_fits_periodic(G.coord, cfg_in) ? cfg_in : TileCfg{6, 0, cfg_in.band};
   const TileMap T = make_tilemap(G, cfg.lx, cfg.ly, cfg.band);
   const int per = (T.ntiles + BHAH_NXCD - 1) / BHAH_NXCD;
-  const dim3 g(per * BHAH_NXCD), b(64);
-  constexpr int SS = BHAH_SINH_SPHERICAL, SC = BHAH_SINH_CYLINDRICAL, SP = BHAH_SPHERICAL;
-  switch (rhs_variant(G.coord, G.N1, G.N2)) {
-    case 2 * SS: hipLaunchKernelGGL((k_rhs_fused<SS, false>), g, b, 0, s, G, T, eta, y, st, aux); break;
-    case 2 * SS + 1: hipLaunchKernelGGL((k_rhs_fused<SS, true>), g, b, 0, s, G, T, eta, y, st, aux); break;
-    case 2 * SC: hipLaunchKernelGGL((k_rhs_fused<SC, false>), g, b, 0, s, G, T, eta, y, st, aux); break;
-    case 2 * SC + 1: hipLaunchKernelGGL((k_rhs_fused<SC, true>), g, b, 0, s, G, T, eta, y, st, aux); break;
-    case 2 * SP: hipLaunchKernelGGL((k_rhs_fused<SP, false>), g, b, 0, s, G, T, eta, y, st, aux); break;
-    default: hipLaunchKernelGGL((k_rhs_fused<SP, true>), g, b, 0, s, G, T, eta, y, st, aux); break;
-  }
+  kFused[rhs_variant(G.coord, G.N1, G.N2)][ga.ko() ? 1 : 0](dim3(per * BHAH_NXCD), s, G, T, ga, y, st, aux);
 }
 
 void launch_rhs_batch(int variant, const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage,
-                      double eta, int blocks, hipStream_t s) {
-  const dim3 g(blocks), b(64);
-  constexpr int SS = BHAH_SINH_SPHERICAL, SC = BHAH_SINH_CYLINDRICAL, SP = BHAH_SPHERICAL;
-  switch (variant) {
-    case 2 * SS: hipLaunchKernelGGL((k_rhs_batch<SS, false>), g, b, 0, s, jobs, hdr, work, stage, eta); break;
-    case 2 * SS + 1: hipLaunchKernelGGL((k_rhs_batch<SS, true>), g, b, 0, s, jobs, hdr, work, stage, eta); break;
-    case 2 * SC: hipLaunchKernelGGL((k_rhs_batch<SC, false>), g, b, 0, s, jobs, hdr, work, stage, eta); break;
-    case 2 * SC + 1: hipLaunchKernelGGL((k_rhs_batch<SC, true>), g, b, 0, s, jobs, hdr, work, stage, eta); break;
-    case 2 * SP: hipLaunchKernelGGL((k_rhs_batch<SP, false>), g, b, 0, s, jobs, hdr, work, stage, eta); break;
-    default: hipLaunchKernelGGL((k_rhs_batch<SP, true>), g, b, 0, s, jobs, hdr, work, stage, eta); break;
-  }
+                      const Gauge& ga, int blocks, hipStream_t s) {
+  kBatch[variant][ga.ko() ? 1 : 0](dim3(blocks), s, jobs, hdr, work, stage, ga);
 }
 
 }  // namespace bhah

@@ -165,7 +165,7 @@ int bhah_server_create(const bhah_server_params* p, void* stream, bhah_server** 
   if (!p || !out) return bhah::fail(BHAH_EINVAL, "bhah_server_create: NULL argument");
   if (p->max_jobs < 1 || p->steps_per_tick < 1 || !(p->budget_bytes > 0))
     return bhah::fail(BHAH_EINVAL, "bhah_server_create: max_jobs, steps_per_tick and budget must be positive");
-  if (p->gauge.shift_variant != 0) return bhah::fail(BHAH_EINVAL, "bhah_server_create: shift_variant must be 0");
+  if (int rc = bhah::check_gauge(&p->gauge, "bhah_server_create")) return rc;
   bhah_server* s = new (std::nothrow) bhah_server(*p, (hipStream_t)stream);
   if (!s) return bhah::fail(BHAH_ENOMEM, "bhah_server_create: host allocation failed");
   s->engine.set_graph_steps(p->steps_per_tick);

@@ -53,7 +53,7 @@ def _setup(jobs):
     return grids, ys, wss
 
 
-def _solo(grids, ys0, nsteps):
+def _solo(grids, ys0, nsteps, diss=(0.0, 0.0)):
     import torch
     from paper_2505_00097_amd import capi
     out = []
@@ -61,7 +61,7 @@ def _solo(grids, ys0, nsteps):
         y = y0.clone()
         ws = g.workspace()
         for _ in range(n):
-            capi.rk4_step(g.h, y, ws, g.dt)
+            capi.rk4_step(g.h, y, ws, g.dt, diss=diss)
         out.append(y)
     torch.cuda.synchronize()
     return out
@@ -90,6 +90,27 @@ def test_batch_matches_solo_bitwise(tmp_path):
     for j in range(len(jobs)):
         lx, ly, band = capi.batch_get_tile(b, j)
         assert 3 <= lx <= 6 and 0 <= ly and lx + ly <= 6 and band >= 1
+    capi.batch_destroy(b)
+
+
+def test_batch_with_dissipation_matches_solo_bitwise():
+    """Kreiss-Oliger dissipation in the ensemble kernels: every job equals
+    its solo evolution with the same strengths, bit for bit."""
+    _case("batch dissipation")
+    import torch
+    from paper_2505_00097_amd import capi
+    diss = (0.99, 0.3)
+    jobs = _small_jobs()
+    grids, ys, wss = _setup(jobs)
+    ys0 = [y.clone() for y in ys]
+    b = capi.batch_create([g.h for g in grids], eta=2.0, diss=diss)
+    capi.batch_step(b, ys, wss, [g.dt for g in grids], nsteps=7)
+    torch.cuda.synchronize()
+    solo = _solo(grids, ys0, [7] * len(jobs), diss=diss)
+    plain = _solo(grids, ys0, [7] * len(jobs))
+    for k, (y, s, p) in enumerate(zip(ys, solo, plain)):
+        assert torch.equal(y, s), k
+        assert not torch.equal(y, p), k  # the dissipation is on
     capi.batch_destroy(b)
 
 
