@@ -20,7 +20,9 @@
  *   - optional Kreiss-Oliger dissipation added to each rescaled right-hand
  *     side (Sec. 4.2, strengths for gauge and metric variables);
  *   - boundary fill after every RK substage: outer extrapolation, then inner
- *     parity copies (Sec. 3, ordered boundary steps);
+ *     parity copies (Sec. 3, ordered boundary steps); or, with the radiation
+ *     outer boundary, the pure-outer points evolved by a Sommerfeld condition
+ *     and only the inner copies refilled;
  *   - classical RK4 (Sec. 4.2.1 footnote), or the three-stage strong-
  *     stability-preserving Runge-Kutta scheme the production head-on run of
  *     Sec. 4.2 uses (SSPRK3 of Gottlieb, Shu and Tadmor, cited there).
@@ -73,6 +75,7 @@ int oracle_check(const oracle_params* p) {
   if (!p) return -1;
   if (p->coord < 0 || p->coord > 2) return -1;
   if (p->ng < 3) return -1;
+  if (p->bc_kind != 0 && p->bc_kind != 1) return -1;
   /* the periodic phi direction may have fewer cells than ghost layers (its
    * ghosts wrap around as often as needed); the others need N >= ng */
   const int dphi = p->coord == 1 ? 1 : 2;
@@ -215,13 +218,9 @@ void oracle_xx_to_cart(const oracle_params* p, const double xx[3], double x[3]) 
   xx_to_cart(&G, xx, x);
 }
 
-/* Rescaled basis e~_(i) = e^_(i) / S_(i) with e^_(i) = d x / d xx^i (Sec. 2.2),
- * e[i][a] = Cartesian component a of e~_(i).                                */
-static void rescaled_basis(const Grid* G, const double xx[3], double e[3][3]) {
+/* Jacobian J[i][a] = d x^a / d xx^i of the Cartesian map above. */
+static void jacobian(const Grid* G, const double xx[3], double J[3][3]) {
   const oracle_params* p = &G->p;
-  double S[3], dS[3][3], ddS[3][3][3];
-  scale_factors(G, xx, S, dS, ddS);
-  double J[3][3]; /* J[i][a] = d x^a / d xx^i */
   double R[4];
   if (p->coord == 1) {
     double Z[4];
@@ -238,6 +237,15 @@ static void rescaled_basis(const Grid* G, const double xx[3], double e[3][3]) {
     J[1][0] = R[0] * ct * cp; J[1][1] = R[0] * ct * sp; J[1][2] = -R[0] * st;
     J[2][0] = -R[0] * st * sp; J[2][1] = R[0] * st * cp; J[2][2] = 0.0;
   }
+}
+
+/* Rescaled basis e~_(i) = e^_(i) / S_(i) with e^_(i) = d x / d xx^i (Sec. 2.2),
+ * e[i][a] = Cartesian component a of e~_(i).                                */
+static void rescaled_basis(const Grid* G, const double xx[3], double e[3][3]) {
+  double S[3], dS[3][3], ddS[3][3][3];
+  scale_factors(G, xx, S, dS, ddS);
+  double J[3][3];
+  jacobian(G, xx, J);
   for (int i = 0; i < 3; i++)
     for (int a = 0; a < 3; a++) e[i][a] = J[i][a] / S[i];
 }
@@ -377,12 +385,15 @@ static double gf_sign(int g, int parity) {
  * transverse range widened by the faces already done. Only outer-boundary
  * points (those the round trip maps to themselves) are written.
  * Step 2, inner boundary: copy from the mapped source with parity signs.   */
+/* outer = 1: extrapolate the pure-outer points in shell order, then copy the
+ * inner ghosts; outer = 0 (radiation boundary inside the time integrator):
+ * the inner copies only.                                                    */
 static void apply_bcs_with_maps(const Grid* G, const int* kind, const int* src,
-                                const int* parity, double* y) {
+                                const int* parity, double* y, int outer) {
   const int ng = G->p.ng;
   int lo[3], hi[3]; /* current face ranges, [lo, hi) */
   for (int d = 0; d < 3; d++) { lo[d] = ng; hi[d] = ng + G->p.N[d]; }
-  for (int layer = 0; layer < ng; layer++) {
+  for (int layer = 0; layer < (outer ? ng : 0); layer++) {
     for (int d = 0; d < 3; d++) {
       for (int side = 0; side < 2; side++) {
         const int face = side == 0 ? lo[d] - 1 : hi[d];
@@ -420,7 +431,7 @@ int oracle_apply_bcs(const oracle_params* p, double* y) {
   int* src = (int*)malloc(sizeof(int) * G.np);
   int* par = (int*)malloc(sizeof(int) * G.np);
   int rc = build_maps(&G, kind, src, par);
-  if (rc == 0) apply_bcs_with_maps(&G, kind, src, par, y);
+  if (rc == 0) apply_bcs_with_maps(&G, kind, src, par, y, 1);
   free(kind); free(src); free(par);
   return rc;
 }
@@ -1029,6 +1040,76 @@ static void interior_index(const Grid* G, long long t, int* i0, int* i1, int* i2
   *i2 = ng + (int)(t / (N0 * N1));
 }
 
+/* ------------------------------------------------------------------------ */
+/* Sommerfeld radiation outer boundary. Sec. 3 names Sommerfeld radiation
+ * conditions for the outer ghost points but gives no form. Reading: near the
+ * outer boundary every rescaled gridfunction is an outgoing spherical wave
+ * about its asymptotic value, f = f_inf + u(t - r/v)/r, which any such u
+ * satisfies through
+ *   d_t f = -v (f - f_inf)/r - v rhat.grad f
+ * at each pure-outer ghost point; f_inf = 1 for alpha and W, 0 otherwise;
+ * v = sqrt(2) for alpha (the asymptotic gauge speed of 1+log slicing), 1
+ * otherwise. rhat.grad f = sum_i (x/r . grad xx^i) df/dxx^i, each logical
+ * derivative the 4th-order five-point one, centred where the array allows and
+ * shifted to stay inside it otherwise. The pure-outer points are then
+ * advanced by the time integrator like interior points, and the inner ghosts
+ * are copies as before.                                                     */
+static double somm_finf(int g) { return (g == ALPHA || g == CF) ? 1.0 : 0.0; }
+static double somm_speed(int g) { return g == ALPHA ? sqrt(2.0) : 1.0; }
+
+/* w[j] with f'(0) ~ sum_j w[j] f(m[j]): the derivative at 0 of the Lagrange
+ * interpolant through the five integer nodes m[]                           */
+static void lagrange_d1(const int m[5], double w[5]) {
+  for (int j = 0; j < 5; j++) {
+    double s = 0.0;
+    for (int k = 0; k < 5; k++) {
+      if (k == j) continue;
+      double prod = 1.0 / (double)(m[j] - m[k]);
+      for (int l = 0; l < 5; l++)
+        if (l != j && l != k) prod *= (0.0 - m[l]) / (double)(m[j] - m[l]);
+      s += prod;
+    }
+    w[j] = s;
+  }
+}
+
+static void radiation_point(const Grid* G, const double* y, int i0, int i1, int i2, double rhs[NGF]) {
+  const int idx[3] = {i0, i1, i2};
+  const double xx[3] = {xx_of(G, 0, i0), xx_of(G, 1, i1), xx_of(G, 2, i2)};
+  double x[3], J[3][3], K[3][3];
+  xx_to_cart(G, xx, x);
+  const double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+  jacobian(G, xx, J);
+  inverse3(J, K); /* K[a][i] = d xx^i / d x^a */
+  double rd[3];    /* rhat . grad xx^i */
+  for (int i = 0; i < 3; i++) {
+    rd[i] = 0.0;
+    for (int a = 0; a < 3; a++) rd[i] += x[a] / r * K[a][i];
+  }
+  int s[3];
+  double w[3][5];
+  for (int d = 0; d < 3; d++) {
+    s[d] = -2;
+    if (idx[d] - 2 < 0) s[d] = -idx[d];
+    if (idx[d] + 2 > G->n[d] - 1) s[d] = G->n[d] - 1 - idx[d] - 4;
+    int m[5];
+    for (int j = 0; j < 5; j++) m[j] = s[d] + j;
+    lagrange_d1(m, w[d]);
+  }
+  const long long q = flat(G, i0, i1, i2);
+  for (int g = 0; g < NGF; g++) {
+    const double* f = y + g * G->np + q;
+    double drf = 0.0;
+    for (int d = 0; d < 3; d++) {
+      double D = 0.0;
+      for (int j = 0; j < 5; j++) D += w[d][j] * f[(s[d] + j) * G->st[d]];
+      drf += rd[d] * D / G->dxx[d];
+    }
+    const double v = somm_speed(g);
+    rhs[g] = -v * (f[0] - somm_finf(g)) / r - v * drf;
+  }
+}
+
 int oracle_rhs(const oracle_params* p, double eta, const double* y, double* rhs) {
   Grid G;
   if (grid_setup(p, &G)) return -1;
@@ -1041,6 +1122,23 @@ int oracle_rhs(const oracle_params* p, double eta, const double* y, double* rhs)
     bssn_point(&G, eta, y, i0, i1, i2, &o);
     const long long q = flat(&G, i0, i1, i2);
     for (int g = 0; g < NGF; g++) rhs[g * G.np + q] = o.rhs[g];
+  }
+  if (p->bc_kind == 1) { /* the radiation condition at the pure-outer points */
+    int* kind = (int*)malloc(sizeof(int) * G.np);
+    int* src = (int*)malloc(sizeof(int) * G.np);
+    int* par = (int*)malloc(sizeof(int) * G.np);
+    const int rc = build_maps(&G, kind, src, par);
+    if (rc == 0)
+      for (long long q = 0; q < G.np; q++) {
+        if (kind[q] != 1) continue;
+        const int i0 = (int)(q % G.n[0]), i1 = (int)((q / G.n[0]) % G.n[1]),
+                  i2 = (int)(q / ((long long)G.n[0] * G.n[1]));
+        double r[NGF];
+        radiation_point(&G, y, i0, i1, i2, r);
+        for (int g = 0; g < NGF; g++) rhs[g * G.np + q] = r[g];
+      }
+    free(kind); free(src); free(par);
+    if (rc) return rc;
   }
   return 0;
 }
@@ -1105,6 +1203,7 @@ int oracle_rk4_step(const oracle_params* p, double eta, double dt, double* y) {
   int* src = (int*)malloc(sizeof(int) * G.np);
   int* par = (int*)malloc(sizeof(int) * G.np);
   int rc = build_maps(&G, kind, src, par);
+  const int rad = p->bc_kind == 1;
   if (rc == 0) {
     const double c[3] = {0.5, 0.5, 1.0};
     memcpy(ys, y, sizeof(double) * n);
@@ -1112,18 +1211,18 @@ int oracle_rk4_step(const oracle_params* p, double eta, double dt, double* y) {
       oracle_rhs(p, eta, ys, k[s]);
       if (s == 3) break;
       for (long long t = 0; t < G.np; t++)
-        if (kind[t] == 0)
+        if (kind[t] == 0 || (rad && kind[t] == 1))
           for (int g = 0; g < NGF; g++)
             ys[g * G.np + t] = y[g * G.np + t] + c[s] * dt * k[s][g * G.np + t];
-      apply_bcs_with_maps(&G, kind, src, par, ys);
+      apply_bcs_with_maps(&G, kind, src, par, ys, !rad);
     }
     for (long long t = 0; t < G.np; t++)
-      if (kind[t] == 0)
+      if (kind[t] == 0 || (rad && kind[t] == 1))
         for (int g = 0; g < NGF; g++) {
           const long long e = g * G.np + t;
           y[e] = y[e] + dt / 6.0 * (k[0][e] + 2.0 * k[1][e] + 2.0 * k[2][e] + k[3][e]);
         }
-    apply_bcs_with_maps(&G, kind, src, par, y);
+    apply_bcs_with_maps(&G, kind, src, par, y, !rad);
   }
   for (int s = 0; s < 4; s++) free(k[s]);
   free(ys); free(kind); free(src); free(par);
@@ -1147,36 +1246,37 @@ int oracle_ssprk3_step(const oracle_params* p, double eta, double dt, double* y)
   int* src = (int*)malloc(sizeof(int) * G.np);
   int* par = (int*)malloc(sizeof(int) * G.np);
   int rc = build_maps(&G, kind, src, par);
+  const int rad = p->bc_kind == 1;
   if (rc == 0) {
     /* stage 1: forward Euler from y_n */
     memcpy(y1, y, sizeof(double) * n);
     oracle_rhs(p, eta, y, k);
     for (long long t = 0; t < G.np; t++)
-      if (kind[t] == 0)
+      if (kind[t] == 0 || (rad && kind[t] == 1))
         for (int g = 0; g < NGF; g++) {
           const long long e = g * G.np + t;
           y1[e] = y[e] + dt * k[e];
         }
-    apply_bcs_with_maps(&G, kind, src, par, y1);
+    apply_bcs_with_maps(&G, kind, src, par, y1, !rad);
     /* stage 2: average of y_n and a forward-Euler step from y1 */
     memcpy(y2, y1, sizeof(double) * n);
     oracle_rhs(p, eta, y1, k);
     for (long long t = 0; t < G.np; t++)
-      if (kind[t] == 0)
+      if (kind[t] == 0 || (rad && kind[t] == 1))
         for (int g = 0; g < NGF; g++) {
           const long long e = g * G.np + t;
           y2[e] = 0.75 * y[e] + 0.25 * (y1[e] + dt * k[e]);
         }
-    apply_bcs_with_maps(&G, kind, src, par, y2);
+    apply_bcs_with_maps(&G, kind, src, par, y2, !rad);
     /* stage 3: average of y_n and a forward-Euler step from y2 */
     oracle_rhs(p, eta, y2, k);
     for (long long t = 0; t < G.np; t++)
-      if (kind[t] == 0)
+      if (kind[t] == 0 || (rad && kind[t] == 1))
         for (int g = 0; g < NGF; g++) {
           const long long e = g * G.np + t;
           y[e] = (1.0 / 3.0) * y[e] + (2.0 / 3.0) * (y2[e] + dt * k[e]);
         }
-    apply_bcs_with_maps(&G, kind, src, par, y);
+    apply_bcs_with_maps(&G, kind, src, par, y, !rad);
   }
   free(k); free(y1); free(y2); free(kind); free(src); free(par);
   return rc;

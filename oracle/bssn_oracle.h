@@ -34,6 +34,9 @@ typedef struct {
   /* Kreiss-Oliger dissipation strengths (Sec. 4.2), 0 = off: diss_gauge for
    * alpha, vet^i, bet^i; diss_metric for every other gridfunction. */
   double diss_gauge, diss_metric;
+  /* outer boundary (Sec. 3): 0 quadratic extrapolation, 1 Sommerfeld
+   * radiation condition evolved at the pure-outer ghost points */
+  int bc_kind;
 } oracle_params;
 
 /* 0 if the parameters describe a grid the oracle supports, -1 otherwise. */
@@ -71,7 +74,8 @@ int oracle_id_brill_lindquist(const oracle_params* p, int np, const double* m,
                               const double* pos, int lapse_kind, double* y);
 
 /* Rescaled right-hand sides at every interior point (ghost entries of rhs
- * untouched). eta: Gamma-driver damping. */
+ * untouched; with bc_kind 1 also at every pure-outer ghost point, from the
+ * radiation condition). eta: Gamma-driver damping. */
 int oracle_rhs(const oracle_params* p, double eta, const double* y, double* rhs);
 
 /* Right-hand sides at a list of interior points (flat indices). out[24*q+g].
@@ -86,7 +90,9 @@ int oracle_rhs_points(const oracle_params* p, double eta, const double* y, int n
 int oracle_constraints(const oracle_params* p, const double* y, double* H, double* M,
                        double* C);
 
-/* One classical RK4 step in place (ghosts refilled after each stage). */
+/* One classical RK4 step in place (ghosts refilled after each stage; with
+ * bc_kind 1 the pure-outer points are advanced like interior points and only
+ * the inner ghosts are refilled). */
 int oracle_rk4_step(const oracle_params* p, double eta, double dt, double* y);
 
 /* One SSPRK3 step in place (ghosts refilled after each stage). */

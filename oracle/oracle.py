@@ -24,7 +24,7 @@ class OracleParams(ctypes.Structure):
     _fields_ = [("coord", ctypes.c_int), ("N", ctypes.c_int * 3), ("ng", ctypes.c_int),
                 ("ampl", ctypes.c_double * 3), ("sinhw", ctypes.c_double * 3),
                 ("cfl", ctypes.c_double), ("diss_gauge", ctypes.c_double),
-                ("diss_metric", ctypes.c_double)]
+                ("diss_metric", ctypes.c_double), ("bc_kind", ctypes.c_int)]
 
 
 _lib = None
@@ -78,9 +78,11 @@ class Grid:
     """A grid description for the oracle (host arrays only)."""
 
     def __init__(self, coord, N, ampl=(10.0, 10.0, 10.0), sinhw=(0.2, 0.2, 0.2), cfl=0.5, ng=3,
-                 diss=(0.0, 0.0)):
-        """diss: Kreiss-Oliger strengths (gauge, metric); (0, 0) is off."""
+                 diss=(0.0, 0.0), bc_kind=0):
+        """diss: Kreiss-Oliger strengths (gauge, metric); (0, 0) is off.
+        bc_kind: 0 extrapolated outer ghosts, 1 Sommerfeld radiation."""
         self.p = OracleParams()
+        self.p.bc_kind = int(bc_kind)
         self.p.diss_gauge = float(diss[0])
         self.p.diss_metric = float(diss[1])
         self.p.coord = int(coord)
