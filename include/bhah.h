@@ -70,8 +70,19 @@ enum { BHAH_SINH_SPHERICAL = 0, BHAH_SINH_CYLINDRICAL = 1, BHAH_SPHERICAL = 2 };
  * BHAH_BC_EXTRAP: quadratic extrapolation along the face normal,
  * f(g) = 3 f(g-1) - 3 f(g-2) + f(g-3), applied ghost layer by ghost layer in
  * the order x0 faces, x1 faces, x2 faces, each face range growing by the
- * layers already filled.                                                     */
-enum { BHAH_BC_EXTRAP = 0 };
+ * layers already filled.
+ * BHAH_BC_RADIATION: Sommerfeld radiation condition (Sec. 3 names it; its
+ * form here is an outgoing spherical wave about the asymptotic value):
+ * every pure-outer ghost point is an evolved point with
+ *   d_t f = -v (f - f_inf)/r - v df/dr,
+ * f_inf = 1 for alpha and cf, 0 otherwise; v = sqrt(2) for alpha, 1
+ * otherwise; df/dr through the logical derivatives along the mapped radial
+ * directions (xx0, and xx2 on SinhCylindrical grids), 4th-order five-point
+ * stencils centred where the array allows, shifted inward otherwise. The
+ * time integrators advance those points like interior ones and refill only
+ * the inner ghosts (parity copies of interior or outer points).
+ * bhah_apply_bcs always uses the extrapolation (initial fill of any grid). */
+enum { BHAH_BC_EXTRAP = 0, BHAH_BC_RADIATION = 1 };
 
 /* ---- the 24 evolved rescaled gridfunctions (Sec. 2.1 last gauge paragraph;
  * rescaling Sec. 2.2): h_ij = eps_ij/(S_i S_j), a_ij = Abar_ij/(S_i S_j),
@@ -97,7 +108,8 @@ typedef struct bhah_batch bhah_batch; /* opaque ensemble of grids        */
 /* Grid parameters. nghosts must be 3 (4th-order FD with upwinded advection
  * needs N_FD/2 + 1 ghost layers, Sec. 3 and Sec. 4.2.1). ampl[]/sinhw[]
  * entries for directions without a map are ignored. cfl scales the time step
- * (Sec. 4.1 uses 0.5). bc_kind must be BHAH_BC_EXTRAP.                       */
+ * (Sec. 4.1 uses 0.5). bc_kind: BHAH_BC_EXTRAP or BHAH_BC_RADIATION (the
+ * ensemble and the server take extrapolation grids only).                   */
 typedef struct {
   int coord;
   int N[3];
@@ -185,7 +197,9 @@ int bhah_apply_bcs(const bhah_grid* g, double* y, void* stream);
 
 /* BSSN + gauge right-hand sides (Eqs. 7-15 with Eq. 12) of the rescaled
  * variables at every interior point. y must have valid ghosts. rhs has the
- * state layout; only its interior points are written. aux receives
+ * state layout; only its interior points are written (and, on a
+ * BHAH_BC_RADIATION grid, its pure-outer points, with the radiation
+ * condition's right-hand side). aux receives
  * BHAH_NUM_AUX_GFS gridfunctions (state layout, interior points) computed on
  * the way, or may be NULL to skip them. All 4th-order finite differences,
  * advection terms beta^k d_k upwinded (Sec. 3 second paragraph).            */

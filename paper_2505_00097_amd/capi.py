@@ -14,6 +14,7 @@ NUM_GFS = 24
 NUM_AUX_GFS = 9
 SINH_SPHERICAL, SINH_CYLINDRICAL, SPHERICAL = 0, 1, 2
 OK, EINVAL, EDEVICE, ENOMEM = 0, -1, -2, -3
+BC_EXTRAP, BC_RADIATION = 0, 1  # outer boundary kinds (bhah_grid_params.bc_kind)
 GF_NAMES = ["aDD00", "aDD01", "aDD02", "aDD11", "aDD12", "aDD22", "alpha",
             "betU0", "betU1", "betU2", "cf", "hDD00", "hDD01", "hDD02", "hDD11",
             "hDD12", "hDD22", "lambdaU0", "lambdaU1", "lambdaU2", "trK",
@@ -164,7 +165,7 @@ def gauge(eta=2.0, diss=(0.0, 0.0)):
 
 
 # ---- the C ABI, one Python function per entry point ----------------------
-def grid_create(coord, N, ampl=(10.0, 10.0, 10.0), sinhw=(0.2, 0.2, 0.2), cfl=0.5):
+def grid_create(coord, N, ampl=(10.0, 10.0, 10.0), sinhw=(0.2, 0.2, 0.2), cfl=0.5, bc_kind=0):
     p = GridParams()
     p.coord = int(coord)
     for d in range(3):
@@ -173,7 +174,7 @@ def grid_create(coord, N, ampl=(10.0, 10.0, 10.0), sinhw=(0.2, 0.2, 0.2), cfl=0.
         p.sinhw[d] = float(sinhw[d])
     p.nghosts = 3
     p.cfl = float(cfl)
-    p.bc_kind = 0
+    p.bc_kind = int(bc_kind)
     h = _vp()
     _check(lib().bhah_grid_create(ctypes.byref(p), ctypes.byref(h)), "bhah_grid_create")
     return h
@@ -365,8 +366,8 @@ def server_destroy(s):
 class Grid:
     """A grid on the current device plus helpers to allocate its arrays."""
 
-    def __init__(self, coord, N, ampl=(10.0, 10.0, 10.0), sinhw=(0.2, 0.2, 0.2), cfl=0.5):
-        self.h = grid_create(coord, N, ampl, sinhw, cfl)
+    def __init__(self, coord, N, ampl=(10.0, 10.0, 10.0), sinhw=(0.2, 0.2, 0.2), cfl=0.5, bc_kind=0):
+        self.h = grid_create(coord, N, ampl, sinhw, cfl, bc_kind)
         self.info = grid_get_info(self.h)
         self.coord = int(coord)
         self.N = tuple(int(n) for n in N)

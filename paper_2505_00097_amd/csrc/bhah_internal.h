@@ -66,6 +66,23 @@ struct GhostDev {
   const double* w;      // [n_terms]
 };
 
+// Pure-outer ghost points evolved by the radiation condition: flat index,
+// packed stencil starts (s0 + 4) | (s2 + 4) << 4 of the five-point logical
+// derivatives along xx0 and xx2 (s in -4..0), and per point 1/r and
+// (rhat . grad xx^k) / dxx^k for k = 0, 2 (zero where r does not depend on
+// xx^k).
+struct RadDev {
+  int n;
+  const int* q;       // [n]
+  const int* shift;   // [n]
+  const double* coef;  // [n][3]
+};
+// host copy of a ghost list in the GhostDev layout
+struct HostGhosts {
+  std::vector<int> dst, start, par, src;
+  std::vector<double> w;
+};
+
 // RK stage epilogue of the right-hand-side kernel: with rhs != nullptr the
 // right-hand side k is stored; otherwise out1 = base1 + c1 k and, if out2 is
 // set, out2 = base2 + c2 k, gridfunction by gridfunction. With base2 set but
@@ -202,6 +219,17 @@ struct bhah_grid {
   bhah::GhostDev ghost_stage;  // device view of the r_* list
   int max_terms;
   bhah::TileCfg tile;  // tile shape and walk of the RHS kernel
+  // radiation outer boundary: the evolved outer points and the inner ghosts
+  // as one-hop parity copies (all of them; those with an interior phi index)
+  std::vector<int> rad_q, rad_shift;
+  std::vector<double> rad_coef;
+  bhah::HostGhosts inner_full, inner_stage;
+  bhah::RadDev rad{};
+  bhah::GhostDev ghost_inner{}, ghost_inner_stage{};
+  int* d_rad_i = nullptr;     // q | shift
+  double* d_rad_c = nullptr;
+  int* d_inner_ints[2] = {nullptr, nullptr};
+  double* d_inner_w[2] = {nullptr, nullptr};
   // device allocations
   double* d_tab[3];
   int* d_ints;      // dst | start | parity | src packed
@@ -224,6 +252,9 @@ void launch_rhs_batch(int variant, const BatchJob* jobs, const BatchHdr* hdr, co
 void launch_ghosts_batch(const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage, int which,
                          int blocks, hipStream_t s);
 void launch_hamiltonian(const GridDev& G, const double* y, double* H, hipStream_t s);
+// radiation condition at the pure-outer points of one stage: the right-hand
+// side of `in` combined as in st (same semantics as the RHS kernel)
+void launch_radiation(const GridDev& G, const RadDev& R, const double* in, const StageArgs& st, hipStream_t s);
 void launch_constraints(const GridDev& G, const double* y, double* H, double* Mo, double* Co, hipStream_t s);
 
 // The four stages of one classical RK4 step on state y with workspace ws

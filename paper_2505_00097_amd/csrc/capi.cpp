@@ -68,7 +68,9 @@ void ssprk3_stages(double dt, double* y, double* ws, long long n, StageArgs st[3
 static void free_device(bhah_grid* g) {
   for (int d = 0; d < 3; d++)
     if (g->d_tab[d]) (void)hipFree(g->d_tab[d]);
-  for (void* p : {(void*)g->d_ints, (void*)g->d_w, (void*)g->d_rints, (void*)g->d_rw})
+  for (void* p : {(void*)g->d_ints, (void*)g->d_w, (void*)g->d_rints, (void*)g->d_rw, (void*)g->d_rad_i,
+                  (void*)g->d_rad_c, (void*)g->d_inner_ints[0], (void*)g->d_inner_w[0], (void*)g->d_inner_ints[1],
+                  (void*)g->d_inner_w[1]})
     if (p) (void)hipFree(p);
 }
 
@@ -95,6 +97,41 @@ static hipError_t upload_ghosts(const std::vector<int>& dst, const std::vector<i
   out->src = *d_ints + 3 * ng + 1;
   out->w = *d_w;
   return e;
+}
+
+// Upload the radiation lists: the outer points (q | shift packed, 3
+// coefficients each) and the two inner-copy lists.
+static hipError_t upload_radiation(bhah_grid* g) {
+  const size_t n = g->rad_q.size();
+  std::vector<int> packed(g->rad_q);
+  packed.insert(packed.end(), g->rad_shift.begin(), g->rad_shift.end());
+  hipError_t e = hipMalloc((void**)&g->d_rad_i, (n ? 2 * n : 1) * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void**)&g->d_rad_c, (n ? 3 * n : 1) * sizeof(double));
+  if (e == hipSuccess && n) e = hipMemcpy(g->d_rad_i, packed.data(), 2 * n * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess && n)
+    e = hipMemcpy(g->d_rad_c, g->rad_coef.data(), 3 * n * sizeof(double), hipMemcpyHostToDevice);
+  g->rad = RadDev{(int)n, g->d_rad_i, g->d_rad_i + n, g->d_rad_c};
+  const HostGhosts* L[2] = {&g->inner_full, &g->inner_stage};
+  GhostDev* D[2] = {&g->ghost_inner, &g->ghost_inner_stage};
+  for (int k = 0; k < 2 && e == hipSuccess; k++)
+    e = upload_ghosts(L[k]->dst, L[k]->start, L[k]->par, L[k]->src, L[k]->w, &g->d_inner_ints[k],
+                      &g->d_inner_w[k], D[k]);
+  return e;
+}
+
+// One stage of a time integrator: the interior right-hand side combined as in
+// st, with the radiation boundary also at the pure-outer points, then the
+// ghost fill of the stage's result (all ghosts after the last stage, those
+// with an interior phi index before: the stencils never read phi ghosts).
+static void run_stage(const bhah_grid* g, const Gauge& ga, const double* in, const StageArgs& st, double* gdst,
+                      bool last, hipStream_t s) {
+  launch_rhs_fused(g->dev, ga, in, nullptr, st, s, g->tile);
+  if (g->params.bc_kind == BHAH_BC_RADIATION) {
+    launch_radiation(g->dev, g->rad, in, st, s);
+    launch_ghosts(last ? g->ghost_inner : g->ghost_inner_stage, gdst, g->dev.sgf, s);
+  } else {
+    launch_ghosts(last ? g->ghost : g->ghost_stage, gdst, g->dev.sgf, s);
+  }
 }
 
 }  // namespace bhah
@@ -127,6 +164,7 @@ int bhah_grid_create(const bhah_grid_params* params, bhah_grid** out) {
     e = upload_ghosts(g->g_dst, g->g_start, g->g_par, g->g_src, g->g_w, &g->d_ints, &g->d_w, &g->ghost);
   if (e == hipSuccess)
     e = upload_ghosts(g->r_dst, g->r_start, g->r_par, g->r_src, g->r_w, &g->d_rints, &g->d_rw, &g->ghost_stage);
+  if (e == hipSuccess && params->bc_kind == BHAH_BC_RADIATION) e = upload_radiation(g);
   if (e != hipSuccess) {
     const int code = e == hipErrorOutOfMemory ? BHAH_ENOMEM : BHAH_EDEVICE;
     fail(code, std::string("bhah_grid_create: ") + hipGetErrorString(e));
@@ -203,6 +241,7 @@ int bhah_bssn_rhs(const bhah_grid* g, const bhah_gauge_params* gp, const double*
   if (int rc = check_gauge(gp, "bhah_bssn_rhs")) return rc;
   StageArgs st{rhs, nullptr, nullptr, 0.0, nullptr, nullptr, 0.0};
   launch_rhs_fused(g->dev, gauge_of(*gp), y, aux, st, (hipStream_t)stream, g->tile);
+  if (g->params.bc_kind == BHAH_BC_RADIATION) launch_radiation(g->dev, g->rad, y, st, (hipStream_t)stream);
   return check_launch("bhah_bssn_rhs");
 }
 
@@ -215,10 +254,7 @@ int bhah_rk4_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt, do
   const double* in[4];
   double* gdst[4];
   rk4_stages(dt, y, workspace, g->info.state_doubles, st, in, gdst);
-  for (int k = 0; k < 4; k++) {
-    launch_rhs_fused(g->dev, gauge_of(*gp), in[k], nullptr, st[k], s, g->tile);
-    launch_ghosts(k < 3 ? g->ghost_stage : g->ghost, gdst[k], g->dev.sgf, s);
-  }
+  for (int k = 0; k < 4; k++) run_stage(g, gauge_of(*gp), in[k], st[k], gdst[k], k == 3, s);
   return check_launch("bhah_rk4_step");
 }
 
@@ -231,10 +267,7 @@ int bhah_ssprk3_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt,
   const double* in[3];
   double* gdst[3];
   ssprk3_stages(dt, y, workspace, g->info.state_doubles, st, in, gdst);
-  for (int k = 0; k < 3; k++) {
-    launch_rhs_fused(g->dev, gauge_of(*gp), in[k], nullptr, st[k], s, g->tile);
-    launch_ghosts(k < 2 ? g->ghost_stage : g->ghost, gdst[k], g->dev.sgf, s);
-  }
+  for (int k = 0; k < 3; k++) run_stage(g, gauge_of(*gp), in[k], st[k], gdst[k], k == 2, s);
   return check_launch("bhah_ssprk3_step");
 }
 

@@ -77,6 +77,8 @@ int Engine::set_jobs(const std::vector<EngineJob>& jobs) {
   for (const EngineJob& j : jobs) {
     if (!j.g || !j.y || !j.ws) return fail(BHAH_EINVAL, "batch: NULL grid, state or workspace");
     if (j.g->params.coord < 0 || j.g->params.coord > 2) return fail(BHAH_EINVAL, "batch: bad coordinate family");
+    if (j.g->params.bc_kind != BHAH_BC_EXTRAP)
+      return fail(BHAH_EINVAL, "batch: only extrapolation outer boundaries (no radiation) in ensembles");
   }
   if (jobs != jobs_) {
     jobs_ = jobs;

@@ -74,7 +74,8 @@ int build_grid_host(const bhah_grid_params* p, bhah_grid* g) {
   const int coord = p->coord;
   if (coord < 0 || coord > 2) return fail(BHAH_EINVAL, "coord must be 0, 1 or 2");
   if (p->nghosts != NG) return fail(BHAH_EINVAL, "nghosts must be 3");
-  if (p->bc_kind != BHAH_BC_EXTRAP) return fail(BHAH_EINVAL, "bc_kind must be BHAH_BC_EXTRAP");
+  if (p->bc_kind != BHAH_BC_EXTRAP && p->bc_kind != BHAH_BC_RADIATION)
+    return fail(BHAH_EINVAL, "bc_kind must be BHAH_BC_EXTRAP or BHAH_BC_RADIATION");
   const int dphi = coord == BHAH_SINH_CYLINDRICAL ? 1 : 2;
   for (int d = 0; d < 3; d++) {
     if (d != dphi && p->N[d] < NG) return fail(BHAH_EINVAL, "N[d] < nghosts in a non-periodic direction");
@@ -272,6 +273,58 @@ int build_grid_host(const bhah_grid_params* p, bhah_grid* g) {
   g->r_start.push_back((int)g->r_src.size());
   I.n_pure_outer = n_outer;
   I.n_inner = n_inner;
+
+  // ---- radiation outer boundary ------------------------------------------
+  g->rad_q.clear(); g->rad_shift.clear(); g->rad_coef.clear();
+  g->inner_full = HostGhosts{};
+  g->inner_stage = HostGhosts{};
+  if (p->bc_kind == BHAH_BC_RADIATION) {
+    // five-point stencil start along a direction of n points at index i:
+    // centred where it fits, else shifted to stay inside the array
+    auto start_of = [](int i, int nd) { return i - 2 < 0 ? -i : (i + 2 > nd - 1 ? nd - 1 - i - 4 : -2); };
+    for (int i2 = 0; i2 < n[2]; i2++)
+      for (int i1 = 0; i1 < n[1]; i1++)
+        for (int i0 = 0; i0 < n[0]; i0++) {
+          int src, par;
+          const int k = classify(i0, i1, i2, src, par);
+          if (k == 0) continue;
+          const int q = flat(i0, i1, i2);
+          if (k == 1) {
+            // rhat . grad xx^k from the radial maps: r = r(xx0) on the
+            // spherical families; r = sqrt(rho^2 + z^2), rho(xx0), z(xx2) on
+            // the cylindrical one
+            const double* t0 = &g->tab[0][(size_t)i0 * TAB_W];
+            double r, a0, a2 = 0.0;
+            if (coord == BHAH_SINH_CYLINDRICAL) {
+              const double* t2 = &g->tab[2][(size_t)i2 * TAB_W];
+              r = std::sqrt(t0[0] * t0[0] + t2[0] * t2[0]);
+              a0 = t0[0] / r / t0[1];
+              a2 = t2[0] / r / t2[1];
+            } else {
+              r = t0[0];
+              a0 = 1.0 / t0[1];
+            }
+            const int s0 = start_of(i0, n[0]);
+            const int s2 = coord == BHAH_SINH_CYLINDRICAL ? start_of(i2, n[2]) : -2;
+            g->rad_q.push_back(q);
+            g->rad_shift.push_back((s0 + 4) | ((s2 + 4) << 4));
+            g->rad_coef.push_back(1.0 / r);
+            g->rad_coef.push_back(a0 / I.dxx[0]);
+            g->rad_coef.push_back(a2 / I.dxx[2]);
+          } else {
+            const int idx = pd == 1 ? i1 : i2;
+            for (HostGhosts* L : {&g->inner_full, &g->inner_stage}) {
+              if (L == &g->inner_stage && (idx < NG || idx >= NG + p->N[pd])) continue;
+              L->dst.push_back(q);
+              L->start.push_back((int)L->src.size());
+              L->par.push_back(par);
+              L->src.push_back(src);
+              L->w.push_back(1.0);
+            }
+          }
+        }
+    for (HostGhosts* L : {&g->inner_full, &g->inner_stage}) L->start.push_back((int)L->src.size());
+  }
   return BHAH_OK;
 }
 

@@ -107,6 +107,68 @@ __global__ void __launch_bounds__(64) k_brill_lindquist(GridDev G, Punctures P, 
   y[6 * G.sgf + q] = P.lapse_kind == 0 ? ip2 : 1.0;     // alpha
 }
 
+// ---- Sommerfeld radiation condition at the pure-outer points --------------
+// d_t f = -v (f - f_inf)/r - v (c0 D0 f + c2 D2 f), with D_k the five-point
+// 4th-order first derivative in grid units along xx^k starting s_k points
+// from the point (s = -2 centred; -4, -3 at a max face, -1, 0 at a min face)
+// and c_k = (rhat . grad xx^k)/dxx^k precomputed per point. One thread per
+// (outer point, group of GF_PER gridfunctions); the result is combined into
+// the stage arrays exactly as the right-hand-side kernel does it.
+__constant__ double kRadW[5][5] = {
+    {3.0 / 12, -16.0 / 12, 36.0 / 12, -48.0 / 12, 25.0 / 12},  // nodes -4..0
+    {-1.0 / 12, 6.0 / 12, -18.0 / 12, 10.0 / 12, 3.0 / 12},    // nodes -3..1
+    {1.0 / 12, -8.0 / 12, 0.0, 8.0 / 12, -1.0 / 12},           // nodes -2..2
+    {-3.0 / 12, -10.0 / 12, 18.0 / 12, -6.0 / 12, 1.0 / 12},   // nodes -1..3
+    {-25.0 / 12, 48.0 / 12, -36.0 / 12, 16.0 / 12, -3.0 / 12}  // nodes 0..4
+};
+
+__global__ void __launch_bounds__(256) k_radiation(GridDev G, RadDev R, const double* __restrict__ in,
+                                                   StageArgs st) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= R.n) return;
+  const int g0 = (int)blockIdx.y * GF_PER;
+  const long long q = R.q[t];
+  const int sh = R.shift[t];
+  const int s0 = (sh & 15) - 4, s2 = ((sh >> 4) & 15) - 4;
+  const double ir = R.coef[3 * t], c0 = R.coef[3 * t + 1], c2 = R.coef[3 * t + 2];
+  const bool cyl = G.coord == BHAH_SINH_CYLINDRICAL;
+  double k[GF_PER];
+#pragma unroll
+  for (int j = 0; j < GF_PER; j++) {
+    const int g = g0 + j;
+    const double* f = in + g * G.sgf + q;
+    double d0 = 0.0, d2 = 0.0;
+#pragma unroll
+    for (int m = 0; m < 5; m++) d0 += kRadW[s0 + 4][m] * f[s0 + m];
+    if (cyl) {
+#pragma unroll
+      for (int m = 0; m < 5; m++) d2 += kRadW[s2 + 4][m] * f[(long long)(s2 + m) * G.s2];
+    }
+    const double v = g == BHAH_ALPHA ? 1.4142135623730951 : 1.0;  // sqrt(2) for the lapse
+    const double finf = (g == BHAH_ALPHA || g == BHAH_CF) ? 1.0 : 0.0;
+    k[j] = -v * (f[0] - finf) * ir - v * (c0 * d0 + c2 * d2);
+  }
+  // the stage combination (semantics of StageArgs)
+#pragma unroll
+  for (int j = 0; j < GF_PER; j++) {
+    const long long e = (g0 + j) * G.sgf + q;
+    if (st.rhs) {
+      st.rhs[e] = k[j];
+    } else if (st.out2 == nullptr && st.base2 != nullptr) {
+      st.out1[e] = st.m1 * st.base1[e] + st.m2 * st.base2[e] + st.c1 * k[j];
+    } else {
+      const double b1 = st.base1[e], b2 = st.out2 ? st.base2[e] : 0.0;
+      st.out1[e] = b1 + st.c1 * k[j];
+      if (st.out2) st.out2[e] = b2 + st.c2 * k[j];
+    }
+  }
+}
+
+void launch_radiation(const GridDev& G, const RadDev& R, const double* in, const StageArgs& st, hipStream_t s) {
+  if (R.n == 0) return;
+  hipLaunchKernelGGL(k_radiation, dim3((R.n + 255) / 256, NGF / GF_PER), dim3(256), 0, s, G, R, in, st);
+}
+
 int launch_brill_lindquist(const GridDev& G, int n, const double* m, const double* pos, int lapse_kind,
                            double* y, hipStream_t s) {
   if (n < 0 || n > MAX_PUNCT) return -1;

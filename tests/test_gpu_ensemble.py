@@ -114,6 +114,14 @@ def test_batch_with_dissipation_matches_solo_bitwise():
     capi.batch_destroy(b)
 
 
+def test_batch_rejects_radiation_grids():
+    _case("batch radiation rejected")
+    from paper_2505_00097_amd import capi
+    g = capi.Grid(wl.SINH_CYLINDRICAL, (16, 2, 32), (20.0,) * 3, (0.2,) * 3, bc_kind=capi.BC_RADIATION)
+    with pytest.raises(capi.BhahError, match="extrapolation"):
+        capi.batch_create([g.h], eta=2.0)
+
+
 def test_batch_active_mask_and_swaps():
     _case("batch active mask")
     import torch

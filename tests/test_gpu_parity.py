@@ -245,6 +245,86 @@ def test_ssprk3_with_dissipation_matches_oracle(name, m, pos, steps):
     assert np.all(err <= tol), fmt(orc.GF_NAMES, err / tol)
 
 
+def _pair_radiation(name):
+    from paper_2505_00097_amd import capi
+    coord, N, ampl, w = GRIDS[name]
+    return (capi.Grid(coord, N, ampl, w, bc_kind=capi.BC_RADIATION),
+            orc.Grid(coord, N, ampl=ampl, sinhw=w, bc_kind=1))
+
+
+@pytest.mark.parametrize("name", ["tiny", "cyl_ragged", "cyl_3d", "spherical"])
+def test_radiation_rhs_matches_oracle(name):
+    """With the Sommerfeld outer boundary the right-hand side covers the
+    pure-outer points too: both against the oracle."""
+    from paper_2505_00097_amd import capi
+    g, og = _pair_radiation(name)
+    kind, _, _ = g.bc_maps()
+    k = kind.reshape(og.n[2], og.n[1], og.n[0])
+    pts = (k == 0) | (k == 1)
+    outer = k == 1
+    bl = og.apply_bcs(og.brill_lindquist([0.5, 0.3], [(0.1, 0.0, 0.4), (0.0, -0.1, -0.5)]))
+    for label, y in (("bl", bl), ("smooth_random", og.apply_bcs(wl.smooth_random_state(og.n, seed=21)))):
+        _print_case("rhs_radiation", name, label)
+        ref = og.rhs(y, eta=2.0)
+        yg = to_gpu(y)
+        r = g.state()
+        r.zero_()
+        capi.bssn_rhs(g.h, yg, r, eta=2.0)
+        out = to_cpu(r)
+        err = gf_errors(out, ref, pts)
+        floor = rounding_floor(lambda v: og.rhs(v, eta=2.0), y, lambda a, b: gf_errors(a, b, pts))
+        tol = np.maximum(RHS_TOL, floor)
+        print("  err", fmt(orc.GF_NAMES, err), flush=True)
+        assert np.all(err <= tol), (label, fmt(orc.GF_NAMES, err / tol))
+        # the outer points on their own, against their own magnitude
+        eo = gf_errors(out, ref, outer)
+        assert np.all(eo <= np.maximum(RHS_TOL, rounding_floor(lambda v: og.rhs(v, eta=2.0), y,
+                                                                lambda a, b: gf_errors(a, b, outer)))), eo
+
+
+@pytest.mark.parametrize("name,steps", [("tiny", 100), ("cyl_ragged", 60)])
+def test_radiation_rk4_evolution_matches_oracle(name, steps):
+    _print_case("evolve_radiation", name, steps)
+    from paper_2505_00097_amd import capi
+    g, og = _pair_radiation(name)
+    m, pos = [0.5, 0.5], [(0, 0, 0.5), (0, 0, -0.5)]
+    y = g.state()
+    capi.set_initial_data_brill_lindquist(g.h, m, pos, y)
+    ws = g.workspace()
+    yo = og.brill_lindquist(m, np.array(pos).reshape(-1, 3))
+    dt = og.dt()
+    for _ in range(steps):
+        capi.rk4_step(g.h, y, ws, dt, eta=2.0)
+        og.rk4_step(yo, dt, eta=2.0)
+    out = to_cpu(y)
+    err = gf_errors(out, yo, (slice(None),) * 3)  # every point, ghosts included
+    print("  err", fmt(orc.GF_NAMES, err), flush=True)
+    assert np.all(err <= EVOL_TOL), fmt(orc.GF_NAMES, err)
+
+
+def test_production_numerics_match_oracle():
+    """The head-on run's numerics of Sec. 4.2 at 4th order: SSPRK3, Kreiss-
+    Oliger dissipation 0.99 / 0.3 and the Sommerfeld outer boundary."""
+    _print_case("evolve_production", "cyl_ragged", 40)
+    from paper_2505_00097_amd import capi
+    coord, N, ampl, w = GRIDS["cyl_ragged"]
+    g = capi.Grid(coord, N, ampl, w, bc_kind=capi.BC_RADIATION)
+    og = orc.Grid(coord, N, ampl=ampl, sinhw=w, bc_kind=1, diss=DISS)
+    m, pos = [0.5, 0.5], [(0, 0, 0.5), (0, 0, -0.5)]
+    y = g.state()
+    capi.set_initial_data_brill_lindquist(g.h, m, pos, y)
+    ws = g.workspace()
+    yo = og.brill_lindquist(m, np.array(pos).reshape(-1, 3))
+    dt = og.dt()
+    for _ in range(40):
+        capi.ssprk3_step(g.h, y, ws, dt, eta=2.0, diss=DISS)
+        og.ssprk3_step(yo, dt, eta=2.0)
+    out = to_cpu(y)
+    err = gf_errors(out, yo, (slice(None),) * 3)
+    print("  err", fmt(orc.GF_NAMES, err), flush=True)
+    assert np.all(err <= EVOL_TOL), fmt(orc.GF_NAMES, err)
+
+
 def test_rhs_is_deterministic():
     _print_case("determinism")
     g, og = _pair("sph_ragged")
