@@ -158,7 +158,9 @@ enum { PK_PC = 0, PK_QS = 6, PK_Y = 9, PK_ZA = 15, PK_BV = 16, PK_BD = 19, PK_RT
        PK_DH = PK_OUT, PK_D1 = 55, PK_ADV = 70 };
 static_assert(PK_ADV + 8 == PARK && PK_DH + 18 <= PK_OUT + G_VETU0, "park layout");
 
-template <int C, bool AX, bool KO>
+// MIX: the epilogue also handles stages that mix two states (SSPRK3); the
+// ensemble kernel, which runs RK4 stages only, is built without it.
+template <int C, bool AX, bool KO, bool MIX>
 __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, const double* __restrict__ y,
                                             const StageArgs& st, int i0, int i1, int i2, unsigned q,
                                             double* __restrict__ aux, double* __restrict__ park) {
@@ -808,7 +810,7 @@ __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, c
     // base2 and out2 are Cacc at the same point; SSPRK3 mixes y with A or B
     // into B or y), but the compiler cannot know it and would otherwise put
     // each load behind the stores before it.
-    const bool two = st.out2 != nullptr, mix = !two && st.base2 != nullptr, same = st.base2 == st.base1;
+    const bool two = st.out2 != nullptr, mix = MIX && !two && st.base2 != nullptr, same = st.base2 == st.base1;
     double b1[NGF], b2[NGF];
 #pragma unroll
     for (int g = 0; g < NGF; g++) b1[g] = gf_ld(st.base1, G.sgf, g, q * 8u, 0);
@@ -890,7 +892,7 @@ k_rhs_fused(GridDev G, TileMap T, Gauge ga, const double* __restrict__ y, StageA
   if (!tile_point(G, T, w, (int)threadIdx.x, i0, i1, i2)) return;
   const unsigned q = (unsigned)(i0 + G.s1 * i1 + G.s2 * i2);
   __shared__ double park[PARK * 64];
-  fused_point<C, AX, KO>(G, ga, y, st, i0, i1, i2, q, aux, park + threadIdx.x);
+  fused_point<C, AX, KO, true>(G, ga, y, st, i0, i1, i2, q, aux, park + threadIdx.x);
 }
 
 // Persistent form for ensembles: a fixed grid of blocks (a multiple of the XCD
@@ -914,7 +916,7 @@ k_rhs_batch(const BatchJob* __restrict__ jobs, const BatchHdr* __restrict__ hdr,
     if (!tile_point(G, J->T, wk.y, (int)threadIdx.x, i0, i1, i2)) continue;
     const unsigned q = (unsigned)(i0 + G.s1 * i1 + G.s2 * i2);
     const StageArgs st = J->st[stage];
-    fused_point<C, AX, KO>(G, ga, J->in[stage], st, i0, i1, i2, q, nullptr, park + threadIdx.x);
+    fused_point<C, AX, KO, false>(G, ga, J->in[stage], st, i0, i1, i2, q, nullptr, park + threadIdx.x);
   }
 }
 
