@@ -108,8 +108,8 @@ typedef struct bhah_batch bhah_batch; /* opaque ensemble of grids        */
 /* Grid parameters. nghosts must be 3 (4th-order FD with upwinded advection
  * needs N_FD/2 + 1 ghost layers, Sec. 3 and Sec. 4.2.1). ampl[]/sinhw[]
  * entries for directions without a map are ignored. cfl scales the time step
- * (Sec. 4.1 uses 0.5). bc_kind: BHAH_BC_EXTRAP or BHAH_BC_RADIATION (the
- * ensemble and the server take extrapolation grids only).                   */
+ * (Sec. 4.1 uses 0.5). bc_kind: BHAH_BC_EXTRAP or BHAH_BC_RADIATION (both
+ * in solo calls, ensembles and the server).                                 */
 typedef struct {
   int coord;
   int N[3];

@@ -316,10 +316,10 @@ def server_create(budget_bytes, max_jobs, steps_per_tick=10, keep_results=False,
     return s
 
 
-def job_desc(coord, N, ampl, sinhw, cfl, masses, positions, nsteps, lapse_kind=0):
+def job_desc(coord, N, ampl, sinhw, cfl, masses, positions, nsteps, lapse_kind=0, bc_kind=0):
     d = JobDesc()
     d.grid = GridParams(int(coord), (ctypes.c_int * 3)(*N), 3, (ctypes.c_double * 3)(*ampl),
-                        (ctypes.c_double * 3)(*sinhw), float(cfl), 0)
+                        (ctypes.c_double * 3)(*sinhw), float(cfl), int(bc_kind))
     d.n_punct = len(masses)
     for i, (m, x) in enumerate(zip(masses, positions)):
         d.masses[i] = float(m)

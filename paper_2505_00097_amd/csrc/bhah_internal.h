@@ -147,6 +147,7 @@ struct TileMap {
 struct BatchJob {
   GridDev G;
   GhostDev gh[2];  // ghosts with an interior phi index; all ghosts
+  RadDev rad;      // outer points evolved by the radiation condition (n = 0 otherwise)
   TileMap T;
   StageArgs st[5];
   const double* in[5];
@@ -156,12 +157,13 @@ struct BatchJob {
 // Work list header: the (job, tile) list of kernel variant v (rhs_variant)
 // starts at tile_off[v] and holds n_tiles[v] entries; the (job, chunk of 256 ghost
 // points) list of ghost list w (as BatchJob::gh) starts at chunk_off[w] and
-// holds n_chunks[w] entries.
+// holds n_chunks[w] entries; chunk list 2 is the (job, chunk of 256
+// radiation points) list.
 struct BatchHdr {
   int n_tiles[NVAR];
   int tile_off[NVAR];
-  int n_chunks[2];
-  int chunk_off[2];
+  int n_chunks[3];
+  int chunk_off[3];
 };
 
 // Ghost classification of a point from the closed-form index reflections
@@ -255,6 +257,8 @@ void launch_hamiltonian(const GridDev& G, const double* y, double* H, hipStream_
 // radiation condition at the pure-outer points of one stage: the right-hand
 // side of `in` combined as in st (same semantics as the RHS kernel)
 void launch_radiation(const GridDev& G, const RadDev& R, const double* in, const StageArgs& st, hipStream_t s);
+void launch_radiation_batch(const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage, int blocks,
+                            hipStream_t s);
 void launch_constraints(const GridDev& G, const double* y, double* H, double* Mo, double* Co, hipStream_t s);
 
 // The four stages of one classical RK4 step on state y with workspace ws

@@ -77,8 +77,6 @@ int Engine::set_jobs(const std::vector<EngineJob>& jobs) {
   for (const EngineJob& j : jobs) {
     if (!j.g || !j.y || !j.ws) return fail(BHAH_EINVAL, "batch: NULL grid, state or workspace");
     if (j.g->params.coord < 0 || j.g->params.coord > 2) return fail(BHAH_EINVAL, "batch: bad coordinate family");
-    if (j.g->params.bc_kind != BHAH_BC_EXTRAP)
-      return fail(BHAH_EINVAL, "batch: only extrapolation outer boundaries (no radiation) in ensembles");
   }
   if (jobs != jobs_) {
     jobs_ = jobs;
@@ -120,7 +118,7 @@ int Engine::ensure_device(hipStream_t s) {
 void Engine::drop_graphs() {
   for (auto& kv : graphs_) (void)hipGraphExecDestroy(kv.second);
   graphs_.clear();
-  for (int f = 0; f < NVAR; f++) fam_in_graphs_[f] = false;
+  for (int f = 0; f <= NVAR; f++) fam_in_graphs_[f] = false;
 }
 
 // Fill the host blob: header, job table (all jobs) and work lists of the
@@ -138,7 +136,8 @@ void Engine::build_blob(const std::vector<TileCfg>& cfg, const std::vector<int>&
     maps[j] = make_tilemap(jobs_[j].g->dev, cfg[j].lx, cfg[j].ly, cfg[j].band);
   for (int j : sel) {
     nt += maps[j].ntiles * repeat;
-    nc += (jobs_[j].g->ghost_stage.n_ghost + 255) / 256 + (jobs_[j].g->ghost.n_ghost + 255) / 256;
+    const JobLists l = lists_of(j);
+    nc += (l.gh[0].n_ghost + 255) / 256 + (l.gh[1].n_ghost + 255) / 256 + (l.rad.n + 255) / 256;
   }
   // the previous upload must have left the pinned buffer before it is reused
   if (upload_done_) (void)hipEventSynchronize(upload_done_);
@@ -171,8 +170,10 @@ void Engine::build_blob(const std::vector<TileCfg>& cfg, const std::vector<int>&
     const EngineJob& e = jobs_[j];
     BatchJob& b = J[j];
     b.G = e.g->dev;
-    b.gh[0] = e.g->ghost_stage;
-    b.gh[1] = e.g->ghost;
+    const JobLists l = lists_of(j);
+    b.gh[0] = l.gh[0];
+    b.gh[1] = l.gh[1];
+    b.rad = l.rad;
     b.T = maps[j];
     const double* in[4];
     double* gd[4];
@@ -198,15 +199,17 @@ void Engine::build_blob(const std::vector<TileCfg>& cfg, const std::vector<int>&
     fam_present_[f] = hdr->n_tiles[f] > 0 || fam_present_[f];
   }
   int cpos = 0;
-  for (int w = 0; w < 2; w++) {
+  for (int w = 0; w < 3; w++) {
     hdr->chunk_off[w] = cpos;
     for (int j : sel) {
-      const GhostDev& gh = w == 0 ? jobs_[j].g->ghost_stage : jobs_[j].g->ghost;
-      const int n = (gh.n_ghost + 255) / 256;
+      const JobLists l = lists_of(j);
+      const int pts = w < 2 ? l.gh[w].n_ghost : l.rad.n;
+      const int n = (pts + 255) / 256;
       for (int c = 0; c < n; c++) chunks[cpos++] = int2{j, c};
     }
     hdr->n_chunks[w] = cpos - hdr->chunk_off[w];
   }
+  fam_present_[NVAR] = hdr->n_chunks[2] > 0 || fam_present_[NVAR];
   n_tiles_ = pos;
   n_chunks_ = cpos;
   blob_bytes_ = (size_t)(L.chunks + sizeof(int2) * (size_t)cpos);
@@ -303,6 +306,8 @@ int Engine::capture(int nsteps, hipStream_t s, hipGraphExec_t* out) {
     for (int stage = 0; stage < 4; stage++) {
       for (int f = 0; f < NVAR; f++)
         if (fam_present_[f]) launch_rhs_batch(f, dj, dh, dt, stage, gauge_of(gp_), rhs_blocks_, cap_stream_);
+      // outer points of radiation-boundary jobs, before their inner ghosts are copied
+      if (fam_present_[NVAR]) launch_radiation_batch(dj, dh, dc, stage, ghost_blocks_, cap_stream_);
       const int which = stage == 3 && k == nsteps - 1 ? 1 : 0;
       launch_ghosts_batch(dj, dh, dc, stage, which, ghost_blocks_, cap_stream_);
     }
@@ -316,7 +321,7 @@ int Engine::capture(int nsteps, hipStream_t s, hipGraphExec_t* out) {
   }
   rc = check_hip(hipGraphInstantiate(out, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
   (void)hipGraphDestroy(graph);
-  for (int f = 0; f < NVAR; f++) fam_in_graphs_[f] = fam_present_[f];
+  for (int f = 0; f <= NVAR; f++) fam_in_graphs_[f] = fam_present_[f];
   return rc;
 }
 
@@ -333,7 +338,7 @@ int Engine::step(int nsteps, hipStream_t s) {
     if ((rc = upload(s))) return rc;
     dirty_ = false;
   }
-  for (int f = 0; f < NVAR; f++)
+  for (int f = 0; f <= NVAR; f++)
     if (fam_present_[f] && !fam_in_graphs_[f]) drop_graphs();
   while (nsteps > 0) {
     const int k = std::min(nsteps, graph_steps_);

@@ -90,8 +90,22 @@ class Engine {
   int cap_jobs_ = 0, cap_tiles_ = 0, cap_chunks_ = 0;
   hipEvent_t upload_done_ = nullptr;
   int n_tiles_ = 0, n_chunks_ = 0;
-  bool fam_present_[NVAR] = {};    // kernel variants with tiles in some blob
-  bool fam_in_graphs_[NVAR] = {};  // ... and in the captured graphs
+  // kernel variants with tiles in some blob (entry NVAR: radiation points)
+  bool fam_present_[NVAR + 1] = {};
+  bool fam_in_graphs_[NVAR + 1] = {};  // ... and in the captured graphs
+  // the ghost lists refilled after a stage (gh[0]: ghosts with an interior
+  // phi index, gh[1]: all) and the radiation points of job j: a
+  // radiation-boundary grid refills only its inner ghosts (one-hop copies)
+  // and evolves its outer points
+  struct JobLists {
+    GhostDev gh[2];
+    RadDev rad;
+  };
+  JobLists lists_of(int j) const {
+    const bhah_grid* g = jobs_[j].g;
+    if (g->params.bc_kind == BHAH_BC_RADIATION) return JobLists{{g->ghost_inner_stage, g->ghost_inner}, g->rad};
+    return JobLists{{g->ghost_stage, g->ghost}, RadDev{}};
+  }
 
   int rhs_blocks_ = 0, ghost_blocks_ = 0;
   int blocks_per_cu_ = 4;

@@ -122,11 +122,8 @@ __constant__ double kRadW[5][5] = {
     {-25.0 / 12, 48.0 / 12, -36.0 / 12, 16.0 / 12, -3.0 / 12}  // nodes 0..4
 };
 
-__global__ void __launch_bounds__(256) k_radiation(GridDev G, RadDev R, const double* __restrict__ in,
-                                                   StageArgs st) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= R.n) return;
-  const int g0 = (int)blockIdx.y * GF_PER;
+__device__ __forceinline__ void radiation_point(const GridDev& G, const RadDev& R, int t,
+                                                const double* __restrict__ in, const StageArgs& st, int g0) {
   const long long q = R.q[t];
   const int sh = R.shift[t];
   const int s0 = (sh & 15) - 4, s2 = ((sh >> 4) & 15) - 4;
@@ -164,9 +161,36 @@ __global__ void __launch_bounds__(256) k_radiation(GridDev G, RadDev R, const do
   }
 }
 
+__global__ void __launch_bounds__(256) k_radiation(GridDev G, RadDev R, const double* __restrict__ in,
+                                                   StageArgs st) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < R.n) radiation_point(G, R, t, in, st, (int)blockIdx.y * GF_PER);
+}
+
 void launch_radiation(const GridDev& G, const RadDev& R, const double* in, const StageArgs& st, hipStream_t s) {
   if (R.n == 0) return;
   hipLaunchKernelGGL(k_radiation, dim3((R.n + 255) / 256, NGF / GF_PER), dim3(256), 0, s, G, R, in, st);
+}
+
+// Ensemble form: blocks stride over the (job, chunk of 256 radiation points)
+// list; each job's stage input and combination come from its table entry.
+__global__ void __launch_bounds__(256) k_radiation_batch(const BatchJob* __restrict__ jobs,
+                                                         const BatchHdr* __restrict__ hdr,
+                                                         const int2* __restrict__ work, int stage) {
+  const int n = hdr->n_chunks[2];
+  const int2* wl = work + hdr->chunk_off[2];
+  const int g0 = (int)blockIdx.y * GF_PER;
+  for (int c = (int)blockIdx.x; c < n; c += (int)gridDim.x) {
+    const int2 wk = wl[c];
+    const BatchJob* J = jobs + wk.x;
+    const int t = wk.y * 256 + (int)threadIdx.x;
+    if (t < J->rad.n) radiation_point(J->G, J->rad, t, J->in[stage], J->st[stage], g0);
+  }
+}
+
+void launch_radiation_batch(const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage, int blocks,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_radiation_batch, dim3(blocks, NGF / GF_PER), dim3(256), 0, s, jobs, hdr, work, stage);
 }
 
 int launch_brill_lindquist(const GridDev& G, int n, const double* m, const double* pos, int lapse_kind,

@@ -114,12 +114,53 @@ def test_batch_with_dissipation_matches_solo_bitwise():
     capi.batch_destroy(b)
 
 
-def test_batch_rejects_radiation_grids():
-    _case("batch radiation rejected")
+def test_batch_with_radiation_grids_matches_solo_bitwise():
+    """Grids with the Sommerfeld outer boundary in an ensemble, mixed with
+    extrapolation grids of the same shapes: each job equals its solo
+    evolution bit for bit (outer points evolved by the same device code,
+    inner ghosts copied from the one-hop lists)."""
+    _case("batch radiation")
+    import torch
     from paper_2505_00097_amd import capi
-    g = capi.Grid(wl.SINH_CYLINDRICAL, (16, 2, 32), (20.0,) * 3, (0.2,) * 3, bc_kind=capi.BC_RADIATION)
-    with pytest.raises(capi.BhahError, match="extrapolation"):
-        capi.batch_create([g.h], eta=2.0)
+    jobs = _small_jobs()
+    grids, ys, wss = _setup(jobs)
+    # a radiation-boundary twin of every grid, with the same initial data
+    rgrids = [capi.Grid(j["coord"], j["N"], j["ampl"], j["sinhw"], j["cfl"], bc_kind=capi.BC_RADIATION)
+              for j in jobs]
+    rys = [y.clone() for y in ys]
+    rwss = [g.workspace() for g in rgrids]
+    allg, ally, allw = grids + rgrids, ys + rys, wss + rwss
+    y0 = [y.clone() for y in ally]
+    b = capi.batch_create([g.h for g in allg], eta=2.0)
+    capi.batch_set_graph_steps(b, 3)
+    capi.batch_step(b, ally, allw, [g.dt for g in allg], nsteps=7)
+    torch.cuda.synchronize()
+    solo = _solo(allg, y0, [7] * len(allg))
+    for k, (y, s) in enumerate(zip(ally, solo)):
+        assert torch.equal(y, s), k
+    # the two boundary kinds really differ
+    assert not torch.equal(ally[0], ally[len(jobs)])
+    capi.batch_destroy(b)
+
+
+def test_server_runs_radiation_jobs():
+    _case("server radiation")
+    import torch
+    from paper_2505_00097_amd import capi
+    j = _server_jobs()[0]
+    srv = capi.server_create(1e10, max_jobs=2, steps_per_tick=3, keep_results=True)
+    i = capi.server_submit(srv, capi.job_desc(j["coord"], j["N"], j["ampl"], j["sinhw"], j["cfl"], j["masses"],
+                                              j["positions"], 8, bc_kind=capi.BC_RADIATION))
+    while capi.server_job_status(srv, i).state != capi.JOB_DONE:
+        capi.server_tick(srv)
+    g = capi.Grid(j["coord"], j["N"], j["ampl"], j["sinhw"], j["cfl"], bc_kind=capi.BC_RADIATION)
+    out = g.state()
+    capi.server_fetch(srv, i, out)
+    y = g.state()
+    capi.set_initial_data_brill_lindquist(g.h, j["masses"], j["positions"], y)
+    (s,) = _solo([g], [y], [8])
+    assert torch.equal(out, s)
+    capi.server_destroy(srv)
 
 
 def test_batch_active_mask_and_swaps():

@@ -325,6 +325,34 @@ def test_production_numerics_match_oracle():
     assert np.all(err <= EVOL_TOL), fmt(orc.GF_NAMES, err)
 
 
+def test_production_numerics_full_size_headon():
+    """The benchmark's production-numerics leg at full size: the head-on
+    workload (SinhCylindrical 128x2x256) with SSPRK3, Kreiss-Oliger 0.99 /
+    0.3 and the Sommerfeld outer boundary, tuned tile shape, 30 steps,
+    against the oracle over every point."""
+    name = "headon_sinhcylindrical_128x2x256"
+    _print_case("evolve_production_full", name, 30)
+    from paper_2505_00097_amd import capi
+    w = wl.WORKLOADS[name]
+    g = capi.Grid(w["coord"], w["N"], w["ampl"], w["sinhw"], w["cfl"], bc_kind=capi.BC_RADIATION)
+    og = orc.Grid(w["coord"], w["N"], ampl=w["ampl"], sinhw=w["sinhw"], cfl=w["cfl"], bc_kind=1, diss=DISS)
+    y = g.state()
+    capi.set_initial_data_brill_lindquist(g.h, w["masses"], w["positions"], y)
+    capi.grid_tune(g.h, y, g.state(), diss=DISS)
+    ws = g.workspace()
+    yo = og.brill_lindquist(w["masses"], w["positions"])
+    dt = og.dt()
+    for s in range(30):
+        capi.ssprk3_step(g.h, y, ws, dt, eta=w["eta"], diss=DISS)
+        og.ssprk3_step(yo, dt, eta=w["eta"])
+        if s % 10 == 9:
+            print("  step", s + 1, flush=True)
+    out = to_cpu(y)
+    err = gf_errors(out, yo, (slice(None),) * 3)
+    print("  err", fmt(orc.GF_NAMES, err), flush=True)
+    assert np.all(err <= EVOL_TOL), fmt(orc.GF_NAMES, err)
+
+
 def test_rhs_is_deterministic():
     _print_case("determinism")
     g, og = _pair("sph_ragged")
