@@ -259,9 +259,11 @@ int bhah_hamiltonian_constraint(const bhah_grid* g, const double* y, double* H,
 /* ---- ensembles: many independent grids advanced together ---------------- *
  * A batch advances n independent grids (jobs) that share gauge parameters.
  * It is the ensemble form of bhah_rk4_step: per stage, one persistent
- * right-hand-side kernel per coordinate family strides over a (job, tile)
- * work list covering every active job, and one ghost-fill kernel over a
- * (job, ghost chunk) list; a step count's worth of stages is captured once
+ * right-hand-side kernel per kernel variant (coordinate family, two phi
+ * planes or more) strides over a (job, tile) work list covering every active
+ * job, one kernel evolves the outer points of radiation-boundary jobs, and
+ * one ghost-fill kernel runs over a (job, ghost chunk) list; the grids may
+ * mix both outer-boundary kinds. A step count's worth of stages is captured once
  * in a hipGraph and replayed. The per-point arithmetic is the same device
  * code as bhah_rk4_step, so each job's result equals its solo evolution
  * bit for bit. Tile shapes are chosen per size class (coordinate family and
