@@ -84,6 +84,10 @@ enum { BHAH_SINH_SPHERICAL = 0, BHAH_SINH_CYLINDRICAL = 1, BHAH_SPHERICAL = 2 };
  * bhah_apply_bcs always uses the extrapolation (initial fill of any grid). */
 enum { BHAH_BC_EXTRAP = 0, BHAH_BC_RADIATION = 1 };
 
+/* ---- time integrators of ensembles and the server ---------------------- *
+ * BHAH_RK4: as bhah_rk4_step; BHAH_SSPRK3: as bhah_ssprk3_step.            */
+enum { BHAH_RK4 = 0, BHAH_SSPRK3 = 1 };
+
 /* ---- the 24 evolved rescaled gridfunctions (Sec. 2.1 last gauge paragraph;
  * rescaling Sec. 2.2): h_ij = eps_ij/(S_i S_j), a_ij = Abar_ij/(S_i S_j),
  * lambda^i = S_i Lambdabar^i, vet^i = S_i beta^i, bet^i = S_i B^i,
@@ -298,6 +302,12 @@ int bhah_batch_step(bhah_batch* b, double* const* y, double* const* ws,
 /* RK4 steps captured per graph (default 10; larger step counts replay it). */
 int bhah_batch_set_graph_steps(bhah_batch* b, int steps);
 
+/* Time integrator of the batch's steps: BHAH_RK4 (the default) or
+ * BHAH_SSPRK3. Each job then equals its solo bhah_rk4_step /
+ * bhah_ssprk3_step evolution bit for bit. Takes effect at the next
+ * bhah_batch_step (the captured graphs are rebuilt). BHAH_EINVAL otherwise. */
+int bhah_batch_set_integrator(bhah_batch* b, int integrator);
+
 /* Launch shape of the right-hand-side kernel: blocks_per_cu > 0 runs that
  * many persistent 64-lane blocks per compute unit striding over the work
  * list (default 4: one wave per SIMD); 0 launches one block per tile.       */
@@ -345,6 +355,7 @@ typedef struct {
                                lengthens every running job's step           */
   bhah_gauge_params gauge;
   const char* tune_cache_path; /* may be NULL                                 */
+  int integrator;           /* BHAH_RK4 or BHAH_SSPRK3                        */
 } bhah_server_params;
 
 typedef struct {

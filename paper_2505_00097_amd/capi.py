@@ -15,6 +15,7 @@ NUM_AUX_GFS = 9
 SINH_SPHERICAL, SINH_CYLINDRICAL, SPHERICAL = 0, 1, 2
 OK, EINVAL, EDEVICE, ENOMEM = 0, -1, -2, -3
 BC_EXTRAP, BC_RADIATION = 0, 1  # outer boundary kinds (bhah_grid_params.bc_kind)
+RK4, SSPRK3 = 0, 1  # integrators of ensembles and the server
 GF_NAMES = ["aDD00", "aDD01", "aDD02", "aDD11", "aDD12", "aDD22", "alpha",
             "betU0", "betU1", "betU2", "cf", "hDD00", "hDD01", "hDD02", "hDD11",
             "hDD12", "hDD22", "lambdaU0", "lambdaU1", "lambdaU2", "trK",
@@ -50,7 +51,7 @@ class ServerParams(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_double), ("max_jobs", ctypes.c_int),
                 ("steps_per_tick", ctypes.c_int), ("keep_results", ctypes.c_int),
                 ("target_points", ctypes.c_longlong),
-                ("gauge", GaugeParams), ("tune_cache_path", ctypes.c_char_p)]
+                ("gauge", GaugeParams), ("tune_cache_path", ctypes.c_char_p), ("integrator", ctypes.c_int)]
 
 
 class JobDesc(ctypes.Structure):
@@ -116,6 +117,7 @@ _SIGS = {
     "bhah_server_destroy": (None, [_vp]),
     "bhah_probe_peaks": (ctypes.c_int, [_vp, _vp, _vp]),
     "bhah_ssprk3_step": (ctypes.c_int, [_vp, ctypes.POINTER(GaugeParams), ctypes.c_double, _vp, _vp, _vp]),
+    "bhah_batch_set_integrator": (ctypes.c_int, [_vp, ctypes.c_int]),
 }
 
 
@@ -286,6 +288,10 @@ def batch_set_graph_steps(b, steps):
     _check(lib().bhah_batch_set_graph_steps(b, int(steps)), "bhah_batch_set_graph_steps")
 
 
+def batch_set_integrator(b, integrator):
+    _check(lib().bhah_batch_set_integrator(b, int(integrator)), "bhah_batch_set_integrator")
+
+
 def batch_set_blocks_per_cu(b, blocks_per_cu):
     _check(lib().bhah_batch_set_blocks_per_cu(b, int(blocks_per_cu)), "bhah_batch_set_blocks_per_cu")
 
@@ -308,9 +314,10 @@ def batch_destroy(b):
 
 
 def server_create(budget_bytes, max_jobs, steps_per_tick=10, keep_results=False, eta=2.0,
-                  tune_cache_path=None, stream=None, target_points=0, diss=(0.0, 0.0)):
+                  tune_cache_path=None, stream=None, target_points=0, diss=(0.0, 0.0), integrator=RK4):
     p = ServerParams(float(budget_bytes), int(max_jobs), int(steps_per_tick), 1 if keep_results else 0,
-                     int(target_points), gauge(eta, diss), tune_cache_path.encode() if tune_cache_path else None)
+                     int(target_points), gauge(eta, diss), tune_cache_path.encode() if tune_cache_path else None,
+                     int(integrator))
     s = _vp()
     _check(lib().bhah_server_create(ctypes.byref(p), _stream(stream), ctypes.byref(s)), "bhah_server_create")
     return s

@@ -51,6 +51,13 @@ int bhah_batch_set_graph_steps(bhah_batch* b, int steps) {
   return BHAH_OK;
 }
 
+int bhah_batch_set_integrator(bhah_batch* b, int integrator) {
+  if (!b || (integrator != BHAH_RK4 && integrator != BHAH_SSPRK3))
+    return bhah::fail(BHAH_EINVAL, "bhah_batch_set_integrator: need a batch and BHAH_RK4 or BHAH_SSPRK3");
+  b->engine.set_integrator(integrator);
+  return BHAH_OK;
+}
+
 int bhah_batch_set_blocks_per_cu(bhah_batch* b, int blocks_per_cu) {
   if (!b || blocks_per_cu < 0) return bhah::fail(BHAH_EINVAL, "bhah_batch_set_blocks_per_cu: bad argument");
   b->engine.set_blocks_per_cu(blocks_per_cu);

@@ -249,8 +249,9 @@ int launch_brill_lindquist(const GridDev& G, int n, const double* m, const doubl
 void launch_rhs_fused(const GridDev& G, const Gauge& ga, const double* y, double* aux, const StageArgs& st,
                       hipStream_t s, const TileCfg& cfg);
 TileMap make_tilemap(const GridDev& G, int lx, int ly, int band);
+// mix: the stages may combine two states (SSPRK3); RK4 stages never do
 void launch_rhs_batch(int variant, const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage,
-                      const Gauge& ga, int blocks, hipStream_t s);
+                      const Gauge& ga, bool mix, int blocks, hipStream_t s);
 void launch_ghosts_batch(const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage, int which,
                          int blocks, hipStream_t s);
 void launch_hamiltonian(const GridDev& G, const double* y, double* H, hipStream_t s);

@@ -175,9 +175,14 @@ void Engine::build_blob(const std::vector<TileCfg>& cfg, const std::vector<int>&
     b.gh[1] = l.gh[1];
     b.rad = l.rad;
     b.T = maps[j];
-    const double* in[4];
-    double* gd[4];
-    rk4_stages(e.dt, e.y, e.ws, e.g->info.state_doubles, b.st, in, gd);
+    const double* in[4] = {nullptr, nullptr, nullptr, nullptr};
+    double* gd[4] = {nullptr, nullptr, nullptr, nullptr};
+    if (integrator_ == BHAH_SSPRK3) {
+      ssprk3_stages(e.dt, e.y, e.ws, e.g->info.state_doubles, b.st, in, gd);
+      b.st[3] = StageArgs{};
+    } else {
+      rk4_stages(e.dt, e.y, e.ws, e.g->info.state_doubles, b.st, in, gd);
+    }
     for (int k = 0; k < 4; k++) {
       b.in[k] = in[k];
       b.gdst[k] = gd[k];
@@ -249,9 +254,9 @@ int Engine::time_class(const SizeClass& c, const TileCfg& cfg, hipStream_t s, do
   if ((rc = check_hip(hipEventCreate(&e1), "hipEventCreate"))) { (void)hipEventDestroy(e0); return rc; }
   const int reps = 3;
   const int blocks = rhs_grid();
-  launch_rhs_batch(variant, dj, dh, dt, 4, gauge_of(gp_), blocks, s);
+  launch_rhs_batch(variant, dj, dh, dt, 4, gauge_of(gp_), false, blocks, s);
   (void)hipEventRecord(e0, s);
-  for (int r = 0; r < reps; r++) launch_rhs_batch(variant, dj, dh, dt, 4, gauge_of(gp_), blocks, s);
+  for (int r = 0; r < reps; r++) launch_rhs_batch(variant, dj, dh, dt, 4, gauge_of(gp_), false, blocks, s);
   (void)hipEventRecord(e1, s);
   rc = check_hip(hipEventSynchronize(e1), "tile timing");
   float ms = 0.f;
@@ -302,13 +307,16 @@ int Engine::capture(int nsteps, hipStream_t s, hipGraphExec_t* out) {
   // The stencils never read phi ghost planes (they wrap phi onto the
   // interior), so within the captured steps only the ghosts with an interior
   // phi index are filled; the last stage of the last step fills all of them.
+  const int nst = integrator_ == BHAH_SSPRK3 ? 3 : 4;
   for (int k = 0; k < nsteps; k++)
-    for (int stage = 0; stage < 4; stage++) {
+    for (int stage = 0; stage < nst; stage++) {
       for (int f = 0; f < NVAR; f++)
-        if (fam_present_[f]) launch_rhs_batch(f, dj, dh, dt, stage, gauge_of(gp_), rhs_blocks_, cap_stream_);
+        if (fam_present_[f])
+          launch_rhs_batch(f, dj, dh, dt, stage, gauge_of(gp_), integrator_ == BHAH_SSPRK3, rhs_blocks_,
+                           cap_stream_);
       // outer points of radiation-boundary jobs, before their inner ghosts are copied
       if (fam_present_[NVAR]) launch_radiation_batch(dj, dh, dc, stage, ghost_blocks_, cap_stream_);
-      const int which = stage == 3 && k == nsteps - 1 ? 1 : 0;
+      const int which = stage == nst - 1 && k == nsteps - 1 ? 1 : 0;
       launch_ghosts_batch(dj, dh, dc, stage, which, ghost_blocks_, cap_stream_);
     }
   hipGraph_t graph = nullptr;

@@ -41,9 +41,19 @@ class Engine {
 
   // Replace the job set (takes effect at the next step). Returns a status.
   int set_jobs(const std::vector<EngineJob>& jobs);
-  // Advance every job by nsteps RK4 steps on stream s (asynchronous).
+  // Advance every job by nsteps steps of the integrator on stream s
+  // (asynchronous).
   int step(int nsteps, hipStream_t s);
   void set_graph_steps(int S) { graph_steps_ = S < 1 ? 1 : S; }
+  // BHAH_RK4 or BHAH_SSPRK3 (the stage arguments and graphs are rebuilt)
+  void set_integrator(int k) {
+    if (k != integrator_) {
+      drop_graphs();
+      dirty_ = true;
+    }
+    integrator_ = k;
+  }
+  int integrator() const { return integrator_; }
   // persistent blocks of the right-hand-side kernel per compute unit;
   // 0 launches one block per tile instead
   void set_blocks_per_cu(int n) {
@@ -112,6 +122,7 @@ class Engine {
   int n_cus_ = 0;
   int rhs_grid() const;
   int graph_steps_ = 10;
+  int integrator_ = BHAH_RK4;
   std::map<int, hipGraphExec_t> graphs_;
   hipStream_t cap_stream_ = nullptr;
 };

@@ -159,7 +159,8 @@ enum { PK_PC = 0, PK_QS = 6, PK_Y = 9, PK_ZA = 15, PK_BV = 16, PK_BD = 19, PK_RT
 static_assert(PK_ADV + 8 == PARK && PK_DH + 18 <= PK_OUT + G_VETU0, "park layout");
 
 // MIX: the epilogue also handles stages that mix two states (SSPRK3); the
-// ensemble kernel, which runs RK4 stages only, is built without it.
+// ensemble kernel is built with it only for SSPRK3 batches (keeping the
+// two-state path out of RK4 stages saves registers there).
 template <int C, bool AX, bool KO, bool MIX>
 __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, const double* __restrict__ y,
                                             const StageArgs& st, int i0, int i1, int i2, unsigned q,
@@ -898,7 +899,7 @@ k_rhs_fused(GridDev G, TileMap T, Gauge ga, const double* __restrict__ y, StageA
 // Persistent form for ensembles: a fixed grid of blocks (a multiple of the XCD
 // count) strides over one kernel variant's (job, tile) work list; every
 // point runs the same fused_point as above.
-template <int C, bool AX, bool KO>
+template <int C, bool AX, bool KO, bool MIX>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
 k_rhs_batch(const BatchJob* __restrict__ jobs, const BatchHdr* __restrict__ hdr, const int2* __restrict__ work,
             int stage, Gauge ga) {
@@ -916,7 +917,7 @@ k_rhs_batch(const BatchJob* __restrict__ jobs, const BatchHdr* __restrict__ hdr,
     if (!tile_point(G, J->T, wk.y, (int)threadIdx.x, i0, i1, i2)) continue;
     const unsigned q = (unsigned)(i0 + G.s1 * i1 + G.s2 * i2);
     const StageArgs st = J->st[stage];
-    fused_point<C, AX, KO, false>(G, ga, J->in[stage], st, i0, i1, i2, q, nullptr, park + threadIdx.x);
+    fused_point<C, AX, KO, MIX>(G, ga, J->in[stage], st, i0, i1, i2, q, nullptr, park + threadIdx.x);
   }
 }
 
@@ -939,10 +940,10 @@ void launch_fused_t(dim3 g, hipStream_t s, const GridDev& G, const TileMap& T, c
                     const StageArgs& st, double* aux) {
   hipLaunchKernelGGL((k_rhs_fused<C, AX, KO>), g, dim3(64), 0, s, G, T, ga, y, st, aux);
 }
-template <int C, bool AX, bool KO>
+template <int C, bool AX, bool KO, bool MIX>
 void launch_batch_t(dim3 g, hipStream_t s, const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage,
                     const Gauge& ga) {
-  hipLaunchKernelGGL((k_rhs_batch<C, AX, KO>), g, dim3(64), 0, s, jobs, hdr, work, stage, ga);
+  hipLaunchKernelGGL((k_rhs_batch<C, AX, KO, MIX>), g, dim3(64), 0, s, jobs, hdr, work, stage, ga);
 }
 using FusedLaunch = void (*)(dim3, hipStream_t, const GridDev&, const TileMap&, const Gauge&, const double*,
                              const StageArgs&, double*);
@@ -955,13 +956,16 @@ static const FusedLaunch kFused[NVAR][2] = {
     {launch_fused_t<SC, true, false>, launch_fused_t<SC, true, true>},
     {launch_fused_t<SP, false, false>, launch_fused_t<SP, false, true>},
     {launch_fused_t<SP, true, false>, launch_fused_t<SP, true, true>}};
-static const BatchLaunch kBatch[NVAR][2] = {
-    {launch_batch_t<SS, false, false>, launch_batch_t<SS, false, true>},
-    {launch_batch_t<SS, true, false>, launch_batch_t<SS, true, true>},
-    {launch_batch_t<SC, false, false>, launch_batch_t<SC, false, true>},
-    {launch_batch_t<SC, true, false>, launch_batch_t<SC, true, true>},
-    {launch_batch_t<SP, false, false>, launch_batch_t<SP, false, true>},
-    {launch_batch_t<SP, true, false>, launch_batch_t<SP, true, true>}};
+// [variant][dissipation][two-state stages (SSPRK3)]
+#define BHAH_BATCH_ROW(C, AX)                                                                    \
+  {                                                                                              \
+    {launch_batch_t<C, AX, false, false>, launch_batch_t<C, AX, false, true>},                   \
+    { launch_batch_t<C, AX, true, false>, launch_batch_t<C, AX, true, true> }                    \
+  }
+static const BatchLaunch kBatch[NVAR][2][2] = {BHAH_BATCH_ROW(SS, false), BHAH_BATCH_ROW(SS, true),
+                                               BHAH_BATCH_ROW(SC, false), BHAH_BATCH_ROW(SC, true),
+                                               BHAH_BATCH_ROW(SP, false), BHAH_BATCH_ROW(SP, true)};
+#undef BHAH_BATCH_ROW
 
 void launch_rhs_fused(const GridDev& G, const Gauge& ga, const double* y, double* aux, const StageArgs& st,
                       hipStream_t s, const TileCfg& cfg_in) {
@@ -972,8 +976,8 @@ void launch_rhs_fused(const GridDev& G, const Gauge& ga, const double* y, double
 }
 
 void launch_rhs_batch(int variant, const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage,
-                      const Gauge& ga, int blocks, hipStream_t s) {
-  kBatch[variant][ga.ko() ? 1 : 0](dim3(blocks), s, jobs, hdr, work, stage, ga);
+                      const Gauge& ga, bool mix, int blocks, hipStream_t s) {
+  kBatch[variant][ga.ko() ? 1 : 0][mix ? 1 : 0](dim3(blocks), s, jobs, hdr, work, stage, ga);
 }
 
 }  // namespace bhah

@@ -166,9 +166,12 @@ int bhah_server_create(const bhah_server_params* p, void* stream, bhah_server** 
   if (p->max_jobs < 1 || p->steps_per_tick < 1 || !(p->budget_bytes > 0))
     return bhah::fail(BHAH_EINVAL, "bhah_server_create: max_jobs, steps_per_tick and budget must be positive");
   if (int rc = bhah::check_gauge(&p->gauge, "bhah_server_create")) return rc;
+  if (p->integrator != BHAH_RK4 && p->integrator != BHAH_SSPRK3)
+    return bhah::fail(BHAH_EINVAL, "bhah_server_create: integrator must be BHAH_RK4 or BHAH_SSPRK3");
   bhah_server* s = new (std::nothrow) bhah_server(*p, (hipStream_t)stream);
   if (!s) return bhah::fail(BHAH_ENOMEM, "bhah_server_create: host allocation failed");
   s->engine.set_graph_steps(p->steps_per_tick);
+  s->engine.set_integrator(p->integrator);
   *out = s;
   return BHAH_OK;
 }

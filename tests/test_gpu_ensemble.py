@@ -143,12 +143,53 @@ def test_batch_with_radiation_grids_matches_solo_bitwise():
     capi.batch_destroy(b)
 
 
-def test_server_runs_radiation_jobs():
+def test_batch_ssprk3_matches_solo_bitwise():
+    """SSPRK3 ensembles (two-state stage epilogue in the batched kernel),
+    with dissipation and grids of both boundary kinds: each job equals its
+    solo bhah_ssprk3_step evolution bit for bit; switching back to RK4
+    rebuilds the stages."""
+    _case("batch ssprk3")
+    import torch
+    from paper_2505_00097_amd import capi
+    diss = (0.99, 0.3)
+    jobs = _small_jobs()
+    grids, ys, wss = _setup(jobs)
+    rgrids = [capi.Grid(j["coord"], j["N"], j["ampl"], j["sinhw"], j["cfl"], bc_kind=capi.BC_RADIATION)
+              for j in jobs[:3]]
+    allg = grids + rgrids
+    ally = ys + [y.clone() for y in ys[:3]]
+    allw = wss + [g.workspace() for g in rgrids]
+    y0 = [y.clone() for y in ally]
+    b = capi.batch_create([g.h for g in allg], eta=2.0, diss=diss)
+    capi.batch_set_integrator(b, capi.SSPRK3)
+    capi.batch_set_graph_steps(b, 4)
+    capi.batch_step(b, ally, allw, [g.dt for g in allg], nsteps=9)
+    torch.cuda.synchronize()
+    for k, (g, y, a) in enumerate(zip(allg, ally, y0)):
+        s = a.clone()
+        ws = g.workspace()
+        for _ in range(9):
+            capi.ssprk3_step(g.h, s, ws, g.dt, diss=diss)
+        torch.cuda.synchronize()
+        assert torch.equal(y, s), k
+    # back to RK4 on the same batch
+    capi.batch_set_integrator(b, capi.RK4)
+    cur = [y.clone() for y in ally]
+    capi.batch_step(b, ally, allw, [g.dt for g in allg], nsteps=2)
+    solo = _solo(allg, cur, [2] * len(allg), diss=diss)
+    for k, (y, s) in enumerate(zip(ally, solo)):
+        assert torch.equal(y, s), k
+    with pytest.raises(capi.BhahError, match="integrator"):
+        capi.batch_set_integrator(b, 7)
+    capi.batch_destroy(b)
+
+
+def test_server_runs_radiation_jobs_with_ssprk3():
     _case("server radiation")
     import torch
     from paper_2505_00097_amd import capi
     j = _server_jobs()[0]
-    srv = capi.server_create(1e10, max_jobs=2, steps_per_tick=3, keep_results=True)
+    srv = capi.server_create(1e10, max_jobs=2, steps_per_tick=3, keep_results=True, integrator=capi.SSPRK3)
     i = capi.server_submit(srv, capi.job_desc(j["coord"], j["N"], j["ampl"], j["sinhw"], j["cfl"], j["masses"],
                                               j["positions"], 8, bc_kind=capi.BC_RADIATION))
     while capi.server_job_status(srv, i).state != capi.JOB_DONE:
@@ -158,8 +199,11 @@ def test_server_runs_radiation_jobs():
     capi.server_fetch(srv, i, out)
     y = g.state()
     capi.set_initial_data_brill_lindquist(g.h, j["masses"], j["positions"], y)
-    (s,) = _solo([g], [y], [8])
-    assert torch.equal(out, s)
+    ws = g.workspace()
+    for _ in range(8):
+        capi.ssprk3_step(g.h, y, ws, g.dt)
+    torch.cuda.synchronize()
+    assert torch.equal(out, y)
     capi.server_destroy(srv)
 
 
