@@ -353,6 +353,57 @@ def test_production_numerics_full_size_headon():
     assert np.all(err <= EVOL_TOL), fmt(orc.GF_NAMES, err)
 
 
+def test_axisymmetric_evolution_keeps_phi_slices_equal():
+    """phi-independent data on an 8-plane SinhSpherical grid (the general
+    kernel, phi wrapped): after 20 RK4 steps on the GPU every phi slice is
+    bitwise equal and the components with an odd number of phi indices are
+    exactly zero."""
+    _print_case("axisymmetry")
+    import test_oracle_symmetry as sym
+    from paper_2505_00097_amd import capi
+    coord, N, ampl, w = wl.SINH_SPHERICAL, (16, 8, 8), (6.0,) * 3, (0.3,) * 3
+    g = capi.Grid(coord, N, ampl, w)
+    og = orc.Grid(coord, N, ampl=ampl, sinhw=w)
+    y = to_gpu(sym.axisymmetric_bl(og, [0.6, 0.4], [(0, 0, 0.7), (0, 0, -0.6)]))
+    ws = g.workspace()
+    for _ in range(20):
+        capi.rk4_step(g.h, y, ws, g.dt)
+    out = to_cpu(y)
+    for k in range(out.shape[1]):
+        assert np.array_equal(out[:, k], out[:, og.ng]), k
+    for k in sym.ODD_PHI_OR_Z:
+        assert np.max(np.abs(out[k])) == 0.0, orc.GF_NAMES[k]
+
+
+@pytest.mark.parametrize("production", [False, True])
+def test_headon_equatorial_mirror_symmetry(production):
+    """The full-size head-on workload (equal masses at z = +-0.5) stays
+    mirror-symmetric across z = 0 on the GPU: 20 RK4 steps, or 20 steps of
+    the production numerics (SSPRK3, Kreiss-Oliger, radiation boundary)."""
+    name = "headon_sinhcylindrical_128x2x256"
+    _print_case("mirror", name, production)
+    import test_oracle_symmetry as sym
+    from paper_2505_00097_amd import capi
+    w = wl.WORKLOADS[name]
+    g = capi.Grid(w["coord"], w["N"], w["ampl"], w["sinhw"], w["cfl"],
+                  bc_kind=capi.BC_RADIATION if production else capi.BC_EXTRAP)
+    og = orc.Grid(w["coord"], w["N"], ampl=w["ampl"], sinhw=w["sinhw"], cfl=w["cfl"])
+    y = g.state()
+    capi.set_initial_data_brill_lindquist(g.h, w["masses"], w["positions"], y)
+    ws = g.workspace()
+    for _ in range(20):
+        if production:
+            capi.ssprk3_step(g.h, y, ws, g.dt, eta=w["eta"], diss=DISS)
+        else:
+            capi.rk4_step(g.h, y, ws, g.dt, eta=w["eta"])
+    out = to_cpu(y)
+    I = og.interior()
+    err = sym.mirror_errors(out, I)
+    print("  mirror", fmt(orc.GF_NAMES, err), flush=True)
+    assert np.all(err <= 1e-10), fmt(orc.GF_NAMES, err)
+    assert np.max(np.abs(out[orc.GF_NAMES.index("vetU2")][I])) > 1e-8
+
+
 def test_rhs_is_deterministic():
     _print_case("determinism")
     g, og = _pair("sph_ragged")
