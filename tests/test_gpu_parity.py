@@ -446,6 +446,102 @@ def test_rhs_full_size_sampled(wname):
     assert np.all(err <= tol), fmt(orc.GF_NAMES, err / tol)
 
 
+def _bl_boxes(og, points, masses, pos):
+    """A state that is flat (W = alpha = 1, all else 0) except in the 7^3 index
+    box around each point, where it holds Brill-Lindquist W = alpha =
+    psi^-2 evaluated at the box points (plain Spherical grid, phi = i2
+    wrapped onto the interior planes); the phi ghost planes are copies of
+    the interior ones. Every stencil of a listed point reads Brill-Lindquist
+    values, and the input costs seconds on the largest grid. Returns the
+    state and the boxes (index arrays) it wrote."""
+    ng, N2 = og.ng, og.N[2]
+    y = og.state()
+    y[orc.GF_NAMES.index("cf")] = 1.0
+    y[orc.GF_NAMES.index("alpha")] = 1.0
+    boxes = []
+    for a, b, c in points:
+        i0 = np.arange(max(a - 3, 0), min(a + 4, og.n[0]))
+        i1 = np.arange(max(b - 3, 0), min(b + 4, og.n[1]))
+        i2 = (np.arange(c - 3, c + 4) - ng) % N2 + ng
+        r = np.array([og.xx(0, j) for j in i0]) * og.p.ampl[0]
+        th = np.array([og.xx(1, j) for j in i1])
+        ph = np.array([og.xx(2, j) for j in i2])
+        R, TH, PH = np.meshgrid(r, th, ph, indexing="ij")
+        x = np.stack([R * np.sin(TH) * np.cos(PH), R * np.sin(TH) * np.sin(PH), R * np.cos(TH)], -1)
+        psi = np.ones(R.shape)
+        for m, cen in zip(masses, pos):
+            psi += m / (2.0 * np.linalg.norm(x - np.asarray(cen), axis=-1))
+        box = np.ix_(i2, i1, i0)
+        val = np.transpose(psi ** -2, (2, 1, 0))
+        y[orc.GF_NAMES.index("cf")][box] = val
+        y[orc.GF_NAMES.index("alpha")][box] = val
+        boxes.append(box)
+    y[:, :ng] = y[:, N2:N2 + ng]
+    y[:, N2 + ng:] = y[:, ng:2 * ng]
+    return y, boxes
+
+
+def test_largest_grid_rhs_sampled_and_batch_step():
+    """The largest grid the benchmark runs, the paper's 1008x168x336
+    Spherical grid (r_max 7.5; 60.3M points with ghosts, close to the 2^26
+    points that keep every stencil offset within 31 bits): the right-hand
+    side at sampled points (the corners and faces of the index range, the
+    last interior point, random ones) against the oracle, and one RK4 step
+    of the ensemble path bitwise equal to the solo step."""
+    _print_case("largest_grid")
+    import torch
+    from paper_2505_00097_amd import capi
+    from gpu_helpers import ulp_perturbed
+    N, ampl = (1008, 168, 336), (7.5,) * 3
+    masses, pos = [0.5, 0.5], [(0.0, 0.0, 0.5), (0.0, 0.0, -0.5)]
+    g = capi.Grid(wl.SPHERICAL, N, ampl, (0.2,) * 3, 0.5)
+    og = orc.Grid(wl.SPHERICAL, N, ampl=ampl, sinhw=(0.2,) * 3)
+    rng = np.random.default_rng(7)
+    ends = [(a, b, c) for a in (0, 1, N[0] - 1) for b in (0, N[1] // 2, N[1] - 1) for c in (0, N[2] - 1)]
+    pick = [(3 + a, 3 + b, 3 + c) for a, b, c in ends]
+    pick += [(3 + rng.integers(N[0]), 3 + rng.integers(N[1]), 3 + rng.integers(N[2])) for _ in range(100)]
+    y, boxes = _bl_boxes(og, pick, masses, pos)
+    print("  input ready", flush=True)
+    idx = np.array([og.flat(*p) for p in pick])
+    yg = to_gpu(y)
+    r = g.state()
+    capi.bssn_rhs(g.h, yg, r)
+    got = r.view(24, -1)[:, torch.from_numpy(idx).to(r.device)].cpu().numpy()[:, None, None, :]
+    del r
+
+    def pts_rhs(v):
+        return og.rhs_points(v, idx).T[:, None, None, :]
+
+    def err_fn(a, b):
+        return gf_errors(a, b, (slice(None),) * 3)
+    ref = pts_rhs(y)
+    err = err_fn(got, ref)
+    # rounding floor: one-ulp perturbations of what the sampled stencils read
+    floor = None
+    for t in range(2):
+        yp = y.copy()
+        for box in boxes:
+            yp[(slice(None),) + box] = ulp_perturbed(yp[(slice(None),) + box], 1000 + t)
+        e = err_fn(pts_rhs(yp), ref)
+        floor = e if floor is None else np.maximum(floor, e)
+        del yp
+    tol = np.maximum(RHS_TOL, floor)
+    print("  err", fmt(orc.GF_NAMES, err), flush=True)
+    assert np.all(err <= tol), fmt(orc.GF_NAMES, err / tol)
+    assert np.max(np.abs(ref)) > 0.0
+    del y
+    # the ensemble kernels at this size: one step, bitwise equal to solo
+    y1, y2 = yg, yg.clone()
+    ws = g.workspace()
+    capi.rk4_step(g.h, y1, ws, g.dt)
+    b = capi.batch_create([g.h], eta=2.0)
+    capi.batch_step(b, [y2], [ws], [g.dt], nsteps=1)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+    assert bool(torch.isfinite(y1).all())
+    capi.batch_destroy(b)
+
+
 @pytest.mark.parametrize("name,m,pos,steps", [
     ("tiny", [1.0], [(0, 0, 0)], 100),
     ("cyl_3d", [0.7, 0.3], [(0.3, 0.1, 0.6), (-0.2, 0, -0.5)], 40),
