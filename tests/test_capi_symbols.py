@@ -79,6 +79,23 @@ def test_grid_create_rejects_bad_map_parameters():
         capi.grid_create(0, (8, 8, 2), cfl=0.0)
 
 
+def test_bad_boundary_kind_integrator_and_server_parameters_are_rejected():
+    """Parameter checks that need no device: an unknown outer-boundary kind,
+    an unknown integrator, negative or non-finite dissipation, and a server
+    integrator out of range."""
+    import ctypes
+    from paper_2505_00097_amd import capi
+    with pytest.raises(capi.BhahError, match="bc_kind"):
+        capi.grid_create(0, (8, 8, 2), bc_kind=2)
+    L = capi.lib()
+    assert L.bhah_batch_set_integrator(None, capi.SSPRK3) == capi.EINVAL
+    for integ, diss in ((5, (0.0, 0.0)), (capi.RK4, (-1.0, 0.3)), (capi.SSPRK3, (0.99, float("nan")))):
+        p = capi.ServerParams(1e9, 2, 5, 0, 0, capi.gauge(2.0, diss), None, integ)
+        h = ctypes.c_void_p()
+        with pytest.raises(capi.BhahError, match="integrator|dissipation"):
+            capi._check(L.bhah_server_create(ctypes.byref(p), None, ctypes.byref(h)), "bhah_server_create")
+
+
 def test_null_arguments_are_rejected():
     from paper_2505_00097_amd import capi
     L = capi.lib()
