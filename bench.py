@@ -109,9 +109,24 @@ def cpu_baseline(w, budget_s):
         el = time.perf_counter() - t0
         if el >= budget_s or steps >= 1000:
             break
-    return {"value": n_int * steps / el, "unit": UNIT, "cores": orc.num_threads(), "kind": "oracle",
+    cores = orc.num_threads()
+    # one more step on a single thread (same build, -O2 -fopenmp)
+    orc.set_num_threads(1)
+    t1 = time.perf_counter()
+    og.rk4_step(y, dt, eta=w["eta"])
+    el1 = time.perf_counter() - t1
+    orc.set_num_threads(cores)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": n_int * steps / el, "unit": UNIT, "cores": cores, "kind": "oracle",
             "sample": f"{steps} RK4 steps of the {w['name']} workload ({n_int} interior points), "
-                      f"{el:.1f} s"}
+                      f"{el:.1f} s",
+            "single_thread_value": n_int / el1, "single_thread_sample": f"1 RK4 step, {el1:.1f} s",
+            "cpu_model": model}
 
 
 def events(n):

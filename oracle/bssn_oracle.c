@@ -1282,6 +1282,14 @@ int oracle_ssprk3_step(const oracle_params* p, double eta, double dt, double* y)
   return rc;
 }
 
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 int oracle_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

@@ -103,6 +103,9 @@ int oracle_ssprk3_step(const oracle_params* p, double eta, double dt, double* y)
 int oracle_fd_point(const oracle_params* p, const double* f, long long idx, double d1[3],
                     double d2[9], double uplus[3], double uminus[3]);
 
+/* Set the number of OpenMP threads the oracle runs with (n > 0). */
+void oracle_set_num_threads(int n);
+
 /* Number of OpenMP threads the oracle runs with. */
 int oracle_num_threads(void);
 

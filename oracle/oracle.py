@@ -58,6 +58,7 @@ def lib():
             "oracle_ssprk3_step": (ctypes.c_int, [P, ctypes.c_double, ctypes.c_double, dp]),
             "oracle_fd_point": (ctypes.c_int, [P, dp, ctypes.c_longlong, dp, dp, dp, dp]),
             "oracle_num_threads": (ctypes.c_int, []),
+            "oracle_set_num_threads": (None, [ctypes.c_int]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -221,3 +222,7 @@ class Grid:
 
 def num_threads():
     return lib().oracle_num_threads()
+
+
+def set_num_threads(n):
+    lib().oracle_set_num_threads(int(n))
