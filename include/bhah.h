@@ -24,15 +24,19 @@
  *                  padding: element (g,i0,i1,i2) is at
  *                  ((g*n_total[2] + i2)*n_total[1] + i1)*n_total[0] + i0.
  *                  The 24 gridfunctions are ordered as in enum bhah_gf.
- *   Pointers     : pointers named y, rhs, aux, H, workspace are DEVICE
- *                  pointers owned by the caller, 8-byte aligned, on the device
- *                  that was current when the grid was created. Pointers named
- *                  host_* or taken as parameters structs are host pointers.
+ *   Pointers     : pointers named y, rhs, aux, H, M, C, workspace are DEVICE
+ *                  pointers owned by the caller, on the device that was
+ *                  current when the grid was created; they must be 8-byte
+ *                  aligned (BHAH_EINVAL otherwise). Pointers named host_* or
+ *                  taken as parameters structs are host pointers.
  *   Streams      : `stream` is a hipStream_t passed as void*; NULL means the
  *                  null stream. Every call that takes a stream only enqueues
  *                  work and returns; results are ready when the stream is.
- *   Memory       : calls that take a stream allocate no device memory. All
- *                  temporaries live in the caller's `workspace`.
+ *   Memory       : calls on a grid that take a stream allocate no device
+ *                  memory; all temporaries live in the caller's `workspace`.
+ *                  Ensembles hold a work description that bhah_batch_step
+ *                  grows with the job set; the server holds its job states;
+ *                  bhah_probe_peaks allocates and frees its test arrays.
  */
 #ifndef BHAH_H
 #define BHAH_H

@@ -36,6 +36,7 @@ int bhah_batch_step(bhah_batch* b, double* const* y, double* const* ws, const do
   for (size_t j = 0; j < b->grids.size(); j++) {
     if (host_active && !host_active[j]) continue;
     if (!y[j] || !ws[j]) return bhah::fail(BHAH_EINVAL, "bhah_batch_step: NULL state or workspace");
+    if (int rc = bhah::check_aligned("bhah_batch_step", {y[j], ws[j]})) return rc;
     if (y[j] == ws[j]) return bhah::fail(BHAH_EINVAL, "bhah_batch_step: workspace aliases state");
     jobs.push_back(bhah::EngineJob{b->grids[j], y[j], ws[j], host_dt[j]});
     b->slot.push_back((int)j);

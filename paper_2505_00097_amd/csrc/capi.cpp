@@ -27,6 +27,12 @@ int check_hip(hipError_t e, const char* what) {
 
 static int check_launch(const char* what) { return check_hip(hipGetLastError(), what); }
 
+int check_aligned(const char* who, std::initializer_list<const void*> ptrs) {
+  for (const void* p : ptrs)
+    if (((uintptr_t)p & 7u) != 0) return fail(BHAH_EINVAL, std::string(who) + ": array not aligned to 8 bytes");
+  return BHAH_OK;
+}
+
 int check_gauge(const bhah_gauge_params* gp, const char* who) {
   if (gp->shift_variant != 0) return fail(BHAH_EINVAL, std::string(who) + ": shift_variant must be 0");
   if (!(gp->diss_gauge >= 0.0) || !(gp->diss_metric >= 0.0) || !std::isfinite(gp->diss_gauge) ||
@@ -216,6 +222,7 @@ int bhah_grid_get_bc_maps(const bhah_grid* g, int* host_kind, int* host_src, int
 
 int bhah_apply_bcs(const bhah_grid* g, double* y, void* stream) {
   if (!g || !y) return fail(BHAH_EINVAL, "bhah_apply_bcs: NULL argument");
+  if (int rc = check_aligned("bhah_apply_bcs", {y})) return rc;
   launch_ghosts(g->ghost, y, g->dev.sgf, (hipStream_t)stream);
   return check_launch("bhah_apply_bcs");
 }
@@ -224,6 +231,7 @@ int bhah_set_initial_data_brill_lindquist(const bhah_grid* g, int n_punct, const
                                           const double* host_pos, int lapse_kind, double* y,
                                           void* stream) {
   if (!g || !y) return fail(BHAH_EINVAL, "bhah_set_initial_data_brill_lindquist: NULL argument");
+  if (int rc = check_aligned("bhah_set_initial_data_brill_lindquist", {y})) return rc;
   if (n_punct > 0 && (!host_masses || !host_pos))
     return fail(BHAH_EINVAL, "bhah_set_initial_data_brill_lindquist: NULL puncture arrays");
   if (lapse_kind != 0 && lapse_kind != 1)
@@ -238,6 +246,7 @@ int bhah_set_initial_data_brill_lindquist(const bhah_grid* g, int n_punct, const
 int bhah_bssn_rhs(const bhah_grid* g, const bhah_gauge_params* gp, const double* y, double* rhs,
                   double* aux, void* stream) {
   if (!g || !gp || !y || !rhs) return fail(BHAH_EINVAL, "bhah_bssn_rhs: NULL argument");
+  if (int rc = check_aligned("bhah_bssn_rhs", {y, rhs, aux})) return rc;
   if (int rc = check_gauge(gp, "bhah_bssn_rhs")) return rc;
   StageArgs st{rhs, nullptr, nullptr, 0.0, nullptr, nullptr, 0.0};
   launch_rhs_fused(g->dev, gauge_of(*gp), y, aux, st, (hipStream_t)stream, g->tile);
@@ -248,6 +257,7 @@ int bhah_bssn_rhs(const bhah_grid* g, const bhah_gauge_params* gp, const double*
 int bhah_rk4_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt, double* y, double* workspace,
                   void* stream) {
   if (!g || !gp || !y || !workspace) return fail(BHAH_EINVAL, "bhah_rk4_step: NULL argument");
+  if (int rc = check_aligned("bhah_rk4_step", {y, workspace})) return rc;
   if (int rc = check_gauge(gp, "bhah_rk4_step")) return rc;
   hipStream_t s = (hipStream_t)stream;
   StageArgs st[4];
@@ -261,6 +271,7 @@ int bhah_rk4_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt, do
 int bhah_ssprk3_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt, double* y, double* workspace,
                      void* stream) {
   if (!g || !gp || !y || !workspace) return fail(BHAH_EINVAL, "bhah_ssprk3_step: NULL argument");
+  if (int rc = check_aligned("bhah_ssprk3_step", {y, workspace})) return rc;
   if (int rc = check_gauge(gp, "bhah_ssprk3_step")) return rc;
   hipStream_t s = (hipStream_t)stream;
   StageArgs st[3];
@@ -290,6 +301,7 @@ int bhah_grid_get_tile(const bhah_grid* g, int* lx, int* ly, int* band) {
 
 int bhah_grid_tune(bhah_grid* g, const bhah_gauge_params* gp, const double* y, double* rhs, void* stream) {
   if (!g || !gp || !y || !rhs) return fail(BHAH_EINVAL, "bhah_grid_tune: NULL argument");
+  if (int rc = check_aligned("bhah_grid_tune", {y, rhs})) return rc;
   if (int rc = check_gauge(gp, "bhah_grid_tune")) return rc;
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0, e1;
@@ -324,6 +336,7 @@ int bhah_grid_tune(bhah_grid* g, const bhah_gauge_params* gp, const double* y, d
 
 int bhah_constraints(const bhah_grid* g, const double* y, double* H, double* M, double* C, void* stream) {
   if (!g || !y) return fail(BHAH_EINVAL, "bhah_constraints: NULL grid or state");
+  if (int rc = check_aligned("bhah_constraints", {y, H, M, C})) return rc;
   if (!H && !M && !C) return BHAH_OK;
   launch_constraints(g->dev, y, H, M, C, (hipStream_t)stream);
   return check_launch("bhah_constraints");
@@ -331,6 +344,7 @@ int bhah_constraints(const bhah_grid* g, const double* y, double* H, double* M, 
 
 int bhah_hamiltonian_constraint(const bhah_grid* g, const double* y, double* H, void* stream) {
   if (!g || !y || !H) return fail(BHAH_EINVAL, "bhah_hamiltonian_constraint: NULL argument");
+  if (int rc = check_aligned("bhah_hamiltonian_constraint", {y, H})) return rc;
   launch_hamiltonian(g->dev, y, H, (hipStream_t)stream);
   return check_launch("bhah_hamiltonian_constraint");
 }

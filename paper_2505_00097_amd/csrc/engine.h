@@ -10,6 +10,7 @@
 // themselves; choices persist in a small JSON cache file.
 #pragma once
 
+#include <initializer_list>
 #include <map>
 #include <string>
 #include <tuple>
@@ -18,6 +19,10 @@
 #include "bhah_internal.h"
 
 namespace bhah {
+
+// BHAH_OK, or BHAH_EINVAL if any of the (possibly null) arrays is not aligned
+// to 8 bytes (a double)
+int check_aligned(const char* who, std::initializer_list<const void*> ptrs);
 
 struct EngineJob {
   const bhah_grid* g;

@@ -263,6 +263,7 @@ int bhah_server_job_status(const bhah_server* s, long long id, bhah_job_status* 
 
 int bhah_server_fetch(bhah_server* s, long long id, double* dst) {
   if (!s || !dst) return bhah::fail(BHAH_EINVAL, "bhah_server_fetch: NULL argument");
+  if (int rc = bhah::check_aligned("bhah_server_fetch", {dst})) return rc;
   auto it = s->jobs.find(id);
   if (it == s->jobs.end() || it->second.state != BHAH_JOB_DONE)
     return bhah::fail(BHAH_EINVAL, "bhah_server_fetch: job unknown, not finished or already released");

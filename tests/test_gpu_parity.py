@@ -812,6 +812,12 @@ def test_invalid_calls_report_errors():
     for bad in ((-0.1, 0.3), (0.99, float("nan")), (float("inf"), 0.0)):
         with pytest.raises(capi.BhahError, match="dissipation"):
             capi.ssprk3_step(g.h, y, g.workspace(), g.dt, diss=bad)
+    # a state pointer that is not aligned to a double is rejected before any launch
+    gp = capi.gauge(2.0)
+    mis = capi.ctypes.c_void_p(y.data_ptr() + 4)
+    rc = capi.lib().bhah_rk4_step(g.h, capi.ctypes.byref(gp), g.dt, mis, capi._ptr(g.workspace()),
+                                  capi._stream(None))
+    assert rc == capi.EINVAL and "aligned" in capi.last_error()
 
 
 @pytest.mark.parametrize("name", ["tiny", "cyl_3d", "sph_ragged", "spherical"])
