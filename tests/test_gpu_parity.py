@@ -325,25 +325,29 @@ def test_production_numerics_match_oracle():
     assert np.all(err <= EVOL_TOL), fmt(orc.GF_NAMES, err)
 
 
-def test_production_numerics_full_size_headon():
-    """The benchmark's production-numerics leg at full size: the head-on
-    workload (SinhCylindrical 128x2x256) with SSPRK3, Kreiss-Oliger 0.99 /
-    0.3 and the Sommerfeld outer boundary, tuned tile shape, 30 steps,
-    against the oracle over every point."""
+@pytest.mark.parametrize("production", [False, True])
+def test_ssprk3_full_size_headon(production):
+    """The benchmark's SSPRK3 legs at full size: the head-on workload
+    (SinhCylindrical 128x2x256) with SSPRK3 alone, and with the production
+    numerics (Kreiss-Oliger 0.99 / 0.3 and the Sommerfeld outer boundary),
+    tuned tile shape, 30 steps, against the oracle over every point."""
     name = "headon_sinhcylindrical_128x2x256"
-    _print_case("evolve_production_full", name, 30)
+    _print_case("evolve_ssprk3_full", name, production, 30)
     from paper_2505_00097_amd import capi
     w = wl.WORKLOADS[name]
-    g = capi.Grid(w["coord"], w["N"], w["ampl"], w["sinhw"], w["cfl"], bc_kind=capi.BC_RADIATION)
-    og = orc.Grid(w["coord"], w["N"], ampl=w["ampl"], sinhw=w["sinhw"], cfl=w["cfl"], bc_kind=1, diss=DISS)
+    diss = DISS if production else (0.0, 0.0)
+    g = capi.Grid(w["coord"], w["N"], w["ampl"], w["sinhw"], w["cfl"],
+                  bc_kind=capi.BC_RADIATION if production else capi.BC_EXTRAP)
+    og = orc.Grid(w["coord"], w["N"], ampl=w["ampl"], sinhw=w["sinhw"], cfl=w["cfl"],
+                  bc_kind=1 if production else 0, diss=diss)
     y = g.state()
     capi.set_initial_data_brill_lindquist(g.h, w["masses"], w["positions"], y)
-    capi.grid_tune(g.h, y, g.state(), diss=DISS)
+    capi.grid_tune(g.h, y, g.state(), diss=diss)
     ws = g.workspace()
     yo = og.brill_lindquist(w["masses"], w["positions"])
     dt = og.dt()
     for s in range(30):
-        capi.ssprk3_step(g.h, y, ws, dt, eta=w["eta"], diss=DISS)
+        capi.ssprk3_step(g.h, y, ws, dt, eta=w["eta"], diss=diss)
         og.ssprk3_step(yo, dt, eta=w["eta"])
         if s % 10 == 9:
             print("  step", s + 1, flush=True)
