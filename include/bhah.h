@@ -281,7 +281,7 @@ int bhah_hamiltonian_constraint(const bhah_grid* g, const double* y, double* H,
  * file, choices are read from it and written back (JSON, one entry per
  * line). The same grid may appear several times (jobs of one resolution).
  * Device memory held by the batch: a work description of roughly
- * 600 B per job + 8 B per tile + 8 B per 256 ghost points.
+ * 750 B per job + 8 B per tile + 8 B per 256 ghost or radiation points.
  * Errors: BHAH_EINVAL for NULL or inconsistent arguments, BHAH_EDEVICE /
  * BHAH_ENOMEM from the runtime. Calls on one batch must not overlap and must
  * be ordered on one stream (or the caller orders them).                      */
