@@ -1,0 +1,35 @@
+"""Host-side checks of the benchmark script (no GPU): it refuses more than one
+GPU with a message, and its measured-traffic lookup only accepts counters
+taken from the current kernel sources."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+def test_traffic_is_reported_only_for_matching_kernel_sources(tmp_path, monkeypatch):
+    sys.path.insert(0, ROOT)
+    import bench
+    name = "headon_sinhcylindrical_128x2x256"
+    counters = open(bench.COUNTERS).read()
+    # the committed summary names its workload and the sources' hash
+    assert f"workload: {name}" in counters and "source_sha256:" in counters
+    # a summary whose hash does not match the sources gives no traffic
+    stale = tmp_path / "counters.txt"
+    lines = [("source_sha256: " + "0" * 64) if l.startswith("source_sha256:") else l
+             for l in counters.splitlines()]
+    stale.write_text("\n".join(lines) + "\n")
+    monkeypatch.setattr(bench, "COUNTERS", str(stale))
+    assert bench.measured_traffic(name) is None
+    # nor for another workload
+    monkeypatch.setattr(bench, "COUNTERS", os.path.join(ROOT, "profiles", "k_rhs_fused_headon_counters.txt"))
+    assert bench.measured_traffic("vacuum3d_sinhspherical_256x128x64") is None
