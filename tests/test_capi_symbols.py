@@ -29,7 +29,7 @@ def test_header_declares_the_boundary():
 def test_library_exports_every_declared_symbol():
     from paper_2505_00097_amd import capi
     if not os.path.exists(capi.LIBPATH):
-        pytest.fail("libbhah.so is not built (run __graft_entry__.build())")
+        pytest.fail("libbhah.so is not built (run paper_2505_00097_amd/build.py)")
     L = ctypes.CDLL(capi.LIBPATH)
     for n in sorted(_declared()):
         assert hasattr(L, n), n
