@@ -50,8 +50,11 @@ std::vector<TileCfg> tile_candidates(const SizeClass& c) {
       if (ez > 1 && ez > N2) continue;
       if (lx < 6 && (1 << lx) > 2 * N0) continue;
       const int ty = (N1 + (1 << ly) - 1) >> ly;
+      // bands of 4 and 16 tile rows: tiles that run at the same time share
+      // stencil planes in the XCD's L2 (16 pays on large 3-D grids)
       out.push_back(TileCfg{lx, ly, 1});
       if (ty > 1) out.push_back(TileCfg{lx, ly, 4});
+      if (ty > 8) out.push_back(TileCfg{lx, ly, 16});
     }
   return out;
 }
