@@ -151,12 +151,12 @@ def time_rhs(capi, g, y, eta, reps, stream):
     return e0.elapsed_time(e1) / 1e3 / reps
 
 
-def make_grids(capi, jobs):
+def make_grids(capi, jobs, bc_kind=0):
     cache, grids = {}, []
     for j in jobs:
         key = (j["coord"], tuple(j["N"]), tuple(j["ampl"]), tuple(j["sinhw"]), j["cfl"])
         if key not in cache:
-            cache[key] = capi.Grid(j["coord"], j["N"], j["ampl"], j["sinhw"], j["cfl"])
+            cache[key] = capi.Grid(j["coord"], j["N"], j["ampl"], j["sinhw"], j["cfl"], bc_kind)
         grids.append(cache[key])
     return grids
 
@@ -191,12 +191,13 @@ def run_ssprk3(capi, wl, stream, steps, diss=(0.0, 0.0), bc_kind=0):
             "finite": bool(torch.isfinite(y).all().item())}
 
 
-def run_batched(capi, wl, stream, steps, seq_steps, graph_steps):
-    """64 uneven head-on jobs: one batch advancing all of them `steps` RK4
-    steps, against the same jobs advanced one at a time."""
+def run_batched(capi, wl, stream, steps, seq_steps, graph_steps, integrator=0, diss=(0.0, 0.0), bc_kind=0):
+    """64 uneven head-on jobs: one batch advancing all of them `steps` steps
+    (RK4 or SSPRK3, optional dissipation and radiation boundary), against the
+    same jobs advanced one at a time with the same numerics."""
     import torch
     jobs = wl.batched_jobs()
-    grids = make_grids(capi, jobs)
+    grids = make_grids(capi, jobs, bc_kind)
     ys, wss = [], []
     for j, g in zip(jobs, grids):
         y = g.state()
@@ -205,7 +206,8 @@ def run_batched(capi, wl, stream, steps, seq_steps, graph_steps):
         wss.append(g.workspace())
     dts = [g.dt for g in grids]
     pts = sum(g.info.n_interior for g in grids)
-    b = capi.batch_create([g.h for g in grids], eta=2.0)
+    b = capi.batch_create([g.h for g in grids], eta=2.0, diss=diss)
+    capi.batch_set_integrator(b, integrator)
     capi.batch_set_graph_steps(b, graph_steps)
     capi.batch_step(b, ys, wss, dts, nsteps=graph_steps, stream=stream)  # tunes tiles, captures graph
     torch.cuda.synchronize()
@@ -226,19 +228,22 @@ def run_batched(capi, wl, stream, steps, seq_steps, graph_steps):
                 for k in range(n_launch)]
     finite = all(bool(torch.isfinite(y).all().item()) for y in ys)
     capi.batch_destroy(b)
-    # the same jobs one after another, plain bhah_rk4_step
+    # the same jobs one after another, plain single-grid steps
+    solo = capi.ssprk3_step if integrator == capi.SSPRK3 else capi.rk4_step
     e0, e1 = events(2)
     t1 = time.perf_counter()
     e0.record(stream)
     for g, y, ws in zip(grids, ys, wss):
         for _ in range(seq_steps):
-            capi.rk4_step(g.h, y, ws, g.dt, eta=2.0, stream=stream)
+            solo(g.h, y, ws, g.dt, eta=2.0, diss=diss, stream=stream)
     e1.record(stream)
     torch.cuda.synchronize()
     el_seq = time.perf_counter() - t1
     batched = pts * steps / el
     seq = pts * seq_steps / el_seq
     return {"workload": "64 head-on BL jobs, SinhCylindrical N_rho~U{48..192} x 2 x 2N_rho, seed 250500097",
+            "integrator": "ssprk3" if integrator == capi.SSPRK3 else "rk4", "dissipation": list(diss),
+            "boundary": "radiation" if bc_kind == capi.BC_RADIATION else "extrapolation",
             "interior_points": pts, "steps": steps, "value": batched, "unit": UNIT,
             "ms_per_step_all_jobs": el * 1e3 / steps,
             "p50_step_ms": percentile(per_step, 50), "p99_step_ms": percentile(per_step, 99),
@@ -444,17 +449,26 @@ def main():
 
         extras = {}
         if args.ssprk3_steps > 0:
-            extras["ssprk3"] = run_ssprk3(capi, wl, stream, args.ssprk3_steps)
+            # SSPRK3 without dissipation is unstable on this grid at CFL 0.5
+            # (non-finite near step 480, in the oracle as well): both legs
+            # carry the production dissipation and differ in the boundary
+            extras["ssprk3"] = run_ssprk3(capi, wl, stream, args.ssprk3_steps, diss=(0.99, 0.3))
             extras["production_numerics"] = run_ssprk3(capi, wl, stream, args.ssprk3_steps, diss=(0.99, 0.3),
                                                         bc_kind=capi.BC_RADIATION)
             torch.cuda.empty_cache()
-            print(f"# ssprk3: {extras['ssprk3']['value']:.3e} pt-steps/s, with dissipation and radiation "
+            print(f"# ssprk3 + dissipation: {extras['ssprk3']['value']:.3e} pt-steps/s, with the radiation "
                   f"boundary {extras['production_numerics']['value']:.3e}", file=sys.stderr, flush=True)
         if args.batched_steps > 0:
             extras["batched"] = run_batched(capi, wl, stream, args.batched_steps, args.batched_seq_steps,
                                             args.graph_steps)
             torch.cuda.empty_cache()
             print(f"# batched: {extras['batched']['value']:.3e} pt-steps/s", file=sys.stderr, flush=True)
+            extras["batched_production_numerics"] = run_batched(
+                capi, wl, stream, args.batched_steps, args.batched_seq_steps, args.graph_steps,
+                integrator=capi.SSPRK3, diss=(0.99, 0.3), bc_kind=capi.BC_RADIATION)
+            torch.cuda.empty_cache()
+            print(f"# batched, SSPRK3 + dissipation + radiation: "
+                  f"{extras['batched_production_numerics']['value']:.3e} pt-steps/s", file=sys.stderr, flush=True)
         if args.study_steps > 0:
             extras["rhs_study_3d"] = run_rhs_study(capi, wl, stream, args.rhs_reps // 5 + 1, args.study_steps)
             torch.cuda.empty_cache()

@@ -10,10 +10,13 @@
  *
  * Discretisation (the plain definition the GPU path must reproduce):
  *   - cell-centred logical grid, N_G ghost layers (Sec. 3);
- *   - every partial derivative of an evolved rescaled variable is a 4th-order
- *     finite difference: centred 5-point stencils, their tensor product for
- *     mixed derivatives, and for the advection terms beta^k d_k the 5-point
- *     stencil shifted one point upwind (Sec. 3, second paragraph);
+ *   - every partial derivative of an evolved rescaled variable is a finite
+ *     difference of order N_FD = 2 (N_G - 1) (Sec. 3: N_G = N_FD/2 + 1 ghost
+ *     layers; the benchmark runs use N_FD = 4, the production head-on run of
+ *     Sec. 4.2 N_FD = 8): centred (N_FD + 1)-point stencils, their tensor
+ *     product for mixed derivatives, and for the advection terms beta^k d_k
+ *     the same width of stencil shifted one point upwind (Sec. 3, second
+ *     paragraph);
  *   - every reference-metric quantity (S_i, its derivatives, Gammahat and its
  *     derivatives) is evaluated analytically (Sec. 2.2, Eq. 22);
  *   - RHS = Eqs. 7-15 with Eq. 12 (Sec. 2.1), unrescaled/rescaled per Sec. 2.2;
@@ -63,18 +66,33 @@ static const int GF_J[NGF] = {0, 1, 2, 1, 2, 2, 0, 0, 0, 0, 0,
 /* ------------------------------------------------------------------------ */
 /* Grid (Sec. 3, first paragraph): logical domain [xxmin, xxmax], N cells,
  * cell-centred points xxmin + (j - ng + 1/2) dxx.                           */
+#define MAXR 5 /* centred stencil radius up to 5: N_FD up to 10 */
+
+/* Finite-difference weights for N_FD = 2R (R = N_G - 1), unit spacing:
+ *   D f  = sum_{j=1..R} d1[j] (f_j - f_-j)
+ *   D2 f = sum_{j=1..R} d2[j] ((f_j - f_0) + (f_-j - f_0))
+ *   U+ f = sum_{m != 1} up[m + R - 1] (f_m - f_1),  m = -(R-1) .. R+1
+ *   KO f = sum_{j=1..R+1} ko[j] ((f_j - f_0) + (f_-j - f_0))
+ * The sums are grouped into differences (the weights of each stencil add up
+ * to zero), so a constant field has exactly zero derivatives.               */
+typedef struct {
+  int R;
+  double d1[MAXR + 1], d2[MAXR + 1], up[2 * MAXR + 1], ko[MAXR + 2];
+} Sten;
+
 typedef struct {
   oracle_params p;
   int n[3];
   long long np;     /* points incl. ghosts */
   long long st[3];  /* flat-index strides */
   double xxmin[3], xxmax[3], dxx[3];
+  Sten fd;
 } Grid;
 
 int oracle_check(const oracle_params* p) {
   if (!p) return -1;
   if (p->coord < 0 || p->coord > 2) return -1;
-  if (p->ng < 3) return -1;
+  if (p->ng < 3 || p->ng > MAXR + 1) return -1;
   if (p->bc_kind != 0 && p->bc_kind != 1) return -1;
   /* the periodic phi direction may have fewer cells than ghost layers (its
    * ghosts wrap around as often as needed); the others need N >= ng */
@@ -92,6 +110,61 @@ int oracle_check(const oracle_params* p) {
     if (p->coord == 0 && !(p->sinhw[0] > 0)) return -1;
   }
   return 0;
+}
+
+/* w[j] with f^(der)(0) ~ sum_j w[j] f(m[j]) (der = 1 or 2): the weights are
+ * the derivatives at 0 of the Lagrange basis polynomials through the n
+ * integer nodes m[], L_j(x) = prod_{i != j} (x - m_i)/(m_j - m_i).          */
+static void lagrange_weights(int n, const int* m, int der, double* w) {
+  for (int j = 0; j < n; j++) {
+    double s = 0.0;
+    for (int k = 0; k < n; k++) {
+      if (k == j) continue;
+      if (der == 1) {
+        double prod = 1.0 / (double)(m[j] - m[k]);
+        for (int i = 0; i < n; i++)
+          if (i != j && i != k) prod *= (0.0 - m[i]) / (double)(m[j] - m[i]);
+        s += prod;
+      } else {
+        for (int l = 0; l < n; l++) {
+          if (l == j || l == k) continue;
+          double prod = 1.0 / ((double)(m[j] - m[k]) * (double)(m[j] - m[l]));
+          for (int i = 0; i < n; i++)
+            if (i != j && i != k && i != l) prod *= (0.0 - m[i]) / (double)(m[j] - m[i]);
+          s += prod;
+        }
+      }
+    }
+    w[j] = s;
+  }
+}
+
+/* Kreiss-Oliger dissipation of order 2R + 1 (Sec. 4.2 runs N_FD = 8 with
+ * ninth-order dissipation operators). Reading: the operator is the
+ * difference of order 2p = 2R + 2, radius p = N_G, scaled to
+ * (-1)^(p+1) delta^2p f / (4^p h), whose Fourier symbol is -sin^2p(theta/2)/h
+ * (it damps the grid-scale modes and is O(h^(2p-1)) on smooth data); with
+ * delta^2p f = sum_j (-1)^(j+p) C(2p, p+j) f_j the grouped weight of the
+ * pair +-j is (-1)^(j+1) C(2p, p+j) / 4^p.                                  */
+static void build_stencils(int R, Sten* S) {
+  int m[2 * MAXR + 3];
+  double w[2 * MAXR + 3];
+  S->R = R;
+  for (int j = 0; j <= 2 * R; j++) m[j] = j - R; /* centred nodes -R..R */
+  lagrange_weights(2 * R + 1, m, 1, w);
+  for (int j = 0; j <= R; j++) S->d1[j] = w[R + j];
+  lagrange_weights(2 * R + 1, m, 2, w);
+  for (int j = 0; j <= R; j++) S->d2[j] = w[R + j];
+  for (int j = 0; j <= 2 * R; j++) m[j] = j - R + 1; /* shifted nodes -(R-1)..R+1 */
+  lagrange_weights(2 * R + 1, m, 1, w);
+  for (int j = 0; j <= 2 * R; j++) S->up[j] = w[j];
+  const int p = R + 1;
+  double binom = 1.0, scale = 1.0; /* C(2p, p + j), 4^-p */
+  for (int k = 0; k < p; k++) scale /= 4.0;
+  for (int j = p; j >= 0; j--) {
+    if (j < p) binom = binom * (double)(p + j + 1) / (double)(p - j); /* C(2p,p+j) from C(2p,p+j+1) */
+    S->ko[j] = ((j + 1) % 2 == 0 ? 1.0 : -1.0) * binom * scale;
+  }
 }
 
 static int grid_setup(const oracle_params* p, Grid* G) {
@@ -115,6 +188,7 @@ static int grid_setup(const oracle_params* p, Grid* G) {
   G->st[1] = G->n[0];
   G->st[2] = (long long)G->n[0] * G->n[1];
   G->np = G->st[2] * G->n[2];
+  build_stencils(p->ng - 1, &G->fd);
   return 0;
 }
 
@@ -466,42 +540,44 @@ int oracle_id_brill_lindquist(const oracle_params* p, int np, const double* m,
 }
 
 /* ------------------------------------------------------------------------ */
-/* 4th-order finite differences along a direction with stride s and spacing h
- * (f points at the centre). Centred: 5 points; upwinded: shifted one point
- * toward +s (U+) or -s (U-), 5 points. Weights:
+/* Finite differences along a direction with stride s and spacing h (f
+ * points at the centre), with the weights above. U+ is the stencil shifted
+ * one point toward +s, U- its mirror image (shifted toward -s); for N_FD = 4
+ * they are
  *   D f  = [8 (f1 - f-1) - (f2 - f-2)] / 12h
  *   D2 f = [-f-2 + 16 f-1 - 30 f0 + 16 f1 - f2] / 12h^2
  *   U+ f = [-3 f-1 - 10 f0 + 18 f1 - 6 f2 + f3] / 12h
- *   U- f = [3 f1 + 10 f0 - 18 f-1 + 6 f-2 - f-3] / 12h
- * Reading: each sum is grouped into differences so that a constant field has
- * exactly zero derivatives (the discrete operator is the same).             */
-static double fd_d1(const double* f, long long s, double h) {
-  return (8.0 * (f[s] - f[-s]) - (f[2 * s] - f[-2 * s])) / (12.0 * h);
+ *   U- f = [3 f1 + 10 f0 - 18 f-1 + 6 f-2 - f-3] / 12h.                     */
+static double fd_d1(const Sten* S, const double* f, long long s, double h) {
+  double a = 0.0;
+  for (int j = S->R; j >= 1; j--) a += S->d1[j] * (f[j * s] - f[-j * s]);
+  return a / h;
 }
-static double fd_d2(const double* f, long long s, double h) {
-  return (16.0 * (f[s] + f[-s]) - (f[2 * s] + f[-2 * s]) - 30.0 * f[0]) / (12.0 * h * h);
+static double fd_d2(const Sten* S, const double* f, long long s, double h) {
+  double a = 0.0;
+  for (int j = S->R; j >= 1; j--) a += S->d2[j] * ((f[j * s] - f[0]) + (f[-j * s] - f[0]));
+  return a / (h * h);
 }
-static double fd_d11(const double* f, long long sk, long long sl, double hk, double hl) {
-  return (8.0 * (fd_d1(f + sk, sl, hl) - fd_d1(f - sk, sl, hl)) -
-          (fd_d1(f + 2 * sk, sl, hl) - fd_d1(f - 2 * sk, sl, hl))) /
-         (12.0 * hk);
+/* D_k D_l f (k != l): the tensor product of two centred first differences */
+static double fd_d11(const Sten* S, const double* f, long long sk, long long sl, double hk, double hl) {
+  double a = 0.0;
+  for (int j = S->R; j >= 1; j--)
+    a += S->d1[j] * (fd_d1(S, f + j * sk, sl, hl) - fd_d1(S, f - j * sk, sl, hl));
+  return a / hk;
 }
-static double fd_up(const double* f, long long s, double h) {
-  return (3.0 * (f[s] - f[-s]) + 10.0 * (f[s] - f[0]) - 6.0 * (f[2 * s] - f[s]) + (f[3 * s] - f[s])) /
-         (12.0 * h);
+static double fd_up(const Sten* S, const double* f, long long s, double h) {
+  double a = 0.0;
+  for (int m = S->R + 1; m >= -(S->R - 1); m--)
+    if (m != 1) a += S->up[m + S->R - 1] * (f[m * s] - f[s]);
+  return a / h;
 }
-/* Kreiss-Oliger operator along one direction (Sec. 4.2 names the strengths
- * and the order: one above the finite-difference order). Reading: with the
- * 4th-order stencils and three ghost layers here it is the radius-3 sixth
- * difference, (1/64) h^5 (d/dx)^6 f = delta^6 f / (64 h), whose Fourier
- * symbol -sin^6(theta/2)/h damps the grid-scale modes.                      */
-static double fd_ko(const double* f, long long s, double h) {
-  return ((f[3 * s] + f[-3 * s]) - 6.0 * (f[2 * s] + f[-2 * s]) + 15.0 * (f[s] + f[-s]) - 20.0 * f[0]) /
-         (64.0 * h);
+static double fd_dn(const Sten* S, const double* f, long long s, double h) {
+  return -fd_up(S, f, -s, h);
 }
-static double fd_dn(const double* f, long long s, double h) {
-  return (3.0 * (f[s] - f[-s]) + 10.0 * (f[0] - f[-s]) - 6.0 * (f[-s] - f[-2 * s]) + (f[-s] - f[-3 * s])) /
-         (12.0 * h);
+static double fd_ko(const Sten* S, const double* f, long long s, double h) {
+  double a = 0.0;
+  for (int j = S->R + 1; j >= 1; j--) a += S->ko[j] * ((f[j * s] - f[0]) + (f[-j * s] - f[0]));
+  return a / h;
 }
 
 int oracle_fd_point(const oracle_params* p, const double* f, long long idx, double d1[3],
@@ -510,13 +586,20 @@ int oracle_fd_point(const oracle_params* p, const double* f, long long idx, doub
   if (grid_setup(p, &G)) return -1;
   const double* c = f + idx;
   for (int k = 0; k < 3; k++) {
-    d1[k] = fd_d1(c, G.st[k], G.dxx[k]);
-    uplus[k] = fd_up(c, G.st[k], G.dxx[k]);
-    uminus[k] = fd_dn(c, G.st[k], G.dxx[k]);
+    d1[k] = fd_d1(&G.fd, c, G.st[k], G.dxx[k]);
+    uplus[k] = fd_up(&G.fd, c, G.st[k], G.dxx[k]);
+    uminus[k] = fd_dn(&G.fd, c, G.st[k], G.dxx[k]);
     for (int l = 0; l < 3; l++)
-      d2[3 * k + l] = k == l ? fd_d2(c, G.st[k], G.dxx[k])
-                             : fd_d11(c, G.st[k], G.st[l], G.dxx[k], G.dxx[l]);
+      d2[3 * k + l] = k == l ? fd_d2(&G.fd, c, G.st[k], G.dxx[k])
+                             : fd_d11(&G.fd, c, G.st[k], G.st[l], G.dxx[k], G.dxx[l]);
   }
+  return 0;
+}
+
+int oracle_ko_point(const oracle_params* p, const double* f, long long idx, double ko[3]) {
+  Grid G;
+  if (grid_setup(p, &G)) return -1;
+  for (int k = 0; k < 3; k++) ko[k] = fd_ko(&G.fd, f + idx, G.st[k], G.dxx[k]);
   return 0;
 }
 
@@ -555,11 +638,11 @@ static void bssn_point(const Grid* G, double eta, const double* y, int i0, int i
   for (int g = 0; g < NGF; g++) {
     const double* f = y + g * np + q;
     v[g] = f[0];
-    for (int k = 0; k < 3; k++) d1[g][k] = fd_d1(f, G->st[k], G->dxx[k]);
+    for (int k = 0; k < 3; k++) d1[g][k] = fd_d1(&G->fd, f, G->st[k], G->dxx[k]);
     for (int k = 0; k < 3; k++)
       for (int l = k; l < 3; l++) {
-        d2[g][k][l] = k == l ? fd_d2(f, G->st[k], G->dxx[k])
-                             : fd_d11(f, G->st[k], G->st[l], G->dxx[k], G->dxx[l]);
+        d2[g][k][l] = k == l ? fd_d2(&G->fd, f, G->st[k], G->dxx[k])
+                             : fd_d11(&G->fd, f, G->st[k], G->st[l], G->dxx[k], G->dxx[l]);
         d2[g][l][k] = d2[g][k][l];
       }
   }
@@ -568,7 +651,8 @@ static void bssn_point(const Grid* G, double eta, const double* y, int i0, int i
   for (int g = 0; g < NGF; g++) {
     const double* f = y + g * np + q;
     for (int k = 0; k < 3; k++)
-      up[g][k] = v[VETU0 + k] > 0.0 ? fd_up(f, G->st[k], G->dxx[k]) : fd_dn(f, G->st[k], G->dxx[k]);
+      up[g][k] = v[VETU0 + k] > 0.0 ? fd_up(&G->fd, f, G->st[k], G->dxx[k])
+                                    : fd_dn(&G->fd, f, G->st[k], G->dxx[k]);
   }
 
   /* ---- 2. reference metric (analytic): gammahat_ij = S_i^2 delta_ij ---- */
@@ -978,7 +1062,7 @@ static void bssn_point(const Grid* G, double eta, const double* y, int i0, int i
       const int gauge = g == ALPHA || (g >= BETU0 && g <= BETU2) || (g >= VETU0 && g <= VETU2);
       const double eps = gauge ? G->p.diss_gauge : G->p.diss_metric;
       const double* f = y + g * np + q;
-      for (int k = 0; k < 3; k++) out->rhs[g] += eps * fd_ko(f, G->st[k], G->dxx[k]);
+      for (int k = 0; k < 3; k++) out->rhs[g] += eps * fd_ko(&G->fd, f, G->st[k], G->dxx[k]);
     }
 
   /* ---- 15. constraints: Eq. 16 (H), Eq. 17 (M^i), C^i ------------------ */
@@ -1050,28 +1134,13 @@ static void interior_index(const Grid* G, long long t, int* i0, int* i1, int* i2
  * at each pure-outer ghost point; f_inf = 1 for alpha and W, 0 otherwise;
  * v = sqrt(2) for alpha (the asymptotic gauge speed of 1+log slicing), 1
  * otherwise. rhat.grad f = sum_i (x/r . grad xx^i) df/dxx^i, each logical
- * derivative the 4th-order five-point one, centred where the array allows and
- * shifted to stay inside it otherwise. The pure-outer points are then
+ * derivative the (N_FD + 1)-point one of the grid's order (Sec. 4.2 pairs
+ * eighth-order differencing with an eighth-order radiation condition),
+ * centred where the array allows and shifted to stay inside it otherwise. The pure-outer points are then
  * advanced by the time integrator like interior points, and the inner ghosts
  * are copies as before.                                                     */
 static double somm_finf(int g) { return (g == ALPHA || g == CF) ? 1.0 : 0.0; }
 static double somm_speed(int g) { return g == ALPHA ? sqrt(2.0) : 1.0; }
-
-/* w[j] with f'(0) ~ sum_j w[j] f(m[j]): the derivative at 0 of the Lagrange
- * interpolant through the five integer nodes m[]                           */
-static void lagrange_d1(const int m[5], double w[5]) {
-  for (int j = 0; j < 5; j++) {
-    double s = 0.0;
-    for (int k = 0; k < 5; k++) {
-      if (k == j) continue;
-      double prod = 1.0 / (double)(m[j] - m[k]);
-      for (int l = 0; l < 5; l++)
-        if (l != j && l != k) prod *= (0.0 - m[l]) / (double)(m[j] - m[l]);
-      s += prod;
-    }
-    w[j] = s;
-  }
-}
 
 static void radiation_point(const Grid* G, const double* y, int i0, int i1, int i2, double rhs[NGF]) {
   const int idx[3] = {i0, i1, i2};
@@ -1086,15 +1155,16 @@ static void radiation_point(const Grid* G, const double* y, int i0, int i1, int 
     rd[i] = 0.0;
     for (int a = 0; a < 3; a++) rd[i] += x[a] / r * K[a][i];
   }
+  const int R = G->fd.R, W = 2 * R + 1; /* stencil width of the FD order */
   int s[3];
-  double w[3][5];
+  double w[3][2 * MAXR + 1];
   for (int d = 0; d < 3; d++) {
-    s[d] = -2;
-    if (idx[d] - 2 < 0) s[d] = -idx[d];
-    if (idx[d] + 2 > G->n[d] - 1) s[d] = G->n[d] - 1 - idx[d] - 4;
-    int m[5];
-    for (int j = 0; j < 5; j++) m[j] = s[d] + j;
-    lagrange_d1(m, w[d]);
+    s[d] = -R;
+    if (idx[d] - R < 0) s[d] = -idx[d];
+    if (idx[d] + R > G->n[d] - 1) s[d] = G->n[d] - 1 - idx[d] - 2 * R;
+    int m[2 * MAXR + 1];
+    for (int j = 0; j < W; j++) m[j] = s[d] + j;
+    lagrange_weights(W, m, 1, w[d]);
   }
   const long long q = flat(G, i0, i1, i2);
   for (int g = 0; g < NGF; g++) {
@@ -1102,7 +1172,7 @@ static void radiation_point(const Grid* G, const double* y, int i0, int i1, int 
     double drf = 0.0;
     for (int d = 0; d < 3; d++) {
       double D = 0.0;
-      for (int j = 0; j < 5; j++) D += w[d][j] * f[(s[d] + j) * G->st[d]];
+      for (int j = 0; j < W; j++) D += w[d][j] * f[(s[d] + j) * G->st[d]];
       drf += rd[d] * D / G->dxx[d];
     }
     const double v = somm_speed(g);

@@ -27,7 +27,7 @@ extern "C" {
 typedef struct {
   int coord;       /* 0 SinhSpherical, 1 SinhCylindrical, 2 Spherical */
   int N[3];        /* interior points per direction */
-  int ng;          /* ghost layers (3) */
+  int ng;          /* ghost layers N_G, 3..6: finite differences of order 2 (N_G - 1) */
   double ampl[3];  /* outer extent of the sinh (or linear) maps */
   double sinhw[3]; /* sinh widths */
   double cfl;
@@ -102,6 +102,10 @@ int oracle_ssprk3_step(const oracle_params* p, double eta, double dt, double* y)
  * doubles) at flat index idx: d1[k], d2[3*k+l], upwinded U+[k], U-[k]. */
 int oracle_fd_point(const oracle_params* p, const double* f, long long idx, double d1[3],
                     double d2[9], double uplus[3], double uminus[3]);
+
+/* Kreiss-Oliger operator (without the strength) of f at flat index idx
+ * along each direction k: ko[k]. */
+int oracle_ko_point(const oracle_params* p, const double* f, long long idx, double ko[3]);
 
 /* Set the number of OpenMP threads the oracle runs with (n > 0). */
 void oracle_set_num_threads(int n);

@@ -57,6 +57,7 @@ def lib():
             "oracle_rk4_step": (ctypes.c_int, [P, ctypes.c_double, ctypes.c_double, dp]),
             "oracle_ssprk3_step": (ctypes.c_int, [P, ctypes.c_double, ctypes.c_double, dp]),
             "oracle_fd_point": (ctypes.c_int, [P, dp, ctypes.c_longlong, dp, dp, dp, dp]),
+            "oracle_ko_point": (ctypes.c_int, [P, dp, ctypes.c_longlong, dp]),
             "oracle_num_threads": (ctypes.c_int, []),
             "oracle_set_num_threads": (None, [ctypes.c_int]),
         }
@@ -215,6 +216,15 @@ class Grid:
         if rc:
             raise RuntimeError("oracle_fd_point failed")
         return d1, d2.reshape(3, 3), up, dn
+
+    def ko_point(self, f, idx):
+        """Kreiss-Oliger operator (unit strength) of f at flat index idx along
+        each direction."""
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        ko = np.zeros(3)
+        if lib().oracle_ko_point(ctypes.byref(self.p), _dp(f), int(idx), _dp(ko)):
+            raise RuntimeError("oracle_ko_point failed")
+        return ko
 
     def flat(self, i0, i1, i2):
         return (i2 * self.n[1] + i1) * self.n[0] + i0

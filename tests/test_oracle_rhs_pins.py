@@ -5,7 +5,10 @@ Convergence checks evaluate analytic data at every point (ghosts included),
 so they test the discrete operator alone; errors are taken at coarse points
 that are also fine points after 3x refinement of a cell-centred grid, where
 4th-order finite differences give an error ratio near 3^4 = 81 (2nd order
-would give 9; a wrong or missing term gives about 1).
+would give 9; a wrong or missing term gives about 1). With N_G = 5 ghost
+layers the differences are of 8th order (Sec. 3, N_G = N_FD/2 + 1; the
+production head-on run of Sec. 4.2) and the ratio is near 3^8 = 6561; the
+bound 400 fails for any stencil of 6th order or lower.
 """
 import numpy as np
 import pytest
@@ -15,14 +18,19 @@ from oracle import oracle as orc
 
 RATIO_MIN = 30.0
 KS_RATIO_MIN = 20.0  # strong-field case, not fully asymptotic at these sizes
+# (ghost layers, smallest error ratio under 3x refinement, smallest median
+# over the fields checked): 4th and 8th order. The 8th-order cases are not
+# fully asymptotic at these sizes (ratios from 169 to about 20000, medians
+# above 560); 4th-order stencils give 50 to 100.
+ORDERS = [(3, RATIO_MIN, RATIO_MIN), (5, 150.0, 500.0)]
 
 
 def _refine(Nc, r=3):
     return tuple(n * r if n > 2 else n for n in Nc)
 
 
-def _common_index(Nc, fine):
-    c, f = an.common_points(Nc, ratio=tuple(3 if n > 2 else 1 for n in Nc))
+def _common_index(Nc, fine, ng=3):
+    c, f = an.common_points(Nc, ng=ng, ratio=tuple(3 if n > 2 else 1 for n in Nc))
     return np.ix_(*(f if fine else c)[::-1])
 
 
@@ -65,31 +73,33 @@ def _away(x, pos, rp, rmax):
     return ok
 
 
+@pytest.mark.parametrize("ng,ratio_min,median_min", ORDERS)
 @pytest.mark.parametrize("coord,Nc,ampl,w,m,pos", BL_CASES)
-def test_bl_rhs_converges_to_closed_form(coord, Nc, ampl, w, m, pos):
+def test_bl_rhs_converges_to_closed_form(coord, Nc, ampl, w, m, pos, ng, ratio_min, median_min):
     """d_t K = -2 psi^-8 |grad psi|^2, d_t a_ij = -8 psi^-8 (psi_i psi_j -
     delta_ij |grad psi|^2/3) in the rescaled frame, every other RHS exactly 0
     (conformally flat, time-symmetric data with alpha = psi^-2, beta = 0)."""
     errs = []
     for fine in (False, True):
         N = _refine(Nc) if fine else Nc
-        g = orc.Grid(coord, N, ampl=ampl, sinhw=w)
-        y = an.bl_state(coord, N, ampl, w, m, pos)
+        g = orc.Grid(coord, N, ampl=ampl, sinhw=w, ng=ng)
+        y = an.bl_state(coord, N, ampl, w, m, pos, ng=ng)
         rhs = g.rhs(y, eta=2.0)
-        ex = an.bl_rhs_closed_form(coord, N, ampl, w, m, pos)
+        ex = an.bl_rhs_closed_form(coord, N, ampl, w, m, pos, ng=ng)
         I = g.interior()
         for gi, name in enumerate(an.GF_NAMES):
             if name != "trK" and not name.startswith("aDD"):
                 assert np.all(rhs[gi][I] == 0.0), name
-        _, x, _ = an.mesh(coord, N, ampl, w)
-        idx = _common_index(Nc, fine)
+        _, x, _ = an.mesh(coord, N, ampl, w, ng=ng)
+        idx = _common_index(Nc, fine, ng)
         sel = _away(x[idx], pos, 0.6, 0.75 * ampl[0])
         errs.append({n: np.max(np.abs(rhs[an.GF[n]][idx] - ex[an.GF[n]][idx])[sel])
                      for n in ("trK", "aDD00", "aDD11", "aDD22", "aDD02")})
         scale = {n: np.max(np.abs(ex[an.GF[n]][idx])[sel]) for n in errs[-1]}
     for n in errs[0]:
         assert errs[1][n] < 1e-2 * scale[n]
-        assert errs[0][n] / errs[1][n] > RATIO_MIN, (n, errs[0][n], errs[1][n])
+        assert errs[0][n] / errs[1][n] > ratio_min, (n, errs[0][n], errs[1][n])
+    assert np.median([errs[0][n] / errs[1][n] for n in errs[0]]) > median_min
 
 
 @pytest.mark.parametrize("coord,Nc,ampl,w,m,pos", BL_CASES)
@@ -112,11 +122,11 @@ def test_bl_hamiltonian_constraint_converges_to_zero(coord, Nc, ampl, w, m, pos)
 
 
 # ----------------------------------------------- Ricci tensor of a curved metric
-def _ricci_case(coord, N, ampl, w, amp=0.15, sigma=0.8, c=(0.35, -0.2, 0.3)):
+def _ricci_case(coord, N, ampl, w, amp=0.15, sigma=0.8, c=(0.35, -0.2, 0.3), ng=3):
     rng = np.random.default_rng(19)
     M = rng.uniform(-1, 1, (3, 3))
     M = M + M.T
-    _, x, E = an.mesh(coord, N, ampl, w)
+    _, x, E = an.mesh(coord, N, ampl, w, ng=ng)
     gmet, dg, ddg = an.gaussian_metric(x, amp, M, c, sigma)
     _, Lam, R = an.christoffel_and_ricci(gmet, dg, ddg)
     y = np.zeros((an.NGF,) + x.shape[:-1])
@@ -134,16 +144,17 @@ def _ricci_case(coord, N, ampl, w, amp=0.15, sigma=0.8, c=(0.35, -0.2, 0.3)):
 
 @pytest.mark.parametrize("coord,Nc,ampl,w", [(an.SINH_SPHERICAL, (12, 8, 8), (2.0,) * 3, (0.4,) * 3),
                                              (an.SINH_CYLINDRICAL, (10, 8, 12), (2.0,) * 3, (0.4,) * 3)])
-def test_ricci_converges_to_textbook_ricci(coord, Nc, ampl, w):
+@pytest.mark.parametrize("ng,ratio_min,median_min", ORDERS)
+def test_ricci_converges_to_textbook_ricci(coord, Nc, ampl, w, ng, ratio_min, median_min):
     """Eq. 12 with Lambdabar^i = Delta^i equals the Ricci tensor of gammabar
     computed from its Christoffel symbols, R_bd = d_a G^a_bd - d_d G^a_ba +
     G^a_ae G^e_bd - G^a_de G^e_ba (here in Cartesian coordinates)."""
     errs, errs_away = [], []
     for fine in (False, True):
         N = _refine(Nc) if fine else Nc
-        g = orc.Grid(coord, N, ampl=ampl, sinhw=w)
-        y, Rf = _ricci_case(coord, N, ampl, w)
-        idx = _common_index(Nc, fine)
+        g = orc.Grid(coord, N, ampl=ampl, sinhw=w, ng=ng)
+        y, Rf = _ricci_case(coord, N, ampl, w, ng=ng)
+        idx = _common_index(Nc, fine, ng)
         flat = np.array([g.flat(i0, i1, i2) for i2 in idx[0].ravel() for i1 in idx[1].ravel()
                          for i0 in idx[2].ravel()])
         _, ric = g.rhs_points(y, flat, want_ricci=True)
@@ -152,20 +163,21 @@ def test_ricci_converges_to_textbook_ricci(coord, Nc, ampl, w):
         errs.append(np.max(err, axis=0))
         # away from the coordinate singularities, where the 1/(r sin(theta))^2
         # factors of the curvilinear operators do not amplify the FD error
-        _, x, _ = an.mesh(coord, N, ampl, w)
+        _, x, _ = an.mesh(coord, N, ampl, w, ng=ng)
         xs = x[idx].reshape(-1, 3)
         away = np.sqrt(xs[:, 0] ** 2 + xs[:, 1] ** 2) > 0.4
         errs_away.append(np.max(err[away], axis=0))
         scale = np.max(np.abs(ex))
-    # 4th-order convergence at every common point, the axis included
-    assert np.all(errs[0] / errs[1] > RATIO_MIN), (errs[0], errs[1])
+    # convergence at the stencils' order at every common point, the axis included
+    assert np.all(errs[0] / errs[1] > ratio_min), (errs[0], errs[1])
     assert np.all(errs_away[1] < 2e-2 * scale), (errs_away[1], scale)
-    assert np.all(errs_away[0] / errs_away[1] > RATIO_MIN), (errs_away[0], errs_away[1])
+    assert np.all(errs_away[0] / errs_away[1] > ratio_min), (errs_away[0], errs_away[1])
+    assert np.median(errs[0] / errs[1]) > median_min
 
 
 # ------------------------------------------------------------ pure gauge shift
-def _gauge_case(coord, N, ampl, w):
-    (X0, X1, X2), x, E = an.mesh(coord, N, ampl, w)
+def _gauge_case(coord, N, ampl, w, ng=3):
+    (X0, X1, X2), x, E = an.mesh(coord, N, ampl, w, ng=ng)
     V = (0.3, -0.2, 0.25)
     L = ((0.2, -0.1, 0.3), (0.15, 0.1, -0.2), (-0.3, 0.25, 0.05))
     xi, dxi, ddxi = an.gauge_field(x, 0.5, (0.2, -0.3, 0.25), 0.9, V, L)
@@ -200,7 +212,8 @@ def _gauge_case(coord, N, ampl, w):
 
 @pytest.mark.parametrize("coord,Nc,ampl,w", [(an.SINH_SPHERICAL, (12, 8, 8), (2.0,) * 3, (0.4,) * 3),
                                              (an.SINH_CYLINDRICAL, (10, 8, 12), (2.0,) * 3, (0.4,) * 3)])
-def test_pure_gauge_shift_converges_to_closed_form(coord, Nc, ampl, w):
+@pytest.mark.parametrize("ng,ratio_min,median_min", ORDERS)
+def test_pure_gauge_shift_converges_to_closed_form(coord, Nc, ampl, w, ng, ratio_min, median_min):
     """Flat data with a shift beta = xi: d_t gammabar = Lie_xi delta - 2/3 delta
     div xi, d_t Lambdabar = lap xi + grad div xi / 3, d_t W = -div xi / 3,
     d_t B = 3/4 d_t Lambdabar, d_t beta^i = beta^j d_j beta^i (coordinate
@@ -208,14 +221,14 @@ def test_pure_gauge_shift_converges_to_closed_form(coord, Nc, ampl, w):
     errs, errs_away = [], []
     for fine in (False, True):
         N = _refine(Nc) if fine else Nc
-        g = orc.Grid(coord, N, ampl=ampl, sinhw=w)
-        y, ex = _gauge_case(coord, N, ampl, w)
+        g = orc.Grid(coord, N, ampl=ampl, sinhw=w, ng=ng)
+        y, ex = _gauge_case(coord, N, ampl, w, ng=ng)
         rhs = g.rhs(y, eta=2.0)
         I = g.interior()
         for name in ("alpha", "trK", "aDD00", "aDD01", "aDD02", "aDD11", "aDD12", "aDD22"):
             assert np.all(rhs[an.GF[name]][I] == 0.0), name
-        idx = _common_index(Nc, fine)
-        _, x, _ = an.mesh(coord, N, ampl, w)
+        idx = _common_index(Nc, fine, ng)
+        _, x, _ = an.mesh(coord, N, ampl, w, ng=ng)
         away = np.sqrt(x[idx][..., 0] ** 2 + x[idx][..., 1] ** 2) > 0.4
         errs.append(np.array([np.max(np.abs(rhs[gi][idx] - ex[gi][idx])) for gi in range(an.NGF)]))
         errs_away.append(np.array([np.max(np.abs(rhs[gi][idx] - ex[gi][idx])[away]) for gi in range(an.NGF)]))
@@ -223,9 +236,10 @@ def test_pure_gauge_shift_converges_to_closed_form(coord, Nc, ampl, w):
     checked = [n for n in an.GF_NAMES if n.startswith(("hDD", "lambdaU", "betU", "vetU")) or n == "cf"]
     for n in checked:
         gi = an.GF[n]
-        assert errs[0][gi] / errs[1][gi] > RATIO_MIN, (n, errs[0][gi], errs[1][gi])
-        assert errs_away[0][gi] / errs_away[1][gi] > RATIO_MIN, (n, errs_away[0][gi], errs_away[1][gi])
+        assert errs[0][gi] / errs[1][gi] > ratio_min, (n, errs[0][gi], errs[1][gi])
+        assert errs_away[0][gi] / errs_away[1][gi] > ratio_min, (n, errs_away[0][gi], errs_away[1][gi])
         assert errs_away[1][gi] < 2e-2 * max(scale[gi], 1e-3), n
+    assert np.median([errs[0][an.GF[n]] / errs[1][an.GF[n]] for n in checked]) > median_min
 
 
 # ---------------------------------------------------------------- RK4 order
