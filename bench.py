@@ -35,6 +35,10 @@ PEAK_HBM = 8.0e12           # bytes/s
 # derivatives that vanish identically there, and its own count applies.
 F_ALG = {(0, False): 5792, (0, True): 5037, (1, False): 5314, (1, True): 4553, (2, False): 5597,
          (2, True): 4842}
+# the same for the 8th-order kernels (five ghost layers), with Kreiss-Oliger
+# dissipation as the production head-on numerics run them
+F_ALG8_KO = {(0, False): 11510, (0, True): 8220, (1, False): 11032, (1, True): 7736, (2, False): 11315,
+             (2, True): 8025}
 
 
 def two_planes(coord, N):
@@ -134,17 +138,17 @@ def events(n):
     return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
 
 
-def time_rhs(capi, g, y, eta, reps, stream):
+def time_rhs(capi, g, y, eta, reps, stream, diss=(0.0, 0.0)):
     """Average duration of one right-hand-side launch (HIP events on the
     launch stream)."""
     import torch
     rhs = g.state()
     for _ in range(5):
-        capi.bssn_rhs(g.h, y, rhs, None, eta=eta, stream=stream)
+        capi.bssn_rhs(g.h, y, rhs, None, eta=eta, diss=diss, stream=stream)
     e0, e1 = events(2)
     e0.record(stream)
     for _ in range(reps):
-        capi.bssn_rhs(g.h, y, rhs, None, eta=eta, stream=stream)
+        capi.bssn_rhs(g.h, y, rhs, None, eta=eta, diss=diss, stream=stream)
     e1.record(stream)
     torch.cuda.synchronize()
     del rhs
@@ -161,14 +165,16 @@ def make_grids(capi, jobs, bc_kind=0):
     return grids
 
 
-def run_ssprk3(capi, wl, stream, steps, diss=(0.0, 0.0), bc_kind=0):
+def run_ssprk3(capi, wl, stream, steps, diss=(0.0, 0.0), bc_kind=0, nghosts=3, rhs_reps=0):
     """The head-on workload advanced with SSPRK3, the integrator of the
     paper's production head-on run (three right-hand sides per step), with
-    optional Kreiss-Oliger dissipation (the run's strengths: 0.99, 0.3) and
-    the Sommerfeld outer boundary."""
+    optional Kreiss-Oliger dissipation (the run's strengths: 0.99, 0.3), the
+    Sommerfeld outer boundary and 8th-order differences (nghosts = 5); with
+    rhs_reps > 0 also the right-hand-side kernel alone (extrapolation grid of
+    the same shape, same dissipation)."""
     import torch
     w = wl.WORKLOADS["headon_sinhcylindrical_128x2x256"]
-    g = capi.Grid(w["coord"], w["N"], w["ampl"], w["sinhw"], w["cfl"], bc_kind=bc_kind)
+    g = capi.Grid(w["coord"], w["N"], w["ampl"], w["sinhw"], w["cfl"], bc_kind=bc_kind, nghosts=nghosts)
     y, ws = g.state(), g.workspace()
     capi.set_initial_data_brill_lindquist(g.h, w["masses"], w["positions"], y, stream=stream)
     capi.grid_tune(g.h, y, g.state(), eta=w["eta"], diss=diss, stream=stream)
@@ -183,12 +189,28 @@ def run_ssprk3(capi, wl, stream, steps, diss=(0.0, 0.0), bc_kind=0):
     step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
     total_s = ev[0].elapsed_time(ev[-1]) / 1e3
     n = g.info.n_interior
-    return {"workload": "headon_sinhcylindrical_128x2x256 with SSPRK3"
-                        + (", Kreiss-Oliger %g/%g" % diss if diss[0] or diss[1] else "")
-                        + (", Sommerfeld outer boundary" if bc_kind else ""), "steps": steps,
-            "value": n * steps / total_s, "unit": UNIT, "ms_per_step": 1e3 * total_s / steps,
-            "p50_step_ms": percentile(step_ms, 50), "p99_step_ms": percentile(step_ms, 99),
-            "finite": bool(torch.isfinite(y).all().item())}
+    out = {"workload": "headon_sinhcylindrical_128x2x256 with SSPRK3"
+                       + (", Kreiss-Oliger %g/%g" % diss if diss[0] or diss[1] else "")
+                       + (", Sommerfeld outer boundary" if bc_kind else "")
+                       + (", 8th-order differences" if nghosts == 5 else ""), "steps": steps,
+           "value": n * steps / total_s, "unit": UNIT, "ms_per_step": 1e3 * total_s / steps,
+           "p50_step_ms": percentile(step_ms, 50), "p99_step_ms": percentile(step_ms, 99),
+           "finite": bool(torch.isfinite(y).all().item()), "tile": list(capi.grid_get_tile(g.h))}
+    if rhs_reps > 0:
+        ge = capi.Grid(w["coord"], w["N"], w["ampl"], w["sinhw"], w["cfl"], nghosts=nghosts)
+        capi.grid_set_tile(ge.h, *capi.grid_get_tile(g.h))
+        ye = ge.state()
+        capi.set_initial_data_brill_lindquist(ge.h, w["masses"], w["positions"], ye, stream=stream)
+        rhs_s = time_rhs(capi, ge, ye, w["eta"], rhs_reps, stream, diss=diss)
+        flops = (F_ALG8_KO if nghosts == 5 and (diss[0] or diss[1]) else {})
+        f = flops.get((w["coord"], two_planes(w["coord"], w["N"])))
+        out["rhs_launch_s"] = rhs_s
+        if f is not None:
+            out["rhs_flops_per_point"] = f
+            out["rhs_TFLOPs"] = f * n / rhs_s / 1e12
+            out["rhs_frac_fp64_peak"] = f * n / rhs_s / PEAK_FP64_VECTOR
+        del ye
+    return out
 
 
 def run_batched(capi, wl, stream, steps, seq_steps, graph_steps, integrator=0, diss=(0.0, 0.0), bc_kind=0):
@@ -455,9 +477,15 @@ def main():
             extras["ssprk3"] = run_ssprk3(capi, wl, stream, args.ssprk3_steps, diss=(0.99, 0.3))
             extras["production_numerics"] = run_ssprk3(capi, wl, stream, args.ssprk3_steps, diss=(0.99, 0.3),
                                                         bc_kind=capi.BC_RADIATION)
+            # the production head-on numerics in full (Sec. 4.2): 8th-order
+            # differences, ninth-order dissipation, eighth-order radiation
+            extras["production_numerics_8th_order"] = run_ssprk3(
+                capi, wl, stream, args.ssprk3_steps, diss=(0.99, 0.3), bc_kind=capi.BC_RADIATION, nghosts=5,
+                rhs_reps=args.rhs_reps)
             torch.cuda.empty_cache()
             print(f"# ssprk3 + dissipation: {extras['ssprk3']['value']:.3e} pt-steps/s, with the radiation "
-                  f"boundary {extras['production_numerics']['value']:.3e}", file=sys.stderr, flush=True)
+                  f"boundary {extras['production_numerics']['value']:.3e}, at 8th order "
+                  f"{extras['production_numerics_8th_order']['value']:.3e}", file=sys.stderr, flush=True)
         if args.batched_steps > 0:
             extras["batched"] = run_batched(capi, wl, stream, args.batched_steps, args.batched_seq_steps,
                                             args.graph_steps)
@@ -511,8 +539,8 @@ def main():
                    "tile": list(capi.grid_get_tile(g.h))},
         "latency": {"p50_step_ms": percentile(step_ms, 50), "p99_step_ms": percentile(step_ms, 99)},
         "finite": finite,
-        "roofline": {"kernel": "k_rhs_fused<%d,%s>" % (w["coord"], "true" if two_planes(w["coord"], w["N"])
-                                                         else "false"), "bound": "alu",
+        "roofline": {"kernel": "k_rhs_fused<%d,%s,false,3>" % (w["coord"], "true" if two_planes(w["coord"], w["N"])
+                                                                 else "false"), "bound": "alu",
                      "achieved": achieved / 1e12, "peak": PEAK_FP64_VECTOR / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_VECTOR, "traffic": traffic,
                      "flops_per_point": f_alg(w["coord"], w["N"]), "points": n_int, "launch_s": rhs_s,

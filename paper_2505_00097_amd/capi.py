@@ -167,14 +167,15 @@ def gauge(eta=2.0, diss=(0.0, 0.0)):
 
 
 # ---- the C ABI, one Python function per entry point ----------------------
-def grid_create(coord, N, ampl=(10.0, 10.0, 10.0), sinhw=(0.2, 0.2, 0.2), cfl=0.5, bc_kind=0):
+def grid_create(coord, N, ampl=(10.0, 10.0, 10.0), sinhw=(0.2, 0.2, 0.2), cfl=0.5, bc_kind=0, nghosts=3):
+    """nghosts 3: 4th-order differences; 5: 8th order."""
     p = GridParams()
     p.coord = int(coord)
     for d in range(3):
         p.N[d] = int(N[d])
         p.ampl[d] = float(ampl[d])
         p.sinhw[d] = float(sinhw[d])
-    p.nghosts = 3
+    p.nghosts = int(nghosts)
     p.cfl = float(cfl)
     p.bc_kind = int(bc_kind)
     h = _vp()
@@ -323,9 +324,9 @@ def server_create(budget_bytes, max_jobs, steps_per_tick=10, keep_results=False,
     return s
 
 
-def job_desc(coord, N, ampl, sinhw, cfl, masses, positions, nsteps, lapse_kind=0, bc_kind=0):
+def job_desc(coord, N, ampl, sinhw, cfl, masses, positions, nsteps, lapse_kind=0, bc_kind=0, nghosts=3):
     d = JobDesc()
-    d.grid = GridParams(int(coord), (ctypes.c_int * 3)(*N), 3, (ctypes.c_double * 3)(*ampl),
+    d.grid = GridParams(int(coord), (ctypes.c_int * 3)(*N), int(nghosts), (ctypes.c_double * 3)(*ampl),
                         (ctypes.c_double * 3)(*sinhw), float(cfl), int(bc_kind))
     d.n_punct = len(masses)
     for i, (m, x) in enumerate(zip(masses, positions)):
@@ -373,8 +374,8 @@ def server_destroy(s):
 class Grid:
     """A grid on the current device plus helpers to allocate its arrays."""
 
-    def __init__(self, coord, N, ampl=(10.0, 10.0, 10.0), sinhw=(0.2, 0.2, 0.2), cfl=0.5, bc_kind=0):
-        self.h = grid_create(coord, N, ampl, sinhw, cfl, bc_kind)
+    def __init__(self, coord, N, ampl=(10.0, 10.0, 10.0), sinhw=(0.2, 0.2, 0.2), cfl=0.5, bc_kind=0, nghosts=3):
+        self.h = grid_create(coord, N, ampl, sinhw, cfl, bc_kind, nghosts)
         self.info = grid_get_info(self.h)
         self.coord = int(coord)
         self.N = tuple(int(n) for n in N)

@@ -1,9 +1,10 @@
 """FP64 operations per interior point of one right-hand-side evaluation.
 
 Compiles the right-hand-side kernel source to optimised device LLVM IR with
-the library's own flags and counts, in each k_rhs_fused<C, AX, KO> kernel (AX:
-the variant for grids with two phi planes, whose identically vanishing phi
-derivatives the compiler removes; KO: Kreiss-Oliger dissipation on), the double
+the library's own flags and counts, in each k_rhs_fused<C, AX, KO, H> kernel
+(AX: the variant for grids with two phi planes, whose identically vanishing
+phi derivatives the compiler removes; KO: Kreiss-Oliger dissipation on; H:
+ghost layers, 3 for 4th-order and 5 for 8th-order differences), the double
 precision fadd / fsub / fmul / fdiv instructions (an fma or fmuladd call
 counts 2) of the basic blocks that store nothing to global memory: that is
 the per-point arithmetic of Eqs. 7-15 after common-subexpression elimination,
@@ -34,12 +35,13 @@ def device_ir(src):
         return f.read()
 
 
-def count(ir, kernel_prefix="_ZN4bhah11k_rhs_fusedILi", dissipation=False):
+def count(ir, kernel_prefix="_ZN4bhah11k_rhs_fusedILi", dissipation=False, nghosts=3):
     """{(coord, two_phi_planes): FP64 operations per point} of the kernels
-    without (or, with dissipation=True, with) Kreiss-Oliger dissipation"""
+    with `nghosts` ghost layers, without (or, with dissipation=True, with)
+    Kreiss-Oliger dissipation"""
     res = {}
-    for m in re.finditer(r"define [^@]*@(" + re.escape(kernel_prefix) + r"(\d)ELb(\d)ELb(\d)E\S*)\(", ir):
-        if bool(int(m.group(4))) != dissipation:
+    for m in re.finditer(r"define [^@]*@(" + re.escape(kernel_prefix) + r"(\d)ELb(\d)ELb(\d)ELi(\d)E\S*)\(", ir):
+        if bool(int(m.group(4))) != dissipation or int(m.group(5)) != nghosts:
             continue
         name, c = m.group(1), (int(m.group(2)), bool(int(m.group(3))))
         body = ir[m.start():ir.index("\n}\n", m.start())]
@@ -55,10 +57,11 @@ def count(ir, kernel_prefix="_ZN4bhah11k_rhs_fusedILi", dissipation=False):
 
 def main():
     ir = device_ir(os.path.join(HERE, "csrc", "rhs_fused.hip"))
-    for ko in (False, True):
-        for (c, ax), n in sorted(count(ir, dissipation=ko).items()):
-            print(f"{COORD_NAMES[c]}{' (two phi planes)' if ax else ''}{' + dissipation' if ko else ''}: "
-                  f"{n} FP64 operations per point")
+    for ng in (3, 5):
+        for ko in (False, True):
+            for (c, ax), n in sorted(count(ir, dissipation=ko, nghosts=ng).items()):
+                print(f"order {2 * (ng - 1)}: {COORD_NAMES[c]}{' (two phi planes)' if ax else ''}"
+                      f"{' + dissipation' if ko else ''}: {n} FP64 operations per point")
 
 
 if __name__ == "__main__":

@@ -11,7 +11,7 @@
 
 namespace bhah {
 
-constexpr int NG = 3;     // ghost layers
+constexpr int NG = 3;     // ghost layers of the 4th-order grids (5 for 8th order)
 constexpr int NGF = 24;   // evolved gridfunctions
 constexpr int NAUX = 9;   // rescaled Ricci (6) + contracted d Gammabar term (3)
 
@@ -34,6 +34,7 @@ struct GridDev {
   int N0, N1, N2;      // interior points
   int n0, n1, n2;      // incl. ghosts
   int s1, s2;          // flat strides of i1, i2 (s0 = 1)
+  int ng;              // ghost layers N_G (3 or 5): differences of order 2 (N_G - 1)
   long long sgf;       // gridfunction stride = n0*n1*n2
   double inv_dx[3];    // 1/dxx
   const double* tab0;  // [n0][TAB_W]
@@ -67,8 +68,9 @@ struct GhostDev {
 };
 
 // Pure-outer ghost points evolved by the radiation condition: flat index,
-// packed stencil starts (s0 + 4) | (s2 + 4) << 4 of the five-point logical
-// derivatives along xx0 and xx2 (s in -4..0), and per point 1/r and
+// packed stencil starts (s0 + 2R) | (s2 + 2R) << 4 of the (2R+1)-point
+// logical derivatives along xx0 and xx2 (s in -2R..0, R = N_G - 1), and per
+// point 1/r and
 // (rhat . grad xx^k) / dxx^k for k = 0, 2 (zero where r does not depend on
 // xx^k).
 struct RadDev {
@@ -76,6 +78,8 @@ struct RadDev {
   const int* q;       // [n]
   const int* shift;   // [n]
   const double* coef;  // [n][3]
+  int R;              // stencil radius N_G - 1
+  const double* w;    // [2R+1][2R+1]: row s + 2R holds the weights of nodes s..s+2R
 };
 // host copy of a ghost list in the GhostDev layout
 struct HostGhosts {
@@ -172,26 +176,27 @@ struct BatchHdr {
 // point and parity bits (bit d: the direction-d basis vector reverses).
 struct Classifier {
   int coord = 0;
+  int ng = NG;
   int N[3] = {0, 0, 0};
   int n[3] = {0, 0, 0};
   int flat(int a, int b, int c) const { return (int)(a + n[0] * (b + n[1] * (long long)c)); }
-  static int wrap(int j, int N) {
-    int m = (j - NG) % N;
+  int wrap(int j, int N) const {
+    int m = (j - ng) % N;
     if (m < 0) m += N;
-    return NG + m;
+    return ng + m;
   }
   int operator()(int i0, int i1, int i2, int& src, int& par) const {
     src = flat(i0, i1, i2);
     par = 0;
-    if (i0 >= NG && i0 < NG + N[0] && i1 >= NG && i1 < NG + N[1] && i2 >= NG && i2 < NG + N[2]) return 0;
+    if (i0 >= ng && i0 < ng + N[0] && i1 >= ng && i1 < ng + N[1] && i2 >= ng && i2 < ng + N[2]) return 0;
     int j0 = i0, j1 = i1, j2 = i2;
     if (coord == BHAH_SINH_CYLINDRICAL) {
-      if (j0 < NG) { j0 = 2 * NG - 1 - j0; j1 += N[1] / 2; par ^= 0b011; }
+      if (j0 < ng) { j0 = 2 * ng - 1 - j0; j1 += N[1] / 2; par ^= 0b011; }
       j1 = wrap(j1, N[1]);
     } else {
-      if (j0 < NG) { j0 = 2 * NG - 1 - j0; j1 = N[1] + 2 * NG - 1 - j1; j2 += N[2] / 2; par ^= 0b101; }
-      if (j1 < NG) { j1 = 2 * NG - 1 - j1; j2 += N[2] / 2; par ^= 0b110; }
-      else if (j1 >= N[1] + NG) { j1 = 2 * (N[1] + NG) - 1 - j1; j2 += N[2] / 2; par ^= 0b110; }
+      if (j0 < ng) { j0 = 2 * ng - 1 - j0; j1 = N[1] + 2 * ng - 1 - j1; j2 += N[2] / 2; par ^= 0b101; }
+      if (j1 < ng) { j1 = 2 * ng - 1 - j1; j2 += N[2] / 2; par ^= 0b110; }
+      else if (j1 >= N[1] + ng) { j1 = 2 * (N[1] + ng) - 1 - j1; j2 += N[2] / 2; par ^= 0b110; }
       j2 = wrap(j2, N[2]);
     }
     if (j0 == i0 && j1 == i1 && j2 == i2) { par = 0; return 1; }
@@ -224,7 +229,7 @@ struct bhah_grid {
   // radiation outer boundary: the evolved outer points and the inner ghosts
   // as one-hop parity copies (all of them; those with an interior phi index)
   std::vector<int> rad_q, rad_shift;
-  std::vector<double> rad_coef;
+  std::vector<double> rad_coef, rad_w;
   bhah::HostGhosts inner_full, inner_stage;
   bhah::RadDev rad{};
   bhah::GhostDev ghost_inner{}, ghost_inner_stage{};

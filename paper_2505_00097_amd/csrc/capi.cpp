@@ -111,12 +111,15 @@ static hipError_t upload_radiation(bhah_grid* g) {
   const size_t n = g->rad_q.size();
   std::vector<int> packed(g->rad_q);
   packed.insert(packed.end(), g->rad_shift.begin(), g->rad_shift.end());
+  // coefficients [n][3], then the stencil weight table
+  const size_t nw = g->rad_w.size();
+  std::vector<double> coef(g->rad_coef);
+  coef.insert(coef.end(), g->rad_w.begin(), g->rad_w.end());
   hipError_t e = hipMalloc((void**)&g->d_rad_i, (n ? 2 * n : 1) * sizeof(int));
-  if (e == hipSuccess) e = hipMalloc((void**)&g->d_rad_c, (n ? 3 * n : 1) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&g->d_rad_c, (3 * n + nw) * sizeof(double));
   if (e == hipSuccess && n) e = hipMemcpy(g->d_rad_i, packed.data(), 2 * n * sizeof(int), hipMemcpyHostToDevice);
-  if (e == hipSuccess && n)
-    e = hipMemcpy(g->d_rad_c, g->rad_coef.data(), 3 * n * sizeof(double), hipMemcpyHostToDevice);
-  g->rad = RadDev{(int)n, g->d_rad_i, g->d_rad_i + n, g->d_rad_c};
+  if (e == hipSuccess) e = hipMemcpy(g->d_rad_c, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice);
+  g->rad = RadDev{(int)n, g->d_rad_i, g->d_rad_i + n, g->d_rad_c, g->params.nghosts - 1, g->d_rad_c + 3 * n};
   const HostGhosts* L[2] = {&g->inner_full, &g->inner_stage};
   GhostDev* D[2] = {&g->ghost_inner, &g->ghost_inner_stage};
   for (int k = 0; k < 2 && e == hipSuccess; k++)
@@ -181,6 +184,7 @@ int bhah_grid_create(const bhah_grid_params* params, bhah_grid** out) {
   g->tile = TileCfg{6, 0, BHAH_DEFAULT_BAND};
   GridDev& D = g->dev;
   D.coord = params->coord;
+  D.ng = params->nghosts;
   D.N0 = params->N[0]; D.N1 = params->N[1]; D.N2 = params->N[2];
   D.n0 = I.n_total[0]; D.n1 = I.n_total[1]; D.n2 = I.n_total[2];
   D.s1 = D.n0;

@@ -68,17 +68,59 @@ void map_row(bool linear, double A, double w, double x, double* out) {
 
 using Comb = std::map<int, long long>;  // interior flat index -> integer weight
 
+// d/dx at 0 of the polynomial interpolating f at the integer nodes s..s+2R:
+// weights w_j = L_j'(0) of the Lagrange basis, summed in exact rational
+// arithmetic (numerators and denominators stay below 2^40 for R <= 4) and
+// rounded once to double.
+struct Frac {
+  long long p = 0, q = 1;
+  static long long gcd(long long a, long long b) {
+    a = a < 0 ? -a : a;
+    while (b) { const long long t = a % b; a = b; b = t; }
+    return a;
+  }
+  Frac norm() const {
+    const long long g = gcd(p, q < 0 ? -q : q);
+    Frac r{p / g, q / g};
+    if (r.q < 0) { r.p = -r.p; r.q = -r.q; }
+    return r;
+  }
+  Frac operator*(const Frac& o) const { return Frac{p * o.p, q * o.q}.norm(); }
+  Frac operator+(const Frac& o) const { return Frac{p * o.q + o.p * q, q * o.q}.norm(); }
+};
+std::vector<double> one_sided_weights(int R) {
+  const int W = 2 * R + 1;
+  std::vector<double> out((size_t)W * W);
+  for (int row = 0; row < W; row++) {
+    const int s = row - 2 * R;
+    for (int j = 0; j < W; j++) {
+      Frac sum;
+      for (int k = 0; k < W; k++) {
+        if (k == j) continue;
+        Frac prod{1, j - k};
+        for (int i = 0; i < W; i++)
+          if (i != j && i != k) prod = prod * Frac{-(s + i), j - i};
+        sum = sum + prod.norm();
+      }
+      out[(size_t)row * W + j] = (double)sum.p / (double)sum.q;
+    }
+  }
+  return out;
+}
+
 }  // namespace
 
 int build_grid_host(const bhah_grid_params* p, bhah_grid* g) {
   const int coord = p->coord;
   if (coord < 0 || coord > 2) return fail(BHAH_EINVAL, "coord must be 0, 1 or 2");
-  if (p->nghosts != NG) return fail(BHAH_EINVAL, "nghosts must be 3");
+  // N_G = 3: 4th-order differences; N_G = 5: 8th order (Sec. 3, N_G = N_FD/2 + 1)
+  if (p->nghosts != 3 && p->nghosts != 5) return fail(BHAH_EINVAL, "nghosts must be 3 or 5");
+  const int ng = p->nghosts;
   if (p->bc_kind != BHAH_BC_EXTRAP && p->bc_kind != BHAH_BC_RADIATION)
     return fail(BHAH_EINVAL, "bc_kind must be BHAH_BC_EXTRAP or BHAH_BC_RADIATION");
   const int dphi = coord == BHAH_SINH_CYLINDRICAL ? 1 : 2;
   for (int d = 0; d < 3; d++) {
-    if (d != dphi && p->N[d] < NG) return fail(BHAH_EINVAL, "N[d] < nghosts in a non-periodic direction");
+    if (d != dphi && p->N[d] < ng) return fail(BHAH_EINVAL, "N[d] < nghosts in a non-periodic direction");
   }
   if (p->N[dphi] < 2 || p->N[dphi] % 2) return fail(BHAH_EINVAL, "N_phi must be even and >= 2");
   if (!(p->ampl[0] > 0)) return fail(BHAH_EINVAL, "ampl[0] must be > 0");
@@ -86,7 +128,7 @@ int build_grid_host(const bhah_grid_params* p, bhah_grid* g) {
   if (coord == BHAH_SINH_CYLINDRICAL && (!(p->ampl[2] > 0) || !(p->sinhw[2] > 0)))
     return fail(BHAH_EINVAL, "ampl[2] and sinhw[2] must be > 0");
   if (!(p->cfl > 0)) return fail(BHAH_EINVAL, "cfl must be > 0");
-  const long long n0 = p->N[0] + 2 * NG, n1 = p->N[1] + 2 * NG, n2 = p->N[2] + 2 * NG;
+  const long long n0 = p->N[0] + 2 * ng, n1 = p->N[1] + 2 * ng, n2 = p->N[2] + 2 * ng;
   if (n0 * n1 * n2 >= (1LL << 26))
     return fail(BHAH_EINVAL, "grid too large: at most 2^26 points including ghosts (31-bit stencil offsets)");
 
@@ -106,7 +148,7 @@ int build_grid_host(const bhah_grid_params* p, bhah_grid* g) {
   I.workspace_doubles = 3 * I.state_doubles;
 
   // ---- 1-D tables --------------------------------------------------------
-  auto xx = [&](int d, int j) { return dom.lo[d] + ((double)(j - NG) + 0.5) * I.dxx[d]; };
+  auto xx = [&](int d, int j) { return dom.lo[d] + ((double)(j - ng) + 0.5) * I.dxx[d]; };
   for (int d = 0; d < 3; d++) g->tab[d].assign((size_t)n[d] * TAB_W, 0.0);
   auto map_full = [&](bool linear, double A, double w, double x, double* row) {
     map_row(linear, A, w, x, row);
@@ -130,9 +172,9 @@ int build_grid_host(const bhah_grid_params* p, bhah_grid* g) {
 
   // ---- CFL time step: cfl * min over interior points of min_i S_i dxx^i ----
   double dsmin = INFINITY;
-  for (int i2 = NG; i2 < NG + p->N[2]; i2++)
-    for (int i1 = NG; i1 < NG + p->N[1]; i1++)
-      for (int i0 = NG; i0 < NG + p->N[0]; i0++) {
+  for (int i2 = ng; i2 < ng + p->N[2]; i2++)
+    for (int i1 = ng; i1 < ng + p->N[1]; i1++)
+      for (int i0 = ng; i0 < ng + p->N[0]; i0++) {
         const double* t0 = &g->tab[0][(size_t)i0 * TAB_W];
         double S[3];
         if (coord == BHAH_SINH_CYLINDRICAL) {
@@ -154,6 +196,7 @@ int build_grid_host(const bhah_grid_params* p, bhah_grid* g) {
   };
   Classifier& classify = g->classify;
   classify.coord = coord;
+  classify.ng = ng;
   for (int d = 0; d < 3; d++) {
     classify.N[d] = p->N[d];
     classify.n[d] = n[d];
@@ -172,9 +215,9 @@ int build_grid_host(const bhah_grid_params* p, bhah_grid* g) {
     const auto it = comb.find(q);
     return it == comb.end() ? none : it->second;
   };
-  int lo[3] = {NG, NG, NG}, hi[3] = {NG + p->N[0], NG + p->N[1], NG + p->N[2]};
+  int lo[3] = {ng, ng, ng}, hi[3] = {ng + p->N[0], ng + p->N[1], ng + p->N[2]};
   const long long st[3] = {1, n0, n0 * n1};
-  for (int layer = 0; layer < NG; layer++) {
+  for (int layer = 0; layer < ng; layer++) {
     for (int d = 0; d < 3; d++) {
       for (int side = 0; side < 2; side++) {
         const int face = side == 0 ? lo[d] - 1 : hi[d];
@@ -261,7 +304,7 @@ int build_grid_host(const bhah_grid_params* p, bhah_grid* g) {
   for (size_t t = 0; t < g->g_dst.size(); t++) {
     const int q = g->g_dst[t];
     const int idx = pd == 1 ? (q / n[0]) % n[1] : q / (n[0] * n[1]);
-    if (idx < NG || idx >= NG + p->N[pd]) continue;
+    if (idx < ng || idx >= ng + p->N[pd]) continue;
     g->r_dst.push_back(q);
     g->r_start.push_back((int)g->r_src.size());
     g->r_par.push_back(g->g_par[t]);
@@ -276,12 +319,15 @@ int build_grid_host(const bhah_grid_params* p, bhah_grid* g) {
 
   // ---- radiation outer boundary ------------------------------------------
   g->rad_q.clear(); g->rad_shift.clear(); g->rad_coef.clear();
+  g->rad_w = one_sided_weights(ng - 1);
   g->inner_full = HostGhosts{};
   g->inner_stage = HostGhosts{};
   if (p->bc_kind == BHAH_BC_RADIATION) {
-    // five-point stencil start along a direction of n points at index i:
-    // centred where it fits, else shifted to stay inside the array
-    auto start_of = [](int i, int nd) { return i - 2 < 0 ? -i : (i + 2 > nd - 1 ? nd - 1 - i - 4 : -2); };
+    // (2R+1)-point stencil start along a direction of n points at index i
+    // (R = N_G - 1, the order of the differencing): centred where it fits,
+    // else shifted to stay inside the array
+    const int R = ng - 1;
+    auto start_of = [R](int i, int nd) { return i - R < 0 ? -i : (i + R > nd - 1 ? nd - 1 - i - 2 * R : -R); };
     for (int i2 = 0; i2 < n[2]; i2++)
       for (int i1 = 0; i1 < n[1]; i1++)
         for (int i0 = 0; i0 < n[0]; i0++) {
@@ -305,16 +351,16 @@ int build_grid_host(const bhah_grid_params* p, bhah_grid* g) {
               a0 = 1.0 / t0[1];
             }
             const int s0 = start_of(i0, n[0]);
-            const int s2 = coord == BHAH_SINH_CYLINDRICAL ? start_of(i2, n[2]) : -2;
+            const int s2 = coord == BHAH_SINH_CYLINDRICAL ? start_of(i2, n[2]) : -R;
             g->rad_q.push_back(q);
-            g->rad_shift.push_back((s0 + 4) | ((s2 + 4) << 4));
+            g->rad_shift.push_back((s0 + 2 * R) | ((s2 + 2 * R) << 4));
             g->rad_coef.push_back(1.0 / r);
             g->rad_coef.push_back(a0 / I.dxx[0]);
             g->rad_coef.push_back(a2 / I.dxx[2]);
           } else {
             const int idx = pd == 1 ? i1 : i2;
             for (HostGhosts* L : {&g->inner_full, &g->inner_stage}) {
-              if (L == &g->inner_stage && (idx < NG || idx >= NG + p->N[pd])) continue;
+              if (L == &g->inner_stage && (idx < ng || idx >= ng + p->N[pd])) continue;
               L->dst.push_back(q);
               L->start.push_back((int)L->src.size());
               L->par.push_back(par);

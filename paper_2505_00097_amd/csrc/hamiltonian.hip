@@ -1,6 +1,6 @@
 // hamiltonian.hip -- the constraints: Hamiltonian (Eq. 16 of arXiv:2505.00097),
 // momentum (Eq. 17) and C^i, one thread per interior point, centred
-// 4th-order differences.
+// differences of the grid's order (4th with 3 ghost layers, 8th with 5).
 #include "rhs_common.h"
 
 namespace bhah {
@@ -14,10 +14,10 @@ struct PointIdx {
 
 __device__ __forceinline__ PointIdx point_of(const GridDev& G) {
   PointIdx p;
-  p.i0 = NG + (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  p.i1 = NG + (int)blockIdx.y;
-  p.i2 = NG + (int)blockIdx.z;
-  p.valid = p.i0 < NG + G.N0;
+  p.i0 = G.ng + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  p.i1 = G.ng + (int)blockIdx.y;
+  p.i2 = G.ng + (int)blockIdx.z;
+  p.valid = p.i0 < G.ng + G.N0;
   p.q = (unsigned)(p.i0 + G.s1 * p.i1 + G.s2 * p.i2);
   return p;
 }
@@ -30,12 +30,12 @@ __device__ __forceinline__ PointIdx point_of(const GridDev& G) {
 //   C^i = Lambdabar^i - Delta^i
 // with phi = -ln(W)/2 (W^2 = e^{-4 phi}); M^i and C^i are returned rescaled
 // like lambda^i (times S_i). Any of H, Mo, Co may be null.
-template <int C>
+template <int C, int NH>
 __device__ __forceinline__ void constraints_point(const GridDev& G, const double* __restrict__ y,
                                                   const PointIdx& p, double* __restrict__ H,
                                                   double* __restrict__ Mo, double* __restrict__ Co) {
-  const Pt P(y, G, C, p.i0, p.i1, p.i2);
-  const Spacing sp = make_spacing(G);
+  const PtT<NH> P(y, G, C, p.i0, p.i1, p.i2);
+  const Spacing sp = make_spacing<NH - 1>(G);
   Ref R;
   load_ref<C>(G, p.i0, p.i1, p.i2, R);
   double Gh[3][3][3];
@@ -153,18 +153,18 @@ __device__ __forceinline__ void constraints_point(const GridDev& G, const double
   }
 }
 
-template <int C>
+template <int C, int NH>
 __global__ void __launch_bounds__(64) k_hamiltonian(GridDev G, const double* __restrict__ y,
                                                    double* __restrict__ H) {
   const PointIdx p = point_of(G);
-  if (p.valid) constraints_point<C>(G, y, p, H, nullptr, nullptr);
+  if (p.valid) constraints_point<C, NH>(G, y, p, H, nullptr, nullptr);
 }
 
-template <int C>
+template <int C, int NH>
 __global__ void __launch_bounds__(64) k_constraints(GridDev G, const double* __restrict__ y, double* __restrict__ H,
                                                    double* __restrict__ Mo, double* __restrict__ Co) {
   const PointIdx p = point_of(G);
-  if (p.valid) constraints_point<C>(G, y, p, H, Mo, Co);
+  if (p.valid) constraints_point<C, NH>(G, y, p, H, Mo, Co);
 }
 
 // ---- launchers -------------------------------------------------------------
@@ -172,28 +172,35 @@ static dim3 grid_of(const GridDev& G, int bx) {
   return dim3((G.N0 + bx - 1) / bx, G.N1, G.N2);
 }
 
-void launch_hamiltonian(const GridDev& G, const double* y, double* H, hipStream_t s) {
+template <int NH>
+static void launch_constraints_t(const GridDev& G, const double* y, double* H, double* Mo, double* Co,
+                                 hipStream_t s) {
   const dim3 g = grid_of(G, 64);
+  const bool only_H = Mo == nullptr && Co == nullptr;
   switch (G.coord) {
-    case BHAH_SINH_SPHERICAL: hipLaunchKernelGGL(k_hamiltonian<BHAH_SINH_SPHERICAL>, g, dim3(64), 0, s, G, y, H); break;
-    case BHAH_SINH_CYLINDRICAL: hipLaunchKernelGGL(k_hamiltonian<BHAH_SINH_CYLINDRICAL>, g, dim3(64), 0, s, G, y, H); break;
-    default: hipLaunchKernelGGL(k_hamiltonian<BHAH_SPHERICAL>, g, dim3(64), 0, s, G, y, H); break;
+    case BHAH_SINH_SPHERICAL:
+      if (only_H) hipLaunchKernelGGL((k_hamiltonian<BHAH_SINH_SPHERICAL, NH>), g, dim3(64), 0, s, G, y, H);
+      else hipLaunchKernelGGL((k_constraints<BHAH_SINH_SPHERICAL, NH>), g, dim3(64), 0, s, G, y, H, Mo, Co);
+      break;
+    case BHAH_SINH_CYLINDRICAL:
+      if (only_H) hipLaunchKernelGGL((k_hamiltonian<BHAH_SINH_CYLINDRICAL, NH>), g, dim3(64), 0, s, G, y, H);
+      else hipLaunchKernelGGL((k_constraints<BHAH_SINH_CYLINDRICAL, NH>), g, dim3(64), 0, s, G, y, H, Mo, Co);
+      break;
+    default:
+      if (only_H) hipLaunchKernelGGL((k_hamiltonian<BHAH_SPHERICAL, NH>), g, dim3(64), 0, s, G, y, H);
+      else hipLaunchKernelGGL((k_constraints<BHAH_SPHERICAL, NH>), g, dim3(64), 0, s, G, y, H, Mo, Co);
+      break;
   }
 }
 
+void launch_hamiltonian(const GridDev& G, const double* y, double* H, hipStream_t s) {
+  if (G.ng == 5) launch_constraints_t<5>(G, y, H, nullptr, nullptr, s);
+  else launch_constraints_t<3>(G, y, H, nullptr, nullptr, s);
+}
+
 void launch_constraints(const GridDev& G, const double* y, double* H, double* Mo, double* Co, hipStream_t s) {
-  const dim3 g = grid_of(G, 64);
-  switch (G.coord) {
-    case BHAH_SINH_SPHERICAL:
-      hipLaunchKernelGGL(k_constraints<BHAH_SINH_SPHERICAL>, g, dim3(64), 0, s, G, y, H, Mo, Co);
-      break;
-    case BHAH_SINH_CYLINDRICAL:
-      hipLaunchKernelGGL(k_constraints<BHAH_SINH_CYLINDRICAL>, g, dim3(64), 0, s, G, y, H, Mo, Co);
-      break;
-    default:
-      hipLaunchKernelGGL(k_constraints<BHAH_SPHERICAL>, g, dim3(64), 0, s, G, y, H, Mo, Co);
-      break;
-  }
+  if (G.ng == 5) launch_constraints_t<5>(G, y, H, Mo, Co, s);
+  else launch_constraints_t<3>(G, y, H, Mo, Co, s);
 }
 
 }  // namespace bhah

@@ -81,9 +81,9 @@ struct Punctures {
 // Brill-Lindquist: psi = 1 + sum m_n / (2 |x - x_n|); W = psi^-2; alpha =
 // psi^-2 (precollapsed) or 1; all other variables zero. Interior points.
 __global__ void __launch_bounds__(64) k_brill_lindquist(GridDev G, Punctures P, double* __restrict__ y) {
-  const int i0 = NG + (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  const int i1 = NG + (int)blockIdx.y, i2 = NG + (int)blockIdx.z;
-  if (i0 >= NG + G.N0) return;
+  const int i0 = G.ng + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  const int i1 = G.ng + (int)blockIdx.y, i2 = G.ng + (int)blockIdx.z;
+  if (i0 >= G.ng + G.N0) return;
   const double r = G.tab0[i0 * TAB_W];
   double x[3];
   if (G.coord == BHAH_SINH_CYLINDRICAL) {
@@ -108,25 +108,27 @@ __global__ void __launch_bounds__(64) k_brill_lindquist(GridDev G, Punctures P, 
 }
 
 // ---- Sommerfeld radiation condition at the pure-outer points --------------
-// d_t f = -v (f - f_inf)/r - v (c0 D0 f + c2 D2 f), with D_k the five-point
-// 4th-order first derivative in grid units along xx^k starting s_k points
-// from the point (s = -2 centred; -4, -3 at a max face, -1, 0 at a min face)
-// and c_k = (rhat . grad xx^k)/dxx^k precomputed per point. One thread per
-// (outer point, group of GF_PER gridfunctions); the result is combined into
-// the stage arrays exactly as the right-hand-side kernel does it.
-__constant__ double kRadW[5][5] = {
-    {3.0 / 12, -16.0 / 12, 36.0 / 12, -48.0 / 12, 25.0 / 12},  // nodes -4..0
-    {-1.0 / 12, 6.0 / 12, -18.0 / 12, 10.0 / 12, 3.0 / 12},    // nodes -3..1
-    {1.0 / 12, -8.0 / 12, 0.0, 8.0 / 12, -1.0 / 12},           // nodes -2..2
-    {-3.0 / 12, -10.0 / 12, 18.0 / 12, -6.0 / 12, 1.0 / 12},   // nodes -1..3
-    {-25.0 / 12, 48.0 / 12, -36.0 / 12, 16.0 / 12, -3.0 / 12}  // nodes 0..4
-};
-
+// d_t f = -v (f - f_inf)/r - v (c0 D0 f + c2 D2 f), with D_k the
+// (2R+1)-point first derivative of the grid's order (R = N_G - 1) in grid
+// units along xx^k starting s_k points from the point (s = -R centred, lower
+// at a max face, higher at a min face) and c_k = (rhat . grad xx^k)/dxx^k
+// precomputed per point; the weights of every start come from the grid's
+// table. One thread per (outer point, group of GF_PER gridfunctions); the
+// result is combined into the stage arrays exactly as the right-hand-side
+// kernel does it.
+template <int RS>
 __device__ __forceinline__ void radiation_point(const GridDev& G, const RadDev& R, int t,
                                                 const double* __restrict__ in, const StageArgs& st, int g0) {
+  constexpr int W = 2 * RS + 1;  // RS: the stencil radius R.R
   const long long q = R.q[t];
   const int sh = R.shift[t];
-  const int s0 = (sh & 15) - 4, s2 = ((sh >> 4) & 15) - 4;
+  const int s0 = (sh & 15) - 2 * RS, s2 = ((sh >> 4) & 15) - 2 * RS;
+  double w0[W], w2[W];
+#pragma unroll
+  for (int m = 0; m < W; m++) {
+    w0[m] = R.w[(s0 + 2 * RS) * W + m];
+    w2[m] = R.w[(s2 + 2 * RS) * W + m];
+  }
   const double ir = R.coef[3 * t], c0 = R.coef[3 * t + 1], c2 = R.coef[3 * t + 2];
   const bool cyl = G.coord == BHAH_SINH_CYLINDRICAL;
   double k[GF_PER];
@@ -136,10 +138,10 @@ __device__ __forceinline__ void radiation_point(const GridDev& G, const RadDev& 
     const double* f = in + g * G.sgf + q;
     double d0 = 0.0, d2 = 0.0;
 #pragma unroll
-    for (int m = 0; m < 5; m++) d0 += kRadW[s0 + 4][m] * f[s0 + m];
+    for (int m = 0; m < W; m++) d0 += w0[m] * f[s0 + m];
     if (cyl) {
 #pragma unroll
-      for (int m = 0; m < 5; m++) d2 += kRadW[s2 + 4][m] * f[(long long)(s2 + m) * G.s2];
+      for (int m = 0; m < W; m++) d2 += w2[m] * f[(long long)(s2 + m) * G.s2];
     }
     const double v = g == BHAH_ALPHA ? 1.4142135623730951 : 1.0;  // sqrt(2) for the lapse
     const double finf = (g == BHAH_ALPHA || g == BHAH_CF) ? 1.0 : 0.0;
@@ -161,19 +163,23 @@ __device__ __forceinline__ void radiation_point(const GridDev& G, const RadDev& 
   }
 }
 
+template <int RS>
 __global__ void __launch_bounds__(256) k_radiation(GridDev G, RadDev R, const double* __restrict__ in,
                                                    StageArgs st) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < R.n) radiation_point(G, R, t, in, st, (int)blockIdx.y * GF_PER);
+  if (t < R.n) radiation_point<RS>(G, R, t, in, st, (int)blockIdx.y * GF_PER);
 }
 
 void launch_radiation(const GridDev& G, const RadDev& R, const double* in, const StageArgs& st, hipStream_t s) {
   if (R.n == 0) return;
-  hipLaunchKernelGGL(k_radiation, dim3((R.n + 255) / 256, NGF / GF_PER), dim3(256), 0, s, G, R, in, st);
+  const dim3 grid((R.n + 255) / 256, NGF / GF_PER);
+  if (R.R == 4) hipLaunchKernelGGL(k_radiation<4>, grid, dim3(256), 0, s, G, R, in, st);
+  else hipLaunchKernelGGL(k_radiation<2>, grid, dim3(256), 0, s, G, R, in, st);
 }
 
-// Ensemble form: blocks stride over the (job, chunk of 256 radiation points)
-// list; each job's stage input and combination come from its table entry.
+// Ensemble form (4th-order grids): blocks stride over the (job, chunk of 256
+// radiation points) list; each job's stage input and combination come from
+// its table entry.
 __global__ void __launch_bounds__(256) k_radiation_batch(const BatchJob* __restrict__ jobs,
                                                          const BatchHdr* __restrict__ hdr,
                                                          const int2* __restrict__ work, int stage) {
@@ -184,7 +190,7 @@ __global__ void __launch_bounds__(256) k_radiation_batch(const BatchJob* __restr
     const int2 wk = wl[c];
     const BatchJob* J = jobs + wk.x;
     const int t = wk.y * 256 + (int)threadIdx.x;
-    if (t < J->rad.n) radiation_point(J->G, J->rad, t, J->in[stage], J->st[stage], g0);
+    if (t < J->rad.n) radiation_point<NG - 1>(J->G, J->rad, t, J->in[stage], J->st[stage], g0);
   }
 }
 

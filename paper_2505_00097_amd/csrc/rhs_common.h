@@ -53,54 +53,95 @@ __device__ __forceinline__ double gf_ld(const double* y, long long sgf, int g, u
   return __builtin_bit_cast(double, v);
 }
 
-// Stencil access around one point. Stencil values are read with raw buffer
-// loads: the per-lane part of the byte offset goes in the vector offset, the
-// part shared by the wave in the scalar offset. The periodic direction phi
-// (i1 on SinhCylindrical grids, i2 on spherical ones) is read with the index
-// wrapped onto the interior planes, so phi ghost points are never read: they
-// are exact copies of those planes (periodicity, no parity change), and the
-// values read are identical. The phi index must be the same for every lane of
-// the wave (tile extent 1 along phi).
-struct Pt {
+// Finite-difference weights of order N_FD = 2R (Sec. 3: N_G = R + 1 ghost
+// layers, the extra layer for the upwinded advection stencils), as integers
+// over a common denominator, unit spacing:
+//   D f  = sum_{j=1..R} d1[j] (f_j - f_-j) / den1
+//   D2 f = (sum_{j=1..R} d2[j] (f_j + f_-j) + d2[0] f_0) / den2
+//   U f  = sum_{m != 1} up[m + R - 1] (f_m - f_1) / den1, m = -(R-1)..R+1,
+//          the centred stencil shifted one point upwind (offsets times the
+//          sign of the shift component)
+//   KO f = (sum_{j=1..R+1} ko[j] (f_j + f_-j) + ko[0] f_0) / kden, the
+//          difference of order 2(R+1) scaled to the Fourier symbol
+//          -sin^(2R+2)(theta/2) (Kreiss-Oliger dissipation of order 2R+1,
+//          Sec. 4.2)
+// R = 2: the 4th-order stencils; R = 4: the 8th-order ones of the
+// production head-on run (Sec. 4.2).
+template <int R>
+struct FdW;
+template <>
+struct FdW<2> {
+  static constexpr double d1[3] = {0.0, 8.0, -1.0}, den1 = 12.0;
+  static constexpr double d2[3] = {-30.0, 16.0, -1.0}, den2 = 12.0;
+  static constexpr double up[5] = {-3.0, -10.0, 18.0, -6.0, 1.0};
+  static constexpr double ko[4] = {-20.0, 15.0, -6.0, 1.0}, kden = 64.0;
+};
+template <>
+struct FdW<4> {
+  static constexpr double d1[5] = {0.0, 672.0, -168.0, 32.0, -3.0}, den1 = 840.0;
+  static constexpr double d2[5] = {-14350.0, 8064.0, -1008.0, 128.0, -9.0}, den2 = 5040.0;
+  static constexpr double up[9] = {-5.0, 60.0, -420.0, -378.0, 1050.0, -420.0, 140.0, -30.0, 3.0};
+  static constexpr double ko[6] = {-252.0, 210.0, -120.0, 45.0, -10.0, 1.0}, kden = 1024.0;
+};
+
+// Stencil access around one point, H = N_G ghost layers (stencil radius up
+// to H). Stencil values are read with raw buffer loads: the per-lane part of
+// the byte offset goes in the vector offset, the part shared by the wave in
+// the scalar offset. The periodic direction phi (i1 on SinhCylindrical
+// grids, i2 on spherical ones) is read with the index wrapped onto the
+// interior planes, so phi ghost points are never read: they are exact copies
+// of those planes (periodicity, no parity change), and the values read are
+// identical. The phi index must be the same for every lane of the wave (tile
+// extent 1 along phi).
+template <int H_>
+struct PtT {
+  static constexpr int H = H_, R = H_ - 1;
   const double* __restrict__ y;
   long long sgf;
-  int pd;       // periodic direction (1 or 2)
-  int se;       // stride of the other transverse direction
-  unsigned vb;  // per-lane byte offset of (i0 - 3, i_e - 3) with the phi index removed
-  int sw[7];    // byte offsets of the wrapped phi planes at offsets -3..3 (wave-uniform)
+  int pd;            // periodic direction (1 or 2)
+  int se;            // stride of the other transverse direction
+  unsigned vb;       // per-lane byte offset of (i0 - H, i_e - H) with the phi index removed
+  int sw[2 * H + 1];  // byte offsets of the wrapped phi planes at offsets -H..H (wave-uniform)
 
-  __device__ __forceinline__ Pt(const double* y_, const GridDev& G, int C, int i0, int i1, int i2)
+  __device__ __forceinline__ PtT(const double* y_, const GridDev& G, int C, int i0, int i1, int i2)
       : y(y_), sgf(G.sgf) {
     pd = C == BHAH_SINH_CYLINDRICAL ? 1 : 2;
     const int sd = pd == 1 ? G.s1 : G.s2;
     const int nd = pd == 1 ? G.N1 : G.N2;
     se = pd == 1 ? G.s2 : G.s1;
     const int ie = pd == 1 ? i2 : i1;
-    const int id = __builtin_amdgcn_readfirstlane((pd == 1 ? i1 : i2) - NG);
-    vb = (unsigned)(i0 - 3 + se * (ie - 3)) * 8u;
+    const int id = __builtin_amdgcn_readfirstlane((pd == 1 ? i1 : i2) - H);
+    vb = (unsigned)(i0 - H + se * (ie - H)) * 8u;
 #pragma unroll
-    for (int o = -3; o <= 3; o++) {
+    for (int o = -H; o <= H; o++) {
       int x = id + o;
-      x += x < 0 ? nd : 0;
-      x += x < 0 ? nd : 0;
-      x -= x >= nd ? nd : 0;
-      x -= x >= nd ? nd : 0;
-      sw[o + 3] = (NG + x) * sd * 8;
+      if constexpr (H == 3) {  // nd >= 2: two corrections each way suffice
+        x += x < 0 ? nd : 0;
+        x += x < 0 ? nd : 0;
+        x -= x >= nd ? nd : 0;
+        x -= x >= nd ? nd : 0;
+      } else {
+        x %= nd;
+        x += x < 0 ? nd : 0;
+      }
+      sw[o + H] = (H + x) * sd * 8;
     }
   }
 
   // value at offsets (a, b, c) along (i0, i1, i2)
   __device__ __forceinline__ double at(int g, int a, int b, int c) const {
     const int od = pd == 1 ? b : c, oe = pd == 1 ? c : b;
-    return gf_ld(y, sgf, g, vb + (unsigned)((a + 3) * 8), sw[od + 3] + (oe + 3) * se * 8);
+    return gf_ld(y, sgf, g, vb + (unsigned)((a + H) * 8), sw[od + H] + (oe + H) * se * 8);
   }
   // values at offsets (a, b, c) and (a + 1, b, c)
   __device__ __forceinline__ void at2(int g, int a, int b, int c, double& lo, double& hi) const {
     const int od = pd == 1 ? b : c, oe = pd == 1 ? c : b;
-    gf_ld2(y, sgf, g, vb + (unsigned)((a + 3) * 8), sw[od + 3] + (oe + 3) * se * 8, lo, hi);
+    gf_ld2(y, sgf, g, vb + (unsigned)((a + H) * 8), sw[od + H] + (oe + H) * se * 8, lo, hi);
   }
   // byte offset of the point shifted by m along the periodic direction
-  __device__ __forceinline__ unsigned vper(int m) const { return vb + 24u + (unsigned)(3 * se * 8 + sw[m + 3]); }
+  __device__ __forceinline__ unsigned vper(int m) const {
+    return vb + (unsigned)(H * 8) + (unsigned)(H * se * 8 + sw[m + H]);
+  }
   template <int K>
   __device__ __forceinline__ double ax(int g, int m) const {
     return K == 0 ? at(g, m, 0, 0) : (K == 1 ? at(g, 0, m, 0) : at(g, 0, 0, m));
@@ -115,96 +156,141 @@ struct Pt {
   }
 };
 
+// 1/(den1 dxx^k), 1/(den2 dxx^k^2), 1/(den1^2 dxx^k dxx^l) for order 2R
 struct Spacing {
-  double i12h[3];       // 1/(12 dxx^k)
-  double i12hh[3];      // 1/(12 dxx^k^2)
-  double i144[3][3];    // 1/(144 dxx^k dxx^l)
+  double d1s[3];
+  double d2s[3];
+  double crs[3][3];
 };
 
+template <int R>
 __device__ __forceinline__ Spacing make_spacing(const GridDev& G) {
   Spacing s;
 #pragma unroll
   for (int k = 0; k < 3; k++) {
-    s.i12h[k] = G.inv_dx[k] * (1.0 / 12.0);
-    s.i12hh[k] = G.inv_dx[k] * G.inv_dx[k] * (1.0 / 12.0);
+    s.d1s[k] = G.inv_dx[k] * (1.0 / FdW<R>::den1);
+    s.d2s[k] = G.inv_dx[k] * G.inv_dx[k] * (1.0 / FdW<R>::den2);
   }
 #pragma unroll
   for (int k = 0; k < 3; k++)
 #pragma unroll
-    for (int l = 0; l < 3; l++) s.i144[k][l] = G.inv_dx[k] * G.inv_dx[l] * (1.0 / 144.0);
+    for (int l = 0; l < 3; l++) s.crs[k][l] = G.inv_dx[k] * G.inv_dx[l] * (1.0 / (FdW<R>::den1 * FdW<R>::den1));
   return s;
 }
 
-// ---- 4th-order finite differences (Sec. 3): centred 5-point stencils,
-// their tensor product for mixed derivatives. Sums are grouped into
-// differences so constant fields have exactly zero derivatives.
-template <int K>
-__device__ __forceinline__ double fd1(const Pt& P, int g, const Spacing& s) {
-  return (8.0 * (P.ax<K>(g, 1) - P.ax<K>(g, -1)) - (P.ax<K>(g, 2) - P.ax<K>(g, -2))) * s.i12h[K];
-}
-template <int K>
-__device__ __forceinline__ double fd2(const Pt& P, int g, const Spacing& s) {
-  return (16.0 * (P.ax<K>(g, 1) + P.ax<K>(g, -1)) - (P.ax<K>(g, 2) + P.ax<K>(g, -2)) -
-          30.0 * P.ax<K>(g, 0)) *
-         s.i12hh[K];
-}
-template <int K, int L>
-__device__ __forceinline__ double fdm(const Pt& P, int g, const Spacing& s) {
-  // D_K D_L f; the inner differences are left unnormalised
-  auto e = [&](int m) {
-    return 8.0 * (P.pl<K, L>(g, m, 1) - P.pl<K, L>(g, m, -1)) -
-           (P.pl<K, L>(g, m, 2) - P.pl<K, L>(g, m, -2));
-  };
-  return (8.0 * (e(1) - e(-1)) - (e(2) - e(-2))) * s.i144[K][L];
-}
-// Batched stencil gathers: values land in a local array first so that a
-// whole batch of loads is in flight before any is consumed.
-//   axis : f(-2), f(-1), f(0), f(1), f(2) along K
-//   cross: f(m, n) along (K, L) for m, n in {-2, -1, 1, 2}, m-major
-template <int K>
-__device__ __forceinline__ void gather_axis(const Pt& P, int g, double v[5]) {
-  if constexpr (K == 0) {  // i0 neighbours are adjacent in memory: pairs per load
-    P.at2(g, -2, 0, 0, v[0], v[1]);
-    v[2] = P.at(g, 0, 0, 0);
-    P.at2(g, 1, 0, 0, v[3], v[4]);
-  } else {
+// ---- centred finite differences (Sec. 3) on gathered values:
+//   axis : v[R + m] = f(m) along one direction, m = -R..R
+//   cross: v[2R a + b] = f(m_a, n_b) for m, n in {-R..-1, 1..R}, a-major
+// Sums are grouped into differences so constant fields have exactly zero
+// first derivatives (the 4th-order second differences sum to zero as well;
+// at 8th order the centre weight is applied as a difference too).
+template <int R>
+__device__ __forceinline__ double d1_axis(const double (&v)[2 * R + 1], double s) {
+  double a = FdW<R>::d1[1] * (v[R + 1] - v[R - 1]);
 #pragma unroll
-    for (int t = 0; t < 5; t++) v[t] = P.ax<K>(g, t - 2);
+  for (int j = 2; j <= R; j++) a += FdW<R>::d1[j] * (v[R + j] - v[R - j]);
+  return a * s;
+}
+template <int R>
+__device__ __forceinline__ double d2_axis(const double (&v)[2 * R + 1], double s) {
+  if constexpr (R == 2) {
+    return (16.0 * (v[3] + v[1]) - (v[4] + v[0]) - 30.0 * v[2]) * s;
+  } else {
+    double a = FdW<R>::d2[1] * ((v[R + 1] - v[R]) + (v[R - 1] - v[R]));
+#pragma unroll
+    for (int j = 2; j <= R; j++) a += FdW<R>::d2[j] * ((v[R + j] - v[R]) + (v[R - j] - v[R]));
+    return a * s;
   }
 }
-template <int K, int L>
-__device__ __forceinline__ void gather_cross(const Pt& P, int g, double v[16]) {
-  constexpr int off[4] = {-2, -1, 1, 2};
+// index of offset m (m != 0) in a cross-stencil row
+template <int R>
+__host__ __device__ constexpr int xo(int m) { return m < 0 ? m + R : m + R - 1; }
+template <int R>
+__device__ __forceinline__ double d2_cross(const double (&v)[4 * R * R], double s) {
+  auto e = [&](int a) {
+    double t = FdW<R>::d1[1] * (v[2 * R * a + xo<R>(1)] - v[2 * R * a + xo<R>(-1)]);
+#pragma unroll
+    for (int j = 2; j <= R; j++) t += FdW<R>::d1[j] * (v[2 * R * a + xo<R>(j)] - v[2 * R * a + xo<R>(-j)]);
+    return t;
+  };
+  double t = FdW<R>::d1[1] * (e(xo<R>(1)) - e(xo<R>(-1)));
+#pragma unroll
+  for (int j = 2; j <= R; j++) t += FdW<R>::d1[j] * (e(xo<R>(j)) - e(xo<R>(-j)));
+  return t * s;
+}
+
+// Batched stencil gathers: values land in a local array first so that a
+// whole batch of loads is in flight before any is consumed.
+template <int K, class PT>
+__device__ __forceinline__ void gather_axis(const PT& P, int g, double (&v)[2 * PT::R + 1]) {
+  constexpr int R = PT::R;
+  if constexpr (K == 0) {  // i0 neighbours are adjacent in memory: pairs per load
+#pragma unroll
+    for (int m = -R; m < 0; m += 2) P.at2(g, m, 0, 0, v[R + m], v[R + m + 1]);
+    v[R] = P.at(g, 0, 0, 0);
+#pragma unroll
+    for (int m = 1; m <= R; m += 2) P.at2(g, m, 0, 0, v[R + m], v[R + m + 1]);
+  } else {
+#pragma unroll
+    for (int t = 0; t < 2 * R + 1; t++) v[t] = P.template ax<K>(g, t - R);
+  }
+}
+template <int K, int L, class PT>
+__device__ __forceinline__ void gather_cross(const PT& P, int g, double (&v)[4 * PT::R * PT::R]) {
+  constexpr int R = PT::R, W = 2 * R;
   if constexpr (K == 0) {  // rows along i0 in pairs per load
 #pragma unroll
-    for (int b = 0; b < 4; b++) {
-      const int o1 = L == 1 ? off[b] : 0, o2 = L == 2 ? off[b] : 0;
-      P.at2(g, -2, o1, o2, v[b], v[4 + b]);
-      P.at2(g, 1, o1, o2, v[8 + b], v[12 + b]);
+    for (int b = 0; b < W; b++) {
+      const int n = b < R ? b - R : b - R + 1;
+      const int o1 = L == 1 ? n : 0, o2 = L == 2 ? n : 0;
+#pragma unroll
+      for (int m = -R; m < 0; m += 2) P.at2(g, m, o1, o2, v[W * xo<R>(m) + b], v[W * xo<R>(m + 1) + b]);
+#pragma unroll
+      for (int m = 1; m <= R; m += 2) P.at2(g, m, o1, o2, v[W * xo<R>(m) + b], v[W * xo<R>(m + 1) + b]);
     }
   } else {
 #pragma unroll
-    for (int a = 0; a < 4; a++)
+    for (int a = 0; a < W; a++)
 #pragma unroll
-      for (int b = 0; b < 4; b++) v[4 * a + b] = P.pl<K, L>(g, off[a], off[b]);
+      for (int b = 0; b < W; b++)
+        v[W * a + b] = P.template pl<K, L>(g, a < R ? a - R : a - R + 1, b < R ? b - R : b - R + 1);
   }
 }
-__device__ __forceinline__ double d1_axis(const double v[5], double s) {
-  return (8.0 * (v[3] - v[1]) - (v[4] - v[0])) * s;
+
+template <int K, class PT>
+__device__ __forceinline__ double fd1(const PT& P, int g, const Spacing& s) {
+  double v[2 * PT::R + 1];
+#pragma unroll
+  for (int t = 0; t < 2 * PT::R + 1; t++) v[t] = P.template ax<K>(g, t - PT::R);
+  return d1_axis<PT::R>(v, s.d1s[K]);
 }
-__device__ __forceinline__ double d2_axis(const double v[5], double s) {
-  return (16.0 * (v[3] + v[1]) - (v[4] + v[0]) - 30.0 * v[2]) * s;
+template <int K, class PT>
+__device__ __forceinline__ double fd2(const PT& P, int g, const Spacing& s) {
+  double v[2 * PT::R + 1];
+#pragma unroll
+  for (int t = 0; t < 2 * PT::R + 1; t++) v[t] = P.template ax<K>(g, t - PT::R);
+  return d2_axis<PT::R>(v, s.d2s[K]);
 }
-__device__ __forceinline__ double d2_cross(const double v[16], double s) {
-  auto e = [&](int a) { return 8.0 * (v[4 * a + 2] - v[4 * a + 1]) - (v[4 * a + 3] - v[4 * a + 0]); };
-  return (8.0 * (e(2) - e(1)) - (e(3) - e(0))) * s;
+template <int K, int L, class PT>
+__device__ __forceinline__ double fdm(const PT& P, int g, const Spacing& s) {
+  // D_K D_L f; the inner differences are left unnormalised
+  double v[4 * PT::R * PT::R];
+#pragma unroll
+  for (int a = 0; a < 2 * PT::R; a++)
+#pragma unroll
+    for (int b = 0; b < 2 * PT::R; b++)
+      v[2 * PT::R * a + b] =
+          P.template pl<K, L>(g, a < PT::R ? a - PT::R : a - PT::R + 1, b < PT::R ? b - PT::R : b - PT::R + 1);
+  return d2_cross<PT::R>(v, s.crs[K][L]);
 }
 
-__device__ __forceinline__ double fd1k(const Pt& P, int g, int k, const Spacing& s) {
+template <class PT>
+__device__ __forceinline__ double fd1k(const PT& P, int g, int k, const Spacing& s) {
   return k == 0 ? fd1<0>(P, g, s) : (k == 1 ? fd1<1>(P, g, s) : fd1<2>(P, g, s));
 }
 // second derivative d_k d_l (any order of k, l)
-__device__ __forceinline__ double fd2kl(const Pt& P, int g, int k, int l, const Spacing& s) {
+template <class PT>
+__device__ __forceinline__ double fd2kl(const PT& P, int g, int k, int l, const Spacing& s) {
   if (k == l) return k == 0 ? fd2<0>(P, g, s) : (k == 1 ? fd2<1>(P, g, s) : fd2<2>(P, g, s));
   const int a = k < l ? k : l, b = k < l ? l : k;
   return a == 0 ? (b == 1 ? fdm<0, 1>(P, g, s) : fdm<0, 2>(P, g, s)) : fdm<1, 2>(P, g, s);
@@ -321,7 +407,8 @@ __device__ __forceinline__ void sym_inverse(const double g[6], double gi[6]) {
 // eps, its first derivatives, gammabar, its inverse, Dhat eps and Delta
 // (Eq. 3; Eq. 4 in the form Delta^k_ij = 1/2 gammabar^kl (Dhat_i eps_lj +
 // Dhat_j eps_il - Dhat_l eps_ij); Eq. 5).
-__device__ __forceinline__ void metric_first(const Pt& P, const Ref& R, const double Gh[3][3][3],
+template <class PT>
+__device__ __forceinline__ void metric_first(const PT& P, const Ref& R, const double Gh[3][3][3],
                                              const Spacing& sp, Metric& M) {
 #pragma unroll
   for (int i = 0; i < 3; i++)
@@ -378,8 +465,8 @@ __device__ __forceinline__ void metric_first(const Pt& P, const Ref& R, const do
 // d_k Gammabar^j_jm = 1/2 (gammabar^jl d_k d_m gammabar_jl
 //                          - gammabar^ja gammabar^lb d_k gammabar_ab d_m gammabar_jl).
 // Rc[ij] is the coordinate-basis Rbar_ij.
-template <int C>
-__device__ __forceinline__ void ricci_and_Q(const Pt& P, const Ref& R, const double Gh[3][3][3],
+template <int C, class PT>
+__device__ __forceinline__ void ricci_and_Q(const PT& P, const Ref& R, const double Gh[3][3][3],
                                             const Spacing& sp, const Metric& M, double Rc[6],
                                             double Q[3], bool want_Q) {
   double dGh[3][3][3][3];

@@ -30,28 +30,77 @@ namespace bhah {
 // Upwinded advection beta^k d_k f of a rescaled gridfunction (Sec. 3: shift
 // advection terms use the stencil shifted one point upwind). With
 // sigma = sign(vet^k) and f(m) = f at offset m*sigma along k:
-//   beta^k U_k f = |beta^k|/(12 dxx^k) [3 (f(1) - f(-1)) + 10 (f(1) - f(0))
-//                                       - 6 (f(2) - f(1)) + (f(3) - f(1))].
-struct Upwind2 {
-  unsigned vp[3], vm[3], v2[3], v3[3];  // per-lane byte offsets of q+s, q-s, q+2s, q+3s
-  unsigned v2m[3], v3m[3];              // q-2s, q-3s (dissipation only)
+//   beta^k U_k f = |beta^k|/(den1 dxx^k) sum_{m != 1} up_m (f(m) - f(1)),
+// m = -(R-1)..R+1; at 4th order
+//   |beta^k|/(12 dxx^k) [3 (f(1) - f(-1)) + 10 (f(1) - f(0))
+//                        - 6 (f(2) - f(1)) + (f(3) - f(1))].
+template <int H>
+struct UpwindT {
+  unsigned vu[3][H];  // per-lane byte offsets of q + m s, m = 1..H (upwind side)
+  unsigned vd[3][H];  // q - m s (downwind side; beyond R - 1 for dissipation only)
   unsigned v0;
-  double w[3];                          // |beta^k| / (12 dxx^k)
+  double w[3];        // |beta^k| / (den1 dxx^k)
 };
 
-// Kreiss-Oliger dissipation (Sec. 4.2): the sixth difference
+// the upwinded sum for f(m), m = -(R-1)..R+1 in upwind orientation; at 4th
+// order in the grouping written above
+template <int R, class F>
+__device__ __forceinline__ double upwind_f(const F& f) {
+  if constexpr (R == 2) {
+    const double fp = f(1), fm = f(-1), f2 = f(2), f0 = f(0), f3 = f(3);
+    return 3.0 * (fp - fm) + 10.0 * (fp - f0) - 6.0 * (f2 - fp) + (f3 - fp);
+  } else {
+    const double f1 = f(1);
+    double a = FdW<R>::up[0] * (f(1 - R) - f1);
+#pragma unroll
+    for (int m = 2 - R; m <= R + 1; m++)
+      if (m != 1) a += FdW<R>::up[m + R - 1] * (f(m) - f1);
+    return a;
+  }
+}
+
+// upwinded stencil sum from centred values v[R + m] = f(m) and the value fu
+// at (R+1) sigma; up selects the side (sigma = +1)
+template <int R>
+__device__ __forceinline__ double upwind_sum(const double (&v)[2 * R + 1], double fu, bool up) {
+  auto f = [&](int m) { return m == R + 1 ? fu : (up ? v[R + m] : v[R - m]); };
+  return upwind_f<R>(f);
+}
+
+// Kreiss-Oliger dissipation (Sec. 4.2): the difference of order 2(R+1)
+// along each logical direction, weighted by eps/(kden dxx^k); at 4th order
 // delta^6 f = f(3) + f(-3) - 6 (f(2) + f(-2)) + 15 (f(1) + f(-1)) - 20 f(0)
-// along each logical direction, weighted by eps/(64 dxx^k). Symmetric in the
-// two sides, so the upwind-ordered stencil values serve as they are.
-__device__ __forceinline__ double ko6(double f3, double fm3, double f2, double fm2, double f1, double fm1,
-                                      double f0) {
-  return (f3 + fm3) - 6.0 * (f2 + fm2) + 15.0 * (f1 + fm1) - 20.0 * f0;
+// over 64 dxx^k. Symmetric in the two sides, so the upwind-ordered stencil
+// values serve as they are. fp[j], fm[j] are f(+-j), j = 1..R+1; at 8th
+// order the sums are taken as differences from f(0) (exact zero on
+// constants).
+template <int R>
+__device__ __forceinline__ double ko_sum(const double (&fp)[R + 2], const double (&fm)[R + 2], double f0) {
+  if constexpr (R == 2) {
+    return (fp[3] + fm[3]) - 6.0 * (fp[2] + fm[2]) + 15.0 * (fp[1] + fm[1]) - 20.0 * f0;
+  } else {
+    double a = FdW<R>::ko[R + 1] * ((fp[R + 1] - f0) + (fm[R + 1] - f0));
+#pragma unroll
+    for (int j = R; j >= 1; j--) a += FdW<R>::ko[j] * ((fp[j] - f0) + (fm[j] - f0));
+    return a;
+  }
+}
+// the same from centred values v (offsets -R..R) and the two outermost
+template <int R>
+__device__ __forceinline__ double ko_v(const double (&v)[2 * R + 1], double fu, double fd) {
+  double fp[R + 2], fm[R + 2];
+#pragma unroll
+  for (int j = 1; j <= R; j++) { fp[j] = v[R + j]; fm[j] = v[R - j]; }
+  fp[R + 1] = fu;
+  fm[R + 1] = fd;
+  fp[0] = fm[0] = v[R];
+  return ko_sum<R>(fp, fm, v[R]);
 }
 
 #define BHAH_PHASE_BARRIER() __builtin_amdgcn_sched_barrier(0)
 
-// Two-plane phi (AX): with exactly two interior phi planes the wrapped
-// offsets +-1 and +-3 land on the other plane and +-2 on the point's own, so
+// Two-plane phi (AX): with exactly two interior phi planes the wrapped odd
+// offsets land on the other plane and the even ones on the point's own, so
 // a phi stencil reads two values, every centred phi first derivative and
 // every mixed derivative involving phi vanishes identically (the grouped
 // differences of equal values), and the upwinded phi stencil reduces to the
@@ -59,11 +108,12 @@ __device__ __forceinline__ double ko6(double f3, double fm3, double f2, double f
 
 // axis gather along K; along phi on a two-plane grid only the two planes are
 // read
-template <int K, int PD, bool AX>
-__device__ __forceinline__ void gather_axis_ax(const Pt& P, int g, double v[5]) {
+template <int K, int PD, bool AX, class PT>
+__device__ __forceinline__ void gather_axis_ax(const PT& P, int g, double (&v)[2 * PT::R + 1]) {
   if constexpr (AX && K == PD) {
-    const double c = P.at(g, 0, 0, 0), o = P.ax<K>(g, 1);
-    v[0] = c; v[1] = o; v[2] = c; v[3] = o; v[4] = c;
+    const double c = P.at(g, 0, 0, 0), o = P.template ax<K>(g, 1);
+#pragma unroll
+    for (int t = 0; t < 2 * PT::R + 1; t++) v[t] = ((t - PT::R) & 1) ? o : c;
   } else {
     gather_axis<K>(P, g, v);
   }
@@ -71,55 +121,54 @@ __device__ __forceinline__ void gather_axis_ax(const Pt& P, int g, double v[5]) 
 
 // compile-time dispatch of the gathers on a (compile-time after unrolling)
 // direction index
-template <int PD, bool AX>
-__device__ __forceinline__ void gather_axis_k(const Pt& P, int g, int k, double v[5]) {
+template <int PD, bool AX, class PT>
+__device__ __forceinline__ void gather_axis_k(const PT& P, int g, int k, double (&v)[2 * PT::R + 1]) {
   if (k == 0) gather_axis_ax<0, PD, AX>(P, g, v);
   else if (k == 1) gather_axis_ax<1, PD, AX>(P, g, v);
   else gather_axis_ax<2, PD, AX>(P, g, v);
 }
-// value three points upwind along k (the fourth point of the shifted stencil),
-// or, with the offsets of the other side, three points downwind
-template <int PD, bool AX>
-__device__ __forceinline__ double upwind3(const Pt& P, int g, int k, const unsigned (&v3)[3], const double v[5]) {
-  if (AX && k == PD) return v[1];
-  return gf_ld(P.y, P.sgf, g, v3[k], 0);
+// value R+1 points upwind along k (the last point of the shifted stencil),
+// or, with the offsets of the other side, R+1 points downwind; on a
+// two-plane grid R+1 is odd, the other plane
+template <int PD, bool AX, class PT>
+__device__ __forceinline__ double upwind_far(const PT& P, int g, int k, const unsigned (&vo)[3][PT::H],
+                                             const double (&v)[2 * PT::R + 1]) {
+  if (AX && k == PD) return v[PT::R - 1];
+  return gf_ld(P.y, P.sgf, g, vo[k][PT::H - 1], 0);
 }
-__device__ __forceinline__ void gather_cross_kl(const Pt& P, int g, int k, int l, double v[16]) {
+template <class PT>
+__device__ __forceinline__ void gather_cross_kl(const PT& P, int g, int k, int l, double (&v)[4 * PT::R * PT::R]) {
   if (k == 0 && l == 1) gather_cross<0, 1>(P, g, v);
   else if (k == 0) gather_cross<0, 2>(P, g, v);
   else gather_cross<1, 2>(P, g, v);
 }
 
 // upwinded advection of N gridfunctions in one batch of loads; with KO also
-// their dissipation (strength eps[t], weights kw[k] = 1/(64 dxx^k))
-template <int N, int PD, bool AX, bool KO>
-__device__ __forceinline__ void advect_batch(const Pt& P, const int (&gl)[N], const Upwind2& U, double (&out)[N],
-                                             const double (&eps)[N], const double (&kw)[3]) {
-  double f0[N], fp[N][3], fm[N][3], f2[N][3], f3[N][3];
-  double fm2[KO ? N : 1][3], fm3[KO ? N : 1][3];
+// their dissipation (strength eps[t], weights kw[k] = 1/(kden dxx^k))
+template <int N, int PD, bool AX, bool KO, class PT>
+__device__ __forceinline__ void advect_batch(const PT& P, const int (&gl)[N], const UpwindT<PT::H>& U,
+                                             double (&out)[N], const double (&eps)[N], const double (&kw)[3]) {
+  constexpr int H = PT::H, R = PT::R;
+  constexpr int ND = KO ? H : R - 1;  // downwind points read
+  double f0[N], fu[N][3][H + 1], fd[N][3][ND + 1];
 #pragma unroll
   for (int t = 0; t < N; t++) {
     const int g = gl[t];
     f0[t] = gf_ld(P.y, P.sgf, g, U.v0, 0);
 #pragma unroll
     for (int k = 0; k < 3; k++) {
-      fp[t][k] = gf_ld(P.y, P.sgf, g, U.vp[k], 0);
-      if (AX && k == PD) {  // two phi planes: +-1, +-3 are the other plane, +-2 this one
-        fm[t][k] = fp[t][k];
-        f2[t][k] = f0[t];
-        f3[t][k] = fp[t][k];
-        if constexpr (KO) {
-          fm2[t][k] = f0[t];
-          fm3[t][k] = fp[t][k];
-        }
-      } else {
-        fm[t][k] = gf_ld(P.y, P.sgf, g, U.vm[k], 0);
-        f2[t][k] = gf_ld(P.y, P.sgf, g, U.v2[k], 0);
-        f3[t][k] = gf_ld(P.y, P.sgf, g, U.v3[k], 0);
-        if constexpr (KO) {
-          fm2[t][k] = gf_ld(P.y, P.sgf, g, U.v2m[k], 0);
-          fm3[t][k] = gf_ld(P.y, P.sgf, g, U.v3m[k], 0);
-        }
+      fu[t][k][1] = gf_ld(P.y, P.sgf, g, U.vu[k][0], 0);
+      if (AX && k == PD) {  // two phi planes: odd offsets are the other plane, even ones this one
+#pragma unroll
+        for (int m = 2; m <= H; m++) fu[t][k][m] = (m & 1) ? fu[t][k][1] : f0[t];
+#pragma unroll
+        for (int m = 1; m <= ND; m++) fd[t][k][m] = (m & 1) ? fu[t][k][1] : f0[t];
+      } else {  // in the order q - s, q + 2s .. q + Hs, then further downwind
+        if constexpr (ND >= 1) fd[t][k][1] = gf_ld(P.y, P.sgf, g, U.vd[k][0], 0);
+#pragma unroll
+        for (int m = 2; m <= H; m++) fu[t][k][m] = gf_ld(P.y, P.sgf, g, U.vu[k][m - 1], 0);
+#pragma unroll
+        for (int m = 2; m <= ND; m++) fd[t][k][m] = gf_ld(P.y, P.sgf, g, U.vd[k][m - 1], 0);
       }
     }
   }
@@ -128,14 +177,23 @@ __device__ __forceinline__ void advect_batch(const Pt& P, const int (&gl)[N], co
   for (int t = 0; t < N; t++) {
     double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < 3; k++)
-      s += U.w[k] * (3.0 * (fp[t][k] - fm[t][k]) + 10.0 * (fp[t][k] - f0[t]) - 6.0 * (f2[t][k] - fp[t][k]) +
-                     (f3[t][k] - fp[t][k]));
+    for (int k = 0; k < 3; k++) {
+      // f(m) for m = -(R-1)..R+1 in upwind orientation
+      auto f = [&](int m) { return m == 0 ? f0[t] : (m > 0 ? fu[t][k][m] : fd[t][k][-m]); };
+      s += U.w[k] * upwind_f<R>(f);
+    }
     if constexpr (KO) {
       double d = 0.0;
 #pragma unroll
-      for (int k = 0; k < 3; k++)
-        d += kw[k] * ko6(f3[t][k], fm3[t][k], f2[t][k], fm2[t][k], fp[t][k], fm[t][k], f0[t]);
+      for (int k = 0; k < 3; k++) {
+        double fp[R + 2], fm[R + 2];
+#pragma unroll
+        for (int j = 0; j <= H; j++) {
+          fp[j] = j == 0 ? f0[t] : fu[t][k][j];
+          fm[j] = j == 0 ? f0[t] : fd[t][k][j];
+        }
+        d += kw[k] * ko_sum<R>(fp, fm, f0[t]);
+      }
       s += eps[t] * d;
     }
     out[t] = s;
@@ -161,20 +219,23 @@ static_assert(PK_ADV + 8 == PARK && PK_DH + 18 <= PK_OUT + G_VETU0, "park layout
 // MIX: the epilogue also handles stages that mix two states (SSPRK3); the
 // ensemble kernel is built with it only for SSPRK3 batches (keeping the
 // two-state path out of RK4 stages saves registers there).
-template <int C, bool AX, bool KO, bool MIX>
+// H: ghost layers N_G; the differences are of order 2(H-1) (3: 4th order,
+// 5: 8th order).
+template <int C, bool AX, bool KO, bool MIX, int H>
 __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, const double* __restrict__ y,
                                             const StageArgs& st, int i0, int i1, int i2, unsigned q,
                                             double* __restrict__ aux, double* __restrict__ park) {
   constexpr int PD = C == BHAH_SINH_CYLINDRICAL ? 1 : 2;  // the periodic (phi) direction
+  constexpr int RR = H - 1, SW = 2 * RR + 1;               // stencil radius and width
   const double eta = ga.eta;
-  double kw[3];  // dissipation weights 1/(64 dxx^k)
+  double kw[3];  // dissipation weights 1/(kden dxx^k)
 #pragma unroll
-  for (int k = 0; k < 3; k++) kw[k] = G.inv_dx[k] * (1.0 / 64.0);
+  for (int k = 0; k < 3; k++) kw[k] = G.inv_dx[k] * (1.0 / FdW<RR>::kden);
   // park[v * 64] is this thread's slot v (lane-consecutive, bank-conflict free)
   auto put = [&](int v, double x) { park[v * 64] = x; };
   auto get = [&](int v) { return park[v * 64]; };
-  const Pt P(y, G, C, i0, i1, i2);
-  const Spacing sp = make_spacing(G);
+  const PtT<H> P(y, G, C, i0, i1, i2);
+  const Spacing sp = make_spacing<RR>(G);
   Ref R;
   load_ref<C>(G, i0, i1, i2, R);
 
@@ -200,32 +261,32 @@ __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, c
   }
 
   // upwind stencil offsets (shift one point towards the side vet^k points to)
-  Upwind2 U;
+  UpwindT<H> U;
   U.v0 = q * 8u;
   {
     const int str[3] = {1, G.s1, G.s2};
 #pragma unroll
     for (int k = 0; k < 3; k++) {
       const int s = vet[k] > 0.0 ? 1 : -1;
+      // in the order q + s, q - s, q + 2s .. q + Hs, q - 2s .. q - Hs
       if (k == P.pd) {
         const bool up = s > 0;
-        U.vp[k] = up ? P.vper(1) : P.vper(-1);
-        U.vm[k] = up ? P.vper(-1) : P.vper(1);
-        U.v2[k] = up ? P.vper(2) : P.vper(-2);
-        U.v3[k] = up ? P.vper(3) : P.vper(-3);
-        if constexpr (KO) {
-          U.v2m[k] = up ? P.vper(-2) : P.vper(2);
-          U.v3m[k] = up ? P.vper(-3) : P.vper(3);
-        }
+        U.vu[k][0] = up ? P.vper(1) : P.vper(-1);
+        U.vd[k][0] = up ? P.vper(-1) : P.vper(1);
+#pragma unroll
+        for (int m = 2; m <= H; m++) U.vu[k][m - 1] = up ? P.vper(m) : P.vper(-m);
+#pragma unroll
+        for (int m = 2; m <= H; m++) U.vd[k][m - 1] = up ? P.vper(-m) : P.vper(m);
       } else {
         const int o = s * str[k];
-        U.vp[k] = (q + o) * 8u; U.vm[k] = (q - o) * 8u; U.v2[k] = (q + 2 * o) * 8u; U.v3[k] = (q + 3 * o) * 8u;
-        if constexpr (KO) {
-          U.v2m[k] = (q - 2 * o) * 8u;
-          U.v3m[k] = (q - 3 * o) * 8u;
-        }
+        U.vu[k][0] = (q + o) * 8u;
+        U.vd[k][0] = (q - o) * 8u;
+#pragma unroll
+        for (int m = 2; m <= H; m++) U.vu[k][m - 1] = (q + m * o) * 8u;
+#pragma unroll
+        for (int m = 2; m <= H; m++) U.vd[k][m - 1] = (q - m * o) * 8u;
       }
-      U.w[k] = fabs(beta[k]) * sp.i12h[k];
+      U.w[k] = fabs(beta[k]) * sp.d1s[k];
     }
   }
 
@@ -253,48 +314,58 @@ __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, c
       for (int l = k; l < 3; l++) {
         double dd[11];
         if (k == l) {
-          // f(-2..2) along k, and f(3 s) on the upwind side for the advection
-          double v[11][5], f3[11], fm3[KO ? 11 : 1];
+          // f(-R..R) along k, and f((R+1) s) on the upwind side for the
+          // advection; at 8th order in batches of four gridfunctions
+          constexpr int TB = H == 3 ? 11 : 4;
 #pragma unroll
-          for (int t = 0; t < 11; t++) {
-            gather_axis_k<PD, AX>(P, G11[t], k, v[t]);
-            f3[t] = upwind3<PD, AX>(P, G11[t], k, U.v3, v[t]);
-            if constexpr (KO) fm3[t] = upwind3<PD, AX>(P, G11[t], k, U.v3m, v[t]);
-          }
-          BHAH_PHASE_BARRIER();
-          const bool up = vet[k] > 0.0;
+          for (int t0 = 0; t0 < 11; t0 += TB) {
+            double v[TB][SW], fu[TB], fd[KO ? TB : 1];
 #pragma unroll
-          for (int t = 0; t < 11; t++) {
-            const double fp = up ? v[t][3] : v[t][1], fm = up ? v[t][1] : v[t][3];
-            const double f2 = up ? v[t][4] : v[t][0], f0 = v[t][2];
-            adv[t] += U.w[k] * (3.0 * (fp - fm) + 10.0 * (fp - f0) - 6.0 * (f2 - fp) + (f3[t] - fp));
-            // h_ij and W take the metric strength, alpha and vet^i the gauge one
-            if constexpr (KO)
-              adv[t] += (t < 7 ? ga.dm : ga.dg) * kw[k] * ko6(f3[t], fm3[t], v[t][4], v[t][0], v[t][3], v[t][1], f0);
-          }
+            for (int t = 0; t < TB; t++)
+              if (t0 + t < 11) {
+                gather_axis_k<PD, AX>(P, G11[t0 + t], k, v[t]);
+                fu[t] = upwind_far<PD, AX>(P, G11[t0 + t], k, U.vu, v[t]);
+                if constexpr (KO) fd[t] = upwind_far<PD, AX>(P, G11[t0 + t], k, U.vd, v[t]);
+              }
+            BHAH_PHASE_BARRIER();
+            const bool up = vet[k] > 0.0;
 #pragma unroll
-          for (int t = 0; t < 11; t++) dd[t] = d2_axis(v[t], sp.i12hh[k]);
-          // the same stencil values give the first derivatives along k
+            for (int t = 0; t < TB; t++)
+              if (t0 + t < 11) {
+                const int tt = t0 + t;
+                adv[tt] += U.w[k] * upwind_sum<RR>(v[t], fu[t], up);
+                // h_ij and W take the metric strength, alpha and vet^i the gauge one
+                if constexpr (KO) adv[tt] += (tt < 7 ? ga.dm : ga.dg) * kw[k] * ko_v<RR>(v[t], fu[t], fd[t]);
+              }
 #pragma unroll
-          for (int t = 0; t < 11; t++) {
-            const double d1 = AX && k == PD ? 0.0 : d1_axis(v[t], sp.i12h[k]);
-            const int slot = t < 6 ? PK_DH + 3 * t : (t == 6 ? PK_D1 + 9 : (t == 7 ? PK_D1 + 12 : PK_D1 + 3 * (t - 8)));
-            put(slot + k, d1);
+            for (int t = 0; t < TB; t++)
+              if (t0 + t < 11) dd[t0 + t] = d2_axis<RR>(v[t], sp.d2s[k]);
+            // the same stencil values give the first derivatives along k
+#pragma unroll
+            for (int t = 0; t < TB; t++)
+              if (t0 + t < 11) {
+                const int tt = t0 + t;
+                const double d1 = AX && k == PD ? 0.0 : d1_axis<RR>(v[t], sp.d1s[k]);
+                const int slot =
+                    tt < 6 ? PK_DH + 3 * tt : (tt == 6 ? PK_D1 + 9 : (tt == 7 ? PK_D1 + 12 : PK_D1 + 3 * (tt - 8)));
+                put(slot + k, d1);
+              }
           }
         } else if (AX && (k == PD || l == PD)) {
 #pragma unroll
           for (int t = 0; t < 11; t++) dd[t] = 0.0;
         } else {
+          constexpr int TX = H == 3 ? 4 : 1;  // gridfunctions per batch of cross loads
 #pragma unroll
-          for (int t0 = 0; t0 < 11; t0 += 4) {
-            double v[4][16];
+          for (int t0 = 0; t0 < 11; t0 += TX) {
+            double v[TX][4 * RR * RR];
 #pragma unroll
-            for (int t = 0; t < 4; t++)
+            for (int t = 0; t < TX; t++)
               if (t0 + t < 11) gather_cross_kl(P, G11[t0 + t], k, l, v[t]);
             BHAH_PHASE_BARRIER();
 #pragma unroll
-            for (int t = 0; t < 4; t++)
-              if (t0 + t < 11) dd[t0 + t] = d2_cross(v[t], sp.i144[k][l]);
+            for (int t = 0; t < TX; t++)
+              if (t0 + t < 11) dd[t0 + t] = d2_cross<RR>(v[t], sp.crs[k][l]);
           }
         }
         const int kl = sy(k, l);
@@ -484,14 +555,14 @@ __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, c
     // result slots of lambda are free: phase 2 no longer reads PK_DH)
     double Lam[3], DLam[3][3], dlam[3][3];
     {
-      double v[3][3][5], f3[3][3], fm3[KO ? 3 : 1][3];
+      double v[3][3][SW], f3[3][3], fm3[KO ? 3 : 1][3];
 #pragma unroll
       for (int i = 0; i < 3; i++)
 #pragma unroll
         for (int k = 0; k < 3; k++) {
           gather_axis_k<PD, AX>(P, G_LAMU0 + i, k, v[i][k]);
-          f3[i][k] = upwind3<PD, AX>(P, G_LAMU0 + i, k, U.v3, v[i][k]);
-          if constexpr (KO) fm3[i][k] = upwind3<PD, AX>(P, G_LAMU0 + i, k, U.v3m, v[i][k]);
+          f3[i][k] = upwind_far<PD, AX>(P, G_LAMU0 + i, k, U.vu, v[i][k]);
+          if constexpr (KO) fm3[i][k] = upwind_far<PD, AX>(P, G_LAMU0 + i, k, U.vd, v[i][k]);
         }
       BHAH_PHASE_BARRIER();
 #pragma unroll
@@ -500,11 +571,9 @@ __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, c
 #pragma unroll
         for (int k = 0; k < 3; k++) {
           const bool up = vet[k] > 0.0;
-          const double fp = up ? v[i][k][3] : v[i][k][1], fm = up ? v[i][k][1] : v[i][k][3];
-          const double f2 = up ? v[i][k][4] : v[i][k][0], f0 = v[i][k][2];
-          a += U.w[k] * (3.0 * (fp - fm) + 10.0 * (fp - f0) - 6.0 * (f2 - fp) + (f3[i][k] - fp));
-          if constexpr (KO) d += kw[k] * ko6(f3[i][k], fm3[i][k], v[i][k][4], v[i][k][0], v[i][k][3], v[i][k][1], f0);
-          dlam[i][k] = AX && k == PD ? 0.0 : d1_axis(v[i][k], sp.i12h[k]);
+          a += U.w[k] * upwind_sum<RR>(v[i][k], f3[i][k], up);
+          if constexpr (KO) d += kw[k] * ko_v<RR>(v[i][k], f3[i][k], fm3[i][k]);
+          dlam[i][k] = AX && k == PD ? 0.0 : d1_axis<RR>(v[i][k], sp.d1s[k]);
         }
         put(PK_OUT + G_LAMU0 + i, a + ga.dm * d);
         // bet^i's right-hand side takes 3/4 of lambda^i's undissipated one:
@@ -582,12 +651,12 @@ __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, c
   {
     constexpr int GB[4] = {G_ADD00 + 5, G_BETU0, G_BETU0 + 1, G_BETU0 + 2};
     double a4[4];
-    double v[3][5], f3[3], fm3[3];
+    double v[3][SW], f3[3], fm3[3];
 #pragma unroll
     for (int k = 0; k < 3; k++) {
       gather_axis_k<PD, AX>(P, G_TRK, k, v[k]);
-      f3[k] = upwind3<PD, AX>(P, G_TRK, k, U.v3, v[k]);
-      if constexpr (KO) fm3[k] = upwind3<PD, AX>(P, G_TRK, k, U.v3m, v[k]);
+      f3[k] = upwind_far<PD, AX>(P, G_TRK, k, U.vu, v[k]);
+      if constexpr (KO) fm3[k] = upwind_far<PD, AX>(P, G_TRK, k, U.vd, v[k]);
     }
     const double e4[4] = {ga.dm, ga.dg, ga.dg, ga.dg};
     advect_batch<4, PD, AX, KO>(P, GB, U, a4, e4, kw);
@@ -598,11 +667,9 @@ __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, c
 #pragma unroll
     for (int k = 0; k < 3; k++) {
       const bool up = vet[k] > 0.0;
-      const double fp = up ? v[k][3] : v[k][1], fm = up ? v[k][1] : v[k][3];
-      const double f2 = up ? v[k][4] : v[k][0], f0 = v[k][2];
-      advK += U.w[k] * (3.0 * (fp - fm) + 10.0 * (fp - f0) - 6.0 * (f2 - fp) + (f3[k] - fp));
-      if constexpr (KO) advK += ga.dm * kw[k] * ko6(f3[k], fm3[k], v[k][4], v[k][0], v[k][3], v[k][1], f0);
-      dK[k] = AX && k == PD ? 0.0 : d1_axis(v[k], sp.i12h[k]);
+      advK += U.w[k] * upwind_sum<RR>(v[k], f3[k], up);
+      if constexpr (KO) advK += ga.dm * kw[k] * ko_v<RR>(v[k], f3[k], fm3[k]);
+      dK[k] = AX && k == PD ? 0.0 : d1_axis<RR>(v[k], sp.d1s[k]);
     }
     put(PK_OUT + G_TRK, advK);
   }
@@ -858,6 +925,7 @@ __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, c
 // the same time overlap. The hardware hands consecutive workgroup ids to the
 // XCDs in turn; block ids are remapped so that every XCD works through one
 // contiguous range of the walk (its L2 then holds a compact part of the grid).
+template <int H>
 __device__ __forceinline__ bool tile_point(const GridDev& G, const TileMap& T, int w, int lane, int& i0,
                                            int& i1, int& i2) {
   const int full = T.band * T.tz * T.tx;  // tiles in one full band
@@ -872,17 +940,17 @@ __device__ __forceinline__ bool tile_point(const GridDev& G, const TileMap& T, i
   const int j1 = start + r / T.tx;
   const int xt = r - (r / T.tx) * T.tx;
   const int ex = 1 << T.lx, ey = 1 << T.ly;
-  i0 = NG + xt * ex + (lane & (ex - 1));
-  i1 = NG + j1 * ey + ((lane >> T.lx) & (ey - 1));
-  i2 = NG + (j2 << (6 - T.lx - T.ly)) + (lane >> (T.lx + T.ly));
-  return i0 < NG + G.N0 && i1 < NG + G.N1 && i2 < NG + G.N2;
+  i0 = H + xt * ex + (lane & (ex - 1));
+  i1 = H + j1 * ey + ((lane >> T.lx) & (ey - 1));
+  i2 = H + (j2 << (6 - T.lx - T.ly)) + (lane >> (T.lx + T.ly));
+  return i0 < H + G.N0 && i1 < H + G.N1 && i2 < H + G.N2;
 }
 
 // logical position in the walk of the tile a block works on; with G_blocks a
 // multiple of the XCD count, block b runs on XCD b % nxcd
 __device__ __forceinline__ int xcd_remap(int b, int per) { return (b % BHAH_NXCD) * per + b / BHAH_NXCD; }
 
-template <int C, bool AX, bool KO>
+template <int C, bool AX, bool KO, int H>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
 k_rhs_fused(GridDev G, TileMap T, Gauge ga, const double* __restrict__ y, StageArgs st,
             double* __restrict__ aux) {
@@ -890,15 +958,16 @@ k_rhs_fused(GridDev G, TileMap T, Gauge ga, const double* __restrict__ y, StageA
   const int w = xcd_remap((int)blockIdx.x, per);
   if (w >= T.ntiles) return;
   int i0, i1, i2;
-  if (!tile_point(G, T, w, (int)threadIdx.x, i0, i1, i2)) return;
+  if (!tile_point<H>(G, T, w, (int)threadIdx.x, i0, i1, i2)) return;
   const unsigned q = (unsigned)(i0 + G.s1 * i1 + G.s2 * i2);
   __shared__ double park[PARK * 64];
-  fused_point<C, AX, KO, true>(G, ga, y, st, i0, i1, i2, q, aux, park + threadIdx.x);
+  fused_point<C, AX, KO, true, H>(G, ga, y, st, i0, i1, i2, q, aux, park + threadIdx.x);
 }
 
-// Persistent form for ensembles: a fixed grid of blocks (a multiple of the XCD
-// count) strides over one kernel variant's (job, tile) work list; every
-// point runs the same fused_point as above.
+// Persistent form for ensembles (grids with NG ghost layers, 4th order): a
+// fixed grid of blocks (a multiple of the XCD count) strides over one kernel
+// variant's (job, tile) work list; every point runs the same fused_point as
+// above.
 template <int C, bool AX, bool KO, bool MIX>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
 k_rhs_batch(const BatchJob* __restrict__ jobs, const BatchHdr* __restrict__ hdr, const int2* __restrict__ work,
@@ -914,10 +983,10 @@ k_rhs_batch(const BatchJob* __restrict__ jobs, const BatchHdr* __restrict__ hdr,
     const BatchJob* J = jobs + wk.x;
     const GridDev G = J->G;
     int i0, i1, i2;
-    if (!tile_point(G, J->T, wk.y, (int)threadIdx.x, i0, i1, i2)) continue;
+    if (!tile_point<NG>(G, J->T, wk.y, (int)threadIdx.x, i0, i1, i2)) continue;
     const unsigned q = (unsigned)(i0 + G.s1 * i1 + G.s2 * i2);
     const StageArgs st = J->st[stage];
-    fused_point<C, AX, KO, MIX>(G, ga, J->in[stage], st, i0, i1, i2, q, nullptr, park + threadIdx.x);
+    fused_point<C, AX, KO, MIX, NG>(G, ga, J->in[stage], st, i0, i1, i2, q, nullptr, park + threadIdx.x);
   }
 }
 
@@ -934,11 +1003,12 @@ TileMap make_tilemap(const GridDev& G, int lx, int ly, int band) {
   return T;
 }
 
-// launch tables over (variant = 2 coord + two phi planes, dissipation on)
-template <int C, bool AX, bool KO>
+// launch tables over (ghost layers 3 or 5, variant = 2 coord + two phi
+// planes, dissipation on)
+template <int C, bool AX, bool KO, int H>
 void launch_fused_t(dim3 g, hipStream_t s, const GridDev& G, const TileMap& T, const Gauge& ga, const double* y,
                     const StageArgs& st, double* aux) {
-  hipLaunchKernelGGL((k_rhs_fused<C, AX, KO>), g, dim3(64), 0, s, G, T, ga, y, st, aux);
+  hipLaunchKernelGGL((k_rhs_fused<C, AX, KO, H>), g, dim3(64), 0, s, G, T, ga, y, st, aux);
 }
 template <int C, bool AX, bool KO, bool MIX>
 void launch_batch_t(dim3 g, hipStream_t s, const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage,
@@ -949,13 +1019,19 @@ using FusedLaunch = void (*)(dim3, hipStream_t, const GridDev&, const TileMap&, 
                              const StageArgs&, double*);
 using BatchLaunch = void (*)(dim3, hipStream_t, const BatchJob*, const BatchHdr*, const int2*, int, const Gauge&);
 constexpr int SS = BHAH_SINH_SPHERICAL, SC = BHAH_SINH_CYLINDRICAL, SP = BHAH_SPHERICAL;
-static const FusedLaunch kFused[NVAR][2] = {
-    {launch_fused_t<SS, false, false>, launch_fused_t<SS, false, true>},
-    {launch_fused_t<SS, true, false>, launch_fused_t<SS, true, true>},
-    {launch_fused_t<SC, false, false>, launch_fused_t<SC, false, true>},
-    {launch_fused_t<SC, true, false>, launch_fused_t<SC, true, true>},
-    {launch_fused_t<SP, false, false>, launch_fused_t<SP, false, true>},
-    {launch_fused_t<SP, true, false>, launch_fused_t<SP, true, true>}};
+#define BHAH_FUSED_ROWS(H)                                                                            \
+  {                                                                                                   \
+    {launch_fused_t<SS, false, false, H>, launch_fused_t<SS, false, true, H>},                        \
+        {launch_fused_t<SS, true, false, H>, launch_fused_t<SS, true, true, H>},                      \
+        {launch_fused_t<SC, false, false, H>, launch_fused_t<SC, false, true, H>},                    \
+        {launch_fused_t<SC, true, false, H>, launch_fused_t<SC, true, true, H>},                      \
+        {launch_fused_t<SP, false, false, H>, launch_fused_t<SP, false, true, H>},                    \
+    {                                                                                                 \
+      launch_fused_t<SP, true, false, H>, launch_fused_t<SP, true, true, H>                           \
+    }                                                                                                 \
+  }
+static const FusedLaunch kFused[2][NVAR][2] = {BHAH_FUSED_ROWS(3), BHAH_FUSED_ROWS(5)};
+#undef BHAH_FUSED_ROWS
 // [variant][dissipation][two-state stages (SSPRK3)]
 #define BHAH_BATCH_ROW(C, AX)                                                                    \
   {                                                                                              \
@@ -972,7 +1048,8 @@ void launch_rhs_fused(const GridDev& G, const Gauge& ga, const double* y, double
   const TileCfg cfg = tile_fits_periodic(G.coord, cfg_in) ? cfg_in : TileCfg{6, 0, cfg_in.band};
   const TileMap T = make_tilemap(G, cfg.lx, cfg.ly, cfg.band);
   const int per = (T.ntiles + BHAH_NXCD - 1) / BHAH_NXCD;
-  kFused[rhs_variant(G.coord, G.N1, G.N2)][ga.ko() ? 1 : 0](dim3(per * BHAH_NXCD), s, G, T, ga, y, st, aux);
+  kFused[G.ng == 5 ? 1 : 0][rhs_variant(G.coord, G.N1, G.N2)][ga.ko() ? 1 : 0](dim3(per * BHAH_NXCD), s, G, T, ga,
+                                                                                y, st, aux);
 }
 
 void launch_rhs_batch(int variant, const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage,

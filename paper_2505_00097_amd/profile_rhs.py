@@ -18,20 +18,23 @@ def main():
     ap.add_argument("--workload", default="vacuum3d_sinhspherical_256x128x64")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--copy-mib", type=int, default=256)
+    ap.add_argument("--nghosts", type=int, default=3, help="3: 4th-order differences, 5: 8th order")
+    ap.add_argument("--dissipation", action="store_true", help="Kreiss-Oliger 0.99 / 0.3 (the production run)")
     args = ap.parse_args()
+    diss = (0.99, 0.3) if args.dissipation else (0.0, 0.0)
     import torch
     from paper_2505_00097_amd import capi
     from paper_2505_00097_amd import workloads as wl
     w = wl.WORKLOADS[args.workload]
-    g = capi.Grid(w["coord"], w["N"], w["ampl"], w["sinhw"], w["cfl"])
+    g = capi.Grid(w["coord"], w["N"], w["ampl"], w["sinhw"], w["cfl"], nghosts=args.nghosts)
     y = g.state()
     capi.set_initial_data_brill_lindquist(g.h, w["masses"], w["positions"], y)
     ws = g.workspace()
     for _ in range(2):
-        capi.rk4_step(g.h, y, ws, g.dt, eta=w["eta"])
+        capi.rk4_step(g.h, y, ws, g.dt, eta=w["eta"], diss=diss)
     rhs = g.state()
     for _ in range(args.reps):
-        capi.bssn_rhs(g.h, y, rhs, None, eta=w["eta"])
+        capi.bssn_rhs(g.h, y, rhs, None, eta=w["eta"], diss=diss)
     n = args.copy_mib * (1 << 20) // 8
     a = torch.ones(n, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)

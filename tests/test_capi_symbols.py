@@ -69,6 +69,20 @@ def test_grid_create_rejects_bad_shapes_before_any_device_call(coord, N, msg):
         capi.grid_create(coord, N)
 
 
+@pytest.mark.parametrize("nghosts", [2, 4, 6])
+def test_grid_create_rejects_unsupported_ghost_counts(nghosts):
+    """3 ghost layers (4th-order differences) or 5 (8th order) only"""
+    from paper_2505_00097_amd import capi
+    with pytest.raises(capi.BhahError, match="nghosts must be 3 or 5"):
+        capi.grid_create(0, (8, 8, 2), nghosts=nghosts)
+
+
+def test_eighth_order_grid_needs_five_points_per_direction():
+    from paper_2505_00097_amd import capi
+    with pytest.raises(capi.BhahError, match="N\\[d\\] < nghosts"):
+        capi.grid_create(1, (4, 2, 8), nghosts=5)
+
+
 def test_grid_create_rejects_bad_map_parameters():
     from paper_2505_00097_amd import capi
     with pytest.raises(capi.BhahError, match="ampl"):

@@ -11,5 +11,5 @@ def test_bench_flops_match_kernel_ir():
     import bench
     from paper_2505_00097_amd import count_flops
     ir = count_flops.device_ir(os.path.join(ROOT, "paper_2505_00097_amd", "csrc", "rhs_fused.hip"))
-    counted = count_flops.count(ir)
-    assert counted == bench.F_ALG
+    assert count_flops.count(ir) == bench.F_ALG
+    assert count_flops.count(ir, dissipation=True, nghosts=5) == bench.F_ALG8_KO

@@ -1,0 +1,272 @@
+"""Parity of the 8th-order path (N_G = 5 ghost layers, Sec. 3; the
+differencing of the production head-on run of Sec. 4.2) with the CPU oracle,
+through the C ABI. Same bars as the 4th-order parity: per right-hand side
+within max(1e-12, the oracle's rounding floor) of each tensor's largest
+interior magnitude; after evolution within max(1e-9, the evolution's
+rounding floor); ghost maps bit-exact.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import fmt, gf_errors, rounding_floor, to_cpu, to_gpu
+from oracle import oracle as orc
+from paper_2505_00097_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+RHS_TOL = 1e-12
+EVOL_TOL = 1e-9
+NG = 5
+DISS = (0.99, 0.3)
+
+GRIDS = {
+    "tiny": (wl.SINH_SPHERICAL, (32, 16, 2), (10.0,) * 3, (0.2,) * 3),
+    "sph_ragged": (wl.SINH_SPHERICAL, (100, 12, 6), (10.0,) * 3, (0.2,) * 3),
+    "cyl_ragged": (wl.SINH_CYLINDRICAL, (70, 2, 140), (20.0,) * 3, (0.2,) * 3),
+    "cyl_3d": (wl.SINH_CYLINDRICAL, (20, 8, 30), (4.0, 4.0, 6.0), (0.3, 0.3, 0.4)),
+    "spherical": (wl.SPHERICAL, (72, 12, 24), (7.5,) * 3, (0.2,) * 3),
+}
+HEADON = ([0.5, 0.5], [(0, 0, 0.5), (0, 0, -0.5)])
+
+
+def _case(*a):
+    print("CASE 8th-order", *a, flush=True)
+
+
+def _pair(name, bc_kind=0, diss=(0.0, 0.0)):
+    import torch  # noqa: F401
+    from paper_2505_00097_amd import capi
+    coord, N, ampl, w = GRIDS[name]
+    return (capi.Grid(coord, N, ampl, w, bc_kind=bc_kind, nghosts=NG),
+            orc.Grid(coord, N, ampl=ampl, sinhw=w, ng=NG, bc_kind=bc_kind, diss=diss))
+
+
+@pytest.mark.parametrize("name", list(GRIDS))
+def test_maps_and_dt_match_oracle(name):
+    _case("maps", name)
+    g, og = _pair(name)
+    assert g.n == og.n
+    assert g.dt == pytest.approx(og.dt(), rel=1e-14)
+    kind, src, par = g.bc_maps()
+    rc, okind, osrc, opar = og.bc_maps()
+    assert rc == 0
+    assert np.array_equal(kind, okind) and np.array_equal(src, osrc) and np.array_equal(par, opar)
+
+
+@pytest.mark.parametrize("name", ["tiny", "cyl_ragged", "sph_ragged"])
+def test_ghost_fill_and_initial_data_match_oracle(name):
+    _case("bcs+id", name)
+    from paper_2505_00097_amd import capi
+    g, og = _pair(name)
+    y0 = wl.smooth_random_state(og.n, seed=13)
+    I = (slice(None),) + og.interior()
+    start = np.full_like(y0, np.nan)
+    start[I] = y0[I]
+    ref = og.apply_bcs(start.copy())
+    yg = to_gpu(start)
+    capi.apply_bcs(g.h, yg)
+    out = to_cpu(yg)
+    assert np.all(np.isfinite(out))
+    # five extrapolated layers: integer weights up to (10+15+6)^4 at a corner
+    scale = np.max(np.abs(ref), axis=(1, 2, 3))
+    err = np.max(np.abs(out - ref), axis=(1, 2, 3)) / scale
+    assert np.all(err < 1e-9), err
+    m, pos = HEADON
+    y = g.state()
+    capi.set_initial_data_brill_lindquist(g.h, m, pos, y)
+    ido = og.brill_lindquist(m, np.array(pos))
+    assert np.max(np.abs(to_cpu(y)[I] - ido[I])) <= 4 * 2.3e-16 * np.max(np.abs(ido[I]))
+
+
+def _check_rhs(g, og, y, diss=(0.0, 0.0), pts=None):
+    from paper_2505_00097_amd import capi
+    ref = og.rhs(y, eta=2.0)
+    r = g.state()
+    r.zero_()
+    capi.bssn_rhs(g.h, to_gpu(y), r, eta=2.0, diss=diss)
+    out = to_cpu(r)
+    pts = og.interior() if pts is None else pts
+    err = gf_errors(out, ref, pts)
+    floor = rounding_floor(lambda v: og.rhs(v, eta=2.0), y, lambda a, b: gf_errors(a, b, pts))
+    tol = np.maximum(RHS_TOL, floor)
+    print("  err", fmt(orc.GF_NAMES, err), flush=True)
+    assert np.all(err <= tol), fmt(orc.GF_NAMES, err / tol)
+    return out
+
+
+@pytest.mark.parametrize("name", list(GRIDS))
+def test_rhs_matches_oracle(name):
+    """every coordinate family, general and two-plane variants, with and
+    without Kreiss-Oliger dissipation (ninth order)"""
+    g, og = _pair(name)
+    _, ogd = _pair(name, diss=DISS)
+    bl = og.brill_lindquist([0.6, 0.4], np.array([(0.1, 0.0, 0.5), (0.0, 0.1, -0.6)]))
+    rnd = og.apply_bcs(wl.smooth_random_state(og.n, seed=7))
+    for label, y in (("bl", bl), ("smooth_random", rnd)):
+        _case("rhs", name, label)
+        _check_rhs(g, og, y)
+        _case("rhs_diss", name, label)
+        out = _check_rhs(g, ogd, y, diss=DISS)
+        if label == "smooth_random":  # the dissipation is really on
+            plain = og.rhs(y, eta=2.0)
+            I = (slice(None),) + og.interior()
+            assert np.max(np.abs(out - plain)[I]) > 1e3 * RHS_TOL * np.max(np.abs(plain))
+
+
+def test_flat_space_rhs_is_exactly_zero():
+    _case("flat")
+    g, og = _pair("cyl_3d")
+    y = og.brill_lindquist([], np.zeros((0, 3)), lapse_kind=1)
+    out = _check_rhs(g, og, y)
+    assert np.all(out[(slice(None),) + og.interior()] == 0.0)
+
+
+@pytest.mark.parametrize("name", ["tiny", "cyl_ragged", "cyl_3d", "spherical"])
+def test_radiation_rhs_matches_oracle(name):
+    """the eighth-order radiation condition at the pure-outer points"""
+    _case("rhs_radiation", name)
+    from paper_2505_00097_amd import capi
+    g, og = _pair(name, bc_kind=capi.BC_RADIATION)
+    kind, _, _ = g.bc_maps()
+    k = kind.reshape(og.n[2], og.n[1], og.n[0])
+    y = og.apply_bcs(og.brill_lindquist([0.5, 0.3], np.array([(0.1, 0.0, 0.4), (0.0, -0.1, -0.5)])))
+    _check_rhs(g, og, y, pts=(k == 0) | (k == 1))
+    _check_rhs(g, og, y, pts=k == 1)
+
+
+@pytest.mark.parametrize("name", ["sph_ragged", "cyl_ragged"])
+def test_tile_shape_does_not_change_results(name):
+    """the tile walk with five ghost layers: every shape gives the same bits"""
+    _case("tiles", name)
+    import torch
+    from paper_2505_00097_amd import capi
+    g, og = _pair(name)
+    y = to_gpu(og.apply_bcs(wl.smooth_random_state(og.n, seed=3)))
+    outs = []
+    shapes = [(6, 0, 4), (5, 0, 1), (4, 0, 16)] if og.coord == wl.SINH_CYLINDRICAL else [(6, 0, 4), (5, 1, 1), (4, 2, 4)]
+    for lx, ly, band in shapes:
+        capi.grid_set_tile(g.h, lx, ly, band)
+        r = g.state()
+        r.zero_()
+        capi.bssn_rhs(g.h, y, r, eta=2.0)
+        torch.cuda.synchronize()
+        outs.append(to_cpu(r))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def _evolve_pair(g, og, steps, stepper, diss, m, pos):
+    from paper_2505_00097_amd import capi
+    y = g.state()
+    capi.set_initial_data_brill_lindquist(g.h, m, pos, y)
+    ws = g.workspace()
+    yo = og.brill_lindquist(m, np.array(pos).reshape(-1, 3))
+    dt = og.dt()
+    gstep = capi.ssprk3_step if stepper == "ssprk3" else capi.rk4_step
+    ostep = og.ssprk3_step if stepper == "ssprk3" else og.rk4_step
+    for s in range(steps):
+        gstep(g.h, y, ws, dt, eta=2.0, diss=diss)
+        ostep(yo, dt, eta=2.0)
+        if s % 20 == 19:
+            print("  step", s + 1, flush=True)
+    return to_cpu(y), yo
+
+
+@pytest.mark.parametrize("name,stepper,steps", [("tiny", "rk4", 100), ("cyl_3d", "rk4", 40),
+                                                ("cyl_ragged", "ssprk3", 40)])
+def test_evolution_matches_oracle(name, stepper, steps):
+    _case("evolve", name, stepper, steps)
+    g, og = _pair(name)
+    out, yo = _evolve_pair(g, og, steps, stepper, (0.0, 0.0), *HEADON)
+    err = gf_errors(out, yo, (slice(None),) * 3)
+    print("  err", fmt(orc.GF_NAMES, err), flush=True)
+    assert np.all(err <= EVOL_TOL), fmt(orc.GF_NAMES, err)
+
+
+def test_production_numerics_match_oracle():
+    """the production head-on numerics of Sec. 4.2 in full: 8th-order
+    differences, ninth-order Kreiss-Oliger dissipation 0.99 / 0.3, the
+    eighth-order radiation condition and SSPRK3"""
+    _case("production", "cyl_ragged", 40)
+    from paper_2505_00097_amd import capi
+    g, og = _pair("cyl_ragged", bc_kind=capi.BC_RADIATION, diss=DISS)
+    out, yo = _evolve_pair(g, og, 40, "ssprk3", DISS, *HEADON)
+    err = gf_errors(out, yo, (slice(None),) * 3)
+    print("  err", fmt(orc.GF_NAMES, err), flush=True)
+    assert np.all(err <= EVOL_TOL), fmt(orc.GF_NAMES, err)
+
+
+def test_production_numerics_full_size_headon():
+    """the head-on workload (SinhCylindrical 128x2x256) with the production
+    numerics at 8th order, tuned tile shape, 30 SSPRK3 steps, every point"""
+    name = "headon_sinhcylindrical_128x2x256"
+    _case("production_full", name, 30)
+    from paper_2505_00097_amd import capi
+    w = wl.WORKLOADS[name]
+    g = capi.Grid(w["coord"], w["N"], w["ampl"], w["sinhw"], w["cfl"], bc_kind=capi.BC_RADIATION, nghosts=NG)
+    og = orc.Grid(w["coord"], w["N"], ampl=w["ampl"], sinhw=w["sinhw"], cfl=w["cfl"], ng=NG, bc_kind=1,
+                  diss=DISS)
+    y = g.state()
+    capi.set_initial_data_brill_lindquist(g.h, w["masses"], w["positions"], y)
+    capi.grid_tune(g.h, y, g.state(), diss=DISS)
+    print("  tile", capi.grid_get_tile(g.h), flush=True)
+    ws = g.workspace()
+    yo = og.brill_lindquist(w["masses"], np.array(w["positions"]))
+    dt = og.dt()
+    for s in range(30):
+        capi.ssprk3_step(g.h, y, ws, dt, eta=w["eta"], diss=DISS)
+        og.ssprk3_step(yo, dt, eta=w["eta"])
+        if s % 10 == 9:
+            print("  step", s + 1, flush=True)
+    err = gf_errors(to_cpu(y), yo, (slice(None),) * 3)
+    print("  err", fmt(orc.GF_NAMES, err), flush=True)
+    assert np.all(err <= EVOL_TOL), fmt(orc.GF_NAMES, err)
+
+
+@pytest.mark.parametrize("name", ["tiny", "cyl_3d", "spherical"])
+def test_constraints_match_oracle(name):
+    _case("constraints", name)
+    import torch
+    from paper_2505_00097_amd import capi
+    g, og = _pair(name)
+    I = og.interior()
+    groups = [[0], [1, 2, 3], [4, 5, 6]]
+
+    def cons(v):
+        H, M, C = og.constraints(v)
+        return np.concatenate([H[None], M, C])
+
+    for label, y in (("bl", og.brill_lindquist([0.8], [(0.1, 0.0, 0.2)])),
+                     ("random", og.apply_bcs(wl.smooth_random_state(og.n, seed=8)))):
+        H, M, C = g._empty(1), g._empty(3), g._empty(3)
+        for t in (H, M, C):
+            t.zero_()
+        capi.constraints(g.h, to_gpu(y), H, M, C)
+        torch.cuda.synchronize()
+        got = np.concatenate([to_cpu(H), to_cpu(M), to_cpu(C)])
+
+        def rel(a, b):
+            return gf_errors(a, b, I, groups=groups)
+        err = rel(got, cons(y))
+        tol = np.maximum(RHS_TOL, rounding_floor(cons, y, rel))
+        print("  ", label, err, flush=True)
+        assert np.all(err <= tol), (label, err, tol)
+        H1 = g._empty(1)
+        capi.hamiltonian_constraint(g.h, to_gpu(y), H1)
+        a, b = to_cpu(H1)[0][I], got[0][I]
+        assert np.max(np.abs(a - b)) <= RHS_TOL * np.max(np.abs(b))
+
+
+def test_ensembles_and_server_take_fourth_order_grids_only():
+    _case("batch_server_reject")
+    from paper_2505_00097_amd import capi
+    g, _ = _pair("tiny")
+    with pytest.raises(capi.BhahError, match="nghosts = 3"):
+        capi.batch_create([g.h])
+    srv = capi.server_create(1e9, max_jobs=2, steps_per_tick=1)
+    try:
+        d = capi.job_desc(wl.SINH_CYLINDRICAL, (16, 2, 32), (6.0,) * 3, (0.3,) * 3, 0.5, *HEADON, 10, nghosts=NG)
+        with pytest.raises(capi.BhahError, match="nghosts = 3"):
+            capi.server_submit(srv, d)
+    finally:
+        capi.server_destroy(srv)
