@@ -554,26 +554,30 @@ __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, c
     // lambda^i: first derivatives and advection from one gather (the
     // result slots of lambda are free: phase 2 no longer reads PK_DH)
     double Lam[3], DLam[3][3], dlam[3][3];
-    {
-      double v[3][3][SW], f3[3][3], fm3[KO ? 3 : 1][3];
+    // at 8th order one component per batch of loads
+    constexpr int LB = H == 3 ? 3 : 1;
 #pragma unroll
-      for (int i = 0; i < 3; i++)
+    for (int i0 = 0; i0 < 3; i0 += LB) {
+      double v[LB][3][SW], f3[LB][3], fm3[KO ? LB : 1][3];
+#pragma unroll
+      for (int ii = 0; ii < LB; ii++)
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-          gather_axis_k<PD, AX>(P, G_LAMU0 + i, k, v[i][k]);
-          f3[i][k] = upwind_far<PD, AX>(P, G_LAMU0 + i, k, U.vu, v[i][k]);
-          if constexpr (KO) fm3[i][k] = upwind_far<PD, AX>(P, G_LAMU0 + i, k, U.vd, v[i][k]);
+          gather_axis_k<PD, AX>(P, G_LAMU0 + i0 + ii, k, v[ii][k]);
+          f3[ii][k] = upwind_far<PD, AX>(P, G_LAMU0 + i0 + ii, k, U.vu, v[ii][k]);
+          if constexpr (KO) fm3[ii][k] = upwind_far<PD, AX>(P, G_LAMU0 + i0 + ii, k, U.vd, v[ii][k]);
         }
       BHAH_PHASE_BARRIER();
 #pragma unroll
-      for (int i = 0; i < 3; i++) {
+      for (int ii = 0; ii < LB; ii++) {
+        const int i = i0 + ii;
         double a = 0.0, d = 0.0;
 #pragma unroll
         for (int k = 0; k < 3; k++) {
           const bool up = vet[k] > 0.0;
-          a += U.w[k] * upwind_sum<RR>(v[i][k], f3[i][k], up);
-          if constexpr (KO) d += kw[k] * ko_v<RR>(v[i][k], f3[i][k], fm3[i][k]);
-          dlam[i][k] = AX && k == PD ? 0.0 : d1_axis<RR>(v[i][k], sp.d1s[k]);
+          a += U.w[k] * upwind_sum<RR>(v[ii][k], f3[ii][k], up);
+          if constexpr (KO) d += kw[k] * ko_v<RR>(v[ii][k], f3[ii][k], fm3[ii][k]);
+          dlam[i][k] = AX && k == PD ? 0.0 : d1_axis<RR>(v[ii][k], sp.d1s[k]);
         }
         put(PK_OUT + G_LAMU0 + i, a + ga.dm * d);
         // bet^i's right-hand side takes 3/4 of lambda^i's undissipated one:
@@ -640,13 +644,23 @@ __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, c
   // upwinded advection of Abar_ij and B^i (five and four gridfunctions per
   // batch of loads), K's first derivatives and advection from one gather in
   // the second batch; the terms formed earlier move to their result slots
-  {
+  if constexpr (H == 3) {
     constexpr int GA[5] = {G_ADD00, G_ADD00 + 1, G_ADD00 + 2, G_ADD00 + 3, G_ADD00 + 4};
     double a5[5];
     const double e5[5] = {ga.dm, ga.dm, ga.dm, ga.dm, ga.dm};
     advect_batch<5, PD, AX, KO>(P, GA, U, a5, e5, kw);
 #pragma unroll
     for (int t = 0; t < 5; t++) put(PK_OUT + GA[t], a5[t]);
+  } else {  // wider stencils: batches of three and two
+    constexpr int GA[3] = {G_ADD00, G_ADD00 + 1, G_ADD00 + 2}, GC[2] = {G_ADD00 + 3, G_ADD00 + 4};
+    double a3[3], a2[2];
+    const double e3[3] = {ga.dm, ga.dm, ga.dm}, e2[2] = {ga.dm, ga.dm};
+    advect_batch<3, PD, AX, KO>(P, GA, U, a3, e3, kw);
+#pragma unroll
+    for (int t = 0; t < 3; t++) put(PK_OUT + GA[t], a3[t]);
+    advect_batch<2, PD, AX, KO>(P, GC, U, a2, e2, kw);
+#pragma unroll
+    for (int t = 0; t < 2; t++) put(PK_OUT + GC[t], a2[t]);
   }
   {
     constexpr int GB[4] = {G_ADD00 + 5, G_BETU0, G_BETU0 + 1, G_BETU0 + 2};
@@ -659,7 +673,16 @@ __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, c
       if constexpr (KO) fm3[k] = upwind_far<PD, AX>(P, G_TRK, k, U.vd, v[k]);
     }
     const double e4[4] = {ga.dm, ga.dg, ga.dg, ga.dg};
-    advect_batch<4, PD, AX, KO>(P, GB, U, a4, e4, kw);
+    if constexpr (H == 3) {
+      advect_batch<4, PD, AX, KO>(P, GB, U, a4, e4, kw);
+    } else {  // wider stencils: two batches of two
+      constexpr int G1[2] = {GB[0], GB[1]}, G2[2] = {GB[2], GB[3]};
+      const double d1e[2] = {e4[0], e4[1]}, d2e[2] = {e4[2], e4[3]};
+      double b1[2], b2[2];
+      advect_batch<2, PD, AX, KO>(P, G1, U, b1, d1e, kw);
+      advect_batch<2, PD, AX, KO>(P, G2, U, b2, d2e, kw);
+      a4[0] = b1[0]; a4[1] = b1[1]; a4[2] = b2[0]; a4[3] = b2[1];
+    }
     put(PK_OUT + GB[0], a4[0]);
 #pragma unroll
     for (int t = 1; t < 4; t++) put(PK_OUT + GB[t], KO ? get(PK_OUT + GB[t]) + a4[t] : a4[t]);
