@@ -201,6 +201,7 @@ def test_production_numerics_full_size_headon():
     numerics at 8th order, tuned tile shape, 30 SSPRK3 steps, every point"""
     name = "headon_sinhcylindrical_128x2x256"
     _case("production_full", name, 30)
+    import torch  # noqa: F401  (device set up by torch before the library loads)
     from paper_2505_00097_amd import capi
     w = wl.WORKLOADS[name]
     g = capi.Grid(w["coord"], w["N"], w["ampl"], w["sinhw"], w["cfl"], bc_kind=capi.BC_RADIATION, nghosts=NG)
@@ -255,6 +256,34 @@ def test_constraints_match_oracle(name):
         capi.hamiltonian_constraint(g.h, to_gpu(y), H1)
         a, b = to_cpu(H1)[0][I], got[0][I]
         assert np.max(np.abs(a - b)) <= RHS_TOL * np.max(np.abs(b))
+
+
+@pytest.mark.parametrize("coord,N", [(wl.SINH_SPHERICAL, (5, 5, 2)), (wl.SINH_CYLINDRICAL, (5, 2, 5)),
+                                     (wl.SPHERICAL, (5, 5, 4)), (wl.SINH_CYLINDRICAL, (7, 4, 9))])
+def test_smallest_grids(coord, N):
+    """Grids as narrow as five ghost layers allow: every interior point's
+    radius-4 stencils (radius 5 upwinded, and the dissipation) reach the
+    outermost ghost layers on both sides; RHS with dissipation and 10 SSPRK3
+    steps with the radiation boundary against the oracle."""
+    _case("smallest", coord, N)
+    import torch  # noqa: F401  (device set up by torch before the library loads)
+    from paper_2505_00097_amd import capi
+    ampl = (2.0, 2.0, 3.0)
+    g = capi.Grid(coord, N, ampl, (0.3,) * 3, nghosts=NG)
+    og = orc.Grid(coord, N, ampl=ampl, sinhw=(0.3,) * 3, ng=NG, diss=DISS)
+    y = og.apply_bcs(og.brill_lindquist([0.4], [(0.1, 0.0, 0.2)]) + 0.01 * wl.smooth_random_state(og.n, seed=2))
+    _check_rhs(g, og, y, diss=DISS)
+    gr = capi.Grid(coord, N, ampl, (0.3,) * 3, bc_kind=capi.BC_RADIATION, nghosts=NG)
+    ogr = orc.Grid(coord, N, ampl=ampl, sinhw=(0.3,) * 3, ng=NG, diss=DISS, bc_kind=1)
+    yg = to_gpu(y)
+    ws = gr.workspace()
+    dt = ogr.dt()
+    for _ in range(10):
+        capi.ssprk3_step(gr.h, yg, ws, dt, eta=2.0, diss=DISS)
+        ogr.ssprk3_step(y, dt, eta=2.0)
+    err = gf_errors(to_cpu(yg), y, (slice(None),) * 3)
+    print("  err", fmt(orc.GF_NAMES, err), flush=True)
+    assert np.all(err <= EVOL_TOL), fmt(orc.GF_NAMES, err)
 
 
 def test_ensembles_and_server_take_fourth_order_grids_only():
