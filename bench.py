@@ -69,9 +69,10 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(workload):
+def measured_traffic(workload, tile=None):
     """HBM bytes per launch from the committed counter summary, or None if it
-    is absent, for another workload, or older than the kernel source."""
+    is absent, for another workload or tile shape, or older than the kernel
+    source."""
     if not os.path.exists(COUNTERS):
         return None
     vals = {}
@@ -81,8 +82,11 @@ def measured_traffic(workload):
             vals[k.strip()] = v.strip()
     if vals.get("source_sha256") != kernel_source_hash() or vals.get("workload") != workload:
         return None
+    key = "hbm_bytes_per_launch"
+    if tile is not None:  # the measurement at this tile shape, if one was taken
+        key += "_tile_" + "_".join(str(int(t)) for t in tile)
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
 
@@ -441,11 +445,12 @@ def main():
         ws = g.workspace()
         H = g._empty(1)
         capi.set_initial_data_brill_lindquist(g.h, w["masses"], w["positions"], y, stream=stream)
-        capi.grid_tune(g.h, y, g.state(), eta=w["eta"], stream=stream)  # tile shape for this grid
         dt = g.dt
         h_every = w.get("h_every", 0)
         for _ in range(args.warmup):
             capi.rk4_step(g.h, y, ws, dt, eta=w["eta"], stream=stream)
+        capi.grid_tune(g.h, y, g.state(), eta=w["eta"], stream=stream)  # tile shape for this grid
+        tile = capi.grid_get_tile(g.h)
         torch.cuda.synchronize()
 
         # ---- timed region: exactly `steps` RK4 steps ----------------------
@@ -518,7 +523,7 @@ def main():
 
     flops = f_alg(w["coord"], w["N"]) * n_int
     achieved = flops / rhs_s
-    traffic = measured_traffic(args.workload)
+    traffic = measured_traffic(args.workload, tile)
     out = {
         "metric": METRIC,
         "value": n_int * args.steps / elapsed,

@@ -258,7 +258,8 @@ int bhah_grid_get_tile(const bhah_grid* g, int* lx, int* ly, int* band);
 
 /* Time every allowed tile shape for this grid on state y (valid ghosts),
  * writing right-hand sides into rhs (state layout, caller-owned scratch),
- * and keep the fastest. Synchronises stream.                                */
+ * after a few warm-up launches, in two passes; keep the first shape (larger
+ * extents along i0 first) within 2% of the fastest. Synchronises stream.    */
 int bhah_grid_tune(bhah_grid* g, const bhah_gauge_params* gp, const double* y,
                    double* rhs, void* stream);
 

@@ -30,6 +30,12 @@ def test_traffic_is_reported_only_for_matching_kernel_sources(tmp_path, monkeypa
     stale.write_text("\n".join(lines) + "\n")
     monkeypatch.setattr(bench, "COUNTERS", str(stale))
     assert bench.measured_traffic(name) is None
-    # nor for another workload
+    # nor for another workload, nor for another tile shape than the one profiled
     monkeypatch.setattr(bench, "COUNTERS", os.path.join(ROOT, "profiles", "k_rhs_fused_headon_counters.txt"))
     assert bench.measured_traffic("vacuum3d_sinhspherical_256x128x64") is None
+    tiles = [l.split(":")[0].rsplit("_", 3)[1:] for l in counters.splitlines()
+             if l.startswith("hbm_bytes_per_launch_tile_")]
+    assert tiles
+    for t in tiles:
+        assert bench.measured_traffic(name, [int(x) for x in t]) is not None
+    assert bench.measured_traffic(name, [2, 0, 1]) is None  # a shape never profiled
