@@ -159,12 +159,12 @@ def time_rhs(capi, g, y, eta, reps, stream, diss=(0.0, 0.0)):
     return e0.elapsed_time(e1) / 1e3 / reps
 
 
-def make_grids(capi, jobs, bc_kind=0):
+def make_grids(capi, jobs, bc_kind=0, nghosts=3):
     cache, grids = {}, []
     for j in jobs:
         key = (j["coord"], tuple(j["N"]), tuple(j["ampl"]), tuple(j["sinhw"]), j["cfl"])
         if key not in cache:
-            cache[key] = capi.Grid(j["coord"], j["N"], j["ampl"], j["sinhw"], j["cfl"], bc_kind)
+            cache[key] = capi.Grid(j["coord"], j["N"], j["ampl"], j["sinhw"], j["cfl"], bc_kind, nghosts)
         grids.append(cache[key])
     return grids
 
@@ -217,13 +217,14 @@ def run_ssprk3(capi, wl, stream, steps, diss=(0.0, 0.0), bc_kind=0, nghosts=3, r
     return out
 
 
-def run_batched(capi, wl, stream, steps, seq_steps, graph_steps, integrator=0, diss=(0.0, 0.0), bc_kind=0):
+def run_batched(capi, wl, stream, steps, seq_steps, graph_steps, integrator=0, diss=(0.0, 0.0), bc_kind=0,
+                nghosts=3):
     """64 uneven head-on jobs: one batch advancing all of them `steps` steps
     (RK4 or SSPRK3, optional dissipation and radiation boundary), against the
     same jobs advanced one at a time with the same numerics."""
     import torch
     jobs = wl.batched_jobs()
-    grids = make_grids(capi, jobs, bc_kind)
+    grids = make_grids(capi, jobs, bc_kind, nghosts)
     ys, wss = [], []
     for j, g in zip(jobs, grids):
         y = g.state()
@@ -270,6 +271,7 @@ def run_batched(capi, wl, stream, steps, seq_steps, graph_steps, integrator=0, d
     return {"workload": "64 head-on BL jobs, SinhCylindrical N_rho~U{48..192} x 2 x 2N_rho, seed 250500097",
             "integrator": "ssprk3" if integrator == capi.SSPRK3 else "rk4", "dissipation": list(diss),
             "boundary": "radiation" if bc_kind == capi.BC_RADIATION else "extrapolation",
+            "fd_order": 2 * (nghosts - 1),
             "interior_points": pts, "steps": steps, "value": batched, "unit": UNIT,
             "ms_per_step_all_jobs": el * 1e3 / steps,
             "p50_step_ms": percentile(per_step, 50), "p99_step_ms": percentile(per_step, 99),
@@ -502,6 +504,13 @@ def main():
             torch.cuda.empty_cache()
             print(f"# batched, SSPRK3 + dissipation + radiation: "
                   f"{extras['batched_production_numerics']['value']:.3e} pt-steps/s", file=sys.stderr, flush=True)
+            extras["batched_production_numerics_8th_order"] = run_batched(
+                capi, wl, stream, args.batched_steps, args.batched_seq_steps, args.graph_steps,
+                integrator=capi.SSPRK3, diss=(0.99, 0.3), bc_kind=capi.BC_RADIATION, nghosts=5)
+            torch.cuda.empty_cache()
+            print(f"# batched, production numerics at 8th order: "
+                  f"{extras['batched_production_numerics_8th_order']['value']:.3e} pt-steps/s", file=sys.stderr,
+                  flush=True)
         if args.study_steps > 0:
             extras["rhs_study_3d"] = run_rhs_study(capi, wl, stream, args.rhs_reps // 5 + 1, args.study_steps)
             torch.cuda.empty_cache()

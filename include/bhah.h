@@ -118,10 +118,11 @@ typedef struct bhah_batch bhah_batch; /* opaque ensemble of grids        */
  * for 8th order (the production head-on run of Sec. 4.2); upwinded advection
  * needs N_FD/2 + 1 ghost layers (Sec. 3). The order applies to every
  * derivative, to the Kreiss-Oliger operator (order N_FD + 1) and to the
- * radiation condition's stencils. Ensembles and the server take nghosts = 3
- * only. ampl[]/sinhw[] entries for directions without a map are ignored.
- * cfl scales the time step (Sec. 4.1 uses 0.5). bc_kind: BHAH_BC_EXTRAP or
- * BHAH_BC_RADIATION (both in solo calls, ensembles and the server).          */
+ * radiation condition's stencils, in solo calls, ensembles (which may mix
+ * both orders) and the server. ampl[]/sinhw[] entries for directions without
+ * a map are ignored. cfl scales the time step (Sec. 4.1 uses 0.5). bc_kind:
+ * BHAH_BC_EXTRAP or BHAH_BC_RADIATION (both in solo calls, ensembles and the
+ * server).                                                                   */
 typedef struct {
   int coord;
   int N[3];

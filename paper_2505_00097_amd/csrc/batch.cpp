@@ -19,8 +19,6 @@ int bhah_batch_create(const bhah_grid* const* grids, int n, const bhah_gauge_par
   if (int rc = bhah::check_gauge(gp, "bhah_batch_create")) return rc;
   for (int j = 0; j < n; j++) {
     if (!grids[j]) return bhah::fail(BHAH_EINVAL, "bhah_batch_create: NULL grid");
-    if (grids[j]->dev.ng != bhah::NG)
-      return bhah::fail(BHAH_EINVAL, "bhah_batch_create: ensembles run 4th-order grids (nghosts = 3)");
   }
   bhah_batch* b = new (std::nothrow) bhah_batch(*gp, tune_cache_path);
   if (!b) return bhah::fail(BHAH_ENOMEM, "bhah_batch_create: host allocation failed");

@@ -126,13 +126,14 @@ inline bool tile_fits_periodic(int coord, const TileCfg& c) {
   return coord == BHAH_SINH_CYLINDRICAL ? c.ly == 0 : c.lx + c.ly == 6;
 }
 
-// The right-hand-side kernel is built per coordinate family and per phi
-// extent: a grid with exactly two interior phi planes (axisymmetric runs)
-// gets a variant that reads each phi stencil as its two planes and drops the
-// phi derivatives that vanish identically there. Variant = 2 coord + that.
-constexpr int NVAR = 6;
-__host__ __device__ inline int rhs_variant(int coord, int N1, int N2) {
-  return 2 * coord + ((coord == BHAH_SINH_CYLINDRICAL ? N1 : N2) == 2 ? 1 : 0);
+// The right-hand-side kernel is built per coordinate family, per phi extent
+// and per differencing order: a grid with exactly two interior phi planes
+// (axisymmetric runs) gets a variant that reads each phi stencil as its two
+// planes and drops the phi derivatives that vanish identically there.
+// Variant = 2 coord + that, plus 6 for the 8th-order grids (5 ghost layers).
+constexpr int NVAR = 12;
+__host__ __device__ inline int rhs_variant(int coord, int N1, int N2, int ng = NG) {
+  return 2 * coord + ((coord == BHAH_SINH_CYLINDRICAL ? N1 : N2) == 2 ? 1 : 0) + (ng == 5 ? 6 : 0);
 }
 
 struct TileMap {

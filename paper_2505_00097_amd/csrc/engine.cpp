@@ -203,7 +203,7 @@ void Engine::build_blob(const std::vector<TileCfg>& cfg, const std::vector<int>&
     for (int r = 0; r < repeat; r++)
       for (int j : sel) {
         const GridDev& G = jobs_[j].g->dev;
-        if (rhs_variant(G.coord, G.N1, G.N2) != f) continue;
+        if (rhs_variant(G.coord, G.N1, G.N2, G.ng) != f) continue;
         for (int t = 0; t < maps[j].ntiles; t++) tiles[pos++] = int2{j, t};
       }
     hdr->n_tiles[f] = pos - hdr->tile_off[f];
@@ -254,15 +254,24 @@ int Engine::time_class(const SizeClass& c, const TileCfg& cfg, hipStream_t s, do
   const BatchJob* dj = (const BatchJob*)(d_blob_ + L.jobs);
   const BatchHdr* dh = (const BatchHdr*)d_blob_;
   const int2* dt = (const int2*)(d_blob_ + L.tiles);
-  const int variant = rhs_variant(std::get<0>(c), std::get<2>(c), std::get<3>(c));
+  // the kernel variants of the class's jobs (4th- and 8th-order grids of one
+  // shape share the class)
+  bool used[NVAR] = {};
+  for (int j : only) {
+    const GridDev& G = jobs_[j].g->dev;
+    used[rhs_variant(G.coord, G.N1, G.N2, G.ng)] = true;
+  }
   hipEvent_t e0, e1;
   if ((rc = check_hip(hipEventCreate(&e0), "hipEventCreate"))) return rc;
   if ((rc = check_hip(hipEventCreate(&e1), "hipEventCreate"))) { (void)hipEventDestroy(e0); return rc; }
   const int reps = 3;
   const int blocks = rhs_grid();
-  launch_rhs_batch(variant, dj, dh, dt, 4, gauge_of(gp_), false, blocks, s);
+  for (int v = 0; v < NVAR; v++)
+    if (used[v]) launch_rhs_batch(v, dj, dh, dt, 4, gauge_of(gp_), false, blocks, s);
   (void)hipEventRecord(e0, s);
-  for (int r = 0; r < reps; r++) launch_rhs_batch(variant, dj, dh, dt, 4, gauge_of(gp_), false, blocks, s);
+  for (int r = 0; r < reps; r++)
+    for (int v = 0; v < NVAR; v++)
+      if (used[v]) launch_rhs_batch(v, dj, dh, dt, 4, gauge_of(gp_), false, blocks, s);
   (void)hipEventRecord(e1, s);
   rc = check_hip(hipEventSynchronize(e1), "tile timing");
   float ms = 0.f;

@@ -177,9 +177,9 @@ void launch_radiation(const GridDev& G, const RadDev& R, const double* in, const
   else hipLaunchKernelGGL(k_radiation<2>, grid, dim3(256), 0, s, G, R, in, st);
 }
 
-// Ensemble form (4th-order grids): blocks stride over the (job, chunk of 256
-// radiation points) list; each job's stage input and combination come from
-// its table entry.
+// Ensemble form: blocks stride over the (job, chunk of 256 radiation points)
+// list; each job's stage input, combination and stencil radius come from its
+// table entry.
 __global__ void __launch_bounds__(256) k_radiation_batch(const BatchJob* __restrict__ jobs,
                                                          const BatchHdr* __restrict__ hdr,
                                                          const int2* __restrict__ work, int stage) {
@@ -190,7 +190,10 @@ __global__ void __launch_bounds__(256) k_radiation_batch(const BatchJob* __restr
     const int2 wk = wl[c];
     const BatchJob* J = jobs + wk.x;
     const int t = wk.y * 256 + (int)threadIdx.x;
-    if (t < J->rad.n) radiation_point<NG - 1>(J->G, J->rad, t, J->in[stage], J->st[stage], g0);
+    if (t < J->rad.n) {
+      if (J->rad.R == 4) radiation_point<4>(J->G, J->rad, t, J->in[stage], J->st[stage], g0);
+      else radiation_point<2>(J->G, J->rad, t, J->in[stage], J->st[stage], g0);
+    }
   }
 }
 

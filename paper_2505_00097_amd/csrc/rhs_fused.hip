@@ -987,16 +987,17 @@ k_rhs_fused(GridDev G, TileMap T, Gauge ga, const double* __restrict__ y, StageA
   fused_point<C, AX, KO, true, H>(G, ga, y, st, i0, i1, i2, q, aux, park + threadIdx.x);
 }
 
-// Persistent form for ensembles (grids with NG ghost layers, 4th order): a
-// fixed grid of blocks (a multiple of the XCD count) strides over one kernel
-// variant's (job, tile) work list; every point runs the same fused_point as
-// above.
-template <int C, bool AX, bool KO, bool MIX>
+// Persistent form for ensembles: a fixed grid of blocks (a multiple of the
+// XCD count) strides over one kernel variant's (job, tile) work list (the
+// jobs of one family, phi extent and order, H ghost layers); every point
+// runs the same fused_point as above.
+template <int C, bool AX, bool KO, bool MIX, int H>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
 k_rhs_batch(const BatchJob* __restrict__ jobs, const BatchHdr* __restrict__ hdr, const int2* __restrict__ work,
             int stage, Gauge ga) {
-  const int n = hdr->n_tiles[2 * C + AX];
-  const int2* wl = work + hdr->tile_off[2 * C + AX];
+  constexpr int V = 2 * C + AX + (H == 5 ? 6 : 0);
+  const int n = hdr->n_tiles[V];
+  const int2* wl = work + hdr->tile_off[V];
   const int per = (n + BHAH_NXCD - 1) / BHAH_NXCD;
   __shared__ double park[PARK * 64];
   for (int t = (int)blockIdx.x; t < per * BHAH_NXCD; t += (int)gridDim.x) {
@@ -1006,10 +1007,10 @@ k_rhs_batch(const BatchJob* __restrict__ jobs, const BatchHdr* __restrict__ hdr,
     const BatchJob* J = jobs + wk.x;
     const GridDev G = J->G;
     int i0, i1, i2;
-    if (!tile_point<NG>(G, J->T, wk.y, (int)threadIdx.x, i0, i1, i2)) continue;
+    if (!tile_point<H>(G, J->T, wk.y, (int)threadIdx.x, i0, i1, i2)) continue;
     const unsigned q = (unsigned)(i0 + G.s1 * i1 + G.s2 * i2);
     const StageArgs st = J->st[stage];
-    fused_point<C, AX, KO, MIX, NG>(G, ga, J->in[stage], st, i0, i1, i2, q, nullptr, park + threadIdx.x);
+    fused_point<C, AX, KO, MIX, H>(G, ga, J->in[stage], st, i0, i1, i2, q, nullptr, park + threadIdx.x);
   }
 }
 
@@ -1033,10 +1034,10 @@ void launch_fused_t(dim3 g, hipStream_t s, const GridDev& G, const TileMap& T, c
                     const StageArgs& st, double* aux) {
   hipLaunchKernelGGL((k_rhs_fused<C, AX, KO, H>), g, dim3(64), 0, s, G, T, ga, y, st, aux);
 }
-template <int C, bool AX, bool KO, bool MIX>
+template <int C, bool AX, bool KO, bool MIX, int H>
 void launch_batch_t(dim3 g, hipStream_t s, const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage,
                     const Gauge& ga) {
-  hipLaunchKernelGGL((k_rhs_batch<C, AX, KO, MIX>), g, dim3(64), 0, s, jobs, hdr, work, stage, ga);
+  hipLaunchKernelGGL((k_rhs_batch<C, AX, KO, MIX, H>), g, dim3(64), 0, s, jobs, hdr, work, stage, ga);
 }
 using FusedLaunch = void (*)(dim3, hipStream_t, const GridDev&, const TileMap&, const Gauge&, const double*,
                              const StageArgs&, double*);
@@ -1056,14 +1057,16 @@ constexpr int SS = BHAH_SINH_SPHERICAL, SC = BHAH_SINH_CYLINDRICAL, SP = BHAH_SP
 static const FusedLaunch kFused[2][NVAR][2] = {BHAH_FUSED_ROWS(3), BHAH_FUSED_ROWS(5)};
 #undef BHAH_FUSED_ROWS
 // [variant][dissipation][two-state stages (SSPRK3)]
-#define BHAH_BATCH_ROW(C, AX)                                                                    \
+#define BHAH_BATCH_ROW(C, AX, H)                                                                 \
   {                                                                                              \
-    {launch_batch_t<C, AX, false, false>, launch_batch_t<C, AX, false, true>},                   \
-    { launch_batch_t<C, AX, true, false>, launch_batch_t<C, AX, true, true> }                    \
+    {launch_batch_t<C, AX, false, false, H>, launch_batch_t<C, AX, false, true, H>},             \
+    { launch_batch_t<C, AX, true, false, H>, launch_batch_t<C, AX, true, true, H> }              \
   }
-static const BatchLaunch kBatch[NVAR][2][2] = {BHAH_BATCH_ROW(SS, false), BHAH_BATCH_ROW(SS, true),
-                                               BHAH_BATCH_ROW(SC, false), BHAH_BATCH_ROW(SC, true),
-                                               BHAH_BATCH_ROW(SP, false), BHAH_BATCH_ROW(SP, true)};
+static const BatchLaunch kBatch[NVAR][2][2] = {
+    BHAH_BATCH_ROW(SS, false, 3), BHAH_BATCH_ROW(SS, true, 3), BHAH_BATCH_ROW(SC, false, 3),
+    BHAH_BATCH_ROW(SC, true, 3),  BHAH_BATCH_ROW(SP, false, 3), BHAH_BATCH_ROW(SP, true, 3),
+    BHAH_BATCH_ROW(SS, false, 5), BHAH_BATCH_ROW(SS, true, 5), BHAH_BATCH_ROW(SC, false, 5),
+    BHAH_BATCH_ROW(SC, true, 5),  BHAH_BATCH_ROW(SP, false, 5), BHAH_BATCH_ROW(SP, true, 5)};
 #undef BHAH_BATCH_ROW
 
 void launch_rhs_fused(const GridDev& G, const Gauge& ga, const double* y, double* aux, const StageArgs& st,

@@ -180,8 +180,6 @@ int bhah_server_submit(bhah_server* s, const bhah_job_desc* job, long long* id) 
   if (!s || !job || !id) return bhah::fail(BHAH_EINVAL, "bhah_server_submit: NULL argument");
   if (job->n_punct < 0 || job->n_punct > 16 || job->nsteps < 0)
     return bhah::fail(BHAH_EINVAL, "bhah_server_submit: 0 <= n_punct <= 16 and nsteps >= 0 required");
-  if (job->grid.nghosts != bhah::NG)
-    return bhah::fail(BHAH_EINVAL, "bhah_server_submit: served jobs run 4th-order grids (nghosts = 3)");
   bhah_server::Job j;
   j.d = *job;
   j.key = grid_key(job->grid);

@@ -286,16 +286,62 @@ def test_smallest_grids(coord, N):
     assert np.all(err <= EVOL_TOL), fmt(orc.GF_NAMES, err)
 
 
-def test_ensembles_and_server_take_fourth_order_grids_only():
-    _case("batch_server_reject")
+def test_ensembles_and_server_run_eighth_order_grids():
+    """8th-order jobs in one ensemble with 4th-order twins of the same shapes
+    (a size class holding both orders), both boundary kinds, SSPRK3 with
+    dissipation and then RK4 without: every job equals its solo steps bit for
+    bit. An 8th-order radiation job through the server likewise."""
+    _case("ensemble_server")
+    import torch
     from paper_2505_00097_amd import capi
-    g, _ = _pair("tiny")
-    with pytest.raises(capi.BhahError, match="nghosts = 3"):
-        capi.batch_create([g.h])
-    srv = capi.server_create(1e9, max_jobs=2, steps_per_tick=1)
+    shapes = [(wl.SINH_CYLINDRICAL, (24, 2, 48), (8.0,) * 3, (0.3,) * 3),
+              (wl.SINH_SPHERICAL, (20, 8, 4), (6.0,) * 3, (0.3,) * 3),
+              (wl.SINH_CYLINDRICAL, (17, 4, 21), (6.0,) * 3, (0.3,) * 3)]
+    grids = [capi.Grid(c, N, a, w, 0.5, bc_kind=bc, nghosts=ng) for c, N, a, w in shapes
+             for ng in (5, 3) for bc in (capi.BC_EXTRAP, capi.BC_RADIATION)]
+    ys = []
+    for g in grids:
+        y = g.state()
+        capi.set_initial_data_brill_lindquist(g.h, *HEADON, y)
+        ys.append(y)
+    wss = [g.workspace() for g in grids]
+    dts = [g.dt for g in grids]
+    b = capi.batch_create([g.h for g in grids], eta=2.0, diss=DISS)
+    capi.batch_set_integrator(b, capi.SSPRK3)
+    capi.batch_set_graph_steps(b, 4)
+    for integrator, diss, nsteps in ((capi.SSPRK3, DISS, 9), (capi.RK4, (0.0, 0.0), 5)):
+        if integrator == capi.RK4:
+            capi.batch_destroy(b)
+            b = capi.batch_create([g.h for g in grids], eta=2.0)
+        y0 = [y.clone() for y in ys]
+        capi.batch_step(b, ys, wss, dts, nsteps=nsteps)
+        torch.cuda.synchronize()
+        step = capi.ssprk3_step if integrator == capi.SSPRK3 else capi.rk4_step
+        for k, (g, y, a) in enumerate(zip(grids, ys, y0)):
+            s_ = a.clone()
+            ws = g.workspace()
+            for _ in range(nsteps):
+                step(g.h, s_, ws, g.dt, diss=diss)
+            torch.cuda.synchronize()
+            assert torch.equal(y, s_), (integrator, k)
+    capi.batch_destroy(b)
+    c, N, a, w = shapes[0]
+    srv = capi.server_create(1e10, max_jobs=2, steps_per_tick=3, keep_results=True, integrator=capi.SSPRK3,
+                             diss=DISS)
     try:
-        d = capi.job_desc(wl.SINH_CYLINDRICAL, (16, 2, 32), (6.0,) * 3, (0.3,) * 3, 0.5, *HEADON, 10, nghosts=NG)
-        with pytest.raises(capi.BhahError, match="nghosts = 3"):
-            capi.server_submit(srv, d)
+        i = capi.server_submit(srv, capi.job_desc(c, N, a, w, 0.5, *HEADON, 8, bc_kind=capi.BC_RADIATION,
+                                                  nghosts=NG))
+        while capi.server_job_status(srv, i).state != capi.JOB_DONE:
+            capi.server_tick(srv)
+        g = capi.Grid(c, N, a, w, 0.5, bc_kind=capi.BC_RADIATION, nghosts=NG)
+        out = g.state()
+        capi.server_fetch(srv, i, out)
+        y = g.state()
+        capi.set_initial_data_brill_lindquist(g.h, *HEADON, y)
+        ws = g.workspace()
+        for _ in range(8):
+            capi.ssprk3_step(g.h, y, ws, g.dt, diss=DISS)
+        torch.cuda.synchronize()
+        assert torch.equal(out, y)
     finally:
         capi.server_destroy(srv)
