@@ -81,8 +81,9 @@ enum { BHAH_SINH_SPHERICAL = 0, BHAH_SINH_CYLINDRICAL = 1, BHAH_SPHERICAL = 2 };
  *   d_t f = -v (f - f_inf)/r - v df/dr,
  * f_inf = 1 for alpha and cf, 0 otherwise; v = sqrt(2) for alpha, 1
  * otherwise; df/dr through the logical derivatives along the mapped radial
- * directions (xx0, and xx2 on SinhCylindrical grids), 4th-order five-point
- * stencils centred where the array allows, shifted inward otherwise. The
+ * directions (xx0, and xx2 on SinhCylindrical grids), (N_FD + 1)-point
+ * stencils of the grid's order centred where the array allows, shifted
+ * inward otherwise. The
  * time integrators advance those points like interior ones and refill only
  * the inner ghosts (parity copies of interior or outer points).
  * bhah_apply_bcs always uses the extrapolation (initial fill of any grid). */
@@ -137,9 +138,12 @@ typedef struct {
  * 2.0). shift_variant must be 0: dB^i/dt uses the full dLambdabar^i/dt of
  * Eq. 11 including its advection term.
  * diss_gauge, diss_metric: Kreiss-Oliger dissipation strengths (Sec. 4.2
- * uses 0.99 and 0.3), >= 0, 0 = off. The term eps/(64 dxx^k) sum_k
- * delta_k^6 f (the radius-3 sixth difference along each logical direction)
- * is added to each rescaled right-hand side after Eqs. 7-15: diss_gauge for
+ * uses 0.99 and 0.3), >= 0, 0 = off. The term eps/(4^N_G dxx^k) sum_k
+ * delta_k^(2 N_G) f (the difference of order 2 N_G and radius N_G along each
+ * logical direction: the sixth over 64 with 3 ghost layers, the tenth over
+ * 1024 with 5), with the sign that makes its Fourier symbol
+ * -sin^(2 N_G)(theta/2)/dxx^k, is added to each rescaled right-hand side
+ * after Eqs. 7-15: diss_gauge for
  * alpha, vet^i, bet^i, diss_metric for the other gridfunctions; bet^i's
  * 3/4 dlambda^i/dt is the undissipated one.                                 */
 typedef struct {
@@ -214,8 +218,9 @@ int bhah_apply_bcs(const bhah_grid* g, double* y, void* stream);
  * BHAH_BC_RADIATION grid, its pure-outer points, with the radiation
  * condition's right-hand side). aux receives
  * BHAH_NUM_AUX_GFS gridfunctions (state layout, interior points) computed on
- * the way, or may be NULL to skip them. All 4th-order finite differences,
- * advection terms beta^k d_k upwinded (Sec. 3 second paragraph).            */
+ * the way, or may be NULL to skip them. Finite differences of the grid's
+ * order (4th or 8th), advection terms beta^k d_k upwinded (Sec. 3 second
+ * paragraph).                                                               */
 int bhah_bssn_rhs(const bhah_grid* g, const bhah_gauge_params* gp,
                   const double* y, double* rhs, double* aux, void* stream);
 
@@ -241,8 +246,8 @@ int bhah_rk4_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt,
 int bhah_ssprk3_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt,
                      double* y, double* workspace, void* stream);
 
-/* All three constraints at every interior point, centred 4th-order
- * differences: H of Eq. 16 (one gridfunction), the momentum constraint M^i of
+/* All three constraints at every interior point, centred differences of
+ * the grid's order: H of Eq. 16 (one gridfunction), the momentum constraint M^i of
  * Eq. 17 and C^i = Lambdabar^i - Delta^i (three gridfunctions each, rescaled
  * like lambda^i: times S_i). Same layout as the state, interior points only;
  * any of H, M, C may be NULL (skipped). y must have valid ghosts.           */
@@ -265,7 +270,7 @@ int bhah_grid_tune(bhah_grid* g, const bhah_gauge_params* gp, const double* y,
                    double* rhs, void* stream);
 
 /* Hamiltonian constraint H of Eq. 16 at every interior point (centred
- * 4th-order differences), written into H (one gridfunction, state point
+ * differences of the grid's order), written into H (one gridfunction, state point
  * layout, interior points only). y must have valid ghosts.                  */
 int bhah_hamiltonian_constraint(const bhah_grid* g, const double* y, double* H,
                                 void* stream);
