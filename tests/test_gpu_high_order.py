@@ -286,6 +286,46 @@ def test_smallest_grids(coord, N):
     assert np.all(err <= EVOL_TOL), fmt(orc.GF_NAMES, err)
 
 
+@pytest.mark.parametrize("wname", ["headon_sinhcylindrical_128x2x256", "vacuum3d_sinhspherical_256x128x64"])
+def test_rhs_full_size_sampled(wname):
+    """the full-size workloads at 8th order with the ninth-order dissipation:
+    the RHS at every point on the GPU, at the tuned tile shape, checked at
+    sampled points (all corners of the interior next to the boundaries plus
+    a random sample)"""
+    _case("rhs_full", wname)
+    import torch  # noqa: F401
+    from paper_2505_00097_amd import capi
+    w = wl.WORKLOADS[wname]
+    g = capi.Grid(w["coord"], w["N"], w["ampl"], w["sinhw"], w["cfl"], nghosts=NG)
+    og = orc.Grid(w["coord"], w["N"], ampl=w["ampl"], sinhw=w["sinhw"], cfl=w["cfl"], ng=NG, diss=DISS)
+    y = og.brill_lindquist(w["masses"], w["positions"])
+    y = og.apply_bcs(y + 0.05 * wl.smooth_random_state(og.n, seed=3))
+    yg = to_gpu(y)
+    capi.grid_tune(g.h, yg, g.state(), diss=DISS)
+    r = g.state()
+    r.zero_()
+    capi.bssn_rhs(g.h, yg, r, eta=2.0, diss=DISS)
+    out = to_cpu(r)
+    rng = np.random.default_rng(1)
+    N = og.N
+    pick = [(NG + a, NG + b, NG + c) for a in (0, 1, N[0] - 1) for b in (0, N[1] - 1)
+            for c in (0, N[2] // 2, N[2] - 1)]
+    for _ in range(400):
+        pick.append((NG + rng.integers(N[0]), NG + rng.integers(N[1]), NG + rng.integers(N[2])))
+    idx = np.array([og.flat(*p) for p in pick])
+
+    def pts_rhs(v):
+        return og.rhs_points(v, idx).T[:, None, None, :]
+
+    def err_fn(a, b):
+        return gf_errors(a, b, (slice(None),) * 3)
+    got = out.reshape(24, -1)[:, idx][:, None, None, :]
+    err = err_fn(got, pts_rhs(y))
+    tol = np.maximum(RHS_TOL, rounding_floor(pts_rhs, y, err_fn))
+    print("  err", fmt(orc.GF_NAMES, err), flush=True)
+    assert np.all(err <= tol), fmt(orc.GF_NAMES, err / tol)
+
+
 def test_ensembles_and_server_run_eighth_order_grids():
     """8th-order jobs in one ensemble with 4th-order twins of the same shapes
     (a size class holding both orders), both boundary kinds, SSPRK3 with
