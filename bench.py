@@ -371,12 +371,26 @@ def run_rhs_study(capi, wl, stream, reps, steps):
     step_s = e0.elapsed_time(e1) / 1e3 / steps
     rhs_s = time_rhs(capi, g, y, w["eta"], reps, stream)
     n = g.info.n_interior
+    tile = list(capi.grid_get_tile(g.h))
+    del y, ws
+    torch.cuda.empty_cache()
+    # the general kernel variant at 8th order with the production dissipation
+    g8 = capi.Grid(w["coord"], w["N"], w["ampl"], w["sinhw"], w["cfl"], nghosts=5)
+    y8 = g8.state()
+    capi.set_initial_data_brill_lindquist(g8.h, w["masses"], w["positions"], y8, stream=stream)
+    diss = (0.99, 0.3)
+    capi.grid_tune(g8.h, y8, g8.state(), eta=w["eta"], diss=diss, stream=stream)
+    rhs8_s = time_rhs(capi, g8, y8, w["eta"], reps, stream, diss=diss)
+    f8 = F_ALG8_KO[(w["coord"], two_planes(w["coord"], w["N"]))]
+    eighth = {"rhs_launch_s": rhs8_s, "flops_per_point": f8, "rhs_TFLOPs": f8 * n / rhs8_s / 1e12,
+              "rhs_frac_fp64_peak": f8 * n / rhs8_s / PEAK_FP64_VECTOR, "tile": list(capi.grid_get_tile(g8.h))}
+    del y8
     return {"workload": "vacuum3d_sinhspherical_256x128x64", "interior_points": n,
             "rhs_launch_s": rhs_s, "rhs_TFLOPs": f_alg(w["coord"], w["N"]) * n / rhs_s / 1e12,
             "rhs_frac_fp64_peak": f_alg(w["coord"], w["N"]) * n / rhs_s / PEAK_FP64_VECTOR,
             "rhs_alg_GBps": BYTES_ALG * n / rhs_s / 1e9,
             "rk4_step_ms": step_s * 1e3, "value": n / step_s, "unit": UNIT,
-            "tile": list(capi.grid_get_tile(g.h))}
+            "tile": tile, "rhs_8th_order_with_dissipation": eighth}
 
 
 def run_paper_grid(capi, wl, stream, name, N, r_max, steps, graph_steps, paper):
