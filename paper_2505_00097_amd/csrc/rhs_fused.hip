@@ -651,6 +651,15 @@ __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, c
     advect_batch<5, PD, AX, KO>(P, GA, U, a5, e5, kw);
 #pragma unroll
     for (int t = 0; t < 5; t++) put(PK_OUT + GA[t], a5[t]);
+  } else if constexpr (!AX) {  // wider stencils in three directions: one gridfunction per batch
+#pragma unroll
+    for (int t = 0; t < 5; t++) {
+      const int gl[1] = {G_ADD00 + t};
+      const double e1[1] = {ga.dm};
+      double a1[1];
+      advect_batch<1, PD, AX, KO>(P, gl, U, a1, e1, kw);
+      put(PK_OUT + G_ADD00 + t, a1[0]);
+    }
   } else {  // wider stencils: batches of three and two
     constexpr int GA[3] = {G_ADD00, G_ADD00 + 1, G_ADD00 + 2}, GC[2] = {G_ADD00 + 3, G_ADD00 + 4};
     double a3[3], a2[2];
@@ -675,6 +684,15 @@ __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, c
     const double e4[4] = {ga.dm, ga.dg, ga.dg, ga.dg};
     if constexpr (H == 3) {
       advect_batch<4, PD, AX, KO>(P, GB, U, a4, e4, kw);
+    } else if constexpr (!AX) {  // wider stencils in three directions: one per batch
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        const int gl[1] = {GB[t]};
+        const double e1[1] = {e4[t]};
+        double a1[1];
+        advect_batch<1, PD, AX, KO>(P, gl, U, a1, e1, kw);
+        a4[t] = a1[0];
+      }
     } else {  // wider stencils: two batches of two
       constexpr int G1[2] = {GB[0], GB[1]}, G2[2] = {GB[2], GB[3]};
       const double d1e[2] = {e4[0], e4[1]}, d2e[2] = {e4[2], e4[3]};
