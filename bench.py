@@ -498,7 +498,7 @@ def main():
             extras["ssprk3"] = run_ssprk3(capi, wl, stream, args.ssprk3_steps, diss=(0.99, 0.3))
             extras["production_numerics"] = run_ssprk3(capi, wl, stream, args.ssprk3_steps, diss=(0.99, 0.3),
                                                         bc_kind=capi.BC_RADIATION)
-            # the production head-on numerics in full (Sec. 4.2): 8th-order
+            # the production head-on numerics in full (Sec. 4.1): 8th-order
             # differences, ninth-order dissipation, eighth-order radiation
             extras["production_numerics_8th_order"] = run_ssprk3(
                 capi, wl, stream, args.ssprk3_steps, diss=(0.99, 0.3), bc_kind=capi.BC_RADIATION, nghosts=5,

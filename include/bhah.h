@@ -11,8 +11,10 @@
  *   - the ghost-zone fill: outer-boundary ghosts first, then inner-boundary
  *     (parity) ghosts, after every Runge-Kutta substage (Sec. 3, ghost-point
  *     classes and the ordered list of boundary steps);
- *   - Brill-Lindquist puncture initial data and the Hamiltonian constraint
- *     (Eq. 16) as a diagnostic.
+ *   - Brill-Lindquist puncture initial data (analytic, conformally flat,
+ *     time-symmetric: the stand-in for the TwoPunctures data of the head-on
+ *     run, Sec. 4.1, which needs a third-party elliptic solver) and the
+ *     Hamiltonian constraint (Eq. 16) as a diagnostic.
  *
  * Conventions shared by every entry point
  *   Return codes : BHAH_OK (0) or a negative BHAH_E* code. A message for the
@@ -116,7 +118,7 @@ typedef struct bhah_batch bhah_batch; /* opaque ensemble of grids        */
 
 /* Grid parameters. nghosts selects the finite-difference order N_FD =
  * 2 (nghosts - 1): 3 for 4th order (the benchmark runs of Sec. 4.2.1) or 5
- * for 8th order (the production head-on run of Sec. 4.2); upwinded advection
+ * for 8th order (the production head-on run of Sec. 4.1); upwinded advection
  * needs N_FD/2 + 1 ghost layers (Sec. 3). The order applies to every
  * derivative, to the Kreiss-Oliger operator (order N_FD + 1) and to the
  * radiation condition's stencils, in solo calls, ensembles (which may mix
@@ -137,7 +139,7 @@ typedef struct {
 /* Gauge parameters: eta is the Gamma-driver damping of Eq. 15 (Sec. 4.1 uses
  * 2.0). shift_variant must be 0: dB^i/dt uses the full dLambdabar^i/dt of
  * Eq. 11 including its advection term.
- * diss_gauge, diss_metric: Kreiss-Oliger dissipation strengths (Sec. 4.2
+ * diss_gauge, diss_metric: Kreiss-Oliger dissipation strengths (Sec. 4.1
  * uses 0.99 and 0.3), >= 0, 0 = off. The term eps/(4^N_G dxx^k) sum_k
  * delta_k^(2 N_G) f (the difference of order 2 N_G and radius N_G along each
  * logical direction: the sixth over 64 with 3 ghost layers, the tenth over
@@ -195,7 +197,9 @@ int bhah_grid_get_info(const bhah_grid* g, bhah_grid_info* info);
 int bhah_grid_get_bc_maps(const bhah_grid* g, int* host_kind, int* host_src,
                           int* host_parity);
 
-/* Brill-Lindquist puncture data: psi = 1 + sum_n m_n / (2 |x - x_n|),
+/* Brill-Lindquist puncture data, the analytic stand-in for the TwoPunctures
+ * initial data of Sec. 4.1 (both conformally flat with K = 0 at the
+ * punctures' rest): psi = 1 + sum_n m_n / (2 |x - x_n|),
  * W = psi^-2, alpha = psi^-2 (lapse_kind 0) or 1 (lapse_kind 1), all other
  * variables zero; interior points are set, then bhah_apply_bcs fills the
  * ghosts. host_masses[n_punct] and host_pos[3*n_punct] (Cartesian x,y,z) are
@@ -236,7 +240,7 @@ int bhah_rk4_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt,
                   double* y, double* workspace, void* stream);
 
 /* One step of size dt of the three-stage strong-stability-preserving
- * Runge-Kutta scheme that the production head-on run of Sec. 4.2 uses
+ * Runge-Kutta scheme that the production head-on run of Sec. 4.1 uses
  * (Gottlieb, Shu and Tadmor), in place on y:
  *   A = y + dt f(y); B = 3/4 y + 1/4 (A + dt f(A));
  *   y <- 1/3 y + 2/3 (B + dt f(B)),

@@ -13,7 +13,7 @@
  *   - every partial derivative of an evolved rescaled variable is a finite
  *     difference of order N_FD = 2 (N_G - 1) (Sec. 3: N_G = N_FD/2 + 1 ghost
  *     layers; the benchmark runs use N_FD = 4, the production head-on run of
- *     Sec. 4.2 N_FD = 8): centred (N_FD + 1)-point stencils, their tensor
+ *     Sec. 4.1 N_FD = 8): centred (N_FD + 1)-point stencils, their tensor
  *     product for mixed derivatives, and for the advection terms beta^k d_k
  *     the same width of stencil shifted one point upwind (Sec. 3, second
  *     paragraph);
@@ -21,14 +21,14 @@
  *     derivatives) is evaluated analytically (Sec. 2.2, Eq. 22);
  *   - RHS = Eqs. 7-15 with Eq. 12 (Sec. 2.1), unrescaled/rescaled per Sec. 2.2;
  *   - optional Kreiss-Oliger dissipation added to each rescaled right-hand
- *     side (Sec. 4.2, strengths for gauge and metric variables);
+ *     side (Sec. 4.1, strengths for gauge and metric variables);
  *   - boundary fill after every RK substage: outer extrapolation, then inner
  *     parity copies (Sec. 3, ordered boundary steps); or, with the radiation
  *     outer boundary, the pure-outer points evolved by a Sommerfeld condition
  *     and only the inner copies refilled;
  *   - classical RK4 (Sec. 4.2.1 footnote), or the three-stage strong-
  *     stability-preserving Runge-Kutta scheme the production head-on run of
- *     Sec. 4.2 uses (SSPRK3 of Gottlieb, Shu and Tadmor, cited there).
+ *     Sec. 4.1 uses (SSPRK3 of Gottlieb, Shu and Tadmor, cited there).
  * Readings where the paper is silent or garbled are marked "Reading:".
  *
  * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared.
@@ -139,7 +139,7 @@ static void lagrange_weights(int n, const int* m, int der, double* w) {
   }
 }
 
-/* Kreiss-Oliger dissipation of order 2R + 1 (Sec. 4.2 runs N_FD = 8 with
+/* Kreiss-Oliger dissipation of order 2R + 1 (Sec. 4.1 runs N_FD = 8 with
  * ninth-order dissipation operators). Reading: the operator is the
  * difference of order 2p = 2R + 2, radius p = N_G, scaled to
  * (-1)^(p+1) delta^2p f / (4^p h), whose Fourier symbol is -sin^2p(theta/2)/h
@@ -511,7 +511,8 @@ int oracle_apply_bcs(const oracle_params* p, double* y) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Brill-Lindquist punctures: conformally flat, time symmetric (K_ij = 0),
+/* Brill-Lindquist punctures (analytic stand-in for the TwoPunctures data of
+ * the head-on run, Sec. 4.1): conformally flat, time symmetric (K_ij = 0),
  * psi = 1 + sum m_n / (2 |x - x_n|), gamma_ij = psi^4 delta_ij, so
  * W = psi^-2, eps = Abar = K = Lambdabar = 0; precollapsed lapse psi^-2
  * (or 1), zero shift and B. Interior points, then the ghost fill.           */
@@ -1052,7 +1053,7 @@ static void bssn_point(const Grid* G, double eta, const double* y, int i0, int i
   out->rhs[TRK] = rhs_K;
   out->rhs[ALPHA] = rhs_alpha;
 
-  /* ---- 14b. Kreiss-Oliger dissipation (Sec. 4.2) ---------------------- */
+  /* ---- 14b. Kreiss-Oliger dissipation (Sec. 4.1) ---------------------- */
   /* Reading: the dissipation is added to each rescaled right-hand side after
    * the equations, with the gauge strength for alpha, vet^i and bet^i and
    * the metric strength for the rest; the 3/4 d_t lambda^i inside bet^i's
@@ -1134,7 +1135,7 @@ static void interior_index(const Grid* G, long long t, int* i0, int* i1, int* i2
  * at each pure-outer ghost point; f_inf = 1 for alpha and W, 0 otherwise;
  * v = sqrt(2) for alpha (the asymptotic gauge speed of 1+log slicing), 1
  * otherwise. rhat.grad f = sum_i (x/r . grad xx^i) df/dxx^i, each logical
- * derivative the (N_FD + 1)-point one of the grid's order (Sec. 4.2 pairs
+ * derivative the (N_FD + 1)-point one of the grid's order (Sec. 4.1 pairs
  * eighth-order differencing with an eighth-order radiation condition),
  * centred where the array allows and shifted to stay inside it otherwise. The pure-outer points are then
  * advanced by the time integrator like interior points, and the inner ghosts
@@ -1299,7 +1300,7 @@ int oracle_rk4_step(const oracle_params* p, double eta, double dt, double* y) {
   return rc;
 }
 
-/* SSPRK3 (Sec. 4.2, the scheme of the Gottlieb-Shu-Tadmor reference), in
+/* SSPRK3 (Sec. 4.1, the scheme of the Gottlieb-Shu-Tadmor reference), in
  * its convex-combination form of forward-Euler steps, with the ghost fill
  * after each stage as for RK4:
  *   y1 = y_n + dt f(y_n);

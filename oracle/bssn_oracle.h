@@ -31,7 +31,7 @@ typedef struct {
   double ampl[3];  /* outer extent of the sinh (or linear) maps */
   double sinhw[3]; /* sinh widths */
   double cfl;
-  /* Kreiss-Oliger dissipation strengths (Sec. 4.2), 0 = off: diss_gauge for
+  /* Kreiss-Oliger dissipation strengths (Sec. 4.1), 0 = off: diss_gauge for
    * alpha, vet^i, bet^i; diss_metric for every other gridfunction. */
   double diss_gauge, diss_metric;
   /* outer boundary (Sec. 3): 0 quadratic extrapolation, 1 Sommerfeld

@@ -62,7 +62,7 @@ void ssprk3_stages(double dt, double* y, double* ws, long long n, StageArgs st[3
                    double* gdst[3]) {
   double* A = ws;
   double* B = ws + n;
-  // SSPRK3 (Sec. 4.2, Gottlieb-Shu-Tadmor), each stage a convex combination
+  // SSPRK3 (Sec. 4.1, Gottlieb-Shu-Tadmor), each stage a convex combination
   // of y_n and a forward-Euler step: A = y + dt k1; B = 3/4 y + 1/4 A +
   // dt/4 k2; y_n+1 = 1/3 y + 2/3 B + 2/3 dt k3, boundary fill after each.
   st[0] = StageArgs{nullptr, y, A, dt, nullptr, nullptr, 0.0, 0.0, 0.0};

@@ -78,7 +78,8 @@ struct Punctures {
   double x[MAX_PUNCT][3];
 };
 
-// Brill-Lindquist: psi = 1 + sum m_n / (2 |x - x_n|); W = psi^-2; alpha =
+// Brill-Lindquist (analytic stand-in for the TwoPunctures data of Sec. 4.1):
+// psi = 1 + sum m_n / (2 |x - x_n|); W = psi^-2; alpha =
 // psi^-2 (precollapsed) or 1; all other variables zero. Interior points.
 __global__ void __launch_bounds__(64) k_brill_lindquist(GridDev G, Punctures P, double* __restrict__ y) {
   const int i0 = G.ng + (int)(blockIdx.x * blockDim.x + threadIdx.x);

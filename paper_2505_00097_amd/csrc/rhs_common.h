@@ -64,9 +64,9 @@ __device__ __forceinline__ double gf_ld(const double* y, long long sgf, int g, u
 //   KO f = (sum_{j=1..R+1} ko[j] (f_j + f_-j) + ko[0] f_0) / kden, the
 //          difference of order 2(R+1) scaled to the Fourier symbol
 //          -sin^(2R+2)(theta/2) (Kreiss-Oliger dissipation of order 2R+1,
-//          Sec. 4.2)
+//          Sec. 4.1)
 // R = 2: the 4th-order stencils; R = 4: the 8th-order ones of the
-// production head-on run (Sec. 4.2).
+// production head-on run (Sec. 4.1).
 template <int R>
 struct FdW;
 template <>

@@ -67,7 +67,7 @@ __device__ __forceinline__ double upwind_sum(const double (&v)[2 * R + 1], doubl
   return upwind_f<R>(f);
 }
 
-// Kreiss-Oliger dissipation (Sec. 4.2): the difference of order 2(R+1)
+// Kreiss-Oliger dissipation (Sec. 4.1): the difference of order 2(R+1)
 // along each logical direction, weighted by eps/(kden dxx^k); at 4th order
 // delta^6 f = f(3) + f(-3) - 6 (f(2) + f(-2)) + 15 (f(1) + f(-1)) - 20 f(0)
 // over 64 dxx^k. Symmetric in the two sides, so the upwind-ordered stencil

@@ -1,5 +1,5 @@
 """Parity of the 8th-order path (N_G = 5 ghost layers, Sec. 3; the
-differencing of the production head-on run of Sec. 4.2) with the CPU oracle,
+differencing of the production head-on run of Sec. 4.1) with the CPU oracle,
 through the C ABI. Same bars as the 4th-order parity: per right-hand side
 within max(1e-12, the oracle's rounding floor) of each tensor's largest
 interior magnitude; after evolution within max(1e-9, the evolution's
@@ -184,7 +184,7 @@ def test_evolution_matches_oracle(name, stepper, steps):
 
 
 def test_production_numerics_match_oracle():
-    """the production head-on numerics of Sec. 4.2 in full: 8th-order
+    """the production head-on numerics of Sec. 4.1 in full: 8th-order
     differences, ninth-order Kreiss-Oliger dissipation 0.99 / 0.3, the
     eighth-order radiation condition and SSPRK3"""
     _case("production", "cyl_ragged", 40)

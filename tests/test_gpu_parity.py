@@ -303,7 +303,7 @@ def test_radiation_rk4_evolution_matches_oracle(name, steps):
 
 
 def test_production_numerics_match_oracle():
-    """The head-on run's numerics of Sec. 4.2 at 4th order: SSPRK3, Kreiss-
+    """The head-on run's numerics of Sec. 4.1 at 4th order: SSPRK3, Kreiss-
     Oliger dissipation 0.99 / 0.3 and the Sommerfeld outer boundary."""
     _print_case("evolve_production", "cyl_ragged", 40)
     from paper_2505_00097_amd import capi

@@ -1,4 +1,4 @@
-"""Pins of the oracle's Kreiss-Oliger dissipation (Sec. 4.2: strengths for the
+"""Pins of the oracle's Kreiss-Oliger dissipation (Sec. 4.1: strengths for the
 gauge and the metric variables, operator one order above the differencing).
 
 The dissipation is additive, so the right-hand side with it minus the one

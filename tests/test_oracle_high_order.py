@@ -1,7 +1,7 @@
 """Pins of the oracle's finite differences of higher order (Sec. 3: the
 differencing order N_FD is selectable and needs N_G = N_FD/2 + 1 ghost
 layers for the upwinded advection stencils; the production head-on run of
-Sec. 4.2 uses N_FD = 8 with ninth-order Kreiss-Oliger dissipation and an
+Sec. 4.1 uses N_FD = 8 with ninth-order Kreiss-Oliger dissipation and an
 eighth-order radiation condition).
 
 Fixed independently of the oracle's Lagrange-polynomial construction:

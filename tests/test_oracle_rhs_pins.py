@@ -7,7 +7,7 @@ that are also fine points after 3x refinement of a cell-centred grid, where
 4th-order finite differences give an error ratio near 3^4 = 81 (2nd order
 would give 9; a wrong or missing term gives about 1). With N_G = 5 ghost
 layers the differences are of 8th order (Sec. 3, N_G = N_FD/2 + 1; the
-production head-on run of Sec. 4.2) and the ratio is near 3^8 = 6561; the
+production head-on run of Sec. 4.1) and the ratio is near 3^8 = 6561; the
 bound 400 fails for any stencil of 6th order or lower.
 """
 import numpy as np
