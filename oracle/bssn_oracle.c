@@ -1,7 +1,7 @@
 /*
  * bssn_oracle.c -- TEST INFRASTRUCTURE: the plain CPU oracle.
  *
- * A deliberately direct FP64 evaluation of the discretised BSSN evolution of
+ * A deliberately direct evaluation of the discretised BSSN evolution of
  * arXiv:2505.00097. Every quantity is built with full 3x3(x3x3) index loops in
  * the order and notation of the paper's equations, with no blocking, fusion
  * or symmetry tricks, so that each step can be compared with the paper by
@@ -31,11 +31,18 @@
  *     Sec. 4.1 uses (SSPRK3 of Gottlieb, Shu and Tadmor, cited there).
  * Readings where the paper is silent or garbled are marked "Reading:".
  *
- * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared.
+ * Precision: every quantity has the type `real` (oracle_real): double in the
+ * FP64 oracle (liboracle.so); the same source compiled with
+ * -DORACLE_REAL="long double" (liboracle_ld.so) is the extended-precision
+ * reference against which both the FP64 oracle and the GPU are measured at
+ * ill-conditioned points. Literal fractions are written as (real)a / b so
+ * that they are rounded in the build's own precision.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared [-DORACLE_REAL="long double"].
  */
 #include "bssn_oracle.h"
 
-#include <math.h>
+#include <tgmath.h> /* math routines chosen by argument type: double or long double */
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -43,6 +50,8 @@
 #endif
 
 #define NGF ORACLE_NGF
+
+typedef oracle_real real; /* double, or long double in the reference build */
 
 /* gridfunction order (alphabetical names of the rescaled variables) */
 enum {
@@ -77,7 +86,7 @@ static const int GF_J[NGF] = {0, 1, 2, 1, 2, 2, 0, 0, 0, 0, 0,
  * to zero), so a constant field has exactly zero derivatives.               */
 typedef struct {
   int R;
-  double d1[MAXR + 1], d2[MAXR + 1], up[2 * MAXR + 1], ko[MAXR + 2];
+  real d1[MAXR + 1], d2[MAXR + 1], up[2 * MAXR + 1], ko[MAXR + 2];
 } Sten;
 
 typedef struct {
@@ -85,7 +94,7 @@ typedef struct {
   int n[3];
   long long np;     /* points incl. ghosts */
   long long st[3];  /* flat-index strides */
-  double xxmin[3], xxmax[3], dxx[3];
+  real xxmin[3], xxmax[3], dxx[3];
   Sten fd;
 } Grid;
 
@@ -115,22 +124,22 @@ int oracle_check(const oracle_params* p) {
 /* w[j] with f^(der)(0) ~ sum_j w[j] f(m[j]) (der = 1 or 2): the weights are
  * the derivatives at 0 of the Lagrange basis polynomials through the n
  * integer nodes m[], L_j(x) = prod_{i != j} (x - m_i)/(m_j - m_i).          */
-static void lagrange_weights(int n, const int* m, int der, double* w) {
+static void lagrange_weights(int n, const int* m, int der, real* w) {
   for (int j = 0; j < n; j++) {
-    double s = 0.0;
+    real s = 0.0;
     for (int k = 0; k < n; k++) {
       if (k == j) continue;
       if (der == 1) {
-        double prod = 1.0 / (double)(m[j] - m[k]);
+        real prod = 1.0 / (real)(m[j] - m[k]);
         for (int i = 0; i < n; i++)
-          if (i != j && i != k) prod *= (0.0 - m[i]) / (double)(m[j] - m[i]);
+          if (i != j && i != k) prod *= (0.0 - m[i]) / (real)(m[j] - m[i]);
         s += prod;
       } else {
         for (int l = 0; l < n; l++) {
           if (l == j || l == k) continue;
-          double prod = 1.0 / ((double)(m[j] - m[k]) * (double)(m[j] - m[l]));
+          real prod = 1.0 / ((real)(m[j] - m[k]) * (real)(m[j] - m[l]));
           for (int i = 0; i < n; i++)
-            if (i != j && i != k && i != l) prod *= (0.0 - m[i]) / (double)(m[j] - m[i]);
+            if (i != j && i != k && i != l) prod *= (0.0 - m[i]) / (real)(m[j] - m[i]);
           s += prod;
         }
       }
@@ -148,7 +157,7 @@ static void lagrange_weights(int n, const int* m, int der, double* w) {
  * pair +-j is (-1)^(j+1) C(2p, p+j) / 4^p.                                  */
 static void build_stencils(int R, Sten* S) {
   int m[2 * MAXR + 3];
-  double w[2 * MAXR + 3];
+  real w[2 * MAXR + 3];
   S->R = R;
   for (int j = 0; j <= 2 * R; j++) m[j] = j - R; /* centred nodes -R..R */
   lagrange_weights(2 * R + 1, m, 1, w);
@@ -159,10 +168,10 @@ static void build_stencils(int R, Sten* S) {
   lagrange_weights(2 * R + 1, m, 1, w);
   for (int j = 0; j <= 2 * R; j++) S->up[j] = w[j];
   const int p = R + 1;
-  double binom = 1.0, scale = 1.0; /* C(2p, p + j), 4^-p */
+  real binom = 1.0, scale = 1.0; /* C(2p, p + j), 4^-p */
   for (int k = 0; k < p; k++) scale /= 4.0;
   for (int j = p; j >= 0; j--) {
-    if (j < p) binom = binom * (double)(p + j + 1) / (double)(p - j); /* C(2p,p+j) from C(2p,p+j+1) */
+    if (j < p) binom = binom * (real)(p + j + 1) / (real)(p - j); /* C(2p,p+j) from C(2p,p+j+1) */
     S->ko[j] = ((j + 1) % 2 == 0 ? 1.0 : -1.0) * binom * scale;
   }
 }
@@ -170,7 +179,7 @@ static void build_stencils(int R, Sten* S) {
 static int grid_setup(const oracle_params* p, Grid* G) {
   if (oracle_check(p)) return -1;
   G->p = *p;
-  const double PI = M_PI;
+  const real PI = (real)3.14159265358979323846264338327950288L;
   if (p->coord == 1) { /* SinhCylindrical: (xx0, phi, xx2) */
     G->xxmin[0] = 0.0; G->xxmax[0] = 1.0;
     G->xxmin[1] = -PI; G->xxmax[1] = PI;
@@ -182,7 +191,7 @@ static int grid_setup(const oracle_params* p, Grid* G) {
   }
   for (int d = 0; d < 3; d++) {
     G->n[d] = p->N[d] + 2 * p->ng;
-    G->dxx[d] = (G->xxmax[d] - G->xxmin[d]) / (double)p->N[d];
+    G->dxx[d] = (G->xxmax[d] - G->xxmin[d]) / (real)p->N[d];
   }
   G->st[0] = 1;
   G->st[1] = G->n[0];
@@ -192,11 +201,11 @@ static int grid_setup(const oracle_params* p, Grid* G) {
   return 0;
 }
 
-static double xx_of(const Grid* G, int d, int j) {
-  return G->xxmin[d] + ((double)(j - G->p.ng) + 0.5) * G->dxx[d];
+static real xx_of(const Grid* G, int d, int j) {
+  return G->xxmin[d] + ((real)(j - G->p.ng) + 0.5) * G->dxx[d];
 }
 
-double oracle_xx(const oracle_params* p, int d, int j) {
+real oracle_xx(const oracle_params* p, int d, int j) {
   Grid G;
   if (grid_setup(p, &G)) return NAN;
   return xx_of(&G, d, j);
@@ -205,12 +214,12 @@ double oracle_xx(const oracle_params* p, int d, int j) {
 /* ------------------------------------------------------------------------ */
 /* Radial map of Eq. 22: x' = A sinh(x/w)/sinh(1/w), with its first three
  * derivatives; the uniform map x' = A x for plain Spherical.               */
-static void radial_map(int linear, double A, double w, double x, double out[4]) {
+static void radial_map(int linear, real A, real w, real x, real out[4]) {
   if (linear) {
     out[0] = A * x; out[1] = A; out[2] = 0.0; out[3] = 0.0;
     return;
   }
-  const double s = sinh(1.0 / w);
+  const real s = sinh(1.0 / w);
   out[0] = A * sinh(x / w) / s;
   out[1] = A * cosh(x / w) / (w * s);
   out[2] = A * sinh(x / w) / (w * w * s);
@@ -218,7 +227,7 @@ static void radial_map(int linear, double A, double w, double x, double out[4]) 
 }
 
 /* inverse of radial_map's value */
-static double radial_map_inv(int linear, double A, double w, double r) {
+static real radial_map_inv(int linear, real A, real w, real r) {
   if (linear) return r / A;
   return w * asinh(r * sinh(1.0 / w) / A);
 }
@@ -228,22 +237,22 @@ static double radial_map_inv(int linear, double A, double w, double r) {
  * second logical derivatives: dS[i][k] = d_k S_i, ddS[i][k][l] = d_k d_l S_i.
  *   (Sinh)Spherical: gammahat = diag(r'^2, r^2, r^2 sin^2 theta)
  *   SinhCylindrical: gammahat = diag(rho'^2, rho^2, z'^2)                  */
-static void scale_factors(const Grid* G, const double xx[3], double S[3], double dS[3][3],
-                          double ddS[3][3][3]) {
-  memset(dS, 0, 9 * sizeof(double));
-  memset(ddS, 0, 27 * sizeof(double));
+static void scale_factors(const Grid* G, const real xx[3], real S[3], real dS[3][3],
+                          real ddS[3][3][3]) {
+  memset(dS, 0, 9 * sizeof(real));
+  memset(ddS, 0, 27 * sizeof(real));
   const oracle_params* p = &G->p;
   if (p->coord == 1) {
-    double R[4], Z[4];
+    real R[4], Z[4];
     radial_map(0, p->ampl[0], p->sinhw[0], xx[0], R);
     radial_map(0, p->ampl[2], p->sinhw[2], xx[2], Z);
     S[0] = R[1]; S[1] = R[0]; S[2] = Z[1];
     dS[0][0] = R[2]; dS[1][0] = R[1]; dS[2][2] = Z[2];
     ddS[0][0][0] = R[3]; ddS[1][0][0] = R[2]; ddS[2][2][2] = Z[3];
   } else {
-    double R[4];
+    real R[4];
     radial_map(p->coord == 2, p->ampl[0], p->sinhw[0], xx[0], R);
-    const double st = sin(xx[1]), ct = cos(xx[1]);
+    const real st = sin(xx[1]), ct = cos(xx[1]);
     S[0] = R[1]; S[1] = R[0]; S[2] = R[0] * st;
     dS[0][0] = R[2];
     dS[1][0] = R[1];
@@ -256,11 +265,11 @@ static void scale_factors(const Grid* G, const double xx[3], double S[3], double
   }
 }
 
-void oracle_scalefactors(const oracle_params* p, const double xx[3], double S[3], double dS[9],
-                         double ddS[27]) {
+void oracle_scalefactors(const oracle_params* p, const real xx[3], real S[3], real dS[9],
+                         real ddS[27]) {
   Grid G;
   if (grid_setup(p, &G)) return;
-  double a[3][3], b[3][3][3];
+  real a[3][3], b[3][3][3];
   scale_factors(&G, xx, S, a, b);
   memcpy(dS, a, sizeof a);
   memcpy(ddS, b, sizeof b);
@@ -268,11 +277,11 @@ void oracle_scalefactors(const oracle_params* p, const double xx[3], double S[3]
 
 /* Cartesian position (Eqs. 18-20 for the spherical family; x = rho cos phi,
  * y = rho sin phi, z for the cylindrical one).                              */
-static void xx_to_cart(const Grid* G, const double xx[3], double x[3]) {
+static void xx_to_cart(const Grid* G, const real xx[3], real x[3]) {
   const oracle_params* p = &G->p;
-  double R[4];
+  real R[4];
   if (p->coord == 1) {
-    double Z[4];
+    real Z[4];
     radial_map(0, p->ampl[0], p->sinhw[0], xx[0], R);
     radial_map(0, p->ampl[2], p->sinhw[2], xx[2], Z);
     x[0] = R[0] * cos(xx[1]);
@@ -286,27 +295,27 @@ static void xx_to_cart(const Grid* G, const double xx[3], double x[3]) {
   }
 }
 
-void oracle_xx_to_cart(const oracle_params* p, const double xx[3], double x[3]) {
+void oracle_xx_to_cart(const oracle_params* p, const real xx[3], real x[3]) {
   Grid G;
   if (grid_setup(p, &G)) return;
   xx_to_cart(&G, xx, x);
 }
 
 /* Jacobian J[i][a] = d x^a / d xx^i of the Cartesian map above. */
-static void jacobian(const Grid* G, const double xx[3], double J[3][3]) {
+static void jacobian(const Grid* G, const real xx[3], real J[3][3]) {
   const oracle_params* p = &G->p;
-  double R[4];
+  real R[4];
   if (p->coord == 1) {
-    double Z[4];
+    real Z[4];
     radial_map(0, p->ampl[0], p->sinhw[0], xx[0], R);
     radial_map(0, p->ampl[2], p->sinhw[2], xx[2], Z);
-    const double cp = cos(xx[1]), sp = sin(xx[1]);
+    const real cp = cos(xx[1]), sp = sin(xx[1]);
     J[0][0] = R[1] * cp;  J[0][1] = R[1] * sp; J[0][2] = 0.0;
     J[1][0] = -R[0] * sp; J[1][1] = R[0] * cp; J[1][2] = 0.0;
     J[2][0] = 0.0;        J[2][1] = 0.0;       J[2][2] = Z[1];
   } else {
     radial_map(p->coord == 2, p->ampl[0], p->sinhw[0], xx[0], R);
-    const double st = sin(xx[1]), ct = cos(xx[1]), sp = sin(xx[2]), cp = cos(xx[2]);
+    const real st = sin(xx[1]), ct = cos(xx[1]), sp = sin(xx[2]), cp = cos(xx[2]);
     J[0][0] = R[1] * st * cp; J[0][1] = R[1] * st * sp; J[0][2] = R[1] * ct;
     J[1][0] = R[0] * ct * cp; J[1][1] = R[0] * ct * sp; J[1][2] = -R[0] * st;
     J[2][0] = -R[0] * st * sp; J[2][1] = R[0] * st * cp; J[2][2] = 0.0;
@@ -315,19 +324,19 @@ static void jacobian(const Grid* G, const double xx[3], double J[3][3]) {
 
 /* Rescaled basis e~_(i) = e^_(i) / S_(i) with e^_(i) = d x / d xx^i (Sec. 2.2),
  * e[i][a] = Cartesian component a of e~_(i).                                */
-static void rescaled_basis(const Grid* G, const double xx[3], double e[3][3]) {
-  double S[3], dS[3][3], ddS[3][3][3];
+static void rescaled_basis(const Grid* G, const real xx[3], real e[3][3]) {
+  real S[3], dS[3][3], ddS[3][3][3];
   scale_factors(G, xx, S, dS, ddS);
-  double J[3][3];
+  real J[3][3];
   jacobian(G, xx, J);
   for (int i = 0; i < 3; i++)
     for (int a = 0; a < 3; a++) e[i][a] = J[i][a] / S[i];
 }
 
-void oracle_rescaled_basis(const oracle_params* p, const double xx[3], double ebasis[9]) {
+void oracle_rescaled_basis(const oracle_params* p, const real xx[3], real ebasis[9]) {
   Grid G;
   if (grid_setup(p, &G)) return;
-  double e[3][3];
+  real e[3][3];
   rescaled_basis(&G, xx, e);
   memcpy(ebasis, e, sizeof e);
 }
@@ -336,18 +345,18 @@ void oracle_rescaled_basis(const oracle_params* p, const double xx[3], double eb
 /* CFL time step. Reading: dt = CFL * min over interior points and directions
  * of S_i dxx^i (the proper grid spacing); with CFL = 0.5 (Sec. 4.1) this
  * reproduces the 8428 iterations quoted for 7.5 M in Sec. 4.2.1.            */
-double oracle_dt(const oracle_params* p) {
+real oracle_dt(const oracle_params* p) {
   Grid G;
   if (grid_setup(p, &G)) return NAN;
-  double dsmin = INFINITY;
+  real dsmin = INFINITY;
   for (int i2 = p->ng; i2 < p->ng + p->N[2]; i2++)
     for (int i1 = p->ng; i1 < p->ng + p->N[1]; i1++)
       for (int i0 = p->ng; i0 < p->ng + p->N[0]; i0++) {
-        double xx[3] = {xx_of(&G, 0, i0), xx_of(&G, 1, i1), xx_of(&G, 2, i2)};
-        double S[3], dS[3][3], ddS[3][3][3];
+        real xx[3] = {xx_of(&G, 0, i0), xx_of(&G, 1, i1), xx_of(&G, 2, i2)};
+        real S[3], dS[3][3], ddS[3][3][3];
         scale_factors(&G, xx, S, dS, ddS);
         for (int d = 0; d < 3; d++) {
-          double ds = fabs(S[d]) * G.dxx[d];
+          real ds = fabs(S[d]) * G.dxx[d];
           if (ds < dsmin) dsmin = ds;
         }
       }
@@ -370,8 +379,8 @@ static int is_interior(const Grid* G, int i0, int i1, int i2) {
          i2 < ng + G->p.N[2];
 }
 
-static int nearest_cell(const Grid* G, int d, double xx) {
-  return (int)floor((xx - G->xxmin[d]) / G->dxx[d] + (double)G->p.ng);
+static int nearest_cell(const Grid* G, int d, real xx) {
+  return (int)floor((xx - G->xxmin[d]) / G->dxx[d] + (real)G->p.ng);
 }
 
 static int wrap_periodic(const Grid* G, int d, int j) {
@@ -382,18 +391,18 @@ static int wrap_periodic(const Grid* G, int d, int j) {
 }
 
 /* Cartesian -> canonical logical coordinates -> nearest cell indices. */
-static void cart_to_cell(const Grid* G, const double x[3], int c[3]) {
+static void cart_to_cell(const Grid* G, const real x[3], int c[3]) {
   const oracle_params* p = &G->p;
   if (p->coord == 1) {
-    const double rho = sqrt(x[0] * x[0] + x[1] * x[1]);
-    const double phi = atan2(x[1], x[0]);
+    const real rho = sqrt(x[0] * x[0] + x[1] * x[1]);
+    const real phi = atan2(x[1], x[0]);
     c[0] = nearest_cell(G, 0, radial_map_inv(0, p->ampl[0], p->sinhw[0], rho));
     c[1] = wrap_periodic(G, 1, nearest_cell(G, 1, phi));
     c[2] = nearest_cell(G, 2, radial_map_inv(0, p->ampl[2], p->sinhw[2], x[2]));
   } else {
-    const double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
-    const double th = acos(x[2] / r);
-    const double phi = atan2(x[1], x[0]);
+    const real r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    const real th = acos(x[2] / r);
+    const real phi = atan2(x[1], x[0]);
     c[0] = nearest_cell(G, 0, radial_map_inv(p->coord == 2, p->ampl[0], p->sinhw[0], r));
     c[1] = nearest_cell(G, 1, th);
     c[2] = wrap_periodic(G, 2, nearest_cell(G, 2, phi));
@@ -409,8 +418,8 @@ static int build_maps(const Grid* G, int* kind, int* src, int* parity) {
         src[q] = (int)q;
         parity[q] = 0;
         if (is_interior(G, i0, i1, i2)) { kind[q] = 0; continue; }
-        double xx[3] = {xx_of(G, 0, i0), xx_of(G, 1, i1), xx_of(G, 2, i2)};
-        double x[3];
+        real xx[3] = {xx_of(G, 0, i0), xx_of(G, 1, i1), xx_of(G, 2, i2)};
+        real x[3];
         xx_to_cart(G, xx, x);
         int c[3];
         cart_to_cell(G, x, c);
@@ -419,12 +428,12 @@ static int build_maps(const Grid* G, int* kind, int* src, int* parity) {
         if (c[0] < 0 || c[0] >= G->n[0] || c[1] < 0 || c[1] >= G->n[1] || c[2] < 0 ||
             c[2] >= G->n[2]) { bad = 1; kind[q] = -1; continue; }
         src[q] = (int)flat(G, c[0], c[1], c[2]);
-        double xs[3] = {xx_of(G, 0, c[0]), xx_of(G, 1, c[1]), xx_of(G, 2, c[2])};
-        double ed[3][3], es[3][3];
+        real xs[3] = {xx_of(G, 0, c[0]), xx_of(G, 1, c[1]), xx_of(G, 2, c[2])};
+        real ed[3][3], es[3][3];
         rescaled_basis(G, xx, ed);
         rescaled_basis(G, xs, es);
         for (int d = 0; d < 3; d++) {
-          const double dot = ed[d][0] * es[d][0] + ed[d][1] * es[d][1] + ed[d][2] * es[d][2];
+          const real dot = ed[d][0] * es[d][0] + ed[d][1] * es[d][1] + ed[d][2] * es[d][2];
           if (fabs(fabs(dot) - 1.0) > 1e-10) bad = 1;
           if (dot < 0) parity[q] |= 1 << d;
         }
@@ -445,8 +454,8 @@ int oracle_bc_maps(const oracle_params* p, int* kind, int* src, int* parity) {
 }
 
 /* sign picked up by gridfunction g under the per-direction parities */
-static double gf_sign(int g, int parity) {
-  double s = 1.0;
+static real gf_sign(int g, int parity) {
+  real s = 1.0;
   if (GF_TYPE[g] >= 1 && (parity >> GF_I[g] & 1)) s = -s;
   if (GF_TYPE[g] == 2 && (parity >> GF_J[g] & 1)) s = -s;
   return s;
@@ -463,7 +472,7 @@ static double gf_sign(int g, int parity) {
  * inner ghosts; outer = 0 (radiation boundary inside the time integrator):
  * the inner copies only.                                                    */
 static void apply_bcs_with_maps(const Grid* G, const int* kind, const int* src,
-                                const int* parity, double* y, int outer) {
+                                const int* parity, real* y, int outer) {
   const int ng = G->p.ng;
   int lo[3], hi[3]; /* current face ranges, [lo, hi) */
   for (int d = 0; d < 3; d++) { lo[d] = ng; hi[d] = ng + G->p.N[d]; }
@@ -483,7 +492,7 @@ static void apply_bcs_with_maps(const Grid* G, const int* kind, const int* src,
               const long long q = flat(G, i0, i1, i2);
               if (kind[q] != 1) continue;
               for (int g = 0; g < NGF; g++) {
-                double* f = y + g * G->np + q;
+                real* f = y + g * G->np + q;
                 f[0] = 3.0 * f[step] - 3.0 * f[2 * step] + f[3 * step];
               }
             }
@@ -498,7 +507,7 @@ static void apply_bcs_with_maps(const Grid* G, const int* kind, const int* src,
         y[g * G->np + q] = gf_sign(g, parity[q]) * y[g * G->np + src[q]];
 }
 
-int oracle_apply_bcs(const oracle_params* p, double* y) {
+int oracle_apply_bcs(const oracle_params* p, real* y) {
   Grid G;
   if (grid_setup(p, &G)) return -1;
   int* kind = (int*)malloc(sizeof(int) * G.np);
@@ -516,20 +525,20 @@ int oracle_apply_bcs(const oracle_params* p, double* y) {
  * psi = 1 + sum m_n / (2 |x - x_n|), gamma_ij = psi^4 delta_ij, so
  * W = psi^-2, eps = Abar = K = Lambdabar = 0; precollapsed lapse psi^-2
  * (or 1), zero shift and B. Interior points, then the ghost fill.           */
-int oracle_id_brill_lindquist(const oracle_params* p, int np, const double* m,
-                              const double* pos, int lapse_kind, double* y) {
+int oracle_id_brill_lindquist(const oracle_params* p, int np, const real* m,
+                              const real* pos, int lapse_kind, real* y) {
   Grid G;
   if (grid_setup(p, &G)) return -1;
-  memset(y, 0, sizeof(double) * NGF * G.np);
+  memset(y, 0, sizeof(real) * NGF * G.np);
   for (int i2 = p->ng; i2 < p->ng + p->N[2]; i2++)
     for (int i1 = p->ng; i1 < p->ng + p->N[1]; i1++)
       for (int i0 = p->ng; i0 < p->ng + p->N[0]; i0++) {
-        double xx[3] = {xx_of(&G, 0, i0), xx_of(&G, 1, i1), xx_of(&G, 2, i2)};
-        double x[3];
+        real xx[3] = {xx_of(&G, 0, i0), xx_of(&G, 1, i1), xx_of(&G, 2, i2)};
+        real x[3];
         xx_to_cart(&G, xx, x);
-        double psi = 1.0;
+        real psi = 1.0;
         for (int n = 0; n < np; n++) {
-          const double dx = x[0] - pos[3 * n], dy = x[1] - pos[3 * n + 1],
+          const real dx = x[0] - pos[3 * n], dy = x[1] - pos[3 * n + 1],
                        dz = x[2] - pos[3 * n + 2];
           psi += m[n] / (2.0 * sqrt(dx * dx + dy * dy + dz * dz));
         }
@@ -549,43 +558,43 @@ int oracle_id_brill_lindquist(const oracle_params* p, int np, const double* m,
  *   D2 f = [-f-2 + 16 f-1 - 30 f0 + 16 f1 - f2] / 12h^2
  *   U+ f = [-3 f-1 - 10 f0 + 18 f1 - 6 f2 + f3] / 12h
  *   U- f = [3 f1 + 10 f0 - 18 f-1 + 6 f-2 - f-3] / 12h.                     */
-static double fd_d1(const Sten* S, const double* f, long long s, double h) {
-  double a = 0.0;
+static real fd_d1(const Sten* S, const real* f, long long s, real h) {
+  real a = 0.0;
   for (int j = S->R; j >= 1; j--) a += S->d1[j] * (f[j * s] - f[-j * s]);
   return a / h;
 }
-static double fd_d2(const Sten* S, const double* f, long long s, double h) {
-  double a = 0.0;
+static real fd_d2(const Sten* S, const real* f, long long s, real h) {
+  real a = 0.0;
   for (int j = S->R; j >= 1; j--) a += S->d2[j] * ((f[j * s] - f[0]) + (f[-j * s] - f[0]));
   return a / (h * h);
 }
 /* D_k D_l f (k != l): the tensor product of two centred first differences */
-static double fd_d11(const Sten* S, const double* f, long long sk, long long sl, double hk, double hl) {
-  double a = 0.0;
+static real fd_d11(const Sten* S, const real* f, long long sk, long long sl, real hk, real hl) {
+  real a = 0.0;
   for (int j = S->R; j >= 1; j--)
     a += S->d1[j] * (fd_d1(S, f + j * sk, sl, hl) - fd_d1(S, f - j * sk, sl, hl));
   return a / hk;
 }
-static double fd_up(const Sten* S, const double* f, long long s, double h) {
-  double a = 0.0;
+static real fd_up(const Sten* S, const real* f, long long s, real h) {
+  real a = 0.0;
   for (int m = S->R + 1; m >= -(S->R - 1); m--)
     if (m != 1) a += S->up[m + S->R - 1] * (f[m * s] - f[s]);
   return a / h;
 }
-static double fd_dn(const Sten* S, const double* f, long long s, double h) {
+static real fd_dn(const Sten* S, const real* f, long long s, real h) {
   return -fd_up(S, f, -s, h);
 }
-static double fd_ko(const Sten* S, const double* f, long long s, double h) {
-  double a = 0.0;
+static real fd_ko(const Sten* S, const real* f, long long s, real h) {
+  real a = 0.0;
   for (int j = S->R + 1; j >= 1; j--) a += S->ko[j] * ((f[j * s] - f[0]) + (f[-j * s] - f[0]));
   return a / h;
 }
 
-int oracle_fd_point(const oracle_params* p, const double* f, long long idx, double d1[3],
-                    double d2[9], double uplus[3], double uminus[3]) {
+int oracle_fd_point(const oracle_params* p, const real* f, long long idx, real d1[3],
+                    real d2[9], real uplus[3], real uminus[3]) {
   Grid G;
   if (grid_setup(p, &G)) return -1;
-  const double* c = f + idx;
+  const real* c = f + idx;
   for (int k = 0; k < 3; k++) {
     d1[k] = fd_d1(&G.fd, c, G.st[k], G.dxx[k]);
     uplus[k] = fd_up(&G.fd, c, G.st[k], G.dxx[k]);
@@ -597,7 +606,7 @@ int oracle_fd_point(const oracle_params* p, const double* f, long long idx, doub
   return 0;
 }
 
-int oracle_ko_point(const oracle_params* p, const double* f, long long idx, double ko[3]) {
+int oracle_ko_point(const oracle_params* p, const real* f, long long idx, real ko[3]) {
   Grid G;
   if (grid_setup(p, &G)) return -1;
   for (int k = 0; k < 3; k++) ko[k] = fd_ko(&G.fd, f + idx, G.st[k], G.dxx[k]);
@@ -606,8 +615,8 @@ int oracle_ko_point(const oracle_params* p, const double* f, long long idx, doub
 
 /* ------------------------------------------------------------------------ */
 /* general symmetric 3x3 inverse */
-static void inverse3(const double a[3][3], double inv[3][3]) {
-  const double det = a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) -
+static void inverse3(const real a[3][3], real inv[3][3]) {
+  const real det = a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) -
                      a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
                      a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
   inv[0][0] = (a[1][1] * a[2][2] - a[1][2] * a[2][1]) / det;
@@ -623,21 +632,21 @@ static void inverse3(const double a[3][3], double inv[3][3]) {
 
 /* Everything the RHS, the Ricci tensor and the constraints need at a point. */
 typedef struct {
-  double rhs[NGF];
-  double ricci_resc[6];
-  double H, M_resc[3], C_resc[3];
+  real rhs[NGF];
+  real ricci_resc[6];
+  real H, M_resc[3], C_resc[3];
 } PointOut;
 
-static void bssn_point(const Grid* G, double eta, const double* y, int i0, int i1, int i2,
+static void bssn_point(const Grid* G, real eta, const real* y, int i0, int i1, int i2,
                        PointOut* out) {
   const long long q = flat(G, i0, i1, i2);
   const long long np = G->np;
-  const double xx[3] = {xx_of(G, 0, i0), xx_of(G, 1, i1), xx_of(G, 2, i2)};
+  const real xx[3] = {xx_of(G, 0, i0), xx_of(G, 1, i1), xx_of(G, 2, i2)};
 
   /* ---- 1. finite differences of the rescaled evolved variables --------- */
-  double v[NGF], d1[NGF][3], d2[NGF][3][3], up[NGF][3];
+  real v[NGF], d1[NGF][3], d2[NGF][3][3], up[NGF][3];
   for (int g = 0; g < NGF; g++) {
-    const double* f = y + g * np + q;
+    const real* f = y + g * np + q;
     v[g] = f[0];
     for (int k = 0; k < 3; k++) d1[g][k] = fd_d1(&G->fd, f, G->st[k], G->dxx[k]);
     for (int k = 0; k < 3; k++)
@@ -650,16 +659,16 @@ static void bssn_point(const Grid* G, double eta, const double* y, int i0, int i
   /* Reading: the upwind side is chosen by the sign of the shift component
    * (vet^k > 0: stencil shifted toward +k, else toward -k).                 */
   for (int g = 0; g < NGF; g++) {
-    const double* f = y + g * np + q;
+    const real* f = y + g * np + q;
     for (int k = 0; k < 3; k++)
       up[g][k] = v[VETU0 + k] > 0.0 ? fd_up(&G->fd, f, G->st[k], G->dxx[k])
                                     : fd_dn(&G->fd, f, G->st[k], G->dxx[k]);
   }
 
   /* ---- 2. reference metric (analytic): gammahat_ij = S_i^2 delta_ij ---- */
-  double S[3], dS[3][3], ddS[3][3][3];
+  real S[3], dS[3][3], ddS[3][3][3];
   scale_factors(G, xx, S, dS, ddS);
-  double gh[3][3] = {{0}}, dgh[3][3][3] = {{{0}}}, ddgh[3][3][3][3] = {{{{0}}}};
+  real gh[3][3] = {{0}}, dgh[3][3][3] = {{{0}}}, ddgh[3][3][3][3] = {{{{0}}}};
   for (int i = 0; i < 3; i++) {
     gh[i][i] = S[i] * S[i];
     for (int k = 0; k < 3; k++) {
@@ -668,16 +677,16 @@ static void bssn_point(const Grid* G, double eta, const double* y, int i0, int i
         ddgh[i][i][k][l] = 2.0 * (dS[i][l] * dS[i][k] + S[i] * ddS[i][k][l]);
     }
   }
-  double ghUU[3][3];
+  real ghUU[3][3];
   inverse3(gh, ghUU);
   /* Christoffel symbols of gammahat and their derivatives:
    * Gh[i][j][k] = Gammahat^i_jk, dGh[i][j][k][l] = d_l Gammahat^i_jk       */
-  double Gh[3][3][3], dGh[3][3][3][3];
-  double dghUU[3][3][3]; /* d_l gammahat^ij */
+  real Gh[3][3][3], dGh[3][3][3][3];
+  real dghUU[3][3][3]; /* d_l gammahat^ij */
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++)
       for (int l = 0; l < 3; l++) {
-        double s = 0.0;
+        real s = 0.0;
         for (int a = 0; a < 3; a++)
           for (int b = 0; b < 3; b++) s -= ghUU[i][a] * dgh[a][b][l] * ghUU[b][j];
         dghUU[i][j][l] = s;
@@ -685,12 +694,12 @@ static void bssn_point(const Grid* G, double eta, const double* y, int i0, int i
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++)
       for (int k = 0; k < 3; k++) {
-        double s = 0.0;
+        real s = 0.0;
         for (int m = 0; m < 3; m++)
           s += 0.5 * ghUU[i][m] * (dgh[m][k][j] + dgh[m][j][k] - dgh[j][k][m]);
         Gh[i][j][k] = s;
         for (int l = 0; l < 3; l++) {
-          double t = 0.0;
+          real t = 0.0;
           for (int m = 0; m < 3; m++)
             t += 0.5 * dghUU[i][m][l] * (dgh[m][k][j] + dgh[m][j][k] - dgh[j][k][m]) +
                  0.5 * ghUU[i][m] * (ddgh[m][k][j][l] + ddgh[m][j][k][l] - ddgh[j][k][m][l]);
@@ -701,8 +710,8 @@ static void bssn_point(const Grid* G, double eta, const double* y, int i0, int i
   /* ---- 3. unrescale (Sec. 2.2): eps_ij = h_ij S_i S_j, Abar likewise,
    *      Lambdabar^i = lambda^i / S_i, beta^i = vet^i / S_i, B^i = bet^i / S_i,
    *      derivatives by the product rule with analytic derivatives of S.   */
-  double ReDD[3][3], dReDD[3][3][3], ddReDD[3][3][3][3];
-  double ReU[3], dReU[3][3], ddReU[3][3][3];
+  real ReDD[3][3], dReDD[3][3][3], ddReDD[3][3][3][3];
+  real ReU[3], dReU[3][3], ddReU[3][3][3];
   for (int i = 0; i < 3; i++) {
     ReU[i] = 1.0 / S[i];
     for (int k = 0; k < 3; k++) {
@@ -721,8 +730,8 @@ static void bssn_point(const Grid* G, double eta, const double* y, int i0, int i
       }
     }
   }
-  double eps[3][3], deps[3][3][3], ddeps[3][3][3][3], deps_up[3][3][3];
-  double Abar[3][3], dAbar[3][3][3], dAbar_up[3][3][3];
+  real eps[3][3], deps[3][3][3], ddeps[3][3][3][3], deps_up[3][3][3];
+  real Abar[3][3], dAbar[3][3][3], dAbar_up[3][3][3];
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++) {
       const int gh_ = HDD00 + SYM[i][j], ga = ADD00 + SYM[i][j];
@@ -738,9 +747,9 @@ static void bssn_point(const Grid* G, double eta, const double* y, int i0, int i
                               d1[gh_][l] * dReDD[i][j][k] + v[gh_] * ddReDD[i][j][k][l];
       }
     }
-  double Lam[3], dLam[3][3], dLam_up[3][3];
-  double beta[3], dbeta[3][3], ddbeta[3][3][3], dbeta_up[3][3];
-  double B[3], dB_up[3][3];
+  real Lam[3], dLam[3][3], dLam_up[3][3];
+  real beta[3], dbeta[3][3], ddbeta[3][3][3], dbeta_up[3][3];
+  real B[3], dB_up[3][3];
   for (int i = 0; i < 3; i++) {
     const int gl = LAMU0 + i, gv = VETU0 + i, gb = BETU0 + i;
     Lam[i] = v[gl] * ReU[i];
@@ -757,8 +766,8 @@ static void bssn_point(const Grid* G, double eta, const double* y, int i0, int i
                           d1[gv][l] * dReU[i][k] + v[gv] * ddReU[i][k][l];
     }
   }
-  const double W = v[CF], K = v[TRK], alpha = v[ALPHA];
-  double dW[3], ddW[3][3], dW_up[3], dK[3], dK_up[3], dalpha[3], ddalpha[3][3], dalpha_up[3];
+  const real W = v[CF], K = v[TRK], alpha = v[ALPHA];
+  real dW[3], ddW[3][3], dW_up[3], dK[3], dK_up[3], dalpha[3], ddalpha[3][3], dalpha_up[3];
   for (int k = 0; k < 3; k++) {
     dW[k] = d1[CF][k]; dW_up[k] = up[CF][k];
     dK[k] = d1[TRK][k]; dK_up[k] = up[TRK][k];
@@ -767,7 +776,7 @@ static void bssn_point(const Grid* G, double eta, const double* y, int i0, int i
   }
 
   /* ---- 4. conformal metric, Eq. 3: gammabar_ij = gammahat_ij + eps_ij --- */
-  double gb[3][3], gbUU[3][3], dgb[3][3][3], ddgb[3][3][3][3];
+  real gb[3][3], gbUU[3][3], dgb[3][3][3], ddgb[3][3][3][3];
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++) {
       gb[i][j] = gh[i][j] + eps[i][j];
@@ -783,26 +792,26 @@ static void bssn_point(const Grid* G, double eta, const double* y, int i0, int i
    *   Delta^k_ij = 1/2 gammabar^kl (Dhat_i eps_lj + Dhat_j eps_il - Dhat_l eps_ij),
    * Dhat_k eps_ij = d_k eps_ij - Gammahat^m_ki eps_mj - Gammahat^m_kj eps_im
    * (Dhat gammahat = 0), which vanishes exactly when eps does.             */
-  double Dhat_eps[3][3][3]; /* [i][j][k] = Dhat_k eps_ij */
+  real Dhat_eps[3][3][3]; /* [i][j][k] = Dhat_k eps_ij */
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++)
       for (int k = 0; k < 3; k++) {
-        double s = deps[i][j][k];
+        real s = deps[i][j][k];
         for (int m = 0; m < 3; m++) s -= Gh[m][k][i] * eps[m][j] + Gh[m][k][j] * eps[i][m];
         Dhat_eps[i][j][k] = s;
       }
-  double DeltaUDD[3][3][3], DeltaU[3], DeltaDDD[3][3][3], Gb[3][3][3];
+  real DeltaUDD[3][3][3], DeltaU[3], DeltaDDD[3][3][3], Gb[3][3][3];
   for (int k = 0; k < 3; k++)
     for (int i = 0; i < 3; i++)
       for (int j = 0; j < 3; j++) {
-        double s = 0.0;
+        real s = 0.0;
         for (int l = 0; l < 3; l++)
           s += 0.5 * gbUU[k][l] * (Dhat_eps[l][j][i] + Dhat_eps[i][l][j] - Dhat_eps[i][j][l]);
         DeltaUDD[k][i][j] = s;
         Gb[k][i][j] = Gh[k][i][j] + s; /* Gammabar = Gammahat + Delta (Eq. 4) */
       }
   for (int k = 0; k < 3; k++) {
-    double s = 0.0;
+    real s = 0.0;
     for (int i = 0; i < 3; i++)
       for (int j = 0; j < 3; j++) s += gbUU[i][j] * DeltaUDD[k][i][j];
     DeltaU[k] = s; /* Eq. 5 */
@@ -810,39 +819,39 @@ static void bssn_point(const Grid* G, double eta, const double* y, int i0, int i
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++)
       for (int k = 0; k < 3; k++) {
-        double s = 0.0;
+        real s = 0.0;
         for (int l = 0; l < 3; l++) s += gb[i][l] * DeltaUDD[l][j][k];
         DeltaDDD[i][j][k] = s; /* Delta_ijk = gammabar_il Delta^l_jk */
       }
 
   /* ---- 6. conformal Ricci tensor, Eq. 12 ------------------------------- */
   /* d_k (Dhat_l eps_ij) and Dhat_k Dhat_l eps_ij (= Dhat_k Dhat_l gammabar_ij) */
-  double DDeps[3][3][3][3]; /* [i][j][l][k] = Dhat_k Dhat_l eps_ij */
+  real DDeps[3][3][3][3]; /* [i][j][l][k] = Dhat_k Dhat_l eps_ij */
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++)
       for (int l = 0; l < 3; l++)
         for (int k = 0; k < 3; k++) {
-          double dD = ddeps[i][j][l][k];
+          real dD = ddeps[i][j][l][k];
           for (int m = 0; m < 3; m++)
             dD -= dGh[m][l][i][k] * eps[m][j] + Gh[m][l][i] * deps[m][j][k] +
                   dGh[m][l][j][k] * eps[i][m] + Gh[m][l][j] * deps[i][m][k];
-          double s = dD;
+          real s = dD;
           for (int m = 0; m < 3; m++)
             s -= Gh[m][k][l] * Dhat_eps[i][j][m] + Gh[m][k][i] * Dhat_eps[m][j][l] +
                  Gh[m][k][j] * Dhat_eps[i][m][l];
           DDeps[i][j][l][k] = s;
         }
-  double DhatLam[3][3]; /* [k][j] = Dhat_j Lambdabar^k */
+  real DhatLam[3][3]; /* [k][j] = Dhat_j Lambdabar^k */
   for (int k = 0; k < 3; k++)
     for (int j = 0; j < 3; j++) {
-      double s = dLam[k][j];
+      real s = dLam[k][j];
       for (int m = 0; m < 3; m++) s += Gh[k][j][m] * Lam[m];
       DhatLam[k][j] = s;
     }
-  double R[3][3];
+  real R[3][3];
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++) {
-      double s = 0.0;
+      real s = 0.0;
       for (int k = 0; k < 3; k++)
         for (int l = 0; l < 3; l++) s += -0.5 * gbUU[k][l] * DDeps[i][j][l][k];
       for (int k = 0; k < 3; k++)
@@ -858,55 +867,55 @@ static void bssn_point(const Grid* G, double eta, const double* y, int i0, int i
     }
 
   /* ---- 7. conformal factor: W = exp(-2 phi) (Sec. 2.1 after Eq. 2) ----- */
-  double phi_d[3], phi_dd[3][3];
+  real phi_d[3], phi_dd[3][3];
   for (int i = 0; i < 3; i++) phi_d[i] = -dW[i] / (2.0 * W);
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++) phi_dd[i][j] = -ddW[i][j] / (2.0 * W) + dW[i] * dW[j] / (2.0 * W * W);
-  const double em4phi = W * W; /* exp(-4 phi) */
+  const real em4phi = W * W; /* exp(-4 phi) */
 
   /* ---- 8. covariant derivatives and contractions ----------------------- */
-  double DbDb_alpha[3][3], DbDb_phi[3][3];
+  real DbDb_alpha[3][3], DbDb_phi[3][3];
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++) {
-      double a = ddalpha[i][j], b = phi_dd[i][j];
+      real a = ddalpha[i][j], b = phi_dd[i][j];
       for (int k = 0; k < 3; k++) { a -= Gb[k][i][j] * dalpha[k]; b -= Gb[k][i][j] * phi_d[k]; }
       DbDb_alpha[i][j] = a;
       DbDb_phi[i][j] = b;
     }
-  double Dbar_beta = 0.0; /* Dbar_k beta^k = d_k beta^k + Gammabar^k_km beta^m */
+  real Dbar_beta = 0.0; /* Dbar_k beta^k = d_k beta^k + Gammabar^k_km beta^m */
   for (int k = 0; k < 3; k++) {
     Dbar_beta += dbeta[k][k];
     for (int m = 0; m < 3; m++) Dbar_beta += Gb[k][k][m] * beta[m];
   }
-  double Dhat_betaU[3][3]; /* [i][j] = Dhat_j beta^i */
+  real Dhat_betaU[3][3]; /* [i][j] = Dhat_j beta^i */
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++) {
-      double s = dbeta[i][j];
+      real s = dbeta[i][j];
       for (int m = 0; m < 3; m++) s += Gh[i][j][m] * beta[m];
       Dhat_betaU[i][j] = s;
     }
-  double Dhat_betaD[3][3]; /* [i][j] = Dhat_i beta_j, beta_j = gammahat_jm beta^m */
+  real Dhat_betaD[3][3]; /* [i][j] = Dhat_i beta_j, beta_j = gammahat_jm beta^m */
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++) {
-      double s = 0.0;
+      real s = 0.0;
       for (int m = 0; m < 3; m++) s += gh[j][m] * Dhat_betaU[m][i];
       Dhat_betaD[i][j] = s;
     }
-  double AbarUD[3][3], AbarUU[3][3];
+  real AbarUD[3][3], AbarUU[3][3];
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++) {
-      double s = 0.0;
+      real s = 0.0;
       for (int k = 0; k < 3; k++) s += gbUU[i][k] * Abar[k][j];
       AbarUD[i][j] = s;
     }
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++) {
-      double s = 0.0;
+      real s = 0.0;
       for (int k = 0; k < 3; k++)
         for (int l = 0; l < 3; l++) s += gbUU[i][k] * gbUU[j][l] * Abar[k][l];
       AbarUU[i][j] = s;
     }
-  double trAbar = 0.0, AbarAbar = 0.0;
+  real trAbar = 0.0, AbarAbar = 0.0;
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++) {
       trAbar += gbUU[i][j] * Abar[i][j];
@@ -916,56 +925,56 @@ static void bssn_point(const Grid* G, double eta, const double* y, int i0, int i
   /* ---- 9. Eq. 7: d_perp eps_ij; d_t = d_perp + Lie_beta ----------------
    * Reading: beta_j in Eq. 7 is lowered with gammahat, so that
    * 2 Dhat_(i beta_j) = Lie_beta gammahat_ij.                              */
-  double rhs_eps[3][3];
+  real rhs_eps[3][3];
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++) {
-      const double dperp = 2.0 / 3.0 * gb[i][j] * (alpha * trAbar - Dbar_beta) +
+      const real dperp = (real)2 / 3 * gb[i][j] * (alpha * trAbar - Dbar_beta) +
                            Dhat_betaD[i][j] + Dhat_betaD[j][i] - 2.0 * alpha * Abar[i][j];
-      double lie = 0.0;
+      real lie = 0.0;
       for (int k = 0; k < 3; k++)
         lie += beta[k] * deps_up[i][j][k] + eps[k][j] * dbeta[k][i] + eps[i][k] * dbeta[k][j];
       rhs_eps[i][j] = dperp + lie;
     }
 
   /* ---- 10. Eq. 8: d_perp Abar_ij --------------------------------------- */
-  double X[3][3];
+  real X[3][3];
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++)
       X[i][j] = -2.0 * alpha * DbDb_phi[i][j] + 4.0 * alpha * phi_d[i] * phi_d[j] +
                 2.0 * (dalpha[i] * phi_d[j] + dalpha[j] * phi_d[i]) - DbDb_alpha[i][j] +
                 alpha * R[i][j];
-  double trX = 0.0;
+  real trX = 0.0;
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++) trX += gbUU[i][j] * X[i][j];
-  double rhs_Abar[3][3];
+  real rhs_Abar[3][3];
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++) {
-      const double XTF = X[i][j] - 1.0 / 3.0 * gb[i][j] * trX;
-      double AA = 0.0;
+      const real XTF = X[i][j] - (real)1 / 3 * gb[i][j] * trX;
+      real AA = 0.0;
       for (int k = 0; k < 3; k++) AA += Abar[i][k] * AbarUD[k][j];
-      const double dperp = -2.0 / 3.0 * Abar[i][j] * Dbar_beta - 2.0 * alpha * AA +
+      const real dperp = -(real)2 / 3 * Abar[i][j] * Dbar_beta - 2.0 * alpha * AA +
                            alpha * Abar[i][j] * K + em4phi * XTF;
-      double lie = 0.0;
+      real lie = 0.0;
       for (int k = 0; k < 3; k++)
         lie += beta[k] * dAbar_up[i][j][k] + Abar[k][j] * dbeta[k][i] + Abar[i][k] * dbeta[k][j];
       rhs_Abar[i][j] = dperp + lie;
     }
 
   /* ---- 11. Eq. 9: d_perp W;  Eq. 10: d_perp K ------------------------- */
-  double advW = 0.0, advK = 0.0, advAlpha = 0.0;
+  real advW = 0.0, advK = 0.0, advAlpha = 0.0;
   for (int k = 0; k < 3; k++) {
     advW += beta[k] * dW_up[k];
     advK += beta[k] * dK_up[k];
     advAlpha += beta[k] * dalpha_up[k];
   }
-  const double rhs_W = -1.0 / 3.0 * W * (Dbar_beta - alpha * K) + advW;
-  double lap_alpha = 0.0, dalpha_dphi = 0.0;
+  const real rhs_W = -(real)1 / 3 * W * (Dbar_beta - alpha * K) + advW;
+  real lap_alpha = 0.0, dalpha_dphi = 0.0;
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++) {
       lap_alpha += gbUU[i][j] * DbDb_alpha[i][j];
       dalpha_dphi += gbUU[i][j] * dalpha[i] * phi_d[j];
     }
-  const double rhs_K = 1.0 / 3.0 * alpha * K * K + alpha * AbarAbar -
+  const real rhs_K = (real)1 / 3 * alpha * K * K + alpha * AbarAbar -
                        em4phi * (lap_alpha + 2.0 * dalpha_dphi) + advK;
 
   /* ---- 12. Eq. 11: d_perp Lambdabar^i ---------------------------------
@@ -973,65 +982,65 @@ static void bssn_point(const Grid* G, double eta, const double* y, int i0, int i
    * -2 Abar^ij (d_j alpha - 6 alpha d_j phi) + 2 alpha Abar^jk Delta^i_jk,
    * the form that follows from adding alpha times the momentum constraint
    * (Eq. 17) and the only one under which the constraints are preserved.   */
-  double DhatDhat_beta[3][3][3]; /* [i][k][j] = Dhat_j Dhat_k beta^i */
+  real DhatDhat_beta[3][3][3]; /* [i][k][j] = Dhat_j Dhat_k beta^i */
   for (int i = 0; i < 3; i++)
     for (int k = 0; k < 3; k++)
       for (int j = 0; j < 3; j++) {
-        double s = ddbeta[i][k][j]; /* d_j (Dhat_k beta^i) */
+        real s = ddbeta[i][k][j]; /* d_j (Dhat_k beta^i) */
         for (int m = 0; m < 3; m++) s += dGh[i][k][m][j] * beta[m] + Gh[i][k][m] * dbeta[m][j];
         for (int m = 0; m < 3; m++)
           s += Gh[i][j][m] * Dhat_betaU[m][k] - Gh[m][j][k] * Dhat_betaU[i][m];
         DhatDhat_beta[i][k][j] = s;
       }
   /* d_k Gammabar^j_jm = 1/2 d_k (gammabar^jl d_m gammabar_jl)             */
-  double dGbc[3][3]; /* [m][k] */
+  real dGbc[3][3]; /* [m][k] */
   for (int m = 0; m < 3; m++)
     for (int k = 0; k < 3; k++) {
-      double s = 0.0;
+      real s = 0.0;
       for (int j = 0; j < 3; j++)
         for (int l = 0; l < 3; l++) {
-          double dUU = 0.0; /* d_k gammabar^jl */
+          real dUU = 0.0; /* d_k gammabar^jl */
           for (int a = 0; a < 3; a++)
             for (int b = 0; b < 3; b++) dUU -= gbUU[j][a] * gbUU[l][b] * dgb[a][b][k];
           s += 0.5 * (dUU * dgb[j][l][m] + gbUU[j][l] * ddgb[j][l][k][m]);
         }
       dGbc[m][k] = s;
     }
-  double Gbc[3]; /* Gammabar^j_jm */
+  real Gbc[3]; /* Gammabar^j_jm */
   for (int m = 0; m < 3; m++) {
     Gbc[m] = 0.0;
     for (int j = 0; j < 3; j++) Gbc[m] += Gb[j][j][m];
   }
-  double dDbar_beta[3]; /* d_k (Dbar_j beta^j) */
+  real dDbar_beta[3]; /* d_k (Dbar_j beta^j) */
   for (int k = 0; k < 3; k++) {
-    double s = 0.0;
+    real s = 0.0;
     for (int j = 0; j < 3; j++) s += ddbeta[j][j][k];
     for (int m = 0; m < 3; m++) s += dGbc[m][k] * beta[m] + Gbc[m] * dbeta[m][k];
     dDbar_beta[k] = s;
   }
-  double rhs_Lam[3];
+  real rhs_Lam[3];
   for (int i = 0; i < 3; i++) {
-    double t2 = 0.0, t4 = 0.0, t5 = 0.0, t6 = 0.0, t7 = 0.0;
+    real t2 = 0.0, t4 = 0.0, t5 = 0.0, t6 = 0.0, t7 = 0.0;
     for (int j = 0; j < 3; j++)
       for (int k = 0; k < 3; k++) t2 += gbUU[j][k] * DhatDhat_beta[i][k][j];
-    const double t3 = 2.0 / 3.0 * DeltaU[i] * Dbar_beta;
+    const real t3 = (real)2 / 3 * DeltaU[i] * Dbar_beta;
     for (int k = 0; k < 3; k++) t4 += gbUU[i][k] * dDbar_beta[k];
-    t4 *= 1.0 / 3.0;
+    t4 *= (real)1 / 3;
     for (int j = 0; j < 3; j++) t5 += -2.0 * AbarUU[i][j] * (dalpha[j] - 6.0 * alpha * phi_d[j]);
     for (int j = 0; j < 3; j++)
       for (int k = 0; k < 3; k++) t6 += 2.0 * alpha * AbarUU[j][k] * DeltaUDD[i][j][k];
-    for (int j = 0; j < 3; j++) t7 += -4.0 / 3.0 * alpha * gbUU[i][j] * dK[j];
-    double lie = 0.0; /* Lie_beta Lambdabar^i = beta^k d_k Lambdabar^i - Lambdabar^k d_k beta^i */
+    for (int j = 0; j < 3; j++) t7 += -(real)4 / 3 * alpha * gbUU[i][j] * dK[j];
+    real lie = 0.0; /* Lie_beta Lambdabar^i = beta^k d_k Lambdabar^i - Lambdabar^k d_k beta^i */
     for (int k = 0; k < 3; k++) lie += beta[k] * dLam_up[i][k] - Lam[k] * dbeta[i][k];
     rhs_Lam[i] = t2 + t3 + t4 + t5 + t6 + t7 + lie;
   }
 
   /* ---- 13. gauge, Eqs. 13-15. Reading: d_t Lambdabar^i in Eq. 15 is the
    * full right-hand side of Lambdabar^i just computed.                     */
-  const double rhs_alpha = -2.0 * alpha * K + advAlpha;
-  double rhs_beta[3], rhs_B[3];
+  const real rhs_alpha = -2.0 * alpha * K + advAlpha;
+  real rhs_beta[3], rhs_B[3];
   for (int i = 0; i < 3; i++) {
-    double ab = 0.0, aB = 0.0;
+    real ab = 0.0, aB = 0.0;
     for (int j = 0; j < 3; j++) { ab += beta[j] * dbeta_up[i][j]; aB += beta[j] * dB_up[i][j]; }
     rhs_beta[i] = B[i] + ab;
     rhs_B[i] = 0.75 * rhs_Lam[i] - eta * B[i] + aB;
@@ -1061,35 +1070,35 @@ static void bssn_point(const Grid* G, double eta, const double* y, int i0, int i
   if (G->p.diss_gauge != 0.0 || G->p.diss_metric != 0.0)
     for (int g = 0; g < NGF; g++) {
       const int gauge = g == ALPHA || (g >= BETU0 && g <= BETU2) || (g >= VETU0 && g <= VETU2);
-      const double eps = gauge ? G->p.diss_gauge : G->p.diss_metric;
-      const double* f = y + g * np + q;
+      const real eps = gauge ? G->p.diss_gauge : G->p.diss_metric;
+      const real* f = y + g * np + q;
       for (int k = 0; k < 3; k++) out->rhs[g] += eps * fd_ko(&G->fd, f, G->st[k], G->dxx[k]);
     }
 
   /* ---- 15. constraints: Eq. 16 (H), Eq. 17 (M^i), C^i ------------------ */
-  double Rtr = 0.0, dphi2 = 0.0, lap_phi = 0.0;
+  real Rtr = 0.0, dphi2 = 0.0, lap_phi = 0.0;
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++) {
       Rtr += gbUU[i][j] * R[i][j];
       dphi2 += gbUU[i][j] * phi_d[i] * phi_d[j];
       lap_phi += gbUU[i][j] * DbDb_phi[i][j];
     }
-  out->H = 2.0 / 3.0 * K * K - AbarAbar + em4phi * (Rtr - 8.0 * dphi2 - 8.0 * lap_phi);
+  out->H = (real)2 / 3 * K * K - AbarAbar + em4phi * (Rtr - 8.0 * dphi2 - 8.0 * lap_phi);
 
-  double dgbUU[3][3][3]; /* d_k gammabar^ij */
+  real dgbUU[3][3][3]; /* d_k gammabar^ij */
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++)
       for (int k = 0; k < 3; k++) {
-        double s = 0.0;
+        real s = 0.0;
         for (int a = 0; a < 3; a++)
           for (int b = 0; b < 3; b++) s -= gbUU[i][a] * dgb[a][b][k] * gbUU[b][j];
         dgbUU[i][j][k] = s;
       }
-  double dAbarUU[3][3][3]; /* d_k Abar^ij */
+  real dAbarUU[3][3][3]; /* d_k Abar^ij */
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++)
       for (int k = 0; k < 3; k++) {
-        double s = 0.0;
+        real s = 0.0;
         for (int a = 0; a < 3; a++)
           for (int b = 0; b < 3; b++)
             s += dgbUU[i][a][k] * gbUU[j][b] * Abar[a][b] + gbUU[i][a] * dgbUU[j][b][k] * Abar[a][b] +
@@ -1097,19 +1106,19 @@ static void bssn_point(const Grid* G, double eta, const double* y, int i0, int i
         dAbarUU[i][j][k] = s;
       }
   for (int i = 0; i < 3; i++) {
-    double div = 0.0; /* Dhat_j Abar^ij */
+    real div = 0.0; /* Dhat_j Abar^ij */
     for (int j = 0; j < 3; j++) {
       div += dAbarUU[i][j][j];
       for (int m = 0; m < 3; m++) div += Gh[i][j][m] * AbarUU[m][j] + Gh[j][j][m] * AbarUU[i][m];
     }
-    double sym = 0.0; /* 2 Abar^k(i Delta^j)_jk */
+    real sym = 0.0; /* 2 Abar^k(i Delta^j)_jk */
     for (int j = 0; j < 3; j++)
       for (int k = 0; k < 3; k++)
         sym += AbarUU[k][i] * DeltaUDD[j][j][k] + AbarUU[k][j] * DeltaUDD[i][j][k];
-    double t6 = 0.0, tK = 0.0;
+    real t6 = 0.0, tK = 0.0;
     for (int j = 0; j < 3; j++) {
       t6 += 6.0 * AbarUU[i][j] * phi_d[j];
-      tK += -2.0 / 3.0 * gbUU[i][j] * dK[j];
+      tK += -(real)2 / 3 * gbUU[i][j] * dK[j];
     }
     out->M_resc[i] = em4phi * (div + sym + t6 + tK) * S[i];
     out->C_resc[i] = (Lam[i] - DeltaU[i]) * S[i];
@@ -1140,25 +1149,25 @@ static void interior_index(const Grid* G, long long t, int* i0, int* i1, int* i2
  * centred where the array allows and shifted to stay inside it otherwise. The pure-outer points are then
  * advanced by the time integrator like interior points, and the inner ghosts
  * are copies as before.                                                     */
-static double somm_finf(int g) { return (g == ALPHA || g == CF) ? 1.0 : 0.0; }
-static double somm_speed(int g) { return g == ALPHA ? sqrt(2.0) : 1.0; }
+static real somm_finf(int g) { return (g == ALPHA || g == CF) ? 1.0 : 0.0; }
+static real somm_speed(int g) { return g == ALPHA ? sqrt((real)2) : 1.0; }
 
-static void radiation_point(const Grid* G, const double* y, int i0, int i1, int i2, double rhs[NGF]) {
+static void radiation_point(const Grid* G, const real* y, int i0, int i1, int i2, real rhs[NGF]) {
   const int idx[3] = {i0, i1, i2};
-  const double xx[3] = {xx_of(G, 0, i0), xx_of(G, 1, i1), xx_of(G, 2, i2)};
-  double x[3], J[3][3], K[3][3];
+  const real xx[3] = {xx_of(G, 0, i0), xx_of(G, 1, i1), xx_of(G, 2, i2)};
+  real x[3], J[3][3], K[3][3];
   xx_to_cart(G, xx, x);
-  const double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+  const real r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
   jacobian(G, xx, J);
   inverse3(J, K); /* K[a][i] = d xx^i / d x^a */
-  double rd[3];    /* rhat . grad xx^i */
+  real rd[3];    /* rhat . grad xx^i */
   for (int i = 0; i < 3; i++) {
     rd[i] = 0.0;
     for (int a = 0; a < 3; a++) rd[i] += x[a] / r * K[a][i];
   }
   const int R = G->fd.R, W = 2 * R + 1; /* stencil width of the FD order */
   int s[3];
-  double w[3][2 * MAXR + 1];
+  real w[3][2 * MAXR + 1];
   for (int d = 0; d < 3; d++) {
     s[d] = -R;
     if (idx[d] - R < 0) s[d] = -idx[d];
@@ -1169,19 +1178,19 @@ static void radiation_point(const Grid* G, const double* y, int i0, int i1, int 
   }
   const long long q = flat(G, i0, i1, i2);
   for (int g = 0; g < NGF; g++) {
-    const double* f = y + g * G->np + q;
-    double drf = 0.0;
+    const real* f = y + g * G->np + q;
+    real drf = 0.0;
     for (int d = 0; d < 3; d++) {
-      double D = 0.0;
+      real D = 0.0;
       for (int j = 0; j < W; j++) D += w[d][j] * f[(s[d] + j) * G->st[d]];
       drf += rd[d] * D / G->dxx[d];
     }
-    const double v = somm_speed(g);
+    const real v = somm_speed(g);
     rhs[g] = -v * (f[0] - somm_finf(g)) / r - v * drf;
   }
 }
 
-int oracle_rhs(const oracle_params* p, double eta, const double* y, double* rhs) {
+int oracle_rhs(const oracle_params* p, real eta, const real* y, real* rhs) {
   Grid G;
   if (grid_setup(p, &G)) return -1;
   const long long nint = (long long)p->N[0] * p->N[1] * p->N[2];
@@ -1204,7 +1213,7 @@ int oracle_rhs(const oracle_params* p, double eta, const double* y, double* rhs)
         if (kind[q] != 1) continue;
         const int i0 = (int)(q % G.n[0]), i1 = (int)((q / G.n[0]) % G.n[1]),
                   i2 = (int)(q / ((long long)G.n[0] * G.n[1]));
-        double r[NGF];
+        real r[NGF];
         radiation_point(&G, y, i0, i1, i2, r);
         for (int g = 0; g < NGF; g++) rhs[g * G.np + q] = r[g];
       }
@@ -1214,8 +1223,8 @@ int oracle_rhs(const oracle_params* p, double eta, const double* y, double* rhs)
   return 0;
 }
 
-int oracle_rhs_points(const oracle_params* p, double eta, const double* y, int npts,
-                      const long long* idx, double* out, double* ricci) {
+int oracle_rhs_points(const oracle_params* p, real eta, const real* y, int npts,
+                      const long long* idx, real* out, real* ricci) {
   Grid G;
   if (grid_setup(p, &G)) return -1;
   for (int t = 0; t < npts; t++) {
@@ -1238,7 +1247,7 @@ int oracle_rhs_points(const oracle_params* p, double eta, const double* y, int n
   return 0;
 }
 
-int oracle_constraints(const oracle_params* p, const double* y, double* H, double* M, double* C) {
+int oracle_constraints(const oracle_params* p, const real* y, real* H, real* M, real* C) {
   Grid G;
   if (grid_setup(p, &G)) return -1;
   const long long nint = (long long)p->N[0] * p->N[1] * p->N[2];
@@ -1263,21 +1272,21 @@ int oracle_constraints(const oracle_params* p, const double* y, double* H, doubl
  *   k1 = f(y_n), y1 = y_n + dt/2 k1; k2 = f(y1), y2 = y_n + dt/2 k2;
  *   k3 = f(y2), y3 = y_n + dt k3;    k4 = f(y3);
  *   y_n+1 = y_n + dt/6 (k1 + 2 k2 + 2 k3 + k4). Interior points only.      */
-int oracle_rk4_step(const oracle_params* p, double eta, double dt, double* y) {
+int oracle_rk4_step(const oracle_params* p, real eta, real dt, real* y) {
   Grid G;
   if (grid_setup(p, &G)) return -1;
   const long long n = NGF * G.np;
-  double* k[4];
-  for (int s = 0; s < 4; s++) k[s] = (double*)calloc((size_t)n, sizeof(double));
-  double* ys = (double*)malloc(sizeof(double) * n);
+  real* k[4];
+  for (int s = 0; s < 4; s++) k[s] = (real*)calloc((size_t)n, sizeof(real));
+  real* ys = (real*)malloc(sizeof(real) * n);
   int* kind = (int*)malloc(sizeof(int) * G.np);
   int* src = (int*)malloc(sizeof(int) * G.np);
   int* par = (int*)malloc(sizeof(int) * G.np);
   int rc = build_maps(&G, kind, src, par);
   const int rad = p->bc_kind == 1;
   if (rc == 0) {
-    const double c[3] = {0.5, 0.5, 1.0};
-    memcpy(ys, y, sizeof(double) * n);
+    const real c[3] = {0.5, 0.5, 1.0};
+    memcpy(ys, y, sizeof(real) * n);
     for (int s = 0; s < 4; s++) {
       oracle_rhs(p, eta, ys, k[s]);
       if (s == 3) break;
@@ -1306,13 +1315,13 @@ int oracle_rk4_step(const oracle_params* p, double eta, double dt, double* y) {
  *   y1 = y_n + dt f(y_n);
  *   y2 = 3/4 y_n + 1/4 (y1 + dt f(y1));
  *   y_n+1 = 1/3 y_n + 2/3 (y2 + dt f(y2)).  Interior points only.          */
-int oracle_ssprk3_step(const oracle_params* p, double eta, double dt, double* y) {
+int oracle_ssprk3_step(const oracle_params* p, real eta, real dt, real* y) {
   Grid G;
   if (grid_setup(p, &G)) return -1;
   const long long n = NGF * G.np;
-  double* k = (double*)calloc((size_t)n, sizeof(double));
-  double* y1 = (double*)malloc(sizeof(double) * n);
-  double* y2 = (double*)malloc(sizeof(double) * n);
+  real* k = (real*)calloc((size_t)n, sizeof(real));
+  real* y1 = (real*)malloc(sizeof(real) * n);
+  real* y2 = (real*)malloc(sizeof(real) * n);
   int* kind = (int*)malloc(sizeof(int) * G.np);
   int* src = (int*)malloc(sizeof(int) * G.np);
   int* par = (int*)malloc(sizeof(int) * G.np);
@@ -1320,7 +1329,7 @@ int oracle_ssprk3_step(const oracle_params* p, double eta, double dt, double* y)
   const int rad = p->bc_kind == 1;
   if (rc == 0) {
     /* stage 1: forward Euler from y_n */
-    memcpy(y1, y, sizeof(double) * n);
+    memcpy(y1, y, sizeof(real) * n);
     oracle_rhs(p, eta, y, k);
     for (long long t = 0; t < G.np; t++)
       if (kind[t] == 0 || (rad && kind[t] == 1))
@@ -1330,7 +1339,7 @@ int oracle_ssprk3_step(const oracle_params* p, double eta, double dt, double* y)
         }
     apply_bcs_with_maps(&G, kind, src, par, y1, !rad);
     /* stage 2: average of y_n and a forward-Euler step from y1 */
-    memcpy(y2, y1, sizeof(double) * n);
+    memcpy(y2, y1, sizeof(real) * n);
     oracle_rhs(p, eta, y1, k);
     for (long long t = 0; t < G.np; t++)
       if (kind[t] == 0 || (rad && kind[t] == 1))
@@ -1345,7 +1354,7 @@ int oracle_ssprk3_step(const oracle_params* p, double eta, double dt, double* y)
       if (kind[t] == 0 || (rad && kind[t] == 1))
         for (int g = 0; g < NGF; g++) {
           const long long e = g * G.np + t;
-          y[e] = (1.0 / 3.0) * y[e] + (2.0 / 3.0) * (y2[e] + dt * k[e]);
+          y[e] = ((real)1 / 3) * y[e] + ((real)2 / 3) * (y2[e] + dt * k[e]);
         }
     apply_bcs_with_maps(&G, kind, src, par, y, !rad);
   }

@@ -9,9 +9,10 @@ components with an odd number of phi indices stay exactly zero.
 Equatorial symmetry: head-on data symmetric under z -> -z stay symmetric:
 components with an odd number of z indices change sign under the mirror,
 the others do not. The mirrored stencils sum in a different order, so this
-holds to rounding: within the rounding floor of one right-hand side, and
-to 1e-10 of each field after a short evolution (a wrong sign or index
-breaks it at order one).
+holds to rounding: for one right-hand side of exactly mirror-symmetric
+input, to the extended-precision build's rounding (1e-16) and to 1e-13 in
+FP64; to 1e-10 of each field after a short evolution of the head-on data
+(a wrong sign or index breaks it at order one).
 
 Both fail for a wrong index or parity sign anywhere in the right-hand side,
 the ghost maps or the integrator.
@@ -19,7 +20,7 @@ the ghost maps or the integrator.
 import numpy as np
 
 import analytic as an
-from gpu_helpers import gf_errors, rounding_floor
+from gpu_helpers import gf_errors
 from oracle import oracle as orc
 
 ODD_PHI_OR_Z = [an.GF[n] for n in ("hDD02", "hDD12", "aDD02", "aDD12", "lambdaU2", "vetU2", "betU2")]
@@ -63,11 +64,17 @@ def test_equatorial_mirror_symmetry_of_rhs_and_evolution():
     og = orc.Grid(an.SINH_CYLINDRICAL, (24, 2, 48), ampl=(20.0,) * 3, sinhw=(0.2,) * 3)
     y = og.brill_lindquist([0.5, 0.5], np.array([(0, 0, 0.5), (0, 0, -0.5)]))
     I = og.interior()
-    # one right-hand side of the initial data (symmetric to one ulp): within
-    # the operator's own rounding floor, its response to one-ulp input
-    # perturbations
-    floor = rounding_floor(lambda v: og.rhs(v, eta=2.0), y, lambda a, b: gf_errors(a, b, I))
-    assert np.all(mirror_errors(og.rhs(y, eta=2.0), I) <= np.maximum(1e-13, 4.0 * floor))
+    # one right-hand side of the initial data made exactly mirror-symmetric
+    # (the data are symmetric to one ulp, which the operator's second
+    # differences on fine cells amplify to 1e-12): symmetric to the
+    # rounding of each build
+    ys = y.copy()
+    for k in range(an.NGF):
+        s = -1.0 if k in ODD_PHI_OR_Z else 1.0
+        ys[k] = 0.5 * (ys[k] + s * ys[k][::-1])
+    assert np.all(mirror_errors(ys, I) == 0.0)
+    assert np.all(mirror_errors(og.twin().rhs(ys.astype(np.longdouble), eta=2.0), I) <= 1e-16)
+    assert np.all(mirror_errors(og.rhs(ys, eta=2.0), I) <= 1e-13)
     for _ in range(20):
         og.rk4_step(y, og.dt(), eta=2.0)
     assert np.all(mirror_errors(y, I) <= 1e-10)
