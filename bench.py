@@ -33,7 +33,7 @@ PEAK_HBM = 8.0e12           # bytes/s
 # paper_2505_00097_amd/count_flops.py prints it (a CPU test keeps the two in
 # step). On grids with two phi planes the kernel variant drops the phi
 # derivatives that vanish identically there, and its own count applies.
-F_ALG = {(0, False): 5792, (0, True): 5037, (1, False): 5314, (1, True): 4553, (2, False): 5597,
+F_ALG = {(0, False): 5858, (0, True): 5037, (1, False): 5380, (1, True): 4553, (2, False): 5663,
          (2, True): 4842}
 # the same for the 8th-order kernels (five ghost layers), with Kreiss-Oliger
 # dissipation as the production head-on numerics run them
@@ -57,6 +57,7 @@ BYTES_ALG = 24 * 8 * 2
 # calibrated by a copy of known size); valid only for the kernel source it
 # was taken from
 COUNTERS = os.path.join(ROOT, "profiles", "k_rhs_fused_headon_counters.txt")
+COUNTERS_3D = os.path.join(ROOT, "profiles", "k_rhs_fused_vacuum3d_counters.txt")
 KERNEL_SOURCES = ["paper_2505_00097_amd/csrc/rhs_fused.hip", "paper_2505_00097_amd/csrc/rhs_common.h",
                   "paper_2505_00097_amd/csrc/bhah_internal.h"]
 
@@ -69,14 +70,20 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
+def counters_path(workload):
+    """the committed counter summary of a workload's right-hand-side kernel"""
+    return {"headon_sinhcylindrical_128x2x256": COUNTERS, "vacuum3d_sinhspherical_256x128x64": COUNTERS_3D}.get(workload)
+
+
 def measured_traffic(workload, tile=None):
     """HBM bytes per launch from the committed counter summary, or None if it
     is absent, for another workload or tile shape, or older than the kernel
     source."""
-    if not os.path.exists(COUNTERS):
+    path = counters_path(workload)
+    if not path or not os.path.exists(path):
         return None
     vals = {}
-    for line in open(COUNTERS):
+    for line in open(path):
         if ":" in line:
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
@@ -89,6 +96,37 @@ def measured_traffic(workload, tile=None):
         return float(vals[key])
     except (KeyError, ValueError):
         return None
+
+
+def roofline(kernel, flops_per_point, points, launch_s, traffic, probe=None):
+    """Roofline entry of a right-hand-side kernel: algorithmic FP64
+    operations and HBM bytes per launch over the measured launch time, the
+    binding roof the one with the larger ideal time (FP64 vector ALU at
+    78.6 TFLOP/s or HBM at 8 TB/s), and the measured HBM bytes per launch
+    (traffic; None when no counters from the current sources exist)."""
+    flops = flops_per_point * points
+    alg_bytes = BYTES_ALG * points
+    t_alu, t_mem = flops / PEAK_FP64_VECTOR, alg_bytes / PEAK_HBM
+    if t_alu >= t_mem:
+        bound, achieved, peak, unit = "alu", flops / launch_s / 1e12, PEAK_FP64_VECTOR / 1e12, "TFLOP/s"
+    else:
+        bound, achieved, peak, unit = "hbm", alg_bytes / launch_s / 1e9, PEAK_HBM / 1e9, "GB/s"
+    out = {"kernel": kernel, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+           "frac": achieved / peak, "traffic": traffic, "flops_per_point": flops_per_point, "points": points,
+           "launch_s": launch_s, "ideal_alu_s": t_alu, "ideal_hbm_s": t_mem,
+           "hbm_alg_GBps": alg_bytes / launch_s / 1e9,
+           "hbm_measured_GBps": traffic / launch_s / 1e9 if traffic else None,
+           "traffic_over_algorithmic": traffic / alg_bytes if traffic else None}
+    if probe:
+        # ceilings measured on this device (FMA chains, streaming triad)
+        out.update({"device_fp64_tflops": probe[0], "frac_of_device_fp64": flops / launch_s / 1e12 / probe[0],
+                    "device_triad_GBps": probe[1]})
+    return out
+
+
+def kernel_name(coord, N, ko=False, nghosts=3):
+    return "k_rhs_fused<%d,%s,%s,%d>" % (coord, "true" if two_planes(coord, N) else "false",
+                                          "true" if ko else "false", nghosts)
 
 
 def percentile(v, p):
@@ -218,10 +256,12 @@ def run_ssprk3(capi, wl, stream, steps, diss=(0.0, 0.0), bc_kind=0, nghosts=3, r
 
 
 def run_batched(capi, wl, stream, steps, seq_steps, graph_steps, integrator=0, diss=(0.0, 0.0), bc_kind=0,
-                nghosts=3):
+                nghosts=3, tune_launch=False):
     """64 uneven head-on jobs: one batch advancing all of them `steps` steps
     (RK4 or SSPRK3, optional dissipation and radiation boundary), against the
-    same jobs advanced one at a time with the same numerics."""
+    same jobs advanced one at a time with the same numerics. With
+    tune_launch the batch first times graph steps x blocks per CU on copies
+    of the states and keeps the fastest (reported beside the default)."""
     import torch
     jobs = wl.batched_jobs()
     grids = make_grids(capi, jobs, bc_kind, nghosts)
@@ -236,23 +276,26 @@ def run_batched(capi, wl, stream, steps, seq_steps, graph_steps, integrator=0, d
     b = capi.batch_create([g.h for g in grids], eta=2.0, diss=diss)
     capi.batch_set_integrator(b, integrator)
     capi.batch_set_graph_steps(b, graph_steps)
-    capi.batch_step(b, ys, wss, dts, nsteps=graph_steps, stream=stream)  # tunes tiles, captures graph
+    if tune_launch:
+        capi.batch_set_launch_tuning(b, True)
+    capi.batch_step(b, ys, wss, dts, nsteps=graph_steps, stream=stream)  # tunes tiles (and launch), captures graphs
     torch.cuda.synchronize()
     info = capi.batch_get_info(b)
-    n_launch = (steps + graph_steps - 1) // graph_steps
+    # timed in chunks of 50 steps (the engine splits each into its graphs)
+    chunk = 50
+    n_launch = (steps + chunk - 1) // chunk
     ev = events(n_launch + 1)
     t0 = time.perf_counter()
     ev[0].record(stream)
     done = 0
     for k in range(n_launch):
-        n = min(graph_steps, steps - done)
+        n = min(chunk, steps - done)
         capi.batch_step(b, ys, wss, dts, nsteps=n, stream=stream)
         done += n
         ev[k + 1].record(stream)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    per_step = [ev[k].elapsed_time(ev[k + 1]) / min(graph_steps, steps - k * graph_steps)
-                for k in range(n_launch)]
+    per_step = [ev[k].elapsed_time(ev[k + 1]) / min(chunk, steps - k * chunk) for k in range(n_launch)]
     finite = all(bool(torch.isfinite(y).all().item()) for y in ys)
     capi.batch_destroy(b)
     # the same jobs one after another, plain single-grid steps
@@ -276,80 +319,86 @@ def run_batched(capi, wl, stream, steps, seq_steps, graph_steps, integrator=0, d
             "ms_per_step_all_jobs": el * 1e3 / steps,
             "p50_step_ms": percentile(per_step, 50), "p99_step_ms": percentile(per_step, 99),
             "sequential_value": seq, "sequential_sample": f"each job {seq_steps} steps alone, {el_seq:.2f} s",
-            "speedup_vs_sequential": batched / seq, "graph_steps": graph_steps,
+            "speedup_vs_sequential": batched / seq, "graph_steps": info.graph_steps,
+            "blocks_per_cu": info.blocks_per_cu,
+            "launch_tuning": ({"graph_steps": info.graph_steps, "blocks_per_cu": info.blocks_per_cu,
+                               "us_per_step": info.launch_us_per_step,
+                               "default_us_per_step (10 graph steps, 4 blocks per CU)": info.launch_default_us_per_step,
+                               "candidates": info.launch_candidates, "seconds": info.launch_tune_seconds,
+                               "from_cache": bool(info.launch_from_cache)} if tune_launch else None),
             "tile_classes_tuned": info.n_classes_tuned, "tune_seconds": info.tune_seconds,
             "tiles": info.n_tiles, "rhs_blocks": info.rhs_blocks, "finite": finite}
 
 
-def run_served(capi, wl, stream, n_jobs, steps_per_tick, seq_probe_steps, target_points):
-    """Poisson-arriving head-on jobs through the continuous-batching server,
-    and a first-come-first-served one-job-at-a-time schedule of the same
-    arrivals priced with measured solo step times."""
-    import torch
-    jobs = wl.served_jobs(n=n_jobs)
-    srv = capi.server_create(200e9, max_jobs=256, steps_per_tick=steps_per_tick, keep_results=False,
+def serve(capi, stream, jobs, descs, max_jobs, steps_per_tick, target_points, label, at_once=False):
+    """Run jobs through a server: each submitted at its arrival time (all at
+    once with at_once), ticks until every job is done. Returns the server's
+    statistics and the wall time from the first arrival to the end."""
+    srv = capi.server_create(200e9, max_jobs=max_jobs, steps_per_tick=steps_per_tick, keep_results=False,
                              eta=2.0, stream=stream, target_points=target_points)
-    descs = [capi.job_desc(j["coord"], j["N"], j["ampl"], j["sinhw"], j["cfl"], j["masses"], j["positions"],
-                           j["steps"]) for j in jobs]
+    arrival = [0.0 if at_once else j["arrival"] for j in jobs]
     t0 = time.perf_counter()
     i = 0
     last_print = t0
     while True:
         now = time.perf_counter() - t0
-        while i < len(jobs) and jobs[i]["arrival"] <= now:
+        while i < len(jobs) and arrival[i] <= now:
             capi.server_submit(srv, descs[i])
             i += 1
         running, queued = capi.server_tick(srv)
         if running == 0 and queued == 0:
             if i >= len(jobs):
                 break
-            time.sleep(max(0.0, jobs[i]["arrival"] - (time.perf_counter() - t0)))
+            time.sleep(max(0.0, arrival[i] - (time.perf_counter() - t0)))
         if time.perf_counter() - last_print > 20.0:
             last_print = time.perf_counter()
-            print(f"# served: {i}/{len(jobs)} arrived, {running} running, {queued} queued", file=sys.stderr,
+            print(f"# {label}: {i}/{len(jobs)} arrived, {running} running, {queued} queued", file=sys.stderr,
                   flush=True)
-    wall = time.perf_counter() - t0 - jobs[0]["arrival"]
+    wall = time.perf_counter() - t0 - arrival[0]
     st = capi.server_get_stats(srv)
     capi.server_destroy(srv)
-    # measured solo step time per resolution
-    t_step = {}
-    for nr in sorted({j["N"][0] for j in jobs}):
-        j = wl.headon_job(2.0, 1.0, nr)
-        g = capi.Grid(j["coord"], j["N"], j["ampl"], j["sinhw"], j["cfl"])
-        y, ws = g.state(), g.workspace()
-        capi.set_initial_data_brill_lindquist(g.h, j["masses"], j["positions"], y, stream=stream)
-        for _ in range(3):
-            capi.rk4_step(g.h, y, ws, g.dt, stream=stream)
-        e0, e1 = events(2)
-        e0.record(stream)
-        for _ in range(seq_probe_steps):
-            capi.rk4_step(g.h, y, ws, g.dt, stream=stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        t_step[nr] = e0.elapsed_time(e1) / 1e3 / seq_probe_steps
-    free, lat, work = 0.0, [], 0.0
-    for j in jobs:
-        start = max(j["arrival"], free)
-        free = start + j["steps"] * t_step[j["N"][0]]
-        lat.append(free - j["arrival"])
-        work += j["steps"] * j["N"][0] * j["N"][1] * j["N"][2]
-    seq_wall = free - jobs[0]["arrival"]
-    seq_busy = sum(j["steps"] * t_step[j["N"][0]] for j in jobs)
-    return {"workload": f"{n_jobs} Poisson-arriving head-on jobs (4/s), N_rho in {{64,96,128,192}}, "
-                        "steps U{200..2000}, seed 250500098, 200 GB budget",
-            "value": st.point_steps / wall, "unit": UNIT, "wall_seconds": wall,
-            "target_points": target_points,
+    return st, wall
+
+
+def served_summary(st, wall):
+    return {"value": st.point_steps / wall, "unit": UNIT, "wall_seconds": wall,
             "busy_value": st.point_steps / st.busy_seconds if st.busy_seconds > 0 else None,
             "busy_seconds": st.busy_seconds, "point_steps": st.point_steps, "jobs_done": st.done,
             "p50_step_ms": st.step_ms_p50, "p99_step_ms": st.step_ms_p99,
             "p50_job_s": st.job_s_p50, "p99_job_s": st.job_s_p99,
-            "peak_running": st.peak_running, "peak_held_GB": st.peak_held_bytes / 1e9,
-            "sequential_fcfs": {"value": work / seq_wall, "wall_seconds": seq_wall,
-                                "busy_seconds": seq_busy, "busy_value": work / seq_busy,
-                                "p50_job_s": percentile(lat, 50), "p99_job_s": percentile(lat, 99),
-                                "solo_step_ms": {str(k): v * 1e3 for k, v in t_step.items()},
-                                "how": "same arrivals, one job at a time in arrival order, priced with "
-                                       "measured solo RK4 step times"}}
+            "peak_running": st.peak_running, "peak_held_GB": st.peak_held_bytes / 1e9}
+
+
+def run_served(capi, wl, stream, n_jobs, steps_per_tick, target_points, n_saturated):
+    """Head-on jobs through the continuous-batching server, against the same
+    jobs through the same server one at a time (max_jobs = 1, first come
+    first served), both measured: the Poisson arrival trace (4 jobs/s), and
+    a saturated load (the first n_saturated jobs of the trace, all arriving
+    at once) where capacity rather than arrivals bounds throughput."""
+    jobs = wl.served_jobs(n=n_jobs)
+    descs = [capi.job_desc(j["coord"], j["N"], j["ampl"], j["sinhw"], j["cfl"], j["masses"], j["positions"],
+                           j["steps"]) for j in jobs]
+    st, wall = serve(capi, stream, jobs, descs, 256, steps_per_tick, target_points, "served")
+    out = {"workload": f"{n_jobs} Poisson-arriving head-on jobs (4/s), N_rho in {{64,96,128,192}}, "
+                       "steps U{200..2000}, seed 250500098, 200 GB budget",
+           "target_points": target_points, "steps_per_tick": steps_per_tick}
+    out.update(served_summary(st, wall))
+    print(f"# served: {out['value']:.3e} pt-steps/s", file=sys.stderr, flush=True)
+    st, wall = serve(capi, stream, jobs, descs, 1, steps_per_tick, 0, "served one at a time")
+    out["sequential_fcfs"] = served_summary(st, wall)
+    out["sequential_fcfs"]["how"] = "the same arrivals through the same server with max_jobs = 1 (measured)"
+    sat = jobs[:n_saturated]
+    st, wall = serve(capi, stream, sat, descs[:n_saturated], 256, steps_per_tick, target_points, "saturated",
+                     at_once=True)
+    out["saturated"] = {"workload": f"the first {n_saturated} jobs of the trace, all arriving at t = 0"}
+    out["saturated"].update(served_summary(st, wall))
+    st, wall = serve(capi, stream, sat, descs[:n_saturated], 1, steps_per_tick, 0, "saturated one at a time",
+                     at_once=True)
+    out["saturated"]["sequential_fcfs"] = served_summary(st, wall)
+    out["saturated"]["speedup_vs_sequential"] = out["saturated"]["value"] / out["saturated"]["sequential_fcfs"]["value"]
+    print(f"# saturated: {out['saturated']['value']:.3e} vs one at a time "
+          f"{out['saturated']['sequential_fcfs']['value']:.3e} pt-steps/s", file=sys.stderr, flush=True)
+    return out
 
 
 def run_rhs_study(capi, wl, stream, reps, steps):
@@ -385,12 +434,51 @@ def run_rhs_study(capi, wl, stream, reps, steps):
     eighth = {"rhs_launch_s": rhs8_s, "flops_per_point": f8, "rhs_TFLOPs": f8 * n / rhs8_s / 1e12,
               "rhs_frac_fp64_peak": f8 * n / rhs8_s / PEAK_FP64_VECTOR, "tile": list(capi.grid_get_tile(g8.h))}
     del y8
-    return {"workload": "vacuum3d_sinhspherical_256x128x64", "interior_points": n,
+    name = "vacuum3d_sinhspherical_256x128x64"
+    return {"workload": name, "interior_points": n,
             "rhs_launch_s": rhs_s, "rhs_TFLOPs": f_alg(w["coord"], w["N"]) * n / rhs_s / 1e12,
             "rhs_frac_fp64_peak": f_alg(w["coord"], w["N"]) * n / rhs_s / PEAK_FP64_VECTOR,
             "rhs_alg_GBps": BYTES_ALG * n / rhs_s / 1e9,
             "rk4_step_ms": step_s * 1e3, "value": n / step_s, "unit": UNIT,
-            "tile": tile, "rhs_8th_order_with_dissipation": eighth}
+            "tile": tile, "rhs_8th_order_with_dissipation": eighth,
+            "roofline": roofline(kernel_name(w["coord"], w["N"]), f_alg(w["coord"], w["N"]), n, rhs_s,
+                                 measured_traffic(name, tile))}
+
+
+def run_tiny(capi, wl, stream, steps, warmup):
+    """The tiny workload (SinhSpherical 32x16x2, one puncture at the origin):
+    single RK4 steps after warm-up, each timed with events (the
+    latency-bound end of the range), and the flat-spacetime run, whose
+    right-hand side must vanish exactly."""
+    import torch
+    w = wl.WORKLOADS["tiny_sinhspherical_32x16x2"]
+    g = capi.Grid(w["coord"], w["N"], w["ampl"], w["sinhw"], w["cfl"])
+    y, ws = g.state(), g.workspace()
+    capi.set_initial_data_brill_lindquist(g.h, w["masses"], w["positions"], y, stream=stream)
+    for _ in range(warmup):
+        capi.rk4_step(g.h, y, ws, g.dt, eta=w["eta"], stream=stream)
+    ev = events(steps + 1)
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for s in range(steps):
+        capi.rk4_step(g.h, y, ws, g.dt, eta=w["eta"], stream=stream)
+        ev[s + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    flat = g.state()
+    capi.set_initial_data_brill_lindquist(g.h, [], [], flat, lapse_kind=1, stream=stream)
+    r = g.state()
+    r.fill_(1.0)
+    capi.bssn_rhs(g.h, flat, r, None, eta=w["eta"], stream=stream)
+    ng = g.info.n_total
+    interior = r.view(24, ng[2], ng[1], ng[0])[:, 3:-3, 3:-3, 3:-3]
+    flat_zero = bool((interior == 0.0).all().item())
+    n = g.info.n_interior
+    return {"workload": "tiny_sinhspherical_32x16x2", "interior_points": n, "steps": steps,
+            "value": n * steps / wall, "unit": UNIT, "median_step_ms": percentile(ms, 50),
+            "p50_step_ms": percentile(ms, 50), "p99_step_ms": percentile(ms, 99),
+            "flat_spacetime_rhs_exactly_zero": flat_zero}
 
 
 def run_paper_grid(capi, wl, stream, name, N, r_max, steps, graph_steps, paper):
@@ -435,7 +523,12 @@ def main():
     ap.add_argument("--served-jobs", type=int, default=256)
     ap.add_argument("--served-target-points", type=int, default=262144,
                     help="admit while running jobs hold fewer interior points (0: no limit)")
+    ap.add_argument("--served-saturated-jobs", type=int, default=128,
+                    help="jobs of the trace submitted at once for the saturated served leg")
     ap.add_argument("--study-steps", type=int, default=20)
+    ap.add_argument("--latency-steps", type=int, default=100,
+                    help="single RK4 steps timed one by one for the p50/p99 step latency")
+    ap.add_argument("--tiny-steps", type=int, default=200, help="timed steps of the tiny workload (0: skip)")
     ap.add_argument("--no-paper-grids", action="store_true")
     ap.add_argument("--ssprk3-steps", type=int, default=500)
     ap.add_argument("--no-probe-peaks", action="store_true",
@@ -470,20 +563,33 @@ def main():
         torch.cuda.synchronize()
 
         # ---- timed region: exactly `steps` RK4 steps ----------------------
-        ev = events(args.steps + 1)
+        # bhah_evolve between Hamiltonian evaluations: the stencils never
+        # read the phi ghost planes, which are filled after each call's last
+        # step (every ghost is valid whenever H is evaluated)
+        chunk = h_every if h_every else args.steps
+        bounds = list(range(0, args.steps, chunk)) + [args.steps]
+        ev = events(len(bounds))
         t0 = time.perf_counter()
         ev[0].record(stream)
-        for s in range(args.steps):
-            capi.rk4_step(g.h, y, ws, dt, eta=w["eta"], stream=stream)
-            if h_every and (s + 1) % h_every == 0:
+        for c in range(len(bounds) - 1):
+            capi.evolve(g.h, y, ws, dt, bounds[c + 1] - bounds[c], eta=w["eta"], stream=stream)
+            if h_every and bounds[c + 1] % h_every == 0:
                 capi.hamiltonian_constraint(g.h, y, H, stream=stream)
-            ev[s + 1].record(stream)
+            ev[c + 1].record(stream)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)]
+        chunk_ms = [(ev[c].elapsed_time(ev[c + 1]) / (bounds[c + 1] - bounds[c])) for c in range(len(bounds) - 1)]
         elapsed = t1 - t0
         finite = bool(torch.isfinite(y).all().item())
         print(f"# plain: {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+        # single-step latency: bhah_rk4_step calls, one event per step
+        lat_ev = events(args.latency_steps + 1)
+        lat_ev[0].record(stream)
+        for s in range(args.latency_steps):
+            capi.rk4_step(g.h, y, ws, dt, eta=w["eta"], stream=stream)
+            lat_ev[s + 1].record(stream)
+        torch.cuda.synchronize()
+        step_ms = [lat_ev[i].elapsed_time(lat_ev[i + 1]) for i in range(args.latency_steps)]
 
         # ---- the dominant kernel: one right-hand-side evaluation ----------
         rhs_s = time_rhs(capi, g, y, w["eta"], args.rhs_reps, stream)
@@ -491,6 +597,11 @@ def main():
         probe = None if args.no_probe_peaks else capi.probe_peaks(stream)
 
         extras = {}
+        if args.tiny_steps > 0:
+            extras["tiny"] = run_tiny(capi, wl, stream, args.tiny_steps, 20)
+            print(f"# tiny: {extras['tiny']['value']:.3e} pt-steps/s, step p50/p99 "
+                  f"{extras['tiny']['p50_step_ms']:.3f}/{extras['tiny']['p99_step_ms']:.3f} ms", file=sys.stderr,
+                  flush=True)
         if args.ssprk3_steps > 0:
             # SSPRK3 without dissipation is unstable on this grid at CFL 0.5
             # (non-finite near step 480, in the oracle as well): both legs
@@ -509,7 +620,7 @@ def main():
                   f"{extras['production_numerics_8th_order']['value']:.3e}", file=sys.stderr, flush=True)
         if args.batched_steps > 0:
             extras["batched"] = run_batched(capi, wl, stream, args.batched_steps, args.batched_seq_steps,
-                                            args.graph_steps)
+                                            args.graph_steps, tune_launch=True)
             torch.cuda.empty_cache()
             print(f"# batched: {extras['batched']['value']:.3e} pt-steps/s", file=sys.stderr, flush=True)
             extras["batched_production_numerics"] = run_batched(
@@ -540,12 +651,10 @@ def main():
             torch.cuda.empty_cache()
             print("# paper grids done", file=sys.stderr, flush=True)
         if args.served_jobs > 0:
-            extras["served"] = run_served(capi, wl, stream, args.served_jobs, args.graph_steps, 30,
-                                          args.served_target_points)
-            print(f"# served: {extras['served']['value']:.3e} pt-steps/s", file=sys.stderr, flush=True)
+            extras["served"] = run_served(capi, wl, stream, args.served_jobs, args.graph_steps,
+                                          args.served_target_points,
+                                          min(args.served_saturated_jobs, args.served_jobs))
 
-    flops = f_alg(w["coord"], w["N"]) * n_int
-    achieved = flops / rhs_s
     traffic = measured_traffic(args.workload, tile)
     out = {
         "metric": METRIC,
@@ -565,19 +674,13 @@ def main():
                    " {}x{}x{}".format(*w["N"]), "interior_points": n_int,
                    "hamiltonian_every": h_every, "dt": dt, "parallelism": "single GPU",
                    "tile": list(capi.grid_get_tile(g.h))},
-        "latency": {"p50_step_ms": percentile(step_ms, 50), "p99_step_ms": percentile(step_ms, 99)},
+        "latency": {"p50_step_ms": percentile(step_ms, 50), "p99_step_ms": percentile(step_ms, 99),
+                    "how": f"{args.latency_steps} single bhah_rk4_step calls after the timed region, one "
+                           "event pair per step",
+                    "timed_chunks_ms_per_step": chunk_ms},
         "finite": finite,
-        "roofline": {"kernel": "k_rhs_fused<%d,%s,false,3>" % (w["coord"], "true" if two_planes(w["coord"], w["N"])
-                                                                 else "false"), "bound": "alu",
-                     "achieved": achieved / 1e12, "peak": PEAK_FP64_VECTOR / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_VECTOR, "traffic": traffic,
-                     "flops_per_point": f_alg(w["coord"], w["N"]), "points": n_int, "launch_s": rhs_s,
-                     "hbm_alg_GBps": BYTES_ALG * n_int / rhs_s / 1e9,
-                     "hbm_measured_GBps": traffic / rhs_s / 1e9 if traffic else None,
-                     # ceilings measured on this device (FMA chains, streaming triad)
-                     "device_fp64_tflops": probe[0] if probe else None,
-                     "frac_of_device_fp64": achieved / 1e12 / probe[0] if probe else None,
-                     "device_triad_GBps": probe[1] if probe else None},
+        "roofline": roofline(kernel_name(w["coord"], w["N"]), f_alg(w["coord"], w["N"]), n_int, rhs_s, traffic,
+                             probe),
         "extras": extras,
     }
     if not args.no_cpu_baseline:

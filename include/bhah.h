@@ -250,6 +250,19 @@ int bhah_rk4_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt,
 int bhah_ssprk3_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt,
                      double* y, double* workspace, void* stream);
 
+/* nsteps steps of bhah_rk4_step (integrator BHAH_RK4) or bhah_ssprk3_step
+ * (BHAH_SSPRK3) in one call, the same arithmetic stage by stage, so the
+ * state on return equals that of nsteps single-step calls bit for bit, and
+ * every ghost of y is valid on return. Between the steps only the ghosts
+ * the stencils read are refilled: the phi ghost planes (exact periodic
+ * copies, never read by the stencils, which wrap the phi index onto the
+ * interior) are filled once, after the last step, instead of after every
+ * step (on the head-on grid they are most of the 215k ghost points).
+ * nsteps = 0 does nothing; nsteps < 0, an unknown integrator or the
+ * arguments rejected by bhah_rk4_step give BHAH_EINVAL.                     */
+int bhah_evolve(const bhah_grid* g, const bhah_gauge_params* gp, int integrator,
+                double dt, int nsteps, double* y, double* workspace, void* stream);
+
 /* All three constraints at every interior point, centred differences of
  * the grid's order: H of Eq. 16 (one gridfunction), the momentum constraint M^i of
  * Eq. 17 and C^i = Lambdabar^i - Delta^i (three gridfunctions each, rescaled
@@ -340,9 +353,27 @@ typedef struct {
   int rhs_blocks;        /* persistent blocks of the right-hand-side kernel  */
   int n_classes_tuned;   /* size classes with a tile choice                  */
   double tune_seconds;   /* wall time spent timing tile candidates           */
+  int blocks_per_cu;     /* persistent RHS blocks per CU (0: one per tile)   */
+  /* launch tuning (bhah_batch_set_launch_tuning) for the current job set:
+   * microseconds per step of the chosen graph steps / blocks per CU and of
+   * the default (10, 4), candidates timed, seconds spent, and 1 if the
+   * choice came from the cache file (then nothing was timed)              */
+  double launch_us_per_step, launch_default_us_per_step, launch_tune_seconds;
+  int launch_candidates, launch_from_cache;
 } bhah_batch_info;
 
 int bhah_batch_get_info(const bhah_batch* b, bhah_batch_info* info);
+
+/* Launch tuning (off by default): with on != 0, the first bhah_batch_step
+ * on a job set not seen before times every pair of graph steps {4, 10, 25}
+ * and persistent blocks per CU {2, 4, 8, one per tile} on device copies of
+ * the jobs' states (the caller's states are untouched; the results are the
+ * same bit for bit whatever the pair), keeps the fastest (the default
+ * (10, 4) unless another is more than 2% faster) and stores it per job-set
+ * signature (the multiset of grid shapes, numerics and the integrator) in
+ * the tile cache file. The copies need one state per job of device memory
+ * for the duration of the tuning (BHAH_ENOMEM otherwise).                   */
+int bhah_batch_set_launch_tuning(bhah_batch* b, int on);
 
 /* Tile choice for job j's size class: log2 extents along i0 and i1 (the
  * extent along i2 is 64 >> (lx + ly)) and band (tile rows of i1 walked
@@ -357,10 +388,14 @@ void bhah_batch_destroy(bhah_batch* b);
  * holds for job states stays within budget_bytes, keeps every admitted
  * job's state (state + RK4 workspace, 4 x info.state_doubles doubles) in
  * device memory, and on each tick advances all running jobs together
- * through one ensemble engine (bhah_batch's kernels and graphs). Jobs of one
- * grid shape share one bhah_grid; freed state slots are reused by later jobs
- * of the same shape. Times are seconds since bhah_server_create on the host
- * steady clock.                                                            */
+ * through one ensemble engine (bhah_batch's kernels and graphs), each job
+ * taking min(its steps left, steps_per_tick) steps. Jobs of one grid shape
+ * share one bhah_grid; freed state slots are reused by later jobs of the
+ * same shape, and free slots of other shapes are given back to the device
+ * when a queued job would not fit the budget otherwise. Times are seconds
+ * since bhah_server_create on the host steady clock; device-side times
+ * (a job's completion, busy time, step latency) come from events on the
+ * server's stream mapped onto that clock.                                  */
 typedef struct bhah_server bhah_server;
 
 typedef struct {
@@ -382,11 +417,14 @@ typedef struct {
   int n_punct;              /* <= 16                                          */
   double masses[16];
   double pos[16][3];        /* Cartesian positions                            */
-  int lapse_kind;           /* as bhah_set_initial_data_brill_lindquist       */
+  int lapse_kind;           /* 0 or 1, as bhah_set_initial_data_brill_lindquist */
   long long nsteps;         /* RK4 steps at the grid's CFL dt (info.dt)       */
 } bhah_job_desc;
 
-enum { BHAH_JOB_QUEUED = 0, BHAH_JOB_RUNNING = 1, BHAH_JOB_DONE = 2, BHAH_JOB_RELEASED = 3 };
+/* DONE: finished, state kept for bhah_server_fetch (keep_results);
+ * RELEASED: finished and its memory reused; FAILED: its initial data could
+ * not be set at admission (it left the queue, other jobs go on).           */
+enum { BHAH_JOB_QUEUED = 0, BHAH_JOB_RUNNING = 1, BHAH_JOB_DONE = 2, BHAH_JOB_RELEASED = 3, BHAH_JOB_FAILED = 4 };
 
 typedef struct {
   int state;                /* BHAH_JOB_*                                      */
@@ -404,16 +442,27 @@ typedef struct {
   double job_s_p50, job_s_p99;      /* submit -> done of finished jobs        */
   double held_bytes, peak_held_bytes;
   int peak_running;
+  long long failed;         /* jobs that failed at admission                  */
 } bhah_server_stats;
 
 /* stream: the stream every device operation of the server runs on.          */
 int bhah_server_create(const bhah_server_params* p, void* stream, bhah_server** out);
-/* Queue a job (arrival time = now); *id receives its handle.                */
+/* Queue a job (arrival time = now); *id receives its handle. BHAH_EINVAL
+ * for a NULL argument, n_punct outside 0..16, nsteps < 0, lapse_kind not 0
+ * or 1, invalid grid parameters, or a job larger than the whole budget.     */
 int bhah_server_submit(bhah_server* s, const bhah_job_desc* job, long long* id);
-/* Admit queued jobs that fit, advance the running ones by
- * min(steps_per_tick, fewest steps left) steps, retire finished ones.
- * Blocks until the tick's device work is done. *running / *queued (may be
- * NULL) receive the counts after the tick.                                  */
+/* Admit queued jobs that fit (their initial data is set on the stream),
+ * enqueue one graph launch in which every running job takes
+ * min(steps_per_tick, its steps left) steps, then wait for the previous
+ * tick's device work: at most one tick is in flight, so the host's
+ * admission and bookkeeping overlap the device's steps. Jobs whose last
+ * steps complete become DONE (keep_results) or RELEASED; a job's results
+ * are final once its status says so. With nothing left running or queued
+ * the tick also waits for its own work, so a tick that reports no job
+ * running and none queued has completed everything. *running (jobs with
+ * steps still to enqueue) and *queued (may be NULL) receive the counts
+ * after the tick; bhah_server_get_stats counts as running also the jobs
+ * whose last steps are still in flight.                                     */
 int bhah_server_tick(bhah_server* s, int* running, int* queued);
 int bhah_server_job_status(const bhah_server* s, long long id, bhah_job_status* st);
 /* Copy a finished job's state (info.state_doubles doubles, device pointer

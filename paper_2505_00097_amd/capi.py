@@ -44,7 +44,10 @@ class GridInfo(ctypes.Structure):
 class BatchInfo(ctypes.Structure):
     _fields_ = [("n_active", ctypes.c_int), ("n_tiles", ctypes.c_int), ("n_chunks", ctypes.c_int),
                 ("graph_steps", ctypes.c_int), ("rhs_blocks", ctypes.c_int),
-                ("n_classes_tuned", ctypes.c_int), ("tune_seconds", ctypes.c_double)]
+                ("n_classes_tuned", ctypes.c_int), ("tune_seconds", ctypes.c_double),
+                ("blocks_per_cu", ctypes.c_int), ("launch_us_per_step", ctypes.c_double),
+                ("launch_default_us_per_step", ctypes.c_double), ("launch_tune_seconds", ctypes.c_double),
+                ("launch_candidates", ctypes.c_int), ("launch_from_cache", ctypes.c_int)]
 
 
 class ServerParams(ctypes.Structure):
@@ -73,10 +76,11 @@ class ServerStats(ctypes.Structure):
                 ("elapsed_seconds", ctypes.c_double), ("step_ms_p50", ctypes.c_double),
                 ("step_ms_p99", ctypes.c_double), ("job_s_p50", ctypes.c_double),
                 ("job_s_p99", ctypes.c_double), ("held_bytes", ctypes.c_double),
-                ("peak_held_bytes", ctypes.c_double), ("peak_running", ctypes.c_int)]
+                ("peak_held_bytes", ctypes.c_double), ("peak_running", ctypes.c_int),
+                ("failed", ctypes.c_longlong)]
 
 
-JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_RELEASED = 0, 1, 2, 3
+JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_RELEASED, JOB_FAILED = 0, 1, 2, 3, 4
 
 
 class BhahError(RuntimeError):
@@ -95,6 +99,8 @@ _SIGS = {
     "bhah_apply_bcs": (ctypes.c_int, [_vp, _vp, _vp]),
     "bhah_bssn_rhs": (ctypes.c_int, [_vp, ctypes.POINTER(GaugeParams), _vp, _vp, _vp, _vp]),
     "bhah_rk4_step": (ctypes.c_int, [_vp, ctypes.POINTER(GaugeParams), ctypes.c_double, _vp, _vp, _vp]),
+    "bhah_evolve": (ctypes.c_int, [_vp, ctypes.POINTER(GaugeParams), ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                   _vp, _vp, _vp]),
     "bhah_hamiltonian_constraint": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "bhah_constraints": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "bhah_grid_set_tile": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
@@ -106,6 +112,7 @@ _SIGS = {
     "bhah_batch_set_graph_steps": (ctypes.c_int, [_vp, ctypes.c_int]),
     "bhah_batch_set_blocks_per_cu": (ctypes.c_int, [_vp, ctypes.c_int]),
     "bhah_batch_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(BatchInfo)]),
+    "bhah_batch_set_launch_tuning": (ctypes.c_int, [_vp, ctypes.c_int]),
     "bhah_batch_get_tile": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp]),
     "bhah_batch_destroy": (None, [_vp]),
     "bhah_server_create": (ctypes.c_int, [ctypes.POINTER(ServerParams), _vp, ctypes.POINTER(_vp)]),
@@ -234,6 +241,12 @@ def ssprk3_step(h, y, workspace, dt, eta=2.0, diss=(0.0, 0.0), stream=None):
            "bhah_ssprk3_step")
 
 
+def evolve(h, y, workspace, dt, nsteps, integrator=RK4, eta=2.0, diss=(0.0, 0.0), stream=None):
+    gp = gauge(eta, diss)
+    _check(lib().bhah_evolve(h, ctypes.byref(gp), int(integrator), float(dt), int(nsteps), _ptr(y), _ptr(workspace),
+                             _stream(stream)), "bhah_evolve")
+
+
 def hamiltonian_constraint(h, y, H, stream=None):
     _check(lib().bhah_hamiltonian_constraint(h, _ptr(y), _ptr(H), _stream(stream)),
            "bhah_hamiltonian_constraint")
@@ -295,6 +308,10 @@ def batch_set_integrator(b, integrator):
 
 def batch_set_blocks_per_cu(b, blocks_per_cu):
     _check(lib().bhah_batch_set_blocks_per_cu(b, int(blocks_per_cu)), "bhah_batch_set_blocks_per_cu")
+
+
+def batch_set_launch_tuning(b, on=True):
+    _check(lib().bhah_batch_set_launch_tuning(b, 1 if on else 0), "bhah_batch_set_launch_tuning")
 
 
 def batch_get_info(b):

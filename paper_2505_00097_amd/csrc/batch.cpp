@@ -74,6 +74,19 @@ int bhah_batch_get_info(const bhah_batch* b, bhah_batch_info* info) {
   info->rhs_blocks = b->engine.rhs_blocks();
   info->n_classes_tuned = b->engine.n_classes_tuned();
   info->tune_seconds = b->engine.tune_seconds();
+  info->blocks_per_cu = b->engine.blocks_per_cu();
+  const bhah::Engine::LaunchTune& t = b->engine.launch_tune();
+  info->launch_us_per_step = t.us_per_step;
+  info->launch_default_us_per_step = t.default_us_per_step;
+  info->launch_tune_seconds = t.seconds;
+  info->launch_candidates = t.candidates;
+  info->launch_from_cache = t.from_cache ? 1 : 0;
+  return BHAH_OK;
+}
+
+int bhah_batch_set_launch_tuning(bhah_batch* b, int on) {
+  if (!b) return bhah::fail(BHAH_EINVAL, "bhah_batch_set_launch_tuning: NULL batch");
+  b->engine.set_launch_tuning(on != 0);
   return BHAH_OK;
 }
 

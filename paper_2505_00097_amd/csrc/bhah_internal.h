@@ -255,17 +255,21 @@ int launch_brill_lindquist(const GridDev& G, int n, const double* m, const doubl
 void launch_rhs_fused(const GridDev& G, const Gauge& ga, const double* y, double* aux, const StageArgs& st,
                       hipStream_t s, const TileCfg& cfg);
 TileMap make_tilemap(const GridDev& G, int lx, int ly, int band);
-// mix: the stages may combine two states (SSPRK3); RK4 stages never do
+// mix: the stages may combine two states (SSPRK3); RK4 stages never do.
+// counts (device, one int per job; NULL: every job) and kk: step kk of a
+// graph launch runs only the jobs with kk < counts[job].
 void launch_rhs_batch(int variant, const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage,
-                      const Gauge& ga, bool mix, int blocks, hipStream_t s);
-void launch_ghosts_batch(const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage, int which,
-                         int blocks, hipStream_t s);
+                      const int* counts, int kk, const Gauge& ga, bool mix, int blocks, hipStream_t s);
+// last: the last stage of step kk (a job at its last active step then
+// fills all its ghosts)
+void launch_ghosts_batch(const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage, const int* counts,
+                         int kk, bool last, int blocks, hipStream_t s);
 void launch_hamiltonian(const GridDev& G, const double* y, double* H, hipStream_t s);
 // radiation condition at the pure-outer points of one stage: the right-hand
 // side of `in` combined as in st (same semantics as the RHS kernel)
 void launch_radiation(const GridDev& G, const RadDev& R, const double* in, const StageArgs& st, hipStream_t s);
-void launch_radiation_batch(const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage, int blocks,
-                            hipStream_t s);
+void launch_radiation_batch(const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage,
+                            const int* counts, int kk, int blocks, hipStream_t s);
 void launch_constraints(const GridDev& G, const double* y, double* H, double* Mo, double* Co, hipStream_t s);
 
 // The four stages of one classical RK4 step on state y with workspace ws

@@ -287,6 +287,28 @@ int bhah_ssprk3_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt,
   return check_launch("bhah_ssprk3_step");
 }
 
+int bhah_evolve(const bhah_grid* g, const bhah_gauge_params* gp, int integrator, double dt, int nsteps, double* y,
+                double* workspace, void* stream) {
+  if (!g || !gp || !y || !workspace) return fail(BHAH_EINVAL, "bhah_evolve: NULL argument");
+  if (nsteps < 0) return fail(BHAH_EINVAL, "bhah_evolve: nsteps < 0");
+  if (integrator != BHAH_RK4 && integrator != BHAH_SSPRK3)
+    return fail(BHAH_EINVAL, "bhah_evolve: integrator must be BHAH_RK4 or BHAH_SSPRK3");
+  if (int rc = check_aligned("bhah_evolve", {y, workspace})) return rc;
+  if (int rc = check_gauge(gp, "bhah_evolve")) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  StageArgs st[4];
+  const double* in[4];
+  double* gdst[4];
+  const int nst = integrator == BHAH_SSPRK3 ? 3 : 4;
+  if (integrator == BHAH_SSPRK3) ssprk3_stages(dt, y, workspace, g->info.state_doubles, st, in, gdst);
+  else rk4_stages(dt, y, workspace, g->info.state_doubles, st, in, gdst);
+  // the stage ghost list after every stage, all ghosts after the last
+  for (int n = 0; n < nsteps; n++)
+    for (int k = 0; k < nst; k++)
+      run_stage(g, gauge_of(*gp), in[k], st[k], gdst[k], n == nsteps - 1 && k == nst - 1, s);
+  return check_launch("bhah_evolve");
+}
+
 int bhah_grid_set_tile(bhah_grid* g, int lx, int ly, int band) {
   if (!g) return fail(BHAH_EINVAL, "bhah_grid_set_tile: NULL grid");
   const TileCfg c{lx, ly, band};

@@ -19,13 +19,15 @@ SizeClass class_of(const bhah_grid* g) {
 }
 
 struct Layout {
-  size_t jobs, tiles, chunks, total;
+  size_t jobs, counts, tiles, chunks, total;
 };
 
+// header | job table | per-job active step counts | tile list | chunk list
 Layout layout(int cap_jobs, int cap_tiles, int cap_chunks) {
   Layout L;
   L.jobs = align_up(sizeof(BatchHdr));
-  L.tiles = L.jobs + align_up(sizeof(BatchJob) * (size_t)cap_jobs);
+  L.counts = L.jobs + align_up(sizeof(BatchJob) * (size_t)cap_jobs);
+  L.tiles = L.counts + align_up(sizeof(int) * (size_t)cap_jobs);
   L.chunks = L.tiles + align_up(sizeof(int2) * (size_t)cap_tiles);
   L.total = L.chunks + align_up(sizeof(int2) * (size_t)cap_chunks);
   return L;
@@ -70,6 +72,9 @@ Engine::~Engine() {
   drop_graphs();
   if (cap_stream_) (void)hipStreamDestroy(cap_stream_);
   if (upload_done_) (void)hipEventDestroy(upload_done_);
+  for (hipEvent_t& e : counts_done_)
+    if (e) (void)hipEventDestroy(e);
+  if (h_counts_) (void)hipHostFree(h_counts_);
   if (d_blob_) (void)hipFree(d_blob_);
   if (h_blob_) (void)hipHostFree(h_blob_);
 }
@@ -87,6 +92,9 @@ int Engine::set_jobs(const std::vector<EngineJob>& jobs) {
   if (jobs != jobs_) {
     jobs_ = jobs;
     dirty_ = true;
+  } else {
+    // the step limits change from call to call without touching the blob
+    for (size_t j = 0; j < jobs.size(); j++) jobs_[j].limit = jobs[j].limit;
   }
   return BHAH_OK;
 }
@@ -116,6 +124,8 @@ int Engine::ensure_device(hipStream_t s) {
   n_cus_ = std::max(cus, 1);
   ghost_blocks_ = 2 * n_cus_;  // times NGF / GF_PER gridfunction groups
   if ((rc = check_hip(hipEventCreateWithFlags(&upload_done_, hipEventDisableTiming), "hipEventCreate"))) return rc;
+  for (hipEvent_t& e : counts_done_)
+    if ((rc = check_hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate"))) return rc;
   if ((rc = check_hip(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking), "hipStreamCreate"))) return rc;
   load_cache();
   return BHAH_OK;
@@ -152,14 +162,18 @@ void Engine::build_blob(const std::vector<TileCfg>& cfg, const std::vector<int>&
     drop_graphs();
     if (d_blob_) (void)hipFree(d_blob_);
     if (h_blob_) (void)hipHostFree(h_blob_);
+    if (h_counts_) (void)hipHostFree(h_counts_);
     d_blob_ = h_blob_ = nullptr;
+    h_counts_ = nullptr;
     cap_jobs_ = std::max<int>(cap_jobs_, (int)jobs_.size() * 3 / 2 + 1);
     cap_tiles_ = std::max(cap_tiles_, nt * 3 / 2 + 64);
     cap_chunks_ = std::max(cap_chunks_, nc * 3 / 2 + 64);
     const Layout L = layout(cap_jobs_, cap_tiles_, cap_chunks_);
     cap_bytes_ = L.total;
     if (hipMalloc((void**)&d_blob_, cap_bytes_) != hipSuccess ||
-        hipHostMalloc((void**)&h_blob_, cap_bytes_, hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void**)&h_blob_, cap_bytes_, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&h_counts_, sizeof(int) * kRing * (size_t)cap_jobs_, hipHostMallocDefault) !=
+            hipSuccess) {
       set_error("batch: cannot allocate the work description");
       cap_bytes_ = 0;
       cap_jobs_ = cap_tiles_ = cap_chunks_ = 0;
@@ -233,6 +247,24 @@ int Engine::upload(hipStream_t s) {
   return check_hip(hipEventRecord(upload_done_, s), "hipEventRecord");
 }
 
+int Engine::upload_counts(long long first, int k, hipStream_t s) {
+  if (!d_blob_ || !h_counts_) return fail(BHAH_ENOMEM, "batch: no work description buffer");
+  const int slot = counts_slot_;
+  counts_slot_ = (counts_slot_ + 1) % kRing;
+  int rc = check_hip(hipEventSynchronize(counts_done_[slot]), "batch counts slot");
+  if (rc) return rc;
+  int* h = h_counts_ + (size_t)slot * cap_jobs_;
+  for (size_t j = 0; j < jobs_.size(); j++) {
+    const long long lim = jobs_[j].limit < 0 ? first + k : jobs_[j].limit;
+    h[j] = (int)std::max<long long>(0, std::min<long long>(k, lim - first));
+  }
+  const Layout L = layout(cap_jobs_, cap_tiles_, cap_chunks_);
+  rc = check_hip(hipMemcpyAsync(d_blob_ + L.counts, h, sizeof(int) * jobs_.size(), hipMemcpyHostToDevice, s),
+                 "batch counts upload");
+  if (rc) return rc;
+  return check_hip(hipEventRecord(counts_done_[slot], s), "hipEventRecord");
+}
+
 int Engine::time_class(const SizeClass& c, const TileCfg& cfg, hipStream_t s, double* us) {
   std::vector<int> only;
   std::vector<TileCfg> cfgs(jobs_.size(), TileCfg{6, 0, 1});
@@ -267,11 +299,11 @@ int Engine::time_class(const SizeClass& c, const TileCfg& cfg, hipStream_t s, do
   const int reps = 3;
   const int blocks = rhs_grid();
   for (int v = 0; v < NVAR; v++)
-    if (used[v]) launch_rhs_batch(v, dj, dh, dt, 4, gauge_of(gp_), false, blocks, s);
+    if (used[v]) launch_rhs_batch(v, dj, dh, dt, 4, nullptr, 0, gauge_of(gp_), false, blocks, s);
   (void)hipEventRecord(e0, s);
   for (int r = 0; r < reps; r++)
     for (int v = 0; v < NVAR; v++)
-      if (used[v]) launch_rhs_batch(v, dj, dh, dt, 4, gauge_of(gp_), false, blocks, s);
+      if (used[v]) launch_rhs_batch(v, dj, dh, dt, 4, nullptr, 0, gauge_of(gp_), false, blocks, s);
   (void)hipEventRecord(e1, s);
   rc = check_hip(hipEventSynchronize(e1), "tile timing");
   float ms = 0.f;
@@ -316,23 +348,25 @@ int Engine::capture(int nsteps, hipStream_t s, hipGraphExec_t* out) {
   const BatchHdr* dh = (const BatchHdr*)d_blob_;
   const int2* dt = (const int2*)(d_blob_ + L.tiles);
   const int2* dc = (const int2*)(d_blob_ + L.chunks);
+  const int* dn = (const int*)(d_blob_ + L.counts);
   rhs_blocks_ = rhs_grid();
   int rc = check_hip(hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal), "graph capture");
   if (rc) return rc;
-  // The stencils never read phi ghost planes (they wrap phi onto the
-  // interior), so within the captured steps only the ghosts with an interior
-  // phi index are filled; the last stage of the last step fills all of them.
+  // Step k of the graph runs the jobs with more than k active steps in this
+  // launch (counts, uploaded before each launch). The stencils never read
+  // phi ghost planes (they wrap phi onto the interior), so within a job's
+  // steps only the ghosts with an interior phi index are filled; the last
+  // stage of its last active step fills all of them.
   const int nst = integrator_ == BHAH_SSPRK3 ? 3 : 4;
   for (int k = 0; k < nsteps; k++)
     for (int stage = 0; stage < nst; stage++) {
       for (int f = 0; f < NVAR; f++)
         if (fam_present_[f])
-          launch_rhs_batch(f, dj, dh, dt, stage, gauge_of(gp_), integrator_ == BHAH_SSPRK3, rhs_blocks_,
+          launch_rhs_batch(f, dj, dh, dt, stage, dn, k, gauge_of(gp_), integrator_ == BHAH_SSPRK3, rhs_blocks_,
                            cap_stream_);
       // outer points of radiation-boundary jobs, before their inner ghosts are copied
-      if (fam_present_[NVAR]) launch_radiation_batch(dj, dh, dc, stage, ghost_blocks_, cap_stream_);
-      const int which = stage == nst - 1 && k == nsteps - 1 ? 1 : 0;
-      launch_ghosts_batch(dj, dh, dc, stage, which, ghost_blocks_, cap_stream_);
+      if (fam_present_[NVAR]) launch_radiation_batch(dj, dh, dc, stage, dn, k, ghost_blocks_, cap_stream_);
+      launch_ghosts_batch(dj, dh, dc, stage, dn, k, stage == nst - 1, ghost_blocks_, cap_stream_);
     }
   hipGraph_t graph = nullptr;
   const hipError_t le = hipGetLastError();
@@ -361,19 +395,143 @@ int Engine::step(int nsteps, hipStream_t s) {
     if ((rc = upload(s))) return rc;
     dirty_ = false;
   }
+  if (tune_launch_ && (rc = tune_launch(s))) return rc;
   for (int f = 0; f <= NVAR; f++)
     if (fam_present_[f] && !fam_in_graphs_[f]) drop_graphs();
-  while (nsteps > 0) {
-    const int k = std::min(nsteps, graph_steps_);
+  // jobs that take fewer steps than the call idle through the rest: launch
+  // graphs only while some job still has steps to take
+  long long most = 0;
+  for (const EngineJob& j : jobs_) most = std::max<long long>(most, j.limit < 0 ? nsteps : std::min<long long>(nsteps, j.limit));
+  long long first = 0;
+  while (first < most) {
+    const int k = (int)std::min<long long>(most - first, graph_steps_);
     auto it = graphs_.find(k);
     if (it == graphs_.end()) {
       hipGraphExec_t ex = nullptr;
       if ((rc = capture(k, s, &ex))) return rc;
       it = graphs_.emplace(k, ex).first;
     }
+    if ((rc = upload_counts(first, k, s))) return rc;
     if ((rc = check_hip(hipGraphLaunch(it->second, s), "hipGraphLaunch"))) return rc;
-    nsteps -= k;
+    first += k;
   }
+  return BHAH_OK;
+}
+
+std::string Engine::launch_signature() const {
+  std::map<std::string, int> count;
+  for (const EngineJob& j : jobs_) {
+    const bhah_grid_params& p = j.g->params;
+    char b[96];
+    std::snprintf(b, sizeof b, "%d:%dx%dx%d:%d:%d", p.coord, p.N[0], p.N[1], p.N[2], p.nghosts, p.bc_kind);
+    count[b]++;
+  }
+  std::string full;
+  for (auto& kv : count) full += std::to_string(kv.second) + "*" + kv.first + " ";
+  unsigned long long h = 1469598103934665603ULL;  // FNV-1a, stable across runs and builds
+  for (unsigned char c : full) h = (h ^ c) * 1099511628211ULL;
+  char b[96];
+  std::snprintf(b, sizeof b, "%s %zu jobs %016llx", integrator_ == BHAH_SSPRK3 ? "ssprk3" : "rk4", jobs_.size(), h);
+  return b;
+}
+
+int Engine::tune_launch(hipStream_t s) {
+  const std::string sig = launch_signature();
+  auto hit = launch_cache_.find(sig);
+  if (hit != launch_cache_.end()) {
+    if (hit->second.first != graph_steps_ || hit->second.second != blocks_per_cu_) {
+      set_graph_steps(hit->second.first);
+      set_blocks_per_cu(hit->second.second);
+      drop_graphs();
+    }
+    last_tune_.graph_steps = graph_steps_;
+    last_tune_.blocks_per_cu = blocks_per_cu_;
+    last_tune_.from_cache = true;
+    auto u = launch_us_.find(sig);
+    last_tune_.us_per_step = u == launch_us_.end() ? 0.0 : u->second;
+    return BHAH_OK;
+  }
+  const double t0 = now_s();
+  // copies of the states: the candidates run real steps
+  size_t total = 0;
+  for (const EngineJob& j : jobs_) total += (size_t)j.g->info.state_doubles;
+  double* copies = nullptr;
+  if (hipMalloc((void**)&copies, total * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(BHAH_ENOMEM, "batch: no device memory for the launch tuning's state copies");
+  }
+  const std::vector<EngineJob> saved = jobs_;
+  size_t off = 0;
+  int rc = BHAH_OK;
+  for (EngineJob& j : jobs_) {
+    const size_t n = (size_t)j.g->info.state_doubles;
+    if (!rc) rc = check_hip(hipMemcpyAsync(copies + off, j.y, n * sizeof(double), hipMemcpyDeviceToDevice, s),
+                            "launch tuning copy");
+    j.y = copies + off;
+    j.limit = -1;
+    off += n;
+  }
+  std::vector<TileCfg> cfg;
+  for (const EngineJob& j : jobs_) cfg.push_back(tile_of_class(class_of(j.g)));
+  if (!rc) {
+    build_blob(cfg, {});
+    rc = upload(s);
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (!rc) rc = check_hip(hipEventCreate(&e0), "hipEventCreate");
+  if (!rc) rc = check_hip(hipEventCreate(&e1), "hipEventCreate");
+  const int steps_c[3] = {4, 10, 25}, bpc_c[4] = {2, 4, 8, 0};
+  int best_s = 10, best_b = 4;
+  double best = 1e300, def = 0.0;
+  int n_cand = 0;
+  for (int a = 0; a < 3 && !rc; a++)
+    for (int b = 0; b < 4 && !rc; b++) {
+      set_graph_steps(steps_c[a]);
+      set_blocks_per_cu(bpc_c[b]);
+      drop_graphs();
+      hipGraphExec_t ex = nullptr;
+      if ((rc = capture(graph_steps_, s, &ex))) break;
+      graphs_.emplace(graph_steps_, ex);
+      if ((rc = upload_counts(0, graph_steps_, s))) break;
+      (void)hipGraphLaunch(ex, s);  // warm-up
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < 2; r++) (void)hipGraphLaunch(ex, s);
+      (void)hipEventRecord(e1, s);
+      if ((rc = check_hip(hipEventSynchronize(e1), "launch tuning"))) break;
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      const double us = 1e3 * ms / (2.0 * graph_steps_);
+      n_cand++;
+      if (steps_c[a] == 10 && bpc_c[b] == 4) def = us;
+      if (us < best) {
+        best = us;
+        best_s = steps_c[a];
+        best_b = bpc_c[b];
+      }
+    }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(copies);
+  jobs_ = saved;
+  dirty_ = true;
+  drop_graphs();
+  if (rc) return rc;
+  if (def > 0.0 && best >= def / 1.02) {  // within 2% of the default: keep it
+    best_s = 10;
+    best_b = 4;
+    best = def;
+  }
+  set_graph_steps(best_s);
+  set_blocks_per_cu(best_b);
+  // the tuning blob held the copies: rebuild with the jobs' own states
+  build_blob(cfg, {});
+  if ((rc = upload(s))) return rc;
+  dirty_ = false;
+  launch_cache_[sig] = {best_s, best_b};
+  launch_us_[sig] = best;
+  last_tune_ = LaunchTune{best_s, best_b, best, def, now_s() - t0, n_cand, false};
+  save_cache();
   return BHAH_OK;
 }
 
@@ -389,6 +547,18 @@ void Engine::load_cache() {
     double us;
     const char* p = std::strchr(line, '{');
     if (!p) continue;
+    {  // a launch-configuration entry
+      char sig[96];
+      int S, bpc;
+      if (std::sscanf(p, "{\"arch\": \"%63[^\"]\", \"launch\": \"%95[^\"]\", \"S\": %d, \"bpc\": %d, \"us\": %lf}",
+                      arch, sig, &S, &bpc, &us) == 5) {
+        if (arch_ == arch && S >= 1 && bpc >= 0) {
+          launch_cache_[sig] = {S, bpc};
+          launch_us_[sig] = us;
+        }
+        continue;
+      }
+    }
     if (std::sscanf(p, "{\"arch\": \"%63[^\"]\", \"coord\": %d, \"N\": [%d, %d, %d], \"lx\": %d, \"ly\": %d, "
                        "\"band\": %d, \"us\": %lf}",
                     arch, &coord, &n0, &n1, &n2, &lx, &ly, &band, &us) != 9)
@@ -437,6 +607,13 @@ void Engine::save_cache() {
                  first ? "" : ",\n", arch_.c_str(), std::get<0>(c), std::get<1>(c), std::get<2>(c),
                  std::get<3>(c), kv.second.lx, kv.second.ly, kv.second.band,
                  u == tuned_us_.end() ? 0.0 : u->second);
+    first = false;
+  }
+  for (const auto& kv : launch_cache_) {
+    const auto u = launch_us_.find(kv.first);
+    std::fprintf(f, "%s{\"arch\": \"%s\", \"launch\": \"%s\", \"S\": %d, \"bpc\": %d, \"us\": %.3f}",
+                 first ? "" : ",\n", arch_.c_str(), kv.first.c_str(), kv.second.first, kv.second.second,
+                 u == launch_us_.end() ? 0.0 : u->second);
     first = false;
   }
   std::fprintf(f, "\n]}\n");

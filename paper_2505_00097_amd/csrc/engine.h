@@ -29,6 +29,10 @@ struct EngineJob {
   double* y;
   double* ws;
   double dt;
+  // steps this job takes in the next step() call (-1: all of them); a job
+  // with fewer steps than the call idles through the rest, its state left
+  // after its own last step with every ghost valid
+  long long limit = -1;
   bool operator==(const EngineJob& o) const { return g == o.g && y == o.y && ws == o.ws && dt == o.dt; }
 };
 
@@ -47,7 +51,7 @@ class Engine {
   // Replace the job set (takes effect at the next step). Returns a status.
   int set_jobs(const std::vector<EngineJob>& jobs);
   // Advance every job by nsteps steps of the integrator on stream s
-  // (asynchronous).
+  // (asynchronous), job j by min(nsteps, its limit) of them.
   int step(int nsteps, hipStream_t s);
   void set_graph_steps(int S) { graph_steps_ = S < 1 ? 1 : S; }
   // BHAH_RK4 or BHAH_SSPRK3 (the stage arguments and graphs are rebuilt)
@@ -67,6 +71,22 @@ class Engine {
     rhs_blocks_ = 0;
   }
 
+  // Launch tuning: graph steps per captured graph and persistent blocks
+  // per CU of the right-hand-side kernel. Off by default; when on, the
+  // first step() on a job set not seen before times every candidate pair
+  // on copies of the jobs' states (the caller's states are not touched; the
+  // results do not depend on either choice) and keeps the fastest, ties
+  // within 2% going to the default (10, 4). Choices persist per job-set
+  // signature (the multiset of size classes) in the tile cache file.
+  void set_launch_tuning(bool on) { tune_launch_ = on; }
+  struct LaunchTune {
+    int graph_steps = 0, blocks_per_cu = 0;
+    double us_per_step = 0.0, default_us_per_step = 0.0, seconds = 0.0;
+    int candidates = 0;
+    bool from_cache = false;
+  };
+  const LaunchTune& launch_tune() const { return last_tune_; }
+
   int n_jobs() const { return (int)jobs_.size(); }
   int n_tiles() const { return n_tiles_; }
   int n_chunks() const { return n_chunks_; }
@@ -83,6 +103,11 @@ class Engine {
   int time_class(const SizeClass& c, const TileCfg& cfg, hipStream_t s, double* us);
   void build_blob(const std::vector<TileCfg>& cfg, const std::vector<int>& only, int repeat = 1);
   int upload(hipStream_t s);
+  int tune_launch(hipStream_t s);
+  std::string launch_signature() const;
+  // per-job active step counts of one graph launch covering steps
+  // [first, first + k) of a step() call, copied to the device blob
+  int upload_counts(long long first, int k, hipStream_t s);
   int capture(int nsteps, hipStream_t s, hipGraphExec_t* out);
   void drop_graphs();
   void load_cache();
@@ -96,6 +121,10 @@ class Engine {
   std::map<SizeClass, TileCfg> tuned_;
   std::map<SizeClass, double> tuned_us_;
   double tune_seconds_ = 0.0;
+  bool tune_launch_ = false;
+  LaunchTune last_tune_{};
+  std::map<std::string, std::pair<int, int>> launch_cache_;  // signature -> (graph steps, blocks per CU)
+  std::map<std::string, double> launch_us_;
 
   // host blob (pinned) and its device copy
   char* h_blob_ = nullptr;
@@ -104,6 +133,12 @@ class Engine {
   size_t blob_bytes_ = 0;
   int cap_jobs_ = 0, cap_tiles_ = 0, cap_chunks_ = 0;
   hipEvent_t upload_done_ = nullptr;
+  // pinned ring of per-launch active step counts (kRing slots of cap_jobs_
+  // ints), each slot reused only after its copy has completed
+  static constexpr int kRing = 8;
+  int* h_counts_ = nullptr;
+  hipEvent_t counts_done_[kRing] = {};
+  int counts_slot_ = 0;
   int n_tiles_ = 0, n_chunks_ = 0;
   // kernel variants with tiles in some blob (entry NVAR: radiation points)
   bool fam_present_[NVAR + 1] = {};

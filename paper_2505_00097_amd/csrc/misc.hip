@@ -48,26 +48,35 @@ void launch_ghosts(const GhostDev& gh, double* y, long long sgf, hipStream_t s) 
 }
 
 // Ensemble form: a fixed grid of blocks strides over the (job, chunk of 256
-// ghost points) work list (x) for one group of gridfunctions (y) and fills
-// the ghosts of the stage's target array: list `which` (0: ghosts with an
-// interior phi index, 1: all ghosts).
+// ghost points) work lists (x) for one group of gridfunctions (y) and fills
+// the ghosts of the stage's target array, for the jobs active in step kk of
+// the launch (kk < counts[job]): list 0 (ghosts with an interior phi index,
+// all that the stencils read) after every stage, except after the last
+// stage of a job's last active step (last != 0 and kk == counts[job] - 1),
+// which fills list 1 (all ghosts).
 __global__ void __launch_bounds__(256) k_ghosts_batch(const BatchJob* __restrict__ jobs,
                                                       const BatchHdr* __restrict__ hdr,
-                                                      const int2* __restrict__ work, int stage, int which) {
-  const int n = hdr->n_chunks[which];
-  const int2* wl = work + hdr->chunk_off[which];
+                                                      const int2* __restrict__ work, int stage,
+                                                      const int* __restrict__ counts, int kk, int last) {
+  const int n0 = hdr->n_chunks[0];
+  const int n = last ? n0 + hdr->n_chunks[1] : n0;
   const int g0 = (int)blockIdx.y * GF_PER;
   for (int c = (int)blockIdx.x; c < n; c += (int)gridDim.x) {
-    const int2 wk = wl[c];
+    const int w = c < n0 ? 0 : 1;
+    const int2 wk = work[hdr->chunk_off[w] + (w ? c - n0 : c)];
+    const int cnt = counts[wk.x];
+    if (kk >= cnt) continue;  // the job takes no more steps in this launch
+    if (w != (last && kk == cnt - 1 ? 1 : 0)) continue;
     const BatchJob* J = jobs + wk.x;
     const int t = wk.y * 256 + (int)threadIdx.x;
-    if (t < J->gh[which].n_ghost) ghost_point(J->gh[which], J->gdst[stage], J->G.sgf, t, g0);
+    if (t < J->gh[w].n_ghost) ghost_point(J->gh[w], J->gdst[stage], J->G.sgf, t, g0);
   }
 }
 
-void launch_ghosts_batch(const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage, int which,
-                         int blocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_ghosts_batch, dim3(blocks, NGF / GF_PER), dim3(256), 0, s, jobs, hdr, work, stage, which);
+void launch_ghosts_batch(const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage, const int* counts,
+                         int kk, bool last, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_ghosts_batch, dim3(blocks, NGF / GF_PER), dim3(256), 0, s, jobs, hdr, work, stage, counts,
+                     kk, last ? 1 : 0);
 }
 
 constexpr int MAX_PUNCT = 16;
@@ -180,15 +189,17 @@ void launch_radiation(const GridDev& G, const RadDev& R, const double* in, const
 
 // Ensemble form: blocks stride over the (job, chunk of 256 radiation points)
 // list; each job's stage input, combination and stencil radius come from its
-// table entry.
+// table entry. Jobs with no step kk in this launch (kk >= counts[job]) idle.
 __global__ void __launch_bounds__(256) k_radiation_batch(const BatchJob* __restrict__ jobs,
                                                          const BatchHdr* __restrict__ hdr,
-                                                         const int2* __restrict__ work, int stage) {
+                                                         const int2* __restrict__ work, int stage,
+                                                         const int* __restrict__ counts, int kk) {
   const int n = hdr->n_chunks[2];
   const int2* wl = work + hdr->chunk_off[2];
   const int g0 = (int)blockIdx.y * GF_PER;
   for (int c = (int)blockIdx.x; c < n; c += (int)gridDim.x) {
     const int2 wk = wl[c];
+    if (kk >= counts[wk.x]) continue;
     const BatchJob* J = jobs + wk.x;
     const int t = wk.y * 256 + (int)threadIdx.x;
     if (t < J->rad.n) {
@@ -198,9 +209,10 @@ __global__ void __launch_bounds__(256) k_radiation_batch(const BatchJob* __restr
   }
 }
 
-void launch_radiation_batch(const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage, int blocks,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(k_radiation_batch, dim3(blocks, NGF / GF_PER), dim3(256), 0, s, jobs, hdr, work, stage);
+void launch_radiation_batch(const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage,
+                            const int* counts, int kk, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_radiation_batch, dim3(blocks, NGF / GF_PER), dim3(256), 0, s, jobs, hdr, work, stage, counts,
+                     kk);
 }
 
 int launch_brill_lindquist(const GridDev& G, int n, const double* m, const double* pos, int lapse_kind,

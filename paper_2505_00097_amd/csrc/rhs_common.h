@@ -181,9 +181,13 @@ __device__ __forceinline__ Spacing make_spacing(const GridDev& G) {
 // ---- centred finite differences (Sec. 3) on gathered values:
 //   axis : v[R + m] = f(m) along one direction, m = -R..R
 //   cross: v[2R a + b] = f(m_a, n_b) for m, n in {-R..-1, 1..R}, a-major
-// Sums are grouped into differences so constant fields have exactly zero
-// first derivatives (the 4th-order second differences sum to zero as well;
-// at 8th order the centre weight is applied as a difference too).
+// Sums are grouped into differences: first differences pair f(j) with
+// f(-j), second differences take f(j) - f(0) and f(-j) - f(0) before any
+// weight. Constant fields then have exactly zero derivatives, and the
+// subtractions of nearby values are exact, so the rounding error stays of
+// the size of the differences rather than of |f| / h^2 (an ungrouped
+// 16 (f1 + f-1) - (f2 + f-2) - 30 f0 loses about 30 eps |f| / h^2 where f
+// is nearly constant, far above 1e-12 of the result on fine sinh cells).
 template <int R>
 __device__ __forceinline__ double d1_axis(const double (&v)[2 * R + 1], double s) {
   double a = FdW<R>::d1[1] * (v[R + 1] - v[R - 1]);
@@ -193,14 +197,10 @@ __device__ __forceinline__ double d1_axis(const double (&v)[2 * R + 1], double s
 }
 template <int R>
 __device__ __forceinline__ double d2_axis(const double (&v)[2 * R + 1], double s) {
-  if constexpr (R == 2) {
-    return (16.0 * (v[3] + v[1]) - (v[4] + v[0]) - 30.0 * v[2]) * s;
-  } else {
-    double a = FdW<R>::d2[1] * ((v[R + 1] - v[R]) + (v[R - 1] - v[R]));
+  double a = FdW<R>::d2[1] * ((v[R + 1] - v[R]) + (v[R - 1] - v[R]));
 #pragma unroll
-    for (int j = 2; j <= R; j++) a += FdW<R>::d2[j] * ((v[R + j] - v[R]) + (v[R - j] - v[R]));
-    return a * s;
-  }
+  for (int j = 2; j <= R; j++) a += FdW<R>::d2[j] * ((v[R + j] - v[R]) + (v[R - j] - v[R]));
+  return a * s;
 }
 // index of offset m (m != 0) in a cross-stencil row
 template <int R>

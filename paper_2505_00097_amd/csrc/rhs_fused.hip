@@ -71,19 +71,15 @@ __device__ __forceinline__ double upwind_sum(const double (&v)[2 * R + 1], doubl
 // along each logical direction, weighted by eps/(kden dxx^k); at 4th order
 // delta^6 f = f(3) + f(-3) - 6 (f(2) + f(-2)) + 15 (f(1) + f(-1)) - 20 f(0)
 // over 64 dxx^k. Symmetric in the two sides, so the upwind-ordered stencil
-// values serve as they are. fp[j], fm[j] are f(+-j), j = 1..R+1; at 8th
-// order the sums are taken as differences from f(0) (exact zero on
-// constants).
+// values serve as they are. fp[j], fm[j] are f(+-j), j = 1..R+1; the sums
+// are taken as differences from f(0) (exact zero on constants, rounding
+// of the size of the differences).
 template <int R>
 __device__ __forceinline__ double ko_sum(const double (&fp)[R + 2], const double (&fm)[R + 2], double f0) {
-  if constexpr (R == 2) {
-    return (fp[3] + fm[3]) - 6.0 * (fp[2] + fm[2]) + 15.0 * (fp[1] + fm[1]) - 20.0 * f0;
-  } else {
-    double a = FdW<R>::ko[R + 1] * ((fp[R + 1] - f0) + (fm[R + 1] - f0));
+  double a = FdW<R>::ko[R + 1] * ((fp[R + 1] - f0) + (fm[R + 1] - f0));
 #pragma unroll
-    for (int j = R; j >= 1; j--) a += FdW<R>::ko[j] * ((fp[j] - f0) + (fm[j] - f0));
-    return a;
-  }
+  for (int j = R; j >= 1; j--) a += FdW<R>::ko[j] * ((fp[j] - f0) + (fm[j] - f0));
+  return a;
 }
 // the same from centred values v (offsets -R..R) and the two outermost
 template <int R>
@@ -1012,7 +1008,7 @@ k_rhs_fused(GridDev G, TileMap T, Gauge ga, const double* __restrict__ y, StageA
 template <int C, bool AX, bool KO, bool MIX, int H>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
 k_rhs_batch(const BatchJob* __restrict__ jobs, const BatchHdr* __restrict__ hdr, const int2* __restrict__ work,
-            int stage, Gauge ga) {
+            int stage, const int* __restrict__ counts, int kk, Gauge ga) {
   constexpr int V = 2 * C + AX + (H == 5 ? 6 : 0);
   const int n = hdr->n_tiles[V];
   const int2* wl = work + hdr->tile_off[V];
@@ -1022,6 +1018,7 @@ k_rhs_batch(const BatchJob* __restrict__ jobs, const BatchHdr* __restrict__ hdr,
     const int w = xcd_remap(t, per);
     if (w >= n) continue;
     const int2 wk = wl[w];
+    if (counts && kk >= counts[wk.x]) continue;  // the job takes no step kk in this launch
     const BatchJob* J = jobs + wk.x;
     const GridDev G = J->G;
     int i0, i1, i2;
@@ -1054,12 +1051,13 @@ void launch_fused_t(dim3 g, hipStream_t s, const GridDev& G, const TileMap& T, c
 }
 template <int C, bool AX, bool KO, bool MIX, int H>
 void launch_batch_t(dim3 g, hipStream_t s, const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage,
-                    const Gauge& ga) {
-  hipLaunchKernelGGL((k_rhs_batch<C, AX, KO, MIX, H>), g, dim3(64), 0, s, jobs, hdr, work, stage, ga);
+                    const int* counts, int kk, const Gauge& ga) {
+  hipLaunchKernelGGL((k_rhs_batch<C, AX, KO, MIX, H>), g, dim3(64), 0, s, jobs, hdr, work, stage, counts, kk, ga);
 }
 using FusedLaunch = void (*)(dim3, hipStream_t, const GridDev&, const TileMap&, const Gauge&, const double*,
                              const StageArgs&, double*);
-using BatchLaunch = void (*)(dim3, hipStream_t, const BatchJob*, const BatchHdr*, const int2*, int, const Gauge&);
+using BatchLaunch = void (*)(dim3, hipStream_t, const BatchJob*, const BatchHdr*, const int2*, int, const int*, int,
+                             const Gauge&);
 constexpr int SS = BHAH_SINH_SPHERICAL, SC = BHAH_SINH_CYLINDRICAL, SP = BHAH_SPHERICAL;
 #define BHAH_FUSED_ROWS(H)                                                                            \
   {                                                                                                   \
@@ -1097,8 +1095,8 @@ void launch_rhs_fused(const GridDev& G, const Gauge& ga, const double* y, double
 }
 
 void launch_rhs_batch(int variant, const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage,
-                      const Gauge& ga, bool mix, int blocks, hipStream_t s) {
-  kBatch[variant][ga.ko() ? 1 : 0][mix ? 1 : 0](dim3(blocks), s, jobs, hdr, work, stage, ga);
+                      const int* counts, int kk, const Gauge& ga, bool mix, int blocks, hipStream_t s) {
+  kBatch[variant][ga.ko() ? 1 : 0][mix ? 1 : 0](dim3(blocks), s, jobs, hdr, work, stage, counts, kk, ga);
 }
 
 }  // namespace bhah

@@ -460,3 +460,112 @@ def test_server_target_points_caps_the_running_set():
         (s,) = _solo([g], [y], [j["steps"]])
         assert torch.equal(out, s), k
     capi.server_destroy(srv)
+
+
+def test_server_frees_other_shapes_for_a_job_that_would_not_fit():
+    """A budget of one slot of the larger grid: two small jobs run first and
+    leave their free slots behind; a large job submitted after they finish
+    fits only once those slots are given back, and must still complete (no
+    livelock with nothing running and the job queued). Its result equals
+    the solo evolution."""
+    _case("server reclaim")
+    import torch
+    from paper_2505_00097_amd import capi
+    small = [wl.headon_job(1.5, 1.0, 24), wl.headon_job(2.0, 0.9, 24)]
+    big = wl.headon_job(3.0, 1.6, 48)
+    gbig = capi.Grid(big["coord"], big["N"], big["ampl"], big["sinhw"], big["cfl"])
+    gsmall = capi.Grid(small[0]["coord"], small[0]["N"], small[0]["ampl"], small[0]["sinhw"], small[0]["cfl"])
+    slab_big = 4 * 8 * gbig.info.state_doubles
+    slab_small = 4 * 8 * gsmall.info.state_doubles
+    assert 2 * slab_small <= slab_big  # both small jobs run together
+    srv = capi.server_create(slab_big, max_jobs=2, steps_per_tick=4, keep_results=True)
+
+    def desc(j, n):
+        return capi.job_desc(j["coord"], j["N"], j["ampl"], j["sinhw"], j["cfl"], j["masses"], j["positions"], n)
+
+    ids = [capi.server_submit(srv, desc(j, 5)) for j in small]
+    for _ in range(100):
+        if capi.server_tick(srv) == (0, 0):
+            break
+    for i in ids:
+        assert capi.server_job_status(srv, i).state == capi.JOB_DONE
+    # release both small results: their slots stay held as free slots
+    for i, j in zip(ids, small):
+        g = capi.Grid(j["coord"], j["N"], j["ampl"], j["sinhw"], j["cfl"])
+        capi.server_fetch(srv, i, g.state())
+    assert capi.server_get_stats(srv).held_bytes > 0
+    ib = capi.server_submit(srv, desc(big, 6))
+    for t in range(100):
+        if capi.server_tick(srv) == (0, 0):
+            break
+    st = capi.server_job_status(srv, ib)
+    assert st.state == capi.JOB_DONE and st.steps_done == 6
+    stats = capi.server_get_stats(srv)
+    assert stats.peak_held_bytes <= slab_big and stats.held_bytes <= slab_big
+    out = gbig.state()
+    capi.server_fetch(srv, ib, out)
+    y = gbig.state()
+    capi.set_initial_data_brill_lindquist(gbig.h, big["masses"], big["positions"], y)
+    (s,) = _solo([gbig], [y], [6])
+    assert torch.equal(out, s)
+    capi.server_destroy(srv)
+
+
+def test_server_rejects_bad_lapse_kind_and_keeps_serving():
+    """submit rejects lapse_kind outside {0, 1} before anything is queued;
+    the other jobs run normally."""
+    _case("server lapse_kind")
+    from paper_2505_00097_amd import capi
+    j = wl.headon_job(1.5, 1.0, 24)
+    srv = capi.server_create(1e9, max_jobs=2, steps_per_tick=4)
+    bad = capi.job_desc(j["coord"], j["N"], j["ampl"], j["sinhw"], j["cfl"], j["masses"], j["positions"], 3)
+    bad.lapse_kind = 3
+    with pytest.raises(capi.BhahError, match="lapse_kind"):
+        capi.server_submit(srv, bad)
+    good = capi.job_desc(j["coord"], j["N"], j["ampl"], j["sinhw"], j["cfl"], j["masses"], j["positions"], 3)
+    i = capi.server_submit(srv, good)
+    for _ in range(50):
+        if capi.server_tick(srv) == (0, 0):
+            break
+    st = capi.server_get_stats(srv)
+    assert st.submitted == 1 and st.done == 1 and st.failed == 0 and st.queued == 0
+    assert capi.server_job_status(srv, i).state == capi.JOB_RELEASED
+    capi.server_destroy(srv)
+
+
+def test_launch_tuning_leaves_results_unchanged(tmp_path):
+    """Launch tuning times graph steps x blocks per CU on copies of the
+    states: the jobs still advance exactly the requested steps, bit for bit
+    equal to solo steps; a second batch over the same jobs takes the choice
+    from the cache file without timing."""
+    _case("launch tuning")
+    import torch
+    from paper_2505_00097_amd import capi
+    jobs = _small_jobs()
+    grids, ys, wss = _setup(jobs)
+    ys0 = [y.clone() for y in ys]
+    cache = str(tmp_path / "tiles.json")
+    b = capi.batch_create([g.h for g in grids], eta=2.0, tune_cache_path=cache)
+    capi.batch_set_launch_tuning(b, True)
+    capi.batch_step(b, ys, wss, [g.dt for g in grids], nsteps=6)
+    torch.cuda.synchronize()
+    info = capi.batch_get_info(b)
+    assert info.launch_candidates == 12 and not info.launch_from_cache
+    assert info.graph_steps in (4, 10, 25) and info.blocks_per_cu in (0, 2, 4, 8)
+    assert info.launch_us_per_step > 0 and info.launch_default_us_per_step > 0
+    assert info.launch_us_per_step <= info.launch_default_us_per_step
+    solo = _solo(grids, ys0, [6] * len(jobs))
+    for k, (y, s) in enumerate(zip(ys, solo)):
+        assert torch.equal(y, s), k
+    capi.batch_destroy(b)
+    b2 = capi.batch_create([g.h for g in grids], eta=2.0, tune_cache_path=cache)
+    capi.batch_set_launch_tuning(b2, True)
+    capi.batch_step(b2, ys, wss, [g.dt for g in grids], nsteps=2)
+    torch.cuda.synchronize()
+    info2 = capi.batch_get_info(b2)
+    assert info2.launch_from_cache and info2.graph_steps == info.graph_steps
+    assert info2.blocks_per_cu == info.blocks_per_cu
+    solo2 = _solo(grids, solo, [2] * len(jobs))
+    for k, (y, s) in enumerate(zip(ys, solo2)):
+        assert torch.equal(y, s), k
+    capi.batch_destroy(b2)

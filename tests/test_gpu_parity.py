@@ -12,7 +12,7 @@ exact.
 import numpy as np
 import pytest
 
-from gpu_helpers import fmt, gf_errors, rounding_floor, to_cpu, to_gpu
+from gpu_helpers import check_parity, fmt, gf_errors, ld, to_cpu, to_gpu
 from oracle import oracle as orc
 from paper_2505_00097_amd import workloads as wl
 
@@ -143,33 +143,23 @@ def _states(name, og):
 @pytest.mark.parametrize("name", ["tiny", "sph_ragged", "cyl_ragged", "cyl_3d", "spherical"])
 def test_rhs_matches_oracle(name):
     g, og = _pair(name)
+    ol = og.twin()
     for label, y in _states(name, og):
         _print_case("rhs", name, label)
         ref = og.rhs(y, eta=2.0)
+        refl = ol.rhs(ld(y), eta=2.0)
         out, aux = _rhs_gpu(g, y)
         I = og.interior()
-        err = gf_errors(out, ref, I)
-        floor = rounding_floor(lambda v: og.rhs(v, eta=2.0), y, lambda a, b: gf_errors(a, b, I))
-        tol = np.maximum(RHS_TOL, floor)
-        print("  err", fmt(orc.GF_NAMES, err), flush=True)
-        print("  floor", fmt(orc.GF_NAMES, floor), flush=True)
-        assert np.all(err <= tol), (label, fmt(orc.GF_NAMES, err / tol))
+        check_parity(f"rhs {name} {label}", out, ref, refl, I, RHS_TOL, names=orc.GF_NAMES)
         if label == "flat":
             assert np.all(out[(slice(None),) + I] == 0.0)
         # the Ricci tensor the right-hand side used
         pts = np.array([og.flat(i0, i1, i2) for i2 in range(3, 3 + og.N[2]) for i1 in range(3, 3 + og.N[1])
                         for i0 in range(3, 3 + og.N[0])])
-        def ricci(v):
-            return og.rhs_points(v, pts, want_ricci=True)[1]
-
-        def rel(a, b):
-            sc = np.max(np.abs(b))
-            return np.max(np.abs(a - b), axis=0) / sc if sc > 0 else np.max(np.abs(a), axis=0)
-        ric = ricci(y)
+        ric = og.rhs_points(y, pts, want_ricci=True)[1]
+        ricl = ol.rhs_points(ld(y), pts, want_ricci=True)[1]
         gr = np.stack([aux[c].reshape(-1)[pts] for c in range(6)], -1)
-        rerr = rel(gr, ric)
-        rtol = np.maximum(RHS_TOL, rounding_floor(ricci, y, rel))
-        assert np.all(rerr <= rtol), (label, rerr, rtol)
+        check_parity(f"ricci {name} {label}", gr.T, ric.T, ricl.T, slice(None), RHS_TOL, groups=[range(6)])
 
 
 DISS = (0.99, 0.3)  # Kreiss-Oliger strengths of the paper's head-on run (gauge, metric)
@@ -187,20 +177,18 @@ def test_rhs_with_dissipation_matches_oracle(name):
     from paper_2505_00097_amd import capi
     g, og0 = _pair(name)
     og = _oracle_diss(name)
+    ol = og.twin()
     for label, y in _states(name, og):
         _print_case("rhs_diss", name, label)
         ref = og.rhs(y, eta=2.0)
+        refl = ol.rhs(ld(y), eta=2.0)
         yg = to_gpu(y)
         r = g.state()
         r.zero_()
         capi.bssn_rhs(g.h, yg, r, eta=2.0, diss=DISS)
         out = to_cpu(r)
         I = og.interior()
-        err = gf_errors(out, ref, I)
-        floor = rounding_floor(lambda v: og.rhs(v, eta=2.0), y, lambda a, b: gf_errors(a, b, I))
-        tol = np.maximum(RHS_TOL, floor)
-        print("  err", fmt(orc.GF_NAMES, err), flush=True)
-        assert np.all(err <= tol), (label, fmt(orc.GF_NAMES, err / tol))
+        check_parity(f"rhs+ko {name} {label}", out, ref, refl, I, RHS_TOL, names=orc.GF_NAMES)
         if label == "smooth_random":  # the dissipation is really on
             plain = og0.rhs(y, eta=2.0)
             assert np.max(np.abs(out - plain)[(slice(None),) + I]) > 1e3 * RHS_TOL * np.max(np.abs(plain))
@@ -217,32 +205,19 @@ def test_ssprk3_with_dissipation_matches_oracle(name, m, pos, steps):
     from paper_2505_00097_amd import capi
     g, _ = _pair(name)
     og = _oracle_diss(name)
+    ol = og.twin()
     y = g.state()
     capi.set_initial_data_brill_lindquist(g.h, m, pos, y)
     ws = g.workspace()
     yo = og.brill_lindquist(m, np.array(pos).reshape(-1, 3))
+    yl = ld(yo)
     dt = og.dt()
     for _ in range(steps):
         capi.ssprk3_step(g.h, y, ws, dt, eta=2.0, diss=DISS)
         og.ssprk3_step(yo, dt, eta=2.0)
-    out = to_cpu(y)
-    I = og.interior()
-    err = gf_errors(out, yo, I)
-    # the evolution's own rounding floor: the oracle's response, over the same
-    # steps, to one-ulp perturbations of the initial data (strong fields near
-    # the punctures amplify rounding differences step by step)
-    y0 = og.brill_lindquist(m, np.array(pos).reshape(-1, 3))
-
-    def evolve(v):
-        v = og.apply_bcs(v.copy())
-        for _ in range(steps):
-            og.ssprk3_step(v, dt, eta=2.0)
-        return v
-    floor = rounding_floor(evolve, y0, lambda a, b: gf_errors(a, b, I))
-    tol = np.maximum(EVOL_TOL, floor)
-    print("  err", fmt(orc.GF_NAMES, err), flush=True)
-    print("  floor", fmt(orc.GF_NAMES, floor), flush=True)
-    assert np.all(err <= tol), fmt(orc.GF_NAMES, err / tol)
+        ol.ssprk3_step(yl, dt, eta=2.0)
+    check_parity(f"ssprk3+ko {name} {steps} steps", to_cpu(y), yo, yl, og.interior(), EVOL_TOL,
+                 names=orc.GF_NAMES)
 
 
 def _pair_radiation(name):
@@ -258,6 +233,7 @@ def test_radiation_rhs_matches_oracle(name):
     pure-outer points too: both against the oracle."""
     from paper_2505_00097_amd import capi
     g, og = _pair_radiation(name)
+    ol = og.twin()
     kind, _, _ = g.bc_maps()
     k = kind.reshape(og.n[2], og.n[1], og.n[0])
     pts = (k == 0) | (k == 1)
@@ -266,63 +242,61 @@ def test_radiation_rhs_matches_oracle(name):
     for label, y in (("bl", bl), ("smooth_random", og.apply_bcs(wl.smooth_random_state(og.n, seed=21)))):
         _print_case("rhs_radiation", name, label)
         ref = og.rhs(y, eta=2.0)
+        refl = ol.rhs(ld(y), eta=2.0)
         yg = to_gpu(y)
         r = g.state()
         r.zero_()
         capi.bssn_rhs(g.h, yg, r, eta=2.0)
         out = to_cpu(r)
-        err = gf_errors(out, ref, pts)
-        floor = rounding_floor(lambda v: og.rhs(v, eta=2.0), y, lambda a, b: gf_errors(a, b, pts))
-        tol = np.maximum(RHS_TOL, floor)
-        print("  err", fmt(orc.GF_NAMES, err), flush=True)
-        assert np.all(err <= tol), (label, fmt(orc.GF_NAMES, err / tol))
+        check_parity(f"rhs radiation {name} {label}", out, ref, refl, pts, RHS_TOL, names=orc.GF_NAMES)
         # the outer points on their own, against their own magnitude
-        eo = gf_errors(out, ref, outer)
-        assert np.all(eo <= np.maximum(RHS_TOL, rounding_floor(lambda v: og.rhs(v, eta=2.0), y,
-                                                                lambda a, b: gf_errors(a, b, outer)))), eo
+        check_parity(f"rhs radiation outer {name} {label}", out, ref, refl, outer, RHS_TOL, names=orc.GF_NAMES)
 
 
-@pytest.mark.parametrize("name,steps", [("tiny", 100), ("cyl_ragged", 60)])
+@pytest.mark.parametrize("name,steps", [("tiny", 100), ("cyl_ragged", 30)])
 def test_radiation_rk4_evolution_matches_oracle(name, steps):
     _print_case("evolve_radiation", name, steps)
     from paper_2505_00097_amd import capi
     g, og = _pair_radiation(name)
+    ol = og.twin()
     m, pos = [0.5, 0.5], [(0, 0, 0.5), (0, 0, -0.5)]
     y = g.state()
     capi.set_initial_data_brill_lindquist(g.h, m, pos, y)
     ws = g.workspace()
     yo = og.brill_lindquist(m, np.array(pos).reshape(-1, 3))
+    yl = ld(yo)
     dt = og.dt()
     for _ in range(steps):
         capi.rk4_step(g.h, y, ws, dt, eta=2.0)
         og.rk4_step(yo, dt, eta=2.0)
-    out = to_cpu(y)
-    err = gf_errors(out, yo, (slice(None),) * 3)  # every point, ghosts included
-    print("  err", fmt(orc.GF_NAMES, err), flush=True)
-    assert np.all(err <= EVOL_TOL), fmt(orc.GF_NAMES, err)
+        ol.rk4_step(yl, dt, eta=2.0)
+    # every point, ghosts included
+    check_parity(f"rk4 radiation {name} {steps} steps", to_cpu(y), yo, yl, (slice(None),) * 3, EVOL_TOL,
+                 names=orc.GF_NAMES)
 
 
 def test_production_numerics_match_oracle():
     """The head-on run's numerics of Sec. 4.1 at 4th order: SSPRK3, Kreiss-
     Oliger dissipation 0.99 / 0.3 and the Sommerfeld outer boundary."""
-    _print_case("evolve_production", "cyl_ragged", 40)
+    _print_case("evolve_production", "cyl_ragged", 20)
     from paper_2505_00097_amd import capi
     coord, N, ampl, w = GRIDS["cyl_ragged"]
     g = capi.Grid(coord, N, ampl, w, bc_kind=capi.BC_RADIATION)
     og = orc.Grid(coord, N, ampl=ampl, sinhw=w, bc_kind=1, diss=DISS)
+    ol = og.twin()
     m, pos = [0.5, 0.5], [(0, 0, 0.5), (0, 0, -0.5)]
     y = g.state()
     capi.set_initial_data_brill_lindquist(g.h, m, pos, y)
     ws = g.workspace()
     yo = og.brill_lindquist(m, np.array(pos).reshape(-1, 3))
+    yl = ld(yo)
     dt = og.dt()
-    for _ in range(40):
+    for _ in range(20):
         capi.ssprk3_step(g.h, y, ws, dt, eta=2.0, diss=DISS)
         og.ssprk3_step(yo, dt, eta=2.0)
-    out = to_cpu(y)
-    err = gf_errors(out, yo, (slice(None),) * 3)
-    print("  err", fmt(orc.GF_NAMES, err), flush=True)
-    assert np.all(err <= EVOL_TOL), fmt(orc.GF_NAMES, err)
+        ol.ssprk3_step(yl, dt, eta=2.0)
+    check_parity("production cyl_ragged 20 steps", to_cpu(y), yo, yl, (slice(None),) * 3, EVOL_TOL,
+                 names=orc.GF_NAMES)
 
 
 @pytest.mark.parametrize("production", [False, True])
@@ -349,12 +323,10 @@ def test_ssprk3_full_size_headon(production):
     for s in range(30):
         capi.ssprk3_step(g.h, y, ws, dt, eta=w["eta"], diss=diss)
         og.ssprk3_step(yo, dt, eta=w["eta"])
-        if s % 10 == 9:
+        if s % 5 == 4:
             print("  step", s + 1, flush=True)
-    out = to_cpu(y)
-    err = gf_errors(out, yo, (slice(None),) * 3)
-    print("  err", fmt(orc.GF_NAMES, err), flush=True)
-    assert np.all(err <= EVOL_TOL), fmt(orc.GF_NAMES, err)
+    check_parity(f"ssprk3{' production' if production else ''} headon full size 30 steps", to_cpu(y), yo, None,
+                 (slice(None),) * 3, EVOL_TOL, names=orc.GF_NAMES)
 
 
 def test_axisymmetric_evolution_keeps_phi_slices_equal():
@@ -418,9 +390,10 @@ def test_rhs_is_deterministic():
 
 
 @pytest.mark.parametrize("wname", ["headon_sinhcylindrical_128x2x256", "vacuum3d_sinhspherical_256x128x64"])
-def test_rhs_full_size_sampled(wname):
-    """Full-size workloads: the RHS at every point on the GPU, checked at
-    sampled points (all near the inner boundary plus a random sample)."""
+def test_rhs_full_size_every_point(wname):
+    """Full-size workloads at the benchmark's launch configuration (the tuned
+    tile shape): the right-hand side at every interior point against the
+    oracle."""
     _print_case("rhs_full", wname)
     from paper_2505_00097_amd import capi
     w = wl.WORKLOADS[wname]
@@ -428,26 +401,14 @@ def test_rhs_full_size_sampled(wname):
     og = orc.Grid(w["coord"], w["N"], ampl=w["ampl"], sinhw=w["sinhw"], cfl=w["cfl"])
     y = og.brill_lindquist(w["masses"], w["positions"])
     y = og.apply_bcs(y + 0.05 * wl.smooth_random_state(og.n, seed=3))
-    # the launch configuration the benchmark times: the tuned tile shape
     capi.grid_tune(g.h, to_gpu(y), g.state())
     out, _ = _rhs_gpu(g, y)
-    rng = np.random.default_rng(1)
-    N = og.N
-    pick = [(3 + a, 3 + b, 3 + c) for a in (0, 1, N[0] - 1) for b in (0, N[1] - 1) for c in (0, N[2] // 2, N[2] - 1)]
-    for _ in range(400):
-        pick.append((3 + rng.integers(N[0]), 3 + rng.integers(N[1]), 3 + rng.integers(N[2])))
-    idx = np.array([og.flat(*p) for p in pick])
-    def pts_rhs(v):
-        return og.rhs_points(v, idx).T[:, None, None, :]
-
-    def err_fn(a, b):
-        return gf_errors(a, b, (slice(None),) * 3)
-    ref = pts_rhs(y)
-    got = out.reshape(24, -1)[:, idx][:, None, None, :]
-    err = err_fn(got, ref)
-    tol = np.maximum(RHS_TOL, rounding_floor(pts_rhs, y, err_fn))
-    print("  err", fmt(orc.GF_NAMES, err), flush=True)
-    assert np.all(err <= tol), fmt(orc.GF_NAMES, err / tol)
+    print("  gpu done", flush=True)
+    ref = og.rhs(y, eta=2.0)
+    print("  oracle done", flush=True)
+    refl = og.twin().rhs(ld(y), eta=2.0)
+    print("  extended-precision oracle done", flush=True)
+    check_parity(f"rhs full size {wname}", out, ref, refl, og.interior(), RHS_TOL, names=orc.GF_NAMES)
 
 
 def _bl_boxes(og, points, masses, pos):
@@ -491,11 +452,13 @@ def test_largest_grid_rhs_sampled_and_batch_step():
     points that keep every stencil offset within 31 bits): the right-hand
     side at sampled points (the corners and faces of the index range, the
     last interior point, random ones) against the oracle, and one RK4 step
-    of the ensemble path bitwise equal to the solo step."""
+    of the ensemble path bitwise equal to the solo step. Near the origin
+    and the axis of this grid the trK right-hand side is ill-conditioned in
+    FP64 (second differences over cells of 1e-3 of the radius); there the
+    bar is the FP64 oracle's own error against the extended-precision one."""
     _print_case("largest_grid")
     import torch
     from paper_2505_00097_amd import capi
-    from gpu_helpers import ulp_perturbed
     N, ampl = (1008, 168, 336), (7.5,) * 3
     masses, pos = [0.5, 0.5], [(0.0, 0.0, 0.5), (0.0, 0.0, -0.5)]
     g = capi.Grid(wl.SPHERICAL, N, ampl, (0.2,) * 3, 0.5)
@@ -512,28 +475,21 @@ def test_largest_grid_rhs_sampled_and_batch_step():
     capi.bssn_rhs(g.h, yg, r)
     got = r.view(24, -1)[:, torch.from_numpy(idx).to(r.device)].cpu().numpy()[:, None, None, :]
     del r
-
-    def pts_rhs(v):
-        return og.rhs_points(v, idx).T[:, None, None, :]
-
-    def err_fn(a, b):
-        return gf_errors(a, b, (slice(None),) * 3)
-    ref = pts_rhs(y)
-    err = err_fn(got, ref)
-    # rounding floor: one-ulp perturbations of what the sampled stencils read
-    floor = None
-    for t in range(2):
-        yp = y.copy()
-        for box in boxes:
-            yp[(slice(None),) + box] = ulp_perturbed(yp[(slice(None),) + box], 1000 + t)
-        e = err_fn(pts_rhs(yp), ref)
-        floor = e if floor is None else np.maximum(floor, e)
-        del yp
-    tol = np.maximum(RHS_TOL, floor)
-    print("  err", fmt(orc.GF_NAMES, err), flush=True)
-    assert np.all(err <= tol), fmt(orc.GF_NAMES, err / tol)
-    assert np.max(np.abs(ref)) > 0.0
+    ref = og.rhs_points(y, idx).T[:, None, None, :]
+    # the extended-precision input: every value the sampled stencils read
+    # (the 7^3 boxes), in an otherwise untouched zero array (pages that are
+    # never written are never allocated)
+    yl = np.zeros(y.shape, dtype=np.longdouble)
+    for box in boxes:
+        yl[(slice(None),) + box] = y[(slice(None),) + box]
+    ng, N2 = og.ng, og.N[2]  # the phi ghost planes, which the oracle reads, as in the FP64 input
+    yl[:, :ng] = yl[:, N2:N2 + ng]
+    yl[:, N2 + ng:] = yl[:, ng:2 * ng]
     del y
+    refl = og.twin().rhs_points(yl, idx).T[:, None, None, :]
+    del yl
+    assert np.max(np.abs(ref)) > 0.0
+    check_parity("rhs largest grid sampled", got, ref, refl, (slice(None),) * 3, RHS_TOL, names=orc.GF_NAMES)
     # the ensemble kernels at this size: one step, bitwise equal to solo
     y1, y2 = yg, yg.clone()
     ws = g.workspace()
@@ -554,19 +510,22 @@ def test_rk4_evolution_matches_oracle(name, m, pos, steps):
     _print_case("evolve", name, steps)
     from paper_2505_00097_amd import capi
     g, og = _pair(name)
+    ol = og.twin()
     y = g.state()
     capi.set_initial_data_brill_lindquist(g.h, m, pos, y)
     ws = g.workspace()
     yo = og.brill_lindquist(m, np.array(pos).reshape(-1, 3))
+    yl = ld(yo)
     dt = og.dt()
     for _ in range(steps):
         capi.rk4_step(g.h, y, ws, dt, eta=2.0)
         og.rk4_step(yo, dt, eta=2.0)
+        ol.rk4_step(yl, dt, eta=2.0)
     out = to_cpu(y)
-    err = gf_errors(out, yo, og.interior())
-    assert np.all(err <= EVOL_TOL), fmt(orc.GF_NAMES, err)
+    check_parity(f"rk4 {name} {steps} steps", out, yo, yl, og.interior(), EVOL_TOL, names=orc.GF_NAMES)
     # ghosts too
-    assert np.max(np.abs(out - yo)) <= EVOL_TOL * np.max(np.abs(yo))
+    check_parity(f"rk4 {name} {steps} steps, every point", out, yo, yl, (slice(None),) * 3, EVOL_TOL,
+                 groups=[range(24)], names=orc.GF_NAMES)
 
 
 @pytest.mark.parametrize("name,m,pos,steps", [
@@ -580,19 +539,21 @@ def test_ssprk3_evolution_matches_oracle(name, m, pos, steps):
     _print_case("evolve_ssprk3", name, steps)
     from paper_2505_00097_amd import capi
     g, og = _pair(name)
+    ol = og.twin()
     y = g.state()
     capi.set_initial_data_brill_lindquist(g.h, m, pos, y)
     ws = g.workspace()
     yo = og.brill_lindquist(m, np.array(pos).reshape(-1, 3))
+    yl = ld(yo)
     dt = og.dt()
     for _ in range(steps):
         capi.ssprk3_step(g.h, y, ws, dt, eta=2.0)
         og.ssprk3_step(yo, dt, eta=2.0)
+        ol.ssprk3_step(yl, dt, eta=2.0)
     out = to_cpu(y)
-    err = gf_errors(out, yo, og.interior())
-    print("  err", fmt(orc.GF_NAMES, err), flush=True)
-    assert np.all(err <= EVOL_TOL), fmt(orc.GF_NAMES, err)
-    assert np.max(np.abs(out - yo)) <= EVOL_TOL * np.max(np.abs(yo))
+    check_parity(f"ssprk3 {name} {steps} steps", out, yo, yl, og.interior(), EVOL_TOL, names=orc.GF_NAMES)
+    check_parity(f"ssprk3 {name} {steps} steps, every point", out, yo, yl, (slice(None),) * 3, EVOL_TOL,
+                 groups=[range(24)], names=orc.GF_NAMES)
 
 
 def test_headon_workload_100_steps_matches_oracle():
@@ -605,6 +566,7 @@ def test_headon_workload_100_steps_matches_oracle():
     w = wl.WORKLOADS[name]
     g = capi.Grid(w["coord"], w["N"], w["ampl"], w["sinhw"], w["cfl"])
     og = orc.Grid(w["coord"], w["N"], ampl=w["ampl"], sinhw=w["sinhw"], cfl=w["cfl"])
+    ol = og.twin()
     y = g.state()
     capi.set_initial_data_brill_lindquist(g.h, w["masses"], w["positions"], y)
     capi.grid_tune(g.h, y, g.state())
@@ -615,25 +577,16 @@ def test_headon_workload_100_steps_matches_oracle():
     for s in range(100):
         capi.rk4_step(g.h, y, ws, dt, eta=w["eta"])
         og.rk4_step(yo, dt, eta=w["eta"])
-        if s % 25 == 24:
+        if s % 10 == 9:
             print("  step", s + 1, flush=True)
     out = to_cpu(y)
-    err = gf_errors(out, yo, og.interior())
-    print("  err", fmt(orc.GF_NAMES, err), flush=True)
-    assert np.all(err <= EVOL_TOL), fmt(orc.GF_NAMES, err)
+    check_parity("rk4 headon full size 100 steps", out, yo, None, og.interior(), EVOL_TOL, names=orc.GF_NAMES)
     # H on the evolved full-size state (same input on both sides)
     Hg = g._empty(1)
     capi.hamiltonian_constraint(g.h, y, Hg)
     I = og.interior()
-
-    def ham(v):
-        return og.constraints(v)[0][None]
-
-    def rel(a, b):
-        return gf_errors(a, b, I, groups=[[0]])
-    herr = rel(to_cpu(Hg), ham(out))
-    floor = rounding_floor(ham, out, rel)
-    assert np.all(herr <= np.maximum(RHS_TOL, floor)), (herr, floor)
+    check_parity("H headon after 100 steps", to_cpu(Hg), og.constraints(out)[0][None],
+                 ol.constraints(ld(out))[0][None], I, RHS_TOL, groups=[[0]])
 
 
 @pytest.mark.parametrize("name", ["tiny", "cyl_3d", "sph_ragged"])
@@ -641,20 +594,14 @@ def test_hamiltonian_matches_oracle(name):
     _print_case("ham", name)
     from paper_2505_00097_amd import capi
     g, og = _pair(name)
-    for y in (og.brill_lindquist([0.8], [(0.1, 0.0, 0.2)]), og.apply_bcs(wl.smooth_random_state(og.n, seed=4))):
+    ol = og.twin()
+    I = og.interior()
+    for label, y in (("bl", og.brill_lindquist([0.8], [(0.1, 0.0, 0.2)])),
+                     ("smooth_random", og.apply_bcs(wl.smooth_random_state(og.n, seed=4)))):
         Hg = g._empty(1)
         capi.hamiltonian_constraint(g.h, to_gpu(y), Hg)
-        I = og.interior()
-
-        def ham(v):
-            return og.constraints(v)[0]
-
-        def rel(a, b):
-            return np.max(np.abs(a[I] - b[I])) / np.max(np.abs(b[I]))
-        Ho = ham(y)
-        out = to_cpu(Hg)[0]
-        tol = max(RHS_TOL, rounding_floor(ham, y, rel))
-        assert rel(out, Ho) <= tol, (rel(out, Ho), tol)
+        check_parity(f"H {name} {label}", to_cpu(Hg), og.constraints(y)[0][None], ol.constraints(ld(y))[0][None],
+                     I, RHS_TOL, groups=[[0]])
 
 
 def test_batch_matches_solo():
@@ -783,21 +730,21 @@ def test_smallest_grids(coord, N):
     ampl = (2.0, 2.0, 3.0)
     g = capi.Grid(coord, N, ampl, (0.3,) * 3)
     og = orc.Grid(coord, N, ampl=ampl, sinhw=(0.3,) * 3)
+    ol = og.twin()
     y = og.apply_bcs(og.brill_lindquist([0.4], [(0.1, 0.0, 0.2)]) + 0.01 * wl.smooth_random_state(og.n, seed=2))
     out, _ = _rhs_gpu(g, y)
-    ref = og.rhs(y, eta=2.0)
     I = og.interior()
-    err = gf_errors(out, ref, I)
-    floor = rounding_floor(lambda v: og.rhs(v, eta=2.0), y, lambda a, b: gf_errors(a, b, I))
-    assert np.all(err <= np.maximum(RHS_TOL, floor)), fmt(orc.GF_NAMES, err)
+    check_parity(f"rhs smallest {coord} {N}", out, og.rhs(y, eta=2.0), ol.rhs(ld(y), eta=2.0), I, RHS_TOL,
+                 names=orc.GF_NAMES)
     yg = to_gpu(y)
+    yl = ld(y)
     ws = g.workspace()
     dt = og.dt()
     for _ in range(10):
         capi.rk4_step(g.h, yg, ws, dt)
         og.rk4_step(y, dt, eta=2.0)
-    err = gf_errors(to_cpu(yg), y, I)
-    assert np.all(err <= EVOL_TOL), fmt(orc.GF_NAMES, err)
+        ol.rk4_step(yl, dt, eta=2.0)
+    check_parity(f"rk4 smallest {coord} {N} 10 steps", to_cpu(yg), y, yl, I, EVOL_TOL, names=orc.GF_NAMES)
 
 
 def test_invalid_calls_report_errors():
@@ -828,12 +775,13 @@ def test_invalid_calls_report_errors():
 def test_constraints_match_oracle(name):
     """H (Eq. 16), M^i (Eq. 17) and C^i from bhah_constraints against the
     oracle: exactly zero momentum and C^i on Brill-Lindquist data, and within
-    max(1e-12, the oracle's rounding floor) on evolved and smooth random
-    states (each constraint measured against its own largest magnitude)."""
+    the per-RHS bar on evolved and smooth random states (each constraint
+    measured against its own largest magnitude)."""
     _print_case("constraints", name)
     import torch
     from paper_2505_00097_amd import capi
     g, og = _pair(name)
+    ol = og.twin()
     I = og.interior()
     bl = og.brill_lindquist([0.8], [(0.1, 0.0, 0.2)])
     ev = bl.copy()
@@ -841,8 +789,8 @@ def test_constraints_match_oracle(name):
         og.rk4_step(ev, og.dt(), eta=2.0)
     rnd = og.apply_bcs(wl.smooth_random_state(og.n, seed=8))
 
-    def cons(v):
-        H, M, C = og.constraints(v)
+    def cons(o, v):
+        H, M, C = o.constraints(v)
         return np.concatenate([H[None], M, C])
 
     groups = [[0], [1, 2, 3], [4, 5, 6]]
@@ -855,14 +803,7 @@ def test_constraints_match_oracle(name):
         got = np.concatenate([to_cpu(H), to_cpu(M), to_cpu(C)])
         if label == "bl":
             assert np.all(got[1:][(slice(None),) + I] == 0.0)
-        ref = cons(y)
-
-        def rel(a, b):
-            return gf_errors(a, b, I, groups=groups)
-        err = rel(got, ref)
-        tol = np.maximum(RHS_TOL, rounding_floor(cons, y, rel))
-        print("  ", label, err, flush=True)
-        assert np.all(err <= tol), (label, err, tol)
+        check_parity(f"constraints {name} {label}", got, cons(og, y), cons(ol, ld(y)), I, RHS_TOL, groups=groups)
     # bhah_hamiltonian_constraint gives the same H up to rounding (another
     # kernel instance: the compiler may contract differently)
     y = to_gpu(ev)
@@ -881,3 +822,35 @@ def test_probe_peaks_are_plausible():
     print(f"probe: fp64 {tf:.1f} TFLOP/s, triad {gbps:.0f} GB/s")
     assert 5.0 < tf < 78.6 * 1.05
     assert 500.0 < gbps < 8000.0 * 1.05
+
+
+@pytest.mark.parametrize("name,integrator,radiation", [("cyl_ragged", "rk4", False), ("sph_ragged", "rk4", False),
+                                                       ("cyl_ragged", "ssprk3", True), ("spherical", "ssprk3", False)])
+def test_evolve_equals_single_steps(name, integrator, radiation):
+    """bhah_evolve (n steps in one call, phi ghost planes filled only after
+    the last) equals n calls of the single-step entry point bit for bit,
+    ghosts included; nsteps = 0 changes nothing and nsteps < 0 is refused."""
+    _print_case("evolve_n", name, integrator, radiation)
+    import torch
+    from paper_2505_00097_amd import capi
+    coord, N, ampl, w = GRIDS[name]
+    g = capi.Grid(coord, N, ampl, w, bc_kind=capi.BC_RADIATION if radiation else capi.BC_EXTRAP)
+    diss = DISS if integrator == "ssprk3" else (0.0, 0.0)
+    y = g.state()
+    capi.set_initial_data_brill_lindquist(g.h, [0.6, 0.4], [(0.2, 0.0, 0.5), (0.0, 0.1, -0.5)], y)
+    y1, y2 = y.clone(), y.clone()
+    ws = g.workspace()
+    step = capi.ssprk3_step if integrator == "ssprk3" else capi.rk4_step
+    for _ in range(7):
+        step(g.h, y1, ws, g.dt, diss=diss)
+    capi.evolve(g.h, y2, ws, g.dt, 7, integrator=capi.SSPRK3 if integrator == "ssprk3" else capi.RK4, diss=diss)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+    y3 = y2.clone()
+    capi.evolve(g.h, y3, ws, g.dt, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(y3, y2)
+    with pytest.raises(capi.BhahError, match="nsteps"):
+        capi.evolve(g.h, y3, ws, g.dt, -1)
+    with pytest.raises(capi.BhahError, match="integrator"):
+        capi.evolve(g.h, y3, ws, g.dt, 1, integrator=7)
