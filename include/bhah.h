@@ -263,6 +263,26 @@ int bhah_ssprk3_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt,
 int bhah_evolve(const bhah_grid* g, const bhah_gauge_params* gp, int integrator,
                 double dt, int nsteps, double* y, double* workspace, void* stream);
 
+/* ---- allocation-free RK4 step ---------------------------------------------
+ * For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid allocation): one
+ * bhah_rk4_step whose workspace is a library-owned file-scope device array
+ * instead of a caller buffer. The array holds three states of at most
+ * BHAH_NOALLOC_MAX_POINTS points (ghosts included): 3 x 24 x 294912 doubles,
+ * about 162 MiB, on every device the library runs on, from the library's
+ * load until the process ends. A grid with more points (info.n_points) gets
+ * BHAH_EINVAL; other arguments and errors are as for bhah_rk4_step, and the
+ * result is the same, bit for bit. The call allocates nothing; its first
+ * call on a device (the device current at the call, which must be the
+ * grid's) looks up the array's device address once. Every call on one
+ * device shares that device's array: calls that overlap on one GPU (two
+ * streams, two host threads) race and must be serialised by the caller.
+ * No part of the array needs clearing: every workspace value a step reads
+ * is written earlier in the same step.                                      */
+#define BHAH_NOALLOC_MAX_POINTS 294912
+int bhah_rk4_step_noalloc(const bhah_grid* g, const bhah_gauge_params* gp, double dt,
+                          double* y, void* stream);
+
 /* All three constraints at every interior point, centred differences of
  * the grid's order: H of Eq. 16 (one gridfunction), the momentum constraint M^i of
  * Eq. 17 and C^i = Lambdabar^i - Delta^i (three gridfunctions each, rescaled

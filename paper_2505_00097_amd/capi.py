@@ -99,6 +99,7 @@ _SIGS = {
     "bhah_apply_bcs": (ctypes.c_int, [_vp, _vp, _vp]),
     "bhah_bssn_rhs": (ctypes.c_int, [_vp, ctypes.POINTER(GaugeParams), _vp, _vp, _vp, _vp]),
     "bhah_rk4_step": (ctypes.c_int, [_vp, ctypes.POINTER(GaugeParams), ctypes.c_double, _vp, _vp, _vp]),
+    "bhah_rk4_step_noalloc": (ctypes.c_int, [_vp, ctypes.POINTER(GaugeParams), ctypes.c_double, _vp, _vp]),
     "bhah_evolve": (ctypes.c_int, [_vp, ctypes.POINTER(GaugeParams), ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                    _vp, _vp, _vp]),
     "bhah_hamiltonian_constraint": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
@@ -239,6 +240,15 @@ def ssprk3_step(h, y, workspace, dt, eta=2.0, diss=(0.0, 0.0), stream=None):
     gp = gauge(eta, diss)
     _check(lib().bhah_ssprk3_step(h, ctypes.byref(gp), float(dt), _ptr(y), _ptr(workspace), _stream(stream)),
            "bhah_ssprk3_step")
+
+
+def rk4_step_noalloc(h, y, dt, eta=2.0, diss=(0.0, 0.0), stream=None):
+    gp = gauge(eta, diss)
+    _check(lib().bhah_rk4_step_noalloc(h, ctypes.byref(gp), float(dt), _ptr(y), _stream(stream)),
+           "bhah_rk4_step_noalloc")
+
+
+NOALLOC_MAX_POINTS = 294912
 
 
 def evolve(h, y, workspace, dt, nsteps, integrator=RK4, eta=2.0, diss=(0.0, 0.0), stream=None):

@@ -281,6 +281,10 @@ void rk4_stages(double dt, double* y, double* ws, long long n, StageArgs st[4], 
 void ssprk3_stages(double dt, double* y, double* ws, long long n, StageArgs st[3], const double* in[3],
                    double* gdst[3]);
 
+// device address of this device's bhah_rk4_step_noalloc workspace (3 x NGF x
+// BHAH_NOALLOC_MAX_POINTS doubles), looked up on first use per device
+int noalloc_workspace(double** ws);
+
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);
 int check_hip(hipError_t e, const char* what);

@@ -273,6 +273,25 @@ int bhah_rk4_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt, do
   return check_launch("bhah_rk4_step");
 }
 
+int bhah_rk4_step_noalloc(const bhah_grid* g, const bhah_gauge_params* gp, double dt, double* y, void* stream) {
+  if (!g || !gp || !y) return fail(BHAH_EINVAL, "bhah_rk4_step_noalloc: NULL argument");
+  if (g->info.n_points > BHAH_NOALLOC_MAX_POINTS)
+    return fail(BHAH_EINVAL, "bhah_rk4_step_noalloc: grid has " + std::to_string(g->info.n_points) +
+                                 " points, more than BHAH_NOALLOC_MAX_POINTS (" +
+                                 std::to_string(BHAH_NOALLOC_MAX_POINTS) + ")");
+  if (int rc = check_aligned("bhah_rk4_step_noalloc", {y})) return rc;
+  if (int rc = check_gauge(gp, "bhah_rk4_step_noalloc")) return rc;
+  double* ws = nullptr;
+  if (int rc = noalloc_workspace(&ws)) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  StageArgs st[4];
+  const double* in[4];
+  double* gdst[4];
+  rk4_stages(dt, y, ws, g->info.state_doubles, st, in, gdst);
+  for (int k = 0; k < 4; k++) run_stage(g, gauge_of(*gp), in[k], st[k], gdst[k], k == 3, s);
+  return check_launch("bhah_rk4_step_noalloc");
+}
+
 int bhah_ssprk3_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt, double* y, double* workspace,
                      void* stream) {
   if (!g || !gp || !y || !workspace) return fail(BHAH_EINVAL, "bhah_ssprk3_step: NULL argument");

@@ -1,7 +1,35 @@
-// misc.hip -- ghost fill and Brill-Lindquist initial data.
+// misc.hip -- ghost fill and Brill-Lindquist initial data; the workspace of
+// the allocation-free RK4 entry point.
+#include <mutex>
+
 #include "bhah_internal.h"
 
 namespace bhah {
+
+// Workspace of bhah_rk4_step_noalloc (three states of at most
+// BHAH_NOALLOC_MAX_POINTS points): a file-scope device array, one copy per
+// device. In host code its name is a host-side stand-in, never a device
+// address: kernels get the address that hipGetSymbolAddress returns for the
+// current device, looked up once per device and kept below.
+constexpr long long kScratchDoubles = 3LL * NGF * BHAH_NOALLOC_MAX_POINTS;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+int noalloc_workspace(double** ws) {
+  int dev = 0;
+  if (int rc = check_hip(hipGetDevice(&dev), "hipGetDevice")) return rc;
+  if (dev < 0 || dev >= kMaxDevices) return fail(BHAH_EINVAL, "bhah_rk4_step_noalloc: device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (int rc = check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress")) return rc;
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *ws = g_scratch_ptr[dev];
+  return BHAH_OK;
+}
 
 // Every ghost point takes sign * sum_t w_t y[src_t]; all sources are interior
 // points, so ghosts can be filled in any order and in parallel (Sec. 3
