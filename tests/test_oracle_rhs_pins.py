@@ -23,6 +23,8 @@ KS_RATIO_MIN = 20.0  # strong-field case, not fully asymptotic at these sizes
 # fully asymptotic at these sizes (ratios from 169 to about 20000, medians
 # above 560); 4th-order stencils give 50 to 100.
 ORDERS = [(3, RATIO_MIN, RATIO_MIN), (5, 150.0, 500.0)]
+# the same, with the extended-precision build of the oracle at 4th order
+ORDERS_BOTH_BUILDS = [o + (False,) for o in ORDERS] + [ORDERS[0] + (True,)]
 
 
 def _refine(Nc, r=3):
@@ -37,8 +39,9 @@ def _common_index(Nc, fine, ng=3):
 # ---------------------------------------------------------------- flat space
 @pytest.mark.parametrize("coord,N", [(an.SINH_SPHERICAL, (8, 6, 4)), (an.SINH_CYLINDRICAL, (8, 4, 10)),
                                      (an.SPHERICAL, (6, 6, 6)), (an.SINH_SPHERICAL, (32, 16, 2))])
-def test_flat_space_rhs_and_constraints_exactly_zero(coord, N):
-    g = orc.Grid(coord, N, ampl=(10.0,) * 3)
+@pytest.mark.parametrize("ld", [False, True])
+def test_flat_space_rhs_and_constraints_exactly_zero(coord, N, ld):
+    g = orc.Grid(coord, N, ampl=(10.0,) * 3, ld=ld)
     y = g.brill_lindquist([], np.zeros((0, 3)), lapse_kind=1)
     rhs = g.rhs(y, eta=2.0)
     H, M, C = g.constraints(y)
@@ -73,17 +76,17 @@ def _away(x, pos, rp, rmax):
     return ok
 
 
-@pytest.mark.parametrize("ng,ratio_min,median_min", ORDERS)
+@pytest.mark.parametrize("ng,ratio_min,median_min,ld", ORDERS_BOTH_BUILDS)
 @pytest.mark.parametrize("coord,Nc,ampl,w,m,pos", BL_CASES)
-def test_bl_rhs_converges_to_closed_form(coord, Nc, ampl, w, m, pos, ng, ratio_min, median_min):
+def test_bl_rhs_converges_to_closed_form(coord, Nc, ampl, w, m, pos, ng, ratio_min, median_min, ld):
     """d_t K = -2 psi^-8 |grad psi|^2, d_t a_ij = -8 psi^-8 (psi_i psi_j -
     delta_ij |grad psi|^2/3) in the rescaled frame, every other RHS exactly 0
     (conformally flat, time-symmetric data with alpha = psi^-2, beta = 0)."""
     errs = []
     for fine in (False, True):
         N = _refine(Nc) if fine else Nc
-        g = orc.Grid(coord, N, ampl=ampl, sinhw=w, ng=ng)
-        y = an.bl_state(coord, N, ampl, w, m, pos, ng=ng)
+        g = orc.Grid(coord, N, ampl=ampl, sinhw=w, ng=ng, ld=ld)
+        y = g.vec(an.bl_state(coord, N, ampl, w, m, pos, ng=ng))
         rhs = g.rhs(y, eta=2.0)
         ex = an.bl_rhs_closed_form(coord, N, ampl, w, m, pos, ng=ng)
         I = g.interior()
@@ -144,20 +147,20 @@ def _ricci_case(coord, N, ampl, w, amp=0.15, sigma=0.8, c=(0.35, -0.2, 0.3), ng=
 
 @pytest.mark.parametrize("coord,Nc,ampl,w", [(an.SINH_SPHERICAL, (12, 8, 8), (2.0,) * 3, (0.4,) * 3),
                                              (an.SINH_CYLINDRICAL, (10, 8, 12), (2.0,) * 3, (0.4,) * 3)])
-@pytest.mark.parametrize("ng,ratio_min,median_min", ORDERS)
-def test_ricci_converges_to_textbook_ricci(coord, Nc, ampl, w, ng, ratio_min, median_min):
+@pytest.mark.parametrize("ng,ratio_min,median_min,ld", ORDERS_BOTH_BUILDS)
+def test_ricci_converges_to_textbook_ricci(coord, Nc, ampl, w, ng, ratio_min, median_min, ld):
     """Eq. 12 with Lambdabar^i = Delta^i equals the Ricci tensor of gammabar
     computed from its Christoffel symbols, R_bd = d_a G^a_bd - d_d G^a_ba +
     G^a_ae G^e_bd - G^a_de G^e_ba (here in Cartesian coordinates)."""
     errs, errs_away = [], []
     for fine in (False, True):
         N = _refine(Nc) if fine else Nc
-        g = orc.Grid(coord, N, ampl=ampl, sinhw=w, ng=ng)
+        g = orc.Grid(coord, N, ampl=ampl, sinhw=w, ng=ng, ld=ld)
         y, Rf = _ricci_case(coord, N, ampl, w, ng=ng)
         idx = _common_index(Nc, fine, ng)
         flat = np.array([g.flat(i0, i1, i2) for i2 in idx[0].ravel() for i1 in idx[1].ravel()
                          for i0 in idx[2].ravel()])
-        _, ric = g.rhs_points(y, flat, want_ricci=True)
+        _, ric = g.rhs_points(g.vec(y), flat, want_ricci=True)
         ex = np.stack([Rf[idx][..., i, j].ravel() for (i, j) in an.SYM], -1)
         err = np.abs(ric - ex)
         errs.append(np.max(err, axis=0))
@@ -212,8 +215,8 @@ def _gauge_case(coord, N, ampl, w, ng=3):
 
 @pytest.mark.parametrize("coord,Nc,ampl,w", [(an.SINH_SPHERICAL, (12, 8, 8), (2.0,) * 3, (0.4,) * 3),
                                              (an.SINH_CYLINDRICAL, (10, 8, 12), (2.0,) * 3, (0.4,) * 3)])
-@pytest.mark.parametrize("ng,ratio_min,median_min", ORDERS)
-def test_pure_gauge_shift_converges_to_closed_form(coord, Nc, ampl, w, ng, ratio_min, median_min):
+@pytest.mark.parametrize("ng,ratio_min,median_min,ld", ORDERS_BOTH_BUILDS)
+def test_pure_gauge_shift_converges_to_closed_form(coord, Nc, ampl, w, ng, ratio_min, median_min, ld):
     """Flat data with a shift beta = xi: d_t gammabar = Lie_xi delta - 2/3 delta
     div xi, d_t Lambdabar = lap xi + grad div xi / 3, d_t W = -div xi / 3,
     d_t B = 3/4 d_t Lambdabar, d_t beta^i = beta^j d_j beta^i (coordinate
@@ -221,9 +224,9 @@ def test_pure_gauge_shift_converges_to_closed_form(coord, Nc, ampl, w, ng, ratio
     errs, errs_away = [], []
     for fine in (False, True):
         N = _refine(Nc) if fine else Nc
-        g = orc.Grid(coord, N, ampl=ampl, sinhw=w, ng=ng)
+        g = orc.Grid(coord, N, ampl=ampl, sinhw=w, ng=ng, ld=ld)
         y, ex = _gauge_case(coord, N, ampl, w, ng=ng)
-        rhs = g.rhs(y, eta=2.0)
+        rhs = g.rhs(g.vec(y), eta=2.0)
         I = g.interior()
         for name in ("alpha", "trK", "aDD00", "aDD01", "aDD02", "aDD11", "aDD12", "aDD22"):
             assert np.all(rhs[an.GF[name]][I] == 0.0), name
