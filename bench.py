@@ -58,6 +58,8 @@ BYTES_ALG = 24 * 8 * 2
 # was taken from
 COUNTERS = os.path.join(ROOT, "profiles", "k_rhs_fused_headon_counters.txt")
 COUNTERS_3D = os.path.join(ROOT, "profiles", "k_rhs_fused_vacuum3d_counters.txt")
+COUNTERS_8 = os.path.join(ROOT, "profiles", "k_rhs_fused_headon_8th_order_counters.txt")
+COUNTERS_3D_8 = os.path.join(ROOT, "profiles", "k_rhs_fused_vacuum3d_8th_order_counters.txt")
 KERNEL_SOURCES = ["paper_2505_00097_amd/csrc/rhs_fused.hip", "paper_2505_00097_amd/csrc/rhs_common.h",
                   "paper_2505_00097_amd/csrc/bhah_internal.h"]
 
@@ -70,16 +72,20 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def counters_path(workload):
-    """the committed counter summary of a workload's right-hand-side kernel"""
-    return {"headon_sinhcylindrical_128x2x256": COUNTERS, "vacuum3d_sinhspherical_256x128x64": COUNTERS_3D}.get(workload)
+def counters_path(workload, nghosts=3):
+    """the committed counter summary of a workload's right-hand-side kernel
+    (at 8th order: the variant with the production dissipation)"""
+    return {("headon_sinhcylindrical_128x2x256", 3): COUNTERS,
+            ("vacuum3d_sinhspherical_256x128x64", 3): COUNTERS_3D,
+            ("headon_sinhcylindrical_128x2x256", 5): COUNTERS_8,
+            ("vacuum3d_sinhspherical_256x128x64", 5): COUNTERS_3D_8}.get((workload, nghosts))
 
 
-def measured_traffic(workload, tile=None):
+def measured_traffic(workload, tile=None, nghosts=3):
     """HBM bytes per launch from the committed counter summary, or None if it
     is absent, for another workload or tile shape, or older than the kernel
     source."""
-    path = counters_path(workload)
+    path = counters_path(workload, nghosts)
     if not path or not os.path.exists(path):
         return None
     vals = {}
@@ -251,6 +257,10 @@ def run_ssprk3(capi, wl, stream, steps, diss=(0.0, 0.0), bc_kind=0, nghosts=3, r
             out["rhs_flops_per_point"] = f
             out["rhs_TFLOPs"] = f * n / rhs_s / 1e12
             out["rhs_frac_fp64_peak"] = f * n / rhs_s / PEAK_FP64_VECTOR
+            if nghosts == 5:
+                tile = list(capi.grid_get_tile(ge.h))
+                out["roofline"] = roofline(kernel_name(w["coord"], w["N"], ko=True, nghosts=5), f, n, rhs_s,
+                                           measured_traffic("headon_sinhcylindrical_128x2x256", tile, nghosts=5))
         del ye
     return out
 
@@ -431,10 +441,13 @@ def run_rhs_study(capi, wl, stream, reps, steps):
     capi.grid_tune(g8.h, y8, g8.state(), eta=w["eta"], diss=diss, stream=stream)
     rhs8_s = time_rhs(capi, g8, y8, w["eta"], reps, stream, diss=diss)
     f8 = F_ALG8_KO[(w["coord"], two_planes(w["coord"], w["N"]))]
-    eighth = {"rhs_launch_s": rhs8_s, "flops_per_point": f8, "rhs_TFLOPs": f8 * n / rhs8_s / 1e12,
-              "rhs_frac_fp64_peak": f8 * n / rhs8_s / PEAK_FP64_VECTOR, "tile": list(capi.grid_get_tile(g8.h))}
-    del y8
+    tile8 = list(capi.grid_get_tile(g8.h))
     name = "vacuum3d_sinhspherical_256x128x64"
+    eighth = {"rhs_launch_s": rhs8_s, "flops_per_point": f8, "rhs_TFLOPs": f8 * n / rhs8_s / 1e12,
+              "rhs_frac_fp64_peak": f8 * n / rhs8_s / PEAK_FP64_VECTOR, "tile": tile8,
+              "roofline": roofline(kernel_name(w["coord"], w["N"], ko=True, nghosts=5), f8, n, rhs8_s,
+                                   measured_traffic(name, tile8, nghosts=5))}
+    del y8
     return {"workload": name, "interior_points": n,
             "rhs_launch_s": rhs_s, "rhs_TFLOPs": f_alg(w["coord"], w["N"]) * n / rhs_s / 1e12,
             "rhs_frac_fp64_peak": f_alg(w["coord"], w["N"]) * n / rhs_s / PEAK_FP64_VECTOR,

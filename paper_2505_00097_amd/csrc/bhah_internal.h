@@ -44,14 +44,26 @@ struct GridDev {
 
 // sign flip of gridfunction g under the parity bits par (bit d: the
 // direction-d basis vector reverses); tensor type per gridfunction: scalar,
-// vector (index i) or rank 2 (indices i, j)
-__host__ __device__ __forceinline__ int gf_flip(int g, int par) {
+// vector (index i) or rank 2 (indices i, j). The flip is the parity of the
+// reversed directions among the gridfunction's indices: a mask of them per
+// gridfunction (a direction that appears twice cancels), four bits each,
+// packed into two 64-bit constants so that the lookup needs no memory.
+__host__ __device__ constexpr unsigned long long gf_flip_masks(int first) {
   constexpr int I[NGF] = {0, 0, 0, 1, 1, 2, -1, 0, 1, 2, -1, 0, 0, 0, 1, 1, 2, 0, 1, 2, -1, 0, 1, 2};
   constexpr int J[NGF] = {0, 1, 2, 1, 2, 2, -1, -1, -1, -1, -1, 0, 1, 2, 1, 2, 2, -1, -1, -1, -1, -1, -1, -1};
-  int f = 0;
-  if (I[g] >= 0) f ^= (par >> I[g]) & 1;
-  if (J[g] >= 0) f ^= (par >> J[g]) & 1;
-  return f;
+  unsigned long long m = 0;
+  for (int g = first; g < first + 16 && g < NGF; g++) {
+    unsigned long long b = 0;
+    if (I[g] >= 0) b ^= 1ull << I[g];
+    if (J[g] >= 0) b ^= 1ull << J[g];
+    m |= b << (4 * (g - first));
+  }
+  return m;
+}
+__host__ __device__ __forceinline__ int gf_flip(int g, int par) {
+  constexpr unsigned long long LO = gf_flip_masks(0), HI = gf_flip_masks(16);
+  const unsigned m = (unsigned)((g < 16 ? LO >> (4 * g) : HI >> (4 * (g - 16))) & 0xFull);
+  return __builtin_popcount((unsigned)par & m) & 1;
 }
 
 // Ghost fill list: every ghost point p receives

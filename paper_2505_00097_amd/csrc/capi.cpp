@@ -133,8 +133,8 @@ static hipError_t upload_radiation(bhah_grid* g) {
 // st, with the radiation boundary also at the pure-outer points, then the
 // ghost fill of the stage's result (all ghosts after the last stage, those
 // with an interior phi index before: the stencils never read phi ghosts).
-static void run_stage(const bhah_grid* g, const Gauge& ga, const double* in, const StageArgs& st, double* gdst,
-                      bool last, hipStream_t s) {
+static int run_stage(const bhah_grid* g, const Gauge& ga, const double* in, const StageArgs& st, double* gdst,
+                     bool last, hipStream_t s) {
   launch_rhs_fused(g->dev, ga, in, nullptr, st, s, g->tile);
   if (g->params.bc_kind == BHAH_BC_RADIATION) {
     launch_radiation(g->dev, g->rad, in, st, s);
@@ -142,6 +142,7 @@ static void run_stage(const bhah_grid* g, const Gauge& ga, const double* in, con
   } else {
     launch_ghosts(last ? g->ghost : g->ghost_stage, gdst, g->dev.sgf, s);
   }
+  return check_launch("stage launch");
 }
 
 }  // namespace bhah
@@ -269,7 +270,8 @@ int bhah_rk4_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt, do
   const double* in[4];
   double* gdst[4];
   rk4_stages(dt, y, workspace, g->info.state_doubles, st, in, gdst);
-  for (int k = 0; k < 4; k++) run_stage(g, gauge_of(*gp), in[k], st[k], gdst[k], k == 3, s);
+  for (int k = 0; k < 4; k++)
+    if (int rc = run_stage(g, gauge_of(*gp), in[k], st[k], gdst[k], k == 3, s)) return rc;
   return check_launch("bhah_rk4_step");
 }
 
@@ -288,7 +290,8 @@ int bhah_rk4_step_noalloc(const bhah_grid* g, const bhah_gauge_params* gp, doubl
   const double* in[4];
   double* gdst[4];
   rk4_stages(dt, y, ws, g->info.state_doubles, st, in, gdst);
-  for (int k = 0; k < 4; k++) run_stage(g, gauge_of(*gp), in[k], st[k], gdst[k], k == 3, s);
+  for (int k = 0; k < 4; k++)
+    if (int rc = run_stage(g, gauge_of(*gp), in[k], st[k], gdst[k], k == 3, s)) return rc;
   return check_launch("bhah_rk4_step_noalloc");
 }
 
@@ -302,7 +305,8 @@ int bhah_ssprk3_step(const bhah_grid* g, const bhah_gauge_params* gp, double dt,
   const double* in[3];
   double* gdst[3];
   ssprk3_stages(dt, y, workspace, g->info.state_doubles, st, in, gdst);
-  for (int k = 0; k < 3; k++) run_stage(g, gauge_of(*gp), in[k], st[k], gdst[k], k == 2, s);
+  for (int k = 0; k < 3; k++)
+    if (int rc = run_stage(g, gauge_of(*gp), in[k], st[k], gdst[k], k == 2, s)) return rc;
   return check_launch("bhah_ssprk3_step");
 }
 
@@ -324,7 +328,8 @@ int bhah_evolve(const bhah_grid* g, const bhah_gauge_params* gp, int integrator,
   // the stage ghost list after every stage, all ghosts after the last
   for (int n = 0; n < nsteps; n++)
     for (int k = 0; k < nst; k++)
-      run_stage(g, gauge_of(*gp), in[k], st[k], gdst[k], n == nsteps - 1 && k == nst - 1, s);
+      if (int rc = run_stage(g, gauge_of(*gp), in[k], st[k], gdst[k], n == nsteps - 1 && k == nst - 1, s))
+        return rc;
   return check_launch("bhah_evolve");
 }
 

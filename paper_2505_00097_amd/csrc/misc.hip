@@ -39,6 +39,12 @@ int noalloc_workspace(double** ws) {
 // ghost points and keeps more loads in flight.
 constexpr int GF_PER = 4;
 static_assert(NGF % GF_PER == 0, "gridfunction groups");
+// Terms are fetched GT at a time: the chunk's weights and source indices in
+// one round of loads, then its values in the next, so a ghost of up to GT
+// terms (every face ghost of an extrapolating boundary has three) costs three
+// dependent rounds (record, terms, values) instead of two per term. The sum
+// still runs in term order, one fused multiply-add per term.
+constexpr int GT = 4;
 
 __device__ __forceinline__ void ghost_point(const GhostDev& gh, double* __restrict__ y, long long sgf, int t,
                                             int g0) {
@@ -54,11 +60,23 @@ __device__ __forceinline__ void ghost_point(const GhostDev& gh, double* __restri
   } else {
 #pragma unroll
     for (int j = 0; j < GF_PER; j++) v[j] = 0.0;
-    for (int k = s0; k < s1; k++) {
-      const double w = gh.w[k];
-      const int src = gh.src[k];
+    for (int k = s0; k < s1; k += GT) {
+      // past the last term the chunk rereads that term (in bounds, not summed)
+      double w[GT], x[GT][GF_PER];
 #pragma unroll
-      for (int j = 0; j < GF_PER; j++) v[j] += w * y[(g0 + j) * sgf + src];
+      for (int u = 0; u < GT; u++) {
+        const int ku = min(k + u, s1 - 1);
+        w[u] = gh.w[ku];
+        const int src = gh.src[ku];
+#pragma unroll
+        for (int j = 0; j < GF_PER; j++) x[u][j] = y[(g0 + j) * sgf + src];
+      }
+#pragma unroll
+      for (int u = 0; u < GT; u++)
+        if (k + u < s1) {
+#pragma unroll
+          for (int j = 0; j < GF_PER; j++) v[j] += w[u] * x[u][j];
+        }
     }
   }
 #pragma unroll

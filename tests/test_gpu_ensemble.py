@@ -12,7 +12,7 @@ import json
 import numpy as np
 import pytest
 
-from gpu_helpers import gf_errors, to_cpu
+from gpu_helpers import check_parity, to_cpu
 from oracle import oracle as orc
 from paper_2505_00097_amd import workloads as wl
 
@@ -310,8 +310,8 @@ def test_batch_job_against_oracle():
         yo = og.brill_lindquist(j["masses"], j["positions"])
         for _ in range(n):
             og.rk4_step(yo, og.dt(), eta=2.0)
-        err = gf_errors(to_cpu(ys[k]), yo, og.interior())
-        assert np.all(err <= 1e-9), err
+        check_parity(f"batch job {k} rk4 {n} steps", to_cpu(ys[k]).reshape(yo.shape), yo, None, og.interior(), 1e-9,
+                     names=orc.GF_NAMES)
     capi.batch_destroy(b)
 
 
