@@ -957,11 +957,15 @@ __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, c
 // slower.
 
 // Tiles: 64 points, 2^lx along i0 times 2^ly along i1 times 64 >> (lx + ly)
-// along i2; the tile grid is walked in bands of `band` tile rows of i1, then
-// i2, then i1 within the band, then i0, so the stencils of tiles that run at
-// the same time overlap. The hardware hands consecutive workgroup ids to the
-// XCDs in turn; block ids are remapped so that every XCD works through one
-// contiguous range of the walk (its L2 then holds a compact part of the grid).
+// along i2; the tile grid is walked in bands of `band` tile rows of i1, and
+// within a band by i0 tile column, then i2, then i1 (fastest), so the tiles
+// that run at the same time form a compact block of one column whose
+// stencils overlap. The hardware hands consecutive workgroup ids to the XCDs
+// in turn; block ids are remapped so that every XCD works through one
+// contiguous range of the walk (its L2 then holds a compact part of the
+// grid). On the 3-D grid the column-first order moves a third (4th order)
+// to a quarter (8th order) of the HBM bytes of an i0-fastest order, at the
+// same speed.
 template <int H>
 __device__ __forceinline__ bool tile_point(const GridDev& G, const TileMap& T, int w, int lane, int& i0,
                                            int& i1, int& i2) {
@@ -972,10 +976,10 @@ __device__ __forceinline__ bool tile_point(const GridDev& G, const TileMap& T, i
   const int start = bi * T.band;
   const int hgt = min(T.band, T.ty - start);
   const int idx = w - start * T.tz * T.tx;
-  const int j2 = idx / (hgt * T.tx);
-  const int r = idx - j2 * hgt * T.tx;
-  const int j1 = start + r / T.tx;
-  const int xt = r - (r / T.tx) * T.tx;
+  const int xt = idx / (hgt * T.tz);
+  const int r = idx - xt * hgt * T.tz;
+  const int j2 = r / hgt;
+  const int j1 = start + (r - j2 * hgt);
   const int ex = 1 << T.lx, ey = 1 << T.ly;
   i0 = H + xt * ex + (lane & (ex - 1));
   i1 = H + j1 * ey + ((lane >> T.lx) & (ey - 1));
