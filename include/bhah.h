@@ -291,18 +291,39 @@ int bhah_rk4_step_noalloc(const bhah_grid* g, const bhah_gauge_params* gp, doubl
 int bhah_constraints(const bhah_grid* g, const double* y, double* H, double* M,
                      double* C, void* stream);
 
-/* Tile shape of this grid's right-hand-side kernel (bhah_bssn_rhs and
- * bhah_rk4_step): 64 points, 2^lx along i0, 2^ly along i1, 64 >> (lx + ly)
- * along i2, walked in bands of `band` tile rows of i1. The extent along phi
- * (i1 on SinhCylindrical grids, i2 otherwise) must be 1. Default (6, 0, 4).
- * The shape changes speed only: every point's arithmetic is the same.       */
+/* Tile shape of this grid's right-hand-side kernel (bhah_bssn_rhs,
+ * bhah_rk4_step, bhah_ssprk3_step, bhah_evolve): 64 points, 2^lx along i0,
+ * 2^ly along i1, 64 >> (lx + ly) along i2, walked in bands of `band` tile
+ * rows of i1. The extent along phi (i1 on SinhCylindrical grids, i2
+ * otherwise) must be 1. Default (6, 0, 4). The shape changes speed only:
+ * every point's arithmetic is the same. Setting a shape keeps the number of
+ * waves per tile (below).                                                   */
 int bhah_grid_set_tile(bhah_grid* g, int lx, int ly, int band);
 int bhah_grid_get_tile(const bhah_grid* g, int* lx, int* ly, int* band);
 
+/* Waves per tile of this grid's right-hand-side kernel: 1 (default: one
+ * wave computes all of a point's right-hand sides) or 2 (two waves of one
+ * block share each point, one the metric part of Eqs. 7-15 with the Ricci
+ * tensor of Eq. 12, the other the gauge part, exchanging intermediates
+ * through LDS; each wave runs on its own SIMD). Two waves shorten a step on
+ * grids with at most half as many tiles as the device has SIMDs; the
+ * results agree with one wave to rounding (the sums are grouped
+ * differently), not bit for bit. The two-wave kernel exists at 4th order
+ * (nghosts = 3) without dissipation for every family and phi extent except
+ * the general SinhSpherical one, and with dissipation for SinhCylindrical
+ * grids of two phi planes; elsewhere the one-wave kernel runs whatever this
+ * is set to. Any value other than 1 or 2 gets BHAH_EINVAL. The ensemble
+ * engine and the server always use one wave per tile.                       */
+int bhah_grid_set_waves_per_tile(bhah_grid* g, int waves);
+int bhah_grid_get_waves_per_tile(const bhah_grid* g, int* waves);
+
 /* Time every allowed tile shape for this grid on state y (valid ghosts),
- * writing right-hand sides into rhs (state layout, caller-owned scratch),
- * after a few warm-up launches, in two passes; keep the first shape (larger
- * extents along i0 first) within 2% of the fastest. Synchronises stream.    */
+ * with one and with two waves per tile, writing right-hand sides into rhs
+ * (state layout, caller-owned scratch), after a few warm-up launches, in
+ * two passes; keep the first candidate within 2% of the fastest, one-wave
+ * shapes before two-wave ones and larger extents along i0 first (so two
+ * waves are chosen only when more than 2% faster than every one-wave
+ * shape). Synchronises stream.                                              */
 int bhah_grid_tune(bhah_grid* g, const bhah_gauge_params* gp, const double* y,
                    double* rhs, void* stream);
 

@@ -19,6 +19,7 @@ DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-pa
           "-ffp-contract=fast"]
 SOURCES = {
     "rhs_fused.hip": DEVICE + ["-fno-signed-zeros", "-ffinite-math-only"],
+    "rhs_pair.hip": DEVICE + ["-fno-signed-zeros", "-ffinite-math-only"],
     "hamiltonian.hip": DEVICE + ["-fno-signed-zeros", "-ffinite-math-only"],
     "misc.hip": DEVICE,
     "probe.hip": DEVICE,

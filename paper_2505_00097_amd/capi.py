@@ -106,6 +106,8 @@ _SIGS = {
     "bhah_constraints": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "bhah_grid_set_tile": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "bhah_grid_get_tile": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "bhah_grid_set_waves_per_tile": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "bhah_grid_get_waves_per_tile": (ctypes.c_int, [_vp, _vp]),
     "bhah_grid_tune": (ctypes.c_int, [_vp, ctypes.POINTER(GaugeParams), _vp, _vp, _vp]),
     "bhah_batch_create": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(GaugeParams), ctypes.c_char_p,
                                          ctypes.POINTER(_vp)]),
@@ -275,6 +277,16 @@ def grid_get_tile(h):
     _check(lib().bhah_grid_get_tile(h, ctypes.byref(lx), ctypes.byref(ly), ctypes.byref(band)),
            "bhah_grid_get_tile")
     return lx.value, ly.value, band.value
+
+
+def grid_set_waves_per_tile(h, waves):
+    _check(lib().bhah_grid_set_waves_per_tile(h, int(waves)), "bhah_grid_set_waves_per_tile")
+
+
+def grid_get_waves_per_tile(h):
+    w = ctypes.c_int()
+    _check(lib().bhah_grid_get_waves_per_tile(h, ctypes.byref(w)), "bhah_grid_get_waves_per_tile")
+    return w.value
 
 
 def grid_tune(h, y, rhs, eta=2.0, diss=(0.0, 0.0), stream=None):

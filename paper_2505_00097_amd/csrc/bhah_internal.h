@@ -129,6 +129,7 @@ int check_gauge(const bhah_gauge_params* gp, const char* who);
 // walked in bands of `band` tile rows of i1.
 struct TileCfg {
   int lx, ly, band;
+  int waves = 1;  // waves per 64-point tile of the solo kernel: 1 (rhs_fused.hip) or 2 (rhs_pair.hip)
 };
 
 // The stencil code reads the periodic direction (phi: i1 on SinhCylindrical
@@ -267,6 +268,12 @@ int launch_brill_lindquist(const GridDev& G, int n, const double* m, const doubl
 void launch_rhs_fused(const GridDev& G, const Gauge& ga, const double* y, double* aux, const StageArgs& st,
                       hipStream_t s, const TileCfg& cfg);
 TileMap make_tilemap(const GridDev& G, int lx, int ly, int band);
+// the right-hand side with two waves per tile (rhs_pair.hip); same
+// arguments and results as the one-wave kernel, to rounding; built for the
+// variants have_rhs_pair reports
+bool have_rhs_pair(const GridDev& G, bool ko);
+void launch_rhs_pair(const GridDev& G, const Gauge& ga, const double* y, double* aux, const StageArgs& st,
+                     hipStream_t s, const TileMap& T);
 // mix: the stages may combine two states (SSPRK3); RK4 stages never do.
 // counts (device, one int per job; NULL: every job) and kk: step kk of a
 // graph launch runs only the jobs with kk < counts[job].

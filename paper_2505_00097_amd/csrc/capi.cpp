@@ -335,7 +335,7 @@ int bhah_evolve(const bhah_grid* g, const bhah_gauge_params* gp, int integrator,
 
 int bhah_grid_set_tile(bhah_grid* g, int lx, int ly, int band) {
   if (!g) return fail(BHAH_EINVAL, "bhah_grid_set_tile: NULL grid");
-  const TileCfg c{lx, ly, band};
+  const TileCfg c{lx, ly, band, g->tile.waves};
   if (lx < 0 || ly < 0 || lx + ly > 6 || band < 1 || !tile_fits_periodic(g->params.coord, c))
     return fail(BHAH_EINVAL, "bhah_grid_set_tile: need 0 <= lx, ly, lx + ly <= 6, band >= 1 and extent 1 along phi");
   g->tile = c;
@@ -347,6 +347,19 @@ int bhah_grid_get_tile(const bhah_grid* g, int* lx, int* ly, int* band) {
   if (lx) *lx = g->tile.lx;
   if (ly) *ly = g->tile.ly;
   if (band) *band = g->tile.band;
+  return BHAH_OK;
+}
+
+int bhah_grid_set_waves_per_tile(bhah_grid* g, int waves) {
+  if (!g || (waves != 1 && waves != 2))
+    return fail(BHAH_EINVAL, "bhah_grid_set_waves_per_tile: need a grid and 1 or 2 waves");
+  g->tile.waves = waves;
+  return BHAH_OK;
+}
+
+int bhah_grid_get_waves_per_tile(const bhah_grid* g, int* waves) {
+  if (!g || !waves) return fail(BHAH_EINVAL, "bhah_grid_get_waves_per_tile: NULL argument");
+  *waves = g->tile.waves;
   return BHAH_OK;
 }
 
@@ -364,7 +377,15 @@ int bhah_grid_tune(bhah_grid* g, const bhah_gauge_params* gp, const double* y, d
   }
   const StageArgs st{rhs, nullptr, nullptr, 0.0, nullptr, nullptr, 0.0};
   const SizeClass cls{g->params.coord, g->params.N[0], g->params.N[1], g->params.N[2]};
-  const std::vector<TileCfg> cand = tile_candidates(cls);
+  // every tile shape with one wave per tile, then the same shapes with two
+  // (the two-wave kernel wins only where the grid leaves SIMDs idle)
+  std::vector<TileCfg> cand = tile_candidates(cls);
+  const size_t n1 = have_rhs_pair(g->dev, gauge_of(*gp).ko()) ? cand.size() : 0;
+  for (size_t i = 0; i < n1; i++) {
+    TileCfg c = cand[i];
+    c.waves = 2;
+    cand.push_back(c);
+  }
   // a few launches first (clocks and caches settle), then every candidate
   // timed in two passes; each keeps its better pass
   for (int r = 0; r < 8; r++) launch_rhs_fused(g->dev, gauge_of(*gp), y, nullptr, st, s, g->tile);

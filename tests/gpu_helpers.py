@@ -58,17 +58,22 @@ def _abs_errors(a, ref, pts):
     return np.array([float(np.max(np.abs(a[g][pts].astype(np.longdouble) - ref[g][pts]))) for g in range(len(ref))])
 
 
-def pointwise(a, ref, pts):
+def pointwise(a, ref, pts, groups=GROUPS):
     """p50 / p99 / max of |a - ref| / |ref| over the points where |ref| exceeds
-    1e-8 of its gridfunction's largest magnitude, all gridfunctions together"""
+    1e-8 of its gridfunction's largest magnitude, all gridfunctions together;
+    components that vanish by symmetry (largest magnitude below 1e-6 of their
+    tensor's, round-off only) are left out"""
     rel = []
-    for g in range(len(ref)):
-        r = ref[g][pts]
-        m = float(np.max(np.abs(r))) if r.size else 0.0
-        if m == 0.0:
-            continue
-        sel = np.abs(r) > 1e-8 * m
-        rel.append((np.abs(a[g][pts][sel].astype(np.longdouble) - r[sel]) / np.abs(r[sel])).astype(np.float64))
+    for grp in groups:
+        own = {g: float(np.max(np.abs(ref[g][pts]))) if ref[g][pts].size else 0.0 for g in grp}
+        top = max(own.values())
+        for g in grp:
+            m = own[g]
+            if m == 0.0 or m < 1e-6 * top:
+                continue
+            r = ref[g][pts]
+            sel = np.abs(r) > 1e-8 * m
+            rel.append((np.abs(a[g][pts][sel].astype(np.longdouble) - r[sel]) / np.abs(r[sel])).astype(np.float64))
     v = np.concatenate(rel) if rel else np.zeros(1)
     return float(np.percentile(v, 50)), float(np.percentile(v, 99)), float(np.max(v))
 
@@ -94,7 +99,7 @@ def check_parity(label, gpu, fp64, ld, pts, tol, groups=GROUPS, names=None):
     # relative errors for the report (absolute where the tensor is zero)
     rel = np.where(scale > 0, scale, 1.0)
     e_gpu, e_cpu = d_gpu / rel, d_cpu / rel
-    p50, p99, pmax = pointwise(gpu, ld, pts)
+    p50, p99, pmax = pointwise(gpu, ld, pts, groups)
     worst = int(np.argmax(d_gpu / allowed))
     nm = names[worst] if names is not None else str(worst)
     print(f"PARITY {label} | gpu {np.max(e_gpu):.2e} | fp64 {np.max(e_cpu):.2e} | tol {tol:.0e} | "

@@ -525,7 +525,7 @@ def test_rk4_evolution_matches_oracle(name, m, pos, steps):
     check_parity(f"rk4 {name} {steps} steps", out, yo, yl, og.interior(), EVOL_TOL, names=orc.GF_NAMES)
     # ghosts too
     check_parity(f"rk4 {name} {steps} steps, every point", out, yo, yl, (slice(None),) * 3, EVOL_TOL,
-                 groups=[range(24)], names=orc.GF_NAMES)
+                 names=orc.GF_NAMES)
 
 
 @pytest.mark.parametrize("name,m,pos,steps", [
@@ -553,7 +553,7 @@ def test_ssprk3_evolution_matches_oracle(name, m, pos, steps):
     out = to_cpu(y)
     check_parity(f"ssprk3 {name} {steps} steps", out, yo, yl, og.interior(), EVOL_TOL, names=orc.GF_NAMES)
     check_parity(f"ssprk3 {name} {steps} steps, every point", out, yo, yl, (slice(None),) * 3, EVOL_TOL,
-                 groups=[range(24)], names=orc.GF_NAMES)
+                 names=orc.GF_NAMES)
 
 
 def test_headon_workload_100_steps_matches_oracle():
@@ -686,7 +686,10 @@ def test_phi_ghost_planes_are_never_read(name):
 @pytest.mark.parametrize("name", ["sph_ragged", "cyl_ragged", "spherical"])
 def test_tile_shape_does_not_change_results(name):
     """Every allowed tile shape of the solo kernel gives the same RK4 step,
-    bit for bit; bhah_grid_tune picks one of them; shapes that cross phi are
+    bit for bit, with one wave per tile and again with two (where a two-wave
+    kernel is built; elsewhere the one-wave kernel runs); one and two waves
+    agree to rounding; bhah_grid_tune picks one shape and mode, and the step
+    then equals that mode's, bit for bit; shapes that cross phi are
     rejected."""
     _print_case("solo tiles", name)
     import torch
@@ -694,29 +697,39 @@ def test_tile_shape_does_not_change_results(name):
     g, og = _pair(name)
     y0 = to_gpu(og.apply_bcs(wl.smooth_random_state(og.n, seed=21)))
     ws = g.workspace()
-    ref = None
     shapes = [(6, 0, 4), (5, 0, 1), (4, 0, 4), (3, 0, 1)] if g.coord == wl.SINH_CYLINDRICAL else \
         [(6, 0, 4), (5, 1, 1), (4, 2, 4), (3, 3, 1)]
-    for shp in shapes:
-        capi.grid_set_tile(g.h, *shp)
-        assert capi.grid_get_tile(g.h) == shp
-        y = y0.clone()
-        capi.rk4_step(g.h, y, ws, g.dt)
-        torch.cuda.synchronize()
-        if ref is None:
-            ref = y
-        else:
-            assert torch.equal(y, ref), shp
+    refs = {}
+    for waves in (1, 2):
+        capi.grid_set_waves_per_tile(g.h, waves)
+        ref = None
+        for shp in shapes:
+            capi.grid_set_tile(g.h, *shp)
+            assert capi.grid_get_tile(g.h) == shp and capi.grid_get_waves_per_tile(g.h) == waves
+            y = y0.clone()
+            capi.rk4_step(g.h, y, ws, g.dt)
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = y
+            else:
+                assert torch.equal(y, ref), (waves, shp)
+        refs[waves] = ref
+    a, b = to_cpu(refs[1]), to_cpu(refs[2])
+    check_parity(f"one vs two waves per tile, rk4 step {name}", b, a, None, (slice(None),) * 3, 1e-13,
+                 names=orc.GF_NAMES)
     bad = (5, 1, 1) if g.coord == wl.SINH_CYLINDRICAL else (4, 0, 4)
     with pytest.raises(capi.BhahError):
         capi.grid_set_tile(g.h, *bad)
+    capi.grid_set_waves_per_tile(g.h, 1)
     capi.grid_tune(g.h, y0, g.state())
     lx, ly, band = capi.grid_get_tile(g.h)
     assert 3 <= lx <= 6 and lx + ly <= 6 and band >= 1
+    waves = capi.grid_get_waves_per_tile(g.h)
+    print(f"  tuned: tile {(lx, ly, band)}, {waves} wave(s) per tile", flush=True)
     y = y0.clone()
     capi.rk4_step(g.h, y, ws, g.dt)
     torch.cuda.synchronize()
-    assert torch.equal(y, ref)
+    assert torch.equal(y, refs[waves])
 
 
 @pytest.mark.parametrize("coord,N", [(wl.SINH_SPHERICAL, (3, 3, 2)), (wl.SINH_CYLINDRICAL, (3, 2, 3)),
