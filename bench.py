@@ -64,6 +64,14 @@ KERNEL_SOURCES = ["paper_2505_00097_amd/csrc/rhs_fused.hip", "paper_2505_00097_a
                   "paper_2505_00097_amd/csrc/rhs_common.h", "paper_2505_00097_amd/csrc/bhah_internal.h"]
 
 
+_T0 = time.perf_counter()
+
+
+def stamp():
+    """seconds since the benchmark started, for the progress lines"""
+    return "%6.1fs" % (time.perf_counter() - _T0)
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
@@ -363,7 +371,7 @@ def serve(capi, stream, jobs, descs, max_jobs, steps_per_tick, target_points, la
             time.sleep(max(0.0, arrival[i] - (time.perf_counter() - t0)))
         if time.perf_counter() - last_print > 20.0:
             last_print = time.perf_counter()
-            print(f"# {label}: {i}/{len(jobs)} arrived, {running} running, {queued} queued", file=sys.stderr,
+            print(f"# {stamp()} {label}: {i}/{len(jobs)} arrived, {running} running, {queued} queued", file=sys.stderr,
                   flush=True)
     wall = time.perf_counter() - t0 - arrival[0]
     st = capi.server_get_stats(srv)
@@ -394,7 +402,7 @@ def run_served(capi, wl, stream, n_jobs, steps_per_tick, target_points, n_satura
                        "steps U{200..2000}, seed 250500098, 200 GB budget",
            "target_points": target_points, "steps_per_tick": steps_per_tick}
     out.update(served_summary(st, wall))
-    print(f"# served: {out['value']:.3e} pt-steps/s", file=sys.stderr, flush=True)
+    print(f"# {stamp()} served: {out['value']:.3e} pt-steps/s", file=sys.stderr, flush=True)
     st, wall = serve(capi, stream, jobs, descs, 1, steps_per_tick, 0, "served one at a time")
     out["sequential_fcfs"] = served_summary(st, wall)
     out["sequential_fcfs"]["how"] = "the same arrivals through the same server with max_jobs = 1 (measured)"
@@ -407,7 +415,7 @@ def run_served(capi, wl, stream, n_jobs, steps_per_tick, target_points, n_satura
                      at_once=True)
     out["saturated"]["sequential_fcfs"] = served_summary(st, wall)
     out["saturated"]["speedup_vs_sequential"] = out["saturated"]["value"] / out["saturated"]["sequential_fcfs"]["value"]
-    print(f"# saturated: {out['saturated']['value']:.3e} vs one at a time "
+    print(f"# {stamp()} saturated: {out['saturated']['value']:.3e} vs one at a time "
           f"{out['saturated']['sequential_fcfs']['value']:.3e} pt-steps/s", file=sys.stderr, flush=True)
     return out
 
@@ -599,7 +607,7 @@ def main():
         chunk_ms = [(ev[c].elapsed_time(ev[c + 1]) / (bounds[c + 1] - bounds[c])) for c in range(len(bounds) - 1)]
         elapsed = t1 - t0
         finite = bool(torch.isfinite(y).all().item())
-        print(f"# plain: {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+        print(f"# {stamp()} plain: {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
         # single-step latency: bhah_rk4_step calls, one event per step
         lat_ev = events(args.latency_steps + 1)
         lat_ev[0].record(stream)
@@ -617,7 +625,7 @@ def main():
         extras = {}
         if args.tiny_steps > 0:
             extras["tiny"] = run_tiny(capi, wl, stream, args.tiny_steps, 20)
-            print(f"# tiny: {extras['tiny']['value']:.3e} pt-steps/s, step p50/p99 "
+            print(f"# {stamp()} tiny: {extras['tiny']['value']:.3e} pt-steps/s, step p50/p99 "
                   f"{extras['tiny']['p50_step_ms']:.3f}/{extras['tiny']['p99_step_ms']:.3f} ms", file=sys.stderr,
                   flush=True)
         if args.ssprk3_steps > 0:
@@ -633,31 +641,31 @@ def main():
                 capi, wl, stream, args.ssprk3_steps, diss=(0.99, 0.3), bc_kind=capi.BC_RADIATION, nghosts=5,
                 rhs_reps=args.rhs_reps)
             torch.cuda.empty_cache()
-            print(f"# ssprk3 + dissipation: {extras['ssprk3']['value']:.3e} pt-steps/s, with the radiation "
+            print(f"# {stamp()} ssprk3 + dissipation: {extras['ssprk3']['value']:.3e} pt-steps/s, with the radiation "
                   f"boundary {extras['production_numerics']['value']:.3e}, at 8th order "
                   f"{extras['production_numerics_8th_order']['value']:.3e}", file=sys.stderr, flush=True)
         if args.batched_steps > 0:
             extras["batched"] = run_batched(capi, wl, stream, args.batched_steps, args.batched_seq_steps,
                                             args.graph_steps, tune_launch=True)
             torch.cuda.empty_cache()
-            print(f"# batched: {extras['batched']['value']:.3e} pt-steps/s", file=sys.stderr, flush=True)
+            print(f"# {stamp()} batched: {extras['batched']['value']:.3e} pt-steps/s", file=sys.stderr, flush=True)
             extras["batched_production_numerics"] = run_batched(
                 capi, wl, stream, args.batched_steps, args.batched_seq_steps, args.graph_steps,
                 integrator=capi.SSPRK3, diss=(0.99, 0.3), bc_kind=capi.BC_RADIATION)
             torch.cuda.empty_cache()
-            print(f"# batched, SSPRK3 + dissipation + radiation: "
+            print(f"# {stamp()} batched, SSPRK3 + dissipation + radiation: "
                   f"{extras['batched_production_numerics']['value']:.3e} pt-steps/s", file=sys.stderr, flush=True)
             extras["batched_production_numerics_8th_order"] = run_batched(
                 capi, wl, stream, args.batched_steps, args.batched_seq_steps, args.graph_steps,
                 integrator=capi.SSPRK3, diss=(0.99, 0.3), bc_kind=capi.BC_RADIATION, nghosts=5)
             torch.cuda.empty_cache()
-            print(f"# batched, production numerics at 8th order: "
+            print(f"# {stamp()} batched, production numerics at 8th order: "
                   f"{extras['batched_production_numerics_8th_order']['value']:.3e} pt-steps/s", file=sys.stderr,
                   flush=True)
         if args.study_steps > 0:
             extras["rhs_study_3d"] = run_rhs_study(capi, wl, stream, args.rhs_reps // 5 + 1, args.study_steps)
             torch.cuda.empty_cache()
-            print("# 3-D study done", file=sys.stderr, flush=True)
+            print(f"# {stamp()} 3-D study done", file=sys.stderr, flush=True)
         if not args.no_paper_grids:
             extras["paper_desktop_grid"] = run_paper_grid(
                 capi, wl, stream, "the paper's single-node benchmark grid", (72, 12, 24), 7.5, 8428, 50,
@@ -667,7 +675,7 @@ def main():
                 capi, wl, stream, "the paper's strong-scaling grid", (1008, 168, 336), 7.5, 124, 4,
                 "about 33 s with superB on 64 nodes (7168 cores); about 1462 s with NRPy/OpenMP on one node")
             torch.cuda.empty_cache()
-            print("# paper grids done", file=sys.stderr, flush=True)
+            print(f"# {stamp()} paper grids done", file=sys.stderr, flush=True)
         if args.served_jobs > 0:
             extras["served"] = run_served(capi, wl, stream, args.served_jobs, args.graph_steps,
                                           args.served_target_points,
@@ -706,6 +714,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+        print(f"# {stamp()} cpu baseline done", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 
