@@ -43,7 +43,7 @@ enum {
   XS_RT = 33,    // 6   rescaled Ricci tensor (after barrier 1)
   XS_DH = 42,    // 18  metric wave's park: d_k h_ij at XS_DH + 3 sy(i, j) + k
   XS_GOUT = 60,  // 18  gauge wave's park of its results (gridfunctions 0..10, 17..23)
-  XSLOTS = 78    // 78 x 64 lanes x 8 B = 39 KB per block: four blocks per CU
+  XSLOTS = 78    // 78 x 64 lanes x 8 B = 39 KB per block; two blocks (four waves) per CU
 };
 
 // the gauge wave's result slot of gridfunction g (not one of h_ij)
