@@ -138,10 +138,17 @@ def roofline(kernel, flops_per_point, points, launch_s, traffic, probe=None):
     return out
 
 
-def kernel_name(coord, N, ko=False, nghosts=3, waves=1):
-    return "k_rhs_%s<%d,%s,%s,%d>" % ("pair" if waves == 2 else "fused", coord,
-                                       "true" if two_planes(coord, N) else "false", "true" if ko else "false",
-                                       nghosts)
+def kernel_name(coord, N, ko=False, nghosts=3, waves=1, tile=None):
+    """The right-hand-side kernel the library launches for this grid, tile
+    and mode: on two-phi-plane grids with row tiles (lx = 6) the one-wave
+    kernel reads its phase-1 stencils from an LDS stage (last template
+    argument), except at 8th order with dissipation."""
+    ax = two_planes(coord, N)
+    b = lambda v: "true" if v else "false"
+    if waves == 2:
+        return "k_rhs_pair<%d,%s,%s,%d>" % (coord, b(ax), b(ko), nghosts)
+    staged = ax and tile is not None and tile[0] == 6 and (nghosts == 3 or not ko)
+    return "k_rhs_fused<%d,%s,%s,%d,%s>" % (coord, b(ax), b(ko), nghosts, b(staged))
 
 
 def percentile(v, p):
@@ -268,7 +275,7 @@ def run_ssprk3(capi, wl, stream, steps, diss=(0.0, 0.0), bc_kind=0, nghosts=3, r
             out["rhs_frac_fp64_peak"] = f * n / rhs_s / PEAK_FP64_VECTOR
             if nghosts == 5:
                 tile = list(capi.grid_get_tile(ge.h))
-                out["roofline"] = roofline(kernel_name(w["coord"], w["N"], ko=True, nghosts=5), f, n, rhs_s,
+                out["roofline"] = roofline(kernel_name(w["coord"], w["N"], ko=True, nghosts=5, tile=tile), f, n, rhs_s,
                                            measured_traffic("headon_sinhcylindrical_128x2x256", tile, nghosts=5))
         del ye
     return out
@@ -454,7 +461,7 @@ def run_rhs_study(capi, wl, stream, reps, steps):
     name = "vacuum3d_sinhspherical_256x128x64"
     eighth = {"rhs_launch_s": rhs8_s, "flops_per_point": f8, "rhs_TFLOPs": f8 * n / rhs8_s / 1e12,
               "rhs_frac_fp64_peak": f8 * n / rhs8_s / PEAK_FP64_VECTOR, "tile": tile8,
-              "roofline": roofline(kernel_name(w["coord"], w["N"], ko=True, nghosts=5), f8, n, rhs8_s,
+              "roofline": roofline(kernel_name(w["coord"], w["N"], ko=True, nghosts=5, tile=tile8), f8, n, rhs8_s,
                                    measured_traffic(name, tile8, nghosts=5))}
     del y8
     return {"workload": name, "interior_points": n,
@@ -463,7 +470,7 @@ def run_rhs_study(capi, wl, stream, reps, steps):
             "rhs_alg_GBps": BYTES_ALG * n / rhs_s / 1e9,
             "rk4_step_ms": step_s * 1e3, "value": n / step_s, "unit": UNIT,
             "tile": tile, "rhs_8th_order_with_dissipation": eighth,
-            "roofline": roofline(kernel_name(w["coord"], w["N"]), f_alg(w["coord"], w["N"]), n, rhs_s,
+            "roofline": roofline(kernel_name(w["coord"], w["N"], tile=tile), f_alg(w["coord"], w["N"]), n, rhs_s,
                                  measured_traffic(name, tile))}
 
 
@@ -707,7 +714,8 @@ def main():
                            "event pair per step",
                     "timed_chunks_ms_per_step": chunk_ms},
         "finite": finite,
-        "roofline": roofline(kernel_name(w["coord"], w["N"], waves=waves), f_alg(w["coord"], w["N"]), n_int, rhs_s,
+        "roofline": roofline(kernel_name(w["coord"], w["N"], waves=waves, tile=capi.grid_get_tile(g.h)),
+                             f_alg(w["coord"], w["N"]), n_int, rhs_s,
                              traffic,
                              probe),
         "extras": extras,

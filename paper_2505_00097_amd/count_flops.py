@@ -1,10 +1,11 @@
 """FP64 operations per interior point of one right-hand-side evaluation.
 
 Compiles the right-hand-side kernel source to optimised device LLVM IR with
-the library's own flags and counts, in each k_rhs_fused<C, AX, KO, H> kernel
+the library's own flags and counts, in each k_rhs_fused<C, AX, KO, H, STG> kernel
 (AX: the variant for grids with two phi planes, whose identically vanishing
 phi derivatives the compiler removes; KO: Kreiss-Oliger dissipation on; H:
-ghost layers, 3 for 4th-order and 5 for 8th-order differences), the double
+ghost layers, 3 for 4th-order and 5 for 8th-order differences; STG: phase 1
+through the LDS stage, the same arithmetic on the same values), the double
 precision fadd / fsub / fmul / fdiv instructions (an fma or fmuladd call
 counts 2) of the basic blocks that store nothing to global memory: that is
 the per-point arithmetic of Eqs. 7-15 after common-subexpression elimination,
@@ -35,13 +36,15 @@ def device_ir(src):
         return f.read()
 
 
-def count(ir, kernel_prefix="_ZN4bhah11k_rhs_fusedILi", dissipation=False, nghosts=3):
+def count(ir, kernel_prefix="_ZN4bhah11k_rhs_fusedILi", dissipation=False, nghosts=3, staged=False):
     """{(coord, two_phi_planes): FP64 operations per point} of the kernels
     with `nghosts` ghost layers, without (or, with dissipation=True, with)
-    Kreiss-Oliger dissipation"""
+    Kreiss-Oliger dissipation; staged=True counts the forms whose phase 1
+    reads its stencils from the LDS stage (two phi planes only)"""
     res = {}
-    for m in re.finditer(r"define [^@]*@(" + re.escape(kernel_prefix) + r"(\d)ELb(\d)ELb(\d)ELi(\d)E\S*)\(", ir):
-        if bool(int(m.group(4))) != dissipation or int(m.group(5)) != nghosts:
+    pat = r"(\d)ELb(\d)ELb(\d)ELi(\d)ELb(\d)E\S*)\("
+    for m in re.finditer(r"define [^@]*@(" + re.escape(kernel_prefix) + pat, ir):
+        if bool(int(m.group(4))) != dissipation or int(m.group(5)) != nghosts or bool(int(m.group(6))) != staged:
             continue
         name, c = m.group(1), (int(m.group(2)), bool(int(m.group(3))))
         body = ir[m.start():ir.index("\n}\n", m.start())]
@@ -59,9 +62,11 @@ def main():
     ir = device_ir(os.path.join(HERE, "csrc", "rhs_fused.hip"))
     for ng in (3, 5):
         for ko in (False, True):
+            staged = count(ir, dissipation=ko, nghosts=ng, staged=True)
             for (c, ax), n in sorted(count(ir, dissipation=ko, nghosts=ng).items()):
+                st = f" (staged form: {staged[(c, ax)]})" if (c, ax) in staged else ""
                 print(f"order {2 * (ng - 1)}: {COORD_NAMES[c]}{' (two phi planes)' if ax else ''}"
-                      f"{' + dissipation' if ko else ''}: {n} FP64 operations per point")
+                      f"{' + dissipation' if ko else ''}: {n} FP64 operations per point{st}")
 
 
 if __name__ == "__main__":

@@ -43,15 +43,194 @@ enum { PK_PC = 0, PK_QS = 6, PK_Y = 9, PK_ZA = 15, PK_BV = 16, PK_BD = 19, PK_RT
        PK_DH = PK_OUT, PK_D1 = 55, PK_ADV = 70 };
 static_assert(PK_ADV + 8 == PARK && PK_DH + 18 <= PK_OUT + G_VETU0, "park layout");
 
+// Phase 1 through an LDS stage, on grids with two phi planes and tiles of
+// 64 points along i0. The CU's vector memory address unit takes about the
+// same time for every load instruction of a wave, whatever its width, so the
+// per-lane stencil gathers (one or two values per instruction) keep it busy
+// while the SIMDs wait. Here the wave brings in, for one gridfunction at a
+// time, the values its stencils read on the tile's own phi plane -- rows
+// -H..H along the other transverse direction e, columns -H..63+H along i0 --
+// with a few 16-byte loads shared by the whole wave, and every stencil value
+// then comes from LDS. The stage takes the park slots that phase 1 writes
+// only at its end (0..30); gridfunctions go in batches that fit there, the
+// next batch's loads in flight while the current one is worked. Every
+// accumulation takes the same terms in the same order as the pair-by-pair
+// loop, each as an explicit fused multiply-add (left to itself, the compiler
+// may fuse either product of a sum of two), so the results are bitwise the
+// same.
+template <int H>
+struct StageGeom {
+  static constexpr int RL = 64 + 2 * H;                  // doubles per stage row
+  static constexpr int NP = (2 * H + 1) * RL / 2;        // 16-byte pieces per gridfunction
+  static constexpr int NR = (NP + 63) / 64;              // pieces per lane
+  static constexpr int PER = (31 * 64 * 8) / (NP * 16);  // gridfunctions per batch
+  static constexpr int NB = (11 + PER - 1) / PER;        // batches
+};
+
+template <int C, bool KO, int H>
+__device__ __forceinline__ void phase1_staged(const PtT<H>& P, const Gauge& ga, const Spacing& sp, const Ref& R,
+                                              const UpwindT<H>& U, const double (&vet)[3], const double (&beta)[3],
+                                              const double (&gbU)[6], const double (&SS)[6], const double (&kw)[3],
+                                              double aW, double* __restrict__ stage, double* __restrict__ park,
+                                              int lane, double (&Pc)[6], double (&Qs)[3], double (&Y)[6],
+                                              double& Za, double (&Bv)[3], double (&Bd)[3], double (&adv)[11]) {
+  constexpr int PD = C == BHAH_SINH_CYLINDRICAL ? 1 : 2;  // phi
+  constexpr int E = 3 - PD;                               // the other transverse direction
+  constexpr int RR = H - 1, SW = 2 * RR + 1, XW = 2 * RR;
+  using SG = StageGeom<H>;
+  constexpr int RL = SG::RL, NP = SG::NP, NR = SG::NR, PER = SG::PER, NB = SG::NB;
+  static_assert(PER * NP * 2 <= PK_OUT * 64, "the stage must stay below the slots phase 1 writes");
+  constexpr int G11[11] = {G_HDD00, G_HDD00 + 1, G_HDD00 + 2, G_HDD00 + 3, G_HDD00 + 4, G_HDD00 + 5,
+                           G_CF, G_ALPHA, G_VETU0, G_VETU0 + 1, G_VETU0 + 2};
+  auto put = [&](int v, double x) { park[v * 64] = x; };
+
+  // piece r*64 + lane of a gridfunction's stage (the last ones repeated to
+  // fill the last load): its byte offset from the tile's first column
+  const unsigned vb0 = __builtin_amdgcn_readfirstlane(P.vb);  // lane 0 is never clamped
+  unsigned voff[NR];
+  int poff[NR];
+#pragma unroll
+  for (int r = 0; r < NR; r++) {
+    const int p = min(r * 64 + lane, NP - 1);
+    const int row = p / (RL / 2), col = 2 * (p - row * (RL / 2));
+    voff[r] = vb0 + (unsigned)((col + row * P.se) * 8);
+    poff[r] = 2 * p;
+  }
+  const int soff = P.sw[H];  // the tile's own phi plane
+
+  double G2[6];  // gammabar^ab S_a S_b, doubled off the diagonal
+#pragma unroll
+  for (int a = 0; a < 3; a++)
+#pragma unroll
+    for (int b = a; b < 3; b++) G2[sy(a, b)] = (a == b ? 1.0 : 2.0) * gbU[sy(a, b)] * SS[sy(a, b)];
+  double ck[6], ddW[6];
+#pragma unroll
+  for (int a = 0; a < 6; a++) ck[a] = 0.0;
+
+  const bool up0 = vet[0] > 0.0, upE = vet[E] > 0.0;
+  const int fu0 = up0 ? H : -H, fuE = upE ? H * RL : -H * RL;  // upwind far points
+  double nlo[PER][NR], nhi[PER][NR], nph[PER];
+  auto issue = [&](int b) {
+#pragma unroll
+    for (int t = 0; t < PER; t++)
+      if (b * PER + t < 11) {
+        const int g = G11[b * PER + t];
+#pragma unroll
+        for (int r = 0; r < NR; r++) gf_ld2(P.y, P.sgf, g, voff[r], soff, nlo[t][r], nhi[t][r]);
+        nph[t] = P.template ax<PD>(g, 1);  // the other phi plane
+      }
+  };
+  issue(0);
+#pragma unroll
+  for (int b = 0; b < NB; b++) {
+    double oph[PER];
+#pragma unroll
+    for (int t = 0; t < PER; t++)
+      if (b * PER + t < 11) {
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+          stage[t * 2 * NP + poff[r]] = nlo[t][r];
+          stage[t * 2 * NP + poff[r] + 1] = nhi[t][r];
+        }
+        oph[t] = nph[t];
+      }
+    if (b + 1 < NB) issue(b + 1);
+    BHAH_PHASE_BARRIER();
+#pragma unroll
+    for (int t = 0; t < PER; t++) {
+      const int tt = b * PER + t;
+      if (tt >= 11) continue;
+      const double* F = stage + t * 2 * NP + H * RL + H + lane;  // this point's value
+      auto at = [&](int de, int d0) { return F[de * RL + d0]; };
+      double v0[SW], vE[SW], vP[SW], vx[XW * XW];
+#pragma unroll
+      for (int m = -RR; m <= RR; m++) {
+        v0[RR + m] = at(0, m);
+        vE[RR + m] = at(m, 0);
+      }
+#pragma unroll
+      for (int m = 0; m < SW; m++) vP[m] = ((m - RR) & 1) ? oph[t] : v0[RR];
+#pragma unroll
+      for (int a = 0; a < XW; a++)
+#pragma unroll
+        for (int c = 0; c < XW; c++) vx[XW * a + c] = at(c < RR ? c - RR : c - RR + 1, a < RR ? a - RR : a - RR + 1);
+      const double far0 = F[fu0], farE = F[fuE];
+      double near0 = 0.0, nearE = 0.0;
+      if constexpr (KO) {
+        near0 = F[-fu0];
+        nearE = F[-fuE];
+      }
+      // diagonal pairs in the order k = 0, 1, 2: advection, first derivative
+#pragma unroll
+      for (int k = 0; k < 3; k++) {
+        const double(&vk)[SW] = k == 0 ? v0 : (k == PD ? vP : vE);
+        const double fu = k == 0 ? far0 : (k == PD ? vP[RR - 1] : farE);
+        const bool up = vet[k] > 0.0;
+        adv[tt] = fma(U.w[k], upwind_sum<RR>(vk, fu, up), adv[tt]);
+        if constexpr (KO) {
+          const double fd = k == 0 ? near0 : (k == PD ? vP[RR - 1] : nearE);
+          adv[tt] = fma((tt < 7 ? ga.dm : ga.dg) * kw[k], ko_v<RR>(vk, fu, fd), adv[tt]);
+        }
+        const double d1 = k == PD ? 0.0 : d1_axis<RR>(vk, sp.d1s[k]);
+        const int slot =
+            tt < 6 ? PK_DH + 3 * tt : (tt == 6 ? PK_D1 + 9 : (tt == 7 ? PK_D1 + 12 : PK_D1 + 3 * (tt - 8)));
+        put(slot + k, d1);
+      }
+      const double dd00 = d2_axis<RR>(v0, sp.d2s[0]), ddPP = d2_axis<RR>(vP, sp.d2s[PD]);
+      const double ddEE = d2_axis<RR>(vE, sp.d2s[E]), dd0E = d2_cross<RR>(vx, sp.crs[0][E]);
+      // the pairs (k, l) in the loop's order; those with a phi index vanish
+#pragma unroll
+      for (int k = 0; k < 3; k++)
+#pragma unroll
+        for (int l = k; l < 3; l++) {
+          const int kl = sy(k, l);
+          if (k != l && (k == PD || l == PD)) {
+            if (tt == 7) Y[kl] = 0.0;
+            continue;
+          }
+          const double dd = k != l ? dd0E : (k == 0 ? dd00 : (k == PD ? ddPP : ddEE));
+          const double wg = (k == l ? 1.0 : 2.0) * gbU[kl];
+          if (tt < 6) {
+            Pc[tt] = fma(wg, dd, Pc[tt]);
+            ck[kl] = fma(G2[tt], dd, ck[kl]);
+          } else if (tt == 6) {
+            ddW[kl] = dd;
+          } else if (tt == 7) {
+            Y[kl] = fma(aW, ddW[kl], -dd);
+            Za = fma(wg, dd, Za);
+          } else {
+            const int i = tt - 8;
+            Bv[i] = fma(wg, dd, Bv[i]);
+            if (i == l) Bd[k] = fma(dd, R.iS[l], Bd[k]);
+            if (k != l && i == k) Bd[l] = fma(dd, R.iS[k], Bd[l]);
+          }
+        }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 3; k++)
+#pragma unroll
+    for (int l = k; l < 3; l++) {
+      if (k != l && (k == PD || l == PD)) continue;
+      const double c = ck[sy(k, l)];
+      Qs[k] = fma(beta[l], c, Qs[k]);
+      if (k != l) Qs[l] = fma(beta[k], c, Qs[l]);
+    }
+}
+
 // MIX: the epilogue also handles stages that mix two states (SSPRK3); the
 // ensemble kernel is built with it only for SSPRK3 batches (keeping the
 // two-state path out of RK4 stages saves registers there).
 // H: ghost layers N_G; the differences are of order 2(H-1) (3: 4th order,
 // 5: 8th order).
-template <int C, bool AX, bool KO, bool MIX, int H>
+// STG: phase 1 through the LDS stage (two phi planes, tiles of 64 points
+// along i0); every lane of the wave takes part, and a lane whose point lies
+// past the grid (live false) computes a clamped point and stores nothing.
+template <int C, bool AX, bool KO, bool MIX, int H, bool STG = false>
 __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, const double* __restrict__ y,
                                             const StageArgs& st, int i0, int i1, int i2, unsigned q,
-                                            double* __restrict__ aux, double* __restrict__ park) {
+                                            double* __restrict__ aux, double* __restrict__ park, bool live = true) {
+  static_assert(!STG || AX, "the stage holds one phi plane");
   constexpr int PD = C == BHAH_SINH_CYLINDRICAL ? 1 : 2;  // the periodic (phi) direction
   constexpr int RR = H - 1, SW = 2 * RR + 1;               // stencil radius and width
   const double eta = ga.eta;
@@ -125,7 +304,11 @@ __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, c
   for (int a = 0; a < 6; a++) Pc[a] = 0.0;
 #pragma unroll
   for (int i = 0; i < 3; i++) { Qs[i] = 0.0; Bv[i] = 0.0; Bd[i] = 0.0; }
-  {
+  if constexpr (STG) {
+    const int lane = (int)(threadIdx.x & 63);
+    phase1_staged<C, KO, H>(P, ga, sp, R, U, vet, beta, gbU, SS, kw, alpha * iW, park - lane, park, lane, Pc,
+                            Qs, Y, Za, Bv, Bd, adv);
+  } else {
     double G2[6];  // gammabar^ab S_a S_b, doubled off the diagonal
 #pragma unroll
     for (int a = 0; a < 3; a++)
@@ -160,9 +343,10 @@ __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, c
             for (int t = 0; t < TB; t++)
               if (t0 + t < 11) {
                 const int tt = t0 + t;
-                adv[tt] += U.w[k] * upwind_sum<RR>(v[t], fu[t], up);
+                adv[tt] = fma(U.w[k], upwind_sum<RR>(v[t], fu[t], up), adv[tt]);
                 // h_ij and W take the metric strength, alpha and vet^i the gauge one
-                if constexpr (KO) adv[tt] += (tt < 7 ? ga.dm : ga.dg) * kw[k] * ko_v<RR>(v[t], fu[t], fd[t]);
+                if constexpr (KO)
+                  adv[tt] = fma((tt < 7 ? ga.dm : ga.dg) * kw[k], ko_v<RR>(v[t], fu[t], fd[t]), adv[tt]);
               }
 #pragma unroll
             for (int t = 0; t < TB; t++)
@@ -200,18 +384,18 @@ __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, c
         double c = 0.0;
 #pragma unroll
         for (int a = 0; a < 6; a++) {
-          Pc[a] += wg * dd[a];
-          c += G2[a] * dd[a];
+          Pc[a] = fma(wg, dd[a], Pc[a]);
+          c = fma(G2[a], dd[a], c);
         }
-        Qs[k] += beta[l] * c;
-        if (k != l) Qs[l] += beta[k] * c;
-        Y[kl] = aW * dd[6] - dd[7];
-        Za += wg * dd[7];
+        Qs[k] = fma(beta[l], c, Qs[k]);
+        if (k != l) Qs[l] = fma(beta[k], c, Qs[l]);
+        Y[kl] = fma(aW, dd[6], -dd[7]);
+        Za = fma(wg, dd[7], Za);
 #pragma unroll
         for (int i = 0; i < 3; i++) {
-          Bv[i] += wg * dd[8 + i];
-          if (i == l) Bd[k] += dd[8 + i] * R.iS[l];
-          if (k != l && i == k) Bd[l] += dd[8 + i] * R.iS[k];
+          Bv[i] = fma(wg, dd[8 + i], Bv[i]);
+          if (i == l) Bd[k] = fma(dd[8 + i], R.iS[l], Bd[k]);
+          if (k != l && i == k) Bd[l] = fma(dd[8 + i], R.iS[k], Bd[l]);
         }
       }
   }
@@ -737,6 +921,7 @@ __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, c
   BHAH_PHASE_BARRIER();
 
   // ---- results: right-hand side or RK stage combination ------------------
+  if (STG && !live) return;
   if (st.rhs) {
 #pragma unroll
     for (int g = 0; g < NGF; g++) st.rhs[g * G.sgf + q] = get(PK_OUT + g);
@@ -787,7 +972,7 @@ __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, c
 // per SIMD the compiler spills 700-1000 bytes per lane and the kernel is
 // slower.
 
-template <int C, bool AX, bool KO, int H>
+template <int C, bool AX, bool KO, int H, bool STG>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
 k_rhs_fused(GridDev G, TileMap T, Gauge ga, const double* __restrict__ y, StageArgs st,
             double* __restrict__ aux) {
@@ -795,10 +980,13 @@ k_rhs_fused(GridDev G, TileMap T, Gauge ga, const double* __restrict__ y, StageA
   const int w = xcd_remap((int)blockIdx.x, per);
   if (w >= T.ntiles) return;
   int i0, i1, i2;
-  if (!tile_point<H>(G, T, w, (int)threadIdx.x, i0, i1, i2)) return;
+  const bool live = tile_point<H>(G, T, w, (int)threadIdx.x, i0, i1, i2);
+  if (!STG && !live) return;
+  // a row tile (64 x 1 x 1) can only run past the grid along i0
+  if (STG && !live) i0 = H + G.N0 - 1;
   const unsigned q = (unsigned)(i0 + G.s1 * i1 + G.s2 * i2);
-  __shared__ double park[PARK * 64];
-  fused_point<C, AX, KO, true, H>(G, ga, y, st, i0, i1, i2, q, aux, park + threadIdx.x);
+  __shared__ __attribute__((aligned(16))) double park[PARK * 64];
+  fused_point<C, AX, KO, true, H, STG>(G, ga, y, st, i0, i1, i2, q, aux, park + threadIdx.x, live);
 }
 
 // Persistent form for ensembles: a fixed grid of blocks (a multiple of the
@@ -844,10 +1032,10 @@ TileMap make_tilemap(const GridDev& G, int lx, int ly, int band) {
 
 // launch tables over (ghost layers 3 or 5, variant = 2 coord + two phi
 // planes, dissipation on)
-template <int C, bool AX, bool KO, int H>
+template <int C, bool AX, bool KO, int H, bool STG = false>
 void launch_fused_t(dim3 g, hipStream_t s, const GridDev& G, const TileMap& T, const Gauge& ga, const double* y,
                     const StageArgs& st, double* aux) {
-  hipLaunchKernelGGL((k_rhs_fused<C, AX, KO, H>), g, dim3(64), 0, s, G, T, ga, y, st, aux);
+  hipLaunchKernelGGL((k_rhs_fused<C, AX, KO, H, STG>), g, dim3(64), 0, s, G, T, ga, y, st, aux);
 }
 template <int C, bool AX, bool KO, bool MIX, int H>
 void launch_batch_t(dim3 g, hipStream_t s, const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage,
@@ -872,6 +1060,15 @@ constexpr int SS = BHAH_SINH_SPHERICAL, SC = BHAH_SINH_CYLINDRICAL, SP = BHAH_SP
   }
 static const FusedLaunch kFused[2][NVAR][2] = {BHAH_FUSED_ROWS(3), BHAH_FUSED_ROWS(5)};
 #undef BHAH_FUSED_ROWS
+// the staged phase 1 of the two-phi-plane variants, [ghost layers 3 or 5][coord][dissipation];
+// none at 8th order with dissipation, whose staged form spills registers and runs slower
+static const FusedLaunch kStaged[2][3][2] = {
+    {{launch_fused_t<SS, true, false, 3, true>, launch_fused_t<SS, true, true, 3, true>},
+     {launch_fused_t<SC, true, false, 3, true>, launch_fused_t<SC, true, true, 3, true>},
+     {launch_fused_t<SP, true, false, 3, true>, launch_fused_t<SP, true, true, 3, true>}},
+    {{launch_fused_t<SS, true, false, 5, true>, nullptr},
+     {launch_fused_t<SC, true, false, 5, true>, nullptr},
+     {launch_fused_t<SP, true, false, 5, true>, nullptr}}};
 // [variant][dissipation][two-state stages (SSPRK3)]
 #define BHAH_BATCH_ROW(C, AX, H)                                                                 \
   {                                                                                              \
@@ -885,6 +1082,13 @@ static const BatchLaunch kBatch[NVAR][2][2] = {
     BHAH_BATCH_ROW(SC, true, 5),  BHAH_BATCH_ROW(SP, false, 5), BHAH_BATCH_ROW(SP, true, 5)};
 #undef BHAH_BATCH_ROW
 
+// the staged phase 1 on two-phi-plane grids with row tiles (build with
+// BHAH_RHS_STAGE=0 to keep the per-lane gathers there too)
+#ifndef BHAH_RHS_STAGE
+#define BHAH_RHS_STAGE 1
+#endif
+static constexpr bool rhs_stage_enabled() { return BHAH_RHS_STAGE != 0; }
+
 void launch_rhs_fused(const GridDev& G, const Gauge& ga, const double* y, double* aux, const StageArgs& st,
                       hipStream_t s, const TileCfg& cfg_in) {
   const TileCfg cfg = tile_fits_periodic(G.coord, cfg_in) ? cfg_in : TileCfg{6, 0, cfg_in.band, cfg_in.waves};
@@ -894,8 +1098,15 @@ void launch_rhs_fused(const GridDev& G, const Gauge& ga, const double* y, double
     return;
   }
   const int per = (T.ntiles + BHAH_NXCD - 1) / BHAH_NXCD;
-  kFused[G.ng == 5 ? 1 : 0][rhs_variant(G.coord, G.N1, G.N2)][ga.ko() ? 1 : 0](dim3(per * BHAH_NXCD), s, G, T, ga,
-                                                                                y, st, aux);
+  const int v = rhs_variant(G.coord, G.N1, G.N2);
+  const FusedLaunch staged = (v & 1) && T.lx == 6 && rhs_stage_enabled()
+                                 ? kStaged[G.ng == 5 ? 1 : 0][G.coord][ga.ko() ? 1 : 0]
+                                 : nullptr;
+  if (staged) {
+    staged(dim3(per * BHAH_NXCD), s, G, T, ga, y, st, aux);
+    return;
+  }
+  kFused[G.ng == 5 ? 1 : 0][v][ga.ko() ? 1 : 0](dim3(per * BHAH_NXCD), s, G, T, ga, y, st, aux);
 }
 
 void launch_rhs_batch(int variant, const BatchJob* jobs, const BatchHdr* hdr, const int2* work, int stage,
