@@ -46,6 +46,16 @@ __device__ __forceinline__ void gf_ld2(const double* y, long long sgf, int g, un
   hi = __builtin_bit_cast(double, (unsigned long long)v.z | ((unsigned long long)v.w << 32));
 }
 
+// two consecutive doubles stored with one 16-byte store, through the same
+// descriptors as the loads
+__device__ __forceinline__ void gf_st2(double* y, long long sgf, int g, unsigned voff, double lo, double hi) {
+  const __amdgpu_buffer_rsrc_t r =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(y + (g >> 2) * 4 * sgf), (short)0, (int)(4 * sgf * 8), 0x00020000);
+  const unsigned long long a = __builtin_bit_cast(unsigned long long, lo), b = __builtin_bit_cast(unsigned long long, hi);
+  const bhah_u4 v = {(unsigned)a, (unsigned)(a >> 32), (unsigned)b, (unsigned)(b >> 32)};
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, voff, (g & 3) * (int)(sgf * 8), 0);
+}
+
 __device__ __forceinline__ double gf_ld(const double* y, long long sgf, int g, unsigned voff, int soff) {
   const __amdgpu_buffer_rsrc_t r =
       __builtin_amdgcn_make_buffer_rsrc((void*)(y + (g >> 2) * 4 * sgf), (short)0, (int)(4 * sgf * 8), 0x00020000);

@@ -922,16 +922,69 @@ __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, c
 
   // ---- results: right-hand side or RK stage combination ------------------
   if (STG && !live) return;
-  if (st.rhs) {
+  // Every base value is read before any result is stored. Within a stage
+  // the arrays never overlap (RK4: base1 is y or Cacc, out1 is A, B or y;
+  // base2 and out2 are Cacc at the same point; SSPRK3 mixes y with A or B
+  // into B or y), but the compiler cannot know it and would otherwise put
+  // each load behind the stores before it. The combinations are explicit
+  // fused multiply-adds, so both forms below round alike.
+  const bool two = st.out2 != nullptr, mix = MIX && !two && st.base2 != nullptr, same = st.base2 == st.base1;
+  auto out1m = [&](double k, double x1, double x2) { return fma(st.c1, k, fma(st.m2, x2, st.m1 * x1)); };
+  // Row pairs: when all 64 lanes are live and lanes 2p, 2p+1 hold adjacent
+  // points of one row, lane l stores (and loads the bases of) points 2p and
+  // 2p+1, p = l mod 32, of gridfunction g + l / 32, reading the results
+  // from the park: one 16-byte access per two gridfunctions and two points,
+  // half the vector memory instructions of the per-lane form (each costs
+  // the CU's address unit the same time whatever its width).
+  const int lane = (int)(threadIdx.x & 63), p2 = 2 * (lane & 31), gs = lane >> 5;
+  bool paired = false;
+  unsigned qa = 0;
+  if (__builtin_amdgcn_read_exec() == ~0ull) {
+    qa = (unsigned)__shfl((int)q, p2);
+    const unsigned qb = (unsigned)__shfl((int)q, p2 + 1);
+    paired = __all(qb == qa + 1u);
+  }
+  if (paired) {
+    const double* pk = park - lane + p2;
+    auto kv = [&](int g, int h) { return pk[(PK_OUT + g + gs) * 64 + h]; };
+    // gridfunction g + gs, g even: the descriptor and scalar offset of g (the
+    // pair never leaves its group of four), the lane's gs in the vector offset
+    const unsigned vo = qa * 8u + (unsigned)(gs * G.sgf * 8);
+    if (st.rhs) {
+#pragma unroll
+      for (int g = 0; g < NGF; g += 2) gf_st2(st.rhs, G.sgf, g, vo, kv(g, 0), kv(g, 1));
+    } else {
+      double b1[NGF / 2][2], b2[NGF / 2][2];
+#pragma unroll
+      for (int g = 0; g < NGF; g += 2) gf_ld2(st.base1, G.sgf, g, vo, 0, b1[g / 2][0], b1[g / 2][1]);
+      if ((two || mix) && !same) {
+#pragma unroll
+        for (int g = 0; g < NGF; g += 2) gf_ld2(st.base2, G.sgf, g, vo, 0, b2[g / 2][0], b2[g / 2][1]);
+      } else {
+#pragma unroll
+        for (int g = 0; g < NGF / 2; g++) { b2[g][0] = b1[g][0]; b2[g][1] = b1[g][1]; }
+      }
+      BHAH_PHASE_BARRIER();
+      if (mix) {
+#pragma unroll
+        for (int g = 0; g < NGF; g += 2) {
+          const int j = g / 2;
+          gf_st2(st.out1, G.sgf, g, vo, out1m(kv(g, 0), b1[j][0], b2[j][0]), out1m(kv(g, 1), b1[j][1], b2[j][1]));
+        }
+      } else {
+#pragma unroll
+        for (int g = 0; g < NGF; g += 2) {
+          const int j = g / 2;
+          const double k0 = kv(g, 0), k1 = kv(g, 1);
+          gf_st2(st.out1, G.sgf, g, vo, fma(st.c1, k0, b1[j][0]), fma(st.c1, k1, b1[j][1]));
+          if (two) gf_st2(st.out2, G.sgf, g, vo, fma(st.c2, k0, b2[j][0]), fma(st.c2, k1, b2[j][1]));
+        }
+      }
+    }
+  } else if (st.rhs) {
 #pragma unroll
     for (int g = 0; g < NGF; g++) st.rhs[g * G.sgf + q] = get(PK_OUT + g);
   } else {
-    // Every base value is read before any result is stored. Within a stage
-    // the arrays never overlap (RK4: base1 is y or Cacc, out1 is A, B or y;
-    // base2 and out2 are Cacc at the same point; SSPRK3 mixes y with A or B
-    // into B or y), but the compiler cannot know it and would otherwise put
-    // each load behind the stores before it.
-    const bool two = st.out2 != nullptr, mix = MIX && !two && st.base2 != nullptr, same = st.base2 == st.base1;
     double b1[NGF], b2[NGF];
 #pragma unroll
     for (int g = 0; g < NGF; g++) b1[g] = gf_ld(st.base1, G.sgf, g, q * 8u, 0);
@@ -945,17 +998,14 @@ __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, c
     BHAH_PHASE_BARRIER();
     if (mix) {
 #pragma unroll
-      for (int g = 0; g < NGF; g++) {
-        const long long e = g * G.sgf + q;
-        st.out1[e] = st.m1 * b1[g] + st.m2 * b2[g] + st.c1 * get(PK_OUT + g);
-      }
+      for (int g = 0; g < NGF; g++) st.out1[g * G.sgf + q] = out1m(get(PK_OUT + g), b1[g], b2[g]);
     } else {
 #pragma unroll
       for (int g = 0; g < NGF; g++) {
         const long long e = g * G.sgf + q;
         const double k = get(PK_OUT + g);
-        st.out1[e] = b1[g] + st.c1 * k;
-        if (two) st.out2[e] = b2[g] + st.c2 * k;
+        st.out1[e] = fma(st.c1, k, b1[g]);
+        if (two) st.out2[e] = fma(st.c2, k, b2[g]);
       }
     }
   }
