@@ -67,6 +67,19 @@ struct StageGeom {
   static constexpr int NB = (11 + PER - 1) / PER;        // batches
 };
 
+// The same on grids with more than two phi planes, for the mixed pairs
+// (0, l), l = 1, 2: the 2R rows a gridfunction's stencil reads along l
+// (offsets -R..-1, 1..R, in that order), columns -R..63+R along i0.
+template <int H>
+struct CrossGeom {
+  static constexpr int R = H - 1;
+  static constexpr int RL = 64 + 2 * R;              // doubles per stage row
+  static constexpr int NP = R * RL;                  // 16-byte pieces per gridfunction
+  static constexpr int NR = (NP + 63) / 64;          // pieces per lane
+  static constexpr int PER = H == 3 ? 4 : 2;         // gridfunctions per batch
+  static_assert(PER * NP * 2 <= PK_OUT * 64, "the stage must stay below the slots phase 1 writes");
+};
+
 template <int C, bool KO, int H>
 __device__ __forceinline__ void phase1_staged(const PtT<H>& P, const Gauge& ga, const Spacing& sp, const Ref& R,
                                               const UpwindT<H>& U, const double (&vet)[3], const double (&beta)[3],
@@ -223,14 +236,14 @@ __device__ __forceinline__ void phase1_staged(const PtT<H>& P, const Gauge& ga, 
 // two-state path out of RK4 stages saves registers there).
 // H: ghost layers N_G; the differences are of order 2(H-1) (3: 4th order,
 // 5: 8th order).
-// STG: phase 1 through the LDS stage (two phi planes, tiles of 64 points
-// along i0); every lane of the wave takes part, and a lane whose point lies
+// STG: phase 1 through the LDS stage (tiles of 64 points along i0): every
+// stencil of phase 1 on two-phi-plane grids, the mixed pairs (0, l)
+// otherwise. Every lane of the wave takes part, and a lane whose point lies
 // past the grid (live false) computes a clamped point and stores nothing.
 template <int C, bool AX, bool KO, bool MIX, int H, bool STG = false>
 __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, const double* __restrict__ y,
                                             const StageArgs& st, int i0, int i1, int i2, unsigned q,
                                             double* __restrict__ aux, double* __restrict__ park, bool live = true) {
-  static_assert(!STG || AX, "the stage holds one phi plane");
   constexpr int PD = C == BHAH_SINH_CYLINDRICAL ? 1 : 2;  // the periodic (phi) direction
   constexpr int RR = H - 1, SW = 2 * RR + 1;               // stencil radius and width
   const double eta = ga.eta;
@@ -244,6 +257,45 @@ __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, c
   const Spacing sp = make_spacing<RR>(G);
   Ref R;
   load_ref<C>(G, i0, i1, i2, R);
+  // staged mixed pairs (general grids): per lane and load, the byte offset
+  // of its piece of row xo(n) for l = 1, 2, and the piece's LDS index
+  using CG = CrossGeom<H>;
+  unsigned cvo[2][CG::NR];
+  int cpo[CG::NR];
+  if constexpr (STG && !AX) {
+    const int lane = (int)(threadIdx.x & 63);
+    const unsigned vb0 = __builtin_amdgcn_readfirstlane(P.vb);  // lane 0 is never clamped
+    const int sd = PD == 1 ? G.s1 : G.s2, nd = PD == 1 ? G.N1 : G.N2;
+    const int id = __builtin_amdgcn_readfirstlane((PD == 1 ? i1 : i2) - H);
+#pragma unroll
+    for (int r = 0; r < CG::NR; r++) {
+      const int p = min(r * 64 + lane, CG::NP - 1);
+      const int row = p / (CG::RL / 2), col = 2 * (p - row * (CG::RL / 2));
+      const int n = row < RR ? row - RR : row - RR + 1;
+      cpo[r] = 2 * p;
+      const unsigned base = vb0 + (unsigned)((col - RR + H) * 8);
+#pragma unroll
+      for (int li = 0; li < 2; li++) {
+        int off;
+        if (li + 1 == PD) {  // rows on the wrapped phi planes, as the accessor wraps them
+          int x = id + n;
+          if constexpr (H == 3) {
+            x += x < 0 ? nd : 0;
+            x += x < 0 ? nd : 0;
+            x -= x >= nd ? nd : 0;
+            x -= x >= nd ? nd : 0;
+          } else {
+            x %= nd;
+            x += x < 0 ? nd : 0;
+          }
+          off = (H + x) * sd * 8 + H * P.se * 8;
+        } else {
+          off = P.sw[H] + (n + H) * P.se * 8;
+        }
+        cvo[li][r] = base + (unsigned)off;
+      }
+    }
+  }
 
   // ---- phase 0: point values and the conformal metric (Eq. 3) -----------
   double h[6], SS[6], gb[6], gbU[6];
@@ -304,7 +356,7 @@ __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, c
   for (int a = 0; a < 6; a++) Pc[a] = 0.0;
 #pragma unroll
   for (int i = 0; i < 3; i++) { Qs[i] = 0.0; Bv[i] = 0.0; Bd[i] = 0.0; }
-  if constexpr (STG) {
+  if constexpr (STG && AX) {
     const int lane = (int)(threadIdx.x & 63);
     phase1_staged<C, KO, H>(P, ga, sp, R, U, vet, beta, gbU, SS, kw, alpha * iW, park - lane, park, lane, Pc,
                             Qs, Y, Za, Bv, Bd, adv);
@@ -365,6 +417,42 @@ __device__ __forceinline__ void fused_point(const GridDev& G, const Gauge& ga, c
         } else if (AX && (k == PD || l == PD)) {
 #pragma unroll
           for (int t = 0; t < 11; t++) dd[t] = 0.0;
+        } else if (STG && !AX && k == 0) {
+          // rows along l through the LDS stage (park slots 0..30, free in phase 1)
+          const int lane = (int)(threadIdx.x & 63), li = l - 1;
+          double* stg = park - lane;
+#pragma unroll
+          for (int t0 = 0; t0 < 11; t0 += CG::PER) {
+            double lo[CG::PER][CG::NR], hi[CG::PER][CG::NR];
+#pragma unroll
+            for (int t = 0; t < CG::PER; t++)
+              if (t0 + t < 11) {
+#pragma unroll
+                for (int r = 0; r < CG::NR; r++) gf_ld2(P.y, P.sgf, G11[t0 + t], cvo[li][r], 0, lo[t][r], hi[t][r]);
+              }
+#pragma unroll
+            for (int t = 0; t < CG::PER; t++)
+              if (t0 + t < 11) {
+#pragma unroll
+                for (int r = 0; r < CG::NR; r++) {
+                  stg[t * 2 * CG::NP + cpo[r]] = lo[t][r];
+                  stg[t * 2 * CG::NP + cpo[r] + 1] = hi[t][r];
+                }
+              }
+            BHAH_PHASE_BARRIER();
+#pragma unroll
+            for (int t = 0; t < CG::PER; t++)
+              if (t0 + t < 11) {
+                const double* F = stg + t * 2 * CG::NP + RR + lane;  // row 0, this point's column
+                double v[4 * RR * RR];
+#pragma unroll
+                for (int a = 0; a < 2 * RR; a++)
+#pragma unroll
+                  for (int b = 0; b < 2 * RR; b++) v[2 * RR * a + b] = F[b * CG::RL + (a < RR ? a - RR : a - RR + 1)];
+                dd[t0 + t] = d2_cross<RR>(v, sp.crs[k][l]);
+              }
+            BHAH_PHASE_BARRIER();
+          }
         } else {
           constexpr int TX = H == 3 ? 4 : 1;  // gridfunctions per batch of cross loads
 #pragma unroll
@@ -1110,15 +1198,18 @@ constexpr int SS = BHAH_SINH_SPHERICAL, SC = BHAH_SINH_CYLINDRICAL, SP = BHAH_SP
   }
 static const FusedLaunch kFused[2][NVAR][2] = {BHAH_FUSED_ROWS(3), BHAH_FUSED_ROWS(5)};
 #undef BHAH_FUSED_ROWS
-// the staged phase 1 of the two-phi-plane variants, [ghost layers 3 or 5][coord][dissipation];
-// none at 8th order with dissipation, whose staged form spills registers and runs slower
-static const FusedLaunch kStaged[2][3][2] = {
-    {{launch_fused_t<SS, true, false, 3, true>, launch_fused_t<SS, true, true, 3, true>},
-     {launch_fused_t<SC, true, false, 3, true>, launch_fused_t<SC, true, true, 3, true>},
-     {launch_fused_t<SP, true, false, 3, true>, launch_fused_t<SP, true, true, 3, true>}},
-    {{launch_fused_t<SS, true, false, 5, true>, nullptr},
-     {launch_fused_t<SC, true, false, 5, true>, nullptr},
-     {launch_fused_t<SP, true, false, 5, true>, nullptr}}};
+// the staged forms, [ghost layers 3 or 5][variant][dissipation]. At 8th
+// order only the two-plane form without dissipation: the others spill
+// registers (the general ones by kilobytes) and run slower.
+#define BHAH_STAGED_ROW3(C)                                                                        \
+  {launch_fused_t<C, false, false, 3, true>, launch_fused_t<C, false, true, 3, true>},             \
+      {launch_fused_t<C, true, false, 3, true>, launch_fused_t<C, true, true, 3, true>}
+#define BHAH_STAGED_ROW5(C) {nullptr, nullptr}, {launch_fused_t<C, true, false, 5, true>, nullptr}
+static const FusedLaunch kStaged[2][NVAR / 2][2] = {
+    {BHAH_STAGED_ROW3(SS), BHAH_STAGED_ROW3(SC), BHAH_STAGED_ROW3(SP)},
+    {BHAH_STAGED_ROW5(SS), BHAH_STAGED_ROW5(SC), BHAH_STAGED_ROW5(SP)}};
+#undef BHAH_STAGED_ROW3
+#undef BHAH_STAGED_ROW5
 // [variant][dissipation][two-state stages (SSPRK3)]
 #define BHAH_BATCH_ROW(C, AX, H)                                                                 \
   {                                                                                              \
@@ -1132,8 +1223,8 @@ static const BatchLaunch kBatch[NVAR][2][2] = {
     BHAH_BATCH_ROW(SC, true, 5),  BHAH_BATCH_ROW(SP, false, 5), BHAH_BATCH_ROW(SP, true, 5)};
 #undef BHAH_BATCH_ROW
 
-// the staged phase 1 on two-phi-plane grids with row tiles (build with
-// BHAH_RHS_STAGE=0 to keep the per-lane gathers there too)
+// the staged forms on row tiles (build with BHAH_RHS_STAGE=0 to keep the
+// per-lane gathers there too)
 #ifndef BHAH_RHS_STAGE
 #define BHAH_RHS_STAGE 1
 #endif
@@ -1149,9 +1240,8 @@ void launch_rhs_fused(const GridDev& G, const Gauge& ga, const double* y, double
   }
   const int per = (T.ntiles + BHAH_NXCD - 1) / BHAH_NXCD;
   const int v = rhs_variant(G.coord, G.N1, G.N2);
-  const FusedLaunch staged = (v & 1) && T.lx == 6 && rhs_stage_enabled()
-                                 ? kStaged[G.ng == 5 ? 1 : 0][G.coord][ga.ko() ? 1 : 0]
-                                 : nullptr;
+  const FusedLaunch staged =
+      T.lx == 6 && rhs_stage_enabled() ? kStaged[G.ng == 5 ? 1 : 0][v][ga.ko() ? 1 : 0] : nullptr;
   if (staged) {
     staged(dim3(per * BHAH_NXCD), s, G, T, ga, y, st, aux);
     return;
