@@ -7,7 +7,9 @@ phi derivatives the compiler removes; KO: Kreiss-Oliger dissipation on; H:
 ghost layers, 3 for 4th-order and 5 for 8th-order differences; STG: phase 1
 through the LDS stage, the same arithmetic on the same values), the double
 precision fadd / fsub / fmul / fdiv instructions (an fma or fmuladd call
-counts 2) of the basic blocks that store nothing to global memory: that is
+counts 2) of the basic blocks that store nothing to global memory (plain or
+buffer stores), less those whose results only feed such stores (the stage
+combination the compiler computes ahead of its store): that is
 the per-point arithmetic of Eqs. 7-15 after common-subexpression elimination,
 without the RK stage combination that follows it. The result is the FLOP
 figure the benchmark divides by the measured launch time.
@@ -48,13 +50,32 @@ def count(ir, kernel_prefix="_ZN4bhah11k_rhs_fusedILi", dissipation=False, nghos
             continue
         name, c = m.group(1), (int(m.group(2)), bool(int(m.group(3))))
         body = ir[m.start():ir.index("\n}\n", m.start())]
-        total = 0
-        for blk in re.split(r"\n(?=[\w.]+:)", body):
-            if re.search(r"store double [^,]+, ptr addrspace\(1\)", blk):
-                continue
-            total += len(re.findall(r"= (?:fadd|fsub|fmul|fdiv)(?: [a-z ]+)? double", blk))
-            total += 2 * len(re.findall(r"call [a-z ]*double @llvm\.(?:fma|fmuladd)\.f64", blk))
-        res[c] = total
+        blocks = re.split(r"\n(?=[\w.]+:)", body)
+        stores = [bool(re.search(r"store double [^,]+, ptr addrspace\(1\)", b)) or "buffer.store" in b for b in blocks]
+        # FP64 operations of the blocks that store nothing, by result name and weight
+        ops, uses = {}, {}
+        for bi, blk in enumerate(blocks):
+            for line in blk.split("\n"):
+                d = re.match(r"\s*(%[\w.]+) = (?:(?:fadd|fsub|fmul|fdiv)(?: [a-z ]+)? double|"
+                             r".*call [a-z ]*double @llvm\.(?:fma|fmuladd)\.f64)", line)
+                if d and not stores[bi]:
+                    ops[d.group(1)] = 2 if "llvm.fma" in line else 1
+                for u in re.findall(r"%[\w.]+", line.split("=", 1)[1] if " = " in line else line):
+                    uses.setdefault(u, []).append((bi, d.group(1) if d else None))
+        # an operation whose every use is a store block's, or another such
+        # operation's, is the stage combination computed ahead of its store
+        dead = set()
+        changed = True
+        while changed:
+            changed = False
+            for v in ops:
+                if v in dead:
+                    continue
+                us = uses.get(v, [])
+                if us and all(stores[bi] or (r is not None and r in dead) for bi, r in us):
+                    dead.add(v)
+                    changed = True
+        res[c] = sum(w for v, w in ops.items() if v not in dead)
     return res
 
 
