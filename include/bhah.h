@@ -296,8 +296,8 @@ int bhah_constraints(const bhah_grid* g, const double* y, double* H, double* M,
  * 2^ly along i1, 64 >> (lx + ly) along i2, walked in bands of `band` tile
  * rows of i1. The extent along phi (i1 on SinhCylindrical grids, i2
  * otherwise) must be 1. Default (6, 0, 4). The shape changes speed only:
- * every point's arithmetic is the same, and results are bitwise equal
- * across shapes. With row tiles (lx = 6) the one-wave kernel brings
+ * every point's arithmetic is the same, and with one wave per tile the
+ * results are bitwise equal across shapes. With row tiles (lx = 6) the one-wave kernel brings
  * stencil rows shared by the tile's points into LDS with a few wide loads
  * (at 4th order; at 8th order on two-phi-plane grids without
  * dissipation). Setting a shape keeps the number of waves per tile
