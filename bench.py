@@ -142,12 +142,12 @@ def kernel_name(coord, N, ko=False, nghosts=3, waves=1, tile=None):
     """The right-hand-side kernel the library launches for this grid, tile
     and mode: with row tiles (lx = 6) the one-wave kernel reads phase-1
     stencils from an LDS stage (last template argument) at 4th order, and
-    at 8th order on two-phi-plane grids without dissipation."""
+    at 8th order on two-phi-plane grids."""
     ax = two_planes(coord, N)
     b = lambda v: "true" if v else "false"
     if waves == 2:
         return "k_rhs_pair<%d,%s,%s,%d>" % (coord, b(ax), b(ko), nghosts)
-    staged = tile is not None and tile[0] == 6 and (nghosts == 3 or (ax and not ko))
+    staged = tile is not None and tile[0] == 6 and (nghosts == 3 or ax)
     return "k_rhs_fused<%d,%s,%s,%d,%s>" % (coord, b(ax), b(ko), nghosts, b(staged))
 
 

@@ -63,8 +63,7 @@ struct StageGeom {
   static constexpr int RL = 64 + 2 * H;                  // doubles per stage row
   static constexpr int NP = (2 * H + 1) * RL / 2;        // 16-byte pieces per gridfunction
   static constexpr int NR = (NP + 63) / 64;              // pieces per lane
-  static constexpr int PER = (31 * 64 * 8) / (NP * 16);  // gridfunctions per batch
-  static constexpr int NB = (11 + PER - 1) / PER;        // batches
+  static constexpr int PER = (31 * 64 * 8) / (NP * 16);  // gridfunctions per batch (at most)
 };
 
 // The same on grids with more than two phi planes, for the mixed pairs
@@ -91,7 +90,9 @@ __device__ __forceinline__ void phase1_staged(const PtT<H>& P, const Gauge& ga, 
   constexpr int E = 3 - PD;                               // the other transverse direction
   constexpr int RR = H - 1, SW = 2 * RR + 1, XW = 2 * RR;
   using SG = StageGeom<H>;
-  constexpr int RL = SG::RL, NP = SG::NP, NR = SG::NR, PER = SG::PER, NB = SG::NB;
+  // at 8th order with dissipation one gridfunction per batch (two spill)
+  constexpr int RL = SG::RL, NP = SG::NP, NR = SG::NR, PER = H == 5 && KO ? 1 : SG::PER;
+  constexpr int NB = (11 + PER - 1) / PER;
   static_assert(PER * NP * 2 <= PK_OUT * 64, "the stage must stay below the slots phase 1 writes");
   constexpr int G11[11] = {G_HDD00, G_HDD00 + 1, G_HDD00 + 2, G_HDD00 + 3, G_HDD00 + 4, G_HDD00 + 5,
                            G_CF, G_ALPHA, G_VETU0, G_VETU0 + 1, G_VETU0 + 2};
@@ -1199,12 +1200,12 @@ constexpr int SS = BHAH_SINH_SPHERICAL, SC = BHAH_SINH_CYLINDRICAL, SP = BHAH_SP
 static const FusedLaunch kFused[2][NVAR][2] = {BHAH_FUSED_ROWS(3), BHAH_FUSED_ROWS(5)};
 #undef BHAH_FUSED_ROWS
 // the staged forms, [ghost layers 3 or 5][variant][dissipation]. At 8th
-// order only the two-plane form without dissipation: the others spill
-// registers (the general ones by kilobytes) and run slower.
+// order only the two-plane forms: the general ones spill kilobytes of
+// registers.
 #define BHAH_STAGED_ROW3(C)                                                                        \
   {launch_fused_t<C, false, false, 3, true>, launch_fused_t<C, false, true, 3, true>},             \
       {launch_fused_t<C, true, false, 3, true>, launch_fused_t<C, true, true, 3, true>}
-#define BHAH_STAGED_ROW5(C) {nullptr, nullptr}, {launch_fused_t<C, true, false, 5, true>, nullptr}
+#define BHAH_STAGED_ROW5(C) {nullptr, nullptr}, {launch_fused_t<C, true, false, 5, true>, launch_fused_t<C, true, true, 5, true>}
 static const FusedLaunch kStaged[2][NVAR / 2][2] = {
     {BHAH_STAGED_ROW3(SS), BHAH_STAGED_ROW3(SC), BHAH_STAGED_ROW3(SP)},
     {BHAH_STAGED_ROW5(SS), BHAH_STAGED_ROW5(SC), BHAH_STAGED_ROW5(SP)}};

@@ -33,8 +33,8 @@ def _grid(name, ng):
 
 
 @pytest.mark.parametrize("name,ng,diss", [
-    ("tiny", 3, (0.0, 0.0)), ("tiny", 3, KO), ("tiny", 5, (0.0, 0.0)),
-    ("cyl_ragged", 3, (0.0, 0.0)), ("cyl_ragged", 3, KO), ("cyl_ragged", 5, (0.0, 0.0)),
+    ("tiny", 3, (0.0, 0.0)), ("tiny", 3, KO), ("tiny", 5, (0.0, 0.0)), ("tiny", 5, KO),
+    ("cyl_ragged", 3, (0.0, 0.0)), ("cyl_ragged", 3, KO), ("cyl_ragged", 5, (0.0, 0.0)), ("cyl_ragged", 5, KO),
     ("sph_ragged", 3, (0.0, 0.0)), ("sph_ragged", 3, KO),
     ("cyl_3d", 3, (0.0, 0.0)), ("cyl_3d", 3, KO),
     ("spherical", 3, (0.0, 0.0)), ("spherical", 3, KO)])
