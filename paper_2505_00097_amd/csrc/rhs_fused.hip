@@ -90,9 +90,9 @@ __device__ __forceinline__ void phase1_staged(const PtT<H>& P, const Gauge& ga, 
   constexpr int E = 3 - PD;                               // the other transverse direction
   constexpr int RR = H - 1, SW = 2 * RR + 1, XW = 2 * RR;
   using SG = StageGeom<H>;
-  // two gridfunctions per batch at 4th order (faster than the four that
-  // fit), one at 8th order with dissipation (two spill)
-  constexpr int RL = SG::RL, NP = SG::NP, NR = SG::NR, PER = H == 3 ? 2 : (KO ? 1 : SG::PER);
+  // two gridfunctions per batch at 4th order and one at 8th: faster than
+  // the four and two that fit (and two spill at 8th order with dissipation)
+  constexpr int RL = SG::RL, NP = SG::NP, NR = SG::NR, PER = H == 3 ? 2 : 1;
   constexpr int NB = (11 + PER - 1) / PER;
   static_assert(PER * NP * 2 <= PK_OUT * 64, "the stage must stay below the slots phase 1 writes");
   constexpr int G11[11] = {G_HDD00, G_HDD00 + 1, G_HDD00 + 2, G_HDD00 + 3, G_HDD00 + 4, G_HDD00 + 5,
