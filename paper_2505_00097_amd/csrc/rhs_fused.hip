@@ -75,7 +75,7 @@ struct CrossGeom {
   static constexpr int RL = 64 + 2 * R;              // doubles per stage row
   static constexpr int NP = R * RL;                  // 16-byte pieces per gridfunction
   static constexpr int NR = (NP + 63) / 64;          // pieces per lane
-  static constexpr int PER = H == 3 ? 4 : 2;         // gridfunctions per batch
+  static constexpr int PER = H == 3 ? 6 : 2;         // gridfunctions per batch
   static_assert(PER * NP * 2 <= PK_OUT * 64, "the stage must stay below the slots phase 1 writes");
 };
 
