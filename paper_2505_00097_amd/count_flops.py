@@ -42,7 +42,8 @@ def count(ir, kernel_prefix="_ZN4bhah11k_rhs_fusedILi", dissipation=False, nghos
     """{(coord, two_phi_planes): FP64 operations per point} of the kernels
     with `nghosts` ghost layers, without (or, with dissipation=True, with)
     Kreiss-Oliger dissipation; staged=True counts the forms whose phase 1
-    reads its stencils from the LDS stage (two phi planes only)"""
+    reads stencils from the LDS stage (every variant at 4th order, the
+    two-phi-plane ones at 8th)"""
     res = {}
     pat = r"(\d)ELb(\d)ELb(\d)ELi(\d)ELb(\d)E\S*)\("
     for m in re.finditer(r"define [^@]*@(" + re.escape(kernel_prefix) + pat, ir):
